@@ -1,0 +1,162 @@
+"""Throughput of full-batch SPFOM iterations on one MI355X.
+
+A step is one whole SPFOM iteration (every row of the hot path: price step,
+per-segment exact best response, fixed-point sales scatter, FP64
+reductions, projected dual step) over the L=2e6-segment, n=2e4-product
+Zipf workload with FP32 iterates and FP64 reductions.  Inputs are resident
+in HBM before timing starts.
+
+Prints one JSON line (stdout).  Progress goes to stderr.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK = 8.0e12          # MI355X HBM3E, bytes/s
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes(inst, esz):
+    """Bytes one segment-kernel launch must move: the CSR entries (product id
+    4 B, v and w esz each), per segment the row pointer (8 B), vt0 and lambda
+    (esz each), per product the price read (esz) and the sales
+    accumulator (8 B)."""
+    nnz, L, n = inst.nnz, inst.L, inst.n
+    per_nnz = 4 + 2 * esz
+    per_seg = 8 + 2 * esz
+    per_prod = esz + 8
+    return nnz * per_nnz + L * per_seg + n * per_prod, dict(per_nnz=per_nnz, per_seg=per_seg,
+                                                            per_prod=per_prod)
+
+
+def cpu_baseline(inst, budget_s=15.0):
+    """Time the FP64 oracle (single thread) on a prefix of the same workload."""
+    import dataclasses
+    import oracle
+    from paper_2602_22421_amd.instances import step_scale
+
+    def prefix(Ls):
+        e = int(inst.seg_ptr[Ls])
+        return dataclasses.replace(inst, L=Ls, seg_ptr=inst.seg_ptr[: Ls + 1].copy(),
+                                   idx=inst.idx[:e], v=inst.v[:e], w=inst.w[:e],
+                                   v0=inst.v0[:Ls], lam=inst.lam[:Ls])
+
+    Ls = min(inst.L, 20000)
+    sub = prefix(Ls)
+    s = oracle.Solver(sub, tau=step_scale(inst, 0.001))
+    t0 = time.perf_counter()
+    s.iterate(np.zeros(inst.m), 1, trace=False)
+    one = time.perf_counter() - t0
+    Ls2 = int(min(inst.L, max(Ls, Ls * budget_s / 3.0 / max(one, 1e-6))))
+    sub = prefix(Ls2)
+    s = oracle.Solver(sub, tau=step_scale(inst, 0.001))
+    iters = 3
+    t0 = time.perf_counter()
+    s.iterate(np.zeros(inst.m), iters, trace=False)
+    dt = time.perf_counter() - t0
+    return {"value": Ls2 * iters / dt, "unit": "segment-updates/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"{iters} FP64 iterations over the first {Ls2} segments "
+                      f"({int(sub.seg_ptr[-1])} CSR entries) of the same instance, "
+                      f"single-threaded C, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--config", type=int, default=1, choices=[0, 1, 2])
+    ap.add_argument("--dtype", default="f32", choices=["f32", "f64"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-timing", action="store_true",
+                    help="skip the per-launch events (roofline fields become null)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
+              f"(the multi-GPU sharding is a design, not a build)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2602_22421_amd import cblp
+    from paper_2602_22421_amd.instances import CONFIG_NAMES, config_instance, step_scale
+
+    cblp.load()
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    t0 = time.perf_counter()
+    inst = config_instance(args.config)
+    npdt = np.float32 if args.dtype == "f32" else np.float64
+    dt = torch.float32 if args.dtype == "f32" else torch.float64
+    inst = inst.cast(npdt)
+    log(f"generated {CONFIG_NAMES[args.config]}: L={inst.L} n={inst.n} m={inst.m} "
+        f"nnz={inst.nnz} in {time.perf_counter() - t0:.1f} s")
+    prob = cblp.Problem(inst, dtype=dt)
+    tau = prob.tensor(step_scale(inst, 0.001))
+    params = cblp.make_params(rule=cblp.SPFOM_STEP_CONST, tau_vec=tau, check_every=10)
+    eta = prob.zeros_eta()
+
+    cblp.spfom_iterate(prob.h, eta, params, args.warmup)
+    torch.cuda.synchronize()
+    log(f"warmup {args.warmup} steps done")
+
+    if not args.no_timing:
+        cblp.cblp_timing(prob.h, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    cblp.spfom_iterate(prob.h, eta, params, args.steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    log(f"timed {args.steps} steps: {wall * 1e3 / args.steps:.3f} ms/step")
+    roof = None
+    if not args.no_timing:
+        (seg_ms, dual_ms), (seg_n, dual_n) = cblp.cblp_timing_read(prob.h)
+        cblp.cblp_timing(prob.h, False)
+        esz = 4 if args.dtype == "f32" else 8
+        nbytes, per = algorithmic_bytes(inst, esz)
+        seg_avg = seg_ms / 1e3 / max(seg_n, 1)
+        achieved = nbytes / seg_avg
+        roof = {"bound": "hbm", "kernel": "k_segments", "achieved": achieved / 1e9,
+                "peak": HBM_PEAK / 1e9, "unit": "GB/s", "frac": achieved / HBM_PEAK,
+                "traffic": None, "bytes_per_launch": nbytes, "per_unit_bytes": per,
+                "kernel_avg_us": seg_avg * 1e6,
+                "dual_kernel_avg_us": dual_ms * 1e3 / max(dual_n, 1)}
+        log(f"segment kernel {seg_avg * 1e6:.1f} us/launch, {achieved / 1e9:.0f} GB/s "
+            f"({100 * achieved / HBM_PEAK:.1f}% of HBM peak); dual kernel "
+            f"{dual_ms * 1e3 / max(dual_n, 1):.1f} us/launch")
+    st = prob.gap(eta)
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle on a bounded sample ...")
+        cpu = cpu_baseline(inst)
+        log(f"cpu baseline {cpu['value']:.3e} segment-updates/s ({cpu['sample']})")
+    value = inst.L * args.steps / wall
+    out = {
+        "metric": "segment-updates/s", "value": value, "unit": "segment-updates/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": wall * 1e3 / args.steps, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": args.dtype, "data": "synthetic",
+        "config": {"workload": CONFIG_NAMES[args.config], "L": inst.L, "n": inst.n,
+                   "m": inst.m, "nnz": inst.nnz,
+                   "iterate": args.dtype, "reductions": "f64", "step_rule": "const",
+                   "dual_bound_after": st["D"]},
+        "roofline": roof, "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    prob.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,185 @@
+/*
+ * cblp.h - C ABI of libcblp.so: full-batch SPFOM for the choice-based LP
+ * (CBLP) under the generalized attraction model, on one AMD Instinct MI355X
+ * (gfx950).
+ *
+ * The method is the parallel primal-dual iteration of the paper (Algorithm 3,
+ * Section 4.3, with every segment sampled in every iteration): each segment
+ * solves its inner assortment problem exactly against the current capacity
+ * duals (Section 4.1, inner problem z_i), the segment sales are summed into
+ * product and resource rows (A s), and the duals take the projected,
+ * optionally regularised step of eq. 16.  Instances follow the problem
+ * statement of Section 3 (segments with arrival rates, consideration sets,
+ * nominal and shadow attractions of the GAM, revenues, capacities) and the
+ * resource-matrix form of Section 5.2 (NRM with bundling).
+ *
+ * Notation used below: segments l in [L], products j in [n], resources
+ * i in [m].  v is the nominal and w the shadow attraction (the paper writes
+ * them the other way round), v0 the no-purchase attraction, lambda the
+ * arrival rate, r the revenue, c the capacity, eta the capacity duals.
+ *
+ * Conventions for every entry point:
+ *  - Pointers marked [dev] are device pointers on the current HIP device;
+ *    [host] are host pointers.  Real arrays have the instance's dtype
+ *    (CBLP_F32: float, CBLP_F64: double) unless typed explicitly.
+ *  - stream is a hipStream_t passed as void*; NULL is the null stream.
+ *    Work is enqueued on it; entry points that return host results
+ *    synchronise that stream before returning.
+ *  - Return value: CBLP_OK (0) or a CBLP_E* code; cblp_last_error() then
+ *    describes the failure (thread-local, valid until the next call on the
+ *    same thread).  No C++ exception crosses this boundary.
+ *  - Results are bitwise reproducible for a given instance, dtype, params
+ *    and device: product sales are summed in 64-bit fixed point and every
+ *    floating-point reduction has a fixed order.
+ */
+#ifndef CBLP_H
+#define CBLP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    CBLP_OK = 0,
+    CBLP_EINVAL = 1,        /* bad size, pointer or value in the instance/params */
+    CBLP_ENOMEM = 2,        /* device or host allocation failed */
+    CBLP_EHIP = 3,          /* a HIP runtime call failed */
+    CBLP_ENONFINITE = 4,    /* an iterate or reduction became NaN/Inf */
+    CBLP_ENOTCONVERGED = 5  /* spfom_solve hit max_iters; stats are filled */
+};
+
+enum { CBLP_F32 = 1, CBLP_F64 = 2 };
+
+/* Step rules for the dual update eta_i <- max(0, (1 - t_i mu) eta_i - t_i (c_i - u_i)). */
+enum {
+    SPFOM_STEP_CONST = 0,   /* t_i = tau_i: the constant step of Algorithm 2 */
+    SPFOM_STEP_POLYAK = 1   /* t_i = tau_i * gamma (D^t - LB) / sum_k tau_k g_k^2 */
+};
+
+/* Columns of one trace row (FP64), one row per iteration. */
+enum {
+    SPFOM_TR_DUAL = 0,      /* D^t = c . eta^{t-1} + sum_l lambda_l R*_l(eta^{t-1}) */
+    SPFOM_TR_PRIMAL = 1,    /* P^t = sum_j r_j S^t_j, revenue of the best responses */
+    SPFOM_TR_Z = 2,         /* sum_l lambda_l R*_l */
+    SPFOM_TR_ETA2 = 3,      /* ||eta^t||^2 */
+    SPFOM_TR_INFEAS = 4,    /* sum_i (u^t_i - c_i)^+ */
+    SPFOM_TR_DBEST = 5,     /* min_{s<=t} D^s (upper bound on the LP optimum) */
+    SPFOM_TR_LB = 6,        /* best certified feasible revenue (lower bound) */
+    SPFOM_TR_GAP = 7,       /* (DBEST - LB) / |DBEST| */
+    SPFOM_TR_STEP = 8,      /* step multiplier (1 for CONST) */
+    SPFOM_TR_THETA = 9,     /* min_i min(1, c_i / ubar_i) at the last check */
+    SPFOM_NTRACE = 10
+};
+
+typedef struct cblp_instance* cblp_t;
+
+/* Iteration parameters (host struct). */
+typedef struct {
+    int32_t rule;           /* SPFOM_STEP_CONST or SPFOM_STEP_POLYAK */
+    int32_t check_every;    /* K >= 1: certified lower bound refreshed every K iterations */
+    double tau;             /* scalar tau_i when tau_vec is NULL (> 0) */
+    const void* tau_vec;    /* [dev] optional per-resource tau_i [m], instance dtype, > 0 */
+    double gamma;           /* Polyak multiplier (0, 2] */
+    double mu;              /* regularisation mu >= 0 of eq. 15/16 (0: Algorithm 2) */
+    double tol;             /* spfom_solve: stop when the certified gap <= tol */
+    int64_t max_iters;      /* spfom_solve: iteration cap */
+} spfom_params;
+
+/* Result summary (host struct, FP64). */
+typedef struct {
+    int64_t iters;          /* iterations since the last reset */
+    double trace[SPFOM_NTRACE]; /* the last trace row */
+    double seconds;         /* wall time of the call (spfom_solve only) */
+    int32_t status;         /* CBLP_OK, CBLP_ENOTCONVERGED or CBLP_ENONFINITE */
+} spfom_stats;
+
+/*
+ * cblp_create - validate an instance and build a solver handle.
+ *
+ * seg_ptr [dev] int64 [L+1]: CSR row pointers of the consideration sets N_l
+ *         (Section 3); seg_ptr[0] = 0, non-decreasing.
+ * prod_idx [dev] int32 [nnz]: product ids in [0, n), distinct within a row.
+ * v, w [dev] [nnz]: nominal and shadow attraction per (segment, product);
+ *         0 <= w < v, finite.  (GAM choice probability, Section 3.)
+ * v0, lambda [dev] [L]: no-purchase attraction (> 0) and arrival rate (>= 0).
+ * r [dev] [n]: revenues (finite).   c [dev] [m]: capacities (>= 0, finite).
+ * a_ptr [dev] int64 [n+1], a_idx [dev] int32 [nnzA], a_val [dev] [nnzA]:
+ *         resource matrix A by product (CSC), entries a_ij >= 0 (Section 5.2,
+ *         eq. 26).  All three NULL means A = identity and requires m == n.
+ * dtype: CBLP_F32 (iterate in FP32, reductions in FP64) or CBLP_F64.
+ *
+ * Ownership: the instance arrays are BORROWED - the caller keeps them alive
+ * and unchanged until cblp_destroy.  The handle owns its workspace (about
+ * 8 (L + 3n + 3m) bytes plus A's transpose).  Validation runs on the
+ * device; any violation returns CBLP_EINVAL and no handle.
+ */
+int cblp_create(cblp_t* out, int64_t L, int64_t n, int64_t m,
+                const int64_t* seg_ptr, const int32_t* prod_idx,
+                const void* v, const void* w, const void* v0, const void* lambda,
+                const void* r, const int64_t* a_ptr, const int32_t* a_idx,
+                const void* a_val, const void* c, int32_t dtype, void* stream);
+
+/* Release the handle and its workspace.  NULL is a no-op. */
+void cblp_destroy(cblp_t h);
+
+/* Clear the solver state (iteration count, Dbest, LB, averaging window). */
+int spfom_reset(cblp_t h, void* stream);
+
+/*
+ * spfom_iterate - run `iters` SPFOM iterations from eta, continuing the
+ * handle's solver state (Algorithm 3 with every segment sampled; dual step
+ * of eq. 16).
+ * eta [dev] [m], in/out: the duals eta^0 on entry, eta^iters on return.
+ * trace [host] nullable, FP64 [iters x SPFOM_NTRACE]: one row per iteration.
+ * out [host] nullable: summary of the last iteration.
+ * If trace or out is non-NULL the call synchronises the stream.
+ */
+int spfom_iterate(cblp_t h, void* eta, const spfom_params* p, int64_t iters,
+                  double* trace, spfom_stats* out, void* stream);
+
+/*
+ * spfom_solve - reset the state and iterate from eta until the certified
+ * relative gap (Dbest - LB)/|Dbest| <= p->tol or p->max_iters iterations;
+ * the gap is read back every p->check_every iterations.  Returns CBLP_OK on
+ * convergence, CBLP_ENOTCONVERGED at the cap (out still filled).
+ * eta [dev] [m] in/out: warm start (or zeros) in, final duals out.
+ */
+int spfom_solve(cblp_t h, void* eta, const spfom_params* p, spfom_stats* out, void* stream);
+
+/*
+ * cblp_gap - one best-response pass at fixed eta [dev] [m] (no dual step, no
+ * state change).  Fills out->trace with DUAL = D(eta), PRIMAL, Z, ETA2 and
+ * INFEAS; the other columns are 0.  Synchronises the stream.
+ */
+int cblp_gap(cblp_t h, const void* eta, spfom_stats* out, void* stream);
+
+/*
+ * cblp_sales - best responses at fixed eta [dev] [m].
+ * S_out [dev] double [n] nullable: product sales S_j = sum_l s_lj.
+ * u_out [dev] double [m] nullable: resource usage u = A S.
+ * seg_R_out [dev] [L] nullable, instance dtype: R*_l per segment.
+ */
+int cblp_sales(cblp_t h, const void* eta, double* S_out, double* u_out, void* seg_R_out,
+               void* stream);
+
+/*
+ * cblp_timing - enable (1) or disable (0) per-launch timing: while enabled,
+ * every launch of the segment kernel (id 0) and of the dual-step kernel
+ * (id 1) is bracketed by a pair of HIP events on the launch stream.  Enabling
+ * clears earlier records.
+ * cblp_timing_read - synchronise the stream and return the summed kernel
+ * times ms[2] (milliseconds) and launch counts launches[2] ([host] arrays
+ * indexed by kernel id) recorded since the last read, then clear them.
+ */
+int cblp_timing(cblp_t h, int32_t enable);
+int cblp_timing_read(cblp_t h, double* ms, int64_t* launches, void* stream);
+
+/* Describe the last failure on this thread ("" if none). */
+const char* cblp_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CBLP_H */

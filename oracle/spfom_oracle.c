@@ -42,8 +42,9 @@
  *   whenever t doubles the window start) has usage ubar and revenue Pbar;
  *   offering it a fraction theta = min(1, min_i c_i / ubar_i) of the time and
  *   the empty assortment otherwise is feasible, so LB = max over checks of
- *   theta * Pbar <= OPT.  gap = (Dbest - LB) / |Dbest|.
+ *   theta * Pbar <= OPT.  gap = (Dbest - LB) / |Dbest| (0 when both are 0).
  */
+#include <float.h>
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
@@ -299,7 +300,7 @@ int orc_iterate(const orc_instance* I, const orc_params* prm, orc_state* st,
             tr[TR_INFEAS] = infeas;
             tr[TR_DBEST] = st->dbest;
             tr[TR_LB] = st->lb;
-            tr[TR_GAP] = (st->dbest - st->lb) / fabs(st->dbest);
+            tr[TR_GAP] = (st->dbest - st->lb) / fmax(fabs(st->dbest), DBL_MIN);
             tr[TR_STEP] = scale;
             tr[TR_THETA] = theta;
         }

@@ -1,0 +1,251 @@
+"""Python binding of libcblp.so (ctypes; argument marshalling only).
+
+Every function named like an entry point of ``include/cblp.h`` passes torch
+device tensors through as raw pointers together with torch's current HIP
+stream; all arithmetic of the method runs in the library's HIP kernels.  The
+library must be built (``python paper_2602_22421_amd/csrc/build.py`` or
+``__graft_entry__.build()``); there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+import torch
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libcblp.so")
+
+CBLP_OK, CBLP_EINVAL, CBLP_ENOMEM, CBLP_EHIP, CBLP_ENONFINITE, CBLP_ENOTCONVERGED = range(6)
+CBLP_F32, CBLP_F64 = 1, 2
+SPFOM_STEP_CONST, SPFOM_STEP_POLYAK = 0, 1
+NTRACE = 10
+TRACE_COLS = ("D", "P", "Z", "eta2", "infeas", "dbest", "lb", "gap", "step", "theta")
+EXPORTS = ("cblp_create", "cblp_destroy", "spfom_reset", "spfom_iterate", "spfom_solve",
+           "cblp_gap", "cblp_sales", "cblp_timing", "cblp_timing_read", "cblp_last_error")
+
+
+class SpfomParams(ctypes.Structure):
+    _fields_ = [("rule", ctypes.c_int32), ("check_every", ctypes.c_int32),
+                ("tau", ctypes.c_double), ("tau_vec", ctypes.c_void_p),
+                ("gamma", ctypes.c_double), ("mu", ctypes.c_double),
+                ("tol", ctypes.c_double), ("max_iters", ctypes.c_int64)]
+
+
+class SpfomStats(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int64), ("trace", ctypes.c_double * NTRACE),
+                ("seconds", ctypes.c_double), ("status", ctypes.c_int32)]
+
+    def as_dict(self):
+        d = {k: float(self.trace[i]) for i, k in enumerate(TRACE_COLS)}
+        d.update(iters=int(self.iters), seconds=float(self.seconds), status=int(self.status))
+        return d
+
+
+class CblpError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"cblp error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def load(path: str = _LIB_PATH) -> ctypes.CDLL:
+    """Load libcblp.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with paper_2602_22421_amd/csrc/build.py")
+    lib = ctypes.CDLL(path)
+    vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
+    lib.cblp_create.restype = ctypes.c_int
+    lib.cblp_create.argtypes = [ctypes.POINTER(vp), i64, i64, i64, vp, vp, vp, vp, vp, vp, vp,
+                                vp, vp, vp, vp, i32, vp]
+    lib.cblp_destroy.restype = None
+    lib.cblp_destroy.argtypes = [vp]
+    lib.spfom_reset.restype = ctypes.c_int
+    lib.spfom_reset.argtypes = [vp, vp]
+    lib.spfom_iterate.restype = ctypes.c_int
+    lib.spfom_iterate.argtypes = [vp, vp, ctypes.POINTER(SpfomParams), i64, vp,
+                                  ctypes.POINTER(SpfomStats), vp]
+    lib.spfom_solve.restype = ctypes.c_int
+    lib.spfom_solve.argtypes = [vp, vp, ctypes.POINTER(SpfomParams), ctypes.POINTER(SpfomStats), vp]
+    lib.cblp_gap.restype = ctypes.c_int
+    lib.cblp_gap.argtypes = [vp, vp, ctypes.POINTER(SpfomStats), vp]
+    lib.cblp_sales.restype = ctypes.c_int
+    lib.cblp_sales.argtypes = [vp, vp, vp, vp, vp, vp]
+    lib.cblp_timing.restype = ctypes.c_int
+    lib.cblp_timing.argtypes = [vp, i32]
+    lib.cblp_timing_read.restype = ctypes.c_int
+    lib.cblp_timing_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double),
+                                     ctypes.POINTER(ctypes.c_int64), vp]
+    lib.cblp_last_error.restype = ctypes.c_char_p
+    lib.cblp_last_error.argtypes = []
+    _lib = lib
+    return lib
+
+
+def last_error() -> str:
+    return load().cblp_last_error().decode()
+
+
+def _check(rc: int, allow=()):
+    if rc != CBLP_OK and rc not in allow:
+        raise CblpError(rc, last_error())
+    return rc
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+# ------------------------------------------------------------------ raw ABI
+
+def cblp_create(L, n, m, seg_ptr, prod_idx, v, w, v0, lam, r, a_ptr, a_idx, a_val, c,
+                dtype: int, stream=None) -> int:
+    h = ctypes.c_void_p()
+    _check(load().cblp_create(ctypes.byref(h), int(L), int(n), int(m), _ptr(seg_ptr),
+                              _ptr(prod_idx), _ptr(v), _ptr(w), _ptr(v0), _ptr(lam), _ptr(r),
+                              _ptr(a_ptr), _ptr(a_idx), _ptr(a_val), _ptr(c), int(dtype),
+                              _stream(stream)))
+    return h.value
+
+
+def cblp_destroy(h) -> None:
+    if h:
+        load().cblp_destroy(ctypes.c_void_p(h))
+
+
+def spfom_reset(h, stream=None) -> None:
+    _check(load().spfom_reset(ctypes.c_void_p(h), _stream(stream)))
+
+
+def spfom_iterate(h, eta, params: SpfomParams, iters: int, trace: Optional[np.ndarray] = None,
+                  stats: Optional[SpfomStats] = None, stream=None) -> None:
+    tp = None
+    if trace is not None:
+        assert trace.dtype == np.float64 and trace.flags.c_contiguous
+        assert trace.shape == (iters, NTRACE)
+        tp = ctypes.c_void_p(trace.ctypes.data)
+    _check(load().spfom_iterate(ctypes.c_void_p(h), _ptr(eta), ctypes.byref(params), int(iters),
+                                tp, None if stats is None else ctypes.byref(stats),
+                                _stream(stream)))
+
+
+def spfom_solve(h, eta, params: SpfomParams, stream=None) -> SpfomStats:
+    st = SpfomStats()
+    _check(load().spfom_solve(ctypes.c_void_p(h), _ptr(eta), ctypes.byref(params),
+                              ctypes.byref(st), _stream(stream)), allow=(CBLP_ENOTCONVERGED,))
+    return st
+
+
+def cblp_gap(h, eta, stream=None) -> SpfomStats:
+    st = SpfomStats()
+    _check(load().cblp_gap(ctypes.c_void_p(h), _ptr(eta), ctypes.byref(st), _stream(stream)))
+    return st
+
+
+def cblp_sales(h, eta, S_out=None, u_out=None, seg_R_out=None, stream=None) -> None:
+    _check(load().cblp_sales(ctypes.c_void_p(h), _ptr(eta), _ptr(S_out), _ptr(u_out),
+                             _ptr(seg_R_out), _stream(stream)))
+
+
+def cblp_timing(h, enable: bool) -> None:
+    _check(load().cblp_timing(ctypes.c_void_p(h), int(bool(enable))))
+
+
+def cblp_timing_read(h, stream=None):
+    """Returns ((segment_ms, dual_ms), (segment_launches, dual_launches))."""
+    ms = (ctypes.c_double * 2)()
+    n = (ctypes.c_int64 * 2)()
+    _check(load().cblp_timing_read(ctypes.c_void_p(h), ms, n, _stream(stream)))
+    return (ms[0], ms[1]), (n[0], n[1])
+
+
+# ------------------------------------------------------------------ convenience
+
+def make_params(*, rule: int = SPFOM_STEP_CONST, check_every: int = 10, tau: float = 1.0,
+                tau_vec: Optional[torch.Tensor] = None, gamma: float = 1.0, mu: float = 0.0,
+                tol: float = 1e-4, max_iters: int = 10000) -> SpfomParams:
+    p = SpfomParams(int(rule), int(check_every), float(tau),
+                    None if tau_vec is None else tau_vec.data_ptr(), float(gamma), float(mu),
+                    float(tol), int(max_iters))
+    p._keep = tau_vec  # keep the tensor alive with the struct
+    return p
+
+
+class Problem:
+    """An instance uploaded to the current device plus its solver handle.
+
+    ``inst`` is any object with the fields of
+    ``paper_2602_22421_amd.instances.Instance``; its real arrays are converted
+    to ``dtype`` (torch.float32 or torch.float64) on the device."""
+
+    def __init__(self, inst, dtype=torch.float32, device="cuda"):
+        self.dtype = dtype
+        self.device = torch.device(device)
+        npdt = np.float32 if dtype == torch.float32 else np.float64
+        dev = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a, dtype=dt)).to(self.device)
+        self.L, self.n, self.m = int(inst.L), int(inst.n), int(inst.m)
+        self.seg_ptr = dev(inst.seg_ptr, np.int64)
+        self.idx = dev(inst.idx, np.int32)
+        self.v, self.w = dev(inst.v, npdt), dev(inst.w, npdt)
+        self.v0, self.lam = dev(inst.v0, npdt), dev(inst.lam, npdt)
+        self.r, self.c = dev(inst.r, npdt), dev(inst.c, npdt)
+        if inst.a_ptr is None:
+            self.a_ptr = self.a_idx = self.a_val = None
+        else:
+            self.a_ptr = dev(inst.a_ptr, np.int64)
+            self.a_idx = dev(inst.a_idx, np.int32)
+            self.a_val = dev(inst.a_val, npdt)
+        self.nnz = int(inst.seg_ptr[-1])
+        self.h = cblp_create(self.L, self.n, self.m, self.seg_ptr, self.idx, self.v, self.w,
+                             self.v0, self.lam, self.r, self.a_ptr, self.a_idx, self.a_val,
+                             self.c, CBLP_F32 if dtype == torch.float32 else CBLP_F64)
+
+    def close(self):
+        if getattr(self, "h", None):
+            cblp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def zeros_eta(self) -> torch.Tensor:
+        return torch.zeros(self.m, dtype=self.dtype, device=self.device)
+
+    def tensor(self, a) -> torch.Tensor:
+        return torch.as_tensor(np.asarray(a), dtype=self.dtype).to(self.device)
+
+    def reset(self):
+        spfom_reset(self.h)
+
+    def iterate(self, eta: torch.Tensor, iters: int, params: SpfomParams, trace: bool = True):
+        tr = np.zeros((int(iters), NTRACE)) if trace else None
+        st = SpfomStats()
+        spfom_iterate(self.h, eta, params, iters, tr, st)
+        return tr, st
+
+    def solve(self, eta: torch.Tensor, params: SpfomParams) -> SpfomStats:
+        return spfom_solve(self.h, eta, params)
+
+    def gap(self, eta: torch.Tensor) -> dict:
+        return cblp_gap(self.h, eta).as_dict()
+
+    def sales(self, eta: torch.Tensor, seg_R: bool = False):
+        S = torch.zeros(self.n, dtype=torch.float64, device=self.device)
+        u = torch.zeros(self.m, dtype=torch.float64, device=self.device)
+        R = torch.zeros(self.L, dtype=self.dtype, device=self.device) if seg_R else None
+        cblp_sales(self.h, eta, S, u, R)
+        return S, u, R

@@ -1,0 +1,250 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
+
+Every instance is seeded and synthetic; the FP32 cases feed the oracle the
+same FP32-rounded inputs promoted to FP64.  Bars: FP64 iterates within 1e-8
+relative (1e-5 after long runs, where a near-tie in a best response can
+flip); FP32 iterates within 1e-5 relative at equal iteration counts on the
+duals, the dual bound and the primal revenue.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2602_22421_amd.instances import (config_instance, make_instance, step_scale)
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+@pytest.fixture(scope="module")
+def cb():
+    _need_gpu()
+    from paper_2602_22421_amd import cblp
+    cblp.load()
+    return cblp
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def _pair(cb, inst, dtype, tau0=0.01, rule=0, gamma=1.0, mu=0.0, K=10):
+    """GPU problem + oracle solver with the same (dtype-rounded) inputs."""
+    npdt = np.float32 if dtype == torch.float32 else np.float64
+    src = inst.cast(npdt)
+    prob = cb.Problem(src, dtype=dtype)
+    tau = step_scale(src, tau0 if rule == 0 else 1.0).astype(npdt)
+    tau_dev = prob.tensor(tau)
+    params = cb.make_params(rule=rule, check_every=K, tau_vec=tau_dev, gamma=gamma, mu=mu)
+    orc = oracle.Solver(src, tau=tau.astype(np.float64), rule=rule, gamma=gamma, mu=mu,
+                        check_every=K)
+    return prob, params, orc, src
+
+
+def _run_both(prob, params, orc, iters_list, eta0=None):
+    eta_g = prob.zeros_eta() if eta0 is None else prob.tensor(eta0)
+    eta_o = np.zeros(prob.m) if eta0 is None else np.asarray(eta0, dtype=np.float64)
+    out = []
+    done = 0
+    for t in iters_list:
+        tr_g, _ = prob.iterate(eta_g, t - done, params)
+        eta_o, tr_o = orc.iterate(eta_o, t - done)
+        done = t
+        out.append((t, eta_g.double().cpu().numpy(), eta_o.copy(), tr_g, tr_o))
+    return out
+
+
+# ---------------------------------------------------------------- single pass
+
+def test_sales_fp64_config0(cb):
+    inst = config_instance(0)
+    prob = cb.Problem(inst, dtype=torch.float64)
+    rng = np.random.default_rng(1)
+    for trial in range(3):
+        eta = rng.uniform(0, 80, inst.m) * (trial > 0)
+        S, u, R = prob.sales(prob.tensor(eta), seg_R=True)
+        br = oracle.best_response(inst, eta)
+        np.testing.assert_allclose(R.cpu().numpy(), br["seg_R"], rtol=1e-12, atol=1e-13)
+        np.testing.assert_allclose(S.cpu().numpy(), br["S"], rtol=1e-11, atol=1e-11)
+        np.testing.assert_allclose(u.cpu().numpy(), br["u"], rtol=1e-11, atol=1e-11)
+        g = prob.gap(prob.tensor(eta))
+        assert g["D"] == pytest.approx(br["D"], rel=1e-12)
+        assert g["Z"] == pytest.approx(br["Z"], rel=1e-12)
+        assert g["P"] == pytest.approx(br["P"], rel=1e-11)
+
+
+def test_sales_fp32_scaled_zipf(cb):
+    inst = config_instance(1, scale=0.01).cast(np.float32)
+    prob = cb.Problem(inst, dtype=torch.float32)
+    rng = np.random.default_rng(2)
+    eta = (rng.uniform(0, 60, inst.m)).astype(np.float32)
+    S, u, R = prob.sales(prob.tensor(eta), seg_R=True)
+    br = oracle.best_response(inst, eta.astype(np.float64))
+    np.testing.assert_allclose(R.double().cpu().numpy(), br["seg_R"], rtol=2e-5, atol=1e-5)
+    assert rel(S.cpu().numpy(), br["S"]) <= 1e-5
+    g = prob.gap(prob.tensor(eta))
+    assert g["D"] == pytest.approx(br["D"], rel=1e-6)
+    assert g["P"] == pytest.approx(br["P"], rel=1e-5)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_sales_resources(cb, dtype):
+    dt = torch.float64 if dtype == "f64" else torch.float32
+    npdt = np.float64 if dtype == "f64" else np.float32
+    inst = config_instance(2, scale=0.002).cast(npdt)
+    prob = cb.Problem(inst, dtype=dt)
+    rng = np.random.default_rng(3)
+    eta = rng.uniform(0, 30, inst.m).astype(npdt)
+    S, u, R = prob.sales(prob.tensor(eta), seg_R=True)
+    br = oracle.best_response(inst, eta.astype(np.float64))
+    tol = 1e-11 if dtype == "f64" else 2e-5
+    np.testing.assert_allclose(R.double().cpu().numpy(), br["seg_R"], rtol=tol, atol=tol)
+    assert rel(u.cpu().numpy(), br["u"]) <= tol
+    assert prob.gap(prob.tensor(eta))["D"] == pytest.approx(br["D"], rel=tol)
+
+
+def test_long_segments_use_streamed_path(cb):
+    """Consideration sets longer than the 64 register-cached products."""
+    inst = make_instance(300, 400, size_lo=60, size_hi=300, zipf=1.1, seed=11, cap_lo=0.3)
+    prob = cb.Problem(inst, dtype=torch.float64)
+    eta = np.random.default_rng(4).uniform(0, 50, inst.m)
+    S, u, R = prob.sales(prob.tensor(eta), seg_R=True)
+    br = oracle.best_response(inst, eta)
+    np.testing.assert_allclose(R.cpu().numpy(), br["seg_R"], rtol=1e-12, atol=1e-13)
+    np.testing.assert_allclose(S.cpu().numpy(), br["S"], rtol=1e-11, atol=1e-11)
+
+
+def test_degenerate_segments(cb):
+    """Empty consideration sets, single products, zero arrival rates."""
+    inst = make_instance(500, 30, size_lo=0, size_hi=3, seed=12, cap_lo=0.3)
+    inst.lam[::7] = 0.0
+    prob = cb.Problem(inst, dtype=torch.float64)
+    eta = np.random.default_rng(5).uniform(0, 90, inst.m)
+    S, u, R = prob.sales(prob.tensor(eta), seg_R=True)
+    br = oracle.best_response(inst, eta)
+    assert (np.diff(inst.seg_ptr) == 0).any()
+    np.testing.assert_allclose(R.cpu().numpy(), br["seg_R"], rtol=1e-12, atol=1e-13)
+    np.testing.assert_allclose(S.cpu().numpy(), br["S"], rtol=1e-11, atol=1e-11)
+
+
+def test_no_segments(cb):
+    inst = make_instance(0, 5, seed=0)
+    inst.c[:] = 2.0
+    prob, params, orc, _ = _pair(cb, inst, torch.float64, tau0=0.1)
+    res = _run_both(prob, params, orc, [3], eta0=np.full(5, 1.0))
+    t, eg, eo, trg, tro = res[0]
+    np.testing.assert_allclose(eg, eo, rtol=1e-14)
+    np.testing.assert_allclose(trg[:, :5], tro[:, :5], rtol=1e-13)
+
+
+# ---------------------------------------------------------------- iterations
+
+@pytest.mark.parametrize("rule", [0, 1])
+def test_iterate_fp64_config0(cb, rule):
+    inst = config_instance(0)
+    prob, params, orc, _ = _pair(cb, inst, torch.float64, tau0=0.002, rule=rule)
+    for t, eg, eo, trg, tro in _run_both(prob, params, orc, [1, 10, 100, 1000]):
+        bar = 1e-8 if t <= 100 else 1e-5
+        assert rel(eg, eo) <= bar, (t, rel(eg, eo))
+        for col in (0, 1, 2, 5, 6):
+            assert rel(trg[:, col], tro[:, col]) <= bar, (t, col)
+
+
+def test_iterate_fp32_scaled_zipf(cb):
+    inst = config_instance(1, scale=0.01)
+    prob, params, orc, _ = _pair(cb, inst, torch.float32, tau0=0.001)
+    for t, eg, eo, trg, tro in _run_both(prob, params, orc, [1, 10, 100]):
+        assert rel(eg, eo) <= 1e-5, (t, rel(eg, eo))
+        assert rel(trg[-1, 0], tro[-1, 0]) <= 1e-5
+        assert rel(trg[-1, 1], tro[-1, 1]) <= 1e-5
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_iterate_resources(cb, dtype):
+    dt = torch.float64 if dtype == "f64" else torch.float32
+    inst = config_instance(2, scale=0.002)
+    prob, params, orc, _ = _pair(cb, inst, dt, tau0=0.001, rule=0, mu=0.01)
+    bar = 1e-8 if dtype == "f64" else 1e-5
+    for t, eg, eo, trg, tro in _run_both(prob, params, orc, [1, 10, 60]):
+        assert rel(eg, eo) <= bar, (t, rel(eg, eo))
+        assert rel(trg[-1, 0], tro[-1, 0]) <= bar
+
+
+def test_bitwise_deterministic(cb):
+    inst = config_instance(1, scale=0.01).cast(np.float32)
+    out = []
+    for _ in range(2):
+        prob = cb.Problem(inst, dtype=torch.float32)
+        params = cb.make_params(tau=0.05)
+        eta = prob.zeros_eta()
+        tr, _ = prob.iterate(eta, 30, params)
+        out.append((eta.cpu().numpy().tobytes(), tr.tobytes()))
+        prob.close()
+    assert out[0] == out[1]
+
+
+def test_solve_config0_reaches_lp_optimum(cb):
+    import os
+    inst = config_instance(0)
+    with open(os.path.join(os.path.dirname(__file__), "golden", "config0_lp.txt")) as f:
+        opt = float([ln for ln in f if ln.startswith("opt")][0].split()[1])
+    prob = cb.Problem(inst, dtype=torch.float64)
+    tau = prob.tensor(step_scale(inst, 1.0))
+    params = cb.make_params(rule=1, tau_vec=tau, gamma=1.0, check_every=10, tol=1e-4,
+                            max_iters=5000)
+    st = prob.solve(prob.zeros_eta(), params).as_dict()
+    assert st["status"] == 0, st
+    assert st["lb"] <= opt * (1 + 1e-12) <= st["dbest"] * (1 + 2e-12)
+    assert abs(st["dbest"] - opt) / opt <= 1e-4 and abs(opt - st["lb"]) / opt <= 1e-4
+
+
+# ---------------------------------------------------------------- validation
+
+@pytest.mark.parametrize("bad", ["w_ge_v", "idx_range", "neg_cap", "nan_v", "zero_v0"])
+def test_create_rejects_invalid(cb, bad):
+    inst = config_instance(0)
+    if bad == "w_ge_v":
+        inst.w[5] = inst.v[5]
+    elif bad == "idx_range":
+        inst.idx[3] = inst.n
+    elif bad == "neg_cap":
+        inst.c[2] = -1.0
+    elif bad == "nan_v":
+        inst.v[7] = np.nan
+    elif bad == "zero_v0":
+        inst.v0[4] = 0.0
+    with pytest.raises(cb.CblpError) as e:
+        cb.Problem(inst, dtype=torch.float64)
+    assert e.value.code == cb.CBLP_EINVAL
+
+
+# ---------------------------------------------------------------- full size
+
+def test_full_size_zipf_sampled(cb):
+    """The L=2e6, n=2e4 workload in the benchmark's launch configuration:
+    per-segment R* on a sample of segments and the totals of one pass."""
+    inst = config_instance(1).cast(np.float32)
+    prob = cb.Problem(inst, dtype=torch.float32)
+    rng = np.random.default_rng(6)
+    eta = (rng.uniform(0, 1, inst.m) * inst.r * 0.6).astype(np.float32)
+    S, u, R = prob.sales(prob.tensor(eta), seg_R=True)
+    R = R.double().cpu().numpy()
+    rho = inst.r.astype(np.float64) - eta.astype(np.float64)
+    for l in rng.choice(inst.L, 2000, replace=False):
+        b, e = inst.seg_ptr[l], inst.seg_ptr[l + 1]
+        Ro, _, _ = oracle.segment_response(rho[inst.idx[b:e]], inst.v[b:e], inst.w[b:e],
+                                           float(inst.v0[l]), float(inst.lam[l]))
+        assert R[l] == pytest.approx(Ro, rel=2e-5, abs=1e-5), l
+    # sum of sales equals the sum of per-segment sales totals (any size)
+    g = prob.gap(prob.tensor(eta))
+    assert g["Z"] == pytest.approx(float(np.dot(inst.lam.astype(np.float64), R)), rel=1e-6)
+    Sg = S.cpu().numpy()
+    assert np.all(Sg >= 0) and g["P"] == pytest.approx(float(np.dot(inst.r, Sg)), rel=1e-9)
