@@ -132,9 +132,10 @@ def main():
                 "peak": HBM_PEAK / 1e9, "unit": "GB/s", "frac": achieved / HBM_PEAK,
                 "traffic": None, "bytes_per_launch": nbytes, "per_unit_bytes": per,
                 "kernel_avg_us": seg_avg * 1e6,
-                "dual_kernel_avg_us": dual_ms * 1e3 / max(dual_n, 1)}
+                "dual_phase_avg_us": dual_ms * 1e3 / max(dual_n, 1),
+                "launch": cblp.cblp_launch_info(prob.h)}
         log(f"segment kernel {seg_avg * 1e6:.1f} us/launch, {achieved / 1e9:.0f} GB/s "
-            f"({100 * achieved / HBM_PEAK:.1f}% of HBM peak); dual kernel "
+            f"({100 * achieved / HBM_PEAK:.1f}% of HBM peak); dual phase "
             f"{dual_ms * 1e3 / max(dual_n, 1):.1f} us/launch")
     st = prob.gap(eta)
     cpu = None

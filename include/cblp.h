@@ -63,7 +63,7 @@ enum {
     SPFOM_TR_DUAL = 0,      /* D^t = c . eta^{t-1} + sum_l lambda_l R*_l(eta^{t-1}) */
     SPFOM_TR_PRIMAL = 1,    /* P^t = sum_j r_j S^t_j, revenue of the best responses */
     SPFOM_TR_Z = 2,         /* sum_l lambda_l R*_l */
-    SPFOM_TR_ETA2 = 3,      /* ||eta^t||^2 */
+    SPFOM_TR_ETA2 = 3,      /* ||eta^{t-1}||^2, the duals the pass was taken at */
     SPFOM_TR_INFEAS = 4,    /* sum_i (u^t_i - c_i)^+ */
     SPFOM_TR_DBEST = 5,     /* min_{s<=t} D^s (upper bound on the LP optimum) */
     SPFOM_TR_LB = 6,        /* best certified feasible revenue (lower bound) */
@@ -165,9 +165,18 @@ int cblp_sales(cblp_t h, const void* eta, double* S_out, double* u_out, void* se
                void* stream);
 
 /*
+ * cblp_launch_info - the launch shape chosen at cblp_create: number of
+ * segment-kernel blocks, number of LDS sales bins per block (products
+ * [0, bins) are accumulated in LDS) and the fixed-point fraction bits of the
+ * sales accumulators.  Each [host] pointer is nullable.
+ */
+int cblp_launch_info(cblp_t h, int32_t* seg_grid, int32_t* bins, int32_t* fx_bits);
+
+/*
  * cblp_timing - enable (1) or disable (0) per-launch timing: while enabled,
- * every launch of the segment kernel (id 0) and of the dual-step kernel
- * (id 1) is bracketed by a pair of HIP events on the launch stream.  Enabling
+ * every launch of the segment kernel (id 0) and every dual phase (id 1: the
+ * sales fold, reductions and dual-step kernels of one iteration) is
+ * bracketed by a pair of HIP events on the launch stream.  Enabling
  * clears earlier records.
  * cblp_timing_read - synchronise the stream and return the summed kernel
  * times ms[2] (milliseconds) and launch counts launches[2] ([host] arrays

@@ -286,10 +286,10 @@ int orc_iterate(const orc_instance* I, const orc_params* prm, orc_state* st,
         for (int64_t i = 0; i < m; ++i) {
             double ti = scale * prm->tau[i];
             double g = u[i] - I->c[i];
+            e2 += eta[i] * eta[i];          /* the duals the pass was taken at */
             double e = (1.0 - ti * prm->mu) * eta[i] + ti * g;
             eta[i] = e > 0.0 ? e : 0.0;
             if (g > 0.0) infeas += g;
-            e2 += eta[i] * eta[i];
         }
         if (trace) {
             double* tr = trace + it * ORC_NTRACE;

@@ -23,7 +23,8 @@ SPFOM_STEP_CONST, SPFOM_STEP_POLYAK = 0, 1
 NTRACE = 10
 TRACE_COLS = ("D", "P", "Z", "eta2", "infeas", "dbest", "lb", "gap", "step", "theta")
 EXPORTS = ("cblp_create", "cblp_destroy", "spfom_reset", "spfom_iterate", "spfom_solve",
-           "cblp_gap", "cblp_sales", "cblp_timing", "cblp_timing_read", "cblp_last_error")
+           "cblp_gap", "cblp_sales", "cblp_launch_info", "cblp_timing", "cblp_timing_read",
+           "cblp_last_error")
 
 
 class SpfomParams(ctypes.Structure):
@@ -77,6 +78,9 @@ def load(path: str = _LIB_PATH) -> ctypes.CDLL:
     lib.cblp_gap.argtypes = [vp, vp, ctypes.POINTER(SpfomStats), vp]
     lib.cblp_sales.restype = ctypes.c_int
     lib.cblp_sales.argtypes = [vp, vp, vp, vp, vp, vp]
+    lib.cblp_launch_info.restype = ctypes.c_int
+    lib.cblp_launch_info.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32),
+                                     ctypes.POINTER(i32)]
     lib.cblp_timing.restype = ctypes.c_int
     lib.cblp_timing.argtypes = [vp, i32]
     lib.cblp_timing_read.restype = ctypes.c_int
@@ -156,6 +160,13 @@ def cblp_gap(h, eta, stream=None) -> SpfomStats:
 def cblp_sales(h, eta, S_out=None, u_out=None, seg_R_out=None, stream=None) -> None:
     _check(load().cblp_sales(ctypes.c_void_p(h), _ptr(eta), _ptr(S_out), _ptr(u_out),
                              _ptr(seg_R_out), _stream(stream)))
+
+
+def cblp_launch_info(h) -> dict:
+    g, b, f = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    _check(load().cblp_launch_info(ctypes.c_void_p(h), ctypes.byref(g), ctypes.byref(b),
+                                   ctypes.byref(f)))
+    return {"seg_grid": g.value, "lds_bins": b.value, "fx_bits": f.value}
 
 
 def cblp_timing(h, enable: bool) -> None:

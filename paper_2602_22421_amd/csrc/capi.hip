@@ -1,0 +1,647 @@
+// libcblp host side: the C ABI of include/cblp.h.
+//
+// One SPFOM iteration (Algorithm 3 with every segment sampled, dual step
+// eq. 16) is a short fixed sequence of launches on the caller's stream:
+//   k_segments                 per-segment best responses and sales scatter
+//   k_fold [k_rows] k_update   sales totals, FP64 reductions, dual step
+//   [k_prices_after]           rho = r - A^T eta for a general A
+// Nothing is read back per iteration; spfom_solve copies one 80-byte trace
+// row to pinned host memory every check_every iterations.
+#include <algorithm>
+#include <cfloat>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "common.hpp"
+
+using namespace cblp;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg)
+{
+    g_err = msg;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                  \
+    do {                                                                               \
+        hipError_t e_ = (expr);                                                        \
+        if (e_ != hipSuccess)                                                          \
+            return fail(CBLP_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+const char* kValidationText[V_NBITS] = {
+    "product index outside [0, n)", "attraction v not finite and > 0",
+    "shadow attraction w outside [0, v)", "no-purchase attraction v0 not finite and > 0",
+    "arrival rate lambda not finite and >= 0", "seg_ptr not non-decreasing from 0 to nnz",
+    "revenue r not finite", "capacity c not finite and >= 0",
+    "resource index outside [0, m)", "resource weight a not finite and >= 0",
+    "a_ptr not non-decreasing from 0 to nnzA"};
+
+// LDS bins per segment block: at most this many, and at most what one block
+// may allocate besides its static shared memory.
+constexpr int kMaxBins = 16384;
+
+}  // namespace
+
+struct cblp_instance {
+    int device = 0;
+    int dtype = CBLP_F32;
+    size_t esz = 4;
+    int64_t L = 0, n = 0, m = 0, nnz = 0, nnzA = 0;
+    const int64_t* seg_ptr = nullptr;
+    const int32_t* idx = nullptr;
+    const void *v = nullptr, *w = nullptr, *v0 = nullptr, *lam = nullptr;
+    const void *r = nullptr, *c = nullptr;
+    const int64_t* a_ptr = nullptr;
+    const int32_t* a_idx = nullptr;
+    const void* a_val = nullptr;
+    // owned workspace
+    void* vt0 = nullptr;
+    void* rho = nullptr;
+    unsigned long long* S_fx = nullptr;
+    unsigned long long* part_S = nullptr;
+    double* S_d = nullptr;
+    double* u_d = nullptr;
+    double* sum_u = nullptr;
+    double* zpart = nullptr;
+    double* bpart = nullptr;
+    double* bpart2 = nullptr;
+    DevState* st = nullptr;         // [2], double-buffered
+    double* trace = nullptr;
+    int64_t trace_rows = 0;
+    int64_t* at_ptr = nullptr;
+    int32_t* at_prod = nullptr;
+    double* at_val = nullptr;
+    double* pinned = nullptr;
+    int seg_grid = 1;
+    int H = 0;
+    int fold_blocks = 1;
+    double fx_scale = 1.0;
+    int64_t t = 0;
+    bool timing = false;
+    std::vector<hipEvent_t> ev_pool;
+    size_t ev_used = 0;
+    std::vector<std::pair<int, size_t>> ev_marks;
+};
+
+namespace {
+
+template <typename P>
+int dalloc(P** p, size_t bytes)
+{
+    *p = nullptr;
+    if (bytes == 0) bytes = 8;
+    if (hipMalloc((void**)p, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(CBLP_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+    }
+    return CBLP_OK;
+}
+
+void release(cblp_instance* h)
+{
+    if (!h) return;
+    void* ptrs[] = {h->vt0, h->rho, h->S_fx, h->part_S, h->S_d, h->u_d, h->sum_u, h->zpart,
+                    h->bpart, h->bpart2, h->st, h->trace, h->at_ptr,
+                    h->at_prod, h->at_val};
+    for (void* p : ptrs)
+        if (p) (void)hipFree(p);
+    if (h->pinned) (void)hipHostFree(h->pinned);
+    for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
+    delete h;
+}
+
+inline hipStream_t S(void* s) { return (hipStream_t)s; }
+
+int timed_begin(cblp_instance* h, int kernel, hipStream_t s, size_t* slot)
+{
+    *slot = SIZE_MAX;
+    if (!h->timing) return CBLP_OK;
+    while (h->ev_pool.size() < h->ev_used + 2) {
+        hipEvent_t e;
+        HIP_TRY(hipEventCreate(&e));
+        h->ev_pool.push_back(e);
+    }
+    *slot = h->ev_used;
+    h->ev_used += 2;
+    h->ev_marks.emplace_back(kernel, *slot);
+    HIP_TRY(hipEventRecord(h->ev_pool[*slot], s));
+    return CBLP_OK;
+}
+
+int timed_end(cblp_instance* h, size_t slot, hipStream_t s)
+{
+    if (slot == SIZE_MAX) return CBLP_OK;
+    HIP_TRY(hipEventRecord(h->ev_pool[slot + 1], s));
+    return CBLP_OK;
+}
+
+int ensure_trace(cblp_instance* h, int64_t rows)
+{
+    if (rows <= h->trace_rows) return CBLP_OK;
+    if (h->trace) (void)hipFree(h->trace);
+    h->trace = nullptr;
+    h->trace_rows = 0;
+    int rc = dalloc(&h->trace, (size_t)rows * SPFOM_NTRACE * sizeof(double));
+    if (rc) return rc;
+    h->trace_rows = rows;
+    return CBLP_OK;
+}
+
+int check_params(const spfom_params* p)
+{
+    if (!p) return fail(CBLP_EINVAL, "params is NULL");
+    if (p->rule != SPFOM_STEP_CONST && p->rule != SPFOM_STEP_POLYAK)
+        return fail(CBLP_EINVAL, "unknown step rule");
+    if (p->check_every < 1) return fail(CBLP_EINVAL, "check_every must be >= 1");
+    if (!p->tau_vec && !(p->tau > 0.0 && std::isfinite(p->tau)))
+        return fail(CBLP_EINVAL, "tau must be finite and > 0");
+    if (!(p->mu >= 0.0) || !std::isfinite(p->mu)) return fail(CBLP_EINVAL, "mu must be >= 0");
+    if (p->rule == SPFOM_STEP_POLYAK && !(p->gamma > 0.0 && p->gamma <= 2.0))
+        return fail(CBLP_EINVAL, "gamma must be in (0, 2]");
+    return CBLP_OK;
+}
+
+template <typename T>
+int run_segments(cblp_instance* h, void* seg_R, hipStream_t s)
+{
+    SegArgs a;
+    a.L = h->L;
+    a.seg_ptr = h->seg_ptr;
+    a.idx = h->idx;
+    a.v = h->v;
+    a.w = h->w;
+    a.vt0 = h->vt0;
+    a.lam = h->lam;
+    a.rho = h->rho;
+    a.H = h->H;
+    a.part_S = h->part_S;
+    a.S_fx = h->S_fx;
+    a.fx_scale = h->fx_scale;
+    a.zpart = h->zpart;
+    a.seg_R = seg_R;
+    size_t slot;
+    int rc = timed_begin(h, 0, s, &slot);
+    if (rc) return rc;
+    HIP_TRY(launch_segments<T>(a, h->seg_grid, s));
+    return timed_end(h, slot, s);
+}
+
+template <typename T>
+int run_phase(cblp_instance* h, void* eta, const spfom_params* p, int mode, double* row,
+              hipStream_t s)
+{
+    PhaseArgs a;
+    a.n = h->n;
+    a.m = h->m;
+    a.mode = mode;
+    a.rule = p ? p->rule : 0;
+    a.check_every = p ? p->check_every : 1;
+    a.gamma = p ? p->gamma : 1.0;
+    a.mu = p ? p->mu : 0.0;
+    a.tau_s = p ? p->tau : 1.0;
+    a.tau_vec = p ? p->tau_vec : nullptr;
+    a.zpart = h->zpart;
+    a.nz = h->seg_grid;
+    a.part_S = h->part_S;
+    a.nseg = h->seg_grid;
+    a.H = h->H;
+    a.S_fx = h->S_fx;
+    a.inv_fx = 1.0 / h->fx_scale;
+    a.r = h->r;
+    a.c = h->c;
+    a.a_ptr = h->a_ptr;
+    a.a_idx = h->a_idx;
+    a.a_val = h->a_val;
+    a.at_ptr = h->at_ptr;
+    a.at_prod = h->at_prod;
+    a.at_val = h->at_val;
+    a.eta = eta;
+    a.rho = h->rho;
+    a.S_d = h->S_d;
+    a.u_d = h->u_d;
+    a.sum_u = h->sum_u;
+    a.bpart = h->bpart;
+    a.bpart2 = h->bpart2;
+    a.fold_blocks = h->fold_blocks;
+    a.st = h->st;
+    a.par = (int)(h->t & 1);
+    a.row = row;
+    size_t slot;
+    int rc = timed_begin(h, 1, s, &slot);
+    if (rc) return rc;
+    HIP_TRY(launch_phase<T>(a, h->a_ptr == nullptr, s));
+    return timed_end(h, slot, s);
+}
+
+template <typename T>
+int iterate_impl(cblp_instance* h, void* eta, const spfom_params* p, int64_t iters,
+                 bool keep_trace, hipStream_t s)
+{
+    HIP_TRY(launch_prices<T>(h->n, h->r, eta, h->a_ptr, h->a_idx, h->a_val, h->rho, s));
+    int rc;
+    for (int64_t it = 0; it < iters; ++it) {
+        double* row = h->trace + (keep_trace ? it : 0) * SPFOM_NTRACE;
+        if ((rc = run_segments<T>(h, nullptr, s))) return rc;
+        if ((rc = run_phase<T>(h, eta, p, 0, row, s))) return rc;
+        h->t += 1;
+    }
+    return CBLP_OK;
+}
+
+template <typename T>
+int evaluate_impl(cblp_instance* h, const void* eta, void* seg_R, hipStream_t s)
+{
+    HIP_TRY(launch_prices<T>(h->n, h->r, eta, h->a_ptr, h->a_idx, h->a_val, h->rho, s));
+    int rc = run_segments<T>(h, seg_R, s);
+    if (rc) return rc;
+    // evaluation leaves eta and the solver state untouched
+    return run_phase<T>(h, const_cast<void*>(eta), nullptr, 1, h->trace, s);
+}
+
+int fill_stats(cblp_instance* h, spfom_stats* out, hipStream_t s, const double* dev_row)
+{
+    HIP_TRY(hipMemcpyAsync(h->pinned, dev_row, SPFOM_NTRACE * sizeof(double),
+                           hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    bool finite = true;
+    for (int q = 0; q < SPFOM_NTRACE; ++q) finite = finite && std::isfinite(h->pinned[q]);
+    if (out) {
+        out->iters = h->t;
+        std::memcpy(out->trace, h->pinned, sizeof(out->trace));
+        out->status = finite ? CBLP_OK : CBLP_ENONFINITE;
+    }
+    if (!finite) return fail(CBLP_ENONFINITE, "non-finite value in the trace row");
+    return CBLP_OK;
+}
+
+int reset_state(cblp_instance* h, hipStream_t s)
+{
+    DevState st[2];
+    std::memset(st, 0, sizeof(st));
+    st[0].dbest = st[1].dbest = INFINITY;
+    HIP_TRY(hipMemcpyAsync(h->st, st, sizeof(st), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemsetAsync(h->sum_u, 0, (size_t)h->m * sizeof(double), s));
+    HIP_TRY(hipStreamSynchronize(s));
+    h->t = 0;
+    return CBLP_OK;
+}
+
+template <typename T>
+int build_transpose(cblp_instance* h, const std::vector<int64_t>& hap, hipStream_t s)
+{
+    const int64_t nA = h->nnzA, n = h->n, m = h->m;
+    std::vector<int32_t> ai((size_t)std::max<int64_t>(nA, 1));
+    std::vector<T> avT((size_t)std::max<int64_t>(nA, 1));
+    if (nA > 0) {
+        HIP_TRY(hipMemcpyAsync(ai.data(), h->a_idx, nA * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(avT.data(), h->a_val, nA * sizeof(T), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+    }
+    std::vector<int64_t> tp((size_t)m + 1, 0);
+    for (int64_t q = 0; q < nA; ++q) tp[ai[q] + 1]++;
+    for (int64_t i = 0; i < m; ++i) tp[i + 1] += tp[i];
+    std::vector<int64_t> fillp(tp.begin(), tp.end() - 1);
+    std::vector<int32_t> tprod((size_t)std::max<int64_t>(nA, 1));
+    std::vector<double> tval((size_t)std::max<int64_t>(nA, 1));
+    for (int64_t j = 0; j < n; ++j)      // products in increasing order: fixed sum order
+        for (int64_t q = hap[j]; q < hap[j + 1]; ++q) {
+            const int64_t dst = fillp[ai[q]]++;
+            tprod[dst] = (int32_t)j;
+            tval[dst] = (double)avT[q];
+        }
+    int rc;
+    if ((rc = dalloc(&h->at_ptr, (m + 1) * sizeof(int64_t)))) return rc;
+    if ((rc = dalloc(&h->at_prod, std::max<int64_t>(nA, 1) * sizeof(int32_t)))) return rc;
+    if ((rc = dalloc(&h->at_val, std::max<int64_t>(nA, 1) * sizeof(double)))) return rc;
+    HIP_TRY(hipMemcpyAsync(h->at_ptr, tp.data(), (m + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    if (nA > 0) {
+        HIP_TRY(hipMemcpyAsync(h->at_prod, tprod.data(), nA * sizeof(int32_t), hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync(h->at_val, tval.data(), nA * sizeof(double), hipMemcpyHostToDevice, s));
+    }
+    HIP_TRY(hipStreamSynchronize(s));
+    return CBLP_OK;
+}
+
+template <typename T>
+int create_impl(cblp_instance* h, hipStream_t s)
+{
+    int rc;
+    std::vector<int64_t> hap;
+    const bool ident = h->a_ptr == nullptr;
+    if (!ident) {
+        hap.resize((size_t)h->n + 1);
+        HIP_TRY(hipMemcpyAsync(hap.data(), h->a_ptr, (h->n + 1) * sizeof(int64_t),
+                               hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        h->nnzA = hap[h->n];
+        if (h->nnzA < 0) return fail(CBLP_EINVAL, "a_ptr[n] < 0");
+    }
+    // validation on the device
+    unsigned* dflags = nullptr;
+    if ((rc = dalloc(&dflags, sizeof(unsigned)))) return rc;
+    unsigned flags = 0;
+    hipError_t e0 = hipMemsetAsync(dflags, 0, sizeof(unsigned), s);
+    hipError_t e1 = e0 == hipSuccess
+                        ? launch_validate<T>(h->L, h->n, h->m, h->nnz, h->nnzA, h->seg_ptr, h->idx,
+                                             h->v, h->w, h->v0, h->lam, h->r, h->c, h->a_ptr,
+                                             h->a_idx, h->a_val, dflags, s)
+                        : e0;
+    hipError_t e2 = e1 == hipSuccess
+                        ? hipMemcpyAsync(&flags, dflags, sizeof(unsigned), hipMemcpyDeviceToHost, s)
+                        : e1;
+    hipError_t e3 = hipStreamSynchronize(s);
+    (void)hipFree(dflags);
+    if (e2 != hipSuccess || e3 != hipSuccess) return fail(CBLP_EHIP, "validation kernel failed");
+    if (flags) {
+        std::string msg = "invalid instance:";
+        for (int b = 0; b < V_NBITS; ++b)
+            if (flags & (1u << b)) msg += std::string(" ") + kValidationText[b] + ";";
+        return fail(CBLP_EINVAL, msg);
+    }
+
+    // launch shape: every resident 1024-thread segment block of every CU, each
+    // with H LDS bins; blocks stride over tiles of 64 segments
+    int cus = 256;
+    size_t lds_block = 64 * 1024;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, h->device) == hipSuccess) {
+        if (prop.multiProcessorCount > 0) cus = prop.multiProcessorCount;
+        if (prop.sharedMemPerBlock > 0) lds_block = prop.sharedMemPerBlock;
+    }
+    const int64_t lds_bins = ((int64_t)lds_block - 1024) / 8;
+    h->H = (int)std::max<int64_t>(1, std::min<int64_t>({h->n, (int64_t)kMaxBins, lds_bins}));
+    const int per_cu = segment_blocks_per_cu<T>(h->H);
+    const int64_t tiles = (h->L + kSegsPerTile - 1) / kSegsPerTile;
+    h->seg_grid = (int)std::max<int64_t>(1, std::min<int64_t>(tiles, (int64_t)cus * per_cu));
+    h->fold_blocks = (int)((h->n + kFoldProducts - 1) / kFoldProducts);
+    const int64_t row_blocks = (h->m + kRowThreads - 1) / kRowThreads;
+
+    const size_t esz = h->esz;
+    if ((rc = dalloc(&h->vt0, (size_t)std::max<int64_t>(h->L, 1) * esz))) return rc;
+    if ((rc = dalloc(&h->rho, (size_t)h->n * esz))) return rc;
+    if ((rc = dalloc(&h->S_fx, (size_t)h->n * 8))) return rc;
+    if ((rc = dalloc(&h->part_S, (size_t)h->seg_grid * std::max(h->H, 1) * 8))) return rc;
+    if ((rc = dalloc(&h->S_d, (size_t)h->n * 8))) return rc;
+    if ((rc = dalloc(&h->u_d, (size_t)h->m * 8))) return rc;
+    if ((rc = dalloc(&h->sum_u, (size_t)h->m * 8))) return rc;
+    if ((rc = dalloc(&h->zpart, (size_t)h->seg_grid * 8))) return rc;
+    if ((rc = dalloc(&h->bpart, (size_t)h->fold_blocks * 8 * 8))) return rc;
+    if ((rc = dalloc(&h->bpart2, (size_t)std::max<int64_t>(row_blocks, 1) * 8 * 8))) return rc;
+    if ((rc = dalloc(&h->st, 2 * sizeof(DevState)))) return rc;
+    if ((rc = ensure_trace(h, 64))) return rc;
+    if (hipHostMalloc((void**)&h->pinned, SPFOM_NTRACE * sizeof(double), hipHostMallocDefault) != hipSuccess)
+        return fail(CBLP_ENOMEM, "hipHostMalloc failed");
+
+    // vt0 and the arrival-rate total that bounds every product's sales
+    const int pblocks = 256;
+    double* lp = nullptr;
+    if ((rc = dalloc(&lp, pblocks * sizeof(double)))) return rc;
+    std::vector<double> hl(pblocks);
+    hipError_t p1 = launch_prepare<T>(h->L, h->seg_ptr, h->w, h->v0, h->lam, h->vt0, lp, pblocks, s);
+    hipError_t p2 = p1 == hipSuccess
+                        ? hipMemcpyAsync(hl.data(), lp, pblocks * sizeof(double), hipMemcpyDeviceToHost, s)
+                        : p1;
+    hipError_t p3 = hipStreamSynchronize(s);
+    (void)hipFree(lp);
+    if (p2 != hipSuccess || p3 != hipSuccess) return fail(CBLP_EHIP, "prepare kernel failed");
+    double tot = 0.0;
+    for (double x : hl) tot += x;
+    int ex = 0;
+    std::frexp(tot + 1.0, &ex);
+    const int bits = std::min(60, 61 - ex);   // sums stay below 2^61
+    if (bits < 8) return fail(CBLP_EINVAL, "arrival rates too large for the 64-bit sales accumulator");
+    h->fx_scale = std::ldexp(1.0, bits);
+
+    if (!ident && (rc = build_transpose<T>(h, hap, s))) return rc;
+
+    HIP_TRY(hipMemsetAsync(h->S_fx, 0, (size_t)h->n * 8, s));
+    return reset_state(h, s);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* cblp_last_error(void) { return g_err.c_str(); }
+
+int cblp_create(cblp_t* out, int64_t L, int64_t n, int64_t m, const int64_t* seg_ptr,
+                const int32_t* prod_idx, const void* v, const void* w, const void* v0,
+                const void* lambda, const void* r, const int64_t* a_ptr, const int32_t* a_idx,
+                const void* a_val, const void* c, int32_t dtype, void* stream)
+{
+    g_err.clear();
+    if (!out) return fail(CBLP_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (L < 0 || n <= 0 || m <= 0) return fail(CBLP_EINVAL, "need L >= 0, n > 0, m > 0");
+    if (n > INT32_MAX || m > INT32_MAX) return fail(CBLP_EINVAL, "n and m must fit in int32");
+    if (dtype != CBLP_F32 && dtype != CBLP_F64)
+        return fail(CBLP_EINVAL, "dtype must be CBLP_F32 or CBLP_F64");
+    if (!seg_ptr || !r || !c || (L > 0 && (!v0 || !lambda)))
+        return fail(CBLP_EINVAL, "NULL instance array");
+    const bool ident = !a_ptr && !a_idx && !a_val;
+    if (!ident && (!a_ptr || !a_idx || !a_val))
+        return fail(CBLP_EINVAL, "a_ptr, a_idx, a_val must be all NULL or all set");
+    if (ident && m != n) return fail(CBLP_EINVAL, "identity resource matrix needs m == n");
+    hipStream_t s = S(stream);
+
+    cblp_instance* h = new (std::nothrow) cblp_instance();
+    if (!h) return fail(CBLP_ENOMEM, "host allocation failed");
+    if (hipGetDevice(&h->device) != hipSuccess) {
+        release(h);
+        return fail(CBLP_EHIP, "hipGetDevice failed");
+    }
+    h->dtype = dtype;
+    h->esz = dtype == CBLP_F32 ? 4 : 8;
+    h->L = L;
+    h->n = n;
+    h->m = m;
+    h->seg_ptr = seg_ptr;
+    h->idx = prod_idx;
+    h->v = v;
+    h->w = w;
+    h->v0 = v0;
+    h->lam = lambda;
+    h->r = r;
+    h->c = c;
+    h->a_ptr = a_ptr;
+    h->a_idx = a_idx;
+    h->a_val = a_val;
+    int64_t nnz = 0;
+    if (hipMemcpyAsync(&nnz, seg_ptr + L, sizeof(int64_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) {
+        release(h);
+        return fail(CBLP_EHIP, "reading seg_ptr[L] failed");
+    }
+    if (nnz < 0 || (nnz > 0 && (!prod_idx || !v || !w))) {
+        release(h);
+        return fail(CBLP_EINVAL, "seg_ptr[L] < 0 or NULL CSR array");
+    }
+    h->nnz = nnz;
+    const int rc = dtype == CBLP_F32 ? create_impl<float>(h, s) : create_impl<double>(h, s);
+    if (rc) {
+        release(h);
+        return rc;
+    }
+    *out = h;
+    return CBLP_OK;
+}
+
+void cblp_destroy(cblp_t h) { release(h); }
+
+int spfom_reset(cblp_t h, void* stream)
+{
+    g_err.clear();
+    if (!h) return fail(CBLP_EINVAL, "handle is NULL");
+    return reset_state(h, S(stream));
+}
+
+int spfom_iterate(cblp_t h, void* eta, const spfom_params* p, int64_t iters, double* trace,
+                  spfom_stats* out, void* stream)
+{
+    g_err.clear();
+    if (!h || !eta) return fail(CBLP_EINVAL, "NULL handle or eta");
+    if (iters < 0) return fail(CBLP_EINVAL, "iters < 0");
+    int rc = check_params(p);
+    if (rc) return rc;
+    hipStream_t s = S(stream);
+    if (trace && (rc = ensure_trace(h, std::max<int64_t>(iters, 1)))) return rc;
+    if (iters == 0) {
+        if (out) {
+            std::memset(out, 0, sizeof(*out));
+            out->iters = h->t;
+        }
+        return CBLP_OK;
+    }
+    rc = h->dtype == CBLP_F32 ? iterate_impl<float>(h, eta, p, iters, trace != nullptr, s)
+                              : iterate_impl<double>(h, eta, p, iters, trace != nullptr, s);
+    if (rc) return rc;
+    if (trace) {
+        HIP_TRY(hipMemcpyAsync(trace, h->trace, iters * SPFOM_NTRACE * sizeof(double),
+                               hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+    }
+    if (out || trace) {
+        const double* last = h->trace + (trace ? (iters - 1) * SPFOM_NTRACE : 0);
+        rc = fill_stats(h, out, s, last);
+        if (out) out->seconds = 0.0;
+        return rc;
+    }
+    return CBLP_OK;
+}
+
+int spfom_solve(cblp_t h, void* eta, const spfom_params* p, spfom_stats* out, void* stream)
+{
+    g_err.clear();
+    if (!h || !eta || !out) return fail(CBLP_EINVAL, "NULL handle, eta or out");
+    int rc = check_params(p);
+    if (rc) return rc;
+    if (p->max_iters < 0 || !(p->tol >= 0.0))
+        return fail(CBLP_EINVAL, "need max_iters >= 0 and tol >= 0");
+    hipStream_t s = S(stream);
+    const auto t0 = std::chrono::steady_clock::now();
+    if ((rc = reset_state(h, s))) return rc;
+    std::memset(out, 0, sizeof(*out));
+    out->status = CBLP_ENOTCONVERGED;
+    while (h->t < p->max_iters) {
+        const int64_t k = std::min<int64_t>(p->check_every, p->max_iters - h->t);
+        rc = h->dtype == CBLP_F32 ? iterate_impl<float>(h, eta, p, k, false, s)
+                                  : iterate_impl<double>(h, eta, p, k, false, s);
+        if (rc) return rc;
+        rc = fill_stats(h, out, s, h->trace);
+        if (rc) {
+            out->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+            return rc;
+        }
+        if (h->t % p->check_every == 0 && out->trace[SPFOM_TR_GAP] <= p->tol) {
+            out->status = CBLP_OK;
+            break;
+        }
+        out->status = CBLP_ENOTCONVERGED;
+    }
+    out->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (out->status != CBLP_OK)
+        return fail(CBLP_ENOTCONVERGED, "certified gap above tol after max_iters iterations");
+    return CBLP_OK;
+}
+
+int cblp_gap(cblp_t h, const void* eta, spfom_stats* out, void* stream)
+{
+    g_err.clear();
+    if (!h || !eta || !out) return fail(CBLP_EINVAL, "NULL handle, eta or out");
+    hipStream_t s = S(stream);
+    int rc = h->dtype == CBLP_F32 ? evaluate_impl<float>(h, eta, nullptr, s)
+                                  : evaluate_impl<double>(h, eta, nullptr, s);
+    if (rc) return rc;
+    rc = fill_stats(h, out, s, h->trace);
+    out->seconds = 0.0;
+    return rc;
+}
+
+int cblp_sales(cblp_t h, const void* eta, double* S_out, double* u_out, void* seg_R_out,
+               void* stream)
+{
+    g_err.clear();
+    if (!h || !eta) return fail(CBLP_EINVAL, "NULL handle or eta");
+    hipStream_t s = S(stream);
+    int rc = h->dtype == CBLP_F32 ? evaluate_impl<float>(h, eta, seg_R_out, s)
+                                  : evaluate_impl<double>(h, eta, seg_R_out, s);
+    if (rc) return rc;
+    if (S_out) HIP_TRY(hipMemcpyAsync(S_out, h->S_d, h->n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    if (u_out) HIP_TRY(hipMemcpyAsync(u_out, h->u_d, h->m * sizeof(double), hipMemcpyDeviceToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return CBLP_OK;
+}
+
+int cblp_launch_info(cblp_t h, int32_t* seg_grid, int32_t* bins, int32_t* fx_bits)
+{
+    g_err.clear();
+    if (!h) return fail(CBLP_EINVAL, "handle is NULL");
+    if (seg_grid) *seg_grid = h->seg_grid;
+    if (bins) *bins = h->H;
+    if (fx_bits) {
+        int e = 0;
+        std::frexp(h->fx_scale, &e);
+        *fx_bits = e - 1;
+    }
+    return CBLP_OK;
+}
+
+int cblp_timing(cblp_t h, int32_t enable)
+{
+    g_err.clear();
+    if (!h) return fail(CBLP_EINVAL, "handle is NULL");
+    h->timing = enable != 0;
+    h->ev_used = 0;
+    h->ev_marks.clear();
+    return CBLP_OK;
+}
+
+int cblp_timing_read(cblp_t h, double* ms, int64_t* launches, void* stream)
+{
+    g_err.clear();
+    if (!h || !ms || !launches) return fail(CBLP_EINVAL, "NULL argument");
+    HIP_TRY(hipStreamSynchronize(S(stream)));
+    ms[0] = ms[1] = 0.0;
+    launches[0] = launches[1] = 0;
+    for (const auto& mk : h->ev_marks) {
+        float t = 0.0f;
+        HIP_TRY(hipEventElapsedTime(&t, h->ev_pool[mk.second], h->ev_pool[mk.second + 1]));
+        ms[mk.first] += (double)t;
+        launches[mk.first] += 1;
+    }
+    h->ev_used = 0;
+    h->ev_marks.clear();
+    return CBLP_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,109 @@
+// Shared declarations of libcblp's kernels and host code (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "cblp.h"
+
+namespace cblp {
+
+// Segment kernel: a 16-lane group (one DPP row) owns one segment and keeps
+// kJ products per lane in registers; a block holds kSegThreads / 16 groups.
+constexpr int kGroup = 16;
+constexpr int kJ = 4;
+constexpr int kSegThreads = 1024;
+constexpr int kSegsPerTile = kSegThreads / kGroup;
+
+// Dual-phase kernels.
+constexpr int kFoldProducts = 64;          // products per fold block
+constexpr int kFoldChunks = 16;            // partial rows split 16 ways
+constexpr int kFoldThreads = kFoldProducts * kFoldChunks;
+constexpr int kRowThreads = 256;
+
+// Device-resident solver state (FP64), updated by the finalising block.
+struct DevState {
+    double dbest, lb, sum_p, scale;
+    long long t, t0, cnt, restart;
+};
+
+struct SegArgs {
+    int64_t L;
+    const int64_t* seg_ptr;
+    const int32_t* idx;
+    const void* v;
+    const void* w;
+    const void* vt0;
+    const void* lam;
+    const void* rho;
+    int H;                         // products [0, H) are summed in LDS bins
+    unsigned long long* part_S;    // [gridDim.x][H] per-block bin totals
+    unsigned long long* S_fx;      // [n] fixed-point sales of products >= H
+    double fx_scale;               // 2^bits
+    double* zpart;                 // [gridDim.x] FP64 partials of sum lambda R*
+    void* seg_R;                   // [L] nullable
+};
+
+struct PhaseArgs {
+    int64_t n, m;
+    int mode;                      // 0: iterate, 1: evaluate at fixed eta
+    int rule, check_every;
+    double gamma, mu, tau_s;
+    const void* tau_vec;           // [m] nullable
+    const double* zpart;
+    int nz;
+    const unsigned long long* part_S;
+    int nseg;
+    int H;
+    unsigned long long* S_fx;
+    double inv_fx;
+    const void* r;
+    const void* c;
+    const int64_t* a_ptr;          // CSC of A by product; NULL: identity
+    const int32_t* a_idx;
+    const void* a_val;
+    const int64_t* at_ptr;         // CSR of A by resource
+    const int32_t* at_prod;
+    const double* at_val;
+    void* eta;
+    void* rho;
+    double* S_d;
+    double* u_d;
+    double* sum_u;
+    double* bpart;                 // [fold blocks][8]
+    double* bpart2;                // [row blocks][8]
+    int fold_blocks;
+    DevState* st;                  // [2]: read st[par], write st[par ^ 1]
+    int par;
+    double* row;                   // trace row of this iteration
+};
+
+// Launchers (one per kernel family), defined next to their kernels.
+template <typename T>
+hipError_t launch_validate(int64_t L, int64_t n, int64_t m, int64_t nnz, int64_t nnzA,
+                           const int64_t* seg_ptr, const int32_t* idx, const void* v,
+                           const void* w, const void* v0, const void* lam, const void* r,
+                           const void* c, const int64_t* a_ptr, const int32_t* a_idx,
+                           const void* a_val, unsigned* flags, hipStream_t s);
+template <typename T>
+hipError_t launch_prepare(int64_t L, const int64_t* seg_ptr, const void* w, const void* v0,
+                          const void* lam, void* vt0, double* lam_part, int blocks,
+                          hipStream_t s);
+template <typename T>
+hipError_t launch_prices(int64_t n, const void* r, const void* eta, const int64_t* a_ptr,
+                         const int32_t* a_idx, const void* a_val, void* rho, hipStream_t s);
+template <typename T>
+hipError_t launch_segments(const SegArgs& a, int grid, hipStream_t s);
+template <typename T>
+int segment_blocks_per_cu(int H);   // resident segment blocks per CU with H bins
+template <typename T>
+hipError_t launch_phase(const PhaseArgs& a, bool identity, hipStream_t s);
+
+enum : unsigned {
+    V_IDX = 1u << 0, V_V = 1u << 1, V_W = 1u << 2, V_V0 = 1u << 3, V_LAM = 1u << 4,
+    V_SEGPTR = 1u << 5, V_R = 1u << 6, V_C = 1u << 7, V_AIDX = 1u << 8, V_AVAL = 1u << 9,
+    V_APTR = 1u << 10, V_NBITS = 11
+};
+
+}  // namespace cblp

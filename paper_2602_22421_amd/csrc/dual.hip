@@ -1,0 +1,269 @@
+// Dual phase of one iteration: sales totals, FP64 reductions, certified
+// bound and the projected dual step (eq. 16).
+//
+//   k_fold    per product: S_j = (sum of the per-block LDS bin rows + the
+//             global tail accumulator) / 2^bits and P = sum r_j S_j; with
+//             A = I also the per-row work below
+//   k_rows    (general A) per resource: u_i = sum_j a_ij S_j through A^T
+//   per row   g_i = u_i - c_i; c.eta, sum (g)^+, the Polyak norm
+//             sum tau_i g_i^2 (g zeroed where the projection binds), ||eta||^2
+//             and the window sums of u for the certified bound
+//   k_update  every block folds the partials in the same fixed order, so all
+//             blocks agree on D = c.eta + sum lambda R*, Dbest, the bound
+//             LB = max over checks of theta * Pbar (theta = min_i min(1,
+//             c_i / ubar_i)), the step multiplier and the window restart;
+//             block 0 writes the next solver state and the trace row, every
+//             block updates its rows: eta_i <- max(0, (1 - t_i mu) eta_i +
+//             t_i g_i), rho_i = r_i - eta_i for A = I.
+//
+// The state is double-buffered (read st[t & 1], write st[(t + 1) & 1]), so
+// no block waits for another and no device-wide fence is needed inside a
+// kernel; kernel boundaries order the phases.  Every floating-point
+// reduction has a fixed shape, so results are bitwise reproducible; sales
+// totals are exact integer sums.
+#include <cfloat>
+
+#include "common.hpp"
+
+namespace cblp {
+namespace {
+
+constexpr int NR = 7;   // P, c.eta, infeasibility, Polyak norm, theta, ||eta||^2, Z
+enum { R_P = 0, R_CETA, R_INF, R_G, R_TH, R_E2, R_Z };
+
+// Deterministic block reduction of NR values (R_TH is a minimum, the rest
+// sums): a shuffle tree inside each wave, then every thread folds the wave
+// results in wave order.  sh holds NR * blockDim/64 doubles.
+__device__ void block_reduce(double (&x)[NR], double* sh)
+{
+#pragma unroll
+    for (int q = 0; q < NR; ++q)
+        for (int o = 32; o > 0; o >>= 1) {
+            const double y = __shfl_down(x[q], o, 64);
+            x[q] = q == R_TH ? fmin(x[q], y) : x[q] + y;
+        }
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int nw = (int)(blockDim.x >> 6);
+    __syncthreads();
+    if (lane == 0)
+#pragma unroll
+        for (int q = 0; q < NR; ++q) sh[q * 16 + wave] = x[q];
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < NR; ++q) {
+        double r = sh[q * 16];
+        for (int w = 1; w < nw; ++w) r = q == R_TH ? fmin(r, sh[q * 16 + w]) : r + sh[q * 16 + w];
+        x[q] = r;
+    }
+}
+
+__device__ __forceinline__ void clear(double (&x)[NR])
+{
+#pragma unroll
+    for (int q = 0; q < NR; ++q) x[q] = 0.0;
+    x[R_TH] = 1.0;
+}
+
+template <typename T>
+__device__ __forceinline__ void row_work(const PhaseArgs& a, int64_t i, double u, long long cnt1,
+                                         double (&x)[NR])
+{
+    const T* c = (const T*)a.c;
+    const T* eta = (const T*)a.eta;
+    const T* tauv = (const T*)a.tau_vec;
+    a.u_d[i] = u;
+    const double ci = (double)c[i], ei = (double)eta[i];
+    const double g = u - ci;
+    x[R_CETA] += ci * ei;
+    x[R_E2] += ei * ei;
+    if (g > 0.0) x[R_INF] += g;
+    const double ti = tauv ? (double)tauv[i] : a.tau_s;
+    const double gh = (ei <= 0.0 && g < 0.0) ? 0.0 : g;
+    x[R_G] += ti * gh * gh;
+    if (a.mode == 0) {
+        const double su = a.sum_u[i] + u;
+        a.sum_u[i] = su;
+        const double ub = su / (double)cnt1;
+        if (ub > ci) x[R_TH] = fmin(x[R_TH], ci / ub);
+    }
+}
+
+__device__ __forceinline__ void store_part(double* p, const double (&x)[NR])
+{
+#pragma unroll
+    for (int q = 0; q < NR; ++q) p[q] = x[q];
+}
+
+template <typename T, bool IDENT>
+__global__ void __launch_bounds__(kFoldThreads) k_fold(PhaseArgs a)
+{
+    __shared__ unsigned long long red[kFoldChunks][kFoldProducts];
+    __shared__ double sh[NR * 16];
+    const int tid = threadIdx.x;
+    const int jj = tid % kFoldProducts, cc = tid / kFoldProducts;
+    const int64_t j = (int64_t)blockIdx.x * kFoldProducts + jj;
+    unsigned long long acc = 0ull;
+    if (j < a.n && j < a.H)
+        for (int b = cc; b < a.nseg; b += kFoldChunks) acc += a.part_S[(size_t)b * a.H + j];
+    red[cc][jj] = acc;
+    const long long cnt1 = a.mode == 0 ? a.st[a.par].cnt + 1 : 1;
+    __syncthreads();
+    double x[NR];
+    clear(x);
+    if (cc == 0 && j < a.n) {
+        unsigned long long tot = a.S_fx[j];
+        a.S_fx[j] = 0ull;
+        for (int q = 0; q < kFoldChunks; ++q) tot += red[q][jj];
+        const double sj = (double)(long long)tot * a.inv_fx;
+        a.S_d[j] = sj;
+        x[R_P] = (double)((const T*)a.r)[j] * sj;
+        if (IDENT) row_work<T>(a, j, sj, cnt1, x);
+    }
+    block_reduce(x, sh);
+    if (tid == 0) store_part(a.bpart + (size_t)blockIdx.x * 8, x);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kRowThreads) k_rows(PhaseArgs a)
+{
+    __shared__ double sh[NR * 16];
+    const int64_t i = (int64_t)blockIdx.x * kRowThreads + threadIdx.x;
+    const long long cnt1 = a.mode == 0 ? a.st[a.par].cnt + 1 : 1;
+    double x[NR];
+    clear(x);
+    if (i < a.m) {
+        double u = 0.0;
+        for (int64_t q = a.at_ptr[i]; q < a.at_ptr[i + 1]; ++q)
+            u += a.at_val[q] * a.S_d[a.at_prod[q]];
+        row_work<T>(a, i, u, cnt1, x);
+    }
+    block_reduce(x, sh);
+    if (threadIdx.x == 0) store_part(a.bpart2 + (size_t)blockIdx.x * 8, x);
+}
+
+template <typename T, bool IDENT>
+__global__ void __launch_bounds__(kRowThreads) k_update(PhaseArgs a)
+{
+    __shared__ double sh[NR * 16];
+    const int tid = threadIdx.x;
+    // every block folds all partials in the same order
+    double x[NR];
+    clear(x);
+    for (int q = tid; q < a.nz; q += kRowThreads) x[R_Z] += a.zpart[q];
+    for (int q = tid; q < a.fold_blocks; q += kRowThreads) x[R_P] += a.bpart[(size_t)q * 8 + R_P];
+    const double* rp = IDENT ? a.bpart : a.bpart2;
+    const int nrow = IDENT ? a.fold_blocks : (int)gridDim.x;
+    for (int q = tid; q < nrow; q += kRowThreads) {
+        const double* p = rp + (size_t)q * 8;
+        x[R_CETA] += p[R_CETA];
+        x[R_INF] += p[R_INF];
+        x[R_G] += p[R_G];
+        x[R_TH] = fmin(x[R_TH], p[R_TH]);
+        x[R_E2] += p[R_E2];
+    }
+    block_reduce(x, sh);
+    const double D = x[R_CETA] + x[R_Z];
+    const bool iter = a.mode == 0;
+    double scale = 0.0;
+    bool restart = false;
+    DevState st = a.st[a.par];
+    double th = x[R_TH];
+    if (iter) {
+        const long long t1 = st.t + 1, cnt1 = st.cnt + 1;
+        st.t = t1;
+        if (D < st.dbest) st.dbest = D;
+        st.sum_p += x[R_P];
+        st.cnt = cnt1;
+        if (t1 % a.check_every == 0) {
+            const double cand = th * (st.sum_p / (double)cnt1);
+            if (cand > st.lb) st.lb = cand;
+        } else {
+            th = 1.0;
+        }
+        scale = 1.0;
+        if (a.rule == SPFOM_STEP_POLYAK) {
+            const double ex = D - st.lb;
+            scale = (x[R_G] > 0.0 && ex > 0.0) ? a.gamma * ex / x[R_G] : 0.0;
+        }
+        st.scale = scale;
+        if (t1 == 1 || t1 == 2 * st.t0) {   // averaging window restarts
+            restart = true;
+            st.t0 = t1;
+            st.cnt = 0;
+            st.sum_p = 0.0;
+        }
+        st.restart = restart ? 1 : 0;
+    }
+    if (blockIdx.x == 0 && tid == 0) {
+        double* row = a.row;
+        row[SPFOM_TR_DUAL] = D;
+        row[SPFOM_TR_PRIMAL] = x[R_P];
+        row[SPFOM_TR_Z] = x[R_Z];
+        row[SPFOM_TR_ETA2] = x[R_E2];
+        row[SPFOM_TR_INFEAS] = x[R_INF];
+        if (iter) {
+            row[SPFOM_TR_DBEST] = st.dbest;
+            row[SPFOM_TR_LB] = st.lb;
+            row[SPFOM_TR_GAP] = (st.dbest - st.lb) / fmax(fabs(st.dbest), DBL_MIN);
+            row[SPFOM_TR_STEP] = scale;
+            row[SPFOM_TR_THETA] = th;
+            a.st[a.par ^ 1] = st;
+        } else {
+            for (int q = SPFOM_TR_DBEST; q < SPFOM_NTRACE; ++q) row[q] = 0.0;
+        }
+    }
+    if (!iter) return;
+    const int64_t i = (int64_t)blockIdx.x * kRowThreads + tid;
+    if (i < a.m) {
+        T* eta = (T*)a.eta;
+        const T* tauv = (const T*)a.tau_vec;
+        const double ti = scale * (tauv ? (double)tauv[i] : a.tau_s);
+        double e = (double)eta[i];
+        e = (1.0 - ti * a.mu) * e + ti * (a.u_d[i] - (double)((const T*)a.c)[i]);
+        if (!(e > 0.0)) e = (e != e) ? e : 0.0;   // projection; NaN stays visible
+        const T et = (T)e;
+        eta[i] = et;
+        if (restart) a.sum_u[i] = 0.0;
+        if (IDENT) ((T*)a.rho)[i] = ((const T*)a.r)[i] - et;
+    }
+}
+
+template <typename T>
+__global__ void k_prices_after(int64_t n, const T* r, const T* eta, const int64_t* a_ptr,
+                               const int32_t* a_idx, const T* a_val, T* rho)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    T x = r[j];
+    for (int64_t q = a_ptr[j]; q < a_ptr[j + 1]; ++q) x -= a_val[q] * eta[a_idx[q]];
+    rho[j] = x;
+}
+
+}  // namespace
+
+template <typename T>
+hipError_t launch_phase(const PhaseArgs& a, bool identity, hipStream_t s)
+{
+    const unsigned fold_grid = (unsigned)a.fold_blocks;
+    const unsigned row_grid = (unsigned)((a.m + kRowThreads - 1) / kRowThreads);
+    if (identity) {
+        hipLaunchKernelGGL((k_fold<T, true>), dim3(fold_grid), dim3(kFoldThreads), 0, s, a);
+        hipLaunchKernelGGL((k_update<T, true>), dim3(row_grid), dim3(kRowThreads), 0, s, a);
+    } else {
+        hipLaunchKernelGGL((k_fold<T, false>), dim3(fold_grid), dim3(kFoldThreads), 0, s, a);
+        hipLaunchKernelGGL(k_rows<T>, dim3(row_grid), dim3(kRowThreads), 0, s, a);
+        hipLaunchKernelGGL((k_update<T, false>), dim3(row_grid), dim3(kRowThreads), 0, s, a);
+        if (a.mode == 0) {
+            const unsigned pg = (unsigned)((a.n + 255) / 256);
+            hipLaunchKernelGGL(k_prices_after<T>, dim3(pg), dim3(256), 0, s, a.n,
+                               (const T*)a.r, (const T*)a.eta, a.a_ptr, a.a_idx,
+                               (const T*)a.a_val, (T*)a.rho);
+        }
+    }
+    return hipGetLastError();
+}
+
+template hipError_t launch_phase<float>(const PhaseArgs&, bool, hipStream_t);
+template hipError_t launch_phase<double>(const PhaseArgs&, bool, hipStream_t);
+
+}  // namespace cblp

@@ -1,0 +1,143 @@
+// Instance validation, per-segment preprocessing and the price step.
+#include "common.hpp"
+
+namespace cblp {
+namespace {
+
+template <typename T>
+__global__ void k_validate(int64_t L, int64_t n, int64_t m, int64_t nnz, int64_t nnzA,
+                           const int64_t* seg_ptr, const int32_t* idx, const T* v, const T* w,
+                           const T* v0, const T* lam, const T* r, const T* c,
+                           const int64_t* a_ptr, const int32_t* a_idx, const T* a_val,
+                           unsigned* flags)
+{
+    unsigned bad = 0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (int64_t q = tid; q < nnz; q += stride) {
+        const int32_t j = idx[q];
+        if (j < 0 || j >= n) bad |= V_IDX;
+        const T a = v[q], b = w[q];
+        if (!(a > T(0)) || !isfinite(a)) bad |= V_V;
+        if (!(b >= T(0)) || !(b < a)) bad |= V_W;
+    }
+    for (int64_t l = tid; l < L; l += stride) {
+        const T a = v0[l], b = lam[l];
+        if (!(a > T(0)) || !isfinite(a)) bad |= V_V0;
+        if (!(b >= T(0)) || !isfinite(b)) bad |= V_LAM;
+        if (seg_ptr[l + 1] < seg_ptr[l]) bad |= V_SEGPTR;
+    }
+    if (tid == 0 && (seg_ptr[0] != 0 || seg_ptr[L] != nnz)) bad |= V_SEGPTR;
+    for (int64_t j = tid; j < n; j += stride) {
+        if (!isfinite(r[j])) bad |= V_R;
+        if (a_ptr && a_ptr[j + 1] < a_ptr[j]) bad |= V_APTR;
+    }
+    for (int64_t i = tid; i < m; i += stride) {
+        const T x = c[i];
+        if (!(x >= T(0)) || !isfinite(x)) bad |= V_C;
+    }
+    if (a_ptr) {
+        if (tid == 0 && (a_ptr[0] != 0 || a_ptr[n] != nnzA)) bad |= V_APTR;
+        for (int64_t q = tid; q < nnzA; q += stride) {
+            const int32_t i = a_idx[q];
+            if (i < 0 || i >= m) bad |= V_AIDX;
+            const T x = a_val[q];
+            if (!(x >= T(0)) || !isfinite(x)) bad |= V_AVAL;
+        }
+    }
+    if (bad) atomicOr(flags, bad);
+}
+
+// vt0_l = v0_l + sum_{j in N_l} w_lj (FP64 sum, stored in T), and block
+// partial sums of lambda: every product's sales are at most sum_l lambda_l,
+// which sets the fixed-point scale of the sales accumulators.
+template <typename T>
+__global__ void k_prepare(int64_t L, const int64_t* seg_ptr, const T* w, const T* v0,
+                          const T* lam, T* vt0, double* lam_part)
+{
+    __shared__ double sh[256];
+    double acc = 0.0;
+    for (int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; l < L;
+         l += (int64_t)gridDim.x * blockDim.x) {
+        double s = (double)v0[l];
+        for (int64_t q = seg_ptr[l]; q < seg_ptr[l + 1]; ++q) s += (double)w[q];
+        vt0[l] = (T)s;
+        acc += (double)lam[l];
+    }
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) lam_part[blockIdx.x] = sh[0];
+}
+
+// rho_j = r_j - sum_i a_ij eta_i  (identity: r_j - eta_j)
+template <typename T>
+__global__ void k_prices(int64_t n, const T* r, const T* eta, const int64_t* a_ptr,
+                         const int32_t* a_idx, const T* a_val, T* rho)
+{
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n;
+         j += (int64_t)gridDim.x * blockDim.x) {
+        T x = r[j];
+        if (!a_ptr) {
+            x -= eta[j];
+        } else {
+            for (int64_t q = a_ptr[j]; q < a_ptr[j + 1]; ++q) x -= a_val[q] * eta[a_idx[q]];
+        }
+        rho[j] = x;
+    }
+}
+
+}  // namespace
+
+template <typename T>
+hipError_t launch_validate(int64_t L, int64_t n, int64_t m, int64_t nnz, int64_t nnzA,
+                           const int64_t* seg_ptr, const int32_t* idx, const void* v,
+                           const void* w, const void* v0, const void* lam, const void* r,
+                           const void* c, const int64_t* a_ptr, const int32_t* a_idx,
+                           const void* a_val, unsigned* flags, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_validate<T>, dim3(1024), dim3(256), 0, s, L, n, m, nnz, nnzA, seg_ptr,
+                       idx, (const T*)v, (const T*)w, (const T*)v0, (const T*)lam,
+                       (const T*)r, (const T*)c, a_ptr, a_idx, (const T*)a_val, flags);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_prepare(int64_t L, const int64_t* seg_ptr, const void* w, const void* v0,
+                          const void* lam, void* vt0, double* lam_part, int blocks,
+                          hipStream_t s)
+{
+    hipLaunchKernelGGL(k_prepare<T>, dim3(blocks), dim3(256), 0, s, L, seg_ptr, (const T*)w,
+                       (const T*)v0, (const T*)lam, (T*)vt0, lam_part);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_prices(int64_t n, const void* r, const void* eta, const int64_t* a_ptr,
+                         const int32_t* a_idx, const void* a_val, void* rho, hipStream_t s)
+{
+    const int64_t blocks = (n + 255) / 256;
+    hipLaunchKernelGGL(k_prices<T>, dim3((unsigned)(blocks < 1 ? 1 : blocks > 4096 ? 4096 : blocks)),
+                       dim3(256), 0, s, n, (const T*)r, (const T*)eta, a_ptr, a_idx,
+                       (const T*)a_val, (T*)rho);
+    return hipGetLastError();
+}
+
+#define CBLP_INST(T)                                                                           \
+    template hipError_t launch_validate<T>(int64_t, int64_t, int64_t, int64_t, int64_t,        \
+                                           const int64_t*, const int32_t*, const void*,       \
+                                           const void*, const void*, const void*, const void*, \
+                                           const void*, const int64_t*, const int32_t*,        \
+                                           const void*, unsigned*, hipStream_t);               \
+    template hipError_t launch_prepare<T>(int64_t, const int64_t*, const void*, const void*,   \
+                                          const void*, void*, double*, int, hipStream_t);      \
+    template hipError_t launch_prices<T>(int64_t, const void*, const void*, const int64_t*,    \
+                                         const int32_t*, const void*, void*, hipStream_t);
+CBLP_INST(float)
+CBLP_INST(double)
+#undef CBLP_INST
+
+}  // namespace cblp
