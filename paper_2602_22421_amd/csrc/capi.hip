@@ -11,6 +11,7 @@
 #include <cfloat>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -64,8 +65,16 @@ struct cblp_instance {
     const int64_t* a_ptr = nullptr;
     const int32_t* a_idx = nullptr;
     const void* a_val = nullptr;
-    // owned workspace
+    // owned: the size-sorted copy of the segments (position p = segment perm[p])
+    int64_t* ptr2 = nullptr;
+    int32_t* idx2 = nullptr;
+    void* v2 = nullptr;
+    void* den2 = nullptr;
     void* vt0 = nullptr;
+    void* lam2 = nullptr;
+    void* Rwarm = nullptr;
+    int32_t* perm = nullptr;
+    // owned workspace
     void* rho = nullptr;
     unsigned long long* S_fx = nullptr;
     unsigned long long* part_S = nullptr;
@@ -83,6 +92,7 @@ struct cblp_instance {
     double* at_val = nullptr;
     double* pinned = nullptr;
     int seg_grid = 1;
+    int seg_variant = 0;
     int H = 0;
     int fold_blocks = 1;
     double fx_scale = 1.0;
@@ -110,7 +120,8 @@ int dalloc(P** p, size_t bytes)
 void release(cblp_instance* h)
 {
     if (!h) return;
-    void* ptrs[] = {h->vt0, h->rho, h->S_fx, h->part_S, h->S_d, h->u_d, h->sum_u, h->zpart,
+    void* ptrs[] = {h->ptr2, h->idx2, h->v2, h->den2, h->vt0, h->lam2, h->Rwarm, h->perm,
+                    h->rho, h->S_fx, h->part_S, h->S_d, h->u_d, h->sum_u, h->zpart,
                     h->bpart, h->bpart2, h->st, h->trace, h->at_ptr,
                     h->at_prod, h->at_val};
     for (void* p : ptrs)
@@ -176,12 +187,14 @@ int run_segments(cblp_instance* h, void* seg_R, hipStream_t s)
 {
     SegArgs a;
     a.L = h->L;
-    a.seg_ptr = h->seg_ptr;
-    a.idx = h->idx;
-    a.v = h->v;
-    a.w = h->w;
+    a.ptr = h->ptr2;
+    a.idx = h->idx2;
+    a.v = h->v2;
+    a.den = h->den2;
     a.vt0 = h->vt0;
-    a.lam = h->lam;
+    a.lam = h->lam2;
+    a.Rwarm = h->Rwarm;
+    a.perm = h->perm;
     a.rho = h->rho;
     a.H = h->H;
     a.part_S = h->part_S;
@@ -192,7 +205,7 @@ int run_segments(cblp_instance* h, void* seg_R, hipStream_t s)
     size_t slot;
     int rc = timed_begin(h, 0, s, &slot);
     if (rc) return rc;
-    HIP_TRY(launch_segments<T>(a, h->seg_grid, s));
+    HIP_TRY(launch_segments<T>(a, h->seg_grid, h->seg_variant, s));
     return timed_end(h, slot, s);
 }
 
@@ -380,14 +393,24 @@ int create_impl(cblp_instance* h, hipStream_t s)
     }
     const int64_t lds_bins = ((int64_t)lds_block - 1024) / 8;
     h->H = (int)std::max<int64_t>(1, std::min<int64_t>({h->n, (int64_t)kMaxBins, lds_bins}));
-    const int per_cu = segment_blocks_per_cu<T>(h->H);
+    // kernel variant and bin count may be overridden for tuning runs
+    h->seg_variant = sizeof(T) == 4 ? 6 : 4;
+    if (const char* ev = std::getenv("CBLP_SEG_VARIANT")) {
+        const int x = std::atoi(ev);
+        if (x >= 0 && x < kSegVariants) h->seg_variant = x;
+    }
+    if (const char* eb = std::getenv("CBLP_SEG_BINS")) {
+        const long x = std::atol(eb);
+        if (x >= 1 && x <= h->H) h->H = (int)x;
+    }
+    const int per_cu = segment_blocks_per_cu<T>(h->H, h->seg_variant);
     const int64_t tiles = (h->L + kSegsPerTile - 1) / kSegsPerTile;
     h->seg_grid = (int)std::max<int64_t>(1, std::min<int64_t>(tiles, (int64_t)cus * per_cu));
     h->fold_blocks = (int)((h->n + kFoldProducts - 1) / kFoldProducts);
     const int64_t row_blocks = (h->m + kRowThreads - 1) / kRowThreads;
 
     const size_t esz = h->esz;
-    if ((rc = dalloc(&h->vt0, (size_t)std::max<int64_t>(h->L, 1) * esz))) return rc;
+    const int64_t L1 = std::max<int64_t>(h->L, 1);
     if ((rc = dalloc(&h->rho, (size_t)h->n * esz))) return rc;
     if ((rc = dalloc(&h->S_fx, (size_t)h->n * 8))) return rc;
     if ((rc = dalloc(&h->part_S, (size_t)h->seg_grid * std::max(h->H, 1) * 8))) return rc;
@@ -402,24 +425,72 @@ int create_impl(cblp_instance* h, hipStream_t s)
     if (hipHostMalloc((void**)&h->pinned, SPFOM_NTRACE * sizeof(double), hipHostMallocDefault) != hipSuccess)
         return fail(CBLP_ENOMEM, "hipHostMalloc failed");
 
-    // vt0 and the arrival-rate total that bounds every product's sales
+    // size-sorted copy of the segments: a stable counting sort by row length
+    {
+        std::vector<int64_t> sp((size_t)h->L + 1);
+        HIP_TRY(hipMemcpyAsync(sp.data(), h->seg_ptr, (h->L + 1) * sizeof(int64_t),
+                               hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        int64_t kmax = 0;
+        for (int64_t l = 0; l < h->L; ++l) kmax = std::max(kmax, sp[l + 1] - sp[l]);
+        std::vector<int64_t> start((size_t)kmax + 2, 0);
+        for (int64_t l = 0; l < h->L; ++l) start[sp[l + 1] - sp[l] + 1]++;
+        for (int64_t k = 0; k <= kmax; ++k) start[k + 1] += start[k];
+        std::vector<int32_t> perm((size_t)L1, 0);
+        for (int64_t l = 0; l < h->L; ++l) perm[start[sp[l + 1] - sp[l]]++] = (int32_t)l;
+        std::vector<int64_t> ptr((size_t)h->L + 1, 0);
+        for (int64_t p = 0; p < h->L; ++p) ptr[p + 1] = ptr[p] + (sp[perm[p] + 1] - sp[perm[p]]);
+        if ((rc = dalloc(&h->ptr2, (size_t)(h->L + 1) * 8))) return rc;
+        if ((rc = dalloc(&h->perm, (size_t)L1 * 4))) return rc;
+        // the copy is followed by kPad entries (product 0, v = 0, den = 1)
+        const size_t ne = (size_t)h->nnz + kPad;
+        if ((rc = dalloc(&h->idx2, ne * 4))) return rc;
+        if ((rc = dalloc(&h->v2, ne * esz))) return rc;
+        if ((rc = dalloc(&h->den2, ne * esz))) return rc;
+        HIP_TRY(hipMemsetAsync(h->idx2 + h->nnz, 0, kPad * 4, s));
+        HIP_TRY(hipMemsetAsync((char*)h->v2 + h->nnz * esz, 0, kPad * esz, s));
+        {
+            std::vector<T> ones(kPad, T(1));
+            HIP_TRY(hipMemcpyAsync((char*)h->den2 + h->nnz * esz, ones.data(), kPad * esz,
+                                   hipMemcpyHostToDevice, s));
+            HIP_TRY(hipStreamSynchronize(s));
+        }
+        if ((rc = dalloc(&h->vt0, (size_t)L1 * esz))) return rc;
+        if ((rc = dalloc(&h->lam2, (size_t)L1 * esz))) return rc;
+        if ((rc = dalloc(&h->Rwarm, (size_t)L1 * esz))) return rc;
+        HIP_TRY(hipMemcpyAsync(h->ptr2, ptr.data(), (h->L + 1) * 8, hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync(h->perm, perm.data(), L1 * 4, hipMemcpyHostToDevice, s));
+        if (h->L > 0)
+            HIP_TRY(launch_relayout<T>(h->L, h->seg_ptr, h->idx, h->v, h->w, h->v0, h->lam,
+                                       h->perm, h->ptr2, h->idx2, h->v2, h->den2, h->vt0,
+                                       h->lam2, h->Rwarm, s));
+        HIP_TRY(hipStreamSynchronize(s));   // the host vectors die here
+    }
+
+    // fixed-point scale of the sales sums from the arrival rates
     const int pblocks = 256;
     double* lp = nullptr;
-    if ((rc = dalloc(&lp, pblocks * sizeof(double)))) return rc;
-    std::vector<double> hl(pblocks);
-    hipError_t p1 = launch_prepare<T>(h->L, h->seg_ptr, h->w, h->v0, h->lam, h->vt0, lp, pblocks, s);
+    if ((rc = dalloc(&lp, 2 * pblocks * sizeof(double)))) return rc;
+    std::vector<double> hl(2 * pblocks);
+    hipError_t p1 = launch_prepare<T>(h->L, h->lam, lp, pblocks, s);
     hipError_t p2 = p1 == hipSuccess
-                        ? hipMemcpyAsync(hl.data(), lp, pblocks * sizeof(double), hipMemcpyDeviceToHost, s)
+                        ? hipMemcpyAsync(hl.data(), lp, 2 * pblocks * sizeof(double), hipMemcpyDeviceToHost, s)
                         : p1;
     hipError_t p3 = hipStreamSynchronize(s);
     (void)hipFree(lp);
     if (p2 != hipSuccess || p3 != hipSuccess) return fail(CBLP_EHIP, "prepare kernel failed");
-    double tot = 0.0;
-    for (double x : hl) tot += x;
-    int ex = 0;
-    std::frexp(tot + 1.0, &ex);
-    const int bits = std::min(60, 61 - ex);   // sums stay below 2^61
-    if (bits < 8) return fail(CBLP_EINVAL, "arrival rates too large for the 64-bit sales accumulator");
+    double tot = 0.0, hi = 0.0;
+    for (int q = 0; q < pblocks; ++q) {
+        tot += hl[2 * q];
+        hi = std::max(hi, hl[2 * q + 1]);
+    }
+    // every 64-bit sum stays below 2^61; an FP32 quantum below 2^30
+    int e_tot = 0, e_hi = 0;
+    std::frexp(tot + 1.0, &e_tot);
+    std::frexp(hi, &e_hi);
+    int bits = std::min(60, 61 - e_tot);
+    if (h->dtype == CBLP_F32) bits = std::min(bits, 30 - e_hi);
+    if (bits < 8) return fail(CBLP_EINVAL, "arrival rates too large for the fixed-point sales sums");
     h->fx_scale = std::ldexp(1.0, bits);
 
     if (!ident && (rc = build_transpose<T>(h, hap, s))) return rc;

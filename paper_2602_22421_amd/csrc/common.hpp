@@ -9,10 +9,12 @@
 
 namespace cblp {
 
-// Segment kernel: a 16-lane group (one DPP row) owns one segment and keeps
-// kJ products per lane in registers; a block holds kSegThreads / 16 groups.
-constexpr int kGroup = 16;
-constexpr int kJ = 4;
+// Segment kernel: an 8-lane group (half a DPP row) owns one segment and keeps
+// a few products per lane in registers; a block holds kSegThreads / 8
+// groups.  Longer rows stream their tail from memory.
+constexpr int kGroup = 8;
+constexpr int kMaxJ = 8;                   // most register slots of any variant
+constexpr int kPad = kGroup * kMaxJ;       // padding entries after the CSR copy
 constexpr int kSegThreads = 1024;
 constexpr int kSegsPerTile = kSegThreads / kGroup;
 
@@ -28,21 +30,26 @@ struct DevState {
     long long t, t0, cnt, restart;
 };
 
+// The segment kernel reads the library's own copy of the instance, with
+// segments reordered by consideration-set size (position p holds original
+// segment perm[p]) so that neighbouring groups have equal-length rows.
 struct SegArgs {
     int64_t L;
-    const int64_t* seg_ptr;
-    const int32_t* idx;
-    const void* v;
-    const void* w;
-    const void* vt0;
-    const void* lam;
-    const void* rho;
+    const int64_t* ptr;            // [L+1] row pointers of the sorted layout
+    const int32_t* idx;            // [nnz] product ids
+    const void* v;                 // [nnz] nominal attraction
+    const void* den;               // [nnz] v - w
+    const void* vt0;               // [L] v0 + sum w
+    const void* lam;               // [L] arrival rates
+    void* Rwarm;                   // [L] last R* per position: Dinkelbach start
+    const int32_t* perm;           // [L] position -> original segment
+    const void* rho;               // [n] reduced revenues
     int H;                         // products [0, H) are summed in LDS bins
     unsigned long long* part_S;    // [gridDim.x][H] per-block bin totals
     unsigned long long* S_fx;      // [n] fixed-point sales of products >= H
-    double fx_scale;               // 2^bits
+    double fx_scale;               // 2^bits; one segment's sale * 2^bits < 2^31 for FP32
     double* zpart;                 // [gridDim.x] FP64 partials of sum lambda R*
-    void* seg_R;                   // [L] nullable
+    void* seg_R;                   // [L] nullable, original segment order
 };
 
 struct PhaseArgs {
@@ -87,16 +94,21 @@ hipError_t launch_validate(int64_t L, int64_t n, int64_t m, int64_t nnz, int64_t
                            const void* c, const int64_t* a_ptr, const int32_t* a_idx,
                            const void* a_val, unsigned* flags, hipStream_t s);
 template <typename T>
-hipError_t launch_prepare(int64_t L, const int64_t* seg_ptr, const void* w, const void* v0,
-                          const void* lam, void* vt0, double* lam_part, int blocks,
-                          hipStream_t s);
+hipError_t launch_prepare(int64_t L, const void* lam, double* lam_part, int blocks,
+                          hipStream_t s);   // lam_part[2 * block] = sum, [2 * block + 1] = max
+template <typename T>
+hipError_t launch_relayout(int64_t L, const int64_t* seg_ptr, const int32_t* idx,
+                           const void* v, const void* w, const void* v0, const void* lam,
+                           const int32_t* perm, const int64_t* ptr, int32_t* idx2, void* v2,
+                           void* den2, void* vt0, void* lam2, void* Rwarm, hipStream_t s);
 template <typename T>
 hipError_t launch_prices(int64_t n, const void* r, const void* eta, const int64_t* a_ptr,
                          const int32_t* a_idx, const void* a_val, void* rho, hipStream_t s);
+constexpr int kSegVariants = 7;
 template <typename T>
-hipError_t launch_segments(const SegArgs& a, int grid, hipStream_t s);
+hipError_t launch_segments(const SegArgs& a, int grid, int variant, hipStream_t s);
 template <typename T>
-int segment_blocks_per_cu(int H);   // resident segment blocks per CU with H bins
+int segment_blocks_per_cu(int H, int variant);   // resident blocks per CU with H bins
 template <typename T>
 hipError_t launch_phase(const PhaseArgs& a, bool identity, hipStream_t s);
 

@@ -1,4 +1,5 @@
-// Instance validation, per-segment preprocessing and the price step.
+// Instance validation, the library's sorted copy of the instance, arrival-rate
+// bounds and the price step.
 #include "common.hpp"
 
 namespace cblp {
@@ -48,29 +49,60 @@ __global__ void k_validate(int64_t L, int64_t n, int64_t m, int64_t nnz, int64_t
     if (bad) atomicOr(flags, bad);
 }
 
-// vt0_l = v0_l + sum_{j in N_l} w_lj (FP64 sum, stored in T), and block
-// partial sums of lambda: every product's sales are at most sum_l lambda_l,
-// which sets the fixed-point scale of the sales accumulators.
+// Block partial sum and maximum of the arrival rates: every product's sales
+// are at most sum_l lambda_l and one segment's sales of one product at most
+// max_l lambda_l, which set the fixed-point scales of the sales sums.
 template <typename T>
-__global__ void k_prepare(int64_t L, const int64_t* seg_ptr, const T* w, const T* v0,
-                          const T* lam, T* vt0, double* lam_part)
+__global__ void k_prepare(int64_t L, const T* lam, double* lam_part)
 {
-    __shared__ double sh[256];
-    double acc = 0.0;
+    __shared__ double sh[256], mx[256];
+    double acc = 0.0, hi = 0.0;
     for (int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; l < L;
          l += (int64_t)gridDim.x * blockDim.x) {
-        double s = (double)v0[l];
-        for (int64_t q = seg_ptr[l]; q < seg_ptr[l + 1]; ++q) s += (double)w[q];
-        vt0[l] = (T)s;
-        acc += (double)lam[l];
+        const double x = (double)lam[l];
+        acc += x;
+        hi = x > hi ? x : hi;
     }
     sh[threadIdx.x] = acc;
+    mx[threadIdx.x] = hi;
     __syncthreads();
     for (int o = 128; o > 0; o >>= 1) {
-        if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+        if ((int)threadIdx.x < o) {
+            sh[threadIdx.x] += sh[threadIdx.x + o];
+            mx[threadIdx.x] = fmax(mx[threadIdx.x], mx[threadIdx.x + o]);
+        }
         __syncthreads();
     }
-    if (threadIdx.x == 0) lam_part[blockIdx.x] = sh[0];
+    if (threadIdx.x == 0) {
+        lam_part[2 * blockIdx.x] = sh[0];
+        lam_part[2 * blockIdx.x + 1] = mx[0];
+    }
+}
+
+// Copy the caller's CSR into the library's layout: position p takes
+// segment perm[p]; entries keep their order within a row; den = v - w.
+template <typename T>
+__global__ void k_relayout(int64_t L, const int64_t* seg_ptr, const int32_t* idx, const T* v,
+                           const T* w, const T* v0, const T* lam, const int32_t* perm,
+                           const int64_t* ptr, int32_t* idx2, T* v2, T* den2, T* vt0, T* lam2,
+                           T* Rwarm)
+{
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < L;
+         p += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t l = perm[p];
+        const int64_t b = seg_ptr[l], k = seg_ptr[l + 1] - b, d = ptr[p];
+        double s = (double)v0[l];
+        for (int64_t q = 0; q < k; ++q) {
+            const T x = v[b + q], y = w[b + q];
+            idx2[d + q] = idx[b + q];
+            v2[d + q] = x;
+            den2[d + q] = x - y;
+            s += (double)y;
+        }
+        vt0[p] = (T)s;
+        lam2[p] = lam[l];
+        Rwarm[p] = T(0);
+    }
 }
 
 // rho_j = r_j - sum_i a_ij eta_i  (identity: r_j - eta_j)
@@ -106,12 +138,21 @@ hipError_t launch_validate(int64_t L, int64_t n, int64_t m, int64_t nnz, int64_t
 }
 
 template <typename T>
-hipError_t launch_prepare(int64_t L, const int64_t* seg_ptr, const void* w, const void* v0,
-                          const void* lam, void* vt0, double* lam_part, int blocks,
-                          hipStream_t s)
+hipError_t launch_prepare(int64_t L, const void* lam, double* lam_part, int blocks, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_prepare<T>, dim3(blocks), dim3(256), 0, s, L, seg_ptr, (const T*)w,
-                       (const T*)v0, (const T*)lam, (T*)vt0, lam_part);
+    hipLaunchKernelGGL(k_prepare<T>, dim3(blocks), dim3(256), 0, s, L, (const T*)lam, lam_part);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_relayout(int64_t L, const int64_t* seg_ptr, const int32_t* idx,
+                           const void* v, const void* w, const void* v0, const void* lam,
+                           const int32_t* perm, const int64_t* ptr, int32_t* idx2, void* v2,
+                           void* den2, void* vt0, void* lam2, void* Rwarm, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_relayout<T>, dim3(2048), dim3(256), 0, s, L, seg_ptr, idx,
+                       (const T*)v, (const T*)w, (const T*)v0, (const T*)lam, perm, ptr, idx2,
+                       (T*)v2, (T*)den2, (T*)vt0, (T*)lam2, (T*)Rwarm);
     return hipGetLastError();
 }
 
@@ -132,10 +173,13 @@ hipError_t launch_prices(int64_t n, const void* r, const void* eta, const int64_
                                            const void*, const void*, const void*, const void*, \
                                            const void*, const int64_t*, const int32_t*,        \
                                            const void*, unsigned*, hipStream_t);               \
-    template hipError_t launch_prepare<T>(int64_t, const int64_t*, const void*, const void*,   \
-                                          const void*, void*, double*, int, hipStream_t);      \
+    template hipError_t launch_prepare<T>(int64_t, const void*, double*, int, hipStream_t);    \
     template hipError_t launch_prices<T>(int64_t, const void*, const void*, const int64_t*,    \
-                                         const int32_t*, const void*, void*, hipStream_t);
+                                         const int32_t*, const void*, void*, hipStream_t);     \
+    template hipError_t launch_relayout<T>(int64_t, const int64_t*, const int32_t*,            \
+                                           const void*, const void*, const void*, const void*, \
+                                           const int32_t*, const int64_t*, int32_t*, void*,    \
+                                           void*, void*, void*, void*, hipStream_t);
 CBLP_INST(float)
 CBLP_INST(double)
 #undef CBLP_INST
