@@ -39,6 +39,31 @@ def algorithmic_bytes(inst, esz):
                                                             per_prod=per_prod)
 
 
+PROFILE_OF = {"plain-L2e6-n2e4-zipf-identity": "k_segments-plain-L2e6-n2e4.md"}
+
+
+def profiled_traffic(workload):
+    """HBM bytes per segment-kernel launch from the committed rocprofv3 summary
+    (FETCH_SIZE and WRITE_SIZE, scaled by the copy calibration), or None when
+    there is none for the workload or the kernel source changed since the
+    counters were taken."""
+    import hashlib
+    name = PROFILE_OF.get(workload)
+    path = os.path.join(ROOT, "profiles", name) if name else None
+    if not path or not os.path.exists(path):
+        return None
+    src = b"".join(open(os.path.join(ROOT, "paper_2602_22421_amd", "csrc", f), "rb").read()
+                   for f in ("segment.hip", "common.hpp"))
+    sha = hashlib.sha256(src).hexdigest()[:16]
+    rec, traffic = None, None
+    for line in open(path):
+        if line.startswith("source_sha256_16:"):
+            rec = line.split()[1]
+        if line.startswith("traffic_bytes_per_launch:"):
+            traffic = float(line.split()[1])
+    return traffic if rec == sha else None
+
+
 def cpu_baseline(inst, budget_s=15.0):
     """Time the FP64 oracle (single thread) on a prefix of the same workload."""
     import dataclasses
@@ -141,7 +166,8 @@ def main():
         achieved = nbytes / seg_avg
         roof = {"bound": "hbm", "kernel": "k_segments", "achieved": achieved / 1e9,
                 "peak": HBM_PEAK / 1e9, "unit": "GB/s", "frac": achieved / HBM_PEAK,
-                "traffic": None, "bytes_per_launch": nbytes, "per_unit_bytes": per,
+                "traffic": profiled_traffic(CONFIG_NAMES[args.config]) if args.dtype == "f32" else None,
+                "bytes_per_launch": nbytes, "per_unit_bytes": per,
                 "kernel_avg_us": seg_avg * 1e6,
                 "dual_phase_avg_us": dual_ms * 1e3 / max(dual_n, 1),
                 "launch": cblp.cblp_launch_info(prob.h)}

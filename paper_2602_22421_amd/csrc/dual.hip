@@ -102,10 +102,21 @@ __global__ void __launch_bounds__(kFoldThreads) k_fold(PhaseArgs a)
     const int tid = threadIdx.x;
     const int jj = tid % kFoldProducts, cc = tid / kFoldProducts;
     const int64_t j = (int64_t)blockIdx.x * kFoldProducts + jj;
-    unsigned long long acc = 0ull;
-    if (j < a.n && j < a.H)
-        for (int b = cc; b < a.nseg; b += kFoldChunks) acc += a.part_S[(size_t)b * a.H + j];
-    red[cc][jj] = acc;
+    // integer sums: four independent accumulators keep four loads in flight
+    unsigned long long a0 = 0ull, a1 = 0ull, a2 = 0ull, a3 = 0ull;
+    if (j < a.n && j < a.H) {
+        const unsigned long long* P = a.part_S + j;
+        const size_t H = (size_t)a.H;
+        int b = cc;
+        for (; b + 3 * kFoldChunks < a.nseg; b += 4 * kFoldChunks) {
+            a0 += P[(size_t)b * H];
+            a1 += P[(size_t)(b + kFoldChunks) * H];
+            a2 += P[(size_t)(b + 2 * kFoldChunks) * H];
+            a3 += P[(size_t)(b + 3 * kFoldChunks) * H];
+        }
+        for (; b < a.nseg; b += kFoldChunks) a0 += P[(size_t)b * H];
+    }
+    red[cc][jj] = (a0 + a1) + (a2 + a3);
     const long long cnt1 = a.mode == 0 ? a.st[a.par].cnt + 1 : 1;
     __syncthreads();
     double x[NR];
