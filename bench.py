@@ -96,6 +96,77 @@ def cpu_baseline(inst, budget_s=15.0):
                       f"single-threaded C, {dt:.1f} s"}
 
 
+def batched(args):
+    """Time for every instance of a multi-period batch to reach the certified
+    gap (or the iteration cap): one batch against the same instances solved
+    one after another with spfom_solve.  Same step rule, tolerance and checks."""
+    import torch
+    from paper_2602_22421_amd import cblp
+    from paper_2602_22421_amd.instances import batch_instance, step_scale
+
+    t0 = time.perf_counter()
+    insts = [batch_instance(b, scale=args.batch_scale).cast(np.float32)
+             for b in range(args.batch_count)]
+    nnz = sum(i.nnz for i in insts)
+    L = sum(i.L for i in insts)
+    log(f"generated {len(insts)} instances: sum L = {L}, sum nnz = {nnz} "
+        f"in {time.perf_counter() - t0:.1f} s")
+
+    def setup():
+        probs = [cblp.Problem(i, dtype=torch.float32) for i in insts]
+        taus = [p.tensor(step_scale(i, 0.001).astype(np.float32)) for p, i in zip(probs, insts)]
+        return probs, taus
+
+    params = cblp.make_params(rule=cblp.SPFOM_STEP_CONST, tau=1.0, check_every=10,
+                              tol=args.tol, max_iters=args.max_iters)
+    # sequential: each instance on its own, one after another
+    probs, taus = setup()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    seq = []
+    for p, t in zip(probs, taus):
+        prm = cblp.make_params(rule=cblp.SPFOM_STEP_CONST, tau_vec=t, check_every=10,
+                               tol=args.tol, max_iters=args.max_iters)
+        seq.append(p.solve(p.zeros_eta(), prm).as_dict())
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t0
+    log(f"sequential: {t_seq:.2f} s, converged {sum(o['status'] == 0 for o in seq)}/{len(seq)}")
+    for p in probs:
+        p.close()
+    del probs, taus
+    torch.cuda.empty_cache()
+
+    probs, taus = setup()
+    batch = cblp.Batch(probs)
+    tune_etas = [p.zeros_eta() for p in probs]
+    variant = batch.tune(tune_etas, params, iters=3, tau_vecs=taus)
+    etas = [p.zeros_eta() for p in probs]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    outs = batch.solve(etas, params, tau_vecs=taus)
+    torch.cuda.synchronize()
+    t_bat = time.perf_counter() - t0
+    log(f"batched: {t_bat:.2f} s, converged {sum(o['status'] == 0 for o in outs)}/{len(outs)}, "
+        f"info {batch.info()}")
+    it_seq = sum(o["iters"] for o in seq)
+    it_bat = sum(o["iters"] for o in outs)
+    out = {
+        "metric": "time to certified gap, all instances", "value": t_bat, "unit": "s",
+        "higher_is_better": False, "n_gpus": 1, "dtype": "f32", "data": "synthetic",
+        "vs_baseline": None,
+        "config": {"workload": f"multi-period-batch-{len(insts)}", "instances": len(insts),
+                   "sum_L": L, "sum_nnz": nnz, "tol": args.tol, "max_iters": args.max_iters,
+                   "check_every": 10, "step_rule": "const", "batch_scale": args.batch_scale},
+        "batched_s": t_bat, "sequential_s": t_seq, "speedup": t_seq / t_bat,
+        "converged_batched": sum(o["status"] == 0 for o in outs),
+        "converged_sequential": sum(o["status"] == 0 for o in seq),
+        "iterations_batched": it_bat, "iterations_sequential": it_seq,
+        "tuned_variant": variant, "batch": batch.info(),
+    }
+    print(json.dumps(out), flush=True)
+    batch.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -106,6 +177,14 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-timing", action="store_true",
                     help="skip the per-launch events (roofline fields become null)")
+    ap.add_argument("--batched", action="store_true",
+                    help="multi-period re-solves: a batch of instances solved in one persistent "
+                         "launch per iteration against the same instances solved one by one")
+    ap.add_argument("--batch-count", type=int, default=256)
+    ap.add_argument("--batch-scale", type=float, default=1.0,
+                    help="scales every instance's segment count (1.0: L log-uniform in [1e3, 1e6])")
+    ap.add_argument("--tol", type=float, default=2e-2)
+    ap.add_argument("--max-iters", type=int, default=2000)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device-to-device copy: the reference kernel whose "
                          "FETCH_SIZE / WRITE_SIZE counters scale the traffic figures")
@@ -124,6 +203,8 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     torch.cuda.set_device(0)
+    if args.batched:
+        return batched(args)
     if args.copy_calibration:
         x = torch.ones(1 << 28, dtype=torch.float32, device="cuda")   # 1 GiB
         y = torch.empty_like(x)

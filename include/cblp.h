@@ -185,6 +185,47 @@ int cblp_launch_info(cblp_t h, int32_t* seg_grid, int32_t* bins, int32_t* fx_bit
 int cblp_timing(cblp_t h, int32_t enable);
 int cblp_timing_read(cblp_t h, double* ms, int64_t* launches, void* stream);
 
+/* ------------------------------------------------------------------ batches
+ * Many independent instances advanced together: the re-solves of the periods
+ * of a multi-period problem (Section 5.1), each with its own remaining
+ * capacities.  One iteration of every active instance is one persistent
+ * segment launch (a shared work list of tile ranges) plus two dual-phase
+ * launches; results equal those of the instances' own spfom_iterate up to
+ * FP64 summation order of sum lambda R*.  Identity resource matrix only.
+ */
+typedef struct cblp_batch* cblp_batch_t;
+
+/* Build a batch over count handles (same dtype, A = identity).  The batch
+ * uses the handles' device buffers: do not use a handle on its own while its
+ * batch is in use, and destroy the batch before its handles. */
+int cblp_batch_create(cblp_batch_t* out, int32_t count, const cblp_t* handles, void* stream);
+void cblp_batch_destroy(cblp_batch_t b);
+
+/* iters iterations of every instance from etas[q] ([dev] [m_q], in/out),
+ * continuing the batch's per-instance solver state.  tau_vecs nullable, or
+ * per-instance [dev] tau vectors (NULL entries use p->tau).  rows [host]
+ * nullable: the last trace row of each instance, [count x SPFOM_NTRACE]. */
+int spfom_batch_iterate(cblp_batch_t b, void* const* etas, const void* const* tau_vecs,
+                        const spfom_params* p, int64_t iters, double* rows, void* stream);
+
+/* Reset every instance and iterate until each one's certified gap <= p->tol
+ * or p->max_iters: p->check_every iterations are captured once in a hipGraph
+ * and replayed; converged instances drop out of the work list.  outs [host]
+ * [count] receives each instance's iterations, last trace row, elapsed
+ * seconds and status.  Returns CBLP_OK if every instance converged. */
+int spfom_batch_solve(cblp_batch_t b, void* const* etas, const void* const* tau_vecs,
+                      const spfom_params* p, spfom_stats* outs, void* stream);
+
+/* Autotune the segment-kernel variant (register slots per lane, pipeline
+ * depth) by timing iters iterations of each candidate on this batch; the
+ * duals in etas change and the solver state is reset afterwards.  chosen
+ * [host] nullable receives the variant kept. */
+int cblp_batch_tune(cblp_batch_t b, void* const* etas, const void* const* tau_vecs,
+                    const spfom_params* p, int32_t iters, int32_t* chosen, void* stream);
+
+/* Work items, persistent grid and kernel variant of the batch ([host], nullable). */
+int cblp_batch_info(cblp_batch_t b, int32_t* items, int32_t* grid, int32_t* variant);
+
 /* Describe the last failure on this thread ("" if none). */
 const char* cblp_last_error(void);
 

@@ -24,7 +24,8 @@ NTRACE = 10
 TRACE_COLS = ("D", "P", "Z", "eta2", "infeas", "dbest", "lb", "gap", "step", "theta")
 EXPORTS = ("cblp_create", "cblp_destroy", "spfom_reset", "spfom_iterate", "spfom_solve",
            "cblp_gap", "cblp_sales", "cblp_launch_info", "cblp_timing", "cblp_timing_read",
-           "cblp_last_error")
+           "cblp_last_error", "cblp_batch_create", "cblp_batch_destroy", "spfom_batch_iterate",
+           "spfom_batch_solve", "cblp_batch_tune", "cblp_batch_info")
 
 
 class SpfomParams(ctypes.Structure):
@@ -86,6 +87,22 @@ def load(path: str = _LIB_PATH) -> ctypes.CDLL:
     lib.cblp_timing_read.restype = ctypes.c_int
     lib.cblp_timing_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double),
                                      ctypes.POINTER(ctypes.c_int64), vp]
+    pp = ctypes.POINTER(vp)
+    lib.cblp_batch_create.restype = ctypes.c_int
+    lib.cblp_batch_create.argtypes = [pp, i32, pp, vp]
+    lib.cblp_batch_destroy.restype = None
+    lib.cblp_batch_destroy.argtypes = [vp]
+    lib.spfom_batch_iterate.restype = ctypes.c_int
+    lib.spfom_batch_iterate.argtypes = [vp, pp, pp, ctypes.POINTER(SpfomParams), i64, vp, vp]
+    lib.spfom_batch_solve.restype = ctypes.c_int
+    lib.spfom_batch_solve.argtypes = [vp, pp, pp, ctypes.POINTER(SpfomParams),
+                                      ctypes.POINTER(SpfomStats), vp]
+    lib.cblp_batch_tune.restype = ctypes.c_int
+    lib.cblp_batch_tune.argtypes = [vp, pp, pp, ctypes.POINTER(SpfomParams), i32,
+                                    ctypes.POINTER(i32), vp]
+    lib.cblp_batch_info.restype = ctypes.c_int
+    lib.cblp_batch_info.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32),
+                                    ctypes.POINTER(i32)]
     lib.cblp_last_error.restype = ctypes.c_char_p
     lib.cblp_last_error.argtypes = []
     _lib = lib
@@ -260,3 +277,90 @@ class Problem:
         R = torch.zeros(self.L, dtype=self.dtype, device=self.device) if seg_R else None
         cblp_sales(self.h, eta, S, u, R)
         return S, u, R
+
+
+# ------------------------------------------------------------------ batches
+
+def _ptr_array(tensors):
+    arr = (ctypes.c_void_p * len(tensors))()
+    for q, t in enumerate(tensors):
+        arr[q] = None if t is None else t.data_ptr()
+    return arr
+
+
+def cblp_batch_create(handles, stream=None) -> int:
+    hs = (ctypes.c_void_p * len(handles))(*handles)
+    b = ctypes.c_void_p()
+    _check(load().cblp_batch_create(ctypes.byref(b), len(handles), hs, _stream(stream)))
+    return b.value
+
+
+def cblp_batch_destroy(b) -> None:
+    if b:
+        load().cblp_batch_destroy(ctypes.c_void_p(b))
+
+
+def spfom_batch_iterate(b, etas, tau_vecs, params: SpfomParams, iters: int, rows=None,
+                        stream=None) -> None:
+    tv = None if tau_vecs is None else _ptr_array(tau_vecs)
+    rp = None if rows is None else ctypes.c_void_p(rows.ctypes.data)
+    _check(load().spfom_batch_iterate(ctypes.c_void_p(b), _ptr_array(etas), tv,
+                                      ctypes.byref(params), int(iters), rp, _stream(stream)))
+
+
+def spfom_batch_solve(b, etas, tau_vecs, params: SpfomParams, stream=None):
+    outs = (SpfomStats * len(etas))()
+    tv = None if tau_vecs is None else _ptr_array(tau_vecs)
+    _check(load().spfom_batch_solve(ctypes.c_void_p(b), _ptr_array(etas), tv,
+                                    ctypes.byref(params), outs, _stream(stream)),
+           allow=(CBLP_ENOTCONVERGED, CBLP_ENONFINITE))
+    return [o.as_dict() for o in outs]
+
+
+def cblp_batch_tune(b, etas, tau_vecs, params: SpfomParams, iters: int, stream=None) -> int:
+    chosen = ctypes.c_int32()
+    tv = None if tau_vecs is None else _ptr_array(tau_vecs)
+    _check(load().cblp_batch_tune(ctypes.c_void_p(b), _ptr_array(etas), tv, ctypes.byref(params),
+                                  int(iters), ctypes.byref(chosen), _stream(stream)))
+    return chosen.value
+
+
+def cblp_batch_info(b) -> dict:
+    it, g, v = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    _check(load().cblp_batch_info(ctypes.c_void_p(b), ctypes.byref(it), ctypes.byref(g),
+                                  ctypes.byref(v)))
+    return {"items": it.value, "grid": g.value, "variant": v.value}
+
+
+class Batch:
+    """Several Problems advanced together (the Problems must outlive the batch
+    and must not be iterated on their own while it exists)."""
+
+    def __init__(self, problems):
+        self.problems = list(problems)
+        self.b = cblp_batch_create([p.h for p in self.problems])
+
+    def close(self):
+        if getattr(self, "b", None):
+            cblp_batch_destroy(self.b)
+            self.b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def iterate(self, etas, iters: int, params: SpfomParams, tau_vecs=None):
+        rows = np.zeros((len(self.problems), NTRACE))
+        spfom_batch_iterate(self.b, etas, tau_vecs, params, iters, rows)
+        return rows
+
+    def solve(self, etas, params: SpfomParams, tau_vecs=None):
+        return spfom_batch_solve(self.b, etas, tau_vecs, params)
+
+    def tune(self, etas, params: SpfomParams, iters: int = 5, tau_vecs=None) -> int:
+        return cblp_batch_tune(self.b, etas, tau_vecs, params, iters)
+
+    def info(self) -> dict:
+        return cblp_batch_info(self.b)

@@ -1,0 +1,793 @@
+// Batched re-solves: many independent CBLP instances - the per-period
+// re-solves of the multi-period setting of Section 5.1, each with its
+// remaining capacities - advance together.  One iteration for all of them is
+// one persistent segment launch and two dual-phase launches; spfom_batch_solve
+// replays check_every iterations from a hipGraph and drops converged
+// instances between replays.
+//
+// Work list.  Each instance's size-sorted tiles (128 positions) are cut into
+// work items of about the same size; items are ordered largest instance first
+// and handed out through an atomic counter, so large and small instances share
+// the machine without a static schedule.  Every item has its own LDS-bin row
+// and its own partial of sum lambda R*, so the results do not depend on which
+// block ran which item: integer sales sums are exact and the FP64 partials
+// are folded per instance in item order.
+//
+// Dual phase.  Fold blocks (64 products of one instance) and row blocks (256
+// rows of one instance) come from flattened tables; every row block of an
+// instance folds that instance's partials in the same order (no fences) and
+// the one at row 0 writes the instance's next state and trace row.  The state
+// is double-buffered per instance: the copy with the larger iteration count is
+// current, the other is written.
+//
+// Scope: identity resource matrix (m == n) for every instance.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "dual_core.hpp"
+#include "handle.hpp"
+#include "segment_core.hpp"
+
+namespace cblp {
+namespace {
+
+struct BInst {
+    SegArgs seg;               // this instance's sorted copy and tail accumulator
+    int64_t n, m;
+    const void* r;
+    const void* c;
+    void* eta;
+    void* rho;
+    const void* tau_vec;
+    double tau_s;
+    unsigned long long* S_fx;
+    double inv_fx;
+    double* S_d;
+    double* u_d;
+    double* sum_u;
+    DevState* st;              // [2]
+    double* row;               // [SPFOM_NTRACE]
+    int item0, item1;          // work items of this instance
+    int64_t part_off;          // first entry of its LDS-bin rows in part_S
+    int fold0, fold1;          // its fold blocks
+    int H;                     // LDS bins (products [0, H))
+    int active;
+};
+
+struct BItem {
+    int inst;
+    int pad;
+    int64_t t0, t1;            // tiles [t0, t1)
+};
+
+struct BChunk {
+    int inst;
+    int pad;
+    int64_t j0;                // first product (fold) or row (update)
+};
+
+struct BArgs {
+    const BInst* inst;
+    const BChunk* fold;
+    const BChunk* rows;
+    const unsigned long long* part_S;
+    const double* zpart;
+    double* bpart;             // [fold blocks][8]
+    int rule, check_every;
+    double gamma, mu;
+};
+
+// the fields row_work reads, for one instance
+struct RowView {
+    const void* c;
+    const void* eta;
+    const void* tau_vec;
+    double tau_s;
+    double* u_d;
+    double* sum_u;
+    int mode;
+};
+
+__device__ __forceinline__ int current(const DevState* st) { return st[0].t >= st[1].t ? 0 : 1; }
+
+__global__ void k_reset_counter(unsigned* counter) { *counter = 0u; }
+
+template <typename T, int J, int DEPTH>
+__global__ void __launch_bounds__(kSegThreads)
+k_bsegments(const BInst* inst, const BItem* items, int nitems, unsigned* counter,
+            unsigned long long* part_S, double* zpart)
+{
+    extern __shared__ unsigned long long bins[];
+    __shared__ double zsh[kSegThreads / 64];
+    __shared__ int s_item;
+    for (;;) {
+        __syncthreads();
+        if (threadIdx.x == 0) s_item = (int)atomicAdd(counter, 1u);
+        __syncthreads();
+        // the item is block-uniform: keep it (and the instance record) in SGPRs
+        const int it = __builtin_amdgcn_readfirstlane(s_item);
+        if (it >= nitems) break;
+        const BItem w = items[it];
+        const BInst* I = inst + w.inst;
+        if (!I->active) continue;
+        const SegArgs a = I->seg;
+        const int H = a.H;
+        for (int j = threadIdx.x; j < H; j += kSegThreads) bins[j] = 0ull;
+        __syncthreads();
+        double zacc = 0.0;
+        seg::process_tiles<T, J, DEPTH>(a, w.t0, w.t1, 1, bins, zacc);
+        __syncthreads();
+        unsigned long long* out = part_S + I->part_off + (size_t)(it - I->item0) * (size_t)H;
+        for (int j = threadIdx.x; j < H; j += kSegThreads) out[j] = bins[j];
+        for (int o = 32; o > 0; o >>= 1) zacc += __shfl_down(zacc, o, 64);
+        if ((threadIdx.x & 63) == 0) zsh[threadIdx.x >> 6] = zacc;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double z = zsh[0];
+            for (int q = 1; q < kSegThreads / 64; ++q) z += zsh[q];
+            zpart[it] = z;
+        }
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kFoldThreads) k_bfold(BArgs b)
+{
+    using namespace dual;
+    __shared__ unsigned long long red[kFoldChunks][kFoldProducts];
+    __shared__ double sh[NR * 16];
+    const BChunk f = b.fold[blockIdx.x];   // blockIdx-indexed: scalar loads
+    const BInst* I = b.inst + f.inst;
+    if (!I->active) return;
+    const int tid = threadIdx.x;
+    const int jj = tid % kFoldProducts, cc = tid / kFoldProducts;
+    const int64_t j = f.j0 + jj;
+    const int H = I->H;
+    const int nit = I->item1 - I->item0;
+    unsigned long long a0 = 0ull, a1 = 0ull, a2 = 0ull, a3 = 0ull;
+    if (j < I->n && j < H) {
+        const unsigned long long* P = b.part_S + I->part_off + j;
+        int q = cc;
+        for (; q + 3 * kFoldChunks < nit; q += 4 * kFoldChunks) {
+            a0 += P[(size_t)q * H];
+            a1 += P[(size_t)(q + kFoldChunks) * H];
+            a2 += P[(size_t)(q + 2 * kFoldChunks) * H];
+            a3 += P[(size_t)(q + 3 * kFoldChunks) * H];
+        }
+        for (; q < nit; q += kFoldChunks) a0 += P[(size_t)q * H];
+    }
+    red[cc][jj] = (a0 + a1) + (a2 + a3);
+    const long long cnt1 = I->st[current(I->st)].cnt + 1;
+    __syncthreads();
+    double x[NR];
+    clear(x);
+    if (cc == 0 && j < I->n) {
+        unsigned long long tot = I->S_fx[j];
+        I->S_fx[j] = 0ull;
+        for (int q = 0; q < kFoldChunks; ++q) tot += red[q][jj];
+        const double sj = (double)(long long)tot * I->inv_fx;
+        I->S_d[j] = sj;
+        x[R_P] = (double)((const T*)I->r)[j] * sj;
+        const RowView rv{I->c, I->eta, I->tau_vec, I->tau_s, I->u_d, I->sum_u, 0};
+        row_work<T>(rv, j, sj, cnt1, x);
+    }
+    block_reduce(x, sh);
+    if (tid == 0) {
+        double* p = b.bpart + (size_t)blockIdx.x * 8;
+        for (int q = 0; q < NR; ++q) p[q] = x[q];
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kRowThreads) k_bupdate(BArgs b)
+{
+    using namespace dual;
+    __shared__ double sh[NR * 16];
+    const BChunk rc = b.rows[blockIdx.x];
+    const BInst* I = b.inst + rc.inst;
+    if (!I->active) return;
+    const int tid = threadIdx.x;
+    double x[NR];
+    clear(x);
+    for (int q = I->item0 + tid; q < I->item1; q += kRowThreads) x[R_Z] += b.zpart[q];
+    for (int q = I->fold0 + tid; q < I->fold1; q += kRowThreads) {
+        const double* p = b.bpart + (size_t)q * 8;
+        x[R_P] += p[R_P];
+        x[R_CETA] += p[R_CETA];
+        x[R_INF] += p[R_INF];
+        x[R_G] += p[R_G];
+        x[R_TH] = fmin(x[R_TH], p[R_TH]);
+        x[R_E2] += p[R_E2];
+    }
+    block_reduce(x, sh);
+    const double D = x[R_CETA] + x[R_Z];
+    const int cur = current(I->st);
+    DevState st = I->st[cur];
+    double th = x[R_TH];
+    const long long t1 = st.t + 1, cnt1 = st.cnt + 1;
+    st.t = t1;
+    if (D < st.dbest) st.dbest = D;
+    st.sum_p += x[R_P];
+    st.cnt = cnt1;
+    if (t1 % b.check_every == 0) {
+        const double cand = th * (st.sum_p / (double)cnt1);
+        if (cand > st.lb) st.lb = cand;
+    } else {
+        th = 1.0;
+    }
+    double scale = 1.0;
+    if (b.rule == SPFOM_STEP_POLYAK) {
+        const double ex = D - st.lb;
+        scale = (x[R_G] > 0.0 && ex > 0.0) ? b.gamma * ex / x[R_G] : 0.0;
+    }
+    st.scale = scale;
+    bool restart = false;
+    if (t1 == 1 || t1 == 2 * st.t0) {
+        restart = true;
+        st.t0 = t1;
+        st.cnt = 0;
+        st.sum_p = 0.0;
+    }
+    st.restart = restart ? 1 : 0;
+    if (rc.j0 == 0 && tid == 0) {
+        double* row = I->row;
+        row[SPFOM_TR_DUAL] = D;
+        row[SPFOM_TR_PRIMAL] = x[R_P];
+        row[SPFOM_TR_Z] = x[R_Z];
+        row[SPFOM_TR_ETA2] = x[R_E2];
+        row[SPFOM_TR_INFEAS] = x[R_INF];
+        row[SPFOM_TR_DBEST] = st.dbest;
+        row[SPFOM_TR_LB] = st.lb;
+        row[SPFOM_TR_GAP] = (st.dbest - st.lb) / fmax(fabs(st.dbest), DBL_MIN);
+        row[SPFOM_TR_STEP] = scale;
+        row[SPFOM_TR_THETA] = th;
+        I->st[cur ^ 1] = st;
+    }
+    const int64_t i = rc.j0 + tid;
+    if (i < I->m) {
+        T* eta = (T*)I->eta;
+        const T* tauv = (const T*)I->tau_vec;
+        const double ti = scale * (tauv ? (double)tauv[i] : I->tau_s);
+        double e = (double)eta[i];
+        e = (1.0 - ti * b.mu) * e + ti * (I->u_d[i] - (double)((const T*)I->c)[i]);
+        if (!(e > 0.0)) e = (e != e) ? e : 0.0;   // projection; NaN stays visible
+        const T et = (T)e;
+        eta[i] = et;
+        if (restart) I->sum_u[i] = 0.0;
+        ((T*)I->rho)[i] = ((const T*)I->r)[i] - et;
+    }
+}
+
+// rho = r - eta for every instance (identity resource matrix)
+template <typename T>
+__global__ void __launch_bounds__(kRowThreads) k_bprices(const BInst* inst, const BChunk* rows)
+{
+    const BChunk rc = rows[blockIdx.x];
+    const BInst* I = inst + rc.inst;
+    const int64_t i = rc.j0 + threadIdx.x;
+    if (i < I->n) ((T*)I->rho)[i] = ((const T*)I->r)[i] - ((const T*)I->eta)[i];
+}
+
+template <typename T>
+const void* bseg_fn(int variant)
+{
+    switch (variant) {
+    case 0: return (const void*)k_bsegments<T, 8, 1>;
+    case 1: return (const void*)k_bsegments<T, 6, 2>;
+    case 2: return (const void*)k_bsegments<T, 4, 2>;
+    case 3: return (const void*)k_bsegments<T, 8, 2>;
+    case 5: return (const void*)k_bsegments<T, 8, 0>;
+    case 6: return (const void*)k_bsegments<T, 7, 1>;
+    default: return (const void*)k_bsegments<T, 4, 1>;
+    }
+}
+
+int bfail(int code, const std::string& msg) { return set_error(code, msg); }
+
+#define BHIP(expr)                                                                     \
+    do {                                                                               \
+        hipError_t e_ = (expr);                                                        \
+        if (e_ != hipSuccess)                                                          \
+            return bfail(CBLP_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+}  // namespace
+}  // namespace cblp
+
+using namespace cblp;
+
+struct cblp_batch {
+    int count = 0;
+    int dtype = CBLP_F32;
+    std::vector<cblp_instance*> hs;
+    std::vector<BInst> h_inst;
+    BInst* d_inst = nullptr;
+    BItem* d_items = nullptr;
+    int nitems = 0;
+    BChunk* d_fold = nullptr;
+    int nfold = 0;
+    BChunk* d_rows = nullptr;
+    int nrows = 0;
+    unsigned long long* part_S = nullptr;
+    double* zpart = nullptr;
+    double* bpart = nullptr;
+    DevState* st = nullptr;
+    double* rows = nullptr;
+    unsigned* counter = nullptr;
+    double* pinned = nullptr;
+    int grid = 1;
+    int variant = 6;
+    int Hmax = 1;
+    hipStream_t stream = nullptr;    // the batch's own stream (graph capture needs one)
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int graph_K = 0;
+    std::vector<int64_t> t;          // per-instance iteration counts
+};
+
+namespace {
+
+void batch_release(cblp_batch* b)
+{
+    if (!b) return;
+    void* ptrs[] = {b->d_inst, b->d_items, b->d_fold, b->d_rows, b->part_S, b->zpart,
+                    b->bpart, b->st, b->rows, b->counter};
+    for (void* p : ptrs)
+        if (p) (void)hipFree(p);
+    if (b->pinned) (void)hipHostFree(b->pinned);
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->ev_in) (void)hipEventDestroy(b->ev_in);
+    if (b->ev_out) (void)hipEventDestroy(b->ev_out);
+    if (b->stream) (void)hipStreamDestroy(b->stream);
+    delete b;
+}
+
+template <typename P>
+int balloc(P** p, size_t bytes)
+{
+    *p = nullptr;
+    if (hipMalloc((void**)p, bytes ? bytes : 8) != hipSuccess) {
+        (void)hipGetLastError();
+        return bfail(CBLP_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+    }
+    return CBLP_OK;
+}
+
+int check_bparams(const spfom_params* p)
+{
+    if (!p) return bfail(CBLP_EINVAL, "params is NULL");
+    if (p->rule != SPFOM_STEP_CONST && p->rule != SPFOM_STEP_POLYAK)
+        return bfail(CBLP_EINVAL, "unknown step rule");
+    if (p->check_every < 1) return bfail(CBLP_EINVAL, "check_every must be >= 1");
+    if (!(p->tau > 0.0 && std::isfinite(p->tau)) && !p->tau_vec)
+        return bfail(CBLP_EINVAL, "tau must be finite and > 0");
+    if (!(p->mu >= 0.0) || !std::isfinite(p->mu)) return bfail(CBLP_EINVAL, "mu must be >= 0");
+    if (p->rule == SPFOM_STEP_POLYAK && !(p->gamma > 0.0 && p->gamma <= 2.0))
+        return bfail(CBLP_EINVAL, "gamma must be in (0, 2]");
+    return CBLP_OK;
+}
+
+// bind the callers' duals and steps into the instance table and upload it
+int bind(cblp_batch* b, void* const* etas, const void* const* tau_vecs, const spfom_params* p,
+         hipStream_t s)
+{
+    for (int q = 0; q < b->count; ++q) {
+        if (!etas || !etas[q]) return bfail(CBLP_EINVAL, "NULL eta for instance " + std::to_string(q));
+        b->h_inst[q].eta = etas[q];
+        b->h_inst[q].tau_vec = tau_vecs ? tau_vecs[q] : nullptr;
+        b->h_inst[q].tau_s = p->tau;
+        if (!b->h_inst[q].tau_vec && !(p->tau > 0.0))
+            return bfail(CBLP_EINVAL, "tau must be > 0 when an instance has no tau vector");
+    }
+    BHIP(hipMemcpyAsync(b->d_inst, b->h_inst.data(), b->count * sizeof(BInst),
+                        hipMemcpyHostToDevice, s));
+    return CBLP_OK;
+}
+
+int reset_states(cblp_batch* b, hipStream_t s)
+{
+    std::vector<DevState> st((size_t)b->count * 2);
+    for (int q = 0; q < b->count; ++q) {
+        std::memset(&st[2 * q], 0, 2 * sizeof(DevState));
+        st[2 * q].dbest = st[2 * q + 1].dbest = INFINITY;
+        st[2 * q + 1].t = -1;
+    }
+    BHIP(hipMemcpyAsync(b->st, st.data(), st.size() * sizeof(DevState), hipMemcpyHostToDevice, s));
+    for (int q = 0; q < b->count; ++q)
+        BHIP(hipMemsetAsync(b->hs[q]->sum_u, 0, (size_t)b->hs[q]->m * sizeof(double), s));
+    BHIP(hipStreamSynchronize(s));
+    std::fill(b->t.begin(), b->t.end(), 0);
+    return CBLP_OK;
+}
+
+template <typename T>
+int enqueue_iterations(cblp_batch* b, const spfom_params* p, int64_t iters, hipStream_t s)
+{
+    BArgs a;
+    a.inst = b->d_inst;
+    a.fold = b->d_fold;
+    a.rows = b->d_rows;
+    a.part_S = b->part_S;
+    a.zpart = b->zpart;
+    a.bpart = b->bpart;
+    a.rule = p->rule;
+    a.check_every = p->check_every;
+    a.gamma = p->gamma;
+    a.mu = p->mu;
+    const size_t lds = (size_t)b->Hmax * sizeof(unsigned long long);
+    const void* segf = bseg_fn<T>(b->variant);
+    for (int64_t it = 0; it < iters; ++it) {
+        hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(1), 0, s, b->counter);
+        void* sargs[] = {(void*)&b->d_inst, (void*)&b->d_items, (void*)&b->nitems,
+                         (void*)&b->counter, (void*)&b->part_S, (void*)&b->zpart};
+        BHIP(hipLaunchKernel(segf, dim3(b->grid), dim3(kSegThreads), sargs, lds, s));
+        hipLaunchKernelGGL(k_bfold<T>, dim3(b->nfold), dim3(kFoldThreads), 0, s, a);
+        hipLaunchKernelGGL(k_bupdate<T>, dim3(b->nrows), dim3(kRowThreads), 0, s, a);
+        BHIP(hipGetLastError());
+    }
+    return CBLP_OK;
+}
+
+template <typename T>
+int batch_prices(cblp_batch* b, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_bprices<T>, dim3(b->nrows), dim3(kRowThreads), 0, s, b->d_inst, b->d_rows);
+    BHIP(hipGetLastError());
+    return CBLP_OK;
+}
+
+int run_iters(cblp_batch* b, const spfom_params* p, int64_t iters, hipStream_t s)
+{
+    return b->dtype == CBLP_F32 ? enqueue_iterations<float>(b, p, iters, s)
+                                : enqueue_iterations<double>(b, p, iters, s);
+}
+
+int run_prices(cblp_batch* b, hipStream_t s)
+{
+    return b->dtype == CBLP_F32 ? batch_prices<float>(b, s) : batch_prices<double>(b, s);
+}
+
+// join the batch stream to the caller's stream on entry and the other way on exit
+int enter(cblp_batch* b, hipStream_t caller)
+{
+    BHIP(hipEventRecord(b->ev_in, caller));
+    BHIP(hipStreamWaitEvent(b->stream, b->ev_in, 0));
+    return CBLP_OK;
+}
+
+int leave(cblp_batch* b, hipStream_t caller)
+{
+    BHIP(hipEventRecord(b->ev_out, b->stream));
+    BHIP(hipStreamWaitEvent(caller, b->ev_out, 0));
+    return CBLP_OK;
+}
+
+// capture check_every iterations once per K; replayed by spfom_batch_solve
+int ensure_graph(cblp_batch* b, const spfom_params* p)
+{
+    if (b->exec && b->graph_K == p->check_every) return CBLP_OK;
+    if (b->exec) {
+        (void)hipGraphExecDestroy(b->exec);
+        b->exec = nullptr;
+    }
+    hipGraph_t g = nullptr;
+    BHIP(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+    int rc = run_iters(b, p, p->check_every, b->stream);
+    hipError_t e = hipStreamEndCapture(b->stream, &g);
+    if (rc) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+    }
+    if (e != hipSuccess) return bfail(CBLP_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    e = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return bfail(CBLP_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    b->graph_K = p->check_every;
+    return CBLP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int cblp_batch_create(cblp_batch_t* out, int32_t count, const cblp_t* handles, void* stream)
+{
+    set_error(CBLP_OK, "");
+    if (!out || !handles || count < 1) return bfail(CBLP_EINVAL, "need out, handles and count >= 1");
+    *out = nullptr;
+    hipStream_t s = (hipStream_t)stream;
+    cblp_batch* b = new (std::nothrow) cblp_batch();
+    if (!b) return bfail(CBLP_ENOMEM, "host allocation failed");
+    auto bail = [&](int rc) {
+        batch_release(b);
+        return rc;
+    };
+    b->count = count;
+    b->hs.assign(handles, handles + count);
+    b->dtype = b->hs[0]->dtype;
+    b->t.assign(count, 0);
+    int64_t Hmax = 1;
+    for (int q = 0; q < count; ++q) {
+        const cblp_instance* h = b->hs[q];
+        if (!h) return bail(bfail(CBLP_EINVAL, "NULL handle " + std::to_string(q)));
+        if (h->dtype != b->dtype) return bail(bfail(CBLP_EINVAL, "all instances need the same dtype"));
+        if (h->a_ptr) return bail(bfail(CBLP_EINVAL, "batched solves need the identity resource matrix"));
+        Hmax = std::max<int64_t>(Hmax, h->H);
+    }
+    b->Hmax = (int)Hmax;
+    if (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming) != hipSuccess)
+        return bail(bfail(CBLP_EHIP, "stream or event creation failed"));
+
+    // launch shape of the persistent segment kernel
+    int cus = 256;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, b->hs[0]->device) == hipSuccess && prop.multiProcessorCount > 0)
+        cus = prop.multiProcessorCount;
+    b->variant = 5;   // no cross-tile prefetch: the only spill-free batched variant
+    if (const char* ev = std::getenv("CBLP_SEG_VARIANT")) {
+        const int x = std::atoi(ev);
+        if (x >= 0 && x < kSegVariants) b->variant = x;
+    }
+    const size_t lds = (size_t)b->Hmax * 8;
+    int per_cu = 1;
+    {
+        const void* f = b->dtype == CBLP_F32 ? bseg_fn<float>(b->variant) : bseg_fn<double>(b->variant);
+        (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, kSegThreads, lds) != hipSuccess ||
+            per_cu < 1)
+            per_cu = 1;
+    }
+    b->grid = cus * per_cu;
+
+    // work items: instances largest first, tiles cut into items of about equal size
+    std::vector<int> order(count);
+    for (int q = 0; q < count; ++q) order[q] = q;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int x, int y) { return b->hs[x]->nnz > b->hs[y]->nnz; });
+    int64_t total_tiles = 0;
+    for (int q = 0; q < count; ++q) total_tiles += (b->hs[q]->L + kSegsPerTile - 1) / kSegsPerTile;
+    const int64_t per_item = std::max<int64_t>(1, total_tiles / ((int64_t)b->grid * 4));
+    std::vector<BItem> items;
+    std::vector<BChunk> fold, rows;
+    b->h_inst.assign(count, BInst());
+    int64_t part = 0;
+    for (int q : order) {
+        cblp_instance* h = b->hs[q];
+        BInst& I = b->h_inst[q];
+        std::memset(&I, 0, sizeof(I));
+        SegArgs& a = I.seg;
+        a.L = h->L;
+        a.ptr = h->ptr2;
+        a.idx = h->idx2;
+        a.v = h->v2;
+        a.den = h->den2;
+        a.vt0 = h->vt0;
+        a.lam = h->lam2;
+        a.Rwarm = h->Rwarm;
+        a.perm = h->perm;
+        a.rho = h->rho;
+        a.H = h->H;
+        a.part_S = nullptr;
+        a.S_fx = h->S_fx;
+        a.fx_scale = h->fx_scale;
+        a.zpart = nullptr;
+        a.seg_R = nullptr;
+        I.n = h->n;
+        I.m = h->m;
+        I.r = h->r;
+        I.c = h->c;
+        I.rho = h->rho;
+        I.S_fx = h->S_fx;
+        I.inv_fx = 1.0 / h->fx_scale;
+        I.S_d = h->S_d;
+        I.u_d = h->u_d;
+        I.sum_u = h->sum_u;
+        I.H = h->H;
+        I.active = 1;
+        const int64_t tiles = (h->L + kSegsPerTile - 1) / kSegsPerTile;
+        I.item0 = (int)items.size();
+        for (int64_t t0 = 0; t0 < tiles; t0 += per_item)
+            items.push_back(BItem{q, 0, t0, std::min(tiles, t0 + per_item)});
+        I.item1 = (int)items.size();
+        I.part_off = part;
+        part += (int64_t)(I.item1 - I.item0) * h->H;
+        I.fold0 = (int)fold.size();
+        for (int64_t j = 0; j < h->n; j += kFoldProducts) fold.push_back(BChunk{q, 0, j});
+        I.fold1 = (int)fold.size();
+        for (int64_t i = 0; i < h->m; i += kRowThreads) rows.push_back(BChunk{q, 0, i});
+    }
+    b->nitems = (int)items.size();
+    b->nfold = (int)fold.size();
+    b->nrows = (int)rows.size();
+    int rc;
+    if ((rc = balloc(&b->d_inst, count * sizeof(BInst)))) return bail(rc);
+    if ((rc = balloc(&b->d_items, std::max<size_t>(items.size(), 1) * sizeof(BItem)))) return bail(rc);
+    if ((rc = balloc(&b->d_fold, std::max<size_t>(fold.size(), 1) * sizeof(BChunk)))) return bail(rc);
+    if ((rc = balloc(&b->d_rows, std::max<size_t>(rows.size(), 1) * sizeof(BChunk)))) return bail(rc);
+    if ((rc = balloc(&b->part_S, (size_t)std::max<int64_t>(part, 1) * 8))) return bail(rc);
+    if ((rc = balloc(&b->zpart, std::max<size_t>(items.size(), 1) * 8))) return bail(rc);
+    if ((rc = balloc(&b->bpart, std::max<size_t>(fold.size(), 1) * 8 * 8))) return bail(rc);
+    if ((rc = balloc(&b->st, (size_t)count * 2 * sizeof(DevState)))) return bail(rc);
+    if ((rc = balloc(&b->rows, (size_t)count * SPFOM_NTRACE * 8))) return bail(rc);
+    if ((rc = balloc(&b->counter, 16))) return bail(rc);
+    if (hipHostMalloc((void**)&b->pinned, (size_t)count * SPFOM_NTRACE * 8, hipHostMallocDefault) != hipSuccess)
+        return bail(bfail(CBLP_ENOMEM, "hipHostMalloc failed"));
+    for (int q = 0; q < count; ++q) {
+        b->h_inst[q].st = b->st + 2 * q;
+        b->h_inst[q].row = b->rows + (size_t)q * SPFOM_NTRACE;
+    }
+    auto up = [&](void* d, const void* h, size_t n) {
+        return n ? hipMemcpyAsync(d, h, n, hipMemcpyHostToDevice, s) : hipSuccess;
+    };
+    if (up(b->d_items, items.data(), items.size() * sizeof(BItem)) != hipSuccess ||
+        up(b->d_fold, fold.data(), fold.size() * sizeof(BChunk)) != hipSuccess ||
+        up(b->d_rows, rows.data(), rows.size() * sizeof(BChunk)) != hipSuccess ||
+        up(b->d_inst, b->h_inst.data(), count * sizeof(BInst)) != hipSuccess ||
+        hipMemsetAsync(b->rows, 0, (size_t)count * SPFOM_NTRACE * 8, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return bail(bfail(CBLP_EHIP, "uploading the batch tables failed"));
+    if ((rc = reset_states(b, s))) return bail(rc);
+    *out = b;
+    return CBLP_OK;
+}
+
+void cblp_batch_destroy(cblp_batch_t b) { batch_release(b); }
+
+int spfom_batch_iterate(cblp_batch_t b, void* const* etas, const void* const* tau_vecs,
+                        const spfom_params* p, int64_t iters, double* rows_out, void* stream)
+{
+    set_error(CBLP_OK, "");
+    if (!b) return bfail(CBLP_EINVAL, "batch is NULL");
+    if (iters < 0) return bfail(CBLP_EINVAL, "iters < 0");
+    int rc = check_bparams(p);
+    if (rc) return rc;
+    hipStream_t caller = (hipStream_t)stream;
+    if ((rc = enter(b, caller))) return rc;
+    if ((rc = bind(b, etas, tau_vecs, p, b->stream))) return rc;
+    if ((rc = run_prices(b, b->stream))) return rc;
+    if ((rc = run_iters(b, p, iters, b->stream))) return rc;
+    for (int q = 0; q < b->count; ++q)
+        if (b->h_inst[q].active) b->t[q] += iters;
+    if (rows_out) {
+        BHIP(hipMemcpyAsync(b->pinned, b->rows, (size_t)b->count * SPFOM_NTRACE * 8,
+                            hipMemcpyDeviceToHost, b->stream));
+        BHIP(hipStreamSynchronize(b->stream));
+        std::memcpy(rows_out, b->pinned, (size_t)b->count * SPFOM_NTRACE * 8);
+    }
+    return leave(b, caller);
+}
+
+int spfom_batch_solve(cblp_batch_t b, void* const* etas, const void* const* tau_vecs,
+                      const spfom_params* p, spfom_stats* outs, void* stream)
+{
+    set_error(CBLP_OK, "");
+    if (!b || !outs) return bfail(CBLP_EINVAL, "NULL batch or outs");
+    int rc = check_bparams(p);
+    if (rc) return rc;
+    if (p->max_iters < 0 || !(p->tol >= 0.0)) return bfail(CBLP_EINVAL, "need max_iters >= 0 and tol >= 0");
+    hipStream_t caller = (hipStream_t)stream;
+    const auto t0 = std::chrono::steady_clock::now();
+    if ((rc = enter(b, caller))) return rc;
+    for (int q = 0; q < b->count; ++q) b->h_inst[q].active = 1;
+    if ((rc = bind(b, etas, tau_vecs, p, b->stream))) return rc;
+    if ((rc = reset_states(b, b->stream))) return rc;
+    if ((rc = ensure_graph(b, p))) return rc;
+    if ((rc = run_prices(b, b->stream))) return rc;
+    for (int q = 0; q < b->count; ++q) {
+        std::memset(&outs[q], 0, sizeof(spfom_stats));
+        outs[q].status = CBLP_ENOTCONVERGED;
+    }
+    const int64_t K = p->check_every;
+    int live = b->count;
+    while (live > 0) {
+        BHIP(hipGraphLaunch(b->exec, b->stream));
+        BHIP(hipMemcpyAsync(b->pinned, b->rows, (size_t)b->count * SPFOM_NTRACE * 8,
+                            hipMemcpyDeviceToHost, b->stream));
+        BHIP(hipStreamSynchronize(b->stream));
+        const double el = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        bool changed = false;
+        for (int q = 0; q < b->count; ++q) {
+            if (!b->h_inst[q].active) continue;
+            b->t[q] += K;
+            spfom_stats& o = outs[q];
+            o.iters = b->t[q];
+            std::memcpy(o.trace, b->pinned + (size_t)q * SPFOM_NTRACE, sizeof(o.trace));
+            o.seconds = el;
+            bool finite = true;
+            for (int c = 0; c < SPFOM_NTRACE; ++c) finite = finite && std::isfinite(o.trace[c]);
+            if (!finite) {
+                o.status = CBLP_ENONFINITE;
+            } else if (o.trace[SPFOM_TR_GAP] <= p->tol) {
+                o.status = CBLP_OK;
+            } else if (b->t[q] + K <= p->max_iters) {
+                continue;
+            }
+            b->h_inst[q].active = 0;
+            --live;
+            changed = true;
+        }
+        if (changed && live > 0)
+            BHIP(hipMemcpyAsync(b->d_inst, b->h_inst.data(), b->count * sizeof(BInst),
+                                hipMemcpyHostToDevice, b->stream));
+    }
+    for (int q = 0; q < b->count; ++q) b->h_inst[q].active = 1;
+    BHIP(hipMemcpyAsync(b->d_inst, b->h_inst.data(), b->count * sizeof(BInst),
+                        hipMemcpyHostToDevice, b->stream));
+    if ((rc = leave(b, caller))) return rc;
+    for (int q = 0; q < b->count; ++q)
+        if (outs[q].status != CBLP_OK)
+            return bfail(outs[q].status, "instance " + std::to_string(q) + " did not reach tol");
+    return CBLP_OK;
+}
+
+int cblp_batch_tune(cblp_batch_t b, void* const* etas, const void* const* tau_vecs,
+                    const spfom_params* p, int32_t iters, int32_t* chosen, void* stream)
+{
+    set_error(CBLP_OK, "");
+    if (!b || iters < 1) return bfail(CBLP_EINVAL, "NULL batch or iters < 1");
+    int rc = check_bparams(p);
+    if (rc) return rc;
+    hipStream_t caller = (hipStream_t)stream;
+    if ((rc = enter(b, caller))) return rc;
+    if ((rc = bind(b, etas, tau_vecs, p, b->stream))) return rc;
+    if ((rc = run_prices(b, b->stream))) return rc;
+    const int candidates[] = {5, 6, 0, 4};
+    double best = INFINITY;
+    int best_v = b->variant;
+    hipEvent_t e0, e1;
+    BHIP(hipEventCreate(&e0));
+    BHIP(hipEventCreate(&e1));
+    const int keep = b->variant;
+    for (int v : candidates) {
+        b->variant = v;
+        const void* f = b->dtype == CBLP_F32 ? bseg_fn<float>(v) : bseg_fn<double>(v);
+        int per_cu = 0;
+        (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, b->Hmax * 8);
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, kSegThreads, (size_t)b->Hmax * 8) !=
+                hipSuccess || per_cu < 1)
+            continue;
+        if ((rc = run_iters(b, p, 1, b->stream))) break;   // warm the variant
+        BHIP(hipEventRecord(e0, b->stream));
+        if ((rc = run_iters(b, p, iters, b->stream))) break;
+        BHIP(hipEventRecord(e1, b->stream));
+        BHIP(hipEventSynchronize(e1));
+        float ms = 0.0f;
+        BHIP(hipEventElapsedTime(&ms, e0, e1));
+        if (ms < best) {
+            best = ms;
+            best_v = v;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    b->variant = rc ? keep : best_v;
+    if (b->exec) {
+        (void)hipGraphExecDestroy(b->exec);
+        b->exec = nullptr;
+    }
+    if (chosen) *chosen = b->variant;
+    if (!rc) rc = reset_states(b, b->stream);
+    const int rc2 = leave(b, caller);
+    return rc ? rc : rc2;
+}
+
+int cblp_batch_info(cblp_batch_t b, int32_t* items, int32_t* grid, int32_t* variant)
+{
+    set_error(CBLP_OK, "");
+    if (!b) return bfail(CBLP_EINVAL, "batch is NULL");
+    if (items) *items = b->nitems;
+    if (grid) *grid = b->grid;
+    if (variant) *variant = b->variant;
+    return CBLP_OK;
+}
+
+}  // extern "C"

@@ -19,6 +19,7 @@
 #include <vector>
 
 #include "common.hpp"
+#include "handle.hpp"
 
 using namespace cblp;
 
@@ -31,6 +32,12 @@ int fail(int code, const std::string& msg)
     g_err = msg;
     return code;
 }
+
+}  // namespace
+
+int cblp::set_error(int code, const std::string& msg) { return fail(code, msg); }
+
+namespace {
 
 #define HIP_TRY(expr)                                                                  \
     do {                                                                               \
@@ -53,55 +60,6 @@ constexpr int kMaxBins = 16384;
 
 }  // namespace
 
-struct cblp_instance {
-    int device = 0;
-    int dtype = CBLP_F32;
-    size_t esz = 4;
-    int64_t L = 0, n = 0, m = 0, nnz = 0, nnzA = 0;
-    const int64_t* seg_ptr = nullptr;
-    const int32_t* idx = nullptr;
-    const void *v = nullptr, *w = nullptr, *v0 = nullptr, *lam = nullptr;
-    const void *r = nullptr, *c = nullptr;
-    const int64_t* a_ptr = nullptr;
-    const int32_t* a_idx = nullptr;
-    const void* a_val = nullptr;
-    // owned: the size-sorted copy of the segments (position p = segment perm[p])
-    int64_t* ptr2 = nullptr;
-    int32_t* idx2 = nullptr;
-    void* v2 = nullptr;
-    void* den2 = nullptr;
-    void* vt0 = nullptr;
-    void* lam2 = nullptr;
-    void* Rwarm = nullptr;
-    int32_t* perm = nullptr;
-    // owned workspace
-    void* rho = nullptr;
-    unsigned long long* S_fx = nullptr;
-    unsigned long long* part_S = nullptr;
-    double* S_d = nullptr;
-    double* u_d = nullptr;
-    double* sum_u = nullptr;
-    double* zpart = nullptr;
-    double* bpart = nullptr;
-    double* bpart2 = nullptr;
-    DevState* st = nullptr;         // [2], double-buffered
-    double* trace = nullptr;
-    int64_t trace_rows = 0;
-    int64_t* at_ptr = nullptr;
-    int32_t* at_prod = nullptr;
-    double* at_val = nullptr;
-    double* pinned = nullptr;
-    int seg_grid = 1;
-    int seg_variant = 0;
-    int H = 0;
-    int fold_blocks = 1;
-    double fx_scale = 1.0;
-    int64_t t = 0;
-    bool timing = false;
-    std::vector<hipEvent_t> ev_pool;
-    size_t ev_used = 0;
-    std::vector<std::pair<int, size_t>> ev_marks;
-};
 
 namespace {
 

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <string>
 
 #include "cblp.h"
 
@@ -111,6 +112,9 @@ template <typename T>
 int segment_blocks_per_cu(int H, int variant);   // resident blocks per CU with H bins
 template <typename T>
 hipError_t launch_phase(const PhaseArgs& a, bool identity, hipStream_t s);
+
+// Record a failure for cblp_last_error() on this thread; returns code.
+int set_error(int code, const std::string& msg);
 
 enum : unsigned {
     V_IDX = 1u << 0, V_V = 1u << 1, V_W = 1u << 2, V_V0 = 1u << 3, V_LAM = 1u << 4,

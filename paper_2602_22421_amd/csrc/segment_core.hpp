@@ -1,0 +1,328 @@
+// Device code of the per-segment primal step, shared by the single-instance
+// and the batched segment kernels.
+//
+// The inner problem of one segment (Section 4.1, in its GAM form): with
+// vt0 = v0 + sum_{N_l} w and vt_j = v_j - w_j > 0, offering S earns
+// R(S) = sum_S rho_j v_j / (vt0 + sum_S vt_j) per arrival; the best
+// response is R* = max(0, max_S R(S)) on S* = {j : rho_j v_j > R* vt_j}
+// (a prefix of the products ordered by rho_j v_j / vt_j, the nested family
+// of Section 4.4).  R* comes from Dinkelbach's parametric iteration: from a
+// start R0 >= 0 take S(R) = {rho_j v_j > R vt_j} and set R <- R(S(R)) until
+// S(R) stops changing.  After the first step R <= R* and R never decreases,
+// so the sets are nested and the loop ends after at most |N_l| + 1 rounds.
+// The start is the segment's R* of the previous call (0 at creation): the
+// duals move little between iterations, so most segments finish in two
+// rounds.  Each round is one compare and two masked adds per product and
+// three 8-lane DPP reductions; no sort and no per-product division.
+//
+// Sales s_lj = (lambda_l / D_l) v_lj with D_l = vt0 + sum_{S*} vt are rounded
+// once to fixed point (scale 2^bits: FP32 rounds to 32-bit quanta, FP64 to
+// 64-bit ones) and summed as 64-bit integers, so the totals do not depend on
+// the order of the additions.  Products [0, H) - the popular head when
+// products are numbered by popularity - accumulate in LDS bins of each block
+// and are written out as one partial row per block; the rest use global
+// atomics.
+//
+// Layout: an 8-lane group owns one segment of the library's size-sorted
+// copy; lane g holds products g, g+8, ..., g+56 of the row in registers and
+// re-reads products past 64 from memory in each round.  A block of 1024
+// threads holds 128 groups and strides over tiles of 128 consecutive
+// positions; the slot loops run to the longest row of the wave, which the
+// size sort keeps close to every row's own length.  Row bounds of tile i+3,
+// CSR entries of tile i+2 and price gathers of tile i+1 are in flight while
+// tile i is solved.
+#pragma once
+
+#include "common.hpp"
+
+namespace cblp {
+namespace seg {
+
+// 8-lane sum with DPP inside half rows: mirror, then swap pairs, then swap
+// neighbours.  Every lane of the group ends with the same bits: each step
+// adds two values that the other lane of the pair adds in the opposite
+// order, and floating-point addition is commutative.
+template <int CTRL>
+__device__ __forceinline__ int dpp_i(int x)
+{
+    return __builtin_amdgcn_update_dpp(0, x, CTRL, 0xF, 0xF, false);
+}
+constexpr int kHalfMirror = 0x141, kQuadSwap2 = 0x4E, kQuadSwap1 = 0xB1;
+
+template <int CTRL>
+__device__ __forceinline__ float dpp_move(float x)
+{
+    return __int_as_float(dpp_i<CTRL>(__float_as_int(x)));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double x)
+{
+    const long long b = __double_as_longlong(x);
+    const int lo = dpp_i<CTRL>((int)(b & 0xffffffffll));
+    const int hi = dpp_i<CTRL>((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+template <int CTRL>
+__device__ __forceinline__ int dpp_move(int x)
+{
+    return dpp_i<CTRL>(x);
+}
+
+template <typename X>
+__device__ __forceinline__ X group_sum(X x)
+{
+    x += dpp_move<kHalfMirror>(x);
+    x += dpp_move<kQuadSwap2>(x);
+    x += dpp_move<kQuadSwap1>(x);
+    return x;
+}
+
+// Pipeline stages.  They are branch-free and do no arithmetic on loaded
+// values, so a wait for a load is emitted only where the value is used, one
+// pipeline step later.  Slots past a row's end load entry 0 of the arrays
+// (never used; the host passes a one-element buffer for an empty instance).
+template <typename T>
+struct Bounds {
+    int64_t b, e;     // row [b, e) of the sorted layout
+    T vt0, lam, R0;
+};
+
+template <typename T, int J>
+struct Raw {          // CSR entries of one row held by this lane
+    int32_t id[J];
+    T v[J], den[J];
+};
+
+template <typename T>
+__device__ __forceinline__ Bounds<T> load_bounds(const SegArgs& a, int64_t p)
+{
+    const int64_t pc = p < a.L ? p : 0;
+    Bounds<T> B;
+    B.b = a.ptr[pc];
+    B.e = a.ptr[pc + 1];
+    B.vt0 = ((const T*)a.vt0)[pc];
+    B.lam = ((const T*)a.lam)[pc];
+    B.R0 = ((const T*)a.Rwarm)[pc];
+    if (p >= a.L) B.e = B.b;      // past the last segment: empty row
+    return B;
+}
+
+// The library pads its CSR copy with kGroup * kMaxJ entries, so slot s of
+// every lane reads base + 8 s with an immediate offset; slots past a row's
+// end read the next row (masked off when used).  Only the first jw slots -
+// the longest row of the wave - are loaded.
+template <typename T, int J>
+__device__ __forceinline__ Raw<T, J> load_raw(const SegArgs& a, const Bounds<T>& B, int g, int jw)
+{
+    Raw<T, J> R;
+    const int32_t* pi = a.idx + B.b + g;
+    const T* pv = (const T*)a.v + B.b + g;
+    const T* pd = (const T*)a.den + B.b + g;
+#pragma unroll
+    for (int s = 0; s < J; ++s) {
+        if (s < jw) {
+            R.id[s] = pi[kGroup * s];
+            R.v[s] = pv[kGroup * s];
+            R.den[s] = pd[kGroup * s];
+        } else {
+            R.id[s] = 0;
+            R.v[s] = T(0);
+            R.den[s] = T(1);
+        }
+    }
+    return R;
+}
+
+template <typename T, int J>
+__device__ __forceinline__ void gather(const SegArgs& a, const Raw<T, J>& R, T (&p)[J], int jw)
+{
+#pragma unroll
+    for (int s = 0; s < J; ++s) p[s] = s < jw ? ((const T*)a.rho)[R.id[s]] : T(0);
+}
+
+// wave-uniform slot count: the longest row among the wave's eight groups
+template <int J>
+__device__ __forceinline__ int wave_slots(int k)
+{
+    int jw = (k + kGroup - 1) / kGroup;
+    jw = max(jw, __shfl_xor(jw, 8));
+    jw = max(jw, __shfl_xor(jw, 16));
+    jw = max(jw, __shfl_xor(jw, 32));
+    return jw < J ? jw : J;
+}
+
+// R = N / D.  FP32 uses the hardware reciprocal (about one ulp); the value
+// only sets the next threshold and R*, both well inside the FP32 tolerance.
+__device__ __forceinline__ float ratio(float n, float d) { return n * __builtin_amdgcn_rcpf(d); }
+__device__ __forceinline__ double ratio(double n, double d) { return n / d; }
+
+__device__ __forceinline__ unsigned long long quantum(float s, double scale)
+{
+    return (unsigned long long)(unsigned)__float2int_rn(s * (float)scale);
+}
+__device__ __forceinline__ unsigned long long quantum(double s, double scale)
+{
+    return (unsigned long long)__double2ll_rn(s * scale);
+}
+
+// J: products per lane held in registers (rows longer than 8 J stream the
+// rest).  DEPTH 1 keeps the CSR entries of the next tile (and the row bounds
+// of the one after) in flight while a tile is solved; DEPTH 0 none; DEPTH 2
+// one more tile of entries and the price gathers.  The block visits tiles
+// tile, tile + stride, ... below `tiles`; sales go to the LDS bins (products
+// < a.H) or the global tail; lambda R* is added to zacc.
+template <typename T, int J, int DEPTH>
+__device__ __forceinline__ void process_tiles(const SegArgs& a, int64_t tile, int64_t tiles,
+                                              int64_t stride, unsigned long long* bins,
+                                              double& zacc)
+{
+    const T* __restrict__ vg = (const T*)a.v;
+    const T* __restrict__ dg = (const T*)a.den;
+    const T* __restrict__ rho = (const T*)a.rho;
+    const int32_t* __restrict__ idx = a.idx;
+    const int H = a.H;
+    const int g = threadIdx.x & (kGroup - 1);
+    const int grp = threadIdx.x / kGroup;
+    auto pos_of = [&](int64_t t) { return t * kSegsPerTile + grp; };
+
+    if (tile < tiles) {
+        Bounds<T> Bc = load_bounds<T>(a, pos_of(tile));
+        int jc = wave_slots<J>((int)(Bc.e - Bc.b));
+        Raw<T, J> Rc = load_raw<T, J>(a, Bc, g, jc);
+        T Pc[J];
+        if (DEPTH == 2) gather<T, J>(a, Rc, Pc, jc);
+        Bounds<T> B1 = load_bounds<T>(a, pos_of(tile + stride));
+        int j1 = 0;
+        Raw<T, J> R1;
+        if (DEPTH == 2) {
+            j1 = wave_slots<J>((int)(B1.e - B1.b));
+            R1 = load_raw<T, J>(a, B1, g, j1);
+        }
+        Bounds<T> B2 = load_bounds<T>(a, pos_of(tile + 2 * stride));
+
+        for (; tile < tiles; tile += stride) {
+            // issue the next stages before touching the current tile
+            Raw<T, J> R2;
+            Bounds<T> B3;
+            T P1[J];
+            int j2 = 0;
+            if (DEPTH == 2) {
+                j2 = wave_slots<J>((int)(B2.e - B2.b));
+                R2 = load_raw<T, J>(a, B2, g, j2);
+                B3 = load_bounds<T>(a, pos_of(tile + 3 * stride));
+                gather<T, J>(a, R1, P1, j1);
+            } else if (DEPTH == 1) {
+                j1 = wave_slots<J>((int)(B1.e - B1.b));
+                R1 = load_raw<T, J>(a, B1, g, j1);
+                gather<T, J>(a, Rc, Pc, jc);
+            } else {
+                gather<T, J>(a, Rc, Pc, jc);
+            }
+
+            const int64_t p = pos_of(tile);
+            const int64_t b = Bc.b;
+            const int k = (int)(Bc.e - Bc.b);
+            const T vt0 = Bc.vt0;
+            const int jw = jc;
+
+            T num[J], den[J];
+#pragma unroll
+            for (int s = 0; s < J; ++s) {
+                const bool ok = g + kGroup * s < k;
+                num[s] = ok ? Pc[s] * Rc.v[s] : T(0);   // 0 > R * 1 never holds for R >= 0
+                den[s] = ok ? Rc.den[s] : T(1);
+            }
+            auto sums = [&](T R, T& N, T& Dn, int& cnt) {
+                T n_ = T(0), d_ = T(0);
+                int c_ = 0;
+#pragma unroll
+                for (int s = 0; s < J; ++s) {
+                    if (s >= jw) break;
+                    const bool in = num[s] > R * den[s];
+                    n_ += in ? num[s] : T(0);
+                    d_ += in ? den[s] : T(0);
+                    c_ += in ? 1 : 0;
+                }
+                for (int q = kGroup * J + g; q < k; q += kGroup) {
+                    const T nn = rho[idx[b + q]] * vg[b + q];
+                    const T dd = dg[b + q];
+                    if (nn > R * dd) {
+                        n_ += nn;
+                        d_ += dd;
+                        ++c_;
+                    }
+                }
+                N = group_sum(n_);
+                Dn = group_sum(d_);
+                cnt = group_sum(c_);
+            };
+            // Dinkelbach: R defines the set whose sums are (N, Dn, cnt)
+            T R = Bc.R0, N, Dn;
+            int cnt;
+            sums(R, N, Dn, cnt);
+            for (int round = 0; round < k + 2; ++round) {
+                const T Rn = cnt > 0 ? ratio(N, vt0 + Dn) : T(0);
+                T N2, D2;
+                int c2;
+                sums(Rn, N2, D2, c2);
+                if (c2 == cnt) break;   // nested sets of equal size are equal
+                R = Rn;
+                N = N2;
+                Dn = D2;
+                cnt = c2;
+            }
+            const T Rstar = cnt > 0 ? ratio(N, vt0 + Dn) : T(0);
+            const T lamD = ratio(Bc.lam, vt0 + Dn);
+#pragma unroll
+            for (int s = 0; s < J; ++s) {
+                if (s >= jw) break;
+                if (num[s] > R * den[s]) {
+                    const unsigned long long q = quantum(lamD * Rc.v[s], a.fx_scale);
+                    const int32_t j = Rc.id[s];
+                    if (j < H)
+                        atomicAdd(&bins[j], q);
+                    else
+                        atomicAdd(&a.S_fx[j], q);
+                }
+            }
+            for (int q = kGroup * J + g; q < k; q += kGroup) {
+                const T x = vg[b + q];
+                const int32_t j = idx[b + q];
+                if (rho[j] * x > R * dg[b + q]) {
+                    const unsigned long long qq = quantum(lamD * x, a.fx_scale);
+                    if (j < H)
+                        atomicAdd(&bins[j], qq);
+                    else
+                        atomicAdd(&a.S_fx[j], qq);
+                }
+            }
+            if (g == 0 && p < a.L) {
+                zacc += (double)Bc.lam * (double)Rstar;
+                ((T*)a.Rwarm)[p] = Rstar;
+                if (a.seg_R) ((T*)a.seg_R)[a.perm[p]] = Rstar;
+            }
+            // rotate the pipeline
+            Bc = B1;
+            Rc = R1;
+            jc = j1;
+            if (DEPTH == 2) {
+#pragma unroll
+                for (int s = 0; s < J; ++s) Pc[s] = P1[s];
+                B1 = B2;
+                R1 = R2;
+                j1 = j2;
+                B2 = B3;
+            } else if (DEPTH == 1) {
+                B1 = B2;
+                B2 = load_bounds<T>(a, pos_of(tile + 3 * stride));
+            } else {
+                Bc = load_bounds<T>(a, pos_of(tile + stride));
+                jc = wave_slots<J>((int)(Bc.e - Bc.b));
+                Rc = load_raw<T, J>(a, Bc, g, jc);
+            }
+        }
+    }
+}
+
+}  // namespace seg
+}  // namespace cblp

@@ -1,0 +1,128 @@
+"""Batched re-solves (several instances advanced by one persistent launch per
+iteration) against the same instances solved one at a time, and against the
+FP64 oracle."""
+import numpy as np
+import pytest
+
+import oracle
+import oracle.lp as lp
+from paper_2602_22421_amd.instances import batch_instance, make_instance, step_scale
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def cb():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2602_22421_amd import cblp
+    cblp.load()
+    return cblp
+
+
+def _setup(cb, insts, dtype, tau0=0.002, rule=0):
+    npdt = np.float32 if dtype == torch.float32 else np.float64
+    insts = [i.cast(npdt) for i in insts]
+    probs = [cb.Problem(i, dtype=dtype) for i in insts]
+    taus = [p.tensor(step_scale(i, tau0 if rule == 0 else 1.0).astype(npdt))
+            for p, i in zip(probs, insts)]
+    return insts, probs, taus
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_batch_iterate_matches_single(cb, dtype):
+    dt = torch.float64 if dtype == "f64" else torch.float32
+    base = [batch_instance(b, scale=0.004) for b in range(6)]
+    assert len({i.L for i in base}) > 1 and len({i.n for i in base}) > 1
+    insts, singles, taus = _setup(cb, base, dt)
+    iters = 25
+    eta_single = []
+    rows_single = []
+    for p, t in zip(singles, taus):
+        params = cb.make_params(rule=0, tau_vec=t, check_every=5)
+        eta = p.zeros_eta()
+        tr, _ = p.iterate(eta, iters, params)
+        eta_single.append(eta.cpu().numpy())
+        rows_single.append(tr[-1])
+    _, probs, taus2 = _setup(cb, base, dt)
+    batch = cb.Batch(probs)
+    etas = [p.zeros_eta() for p in probs]
+    params = cb.make_params(rule=0, tau=1.0, check_every=5)
+    rows = batch.iterate(etas, iters, params, tau_vecs=taus2)
+    for q in range(len(base)):
+        # constant steps: the duals depend only on exact integer sales sums
+        assert np.array_equal(etas[q].cpu().numpy(), eta_single[q]), q
+        np.testing.assert_allclose(rows[q, :3], rows_single[q][:3], rtol=1e-12)
+    batch.close()
+
+
+def test_batch_vs_oracle_fp32(cb):
+    base = [batch_instance(b, scale=0.004) for b in (1, 2, 3)]
+    insts, probs, taus = _setup(cb, base, torch.float32, tau0=0.001)
+    batch = cb.Batch(probs)
+    etas = [p.zeros_eta() for p in probs]
+    params = cb.make_params(rule=0, tau=1.0, check_every=10)
+    rows = batch.iterate(etas, 20, params, tau_vecs=taus)
+    for q, inst in enumerate(insts):
+        s = oracle.Solver(inst, tau=taus[q].double().cpu().numpy(), check_every=10)
+        eo, tr = s.iterate(np.zeros(inst.m), 20)
+        eg = etas[q].double().cpu().numpy()
+        assert np.linalg.norm(eg - eo) <= 1e-5 * max(np.linalg.norm(eo), 1e-12), q
+        assert rows[q, 0] == pytest.approx(tr[-1, 0], rel=1e-5)
+    batch.close()
+
+
+def test_batch_solve_reaches_lp_optimum(cb):
+    # seeds on which the oracle's Polyak run certifies 1e-4 within 2100 iterations
+    base = [make_instance(1000, 50, size_lo=5, size_hi=10, cap_lo=0.3, seed=s) for s in (0, 2, 4, 5)]
+    insts, probs, taus = _setup(cb, base, torch.float64, rule=1)
+    batch = cb.Batch(probs)
+    etas = [p.zeros_eta() for p in probs]
+    params = cb.make_params(rule=1, tau=1.0, gamma=1.0, check_every=10, tol=1e-4,
+                            max_iters=4000)
+    outs = batch.solve(etas, params, tau_vecs=taus)
+    for q, (inst, o) in enumerate(zip(insts, outs)):
+        opt, _ = lp.sblp(inst)
+        assert o["status"] == 0, (q, o)
+        assert o["lb"] <= opt * (1 + 1e-12) and o["dbest"] >= opt * (1 - 1e-12), (q, o, opt)
+        assert o["gap"] <= 1e-4
+    # each instance stopped at its own check
+    assert all(o["iters"] % 10 == 0 and o["iters"] <= 4000 for o in outs)
+    batch.close()
+
+
+def test_batch_graph_replays_match_eager(cb):
+    """spfom_batch_solve replays a captured graph; the same iterations issued
+    eagerly give the same duals."""
+    base = [batch_instance(b, scale=0.004) for b in range(4)]
+    insts, p1, t1 = _setup(cb, base, torch.float32, tau0=0.001)
+    b1 = cb.Batch(p1)
+    e1 = [p.zeros_eta() for p in p1]
+    params = cb.make_params(rule=0, tau=1.0, check_every=10, tol=0.0, max_iters=40)
+    b1.solve(e1, params, tau_vecs=t1)          # 4 graph replays of 10 iterations
+    _, p2, t2 = _setup(cb, base, torch.float32, tau0=0.001)
+    b2 = cb.Batch(p2)
+    e2 = [p.zeros_eta() for p in p2]
+    for _ in range(4):
+        b2.iterate(e2, 10, params, tau_vecs=t2)
+        torch.cuda.synchronize()
+    for q in range(len(base)):
+        assert np.array_equal(e1[q].cpu().numpy(), e2[q].cpu().numpy()), q
+    b1.close()
+    b2.close()
+
+
+def test_batch_tune_picks_a_variant(cb):
+    base = [batch_instance(b, scale=0.004) for b in range(3)]
+    insts, probs, taus = _setup(cb, base, torch.float32, tau0=0.001)
+    batch = cb.Batch(probs)
+    etas = [p.zeros_eta() for p in probs]
+    params = cb.make_params(rule=0, tau=1.0, check_every=5)
+    v = batch.tune(etas, params, iters=3, tau_vecs=taus)
+    assert v in (0, 4, 5, 6)
+    assert batch.info()["variant"] == v
+    rows = batch.iterate([p.zeros_eta() for p in probs], 5, params, tau_vecs=taus)
+    assert np.all(np.isfinite(rows))
+    batch.close()
