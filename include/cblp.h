@@ -226,6 +226,72 @@ int cblp_batch_tune(cblp_batch_t b, void* const* etas, const void* const* tau_ve
 /* Work items, persistent grid and kernel variant of the batch ([host], nullable). */
 int cblp_batch_info(cblp_batch_t b, int32_t* items, int32_t* grid, int32_t* variant);
 
+/* ---------------------------------------------------------- learned warm start
+ * A small network maps four features of each product to a starting capacity
+ * dual for spfom_solve (identity resource matrix, m = n).  Not part of the
+ * paper's method, which leaves learned starts to future work (Section 7); it
+ * only changes the first iterate eta^0 of Algorithm 1, so every certificate
+ * (the dual bound D and the averaged-primal lower bound) keeps its meaning.
+ *
+ * Features per product j, written as X[j*4 + k] (FP32, [n x 4] row-major):
+ *   k=0  min(c_j / d_j, 4), d_j = sum_l lambda_l v_lj / (v_l0 + sum_{i in N_l} v_li),
+ *        the sales of j when every segment is offered its whole consideration
+ *        set (4 where d_j = 0)
+ *   k=1  r_j / max_i r_i  (0 if no revenue is positive)
+ *   k=2  log1p((sum_l v_lj) * n / L)
+ *   k=3  log1p(deg_j * n / L), deg_j = number of segments whose set holds j
+ * The sums are taken in 64-bit fixed point, so X is bitwise reproducible.
+ *
+ * Network: y = w3 . GELU(W2^T GELU(W1^T x + b1) + b2) + b3 with hidden width
+ * 256, GELU(z) = z Phi(z) (exact, erf form).  Parameters are one FP32 vector
+ * of wsnet_num_params() = 67329 entries laid out as W1 [4 x 256] (row k holds
+ * the weights of input k), b1 [256], W2 [256 x 256] (row i = hidden unit i of
+ * the first layer), b2 [256], w3 [256], b3 [1].  Every weight is used rounded
+ * to BF16 (nearest even); the second layer multiplies BF16(h1) by BF16(W2) on
+ * the matrix cores with FP32 accumulation; everything else is FP32.  The
+ * predicted dual is eta_j = max(0, y_j) * r_j.
+ *
+ * Training: mean squared error over rows, L = (1/rows) sum (y - t)^2, minimised
+ * by Adam (beta1 0.9, beta2 0.999, eps 1e-8) on the FP32 parameters.  Backward
+ * uses BF16(dZ2) against BF16(H1) and BF16(W2) on the matrix cores; parameter
+ * gradients are summed over rows in FP64 in a fixed order.
+ *
+ * All pointers named X, Y, y, grads, eta are [dev]; rows are padded inside to
+ * a multiple of 16.  The net owns its parameters and a row-sized workspace it
+ * grows on demand (calls on one net must not overlap).
+ */
+typedef struct wsnet* wsnet_t;
+
+int64_t wsnet_num_params(void);
+
+/* New network with He-normal weights drawn from seed, zero biases. */
+int wsnet_create(wsnet_t* out, uint64_t seed, void* stream);
+void wsnet_destroy(wsnet_t w);
+
+/* get [host] nullable receives the parameters; set [host] nullable replaces
+ * them (and clears the Adam state).  Synchronises the stream. */
+int wsnet_params(wsnet_t w, float* get, const float* set, void* stream);
+
+/* Features of the instance behind h into X [dev] [n x 4].  Synchronises. */
+int wsnet_features(cblp_t h, float* X, void* stream);
+
+/* y [dev] [rows] = network(X [dev] [rows x 4]). */
+int wsnet_forward(wsnet_t w, const float* X, int64_t rows, float* y, void* stream);
+
+/* Loss (host, nullable) and gradient grads [dev] [num_params] (nullable) of
+ * the mean squared error against targets Y [dev] [rows]; no update. */
+int wsnet_gradients(wsnet_t w, const float* X, const float* Y, int64_t rows, float* grads,
+                    double* loss, void* stream);
+
+/* One Adam step of rate lr on the batch (X, Y); loss [host] nullable is the
+ * batch loss before the step (synchronises only when loss is requested). */
+int wsnet_train_step(wsnet_t w, const float* X, const float* Y, int64_t rows, float lr,
+                     double* loss, void* stream);
+
+/* Predicted duals of the instance behind h into eta [dev] [n] (h's dtype);
+ * CBLP_EINVAL unless A = identity. */
+int wsnet_predict(wsnet_t w, cblp_t h, void* eta, void* stream);
+
 /* Describe the last failure on this thread ("" if none). */
 const char* cblp_last_error(void);
 

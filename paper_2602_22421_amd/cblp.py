@@ -25,7 +25,9 @@ TRACE_COLS = ("D", "P", "Z", "eta2", "infeas", "dbest", "lb", "gap", "step", "th
 EXPORTS = ("cblp_create", "cblp_destroy", "spfom_reset", "spfom_iterate", "spfom_solve",
            "cblp_gap", "cblp_sales", "cblp_launch_info", "cblp_timing", "cblp_timing_read",
            "cblp_last_error", "cblp_batch_create", "cblp_batch_destroy", "spfom_batch_iterate",
-           "spfom_batch_solve", "cblp_batch_tune", "cblp_batch_info")
+           "spfom_batch_solve", "cblp_batch_tune", "cblp_batch_info", "wsnet_num_params",
+           "wsnet_create", "wsnet_destroy", "wsnet_params", "wsnet_features", "wsnet_forward",
+           "wsnet_gradients", "wsnet_train_step", "wsnet_predict")
 
 
 class SpfomParams(ctypes.Structure):
@@ -105,6 +107,25 @@ def load(path: str = _LIB_PATH) -> ctypes.CDLL:
                                     ctypes.POINTER(i32)]
     lib.cblp_last_error.restype = ctypes.c_char_p
     lib.cblp_last_error.argtypes = []
+    lib.wsnet_num_params.restype = i64
+    lib.wsnet_num_params.argtypes = []
+    lib.wsnet_create.restype = ctypes.c_int
+    lib.wsnet_create.argtypes = [ctypes.POINTER(vp), ctypes.c_uint64, vp]
+    lib.wsnet_destroy.restype = None
+    lib.wsnet_destroy.argtypes = [vp]
+    lib.wsnet_params.restype = ctypes.c_int
+    lib.wsnet_params.argtypes = [vp, vp, vp, vp]
+    lib.wsnet_features.restype = ctypes.c_int
+    lib.wsnet_features.argtypes = [vp, vp, vp]
+    lib.wsnet_forward.restype = ctypes.c_int
+    lib.wsnet_forward.argtypes = [vp, vp, i64, vp, vp]
+    lib.wsnet_gradients.restype = ctypes.c_int
+    lib.wsnet_gradients.argtypes = [vp, vp, vp, i64, vp, ctypes.POINTER(ctypes.c_double), vp]
+    lib.wsnet_train_step.restype = ctypes.c_int
+    lib.wsnet_train_step.argtypes = [vp, vp, vp, i64, ctypes.c_float,
+                                     ctypes.POINTER(ctypes.c_double), vp]
+    lib.wsnet_predict.restype = ctypes.c_int
+    lib.wsnet_predict.argtypes = [vp, vp, vp, vp]
     _lib = lib
     return lib
 
@@ -364,3 +385,124 @@ class Batch:
 
     def info(self) -> dict:
         return cblp_batch_info(self.b)
+
+
+# ------------------------------------------------------------ learned warm start
+
+def wsnet_num_params() -> int:
+    return int(load().wsnet_num_params())
+
+
+def wsnet_create(seed: int = 0, stream=None) -> int:
+    w = ctypes.c_void_p()
+    _check(load().wsnet_create(ctypes.byref(w), ctypes.c_uint64(seed), _stream(stream)))
+    return w.value
+
+
+def wsnet_destroy(w) -> None:
+    if w:
+        load().wsnet_destroy(ctypes.c_void_p(w))
+
+
+def wsnet_params(w, get: Optional[np.ndarray] = None, set: Optional[np.ndarray] = None,
+                 stream=None) -> None:
+    for a in (get, set):
+        if a is not None:
+            assert a.dtype == np.float32 and a.flags.c_contiguous
+            assert a.size == wsnet_num_params()
+    _check(load().wsnet_params(ctypes.c_void_p(w),
+                               None if get is None else get.ctypes.data_as(ctypes.c_void_p),
+                               None if set is None else set.ctypes.data_as(ctypes.c_void_p),
+                               _stream(stream)))
+
+
+def wsnet_features(h, X: torch.Tensor, stream=None) -> None:
+    assert X.dtype == torch.float32 and X.is_contiguous()
+    _check(load().wsnet_features(ctypes.c_void_p(h), _ptr(X), _stream(stream)))
+
+
+def wsnet_forward(w, X: torch.Tensor, y: torch.Tensor, stream=None) -> None:
+    assert X.dtype == torch.float32 and y.dtype == torch.float32 and X.shape[1] == 4
+    assert X.is_contiguous() and y.numel() >= X.shape[0]
+    _check(load().wsnet_forward(ctypes.c_void_p(w), _ptr(X), X.shape[0], _ptr(y),
+                                _stream(stream)))
+
+
+def wsnet_gradients(w, X: torch.Tensor, Y: torch.Tensor, grads: Optional[torch.Tensor] = None,
+                    stream=None) -> float:
+    assert X.dtype == torch.float32 and Y.dtype == torch.float32 and X.shape[1] == 4
+    assert X.is_contiguous() and Y.numel() == X.shape[0]
+    if grads is not None:
+        assert grads.dtype == torch.float32 and grads.numel() == wsnet_num_params()
+    loss = ctypes.c_double()
+    _check(load().wsnet_gradients(ctypes.c_void_p(w), _ptr(X), _ptr(Y), X.shape[0], _ptr(grads),
+                                  ctypes.byref(loss), _stream(stream)))
+    return loss.value
+
+
+def wsnet_train_step(w, X: torch.Tensor, Y: torch.Tensor, lr: float, want_loss: bool = False,
+                     stream=None) -> Optional[float]:
+    assert X.dtype == torch.float32 and Y.dtype == torch.float32 and X.shape[1] == 4
+    assert X.is_contiguous() and Y.numel() == X.shape[0]
+    loss = ctypes.c_double()
+    _check(load().wsnet_train_step(ctypes.c_void_p(w), _ptr(X), _ptr(Y), X.shape[0],
+                                   ctypes.c_float(lr), ctypes.byref(loss) if want_loss else None,
+                                   _stream(stream)))
+    return loss.value if want_loss else None
+
+
+def wsnet_predict(w, h, eta: torch.Tensor, stream=None) -> None:
+    _check(load().wsnet_predict(ctypes.c_void_p(w), ctypes.c_void_p(h), _ptr(eta),
+                                _stream(stream)))
+
+
+class WarmStartNet:
+    """The warm-start network (owns its device parameters)."""
+
+    def __init__(self, seed: int = 0):
+        self.w = wsnet_create(seed)
+
+    def close(self):
+        if getattr(self, "w", None):
+            wsnet_destroy(self.w)
+            self.w = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def params(self) -> np.ndarray:
+        out = np.empty(wsnet_num_params(), np.float32)
+        wsnet_params(self.w, get=out)
+        return out
+
+    @params.setter
+    def params(self, p) -> None:
+        wsnet_params(self.w, set=np.ascontiguousarray(p, dtype=np.float32))
+
+    def forward(self, X: torch.Tensor) -> torch.Tensor:
+        y = torch.empty(X.shape[0], dtype=torch.float32, device=X.device)
+        wsnet_forward(self.w, X, y)
+        return y
+
+    def gradients(self, X: torch.Tensor, Y: torch.Tensor):
+        g = torch.empty(wsnet_num_params(), dtype=torch.float32, device=X.device)
+        loss = wsnet_gradients(self.w, X, Y, g)
+        return loss, g
+
+    def train_step(self, X: torch.Tensor, Y: torch.Tensor, lr: float, want_loss=False):
+        return wsnet_train_step(self.w, X, Y, lr, want_loss)
+
+    def predict(self, prob: "Problem") -> torch.Tensor:
+        eta = prob.zeros_eta()
+        wsnet_predict(self.w, prob.h, eta)
+        return eta
+
+
+def features(prob: "Problem") -> torch.Tensor:
+    X = torch.empty((prob.n, 4), dtype=torch.float32, device=prob.device)
+    wsnet_features(prob.h, X)
+    return X

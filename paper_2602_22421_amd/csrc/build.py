@@ -7,7 +7,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 PKG = os.path.dirname(HERE)
 ROOT = os.path.dirname(PKG)
 LIB = os.path.join(PKG, "libcblp.so")
-SOURCES = [os.path.join(HERE, f) for f in ("capi.hip", "prep.hip", "segment.hip", "dual.hip", "batch.hip")]
+SOURCES = [os.path.join(HERE, f) for f in ("capi.hip", "prep.hip", "segment.hip", "dual.hip", "batch.hip", "mlp.hip")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

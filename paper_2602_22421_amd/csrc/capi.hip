@@ -78,7 +78,7 @@ int dalloc(P** p, size_t bytes)
 void release(cblp_instance* h)
 {
     if (!h) return;
-    void* ptrs[] = {h->ptr2, h->idx2, h->v2, h->den2, h->vt0, h->lam2, h->Rwarm, h->perm,
+    void* ptrs[] = {h->ptr2, h->idx2, h->v2, h->den2, h->vt0, h->lam2, h->Rwarm, h->v0c, h->perm,
                     h->rho, h->S_fx, h->part_S, h->S_d, h->u_d, h->sum_u, h->zpart,
                     h->bpart, h->bpart2, h->st, h->trace, h->at_ptr,
                     h->at_prod, h->at_val};
@@ -416,12 +416,13 @@ int create_impl(cblp_instance* h, hipStream_t s)
         if ((rc = dalloc(&h->vt0, (size_t)L1 * esz))) return rc;
         if ((rc = dalloc(&h->lam2, (size_t)L1 * esz))) return rc;
         if ((rc = dalloc(&h->Rwarm, (size_t)L1 * esz))) return rc;
+        if ((rc = dalloc(&h->v0c, (size_t)L1 * esz))) return rc;
         HIP_TRY(hipMemcpyAsync(h->ptr2, ptr.data(), (h->L + 1) * 8, hipMemcpyHostToDevice, s));
         HIP_TRY(hipMemcpyAsync(h->perm, perm.data(), L1 * 4, hipMemcpyHostToDevice, s));
         if (h->L > 0)
             HIP_TRY(launch_relayout<T>(h->L, h->seg_ptr, h->idx, h->v, h->w, h->v0, h->lam,
                                        h->perm, h->ptr2, h->idx2, h->v2, h->den2, h->vt0,
-                                       h->lam2, h->Rwarm, s));
+                                       h->lam2, h->Rwarm, h->v0c, s));
         HIP_TRY(hipStreamSynchronize(s));   // the host vectors die here
     }
 

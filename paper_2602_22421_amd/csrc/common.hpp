@@ -101,7 +101,8 @@ template <typename T>
 hipError_t launch_relayout(int64_t L, const int64_t* seg_ptr, const int32_t* idx,
                            const void* v, const void* w, const void* v0, const void* lam,
                            const int32_t* perm, const int64_t* ptr, int32_t* idx2, void* v2,
-                           void* den2, void* vt0, void* lam2, void* Rwarm, hipStream_t s);
+                           void* den2, void* vt0, void* lam2, void* Rwarm, void* v0c,
+                           hipStream_t s);
 template <typename T>
 hipError_t launch_prices(int64_t n, const void* r, const void* eta, const int64_t* a_ptr,
                          const int32_t* a_idx, const void* a_val, void* rho, hipStream_t s);

@@ -27,6 +27,7 @@ struct cblp_instance {
     void* vt0 = nullptr;
     void* lam2 = nullptr;
     void* Rwarm = nullptr;
+    void* v0c = nullptr;            // v0 per position (features only)
     int32_t* perm = nullptr;
     // owned workspace
     void* rho = nullptr;

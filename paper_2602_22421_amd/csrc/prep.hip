@@ -85,7 +85,7 @@ template <typename T>
 __global__ void k_relayout(int64_t L, const int64_t* seg_ptr, const int32_t* idx, const T* v,
                            const T* w, const T* v0, const T* lam, const int32_t* perm,
                            const int64_t* ptr, int32_t* idx2, T* v2, T* den2, T* vt0, T* lam2,
-                           T* Rwarm)
+                           T* Rwarm, T* v0c)
 {
     for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < L;
          p += (int64_t)gridDim.x * blockDim.x) {
@@ -101,6 +101,7 @@ __global__ void k_relayout(int64_t L, const int64_t* seg_ptr, const int32_t* idx
         }
         vt0[p] = (T)s;
         lam2[p] = lam[l];
+        v0c[p] = v0[l];
         Rwarm[p] = T(0);
     }
 }
@@ -148,11 +149,12 @@ template <typename T>
 hipError_t launch_relayout(int64_t L, const int64_t* seg_ptr, const int32_t* idx,
                            const void* v, const void* w, const void* v0, const void* lam,
                            const int32_t* perm, const int64_t* ptr, int32_t* idx2, void* v2,
-                           void* den2, void* vt0, void* lam2, void* Rwarm, hipStream_t s)
+                           void* den2, void* vt0, void* lam2, void* Rwarm, void* v0c,
+                           hipStream_t s)
 {
     hipLaunchKernelGGL(k_relayout<T>, dim3(2048), dim3(256), 0, s, L, seg_ptr, idx,
                        (const T*)v, (const T*)w, (const T*)v0, (const T*)lam, perm, ptr, idx2,
-                       (T*)v2, (T*)den2, (T*)vt0, (T*)lam2, (T*)Rwarm);
+                       (T*)v2, (T*)den2, (T*)vt0, (T*)lam2, (T*)Rwarm, (T*)v0c);
     return hipGetLastError();
 }
 
@@ -179,7 +181,7 @@ hipError_t launch_prices(int64_t n, const void* r, const void* eta, const int64_
     template hipError_t launch_relayout<T>(int64_t, const int64_t*, const int32_t*,            \
                                            const void*, const void*, const void*, const void*, \
                                            const int32_t*, const int64_t*, int32_t*, void*,    \
-                                           void*, void*, void*, void*, hipStream_t);
+                                           void*, void*, void*, void*, void*, hipStream_t);
 CBLP_INST(float)
 CBLP_INST(double)
 #undef CBLP_INST

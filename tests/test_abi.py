@@ -15,7 +15,7 @@ LIB = os.path.join(ROOT, "paper_2602_22421_amd", "libcblp.so")
 def _declared():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"^\s*(?:int|void|const char\*)\s+(\w+)\s*\(", text, flags=re.M)))
+    return sorted(set(re.findall(r"^\s*(?:int64_t|int|void|const char\*)\s+(\w+)\s*\(", text, flags=re.M)))
 
 
 @pytest.fixture(scope="module")

@@ -1,0 +1,211 @@
+"""Learned warm start on the GPU: features, the MFMA forward pass, gradients
+and Adam against the FP64 reference with the same BF16 rounding points,
+training, and the gain over the cold start with its fallback."""
+import numpy as np
+import pytest
+
+import oracle.mlp as om
+from paper_2602_22421_amd.instances import config_instance, make_instance
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def cb():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2602_22421_amd import cblp
+    cblp.load()
+    return cblp
+
+
+def _rows(seed, rows):
+    g = np.random.default_rng(seed)
+    X = np.column_stack([g.uniform(0.1, 4.0, rows), g.uniform(0, 1, rows),
+                         g.uniform(0, 4, rows), g.uniform(0, 4, rows)]).astype(np.float32)
+    Y = g.uniform(0, 1, rows).astype(np.float32)
+    return X, Y
+
+
+def _params(seed):
+    p = om.init_params(seed)
+    g = np.random.default_rng(seed + 1)
+    q = om.unpack(p)
+    q["b1"][:] = g.normal(size=256) * 0.1
+    q["b2"][:] = g.normal(size=256) * 0.1
+    q["b3"][:] = 0.3
+    return p.astype(np.float32)
+
+
+# Forward tolerance.  Both sides round h1 = GELU(z1) to BF16, the GPU from
+# its FP32 value, the reference from FP64; where h1 lies within FP32 error of
+# a BF16 rounding boundary the two round to neighbouring BF16 values.  Such a
+# row differs by at most one BF16 step of one h1_i carried to the output,
+# ulp(h1_i) * sum_u |W2[i,u] w3_u| * max GELU' (GELU' <= 1.13); every other
+# row differs only by FP32 accumulation (256 terms, about 256 * 2^-24 of the
+# sum of |terms|), far below 1e-5 of the output scale here.
+FWD_RTOL = 1e-5
+
+
+def _flip_bound(p, X):
+    q = om.unpack(p.astype(np.float64))
+    h1 = om.gelu(X.astype(np.float64) @ om.bf16(q["W1"]) + q["b1"])
+    ulp = 2.0 ** (np.floor(np.log2(np.abs(h1).max())) - 7)
+    return ulp * np.max(np.abs(om.bf16(q["W2"])) @ np.abs(om.bf16(q["w3"]))) * 1.13
+
+
+@pytest.mark.parametrize("rows", [1, 16, 1000, 4099])
+def test_forward_matches_reference(cb, rows):
+    net = cb.WarmStartNet(seed=1)
+    p = _params(3)
+    net.params = p
+    X, _ = _rows(rows, rows)
+    y = net.forward(torch.from_numpy(X).cuda()).cpu().numpy().astype(np.float64)
+    ref, _ = om.forward(p.astype(np.float64), X.astype(np.float64), bf=True)
+    err = np.abs(y - ref)
+    tight = err <= FWD_RTOL * (np.abs(ref).max() + 1.0)
+    assert tight.mean() >= 0.99, (tight.mean(), err.max())
+    assert err.max() <= _flip_bound(p, X) + FWD_RTOL * (np.abs(ref).max() + 1.0)
+    net.close()
+
+
+def test_forward_single_path_exact(cb):
+    """One live path (input 0 -> unit 5 -> unit 37 -> output): every product has one
+    nonzero term, so the MFMA tile layout must put it in the right place."""
+    p = np.zeros(om.NPARAM, np.float32)
+    q = om.unpack(p)
+    q["W1"][0, 5] = 0.75
+    q["W2"][5, 37] = 1.5
+    q["w3"][37] = -2.0
+    q["b3"][0] = 0.25
+    net = cb.WarmStartNet(seed=0)
+    net.params = p
+    X, _ = _rows(7, 50)
+    y = net.forward(torch.from_numpy(X).cuda()).cpu().numpy()
+    ref, _ = om.forward(p.astype(np.float64), X.astype(np.float64), bf=True)
+    np.testing.assert_allclose(y, ref, rtol=1e-5, atol=1e-6)
+    # and a different (i, u) gives a different answer: the test sees the layout
+    q["W2"][5, 37], q["W2"][37, 5] = 0.0, 1.5
+    q["w3"][37], q["w3"][5] = 0.0, -2.0
+    net.params = p
+    y2 = net.forward(torch.from_numpy(X).cuda()).cpu().numpy()
+    np.testing.assert_allclose(y2, 0.25, atol=1e-6)
+    net.close()
+
+
+def _blocks():
+    off = np.cumsum([0] + [int(np.prod(s)) for _, s in om.SHAPES])
+    return {name: slice(off[i], off[i + 1]) for i, (name, _) in enumerate(om.SHAPES)}
+
+
+@pytest.mark.parametrize("rows", [37, 700])
+def test_gradients_match_reference(cb, rows):
+    net = cb.WarmStartNet(seed=2)
+    p = _params(5)
+    net.params = p
+    X, Y = _rows(11 + rows, rows)
+    loss, g = net.gradients(torch.from_numpy(X).cuda(), torch.from_numpy(Y).cuda())
+    g = g.cpu().numpy().astype(np.float64)
+    lref, gref = om.gradients(p.astype(np.float64), X.astype(np.float64), Y.astype(np.float64))
+    assert loss == pytest.approx(lref, rel=1e-4)
+    for name, sl in _blocks().items():
+        d = np.linalg.norm(g[sl] - gref[sl])
+        # FP32 sums over rows and hidden units, plus rare BF16 boundary flips
+        assert d <= 2e-4 * np.linalg.norm(gref[sl]) + 1e-9, (name, d, np.linalg.norm(gref[sl]))
+    net.close()
+
+
+def test_adam_step_matches_reference(cb):
+    net = cb.WarmStartNet(seed=3)
+    p = _params(9)
+    net.params = p
+    X, Y = _rows(21, 300)
+    lr = 1e-3
+    Xd, Yd = torch.from_numpy(X).cuda(), torch.from_numpy(Y).cuda()
+    p64 = p.astype(np.float64)
+    m = np.zeros_like(p64)
+    v = np.zeros_like(p64)
+    gs = []
+    for step in (1, 2):
+        net.train_step(Xd, Yd, lr)
+        _, g = om.gradients(p64, X.astype(np.float64), Y.astype(np.float64))
+        gs.append(g)
+        p64, m, v = om.adam_step(p64, g, m, v, step, lr)
+    got = net.params.astype(np.float64)
+    # Adam's step m_hat / sqrt(v_hat) depends on the gradient's direction, so
+    # it matches where the gradient is well resolved in FP32 (both steps'
+    # |g| above 1e-4 of its block's largest); each step is at most lr long
+    # (Cauchy-Schwarz on the moment sums), so no entry can differ by over 4 lr
+    ok = np.ones(om.NPARAM, bool)
+    for sl in _blocks().values():
+        for g in gs:
+            ok[sl] &= np.abs(g[sl]) > 1e-4 * np.abs(g[sl]).max()
+    assert ok.mean() > 0.7
+    np.testing.assert_allclose(got[ok], p64[ok], atol=0.02 * lr)
+    assert np.max(np.abs(got - p64)) <= 4.0 * lr
+    net.close()
+
+
+def _feature_instance(kind):
+    if kind == "cfg":       # the L=2e6 Zipf workload shrunk (n = 2000 < LDS-binned products)
+        return config_instance(1, seed=5, scale=0.01)
+    # more products than the LDS bins hold, and products no segment considers
+    return make_instance(3000, 5000, size_lo=5, size_hi=50, zipf=1.1, cap_lo=0.2, cap_hi=0.5,
+                         seed=5)
+
+
+@pytest.mark.parametrize("kind", ["cfg", "wide"])
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_features_match_reference(cb, dtype, kind):
+    dt = torch.float32 if dtype == "f32" else torch.float64
+    inst = _feature_instance(kind).cast(np.float32 if dtype == "f32" else np.float64)
+    prob = cb.Problem(inst, dtype=dt)
+    X = cb.features(prob).cpu().numpy().astype(np.float64)
+    ref = om.features(inst)
+    if kind == "wide":
+        assert (np.bincount(inst.idx, minlength=inst.n) == 0).any()
+    np.testing.assert_allclose(X, ref, rtol=2e-6, atol=1e-7)
+    # deterministic: a second call is bitwise equal
+    X2 = cb.features(prob).cpu().numpy().astype(np.float64)
+    assert np.array_equal(X, X2)
+    prob.close()
+
+
+def test_training_reduces_loss(cb):
+    from paper_2602_22421_amd import warmstart
+    X, _ = _rows(31, 20000)
+    # a smooth target of the kind the duals follow: scarce, valuable products
+    Y = (np.maximum(0.0, 1.0 - X[:, 0]) * X[:, 1] + 0.05 * X[:, 2]).astype(np.float32)
+    net = cb.WarmStartNet(seed=4)
+    Xd, Yd = torch.from_numpy(X).cuda(), torch.from_numpy(Y).cuda()
+    losses = warmstart.train(net, Xd, Yd, epochs=8, batch=1024, lr=2e-3)
+    assert losses[-1] < 0.05 * losses[0], losses
+    net.close()
+
+
+def test_warm_start_gains_and_falls_back(cb):
+    from paper_2602_22421_amd import warmstart
+    spec = warmstart.SolveSpec(tol=1e-3, max_iters=3000)
+    gen = lambda s: make_instance(20000, 400, size_lo=5, size_hi=50, zipf=1.1, cap_lo=0.2,
+                                  cap_hi=0.5, seed=s)
+    X, Y = warmstart.collect([gen(100 + s) for s in range(12)], spec, dtype=torch.float64)
+    net = cb.WarmStartNet(seed=5)
+    warmstart.train(net, X, Y, epochs=60, batch=1024, lr=1e-3)
+    inst = gen(999)
+    prob = cb.Problem(inst, dtype=torch.float64)
+    cold, _ = warmstart.cold_solve(prob, inst, spec)
+    warm, _ = warmstart.warm_solve(net, prob, inst, spec)
+    assert warm["warm"] and warm["D_pred"] < warm["D0"]
+    assert warm["status"] == 0
+    assert warm["iters"] < cold["iters"], (warm, cold)
+    # a network that predicts huge duals is refused: the run equals the cold one
+    bad = np.zeros(om.NPARAM, np.float32)
+    bad[-1] = 1e3                       # y = b3 = 1000 for every product
+    net.params = bad
+    fb, _ = warmstart.warm_solve(net, prob, inst, spec)
+    assert not fb["warm"] and fb["D_pred"] > fb["D0"]
+    assert fb["iters"] == cold["iters"] and fb["dbest"] == cold["dbest"]
+    prob.close()
+    net.close()
