@@ -167,6 +167,105 @@ def batched(args):
     batch.close()
 
 
+def warmstart_bench(args):
+    """Learned warm start: train the network on the duals of solved L=1e5
+    instances of the L=2e6 Zipf generator, then solve held-out L=2e6 instances
+    from its prediction and from zero with the same constant step, recording
+    the iterations and seconds each start needs to certify each gap level
+    (prediction and fallback check included in the warm time)."""
+    import torch
+    from paper_2602_22421_amd import cblp, warmstart
+    from paper_2602_22421_amd.instances import config_instance, step_scale
+
+    caps = {"tight": (0.2, 0.5), "loose": (0.5, 3.0)}[args.ws_caps]
+    stages = [(3e-3, 1500), (1e-3, 1000), (3e-4, 1000)]
+    spec = warmstart.SolveSpec(rule=cblp.SPFOM_STEP_CONST, tau0=args.ws_tau0, check_every=10,
+                               tol=0.0, max_iters=args.max_iters)
+    t0 = time.perf_counter()
+    train_insts = (config_instance(1, seed=10_000 + s, scale=0.05, cap_lo=caps[0], cap_hi=caps[1])
+                   .cast(np.float32) for s in range(args.ws_train))
+    X, Y = warmstart.collect(train_insts, spec, dtype=torch.float32, stages=stages)
+    t_collect = time.perf_counter() - t0
+    log(f"collected {X.shape[0]} products from {args.ws_train} solved L=1e5 instances "
+        f"in {t_collect:.1f} s")
+    net = cblp.WarmStartNet(seed=0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    losses = warmstart.train(net, X, Y, epochs=args.ws_epochs, batch=2048, lr=3e-4)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    log(f"trained {args.ws_epochs} epochs in {t_train:.1f} s: loss {losses[0]:.3e} -> "
+        f"{losses[-1]:.3e} (target variance {float(Y.var()):.3e})")
+    levels = (1e-1, 3e-2, 2e-2, 1e-2, 1e-3, 1e-4)
+    results = []
+    for seed in args.ws_eval_seeds:
+        inst = config_instance(1, seed=seed, cap_lo=caps[0], cap_hi=caps[1]).cast(np.float32)
+        prob = cblp.Problem(inst, dtype=torch.float32)
+        tau = prob.tensor(step_scale(inst, args.ws_tau0).astype(np.float32))
+        params = cblp.make_params(rule=cblp.SPFOM_STEP_CONST, tau_vec=tau, check_every=10)
+        row = {"seed": seed}
+        for start in ("cold", "warm"):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            info = {}
+            if start == "warm":
+                eta = net.predict(prob)
+                d_pred, d0 = prob.gap(eta)["D"], prob.gap(prob.zeros_eta())["D"]
+                info = {"D_pred": d_pred, "D0": d0, "used": bool(d_pred < d0)}
+                if not info["used"]:
+                    eta.zero_()
+            else:
+                eta = prob.zeros_eta()
+            t_start = time.perf_counter() - t0
+            prob.reset()
+            tr = np.zeros((args.max_iters, cblp.NTRACE))
+            t1 = time.perf_counter()
+            cblp.spfom_iterate(prob.h, eta, params, args.max_iters, tr)
+            torch.cuda.synchronize()
+            per_iter = (time.perf_counter() - t1) / args.max_iters
+            gaps = tr[9::10, 7]
+            reach = {}
+            for lv in levels:
+                k = np.nonzero(gaps <= lv)[0]
+                it = int((k[0] + 1) * 10) if len(k) else None
+                reach[f"{lv:g}"] = None if it is None else {
+                    "iters": it, "seconds": t_start + it * per_iter}
+            row[start] = dict(info, reach=reach, final_gap=float(gaps[-1]),
+                              dbest=float(tr[-1, 5]), start_seconds=t_start,
+                              ms_per_iter=per_iter * 1e3)
+            log(f"seed {seed} {start}: final gap {gaps[-1]:.3e}, reach {reach}")
+        results.append(row)
+        prob.close()
+
+    def speedup(lv):
+        r = []
+        for row in results:
+            c, w = row["cold"]["reach"][lv], row["warm"]["reach"][lv]
+            if c and w:
+                r.append(c["seconds"] / w["seconds"])
+        return float(np.mean(r)) if r else None
+
+    head = f"{3e-2:g}"
+    out = {
+        "metric": "time to certified gap 3e-2, warm start vs cold", "unit": "s",
+        "value": float(np.mean([r["warm"]["reach"][head]["seconds"] for r in results
+                                if r["warm"]["reach"][head]])) if all(
+            r["warm"]["reach"][head] for r in results) else None,
+        "higher_is_better": False, "n_gpus": 1, "dtype": "f32", "data": "synthetic",
+        "vs_baseline": None,
+        "config": {"workload": f"warm-start-L2e6-n2e4-zipf-caps-{args.ws_caps}",
+                   "train": f"{args.ws_train} instances L=1e5 n=4472, targets after "
+                            f"{sum(k for _, k in stages)} staged iterations",
+                   "epochs": args.ws_epochs, "tau0": args.ws_tau0,
+                   "max_iters": args.max_iters, "caps": caps},
+        "speedup_by_level": {f"{lv:g}": speedup(f"{lv:g}") for lv in levels},
+        "collect_s": t_collect, "train_s": t_train, "loss_first": losses[0],
+        "loss_last": losses[-1], "target_variance": float(Y.var()), "eval": results,
+    }
+    print(json.dumps(out), flush=True)
+    net.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -185,6 +284,16 @@ def main():
                     help="scales every instance's segment count (1.0: L log-uniform in [1e3, 1e6])")
     ap.add_argument("--tol", type=float, default=2e-2)
     ap.add_argument("--max-iters", type=int, default=2000)
+    ap.add_argument("--warmstart", action="store_true",
+                    help="learned warm start: train on solved L=1e5 instances, compare warm and "
+                         "cold starts on held-out L=2e6 instances")
+    ap.add_argument("--ws-caps", default="tight", choices=["tight", "loose"],
+                    help="capacities 0.2-0.5x (tight, the L=2e6 workload's) or 0.5-3x (loose) "
+                         "of the full-offer demand")
+    ap.add_argument("--ws-train", type=int, default=64)
+    ap.add_argument("--ws-epochs", type=int, default=40)
+    ap.add_argument("--ws-tau0", type=float, default=1e-3)
+    ap.add_argument("--ws-eval-seeds", type=int, nargs="+", default=[101, 102])
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device-to-device copy: the reference kernel whose "
                          "FETCH_SIZE / WRITE_SIZE counters scale the traffic figures")
@@ -205,6 +314,10 @@ def main():
     torch.cuda.set_device(0)
     if args.batched:
         return batched(args)
+    if args.warmstart:
+        if args.max_iters == 2000 and "--max-iters" not in sys.argv:
+            args.max_iters = 3000
+        return warmstart_bench(args)
     if args.copy_calibration:
         x = torch.ones(1 << 28, dtype=torch.float32, device="cuda")   # 1 GiB
         y = torch.empty_like(x)

@@ -288,6 +288,19 @@ int wsnet_gradients(wsnet_t w, const float* X, const float* Y, int64_t rows, flo
 int wsnet_train_step(wsnet_t w, const float* X, const float* Y, int64_t rows, float lr,
                      double* loss, void* stream);
 
+/* epochs passes of Adam over (X [dev] [rows x 4], Y [dev] [rows]) in
+ * minibatches of batch rows (the last one smaller), each epoch in a fresh
+ * random order drawn on the host from seed (mt19937_64, Fisher-Yates); each
+ * minibatch takes one wsnet_train_step.  losses [host] [epochs] nullable
+ * receives each epoch's mean squared error, the batch losses before their
+ * steps.  Synchronises once per epoch. */
+int wsnet_train_epochs(wsnet_t w, const float* X, const float* Y, int64_t rows, int64_t batch,
+                       int32_t epochs, float lr, uint64_t seed, double* losses, void* stream);
+
+/* Training targets of the instance behind h: Y [dev] [n] = eta_j / r_j, 0
+ * where r_j <= 0 (eta [dev] [n], h's dtype); CBLP_EINVAL unless A = identity. */
+int wsnet_targets(cblp_t h, const void* eta, float* Y, void* stream);
+
 /* Predicted duals of the instance behind h into eta [dev] [n] (h's dtype);
  * CBLP_EINVAL unless A = identity. */
 int wsnet_predict(wsnet_t w, cblp_t h, void* eta, void* stream);

@@ -27,7 +27,8 @@ EXPORTS = ("cblp_create", "cblp_destroy", "spfom_reset", "spfom_iterate", "spfom
            "cblp_last_error", "cblp_batch_create", "cblp_batch_destroy", "spfom_batch_iterate",
            "spfom_batch_solve", "cblp_batch_tune", "cblp_batch_info", "wsnet_num_params",
            "wsnet_create", "wsnet_destroy", "wsnet_params", "wsnet_features", "wsnet_forward",
-           "wsnet_gradients", "wsnet_train_step", "wsnet_predict")
+           "wsnet_gradients", "wsnet_train_step", "wsnet_train_epochs", "wsnet_targets",
+           "wsnet_predict")
 
 
 class SpfomParams(ctypes.Structure):
@@ -124,6 +125,11 @@ def load(path: str = _LIB_PATH) -> ctypes.CDLL:
     lib.wsnet_train_step.restype = ctypes.c_int
     lib.wsnet_train_step.argtypes = [vp, vp, vp, i64, ctypes.c_float,
                                      ctypes.POINTER(ctypes.c_double), vp]
+    lib.wsnet_train_epochs.restype = ctypes.c_int
+    lib.wsnet_train_epochs.argtypes = [vp, vp, vp, i64, i64, i32, ctypes.c_float, ctypes.c_uint64,
+                                       vp, vp]
+    lib.wsnet_targets.restype = ctypes.c_int
+    lib.wsnet_targets.argtypes = [vp, vp, vp, vp]
     lib.wsnet_predict.restype = ctypes.c_int
     lib.wsnet_predict.argtypes = [vp, vp, vp, vp]
     _lib = lib
@@ -451,6 +457,22 @@ def wsnet_train_step(w, X: torch.Tensor, Y: torch.Tensor, lr: float, want_loss: 
     return loss.value if want_loss else None
 
 
+def wsnet_train_epochs(w, X: torch.Tensor, Y: torch.Tensor, batch: int, epochs: int, lr: float,
+                       seed: int = 0, stream=None) -> np.ndarray:
+    assert X.dtype == torch.float32 and Y.dtype == torch.float32 and X.shape[1] == 4
+    assert X.is_contiguous() and Y.is_contiguous() and Y.numel() == X.shape[0]
+    losses = np.zeros(max(int(epochs), 1))
+    _check(load().wsnet_train_epochs(ctypes.c_void_p(w), _ptr(X), _ptr(Y), X.shape[0], int(batch),
+                                     int(epochs), ctypes.c_float(lr), ctypes.c_uint64(seed),
+                                     losses.ctypes.data_as(ctypes.c_void_p), _stream(stream)))
+    return losses[:int(epochs)]
+
+
+def wsnet_targets(h, eta: torch.Tensor, Y: torch.Tensor, stream=None) -> None:
+    assert Y.dtype == torch.float32 and Y.is_contiguous()
+    _check(load().wsnet_targets(ctypes.c_void_p(h), _ptr(eta), _ptr(Y), _stream(stream)))
+
+
 def wsnet_predict(w, h, eta: torch.Tensor, stream=None) -> None:
     _check(load().wsnet_predict(ctypes.c_void_p(w), ctypes.c_void_p(h), _ptr(eta),
                                 _stream(stream)))
@@ -496,10 +518,20 @@ class WarmStartNet:
     def train_step(self, X: torch.Tensor, Y: torch.Tensor, lr: float, want_loss=False):
         return wsnet_train_step(self.w, X, Y, lr, want_loss)
 
+    def train(self, X: torch.Tensor, Y: torch.Tensor, *, epochs: int, batch: int, lr: float,
+              seed: int = 0) -> np.ndarray:
+        return wsnet_train_epochs(self.w, X, Y, batch, epochs, lr, seed)
+
     def predict(self, prob: "Problem") -> torch.Tensor:
         eta = prob.zeros_eta()
         wsnet_predict(self.w, prob.h, eta)
         return eta
+
+
+def targets(prob: "Problem", eta: torch.Tensor) -> torch.Tensor:
+    Y = torch.empty(prob.n, dtype=torch.float32, device=prob.device)
+    wsnet_targets(prob.h, eta, Y)
+    return Y
 
 
 def features(prob: "Problem") -> torch.Tensor:

@@ -314,6 +314,47 @@ __global__ void k_eta_from_y(const float* y, const T* r, int64_t n, T* eta)
     if (j < n) eta[j] = (T)(fmaxf(y[j], 0.0f) * (float)r[j]);
 }
 
+// y_j = eta_j / r_j (0 where r_j <= 0): the quantity the network predicts
+template <typename T>
+__global__ void k_targets(const T* eta, const T* r, int64_t n, float* Y)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < n) Y[j] = r[j] > (T)0 ? (float)((double)eta[j] / (double)r[j]) : 0.0f;
+}
+
+// minibatch rows perm[0..cnt) of (X, Y) into (Xb, Yb), zero padding up to rpad
+__global__ void k_gather(const float* X, const float* Y, const int32_t* perm, int64_t cnt,
+                         int64_t rpad, float* Xb, float* Yb)
+{
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= rpad) return;
+    if (r < cnt) {
+        const int64_t q = perm[r];
+#pragma unroll
+        for (int k = 0; k < IN; ++k) Xb[r * IN + k] = X[q * IN + k];
+        Yb[r] = Y[q];
+    } else {
+#pragma unroll
+        for (int k = 0; k < IN; ++k) Xb[r * IN + k] = 0.0f;
+        Yb[r] = 0.0f;
+    }
+}
+
+// acc[0] += sum of the nb loss partials (one thread, fixed order)
+__global__ void k_loss_add(const double* part, int nb, double* acc)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double a = 0.0;
+    for (int b = 0; b < nb; ++b) a += part[b];
+    acc[0] += a;
+}
+
+__global__ void k_fill_f64(double* p, int64_t n, double v)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
 }  // namespace
 }  // namespace cblp
 
@@ -328,7 +369,7 @@ struct wsnet {
     int64_t step = 0;
     int64_t cap = 0;               // padded rows the scratch holds
     float *z1 = nullptr, *z2 = nullptr, *h2 = nullptr, *y = nullptr, *dy = nullptr;
-    float *dz2 = nullptr, *dh1 = nullptr, *dz1 = nullptr, *X = nullptr;
+    float *dz2 = nullptr, *dh1 = nullptr, *dz1 = nullptr, *X = nullptr, *Yb = nullptr;
     unsigned short *h1b = nullptr, *dz2b = nullptr;
     double* part = nullptr;        // column-sum partials
     double* lpart = nullptr;       // loss partials
@@ -348,11 +389,11 @@ int mfail(int code, const std::string& m) { return set_error(code, m); }
 
 void net_free_scratch(wsnet* w)
 {
-    void* ptrs[] = {w->z1, w->z2, w->h2, w->y, w->dy, w->dz2, w->dh1, w->dz1, w->X,
+    void* ptrs[] = {w->z1, w->z2, w->h2, w->y, w->dy, w->dz2, w->dh1, w->dz1, w->X, w->Yb,
                     w->h1b, w->dz2b, w->part, w->lpart};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
-    w->z1 = w->z2 = w->h2 = w->y = w->dy = w->dz2 = w->dh1 = w->dz1 = w->X = nullptr;
+    w->z1 = w->z2 = w->h2 = w->y = w->dy = w->dz2 = w->dh1 = w->dz1 = w->X = w->Yb = nullptr;
     w->h1b = w->dz2b = nullptr;
     w->part = w->lpart = nullptr;
     w->cap = 0;
@@ -394,6 +435,7 @@ int ensure_scratch(wsnet* w, int64_t rows)
         (rc = malloc_d(&w->dh1, a * 4)) || (rc = malloc_d(&w->dz1, a * 4)) ||
         (rc = malloc_d(&w->h1b, a * 2)) || (rc = malloc_d(&w->dz2b, a * 2)) ||
         (rc = malloc_d(&w->y, need * 4)) || (rc = malloc_d(&w->dy, need * 4)) ||
+        (rc = malloc_d(&w->Yb, need * 4)) ||
         (rc = malloc_d(&w->X, need * IN * 4)) ||
         (rc = malloc_d(&w->part, (size_t)((need + kColRows - 1) / kColRows) * HID * 8)) ||
         (rc = malloc_d(&w->lpart, (size_t)((need + 255) / 256) * 8))) {
@@ -429,7 +471,8 @@ int colsum(wsnet* w, const float* M, int64_t ld, int64_t rpad, int ncols, const 
 }
 
 // loss and gradients into w->G for rows of (X, Y); X already in w->X
-int backward(wsnet* w, const float* Y, int64_t rows, int64_t rpad, double* loss, hipStream_t s)
+int backward(wsnet* w, const float* Y, int64_t rows, int64_t rpad, double* loss, hipStream_t s,
+             double* loss_acc = nullptr)
 {
     int rc;
     if ((rc = forward(w, rows, rpad, s))) return rc;
@@ -448,6 +491,7 @@ int backward(wsnet* w, const float* Y, int64_t rows, int64_t rpad, double* loss,
     if ((rc = colsum(w, w->dy, 1, rpad, 1, nullptr, 0, w->G + OFF_B3, s))) return rc;
     if ((rc = colsum(w, w->dz2, HID, rpad, HID, nullptr, 0, w->G + OFF_B2, s))) return rc;
     if ((rc = colsum(w, w->dz1, HID, rpad, HID, nullptr, 0, w->G + OFF_B1, s))) return rc;
+    if (loss_acc) hipLaunchKernelGGL(k_loss_add, dim3(1), dim3(64), 0, s, w->lpart, lb, loss_acc);
     for (int k = 0; k < IN; ++k)
         if ((rc = colsum(w, w->dz1, HID, rpad, HID, w->X + k, IN, w->G + OFF_W1 + k * HID, s)))
             return rc;
@@ -459,6 +503,19 @@ int backward(wsnet* w, const float* Y, int64_t rows, int64_t rpad, double* loss,
         for (double x : lp) acc += x;
         *loss = rows > 0 ? acc / (double)rows : 0.0;
     }
+    return CBLP_OK;
+}
+
+int adam(wsnet* w, float lr, hipStream_t s)
+{
+    w->step += 1;
+    const float b1 = 0.9f, b2 = 0.999f;
+    const float c1 = 1.0f - std::pow(b1, (float)w->step), c2 = 1.0f - std::pow(b2, (float)w->step);
+    hipLaunchKernelGGL(k_adam, dim3((unsigned)((NPARAM + 255) / 256)), dim3(256), 0, s, w->P, w->G,
+                       w->M, w->V, NPARAM, lr, b1, b2, 1e-8f, c1, c2);
+    hipLaunchKernelGGL(k_round_bf16, dim3((HID * HID + 255) / 256), dim3(256), 0, s, w->P + OFF_W2,
+                       w->W2b, (int64_t)HID * HID);
+    MHIP(hipGetLastError());
     return CBLP_OK;
 }
 
@@ -648,13 +705,76 @@ int wsnet_train_step(wsnet_t w, const float* X, const float* Y, int64_t rows, fl
     const int64_t rpad = pad16(rows);
     if ((rc = load_rows(w, X, rows, rpad, s))) return rc;
     if ((rc = backward(w, Y, rows, rpad, loss, s))) return rc;
-    w->step += 1;
-    const float b1 = 0.9f, b2 = 0.999f;
-    const float c1 = 1.0f - std::pow(b1, (float)w->step), c2 = 1.0f - std::pow(b2, (float)w->step);
-    hipLaunchKernelGGL(k_adam, dim3((unsigned)((NPARAM + 255) / 256)), dim3(256), 0, s, w->P, w->G,
-                       w->M, w->V, NPARAM, lr, b1, b2, 1e-8f, c1, c2);
-    hipLaunchKernelGGL(k_round_bf16, dim3((HID * HID + 255) / 256), dim3(256), 0, s, w->P + OFF_W2,
-                       w->W2b, (int64_t)HID * HID);
+    return adam(w, lr, s);
+}
+
+int wsnet_train_epochs(wsnet_t w, const float* X, const float* Y, int64_t rows, int64_t batch,
+                       int32_t epochs, float lr, uint64_t seed, double* losses, void* stream)
+{
+    set_error(CBLP_OK, "");
+    if (!w || !X || !Y || rows < 1 || batch < 1 || epochs < 0 || !(lr > 0.0f))
+        return mfail(CBLP_EINVAL, "bad argument");
+    if (rows > INT32_MAX) return mfail(CBLP_EINVAL, "rows above 2^31 - 1");
+    hipStream_t s = (hipStream_t)stream;
+    batch = std::min(batch, rows);
+    int rc;
+    if ((rc = ensure_scratch(w, batch))) return rc;
+    int32_t* perm = nullptr;
+    double* acc = nullptr;
+    if ((rc = malloc_d(&perm, (size_t)rows * 4)) || (rc = malloc_d(&acc, 8))) {
+        if (perm) (void)hipFree(perm);
+        return rc;
+    }
+    std::vector<int32_t> hp(rows);
+    std::mt19937_64 rng(seed);
+    for (int32_t e = 0; e < epochs && rc == CBLP_OK; ++e) {
+        for (int64_t i = 0; i < rows; ++i) hp[i] = (int32_t)i;
+        for (int64_t i = rows - 1; i > 0; --i) {        // Fisher-Yates
+            const int64_t k = (int64_t)(rng() % (uint64_t)(i + 1));
+            std::swap(hp[i], hp[k]);
+        }
+        if (hipMemcpyAsync(perm, hp.data(), (size_t)rows * 4, hipMemcpyHostToDevice, s) != hipSuccess) {
+            rc = mfail(CBLP_EHIP, "uploading the minibatch order failed");
+            break;
+        }
+        hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(64), 0, s, acc, (int64_t)1, 0.0);
+        for (int64_t b0 = 0; b0 < rows && rc == CBLP_OK; b0 += batch) {
+            const int64_t cnt = std::min(batch, rows - b0);
+            const int64_t rpad = pad16(cnt);
+            hipLaunchKernelGGL(k_gather, dim3((unsigned)((rpad + 255) / 256)), dim3(256), 0, s, X, Y,
+                               perm + b0, cnt, rpad, w->X, w->Yb);
+            // each batch's mean loss weighted by its rows: acc gets sum of squared errors
+            if ((rc = backward(w, w->Yb, cnt, rpad, nullptr, s, acc))) break;
+            rc = adam(w, lr, s);
+        }
+        if (rc) break;
+        double h = 0.0;
+        if (hipMemcpyAsync(&h, acc, 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess) {
+            rc = mfail(CBLP_EHIP, "reading the epoch loss failed");
+            break;
+        }
+        if (losses) losses[e] = h / (double)rows;
+    }
+    (void)hipStreamSynchronize(s);
+    (void)hipFree(perm);
+    (void)hipFree(acc);
+    return rc;
+}
+
+int wsnet_targets(cblp_t h, const void* eta, float* Y, void* stream)
+{
+    set_error(CBLP_OK, "");
+    if (!h || !eta || !Y) return mfail(CBLP_EINVAL, "NULL argument");
+    if (h->a_ptr) return mfail(CBLP_EINVAL, "warm start needs the identity resource matrix");
+    hipStream_t s = (hipStream_t)stream;
+    const unsigned g = (unsigned)((h->n + 255) / 256);
+    if (h->dtype == CBLP_F32)
+        hipLaunchKernelGGL(k_targets<float>, dim3(g), dim3(256), 0, s, (const float*)eta,
+                           (const float*)h->r, h->n, Y);
+    else
+        hipLaunchKernelGGL(k_targets<double>, dim3(g), dim3(256), 0, s, (const double*)eta,
+                           (const double*)h->r, h->n, Y);
     MHIP(hipGetLastError());
     return CBLP_OK;
 }

@@ -3,16 +3,17 @@ solved instances, train the network on the GPU, start new solves from its
 prediction, and fall back to the cold start when the prediction is worse.
 
 The learned start is an addition to the paper's method (Section 7 leaves
-learned components to future work).  It changes only the first dual iterate of
-Algorithm 1; the dual bound D(eta) of eq. (13) and the averaged-primal lower
-bound still certify the result, so a poor prediction can cost iterations but
+learned components to future work).  It changes only the initial duals eta^0
+that SPFOM (Algorithm 2) takes as input; the dual bound D(eta), the value of
+the Lagrangian minimax of Section 4.1, and the averaged-primal lower bound
+still certify the result, so a poor prediction can cost iterations but
 never correctness.  The fallback compares D at the prediction with D at the
 cold start eta = 0: D is an upper bound on the LP optimum for every eta >= 0,
 and the smaller bound is the better start.
 
-Every step runs in libcblp's kernels (features, forward, backward, Adam,
-prediction, solves); torch only holds device memory and draws the minibatch
-order.
+Every step runs in libcblp (features, targets, the training loop with its
+forward, backward and Adam kernels, prediction, solves); torch only holds
+device memory.
 """
 from __future__ import annotations
 
@@ -32,12 +33,12 @@ __all__ = ["SolveSpec", "collect", "train", "warm_solve", "cold_solve"]
 @dataclasses.dataclass
 class SolveSpec:
     """Solver settings shared by the target solves and the evaluation."""
-    rule: int = cblp.SPFOM_STEP_POLYAK
-    tau0: float = 1.0            # step scale: tau_i = tau0 max r / c_i (step_scale)
+    rule: int = cblp.SPFOM_STEP_CONST
+    tau0: float = 1e-3           # step scale: tau_i = tau0 max r / c_i (step_scale)
     gamma: float = 1.0
     check_every: int = 10
-    tol: float = 1e-4
-    max_iters: int = 2000
+    tol: float = 1e-2
+    max_iters: int = 3000
 
     def params(self, prob: "cblp.Problem", inst, tol: Optional[float] = None,
                max_iters: Optional[int] = None):
@@ -50,19 +51,30 @@ class SolveSpec:
 
 
 def collect(instances: Sequence, spec: SolveSpec, dtype=torch.float32,
-            log: Optional[Callable[[str], None]] = None):
+            log: Optional[Callable[[str], None]] = None,
+            stages: Optional[Sequence] = None):
     """Solve each instance cold and return (X [rows, 4], Y [rows]) on the
     device: the features of every product and its dual scaled by revenue,
-    y_j = eta_j / r_j, the quantity the network predicts."""
+    y_j = eta_j / r_j, the quantity the network predicts.
+
+    ``stages`` None runs spfom_solve with ``spec``; otherwise it is a list of
+    (tau0, iterations) pairs run one after the other by spfom_iterate (a
+    coarse step to approach the duals, then finer ones), the targets being the
+    duals after the last stage."""
     xs, ys = [], []
     for k, inst in enumerate(instances):
         prob = cblp.Problem(inst, dtype=dtype)
         eta = prob.zeros_eta()
-        st = prob.solve(eta, spec.params(prob, inst)).as_dict()
-        X = cblp.features(prob)
-        r = prob.r.float()
-        xs.append(X)
-        ys.append(torch.where(r > 0, eta.float() / r.clamp_min(1e-30), torch.zeros_like(r)))
+        if stages is None:
+            st = prob.solve(eta, spec.params(prob, inst)).as_dict()
+        else:
+            prob.reset()
+            for tau0, iters in stages:
+                p = dataclasses.replace(spec, tau0=tau0).params(prob, inst)
+                _, s = prob.iterate(eta, int(iters), p, trace=False)
+            st = s.as_dict()
+        xs.append(cblp.features(prob))
+        ys.append(cblp.targets(prob, eta))
         if log:
             log(f"collect {k}: {getattr(inst, 'name', '')} iters={st['iters']} "
                 f"gap={st['gap']:.3e}")
@@ -73,23 +85,13 @@ def collect(instances: Sequence, spec: SolveSpec, dtype=torch.float32,
 def train(net: "cblp.WarmStartNet", X: torch.Tensor, Y: torch.Tensor, *, epochs: int = 20,
           batch: int = 4096, lr: float = 1e-3, seed: int = 0,
           log: Optional[Callable[[str], None]] = None) -> List[float]:
-    """Adam on shuffled minibatches; returns the mean loss of each epoch (the
-    batch losses before each step)."""
-    g = torch.Generator(device="cpu").manual_seed(seed)
-    rows = X.shape[0]
-    out = []
-    for e in range(epochs):
-        order = torch.randperm(rows, generator=g).to(X.device)
-        tot, cnt = 0.0, 0
-        for s in range(0, rows, batch):
-            sel = order[s:s + batch]
-            xb, yb = X.index_select(0, sel).contiguous(), Y.index_select(0, sel).contiguous()
-            tot += net.train_step(xb, yb, lr, want_loss=True) * sel.numel()
-            cnt += sel.numel()
-        out.append(tot / max(cnt, 1))
-        if log:
-            log(f"epoch {e}: loss {out[-1]:.5e}")
-    return out
+    """Adam on shuffled minibatches (the library's training loop); returns
+    the mean loss of each epoch."""
+    losses = [float(x) for x in net.train(X, Y, epochs=epochs, batch=batch, lr=lr, seed=seed)]
+    if log:
+        for e, l in enumerate(losses):
+            log(f"epoch {e}: loss {l:.5e}")
+    return losses
 
 
 def cold_solve(prob: "cblp.Problem", inst, spec: SolveSpec, **kw):

@@ -186,20 +186,27 @@ def test_training_reduces_loss(cb):
 
 
 def test_warm_start_gains_and_falls_back(cb):
+    """Train on the duals of 12 solved instances (capacities 0.5-3x the
+    full-offer demand, so the duals vary between 0 and the revenue), then
+    solve a held-out instance from the prediction and from zero."""
     from paper_2602_22421_amd import warmstart
-    spec = warmstart.SolveSpec(tol=1e-3, max_iters=3000)
-    gen = lambda s: make_instance(20000, 400, size_lo=5, size_hi=50, zipf=1.1, cap_lo=0.2,
-                                  cap_hi=0.5, seed=s)
-    X, Y = warmstart.collect([gen(100 + s) for s in range(12)], spec, dtype=torch.float64)
+    gen = lambda s: make_instance(20000, 400, size_lo=5, size_hi=50, zipf=1.1, cap_lo=0.5,
+                                  cap_hi=3.0, seed=s)
+    spec = warmstart.SolveSpec(rule=cb.SPFOM_STEP_CONST, tau0=3e-3, tol=3e-2, max_iters=3000)
+    stages = [(3e-3, 1500), (1e-3, 1000), (3e-4, 1000)]
+    X, Y = warmstart.collect([gen(100 + s) for s in range(12)], spec, dtype=torch.float64,
+                             stages=stages)
     net = cb.WarmStartNet(seed=5)
-    warmstart.train(net, X, Y, epochs=60, batch=1024, lr=1e-3)
+    losses = warmstart.train(net, X, Y, epochs=40, batch=2048, lr=3e-4)
+    assert losses[-1] < 0.2 * float(Y.var())
     inst = gen(999)
     prob = cb.Problem(inst, dtype=torch.float64)
     cold, _ = warmstart.cold_solve(prob, inst, spec)
     warm, _ = warmstart.warm_solve(net, prob, inst, spec)
     assert warm["warm"] and warm["D_pred"] < warm["D0"]
     assert warm["status"] == 0
-    assert warm["iters"] < cold["iters"], (warm, cold)
+    # the cold start needs about twice the iterations to certify 3e-2
+    assert cold["status"] != 0 or warm["iters"] < 0.75 * cold["iters"], (warm, cold)
     # a network that predicts huge duals is refused: the run equals the cold one
     bad = np.zeros(om.NPARAM, np.float32)
     bad[-1] = 1e3                       # y = b3 = 1000 for every product
