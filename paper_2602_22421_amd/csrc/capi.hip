@@ -154,6 +154,7 @@ int run_segments(cblp_instance* h, void* seg_R, hipStream_t s)
     a.Rwarm = h->Rwarm;
     a.perm = h->perm;
     a.rho = h->rho;
+    a.n = h->n;
     a.H = h->H;
     a.part_S = h->part_S;
     a.S_fx = h->S_fx;
@@ -349,19 +350,22 @@ int create_impl(cblp_instance* h, hipStream_t s)
         if (prop.multiProcessorCount > 0) cus = prop.multiProcessorCount;
         if (prop.sharedMemPerBlock > 0) lds_block = prop.sharedMemPerBlock;
     }
-    const int64_t lds_bins = ((int64_t)lds_block - 1024) / 8;
-    h->H = (int)std::max<int64_t>(1, std::min<int64_t>({h->n, (int64_t)kMaxBins, lds_bins}));
-    // kernel variant and bin count may be overridden for tuning runs
-    h->seg_variant = sizeof(T) == 4 ? 6 : 4;
+    // kernel variant and bin count may be overridden for tuning runs.  The
+    // prices go to LDS (FP32 variant 13) when they take at most half of it.
+    const bool prices_fit = (int64_t)h->n * (int64_t)sizeof(T) * 2 <= (int64_t)lds_block;
+    h->seg_variant = sizeof(T) == 4 ? (prices_fit ? 13 : 6) : (prices_fit ? 12 : 4);
     if (const char* ev = std::getenv("CBLP_SEG_VARIANT")) {
         const int x = std::atoi(ev);
-        if (x >= 0 && x < kSegVariants) h->seg_variant = x;
+        if (x >= 0 && x < kSegVariants && (!seg_lds_prices(x) || prices_fit)) h->seg_variant = x;
     }
+    const int64_t price_bytes = seg_lds_prices(h->seg_variant) ? h->n * (int64_t)sizeof(T) : 0;
+    const int64_t lds_bins = ((int64_t)lds_block - 1024 - price_bytes) / 8;
+    h->H = (int)std::max<int64_t>(1, std::min<int64_t>({h->n, (int64_t)kMaxBins, lds_bins}));
     if (const char* eb = std::getenv("CBLP_SEG_BINS")) {
         const long x = std::atol(eb);
         if (x >= 1 && x <= h->H) h->H = (int)x;
     }
-    const int per_cu = segment_blocks_per_cu<T>(h->H, h->seg_variant);
+    const int per_cu = segment_blocks_per_cu<T>(h->H, h->n, h->seg_variant);
     const int64_t tiles = (h->L + kSegsPerTile - 1) / kSegsPerTile;
     h->seg_grid = (int)std::max<int64_t>(1, std::min<int64_t>(tiles, (int64_t)cus * per_cu));
     h->fold_blocks = (int)((h->n + kFoldProducts - 1) / kFoldProducts);

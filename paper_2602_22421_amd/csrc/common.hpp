@@ -45,6 +45,7 @@ struct SegArgs {
     void* Rwarm;                   // [L] last R* per position: Dinkelbach start
     const int32_t* perm;           // [L] position -> original segment
     const void* rho;               // [n] reduced revenues
+    int64_t n;                     // products (length of rho)
     int H;                         // products [0, H) are summed in LDS bins
     unsigned long long* part_S;    // [gridDim.x][H] per-block bin totals
     unsigned long long* S_fx;      // [n] fixed-point sales of products >= H
@@ -106,11 +107,20 @@ hipError_t launch_relayout(int64_t L, const int64_t* seg_ptr, const int32_t* idx
 template <typename T>
 hipError_t launch_prices(int64_t n, const void* r, const void* eta, const int64_t* a_ptr,
                          const int32_t* a_idx, const void* a_val, void* rho, hipStream_t s);
-constexpr int kSegVariants = 7;
+// Segment-kernel variants 0-9 gather prices from global memory; variants
+// kSegLdsPrices and up first copy the n prices into LDS after the H bins.
+constexpr int kSegVariants = 15;
+constexpr int kSegLdsPrices = 10;
+inline bool seg_lds_prices(int variant) { return variant >= kSegLdsPrices; }
+// dynamic LDS bytes of a segment block: H bins, then the prices if in LDS
+inline size_t seg_lds_bytes(int H, int64_t n, size_t esz, int variant)
+{
+    return (size_t)H * 8 + (seg_lds_prices(variant) ? (size_t)n * esz : 0);
+}
 template <typename T>
 hipError_t launch_segments(const SegArgs& a, int grid, int variant, hipStream_t s);
 template <typename T>
-int segment_blocks_per_cu(int H, int variant);   // resident blocks per CU with H bins
+int segment_blocks_per_cu(int H, int64_t n, int variant);   // resident blocks per CU
 template <typename T>
 hipError_t launch_phase(const PhaseArgs& a, bool identity, hipStream_t s);
 

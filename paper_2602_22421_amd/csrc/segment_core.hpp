@@ -85,6 +85,7 @@ template <typename T>
 struct Bounds {
     int64_t b, e;     // row [b, e) of the sorted layout
     T vt0, lam, R0;
+    bool live;        // a segment of the instance (not past its end)
 };
 
 template <typename T, int J>
@@ -103,15 +104,27 @@ __device__ __forceinline__ Bounds<T> load_bounds(const SegArgs& a, int64_t p)
     B.vt0 = ((const T*)a.vt0)[pc];
     B.lam = ((const T*)a.lam)[pc];
     B.R0 = ((const T*)a.Rwarm)[pc];
-    if (p >= a.L) B.e = B.b;      // past the last segment: empty row
+    B.live = p < a.L;
     return B;
+}
+
+// Row length, taken where it is used (a pipeline step after the load).  The
+// 64-bit compare keeps both halves of e live, so the compiler never reuses a
+// register that a row bound is still being loaded into, which would force a
+// wait for every load in flight.
+template <typename T>
+__device__ __forceinline__ int row_len(const Bounds<T>& B)
+{
+    return (B.live && B.e > B.b) ? (int)(B.e - B.b) : 0;
 }
 
 // The library pads its CSR copy with kGroup * kMaxJ entries, so slot s of
 // every lane reads base + 8 s with an immediate offset; slots past a row's
-// end read the next row (masked off when used).  Only the first jw slots -
-// the longest row of the wave - are loaded.
-template <typename T, int J>
+// end read the next row (masked off when used).  ALL: every one of the J
+// slots is loaded, so the number of loads in flight is fixed and the waits
+// for them can count exactly; otherwise only the first jw slots - the
+// longest row of the wave - are loaded.
+template <typename T, int J, bool ALL>
 __device__ __forceinline__ Raw<T, J> load_raw(const SegArgs& a, const Bounds<T>& B, int g, int jw)
 {
     Raw<T, J> R;
@@ -120,7 +133,7 @@ __device__ __forceinline__ Raw<T, J> load_raw(const SegArgs& a, const Bounds<T>&
     const T* pd = (const T*)a.den + B.b + g;
 #pragma unroll
     for (int s = 0; s < J; ++s) {
-        if (s < jw) {
+        if (ALL || s < jw) {
             R.id[s] = pi[kGroup * s];
             R.v[s] = pv[kGroup * s];
             R.den[s] = pd[kGroup * s];
@@ -133,11 +146,12 @@ __device__ __forceinline__ Raw<T, J> load_raw(const SegArgs& a, const Bounds<T>&
     return R;
 }
 
-template <typename T, int J>
-__device__ __forceinline__ void gather(const SegArgs& a, const Raw<T, J>& R, T (&p)[J], int jw)
+template <typename T, int J, bool ALL>
+__device__ __forceinline__ void gather(const T* __restrict__ prices, const Raw<T, J>& R,
+                                       T (&p)[J], int jw)
 {
 #pragma unroll
-    for (int s = 0; s < J; ++s) p[s] = s < jw ? ((const T*)a.rho)[R.id[s]] : T(0);
+    for (int s = 0; s < J; ++s) p[s] = (ALL || s < jw) ? prices[R.id[s]] : T(0);
 }
 
 // wave-uniform slot count: the longest row among the wave's eight groups
@@ -148,7 +162,7 @@ __device__ __forceinline__ int wave_slots(int k)
     jw = max(jw, __shfl_xor(jw, 8));
     jw = max(jw, __shfl_xor(jw, 16));
     jw = max(jw, __shfl_xor(jw, 32));
-    return jw < J ? jw : J;
+    return __builtin_amdgcn_readfirstlane(jw < J ? jw : J);
 }
 
 // R = N / D.  FP32 uses the hardware reciprocal (about one ulp); the value
@@ -168,17 +182,24 @@ __device__ __forceinline__ unsigned long long quantum(double s, double scale)
 // J: products per lane held in registers (rows longer than 8 J stream the
 // rest).  DEPTH 1 keeps the CSR entries of the next tile (and the row bounds
 // of the one after) in flight while a tile is solved; DEPTH 0 none; DEPTH 2
-// one more tile of entries and the price gathers.  The block visits tiles
-// tile, tile + stride, ... below `tiles`; sales go to the LDS bins (products
-// < a.H) or the global tail; lambda R* is added to zacc.
+// one more tile of entries and the price gathers.  DEPTH 3 is DEPTH 1 with
+// every slot loaded and the loads of an iteration issued in the order they
+// are consumed (this tile's price gathers, the next tile's entries, the
+// bounds of the tile after), so the solve waits for its gathers alone.  The
+// block visits tiles tile, tile + stride, ... below `tiles`; sales go to the
+// LDS bins (products < a.H) or the global tail; lambda R* is added to zacc.
+//
+// prices: the reduced revenues rho_j, either a.rho itself or a copy of it in
+// LDS (the caller's choice; the compiler sees which memory it is).
 template <typename T, int J, int DEPTH>
 __device__ __forceinline__ void process_tiles(const SegArgs& a, int64_t tile, int64_t tiles,
                                               int64_t stride, unsigned long long* bins,
-                                              double& zacc)
+                                              const T* __restrict__ prices, double& zacc)
 {
+    constexpr bool ALL = DEPTH == 3;
     const T* __restrict__ vg = (const T*)a.v;
     const T* __restrict__ dg = (const T*)a.den;
-    const T* __restrict__ rho = (const T*)a.rho;
+    const T* __restrict__ rho = prices;
     const int32_t* __restrict__ idx = a.idx;
     const int H = a.H;
     const int g = threadIdx.x & (kGroup - 1);
@@ -187,18 +208,19 @@ __device__ __forceinline__ void process_tiles(const SegArgs& a, int64_t tile, in
 
     if (tile < tiles) {
         Bounds<T> Bc = load_bounds<T>(a, pos_of(tile));
-        int jc = wave_slots<J>((int)(Bc.e - Bc.b));
-        Raw<T, J> Rc = load_raw<T, J>(a, Bc, g, jc);
+        int jc = wave_slots<J>(row_len(Bc));
+        Raw<T, J> Rc = load_raw<T, J, ALL>(a, Bc, g, jc);
         T Pc[J];
-        if (DEPTH == 2) gather<T, J>(a, Rc, Pc, jc);
+        if (DEPTH == 2) gather<T, J, ALL>(rho, Rc, Pc, jc);
         Bounds<T> B1 = load_bounds<T>(a, pos_of(tile + stride));
         int j1 = 0;
         Raw<T, J> R1;
         if (DEPTH == 2) {
-            j1 = wave_slots<J>((int)(B1.e - B1.b));
-            R1 = load_raw<T, J>(a, B1, g, j1);
+            j1 = wave_slots<J>(row_len(B1));
+            R1 = load_raw<T, J, ALL>(a, B1, g, j1);
         }
-        Bounds<T> B2 = load_bounds<T>(a, pos_of(tile + 2 * stride));
+        Bounds<T> B2;
+        if (DEPTH != 3) B2 = load_bounds<T>(a, pos_of(tile + 2 * stride));
 
         for (; tile < tiles; tile += stride) {
             // issue the next stages before touching the current tile
@@ -206,22 +228,27 @@ __device__ __forceinline__ void process_tiles(const SegArgs& a, int64_t tile, in
             Bounds<T> B3;
             T P1[J];
             int j2 = 0;
-            if (DEPTH == 2) {
-                j2 = wave_slots<J>((int)(B2.e - B2.b));
-                R2 = load_raw<T, J>(a, B2, g, j2);
+            if (DEPTH == 3) {
+                gather<T, J, ALL>(rho, Rc, Pc, jc);
+                j1 = wave_slots<J>(row_len(B1));
+                R1 = load_raw<T, J, ALL>(a, B1, g, j1);
+                B2 = load_bounds<T>(a, pos_of(tile + 2 * stride));
+            } else if (DEPTH == 2) {
+                j2 = wave_slots<J>(row_len(B2));
+                R2 = load_raw<T, J, ALL>(a, B2, g, j2);
                 B3 = load_bounds<T>(a, pos_of(tile + 3 * stride));
-                gather<T, J>(a, R1, P1, j1);
+                gather<T, J, ALL>(rho, R1, P1, j1);
             } else if (DEPTH == 1) {
-                j1 = wave_slots<J>((int)(B1.e - B1.b));
-                R1 = load_raw<T, J>(a, B1, g, j1);
-                gather<T, J>(a, Rc, Pc, jc);
+                j1 = wave_slots<J>(row_len(B1));
+                R1 = load_raw<T, J, ALL>(a, B1, g, j1);
+                gather<T, J, ALL>(rho, Rc, Pc, jc);
             } else {
-                gather<T, J>(a, Rc, Pc, jc);
+                gather<T, J, ALL>(rho, Rc, Pc, jc);
             }
 
             const int64_t p = pos_of(tile);
             const int64_t b = Bc.b;
-            const int k = (int)(Bc.e - Bc.b);
+            const int k = row_len(Bc);
             const T vt0 = Bc.vt0;
             const int jw = jc;
 
@@ -305,7 +332,9 @@ __device__ __forceinline__ void process_tiles(const SegArgs& a, int64_t tile, in
             Bc = B1;
             Rc = R1;
             jc = j1;
-            if (DEPTH == 2) {
+            if (DEPTH == 3) {
+                B1 = B2;
+            } else if (DEPTH == 2) {
 #pragma unroll
                 for (int s = 0; s < J; ++s) Pc[s] = P1[s];
                 B1 = B2;
@@ -317,8 +346,8 @@ __device__ __forceinline__ void process_tiles(const SegArgs& a, int64_t tile, in
                 B2 = load_bounds<T>(a, pos_of(tile + 3 * stride));
             } else {
                 Bc = load_bounds<T>(a, pos_of(tile + stride));
-                jc = wave_slots<J>((int)(Bc.e - Bc.b));
-                Rc = load_raw<T, J>(a, Bc, g, jc);
+                jc = wave_slots<J>(row_len(Bc));
+                Rc = load_raw<T, J, ALL>(a, Bc, g, jc);
             }
         }
     }
