@@ -79,6 +79,7 @@ void release(cblp_instance* h)
 {
     if (!h) return;
     void* ptrs[] = {h->ptr2, h->idx2, h->v2, h->den2, h->vt0, h->lam2, h->Rwarm, h->v0c, h->perm,
+                    h->seg_blk,
                     h->rho, h->S_fx, h->part_S, h->S_d, h->u_d, h->sum_u, h->zpart,
                     h->bpart, h->bpart2, h->st, h->trace, h->at_ptr,
                     h->at_prod, h->at_val};
@@ -161,6 +162,7 @@ int run_segments(cblp_instance* h, void* seg_R, hipStream_t s)
     a.fx_scale = h->fx_scale;
     a.zpart = h->zpart;
     a.seg_R = seg_R;
+    a.blk = h->seg_blk;
     size_t slot;
     int rc = timed_begin(h, 0, s, &slot);
     if (rc) return rc;
@@ -351,7 +353,7 @@ int create_impl(cblp_instance* h, hipStream_t s)
         if (prop.sharedMemPerBlock > 0) lds_block = prop.sharedMemPerBlock;
     }
     // kernel variant and bin count may be overridden for tuning runs.  The
-    // prices go to LDS (FP32 variant 13) when they take at most half of it.
+    // prices go to LDS when they take at most half of it.
     const bool prices_fit = (int64_t)h->n * (int64_t)sizeof(T) * 2 <= (int64_t)lds_block;
     h->seg_variant = sizeof(T) == 4 ? (prices_fit ? 13 : 6) : (prices_fit ? 12 : 4);
     if (const char* ev = std::getenv("CBLP_SEG_VARIANT")) {
@@ -375,11 +377,9 @@ int create_impl(cblp_instance* h, hipStream_t s)
     const int64_t L1 = std::max<int64_t>(h->L, 1);
     if ((rc = dalloc(&h->rho, (size_t)h->n * esz))) return rc;
     if ((rc = dalloc(&h->S_fx, (size_t)h->n * 8))) return rc;
-    if ((rc = dalloc(&h->part_S, (size_t)h->seg_grid * std::max(h->H, 1) * 8))) return rc;
     if ((rc = dalloc(&h->S_d, (size_t)h->n * 8))) return rc;
     if ((rc = dalloc(&h->u_d, (size_t)h->m * 8))) return rc;
     if ((rc = dalloc(&h->sum_u, (size_t)h->m * 8))) return rc;
-    if ((rc = dalloc(&h->zpart, (size_t)h->seg_grid * 8))) return rc;
     if ((rc = dalloc(&h->bpart, (size_t)h->fold_blocks * 8 * 8))) return rc;
     if ((rc = dalloc(&h->bpart2, (size_t)std::max<int64_t>(row_blocks, 1) * 8 * 8))) return rc;
     if ((rc = dalloc(&h->st, 2 * sizeof(DevState)))) return rc;
@@ -402,6 +402,44 @@ int create_impl(cblp_instance* h, hipStream_t s)
         for (int64_t l = 0; l < h->L; ++l) perm[start[sp[l + 1] - sp[l]]++] = (int32_t)l;
         std::vector<int64_t> ptr((size_t)h->L + 1, 0);
         for (int64_t p = 0; p < h->L; ++p) ptr[p + 1] = ptr[p] + (sp[perm[p] + 1] - sp[perm[p]]);
+        if (seg_class(h->seg_variant)) {
+            // runs of tiles with one slot count (rows ascend, so a tile's last
+            // row is its longest); blocks per run in proportion to its entries
+            std::vector<int64_t> blk;
+            const int64_t grid0 = h->seg_grid;
+            // cost of a run: its entries plus alpha per segment
+            double alpha = 8.0;
+            if (const char* ea = std::getenv("CBLP_CLASS_ALPHA")) alpha = std::atof(ea);
+            const double total = (double)h->nnz + alpha * (double)h->L;
+            int64_t t = 0;
+            while (t < tiles) {
+                auto slots = [&](int64_t tt) {
+                    const int64_t last = std::min(h->L, (tt + 1) * kSegsPerTile) - 1;
+                    const int64_t len = ptr[last + 1] - ptr[last];
+                    return std::min<int64_t>(seg_class_max_slots(sizeof(T)),
+                                             std::max<int64_t>(1, (len + kGroup - 1) / kGroup));
+                };
+                const int64_t J = slots(t);
+                int64_t u = t + 1;
+                while (u < tiles && slots(u) == J) ++u;
+                const int64_t e0 = ptr[t * kSegsPerTile];
+                const int64_t e1 = ptr[std::min(h->L, u * kSegsPerTile)];
+                const int64_t s0 = t * kSegsPerTile, s1 = std::min(h->L, u * kSegsPerTile);
+                const double share =
+                    total > 0 ? ((double)(e1 - e0) + alpha * (double)(s1 - s0)) / total : 1.0;
+                const int64_t g = std::max<int64_t>(1, std::min<int64_t>(u - t, std::llround(share * (double)grid0)));
+                for (int64_t i = 0; i < g; ++i) {
+                    blk.push_back(J);
+                    blk.push_back(t + (u - t) * i / g);
+                    blk.push_back(t + (u - t) * (i + 1) / g);
+                }
+                t = u;
+            }
+            if (blk.empty()) blk = {1, 0, 0};
+            h->seg_grid = (int)(blk.size() / 3);
+            if ((rc = dalloc(&h->seg_blk, blk.size() * 8))) return rc;
+            HIP_TRY(hipMemcpyAsync(h->seg_blk, blk.data(), blk.size() * 8, hipMemcpyHostToDevice, s));
+        }
         if ((rc = dalloc(&h->ptr2, (size_t)(h->L + 1) * 8))) return rc;
         if ((rc = dalloc(&h->perm, (size_t)L1 * 4))) return rc;
         // the copy is followed by kPad entries (product 0, v = 0, den = 1)
@@ -429,6 +467,8 @@ int create_impl(cblp_instance* h, hipStream_t s)
                                        h->lam2, h->Rwarm, h->v0c, s));
         HIP_TRY(hipStreamSynchronize(s));   // the host vectors die here
     }
+    if ((rc = dalloc(&h->part_S, (size_t)h->seg_grid * std::max(h->H, 1) * 8))) return rc;
+    if ((rc = dalloc(&h->zpart, (size_t)h->seg_grid * 8))) return rc;
 
     // fixed-point scale of the sales sums from the arrival rates
     const int pblocks = 256;

@@ -52,6 +52,8 @@ struct SegArgs {
     double fx_scale;               // 2^bits; one segment's sale * 2^bits < 2^31 for FP32
     double* zpart;                 // [gridDim.x] FP64 partials of sum lambda R*
     void* seg_R;                   // [L] nullable, original segment order
+    const int64_t* blk;            // [grid][3] (slots J, first tile, end tile) of each
+                                   // block for the size-class kernels, else unused
 };
 
 struct PhaseArgs {
@@ -109,9 +111,18 @@ hipError_t launch_prices(int64_t n, const void* r, const void* eta, const int64_
                          const int32_t* a_idx, const void* a_val, void* rho, hipStream_t s);
 // Segment-kernel variants 0-9 gather prices from global memory; variants
 // kSegLdsPrices and up first copy the n prices into LDS after the H bins.
-constexpr int kSegVariants = 15;
+// Variants kSegClassLds (prices in LDS) and kSegClassGlobal take the slot
+// count of each block from a table: blocks own runs of tiles of one size class.
+constexpr int kSegVariants = 19;
 constexpr int kSegLdsPrices = 10;
-inline bool seg_lds_prices(int variant) { return variant >= kSegLdsPrices; }
+constexpr int kSegClassLds = 17, kSegClassGlobal = 18;
+inline bool seg_class(int variant) { return variant == kSegClassLds || variant == kSegClassGlobal; }
+// most register slots of the size-class kernels per element size
+inline int seg_class_max_slots(size_t esz) { return esz == 4 ? 7 : 4; }
+inline bool seg_lds_prices(int variant)
+{
+    return variant >= kSegLdsPrices && variant != kSegClassGlobal;
+}
 // dynamic LDS bytes of a segment block: H bins, then the prices if in LDS
 inline size_t seg_lds_bytes(int H, int64_t n, size_t esz, int variant)
 {

@@ -29,6 +29,7 @@ struct cblp_instance {
     void* Rwarm = nullptr;
     void* v0c = nullptr;            // v0 per position (features only)
     int32_t* perm = nullptr;
+    int64_t* seg_blk = nullptr;     // [seg_grid][3] size-class block table (class variants)
     // owned workspace
     void* rho = nullptr;
     unsigned long long* S_fx = nullptr;

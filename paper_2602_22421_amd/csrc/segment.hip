@@ -42,6 +42,58 @@ __global__ void __launch_bounds__(kSegThreads) k_segments(SegArgs a)
     }
 }
 
+// Size-class kernel: block b solves tiles [blk[b][1], blk[b][2]) with
+// blk[b][0] register slots per lane.  The layout is sorted by row length, so
+// a run of tiles has one slot count, and loading every slot of it wastes no
+// more than the rounding of the longest row to a multiple of 8.
+template <typename T, bool LDSP>
+__global__ void __launch_bounds__(kSegThreads) k_segments_cls(SegArgs a)
+{
+    extern __shared__ unsigned long long bins[];   // [a.H], then [a.n] prices if LDSP
+    __shared__ double zsh[kSegThreads / 64];
+    const int H = a.H;
+    T* lprice = (T*)(bins + H);
+    for (int j = threadIdx.x; j < H; j += kSegThreads) bins[j] = 0ull;
+    if (LDSP)
+        for (int64_t j = threadIdx.x; j < a.n; j += kSegThreads) lprice[j] = ((const T*)a.rho)[j];
+    __syncthreads();
+
+    double zacc = 0.0;
+    const int64_t* e = a.blk + 3 * (size_t)blockIdx.x;
+    const int J = (int)e[0];
+    const int64_t t0 = e[1], t1 = e[2];
+    const T* pr = LDSP ? (const T*)lprice : (const T*)a.rho;
+    // FP64 holds at most 4 slots in registers, FP32 7 (longer rows stream
+    // the rest from memory in each round)
+    switch (J) {
+    case 1: seg::process_tiles<T, 1, 3>(a, t0, t1, 1, bins, pr, zacc); break;
+    case 2: seg::process_tiles<T, 2, 3>(a, t0, t1, 1, bins, pr, zacc); break;
+    case 3: seg::process_tiles<T, 3, 3>(a, t0, t1, 1, bins, pr, zacc); break;
+    case 4: seg::process_tiles<T, 4, 3>(a, t0, t1, 1, bins, pr, zacc); break;
+    case 5:
+        if (sizeof(T) == 4) seg::process_tiles<T, sizeof(T) == 4 ? 5 : 4, 3>(a, t0, t1, 1, bins, pr, zacc);
+        break;
+    case 6:
+        if (sizeof(T) == 4) seg::process_tiles<T, sizeof(T) == 4 ? 6 : 4, 3>(a, t0, t1, 1, bins, pr, zacc);
+        break;
+    default:
+        if (sizeof(T) == 4) seg::process_tiles<T, sizeof(T) == 4 ? 7 : 4, 3>(a, t0, t1, 1, bins, pr, zacc);
+        break;
+    }
+
+    __syncthreads();
+    unsigned long long* out = a.part_S + (size_t)blockIdx.x * (size_t)H;
+    for (int j = threadIdx.x; j < H; j += kSegThreads) out[j] = bins[j];
+    for (int o = 32; o > 0; o >>= 1) zacc += __shfl_down(zacc, o, 64);
+    if ((threadIdx.x & 63) == 0) zsh[threadIdx.x >> 6] = zacc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double z = zsh[0];
+        for (int q = 1; q < kSegThreads / 64; ++q) z += zsh[q];
+        a.zpart[blockIdx.x] = z;
+    }
+}
+
 }  // namespace
 
 // Segment-kernel variants: (products per lane in registers, pipeline depth).
@@ -68,6 +120,10 @@ const void* SegVariant<T>::fn(int variant)
     case 12: return (const void*)k_segments<T, 4, 1, true>;
     case 13: return (const void*)k_segments<T, 7, 3, true>;
     case 14: return (const void*)k_segments<T, 6, 1, true>;
+    case 15: return (const void*)k_segments<T, 7, 4, true>;
+    case 16: return (const void*)k_segments<T, 8, 4, true>;
+    case kSegClassLds: return (const void*)k_segments_cls<T, true>;
+    case kSegClassGlobal: return (const void*)k_segments_cls<T, false>;
     default: return (const void*)k_segments<T, 4, 1, false>;
     }
 }

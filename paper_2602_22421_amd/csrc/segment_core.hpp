@@ -154,7 +154,8 @@ __device__ __forceinline__ void gather(const T* __restrict__ prices, const Raw<T
     for (int s = 0; s < J; ++s) p[s] = (ALL || s < jw) ? prices[R.id[s]] : T(0);
 }
 
-// wave-uniform slot count: the longest row among the wave's eight groups
+// wave-uniform slot count: ceil(k / 8) of the longest row among the wave's
+// eight groups (not capped at J: it also bounds the Dinkelbach rounds)
 template <int J>
 __device__ __forceinline__ int wave_slots(int k)
 {
@@ -162,7 +163,7 @@ __device__ __forceinline__ int wave_slots(int k)
     jw = max(jw, __shfl_xor(jw, 8));
     jw = max(jw, __shfl_xor(jw, 16));
     jw = max(jw, __shfl_xor(jw, 32));
-    return __builtin_amdgcn_readfirstlane(jw < J ? jw : J);
+    return __builtin_amdgcn_readfirstlane(jw);
 }
 
 // R = N / D.  FP32 uses the hardware reciprocal (about one ulp); the value
@@ -170,9 +171,10 @@ __device__ __forceinline__ int wave_slots(int k)
 __device__ __forceinline__ float ratio(float n, float d) { return n * __builtin_amdgcn_rcpf(d); }
 __device__ __forceinline__ double ratio(double n, double d) { return n / d; }
 
+// s >= 0 and s * scale < 2^30: round half up by truncating s * scale + 1/2
 __device__ __forceinline__ unsigned long long quantum(float s, double scale)
 {
-    return (unsigned long long)(unsigned)__float2int_rn(s * (float)scale);
+    return (unsigned long long)(unsigned)(int)__builtin_fmaf(s, (float)scale, 0.5f);
 }
 __device__ __forceinline__ unsigned long long quantum(double s, double scale)
 {
@@ -185,7 +187,8 @@ __device__ __forceinline__ unsigned long long quantum(double s, double scale)
 // one more tile of entries and the price gathers.  DEPTH 3 is DEPTH 1 with
 // every slot loaded and the loads of an iteration issued in the order they
 // are consumed (this tile's price gathers, the next tile's entries, the
-// bounds of the tile after), so the solve waits for its gathers alone.  The
+// bounds of the tile after), so the solve waits for its gathers alone; DEPTH
+// 4 is the same order with only the wave's jw slots loaded.  The
 // block visits tiles tile, tile + stride, ... below `tiles`; sales go to the
 // LDS bins (products < a.H) or the global tail; lambda R* is added to zacc.
 //
@@ -197,6 +200,7 @@ __device__ __forceinline__ void process_tiles(const SegArgs& a, int64_t tile, in
                                               const T* __restrict__ prices, double& zacc)
 {
     constexpr bool ALL = DEPTH == 3;
+    constexpr bool ORDERED = DEPTH >= 3;   // DEPTH 4: ordered issue, only jw slots loaded
     const T* __restrict__ vg = (const T*)a.v;
     const T* __restrict__ dg = (const T*)a.den;
     const T* __restrict__ rho = prices;
@@ -220,7 +224,7 @@ __device__ __forceinline__ void process_tiles(const SegArgs& a, int64_t tile, in
             R1 = load_raw<T, J, ALL>(a, B1, g, j1);
         }
         Bounds<T> B2;
-        if (DEPTH != 3) B2 = load_bounds<T>(a, pos_of(tile + 2 * stride));
+        if (!ORDERED) B2 = load_bounds<T>(a, pos_of(tile + 2 * stride));
 
         for (; tile < tiles; tile += stride) {
             // issue the next stages before touching the current tile
@@ -228,7 +232,7 @@ __device__ __forceinline__ void process_tiles(const SegArgs& a, int64_t tile, in
             Bounds<T> B3;
             T P1[J];
             int j2 = 0;
-            if (DEPTH == 3) {
+            if (ORDERED) {
                 gather<T, J, ALL>(rho, Rc, Pc, jc);
                 j1 = wave_slots<J>(row_len(B1));
                 R1 = load_raw<T, J, ALL>(a, B1, g, j1);
@@ -259,16 +263,23 @@ __device__ __forceinline__ void process_tiles(const SegArgs& a, int64_t tile, in
                 num[s] = ok ? Pc[s] * Rc.v[s] : T(0);   // 0 > R * 1 never holds for R >= 0
                 den[s] = ok ? Rc.den[s] : T(1);
             }
-            auto sums = [&](T R, T& N, T& Dn, int& cnt) {
+            // Dinkelbach with wave-wide membership masks.  A full pass forms
+            // S(R) - one ballot per slot - and its sums; a check pass only
+            // compares S(R') with S(R).  A group whose set did not change
+            // repeats the same sums, so the loop is uniform over the wave and
+            // ends when no group of the wave changes.
+            const int js = jw < J ? jw : J;
+            unsigned long long mask[J];
+            auto full = [&](T R, T& N, T& Dn) {
                 T n_ = T(0), d_ = T(0);
-                int c_ = 0;
 #pragma unroll
                 for (int s = 0; s < J; ++s) {
-                    if (s >= jw) break;
+                    mask[s] = 0ull;
+                    if (s >= js) continue;
                     const bool in = num[s] > R * den[s];
+                    mask[s] = __ballot(in);
                     n_ += in ? num[s] : T(0);
                     d_ += in ? den[s] : T(0);
-                    c_ += in ? 1 : 0;
                 }
                 for (int q = kGroup * J + g; q < k; q += kGroup) {
                     const T nn = rho[idx[b + q]] * vg[b + q];
@@ -276,33 +287,67 @@ __device__ __forceinline__ void process_tiles(const SegArgs& a, int64_t tile, in
                     if (nn > R * dd) {
                         n_ += nn;
                         d_ += dd;
-                        ++c_;
                     }
                 }
                 N = group_sum(n_);
                 Dn = group_sum(d_);
-                cnt = group_sum(c_);
             };
-            // Dinkelbach: R defines the set whose sums are (N, Dn, cnt)
+            auto changed = [&](T R, T Rn) {
+                unsigned long long diff = 0ull;
+#pragma unroll
+                for (int s = 0; s < J; ++s) {
+                    if (s >= js) break;
+                    diff |= __ballot(num[s] > Rn * den[s]) ^ mask[s];
+                }
+                if (jw > J) {                     // rows past the register slots
+                    bool t = false;
+                    for (int q = kGroup * J + g; q < k; q += kGroup) {
+                        const T nn = rho[idx[b + q]] * vg[b + q];
+                        const T dd = dg[b + q];
+                        t = t || ((nn > Rn * dd) != (nn > R * dd));
+                    }
+                    diff |= __ballot(t);
+                }
+                return diff;
+            };
+            // R is the threshold of the current set, (N, Dn) its sums and Rs
+            // its ratio; members have num > 0, so the set is empty exactly
+            // when N == 0.  In exact arithmetic the ratios rise until the set
+            // repeats.  Ties within an ulp can instead make a group alternate
+            // between two sets; the loop then runs to its cap, and such a
+            // group keeps the set of larger ratio of the two, which does not
+            // depend on where the iteration started.
             T R = Bc.R0, N, Dn;
-            int cnt;
-            sums(R, N, Dn, cnt);
-            for (int round = 0; round < k + 2; ++round) {
-                const T Rn = cnt > 0 ? ratio(N, vt0 + Dn) : T(0);
-                T N2, D2;
-                int c2;
-                sums(Rn, N2, D2, c2);
-                if (c2 == cnt) break;   // nested sets of equal size are equal
-                R = Rn;
-                N = N2;
-                Dn = D2;
-                cnt = c2;
+            full(R, N, Dn);
+            T Rs = N > T(0) ? ratio(N, vt0 + Dn) : T(0);
+            T pR = R, pN = N, pD = Dn, pRs = Rs;
+            unsigned long long diff = 0ull;
+            for (int round = 0; round <= kGroup * jw + 1; ++round) {
+                diff = changed(R, Rs);
+                if (diff == 0ull) break;
+                pR = R;
+                pN = N;
+                pD = Dn;
+                pRs = Rs;
+                R = Rs;
+                full(R, N, Dn);
+                Rs = N > T(0) ? ratio(N, vt0 + Dn) : T(0);
             }
-            const T Rstar = cnt > 0 ? ratio(N, vt0 + Dn) : T(0);
+            if (diff != 0ull) {
+                const unsigned long long now = changed(R, Rs);
+                const bool cycling = ((now >> (threadIdx.x & 56)) & 0xFFull) != 0ull;
+                if (cycling && pRs > Rs) {
+                    R = pR;
+                    N = pN;
+                    Dn = pD;
+                    Rs = pRs;
+                }
+            }
+            const T Rstar = Rs;
             const T lamD = ratio(Bc.lam, vt0 + Dn);
 #pragma unroll
             for (int s = 0; s < J; ++s) {
-                if (s >= jw) break;
+                if (s >= js) break;
                 if (num[s] > R * den[s]) {
                     const unsigned long long q = quantum(lamD * Rc.v[s], a.fx_scale);
                     const int32_t j = Rc.id[s];
@@ -332,7 +377,7 @@ __device__ __forceinline__ void process_tiles(const SegArgs& a, int64_t tile, in
             Bc = B1;
             Rc = R1;
             jc = j1;
-            if (DEPTH == 3) {
+            if (ORDERED) {
                 B1 = B2;
             } else if (DEPTH == 2) {
 #pragma unroll
