@@ -122,7 +122,7 @@ k_bsegments(const BInst* inst, const BItem* items, int nitems, unsigned* counter
         for (int j = threadIdx.x; j < H; j += kSegThreads) bins[j] = 0ull;
         __syncthreads();
         double zacc = 0.0;
-        seg::process_tiles<T, J, DEPTH>(a, w.t0, w.t1, 1, bins, (const T*)a.rho, zacc);
+        seg::process_tiles<T, J, DEPTH>(a, w.t0, w.t1, 1, bins, seg::FlatPrices<T>{(const T*)a.rho}, zacc);
         __syncthreads();
         unsigned long long* out = part_S + I->part_off + (size_t)(it - I->item0) * (size_t)H;
         for (int j = threadIdx.x; j < H; j += kSegThreads) out[j] = bins[j];
@@ -577,6 +577,7 @@ int cblp_batch_create(cblp_batch_t* out, int32_t count, const cblp_t* handles, v
         a.rho = h->rho;
         a.n = h->n;
         a.H = h->H;
+        a.hp = 0;
         a.part_S = nullptr;
         a.S_fx = h->S_fx;
         a.fx_scale = h->fx_scale;

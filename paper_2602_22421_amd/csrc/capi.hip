@@ -157,6 +157,7 @@ int run_segments(cblp_instance* h, void* seg_R, hipStream_t s)
     a.rho = h->rho;
     a.n = h->n;
     a.H = h->H;
+    a.hp = h->hp;
     a.part_S = h->part_S;
     a.S_fx = h->S_fx;
     a.fx_scale = h->fx_scale;
@@ -360,14 +361,17 @@ int create_impl(cblp_instance* h, hipStream_t s)
         const int x = std::atoi(ev);
         if (x >= 0 && x < kSegVariants && (!seg_lds_prices(x) || prices_fit)) h->seg_variant = x;
     }
-    const int64_t price_bytes = seg_lds_prices(h->seg_variant) ? h->n * (int64_t)sizeof(T) : 0;
+    h->hp = h->seg_variant == kSegSplit ? (int)std::min<int64_t>(h->n, kSplitPrices) : 0;
+    const int64_t price_bytes = h->seg_variant == kSegSplit ? (int64_t)h->hp * (int64_t)sizeof(T)
+                                : seg_lds_prices(h->seg_variant) ? h->n * (int64_t)sizeof(T) : 0;
     const int64_t lds_bins = ((int64_t)lds_block - 1024 - price_bytes) / 8;
     h->H = (int)std::max<int64_t>(1, std::min<int64_t>({h->n, (int64_t)kMaxBins, lds_bins}));
     if (const char* eb = std::getenv("CBLP_SEG_BINS")) {
         const long x = std::atol(eb);
         if (x >= 1 && x <= h->H) h->H = (int)x;
     }
-    const int per_cu = segment_blocks_per_cu<T>(h->H, h->n, h->seg_variant);
+    const int per_cu = segment_blocks_per_cu<T>(
+        h->H, h->seg_variant == kSegSplit ? (int64_t)h->hp : h->n, h->seg_variant);
     const int64_t tiles = (h->L + kSegsPerTile - 1) / kSegsPerTile;
     h->seg_grid = (int)std::max<int64_t>(1, std::min<int64_t>(tiles, (int64_t)cus * per_cu));
     h->fold_blocks = (int)((h->n + kFoldProducts - 1) / kFoldProducts);

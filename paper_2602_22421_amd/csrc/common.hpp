@@ -47,6 +47,7 @@ struct SegArgs {
     const void* rho;               // [n] reduced revenues
     int64_t n;                     // products (length of rho)
     int H;                         // products [0, H) are summed in LDS bins
+    int hp;                        // split-price kernel: prices [0, hp) held in LDS
     unsigned long long* part_S;    // [gridDim.x][H] per-block bin totals
     unsigned long long* S_fx;      // [n] fixed-point sales of products >= H
     double fx_scale;               // 2^bits; one segment's sale * 2^bits < 2^31 for FP32
@@ -113,9 +114,11 @@ hipError_t launch_prices(int64_t n, const void* r, const void* eta, const int64_
 // kSegLdsPrices and up first copy the n prices into LDS after the H bins.
 // Variants kSegClassLds (prices in LDS) and kSegClassGlobal take the slot
 // count of each block from a table: blocks own runs of tiles of one size class.
-constexpr int kSegVariants = 19;
+// Variant kSegSplit holds the prices of products [0, hp) in LDS.
+constexpr int kSegVariants = 20;
 constexpr int kSegLdsPrices = 10;
-constexpr int kSegClassLds = 17, kSegClassGlobal = 18;
+constexpr int kSegClassLds = 17, kSegClassGlobal = 18, kSegSplit = 19;
+constexpr int kSplitPrices = 8192;     // head prices of the split kernel
 inline bool seg_class(int variant) { return variant == kSegClassLds || variant == kSegClassGlobal; }
 // most register slots of the size-class kernels per element size
 inline int seg_class_max_slots(size_t esz) { return esz == 4 ? 7 : 4; }

@@ -50,6 +50,7 @@ struct cblp_instance {
     int seg_grid = 1;
     int seg_variant = 0;
     int H = 0;
+    int hp = 0;                     // split-price kernel: prices held in LDS
     int fold_blocks = 1;
     double fx_scale = 1.0;
     int64_t t = 0;

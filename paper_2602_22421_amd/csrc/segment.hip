@@ -24,14 +24,46 @@ __global__ void __launch_bounds__(kSegThreads) k_segments(SegArgs a)
     double zacc = 0.0;
     const int64_t tiles = (a.L + kSegsPerTile - 1) / kSegsPerTile;
     // the grid never exceeds the tile count, except for L = 0 (one block)
-    seg::process_tiles<T, J, DEPTH>(a, blockIdx.x, tiles, gridDim.x, bins,
-                                    LDSP ? (const T*)lprice : (const T*)a.rho, zacc);
+    const seg::FlatPrices<T> pr{LDSP ? (const T*)lprice : (const T*)a.rho};
+    seg::process_tiles<T, J, DEPTH>(a, blockIdx.x, tiles, gridDim.x, bins, pr, zacc);
 
     __syncthreads();
     unsigned long long* out = a.part_S + (size_t)blockIdx.x * (size_t)H;
     for (int j = threadIdx.x; j < H; j += kSegThreads) out[j] = bins[j];
 
     // block partial of sum lambda R*: fixed shuffle tree, waves in order
+    for (int o = 32; o > 0; o >>= 1) zacc += __shfl_down(zacc, o, 64);
+    if ((threadIdx.x & 63) == 0) zsh[threadIdx.x >> 6] = zacc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double z = zsh[0];
+        for (int q = 1; q < kSegThreads / 64; ++q) z += zsh[q];
+        a.zpart[blockIdx.x] = z;
+    }
+}
+
+// Split-price kernel: the prices of the popular head [0, a.hp) are copied
+// into LDS behind the bins, the rest are gathered from global memory; the
+// smaller copy leaves room for more bins, so fewer sales take global atomics.
+template <typename T, int J>
+__global__ void __launch_bounds__(kSegThreads) k_segments_split(SegArgs a)
+{
+    extern __shared__ unsigned long long bins[];   // [a.H], then [a.hp] prices
+    __shared__ double zsh[kSegThreads / 64];
+    const int H = a.H;
+    T* lprice = (T*)(bins + H);
+    for (int j = threadIdx.x; j < H; j += kSegThreads) bins[j] = 0ull;
+    for (int j = threadIdx.x; j < a.hp; j += kSegThreads) lprice[j] = ((const T*)a.rho)[j];
+    __syncthreads();
+
+    double zacc = 0.0;
+    const int64_t tiles = (a.L + kSegsPerTile - 1) / kSegsPerTile;
+    const seg::SplitPrices<T> pr{(const T*)lprice, (const T*)a.rho, a.hp};
+    seg::process_tiles<T, J, 3>(a, blockIdx.x, tiles, gridDim.x, bins, pr, zacc);
+
+    __syncthreads();
+    unsigned long long* out = a.part_S + (size_t)blockIdx.x * (size_t)H;
+    for (int j = threadIdx.x; j < H; j += kSegThreads) out[j] = bins[j];
     for (int o = 32; o > 0; o >>= 1) zacc += __shfl_down(zacc, o, 64);
     if ((threadIdx.x & 63) == 0) zsh[threadIdx.x >> 6] = zacc;
     __syncthreads();
@@ -62,7 +94,7 @@ __global__ void __launch_bounds__(kSegThreads) k_segments_cls(SegArgs a)
     const int64_t* e = a.blk + 3 * (size_t)blockIdx.x;
     const int J = (int)e[0];
     const int64_t t0 = e[1], t1 = e[2];
-    const T* pr = LDSP ? (const T*)lprice : (const T*)a.rho;
+    const seg::FlatPrices<T> pr{LDSP ? (const T*)lprice : (const T*)a.rho};
     // FP64 holds at most 4 slots in registers, FP32 7 (longer rows stream
     // the rest from memory in each round)
     switch (J) {
@@ -124,6 +156,7 @@ const void* SegVariant<T>::fn(int variant)
     case 16: return (const void*)k_segments<T, 8, 4, true>;
     case kSegClassLds: return (const void*)k_segments_cls<T, true>;
     case kSegClassGlobal: return (const void*)k_segments_cls<T, false>;
+    case kSegSplit: return (const void*)k_segments_split<T, 7>;
     default: return (const void*)k_segments<T, 4, 1, false>;
     }
 }
@@ -131,14 +164,14 @@ const void* SegVariant<T>::fn(int variant)
 template <typename T>
 hipError_t launch_segments(const SegArgs& a, int grid, int variant, hipStream_t s)
 {
-    const size_t lds = seg_lds_bytes(a.H, a.n, sizeof(T), variant);
+    const size_t lds = seg_lds_bytes(a.H, variant == kSegSplit ? a.hp : a.n, sizeof(T), variant);
     void* args[] = {(void*)&a};
     return hipLaunchKernel(SegVariant<T>::fn(variant), dim3(grid), dim3(kSegThreads), args, lds,
                            s);
 }
 
 template <typename T>
-int segment_blocks_per_cu(int H, int64_t n, int variant)
+int segment_blocks_per_cu(int H, int64_t n, int variant)   // n: prices held in LDS
 {
     int blocks = 0;
     const size_t lds = seg_lds_bytes(H, n, sizeof(T), variant);

@@ -146,9 +146,31 @@ __device__ __forceinline__ Raw<T, J> load_raw(const SegArgs& a, const Bounds<T>&
     return R;
 }
 
-template <typename T, int J, bool ALL>
-__device__ __forceinline__ void gather(const T* __restrict__ prices, const Raw<T, J>& R,
-                                       T (&p)[J], int jw)
+// Price tables: all in one memory (global or an LDS copy), or split with
+// the popular head [0, hp) in LDS and the rest read from global memory.
+template <typename T>
+struct FlatPrices {
+    const T* __restrict__ p;
+    __device__ __forceinline__ T operator[](int j) const { return p[j]; }
+};
+template <typename T>
+struct SplitPrices {
+    const T* __restrict__ lds;
+    const T* __restrict__ glob;
+    int hp;
+    // both reads for every lane (no pointer select, which would make a flat
+    // access); head lanes read global entry 0, one shared cache line
+    __device__ __forceinline__ T operator[](int j) const
+    {
+        const bool head = j < hp;
+        const T l = lds[head ? j : 0];
+        const T g = glob[head ? 0 : j];
+        return head ? l : g;
+    }
+};
+
+template <typename T, int J, bool ALL, typename PR>
+__device__ __forceinline__ void gather(const PR& prices, const Raw<T, J>& R, T (&p)[J], int jw)
 {
 #pragma unroll
     for (int s = 0; s < J; ++s) p[s] = (ALL || s < jw) ? prices[R.id[s]] : T(0);
@@ -156,14 +178,16 @@ __device__ __forceinline__ void gather(const T* __restrict__ prices, const Raw<T
 
 // wave-uniform slot count: ceil(k / 8) of the longest row among the wave's
 // eight groups (not capped at J: it also bounds the Dinkelbach rounds)
+// (the first lane of each group holds the group's value; eight lane reads
+// into scalar registers avoid the round trips of cross-lane shuffles)
 template <int J>
 __device__ __forceinline__ int wave_slots(int k)
 {
-    int jw = (k + kGroup - 1) / kGroup;
-    jw = max(jw, __shfl_xor(jw, 8));
-    jw = max(jw, __shfl_xor(jw, 16));
-    jw = max(jw, __shfl_xor(jw, 32));
-    return __builtin_amdgcn_readfirstlane(jw);
+    const int jw = (k + kGroup - 1) / kGroup;
+    int m = __builtin_amdgcn_readlane(jw, 0);
+#pragma unroll
+    for (int q = 1; q < 64 / kGroup; ++q) m = max(m, __builtin_amdgcn_readlane(jw, q * kGroup));
+    return m;
 }
 
 // R = N / D.  FP32 uses the hardware reciprocal (about one ulp); the value
@@ -192,18 +216,18 @@ __device__ __forceinline__ unsigned long long quantum(double s, double scale)
 // block visits tiles tile, tile + stride, ... below `tiles`; sales go to the
 // LDS bins (products < a.H) or the global tail; lambda R* is added to zacc.
 //
-// prices: the reduced revenues rho_j, either a.rho itself or a copy of it in
-// LDS (the caller's choice; the compiler sees which memory it is).
-template <typename T, int J, int DEPTH>
+// prices: the reduced revenues rho_j as a FlatPrices (a.rho itself or a copy
+// of it in LDS; the compiler sees which memory it is) or a SplitPrices.
+template <typename T, int J, int DEPTH, typename PR>
 __device__ __forceinline__ void process_tiles(const SegArgs& a, int64_t tile, int64_t tiles,
                                               int64_t stride, unsigned long long* bins,
-                                              const T* __restrict__ prices, double& zacc)
+                                              const PR& prices, double& zacc)
 {
     constexpr bool ALL = DEPTH == 3;
     constexpr bool ORDERED = DEPTH >= 3;   // DEPTH 4: ordered issue, only jw slots loaded
     const T* __restrict__ vg = (const T*)a.v;
     const T* __restrict__ dg = (const T*)a.den;
-    const T* __restrict__ rho = prices;
+    const PR& rho = prices;
     const int32_t* __restrict__ idx = a.idx;
     const int H = a.H;
     const int g = threadIdx.x & (kGroup - 1);
@@ -215,7 +239,7 @@ __device__ __forceinline__ void process_tiles(const SegArgs& a, int64_t tile, in
         int jc = wave_slots<J>(row_len(Bc));
         Raw<T, J> Rc = load_raw<T, J, ALL>(a, Bc, g, jc);
         T Pc[J];
-        if (DEPTH == 2) gather<T, J, ALL>(rho, Rc, Pc, jc);
+        if (DEPTH == 2) gather<T, J, ALL, PR>(rho, Rc, Pc, jc);
         Bounds<T> B1 = load_bounds<T>(a, pos_of(tile + stride));
         int j1 = 0;
         Raw<T, J> R1;
@@ -233,7 +257,10 @@ __device__ __forceinline__ void process_tiles(const SegArgs& a, int64_t tile, in
             T P1[J];
             int j2 = 0;
             if (ORDERED) {
-                gather<T, J, ALL>(rho, Rc, Pc, jc);
+                gather<T, J, ALL, PR>(rho, Rc, Pc, jc);
+                // keep the gathers ahead of the next tile's loads: a wait for
+                // a gather then never waits for those loads
+                __builtin_amdgcn_sched_barrier(0);
                 j1 = wave_slots<J>(row_len(B1));
                 R1 = load_raw<T, J, ALL>(a, B1, g, j1);
                 B2 = load_bounds<T>(a, pos_of(tile + 2 * stride));
@@ -241,13 +268,13 @@ __device__ __forceinline__ void process_tiles(const SegArgs& a, int64_t tile, in
                 j2 = wave_slots<J>(row_len(B2));
                 R2 = load_raw<T, J, ALL>(a, B2, g, j2);
                 B3 = load_bounds<T>(a, pos_of(tile + 3 * stride));
-                gather<T, J, ALL>(rho, R1, P1, j1);
+                gather<T, J, ALL, PR>(rho, R1, P1, j1);
             } else if (DEPTH == 1) {
                 j1 = wave_slots<J>(row_len(B1));
                 R1 = load_raw<T, J, ALL>(a, B1, g, j1);
-                gather<T, J, ALL>(rho, Rc, Pc, jc);
+                gather<T, J, ALL, PR>(rho, Rc, Pc, jc);
             } else {
-                gather<T, J, ALL>(rho, Rc, Pc, jc);
+                gather<T, J, ALL, PR>(rho, Rc, Pc, jc);
             }
 
             const int64_t p = pos_of(tile);
