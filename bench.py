@@ -40,6 +40,8 @@ def algorithmic_bytes(inst, esz):
 
 
 PROFILE_OF = {"plain-L2e6-n2e4-zipf-identity": "k_segments-plain-L2e6-n2e4.md"}
+# the segment kernel's sources; the profile records their hash
+PROFILE_SOURCES = ("segment.hip", "segment_core.hpp", "common.hpp")
 
 
 def profiled_traffic(workload):
@@ -53,7 +55,7 @@ def profiled_traffic(workload):
     if not path or not os.path.exists(path):
         return None
     src = b"".join(open(os.path.join(ROOT, "paper_2602_22421_amd", "csrc", f), "rb").read()
-                   for f in ("segment.hip", "common.hpp"))
+                   for f in PROFILE_SOURCES)
     sha = hashlib.sha256(src).hexdigest()[:16]
     rec, traffic = None, None
     for line in open(path):
