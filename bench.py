@@ -19,6 +19,7 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+BF16_PEAK = 2.5e15            # dense BF16 matrix-core peak of MI355X, FLOP/s
 HBM_PEAK = 8.0e12          # MI355X HBM3E, bytes/s
 
 
@@ -87,7 +88,7 @@ def cpu_baseline(inst, budget_s=15.0):
     Ls2 = int(min(inst.L, max(Ls, Ls * budget_s / 3.0 / max(one, 1e-6))))
     sub = prefix(Ls2)
     s = oracle.Solver(sub, tau=step_scale(inst, 0.001))
-    iters = 3
+    iters = max(3, int(budget_s / max(one * Ls2 / Ls, 1e-6)))
     t0 = time.perf_counter()
     s.iterate(np.zeros(inst.m), iters, trace=False)
     dt = time.perf_counter() - t0
@@ -198,6 +199,30 @@ def warmstart_bench(args):
     t_train = time.perf_counter() - t0
     log(f"trained {args.ws_epochs} epochs in {t_train:.1f} s: loss {losses[0]:.3e} -> "
         f"{losses[-1]:.3e} (target variance {float(Y.var()):.3e})")
+    # matrix-core throughput of the network: forward over every training row,
+    # and one epoch of training steps (forward, two backward products, Adam)
+    rows = X.shape[0]
+    flops_fwd = 2.0 * rows * (4 * 256 + 256 * 256 + 256)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    net.forward(X)
+    ev[0].record()
+    for _ in range(5):
+        net.forward(X)
+    ev[1].record()
+    ev[2].record()
+    net.train(X, Y, epochs=1, batch=2048, lr=1e-6, seed=1)
+    ev[3].record()
+    torch.cuda.synchronize()
+    fwd_s = ev[0].elapsed_time(ev[1]) / 5e3
+    ep_s = ev[2].elapsed_time(ev[3]) / 1e3
+    mlp = {"rows": rows, "forward_ms": fwd_s * 1e3,
+           "forward_tflops": flops_fwd / fwd_s / 1e12,
+           "forward_frac_bf16_peak": flops_fwd / fwd_s / BF16_PEAK,
+           "train_epoch_ms": ep_s * 1e3,
+           "train_tflops": 3.0 * flops_fwd / ep_s / 1e12,
+           "train_frac_bf16_peak": 3.0 * flops_fwd / ep_s / BF16_PEAK}
+    log(f"network: forward {fwd_s * 1e3:.2f} ms over {rows} rows "
+        f"({mlp['forward_tflops']:.1f} TFLOP/s), training epoch {ep_s * 1e3:.1f} ms")
     levels = (1e-1, 3e-2, 2e-2, 1e-2, 1e-3, 1e-4)
     results = []
     for seed in args.ws_eval_seeds:
@@ -261,6 +286,7 @@ def warmstart_bench(args):
                    "epochs": args.ws_epochs, "tau0": args.ws_tau0,
                    "max_iters": args.max_iters, "caps": caps},
         "speedup_by_level": {f"{lv:g}": speedup(f"{lv:g}") for lv in levels},
+        "network": mlp,
         "collect_s": t_collect, "train_s": t_train, "loss_first": losses[0],
         "loss_last": losses[-1], "target_variance": float(Y.var()), "eval": results,
     }
