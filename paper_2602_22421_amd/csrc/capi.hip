@@ -79,7 +79,7 @@ void release(cblp_instance* h)
 {
     if (!h) return;
     void* ptrs[] = {h->ptr2, h->idx2, h->v2, h->den2, h->vt0, h->lam2, h->Rwarm, h->v0c, h->perm,
-                    h->seg_blk,
+                    h->seg_blk, h->woff, h->idx3, h->v3, h->den3,
                     h->rho, h->S_fx, h->part_S, h->S_d, h->u_d, h->sum_u, h->zpart,
                     h->bpart, h->bpart2, h->st, h->trace, h->at_ptr,
                     h->at_prod, h->at_val};
@@ -164,6 +164,10 @@ int run_segments(cblp_instance* h, void* seg_R, hipStream_t s)
     a.zpart = h->zpart;
     a.seg_R = seg_R;
     a.blk = h->seg_blk;
+    a.woff = h->woff;
+    a.idx3 = h->idx3;
+    a.v3 = h->v3;
+    a.den3 = h->den3;
     size_t slot;
     int rc = timed_begin(h, 0, s, &slot);
     if (rc) return rc;
@@ -356,7 +360,7 @@ int create_impl(cblp_instance* h, hipStream_t s)
     // kernel variant and bin count may be overridden for tuning runs.  The
     // prices go to LDS when they take at most half of it.
     const bool prices_fit = (int64_t)h->n * (int64_t)sizeof(T) * 2 <= (int64_t)lds_block;
-    h->seg_variant = sizeof(T) == 4 ? (prices_fit ? 13 : 6) : (prices_fit ? 12 : 4);
+    h->seg_variant = sizeof(T) == 4 ? (prices_fit ? kSegSlots + 1 : 6) : kSegSlots + 3;
     if (const char* ev = std::getenv("CBLP_SEG_VARIANT")) {
         const int x = std::atoi(ev);
         if (x >= 0 && x < kSegVariants && (!seg_lds_prices(x) || prices_fit)) h->seg_variant = x;
@@ -469,6 +473,27 @@ int create_impl(cblp_instance* h, hipStream_t s)
             HIP_TRY(launch_relayout<T>(h->L, h->seg_ptr, h->idx, h->v, h->w, h->v0, h->lam,
                                        h->perm, h->ptr2, h->idx2, h->v2, h->den2, h->vt0,
                                        h->lam2, h->Rwarm, h->v0c, s));
+        if (seg_slot_major(h->seg_variant)) {
+            // slot-major copy: wave-tile w (positions 8w..8w+7) gets 64 entries per
+            // slot for as many slots as its longest row needs (at least one)
+            const int64_t W = (h->L + kGroup - 1) / kGroup;
+            std::vector<int64_t> woff((size_t)W + 2, 0);   // one spare entry
+            for (int64_t w = 0; w < W; ++w) {
+                int64_t kw = 0;
+                for (int64_t p = w * kGroup; p < std::min(h->L, (w + 1) * kGroup); ++p)
+                    kw = std::max(kw, ptr[p + 1] - ptr[p]);
+                woff[w + 1] = woff[w] + 64 * std::max<int64_t>(1, (kw + kGroup - 1) / kGroup);
+            }
+            const int64_t entries = woff[W] + 64 * kMaxJ;   // loads may run J slots past the end
+            woff[W + 1] = woff[W];
+            if ((rc = dalloc(&h->woff, (size_t)(W + 2) * 8))) return rc;
+            if ((rc = dalloc(&h->idx3, (size_t)entries * 4))) return rc;
+            if ((rc = dalloc(&h->v3, (size_t)entries * esz))) return rc;
+            if ((rc = dalloc(&h->den3, (size_t)entries * esz))) return rc;
+            HIP_TRY(hipMemcpyAsync(h->woff, woff.data(), (W + 2) * 8, hipMemcpyHostToDevice, s));
+            HIP_TRY(launch_relayout_slots<T>(h->L, h->ptr2, h->idx2, h->v2, h->den2, h->woff,
+                                             entries, h->idx3, h->v3, h->den3, s));
+        }
         HIP_TRY(hipStreamSynchronize(s));   // the host vectors die here
     }
     if ((rc = dalloc(&h->part_S, (size_t)h->seg_grid * std::max(h->H, 1) * 8))) return rc;

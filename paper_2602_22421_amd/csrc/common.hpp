@@ -55,6 +55,12 @@ struct SegArgs {
     void* seg_R;                   // [L] nullable, original segment order
     const int64_t* blk;            // [grid][3] (slots J, first tile, end tile) of each
                                    // block for the size-class kernels, else unused
+    // slot-major copy (slot-major kernels): wave-tile w (positions 8w..8w+7)
+    // holds (woff[w+1] - woff[w]) / 64 slots of 64 entries from woff[w]
+    const int64_t* woff;           // [ceil(L/8) + 2], the last entry repeats the total
+    const int32_t* idx3;
+    const void* v3;
+    const void* den3;
 };
 
 struct PhaseArgs {
@@ -108,14 +114,22 @@ hipError_t launch_relayout(int64_t L, const int64_t* seg_ptr, const int32_t* idx
                            void* den2, void* vt0, void* lam2, void* Rwarm, void* v0c,
                            hipStream_t s);
 template <typename T>
+hipError_t launch_relayout_slots(int64_t L, const int64_t* ptr, const int32_t* idx2,
+                                 const void* v2, const void* den2, const int64_t* woff,
+                                 int64_t entries, int32_t* idx3, void* v3, void* den3,
+                                 hipStream_t s);
+template <typename T>
 hipError_t launch_prices(int64_t n, const void* r, const void* eta, const int64_t* a_ptr,
                          const int32_t* a_idx, const void* a_val, void* rho, hipStream_t s);
 // Segment-kernel variants 0-9 gather prices from global memory; variants
 // kSegLdsPrices and up first copy the n prices into LDS after the H bins.
 // Variants kSegClassLds (prices in LDS) and kSegClassGlobal take the slot
 // count of each block from a table: blocks own runs of tiles of one size class.
-// Variant kSegSplit holds the prices of products [0, hp) in LDS.
-constexpr int kSegVariants = 20;
+// Variant kSegSplit holds the prices of products [0, hp) in LDS.  Variants
+// kSegSlots and up read the slot-major copy (see SegArgs::woff).
+constexpr int kSegVariants = 26;
+constexpr int kSegSlots = 20;
+inline bool seg_slot_major(int variant) { return variant >= kSegSlots; }
 constexpr int kSegLdsPrices = 10;
 constexpr int kSegClassLds = 17, kSegClassGlobal = 18, kSegSplit = 19;
 constexpr int kSplitPrices = 8192;     // head prices of the split kernel
@@ -124,7 +138,8 @@ inline bool seg_class(int variant) { return variant == kSegClassLds || variant =
 inline int seg_class_max_slots(size_t esz) { return esz == 4 ? 7 : 4; }
 inline bool seg_lds_prices(int variant)
 {
-    return variant >= kSegLdsPrices && variant != kSegClassGlobal;
+    return variant >= kSegLdsPrices && variant != kSegClassGlobal && variant != kSegSlots + 3 &&
+           variant != kSegSlots + 5;
 }
 // dynamic LDS bytes of a segment block: H bins, then the prices if in LDS
 inline size_t seg_lds_bytes(int H, int64_t n, size_t esz, int variant)

@@ -30,6 +30,10 @@ struct cblp_instance {
     void* v0c = nullptr;            // v0 per position (features only)
     int32_t* perm = nullptr;
     int64_t* seg_blk = nullptr;     // [seg_grid][3] size-class block table (class variants)
+    int64_t* woff = nullptr;        // slot-major copy (slot-major variants): wave-tile offsets
+    int32_t* idx3 = nullptr;
+    void* v3 = nullptr;
+    void* den3 = nullptr;
     // owned workspace
     void* rho = nullptr;
     unsigned long long* S_fx = nullptr;

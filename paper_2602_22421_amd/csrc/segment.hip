@@ -74,6 +74,39 @@ __global__ void __launch_bounds__(kSegThreads) k_segments_split(SegArgs a)
     }
 }
 
+// Slot-major kernel: the per-segment step over the slot-major copy (one
+// contiguous 256-byte read per slot and array for a whole wave).
+template <typename T, int J, bool ALL, bool LDSP, bool TOUCH = false>
+__global__ void __launch_bounds__(kSegThreads) k_segments_slots(SegArgs a)
+{
+    extern __shared__ unsigned long long bins[];   // [a.H], then [a.n] prices if LDSP
+    __shared__ double zsh[kSegThreads / 64];
+    const int H = a.H;
+    T* lprice = (T*)(bins + H);
+    for (int j = threadIdx.x; j < H; j += kSegThreads) bins[j] = 0ull;
+    if (LDSP)
+        for (int64_t j = threadIdx.x; j < a.n; j += kSegThreads) lprice[j] = ((const T*)a.rho)[j];
+    __syncthreads();
+
+    double zacc = 0.0;
+    const int64_t tiles = (a.L + kSegsPerTile - 1) / kSegsPerTile;
+    const seg::FlatPrices<T> pr{LDSP ? (const T*)lprice : (const T*)a.rho};
+    seg::process_tiles_slots<T, J, ALL, seg::FlatPrices<T>, TOUCH>(a, blockIdx.x, tiles, gridDim.x,
+                                                                 bins, pr, zacc);
+
+    __syncthreads();
+    unsigned long long* out = a.part_S + (size_t)blockIdx.x * (size_t)H;
+    for (int j = threadIdx.x; j < H; j += kSegThreads) out[j] = bins[j];
+    for (int o = 32; o > 0; o >>= 1) zacc += __shfl_down(zacc, o, 64);
+    if ((threadIdx.x & 63) == 0) zsh[threadIdx.x >> 6] = zacc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double z = zsh[0];
+        for (int q = 1; q < kSegThreads / 64; ++q) z += zsh[q];
+        a.zpart[blockIdx.x] = z;
+    }
+}
+
 // Size-class kernel: block b solves tiles [blk[b][1], blk[b][2]) with
 // blk[b][0] register slots per lane.  The layout is sorted by row length, so
 // a run of tiles has one slot count, and loading every slot of it wastes no
@@ -157,6 +190,12 @@ const void* SegVariant<T>::fn(int variant)
     case kSegClassLds: return (const void*)k_segments_cls<T, true>;
     case kSegClassGlobal: return (const void*)k_segments_cls<T, false>;
     case kSegSplit: return (const void*)k_segments_split<T, 7>;
+    case kSegSlots: return (const void*)k_segments_slots<T, 7, true, true>;
+    case kSegSlots + 1: return (const void*)k_segments_slots<T, 7, false, true>;
+    case kSegSlots + 2: return (const void*)k_segments_slots<T, 8, true, true>;
+    case kSegSlots + 3: return (const void*)k_segments_slots<T, 4, true, false>;
+    case kSegSlots + 4: return (const void*)k_segments_slots<T, 7, false, true, true>;
+    case kSegSlots + 5: return (const void*)k_segments_slots<T, 4, false, false, true>;
     default: return (const void*)k_segments<T, 4, 1, false>;
     }
 }

@@ -195,14 +195,19 @@ __device__ __forceinline__ int wave_slots(int k)
 __device__ __forceinline__ float ratio(float n, float d) { return n * __builtin_amdgcn_rcpf(d); }
 __device__ __forceinline__ double ratio(double n, double d) { return n / d; }
 
-// s >= 0 and s * scale < 2^30: round half up by truncating s * scale + 1/2
-__device__ __forceinline__ unsigned long long quantum(float s, double scale)
+__device__ __forceinline__ float fmadd(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmadd(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// Fixed-point quantum of a sale lambda v / D, given ls = (lambda / D) 2^bits
+// (a power-of-two scaling, exact).  FP32: the quantum is below 2^30; round
+// half up by truncating ls v + 1/2.  FP64: round to nearest.
+__device__ __forceinline__ unsigned long long quantum(float ls, float v)
 {
-    return (unsigned long long)(unsigned)(int)__builtin_fmaf(s, (float)scale, 0.5f);
+    return (unsigned long long)(unsigned)(int)__builtin_fmaf(ls, v, 0.5f);
 }
-__device__ __forceinline__ unsigned long long quantum(double s, double scale)
+__device__ __forceinline__ unsigned long long quantum(double ls, double v)
 {
-    return (unsigned long long)__double2ll_rn(s * scale);
+    return (unsigned long long)__double2ll_rn(ls * v);
 }
 
 // J: products per lane held in registers (rows longer than 8 J stream the
@@ -283,12 +288,14 @@ __device__ __forceinline__ void process_tiles(const SegArgs& a, int64_t tile, in
             const T vt0 = Bc.vt0;
             const int jw = jc;
 
+            // slots past the row hold num = 0, which never enters a set
+            // (0 > R den is false for R >= 0 and den > 0)
             T num[J], den[J];
 #pragma unroll
             for (int s = 0; s < J; ++s) {
                 const bool ok = g + kGroup * s < k;
-                num[s] = ok ? Pc[s] * Rc.v[s] : T(0);   // 0 > R * 1 never holds for R >= 0
-                den[s] = ok ? Rc.den[s] : T(1);
+                num[s] = ok ? Pc[s] * Rc.v[s] : T(0);
+                den[s] = Rc.den[s];
             }
             // Dinkelbach with wave-wide membership masks.  A full pass forms
             // S(R) - one ballot per slot - and its sums; a check pass only
@@ -305,8 +312,10 @@ __device__ __forceinline__ void process_tiles(const SegArgs& a, int64_t tile, in
                     if (s >= js) continue;
                     const bool in = num[s] > R * den[s];
                     mask[s] = __ballot(in);
-                    n_ += in ? num[s] : T(0);
-                    d_ += in ? den[s] : T(0);
+                    // fma by 0 or 1 adds the value or nothing, rounded once
+                    const T w = in ? T(1) : T(0);
+                    n_ = fmadd(w, num[s], n_);
+                    d_ = fmadd(w, den[s], d_);
                 }
                 for (int q = kGroup * J + g; q < k; q += kGroup) {
                     const T nn = rho[idx[b + q]] * vg[b + q];
@@ -371,12 +380,12 @@ __device__ __forceinline__ void process_tiles(const SegArgs& a, int64_t tile, in
                 }
             }
             const T Rstar = Rs;
-            const T lamD = ratio(Bc.lam, vt0 + Dn);
+            const T lamD = ratio(Bc.lam, vt0 + Dn) * (T)a.fx_scale;
 #pragma unroll
             for (int s = 0; s < J; ++s) {
                 if (s >= js) break;
                 if (num[s] > R * den[s]) {
-                    const unsigned long long q = quantum(lamD * Rc.v[s], a.fx_scale);
+                    const unsigned long long q = quantum(lamD, Rc.v[s]);
                     const int32_t j = Rc.id[s];
                     if (j < H)
                         atomicAdd(&bins[j], q);
@@ -388,7 +397,7 @@ __device__ __forceinline__ void process_tiles(const SegArgs& a, int64_t tile, in
                 const T x = vg[b + q];
                 const int32_t j = idx[b + q];
                 if (rho[j] * x > R * dg[b + q]) {
-                    const unsigned long long qq = quantum(lamD * x, a.fx_scale);
+                    const unsigned long long qq = quantum(lamD, x);
                     if (j < H)
                         atomicAdd(&bins[j], qq);
                     else
@@ -423,6 +432,253 @@ __device__ __forceinline__ void process_tiles(const SegArgs& a, int64_t tile, in
             }
         }
     }
+}
+
+
+// ---------------------------------------------------------------- slot-major
+// The same per-segment step over the slot-major copy: a wave owns the eight
+// rows of one wave-tile, and slot s of the whole wave is 64 consecutive
+// entries (lane 8 q + g holds entry g + 8 s of row q), so every load of a
+// slot is one contiguous 256-byte read.  Places past a row's end hold v = 0
+// (num = 0 never enters a set), so rows need no length masks; slots past the
+// wave-tile's own count (ALL loads J of them) are masked by one scalar test.
+template <typename T>
+struct WaveBounds {
+    int64_t b0, b1;   // entries [b0, b1) of the wave-tile (same in every lane)
+    bool wlive;       // the wave-tile exists
+    T vt0, lam, R0;
+    bool live;        // this group's row exists
+};
+
+// Loads only; the slot count is formed where it is used, a pipeline step
+// later, so no wait is needed here (woff has one spare entry at the end).
+template <typename T>
+__device__ __forceinline__ WaveBounds<T> load_wave_bounds(const SegArgs& a, int64_t t, int wv,
+                                                         int q)
+{
+    const int64_t W = (a.L + kGroup - 1) / kGroup;
+    const int64_t w = t * (kSegsPerTile / kGroup) + wv;
+    const int64_t wc = w < W ? w : 0;
+    WaveBounds<T> B;
+    B.b0 = a.woff[wc];
+    B.b1 = a.woff[wc + 1];
+    B.wlive = w < W;
+    const int64_t p = w * kGroup + q;
+    const int64_t pc = p < a.L ? p : 0;
+    B.vt0 = ((const T*)a.vt0)[pc];
+    B.lam = ((const T*)a.lam)[pc];
+    B.R0 = ((const T*)a.Rwarm)[pc];
+    B.live = p < a.L;
+    return B;
+}
+
+template <typename T>
+__device__ __forceinline__ int64_t wave_base(const WaveBounds<T>& B)
+{
+    return ((int64_t)__builtin_amdgcn_readfirstlane((int)(B.b0 >> 32)) << 32) |
+           (uint32_t)__builtin_amdgcn_readfirstlane((int)B.b0);
+}
+template <typename T>
+__device__ __forceinline__ int wave_jw(const WaveBounds<T>& B)
+{
+    return __builtin_amdgcn_readfirstlane(B.wlive ? (int)((B.b1 - B.b0) >> 6) : 0);
+}
+
+template <typename T, int J, bool ALL>
+__device__ __forceinline__ Raw<T, J> load_slots(const SegArgs& a, const WaveBounds<T>& B, int lane)
+{
+    Raw<T, J> R;
+    const int64_t base = wave_base(B);
+    const int jw = ALL ? J : wave_jw(B);
+    const int32_t* pi = a.idx3 + base + lane;
+    const T* pv = (const T*)a.v3 + base + lane;
+    const T* pd = (const T*)a.den3 + base + lane;
+#pragma unroll
+    for (int s = 0; s < J; ++s) {
+        if (ALL || s < jw) {
+            R.id[s] = pi[64 * s];
+            R.v[s] = pv[64 * s];
+            R.den[s] = pd[64 * s];
+        } else {
+            R.id[s] = 0;
+            R.v[s] = T(0);
+            R.den[s] = T(1);
+        }
+    }
+    return R;
+}
+
+// One load per 128-byte line of a wave-tile's entries (three arrays), whose
+// values are only folded into a sink: it starts the HBM reads of the tile two
+// steps ahead so that its real loads, a step later, find the lines in L2.
+template <typename T>
+__device__ __forceinline__ unsigned touch_tile(const SegArgs& a, const WaveBounds<T>& B, int lane)
+{
+    const int64_t b0 = wave_base(B);
+    const int lines = (int)((B.wlive ? (B.b1 - B.b0) : 0) >> 5);   // 32 entries per line
+    const int arr = lane / 21, ln = lane % 21;                      // 3 arrays x 21 lines
+    const int64_t e = b0 + 32 * (int64_t)ln;
+    unsigned x = 0u;
+    if (arr < 3 && ln < lines) {
+        const unsigned* base = arr == 0 ? (const unsigned*)a.idx3
+                             : arr == 1 ? (const unsigned*)a.v3 : (const unsigned*)a.den3;
+        x = base[e * (arr == 0 ? 1 : (int64_t)(sizeof(T) / 4))];
+    }
+    return x;
+}
+
+template <typename T, int J, bool ALL, typename PR, bool TOUCH = false>
+__device__ __forceinline__ void process_tiles_slots(const SegArgs& a, int64_t tile, int64_t tiles,
+                                                    int64_t stride, unsigned long long* bins,
+                                                    const PR& rho, double& zacc)
+{
+    unsigned sink = 0u;
+    const T* __restrict__ v3 = (const T*)a.v3;
+    const T* __restrict__ d3 = (const T*)a.den3;
+    const int32_t* __restrict__ i3 = a.idx3;
+    const int H = a.H;
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    const int q = lane / kGroup;
+    if (tile >= tiles) return;
+
+    WaveBounds<T> Bc = load_wave_bounds<T>(a, tile, wv, q);
+    Raw<T, J> Rc = load_slots<T, J, ALL>(a, Bc, lane);
+    WaveBounds<T> B1 = load_wave_bounds<T>(a, tile + stride, wv, q);
+    WaveBounds<T> B2;
+    if (TOUCH) B2 = load_wave_bounds<T>(a, tile + 2 * stride, wv, q);
+    T Pc[J];
+    for (; tile < tiles; tile += stride) {
+        gather<T, J, true, PR>(rho, Rc, Pc, J);
+        __builtin_amdgcn_sched_barrier(0);
+        const Raw<T, J> R1 = load_slots<T, J, ALL>(a, B1, lane);
+        WaveBounds<T> B3;
+        if (TOUCH) {
+            sink ^= touch_tile<T>(a, B2, lane);
+            B3 = load_wave_bounds<T>(a, tile + 3 * stride, wv, q);
+        } else {
+            B2 = load_wave_bounds<T>(a, tile + 2 * stride, wv, q);
+        }
+
+        const int jw = wave_jw(Bc);
+        const int64_t base = wave_base(Bc);
+        const int js = jw < J ? jw : J;
+        const T vt0 = Bc.vt0;
+        T num[J], den[J];
+#pragma unroll
+        for (int s = 0; s < J; ++s) {
+            num[s] = s < js ? Pc[s] * Rc.v[s] : T(0);
+            den[s] = Rc.den[s];
+        }
+        unsigned long long mask[J];
+        auto full = [&](T R, T& N, T& Dn) {
+            T n_ = T(0), d_ = T(0);
+#pragma unroll
+            for (int s = 0; s < J; ++s) {
+                mask[s] = 0ull;
+                if (s >= js) continue;
+                const bool in = num[s] > R * den[s];
+                mask[s] = __ballot(in);
+                const T w = in ? T(1) : T(0);
+                n_ = fmadd(w, num[s], n_);
+                d_ = fmadd(w, den[s], d_);
+            }
+            for (int s = J; s < jw; ++s) {            // slots past the registers
+                const int64_t e = base + 64 * s + lane;
+                const T nn = rho[i3[e]] * v3[e];
+                const T dd = d3[e];
+                if (nn > R * dd) {
+                    n_ += nn;
+                    d_ += dd;
+                }
+            }
+            N = group_sum(n_);
+            Dn = group_sum(d_);
+        };
+        auto changed = [&](T R, T Rn) {
+            unsigned long long diff = 0ull;
+#pragma unroll
+            for (int s = 0; s < J; ++s) {
+                if (s >= js) break;
+                diff |= __ballot(num[s] > Rn * den[s]) ^ mask[s];
+            }
+            if (jw > J) {
+                bool t = false;
+                for (int s = J; s < jw; ++s) {
+                    const int64_t e = base + 64 * s + lane;
+                    const T nn = rho[i3[e]] * v3[e];
+                    const T dd = d3[e];
+                    t = t || ((nn > Rn * dd) != (nn > R * dd));
+                }
+                diff |= __ballot(t);
+            }
+            return diff;
+        };
+        // Dinkelbach as in process_tiles (same readings, same cycle rule)
+        T R = Bc.R0, N, Dn;
+        full(R, N, Dn);
+        T Rs = N > T(0) ? ratio(N, vt0 + Dn) : T(0);
+        T pR = R, pN = N, pD = Dn, pRs = Rs;
+        unsigned long long diff = 0ull;
+        for (int round = 0; round <= kGroup * jw + 1; ++round) {
+            diff = changed(R, Rs);
+            if (diff == 0ull) break;
+            pR = R;
+            pN = N;
+            pD = Dn;
+            pRs = Rs;
+            R = Rs;
+            full(R, N, Dn);
+            Rs = N > T(0) ? ratio(N, vt0 + Dn) : T(0);
+        }
+        if (diff != 0ull) {
+            const unsigned long long now = changed(R, Rs);
+            const bool cycling = ((now >> (threadIdx.x & 56)) & 0xFFull) != 0ull;
+            if (cycling && pRs > Rs) {
+                R = pR;
+                N = pN;
+                Dn = pD;
+                Rs = pRs;
+            }
+        }
+        const T Rstar = Rs;
+        const T lamD = ratio(Bc.lam, vt0 + Dn) * (T)a.fx_scale;
+#pragma unroll
+        for (int s = 0; s < J; ++s) {
+            if (s >= js) break;
+            if (num[s] > R * den[s]) {
+                const unsigned long long qv = quantum(lamD, Rc.v[s]);
+                const int32_t j = Rc.id[s];
+                if (j < H)
+                    atomicAdd(&bins[j], qv);
+                else
+                    atomicAdd(&a.S_fx[j], qv);
+            }
+        }
+        for (int s = J; s < jw; ++s) {
+            const int64_t e = base + 64 * s + lane;
+            const T x = v3[e];
+            const int32_t j = i3[e];
+            if (rho[j] * x > R * d3[e]) {
+                const unsigned long long qq = quantum(lamD, x);
+                if (j < H)
+                    atomicAdd(&bins[j], qq);
+                else
+                    atomicAdd(&a.S_fx[j], qq);
+            }
+        }
+        if ((lane & (kGroup - 1)) == 0 && Bc.live) {
+            const int64_t p = (tile * (kSegsPerTile / kGroup) + wv) * kGroup + q;
+            zacc += (double)Bc.lam * (double)Rstar;
+            ((T*)a.Rwarm)[p] = Rstar;
+            if (a.seg_R) ((T*)a.seg_R)[a.perm[p]] = Rstar;
+        }
+        Bc = B1;
+        Rc = R1;
+        B1 = B2;
+        if (TOUCH) B2 = B3;
+    }
+    if (TOUCH && sink == 0x9E3779B9u && a.L < 0) a.zpart[0] = 0.0;   // keeps the touches
 }
 
 }  // namespace seg
