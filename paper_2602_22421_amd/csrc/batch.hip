@@ -99,14 +99,18 @@ __device__ __forceinline__ int current(const DevState* st) { return st[0].t >= s
 
 __global__ void k_reset_counter(unsigned* counter) { *counter = 0u; }
 
-template <typename T, int J, int DEPTH>
+// MODE 0: prices gathered from global memory; 1: the item's instance prices
+// copied into LDS behind the largest instance's bins (Hmax), then gathered
+// there; 2: as 1 over the slot-major copies.
+template <typename T, int J, int DEPTH, int MODE>
 __global__ void __launch_bounds__(kSegThreads)
 k_bsegments(const BInst* inst, const BItem* items, int nitems, unsigned* counter,
-            unsigned long long* part_S, double* zpart)
+            unsigned long long* part_S, double* zpart, int Hmax)
 {
     extern __shared__ unsigned long long bins[];
     __shared__ double zsh[kSegThreads / 64];
     __shared__ int s_item;
+    T* lprice = (T*)(bins + Hmax);
     for (;;) {
         __syncthreads();
         if (threadIdx.x == 0) s_item = (int)atomicAdd(counter, 1u);
@@ -120,9 +124,15 @@ k_bsegments(const BInst* inst, const BItem* items, int nitems, unsigned* counter
         const SegArgs a = I->seg;
         const int H = a.H;
         for (int j = threadIdx.x; j < H; j += kSegThreads) bins[j] = 0ull;
+        if (MODE > 0)
+            for (int64_t j = threadIdx.x; j < a.n; j += kSegThreads) lprice[j] = ((const T*)a.rho)[j];
         __syncthreads();
         double zacc = 0.0;
-        seg::process_tiles<T, J, DEPTH>(a, w.t0, w.t1, 1, bins, seg::FlatPrices<T>{(const T*)a.rho}, zacc);
+        const seg::FlatPrices<T> pr{MODE > 0 ? (const T*)lprice : (const T*)a.rho};
+        if (MODE == 2)
+            seg::process_tiles_slots<T, J, false>(a, w.t0, w.t1, 1, bins, pr, zacc);
+        else
+            seg::process_tiles<T, J, DEPTH>(a, w.t0, w.t1, 1, bins, pr, zacc);
         __syncthreads();
         unsigned long long* out = part_S + I->part_off + (size_t)(it - I->item0) * (size_t)H;
         for (int j = threadIdx.x; j < H; j += kSegThreads) out[j] = bins[j];
@@ -275,17 +285,25 @@ __global__ void __launch_bounds__(kRowThreads) k_bprices(const BInst* inst, cons
     if (i < I->n) ((T*)I->rho)[i] = ((const T*)I->r)[i] - ((const T*)I->eta)[i];
 }
 
+// Batched variants 0-6 as the single-instance ones (prices from global
+// memory); 7: ordered pipeline with the prices in LDS; 8: slot-major copies
+// with the prices in LDS (needs every handle's slot-major copy).
+constexpr int kBatchVariants = 9;
+inline bool bseg_lds_prices(int variant) { return variant >= 7; }
+
 template <typename T>
 const void* bseg_fn(int variant)
 {
     switch (variant) {
-    case 0: return (const void*)k_bsegments<T, 8, 1>;
-    case 1: return (const void*)k_bsegments<T, 6, 2>;
-    case 2: return (const void*)k_bsegments<T, 4, 2>;
-    case 3: return (const void*)k_bsegments<T, 8, 2>;
-    case 5: return (const void*)k_bsegments<T, 8, 0>;
-    case 6: return (const void*)k_bsegments<T, 7, 1>;
-    default: return (const void*)k_bsegments<T, 4, 1>;
+    case 0: return (const void*)k_bsegments<T, 8, 1, 0>;
+    case 1: return (const void*)k_bsegments<T, 6, 2, 0>;
+    case 2: return (const void*)k_bsegments<T, 4, 2, 0>;
+    case 3: return (const void*)k_bsegments<T, 8, 2, 0>;
+    case 5: return (const void*)k_bsegments<T, 8, 0, 0>;
+    case 6: return (const void*)k_bsegments<T, 7, 1, 0>;
+    case 7: return (const void*)k_bsegments<T, sizeof(T) == 4 ? 7 : 4, 3, 1>;
+    case 8: return (const void*)k_bsegments<T, sizeof(T) == 4 ? 7 : 4, 3, 2>;
+    default: return (const void*)k_bsegments<T, 4, 1, 0>;
     }
 }
 
@@ -325,6 +343,8 @@ struct cblp_batch {
     int grid = 1;
     int variant = 6;
     int Hmax = 1;
+    int64_t nmax = 1;               // most products of any instance
+    bool slots_ok = false;          // every handle has its slot-major copy
     hipStream_t stream = nullptr;    // the batch's own stream (graph capture needs one)
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -333,6 +353,12 @@ struct cblp_batch {
 };
 
 namespace {
+
+// dynamic LDS of the batched segment kernel: the largest instance's bins, then
+// (LDS-price variants) room for the largest instance's prices
+size_t bseg_lds(const cblp_batch* b, int variant);
+bool bseg_usable(const cblp_batch* b, int variant);
+
 
 void batch_release(cblp_batch* b)
 {
@@ -421,12 +447,13 @@ int enqueue_iterations(cblp_batch* b, const spfom_params* p, int64_t iters, hipS
     a.check_every = p->check_every;
     a.gamma = p->gamma;
     a.mu = p->mu;
-    const size_t lds = (size_t)b->Hmax * sizeof(unsigned long long);
+    const size_t lds = bseg_lds(b, b->variant);
     const void* segf = bseg_fn<T>(b->variant);
     for (int64_t it = 0; it < iters; ++it) {
         hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(1), 0, s, b->counter);
         void* sargs[] = {(void*)&b->d_inst, (void*)&b->d_items, (void*)&b->nitems,
-                         (void*)&b->counter, (void*)&b->part_S, (void*)&b->zpart};
+                         (void*)&b->counter, (void*)&b->part_S, (void*)&b->zpart,
+                         (void*)&b->Hmax};
         BHIP(hipLaunchKernel(segf, dim3(b->grid), dim3(kSegThreads), sargs, lds, s));
         hipLaunchKernelGGL(k_bfold<T>, dim3(b->nfold), dim3(kFoldThreads), 0, s, a);
         hipLaunchKernelGGL(k_bupdate<T>, dim3(b->nrows), dim3(kRowThreads), 0, s, a);
@@ -470,6 +497,25 @@ int leave(cblp_batch* b, hipStream_t caller)
 }
 
 // capture check_every iterations once per K; replayed by spfom_batch_solve
+size_t bseg_lds(const cblp_batch* b, int variant)
+{
+    const size_t esz = b->dtype == CBLP_F32 ? 4 : 8;
+    return (size_t)b->Hmax * 8 + (bseg_lds_prices(variant) ? (size_t)b->nmax * esz : 0);
+}
+
+// a variant can run on this batch: its data exist and one block fits a CU
+bool bseg_usable(const cblp_batch* b, int variant)
+{
+    if (variant < 0 || variant >= kBatchVariants) return false;
+    if (variant == 8 && !b->slots_ok) return false;
+    const void* f = b->dtype == CBLP_F32 ? bseg_fn<float>(variant) : bseg_fn<double>(variant);
+    const size_t lds = bseg_lds(b, variant);
+    int per_cu = 0;
+    (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, kSegThreads, lds) == hipSuccess &&
+           per_cu >= 1;
+}
+
 int ensure_graph(cblp_batch* b, const spfom_params* p)
 {
     if (b->exec && b->graph_K == p->check_every) return CBLP_OK;
@@ -522,6 +568,11 @@ int cblp_batch_create(cblp_batch_t* out, int32_t count, const cblp_t* handles, v
         Hmax = std::max<int64_t>(Hmax, h->H);
     }
     b->Hmax = (int)Hmax;
+    b->slots_ok = true;
+    for (int q = 0; q < count; ++q) {
+        b->nmax = std::max<int64_t>(b->nmax, b->hs[q]->n);
+        b->slots_ok = b->slots_ok && b->hs[q]->woff != nullptr;
+    }
     if (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming) != hipSuccess)
@@ -532,12 +583,14 @@ int cblp_batch_create(cblp_batch_t* out, int32_t count, const cblp_t* handles, v
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, b->hs[0]->device) == hipSuccess && prop.multiProcessorCount > 0)
         cus = prop.multiProcessorCount;
-    b->variant = 5;   // no cross-tile prefetch: the only spill-free batched variant
-    if (const char* ev = std::getenv("CBLP_SEG_VARIANT")) {
+    // default: slot-major copies with LDS prices when every instance has them
+    // and they fit, else the spill-free global-price variant
+    b->variant = bseg_usable(b, 8) ? 8 : bseg_usable(b, 7) ? 7 : 5;
+    if (const char* ev = std::getenv("CBLP_BATCH_VARIANT")) {
         const int x = std::atoi(ev);
-        if (x >= 0 && x < kSegVariants) b->variant = x;
+        if (x >= 0 && x < kBatchVariants && bseg_usable(b, x)) b->variant = x;
     }
-    const size_t lds = (size_t)b->Hmax * 8;
+    const size_t lds = bseg_lds(b, b->variant);
     int per_cu = 1;
     {
         const void* f = b->dtype == CBLP_F32 ? bseg_fn<float>(b->variant) : bseg_fn<double>(b->variant);
@@ -578,6 +631,11 @@ int cblp_batch_create(cblp_batch_t* out, int32_t count, const cblp_t* handles, v
         a.n = h->n;
         a.H = h->H;
         a.hp = 0;
+        a.blk = nullptr;
+        a.woff = h->woff;
+        a.idx3 = h->idx3;
+        a.v3 = h->v3;
+        a.den3 = h->den3;
         a.part_S = nullptr;
         a.S_fx = h->S_fx;
         a.fx_scale = h->fx_scale;
@@ -742,7 +800,7 @@ int cblp_batch_tune(cblp_batch_t b, void* const* etas, const void* const* tau_ve
     if ((rc = enter(b, caller))) return rc;
     if ((rc = bind(b, etas, tau_vecs, p, b->stream))) return rc;
     if ((rc = run_prices(b, b->stream))) return rc;
-    const int candidates[] = {5, 6, 0, 4};
+    const int candidates[] = {5, 6, 0, 4, 7, 8};
     double best = INFINITY;
     int best_v = b->variant;
     hipEvent_t e0, e1;
@@ -750,13 +808,8 @@ int cblp_batch_tune(cblp_batch_t b, void* const* etas, const void* const* tau_ve
     BHIP(hipEventCreate(&e1));
     const int keep = b->variant;
     for (int v : candidates) {
+        if (!bseg_usable(b, v)) continue;
         b->variant = v;
-        const void* f = b->dtype == CBLP_F32 ? bseg_fn<float>(v) : bseg_fn<double>(v);
-        int per_cu = 0;
-        (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, b->Hmax * 8);
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, kSegThreads, (size_t)b->Hmax * 8) !=
-                hipSuccess || per_cu < 1)
-            continue;
         if ((rc = run_iters(b, p, 1, b->stream))) break;   // warm the variant
         BHIP(hipEventRecord(e0, b->stream));
         if ((rc = run_iters(b, p, iters, b->stream))) break;
