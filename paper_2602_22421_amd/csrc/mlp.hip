@@ -208,6 +208,48 @@ __global__ void __launch_bounds__(256) k_gemm(const unsigned short* A, const uns
     }
 }
 
+// Row-block product for operands whose k index is contiguous in memory:
+// C(m, n) = sum_k A[m lda + k] Bt[n ldb + k] over all N = 256 columns.  A
+// block of four waves owns 16 rows; each wave owns 64 columns (four 16 x 16
+// tiles) and reuses its A fragment, one 8-byte load per k step, for the four
+// products.  EPI as k_gemm.
+template <int EPI>
+__global__ void __launch_bounds__(256) k_gemm_rows(const unsigned short* A, const unsigned short* Bt,
+                                                   float* C, int N, int K, int lda, int ldb,
+                                                   const float* bias, float* hout)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int m0 = blockIdx.x * 16, n0 = wave * 64;
+    const int r = lane & 15, kq = (lane >> 4) * 4;
+    v4f acc[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) acc[t] = (v4f){0.0f, 0.0f, 0.0f, 0.0f};
+    const unsigned short* pa = A + (size_t)(m0 + r) * lda + kq;
+    const unsigned short* pb = Bt + (size_t)(n0 + r) * ldb + kq;
+    for (int k0 = 0; k0 < K; k0 += 16) {
+        const v4s a = *(const v4s*)(pa + k0);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const v4s b = *(const v4s*)(pb + (size_t)16 * t * ldb + k0);
+            acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[t], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int n = n0 + 16 * t + r;
+            const size_t o = (size_t)(m0 + kq + i) * N + n;
+            if (EPI == 0) {
+                C[o] = acc[t][i];
+            } else {
+                const float z = acc[t][i] + bias[n];
+                C[o] = z;
+                hout[o] = gelu(z);
+            }
+        }
+}
+
 // y = h2 . w3 + b3, one wave per row
 __global__ void __launch_bounds__(256) k_l3_fwd(const float* h2, const float* P, int64_t rpad,
                                                 float* y)
@@ -301,10 +343,13 @@ __global__ void k_adam(float* P, const float* G, float* M, float* V, int64_t n, 
     P[i] -= lr * (m / c1) / (sqrtf(v / c2) + eps);
 }
 
-__global__ void k_round_bf16(const float* P, unsigned short* out, int64_t n)
+// BF16 copies of W2 [256 x 256]: as stored (row i = input unit i) and transposed
+__global__ void k_round_w2(const float* W2, unsigned short* out, unsigned short* outT)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) out[i] = f2bf(P[i]);
+    const int i = blockIdx.x, u = threadIdx.x;
+    const unsigned short x = f2bf(W2[i * HID + u]);
+    out[i * HID + u] = x;
+    outT[u * HID + i] = x;
 }
 
 template <typename T>
@@ -366,6 +411,7 @@ struct wsnet {
     float* M = nullptr;            // Adam moments
     float* V = nullptr;
     unsigned short* W2b = nullptr; // BF16 copy of W2
+    unsigned short* W2t = nullptr; // BF16 copy of W2 transposed
     int64_t step = 0;
     int64_t cap = 0;               // padded rows the scratch holds
     float *z1 = nullptr, *z2 = nullptr, *h2 = nullptr, *y = nullptr, *dy = nullptr;
@@ -403,7 +449,7 @@ void net_release(wsnet* w)
 {
     if (!w) return;
     net_free_scratch(w);
-    void* ptrs[] = {w->P, w->G, w->M, w->V, w->W2b};
+    void* ptrs[] = {w->P, w->G, w->M, w->V, w->W2b, w->W2t};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     if (w->pinned) (void)hipHostFree(w->pinned);
@@ -451,8 +497,9 @@ int forward(wsnet* w, int64_t rows, int64_t rpad, hipStream_t s)
 {
     hipLaunchKernelGGL(k_l1_fwd, dim3((unsigned)rpad), dim3(HID), 0, s, w->X, rows, w->P, w->z1,
                        w->h1b);
-    hipLaunchKernelGGL((k_gemm<false, false, 1>), dim3(HID / 64, (unsigned)(rpad / 16)), dim3(256),
-                       0, s, w->h1b, w->W2b, w->z2, HID, HID, HID, HID, w->P + OFF_B2, w->h2);
+    // Z2 = H1 W2: B(k, n) = W2[k][n] = W2t[n][k], contiguous in k
+    hipLaunchKernelGGL(k_gemm_rows<1>, dim3((unsigned)(rpad / 16)), dim3(256), 0, s, w->h1b,
+                       w->W2t, w->z2, HID, HID, HID, HID, w->P + OFF_B2, w->h2);
     hipLaunchKernelGGL(k_l3_fwd, dim3((unsigned)((rpad + 3) / 4)), dim3(256), 0, s, w->h2, w->P,
                        rpad, w->y);
     MHIP(hipGetLastError());
@@ -483,8 +530,9 @@ int backward(wsnet* w, const float* Y, int64_t rows, int64_t rpad, double* loss,
     // dW2 = H1^T dZ2 (K = rows), dH1 = dZ2 W2^T
     hipLaunchKernelGGL((k_gemm<true, false, 0>), dim3(HID / 64, HID / 16), dim3(256), 0, s, w->h1b,
                        w->dz2b, w->G + OFF_W2, HID, (int)rpad, HID, HID, nullptr, nullptr);
-    hipLaunchKernelGGL((k_gemm<false, true, 0>), dim3(HID / 64, (unsigned)(rpad / 16)), dim3(256), 0,
-                       s, w->dz2b, w->W2b, w->dh1, HID, HID, HID, HID, nullptr, nullptr);
+    // dH1 = dZ2 W2^T: B(k, n) = W2[n][k], contiguous in k
+    hipLaunchKernelGGL(k_gemm_rows<0>, dim3((unsigned)(rpad / 16)), dim3(256), 0, s, w->dz2b,
+                       w->W2b, w->dh1, HID, HID, HID, HID, nullptr, nullptr);
     hipLaunchKernelGGL(k_l1_bwd, dim3((unsigned)rpad), dim3(HID), 0, s, w->dh1, w->z1, w->dz1);
     MHIP(hipGetLastError());
     if ((rc = colsum(w, w->h2, HID, rpad, HID, w->dy, 1, w->G + OFF_W3, s))) return rc;
@@ -513,8 +561,7 @@ int adam(wsnet* w, float lr, hipStream_t s)
     const float c1 = 1.0f - std::pow(b1, (float)w->step), c2 = 1.0f - std::pow(b2, (float)w->step);
     hipLaunchKernelGGL(k_adam, dim3((unsigned)((NPARAM + 255) / 256)), dim3(256), 0, s, w->P, w->G,
                        w->M, w->V, NPARAM, lr, b1, b2, 1e-8f, c1, c2);
-    hipLaunchKernelGGL(k_round_bf16, dim3((HID * HID + 255) / 256), dim3(256), 0, s, w->P + OFF_W2,
-                       w->W2b, (int64_t)HID * HID);
+    hipLaunchKernelGGL(k_round_w2, dim3(HID), dim3(HID), 0, s, w->P + OFF_W2, w->W2b, w->W2t);
     MHIP(hipGetLastError());
     return CBLP_OK;
 }
@@ -602,7 +649,8 @@ int wsnet_create(wsnet_t* out, uint64_t seed, void* stream)
     int rc;
     if ((rc = malloc_d(&w->P, NPARAM * 4)) || (rc = malloc_d(&w->G, NPARAM * 4)) ||
         (rc = malloc_d(&w->M, NPARAM * 4)) || (rc = malloc_d(&w->V, NPARAM * 4)) ||
-        (rc = malloc_d(&w->W2b, (size_t)HID * HID * 2))) {
+        (rc = malloc_d(&w->W2b, (size_t)HID * HID * 2)) ||
+        (rc = malloc_d(&w->W2t, (size_t)HID * HID * 2))) {
         net_release(w);
         return rc;
     }
@@ -624,8 +672,7 @@ int wsnet_create(wsnet_t* out, uint64_t seed, void* stream)
         net_release(w);
         return mfail(CBLP_EHIP, "initialising the network failed");
     }
-    hipLaunchKernelGGL(k_round_bf16, dim3((HID * HID + 255) / 256), dim3(256), 0, s, w->P + OFF_W2,
-                       w->W2b, (int64_t)HID * HID);
+    hipLaunchKernelGGL(k_round_w2, dim3(HID), dim3(HID), 0, s, w->P + OFF_W2, w->W2b, w->W2t);
     if (hipGetLastError() != hipSuccess || hipStreamSynchronize(s) != hipSuccess) {
         net_release(w);
         return mfail(CBLP_EHIP, "initialising the network failed");
@@ -643,8 +690,7 @@ int wsnet_params(wsnet_t w, float* get, const float* set, void* stream)
     hipStream_t s = (hipStream_t)stream;
     if (set) {
         MHIP(hipMemcpyAsync(w->P, set, NPARAM * 4, hipMemcpyHostToDevice, s));
-        hipLaunchKernelGGL(k_round_bf16, dim3((HID * HID + 255) / 256), dim3(256), 0, s,
-                           w->P + OFF_W2, w->W2b, (int64_t)HID * HID);
+        hipLaunchKernelGGL(k_round_w2, dim3(HID), dim3(HID), 0, s, w->P + OFF_W2, w->W2b, w->W2t);
         MHIP(hipGetLastError());
         w->step = 0;
         MHIP(hipMemsetAsync(w->M, 0, NPARAM * 4, s));
