@@ -215,14 +215,10 @@ def warmstart_bench(args):
     torch.cuda.synchronize()
     fwd_s = ev[0].elapsed_time(ev[1]) / 5e3
     ep_s = ev[2].elapsed_time(ev[3]) / 1e3
-    # the forward keeps the activations backward needs: X in, z1 and z2 and h2
-    # (FP32) and h1 (BF16) out, h1 read back by the product, y out
-    act_bytes = rows * (4 * 4 + 256 * (4 + 2 + 4 + 4 + 2) + 4)
+    # inference (wsnet_forward) is one fused kernel: 16 B in and 4 B out per row
     mlp = {"rows": rows, "forward_ms": fwd_s * 1e3,
            "forward_tflops": flops_fwd / fwd_s / 1e12,
            "forward_frac_bf16_peak": flops_fwd / fwd_s / BF16_PEAK,
-           "forward_activation_bytes": act_bytes,
-           "forward_frac_hbm": act_bytes / fwd_s / HBM_PEAK,
            "train_epoch_ms": ep_s * 1e3,
            "train_tflops": 3.0 * flops_fwd / ep_s / 1e12,
            "train_frac_bf16_peak": 3.0 * flops_fwd / ep_s / BF16_PEAK}

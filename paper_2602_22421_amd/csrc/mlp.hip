@@ -250,6 +250,88 @@ __global__ void __launch_bounds__(256) k_gemm_rows(const unsigned short* A, cons
         }
 }
 
+// Fused inference: y for 64 rows per block of four waves with no activation
+// leaving the chip.  h1 = GELU(x W1 + b1) is formed in LDS as BF16 (same
+// operations as k_l1_fwd); each wave multiplies the four 16-row tiles by its
+// 64 columns of W2 on the matrix cores, loading each B fragment once for the
+// four tiles; then b2, GELU and the dot with BF16(w3) over its columns; the
+// four waves' partial sums are added in wave order.
+constexpr int kInferRows = 64;
+
+__global__ void __launch_bounds__(256) k_mlp_infer(const float* X, int64_t rows, const float* P,
+                                                   const unsigned short* W2t, float* y)
+{
+    constexpr int RT = kInferRows / 16;
+    __shared__ __attribute__((aligned(16))) unsigned short h1[kInferRows * HID];
+    __shared__ float part[4][kInferRows];
+    const int tid = threadIdx.x;
+    const int64_t m0 = (int64_t)blockIdx.x * kInferRows;
+    {
+        const int u = tid;
+        const float b1 = P[OFF_B1 + u];
+        float w1[IN];
+#pragma unroll
+        for (int k = 0; k < IN; ++k) w1[k] = bfr(P[OFF_W1 + k * HID + u]);
+        for (int r = 0; r < kInferRows; ++r) {
+            const int64_t row = m0 + r;
+            float v = 0.0f;
+            if (row < rows) {
+                float z = b1;
+#pragma unroll
+                for (int k = 0; k < IN; ++k) z += X[row * IN + k] * w1[k];
+                v = gelu(z);
+            }
+            h1[r * HID + u] = f2bf(v);
+        }
+    }
+    __syncthreads();
+    const int lane = tid & 63, wave = tid >> 6;
+    const int n0 = wave * 64;
+    const int r = lane & 15, kq = (lane >> 4) * 4;
+    v4f acc[RT][4];
+#pragma unroll
+    for (int m = 0; m < RT; ++m)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) acc[m][t] = (v4f){0.0f, 0.0f, 0.0f, 0.0f};
+    const unsigned short* pb = W2t + (size_t)(n0 + r) * HID + kq;
+    for (int k0 = 0; k0 < HID; k0 += 16) {
+        v4s bfr4[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) bfr4[t] = *(const v4s*)(pb + (size_t)16 * t * HID + k0);
+#pragma unroll
+        for (int m = 0; m < RT; ++m) {
+            const v4s a = *(const v4s*)(h1 + (16 * m + r) * HID + k0 + kq);
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+                acc[m][t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bfr4[t], acc[m][t], 0, 0, 0);
+        }
+    }
+    float b2[4], w3[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        b2[t] = P[OFF_B2 + n0 + 16 * t + r];
+        w3[t] = bfr(P[OFF_W3 + n0 + 16 * t + r]);
+    }
+#pragma unroll
+    for (int m = 0; m < RT; ++m) {
+        float py[4] = {0.0f, 0.0f, 0.0f, 0.0f};   // rows 16 m + kq + i, this lane's columns
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) py[i] += gelu(acc[m][t][i] + b2[t]) * w3[t];
+        // sum over the 16 lanes of each row group (same kq)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            for (int o = 1; o < 16; o <<= 1) py[i] += __shfl_xor(py[i], o, 64);
+        if (r == 0)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) part[wave][16 * m + kq + i] = py[i];
+    }
+    __syncthreads();
+    if (tid < kInferRows && m0 + tid < rows)
+        y[m0 + tid] = ((part[0][tid] + part[1][tid]) + (part[2][tid] + part[3][tid])) + P[OFF_B3];
+}
+
 // y = h2 . w3 + b3, one wave per row
 __global__ void __launch_bounds__(256) k_l3_fwd(const float* h2, const float* P, int64_t rpad,
                                                 float* y)
@@ -715,12 +797,10 @@ int wsnet_forward(wsnet_t w, const float* X, int64_t rows, float* y, void* strea
     if (!w || !X || !y || rows < 0) return mfail(CBLP_EINVAL, "NULL argument or rows < 0");
     if (rows == 0) return CBLP_OK;
     hipStream_t s = (hipStream_t)stream;
-    int rc;
-    if ((rc = ensure_scratch(w, rows))) return rc;
-    const int64_t rpad = pad16(rows);
-    if ((rc = load_rows(w, X, rows, rpad, s))) return rc;
-    if ((rc = forward(w, rows, rpad, s))) return rc;
-    MHIP(hipMemcpyAsync(y, w->y, (size_t)rows * 4, hipMemcpyDeviceToDevice, s));
+    hipLaunchKernelGGL(k_mlp_infer, dim3((unsigned)((rows + kInferRows - 1) / kInferRows)),
+                       dim3(256), 0, s, X, rows,
+                       w->P, w->W2t, y);
+    MHIP(hipGetLastError());
     return CBLP_OK;
 }
 
@@ -833,11 +913,11 @@ int wsnet_predict(wsnet_t w, cblp_t h, void* eta, void* stream)
     hipStream_t s = (hipStream_t)stream;
     int rc;
     if ((rc = ensure_scratch(w, h->n))) return rc;
-    const int64_t rpad = pad16(h->n);
     rc = h->dtype == CBLP_F32 ? features_impl<float>(h, w->X, s) : features_impl<double>(h, w->X, s);
     if (rc) return rc;
-    if (rpad > h->n) MHIP(hipMemsetAsync(w->X + h->n * IN, 0, (size_t)(rpad - h->n) * IN * 4, s));
-    if ((rc = forward(w, h->n, rpad, s))) return rc;
+    hipLaunchKernelGGL(k_mlp_infer, dim3((unsigned)((h->n + kInferRows - 1) / kInferRows)),
+                       dim3(256), 0, s, w->X, h->n,
+                       w->P, w->W2t, w->y);
     const unsigned g = (unsigned)((h->n + 255) / 256);
     if (h->dtype == CBLP_F32)
         hipLaunchKernelGGL(k_eta_from_y<float>, dim3(g), dim3(256), 0, s, w->y, (const float*)h->r,
