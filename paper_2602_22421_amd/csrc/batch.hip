@@ -162,18 +162,23 @@ __global__ void __launch_bounds__(kFoldThreads) k_bfold(BArgs b)
     const int H = I->H;
     const int nit = I->item1 - I->item0;
     unsigned long long a0 = 0ull, a1 = 0ull, a2 = 0ull, a3 = 0ull;
+    unsigned long long a4 = 0ull, a5 = 0ull, a6 = 0ull, a7 = 0ull;
     if (j < I->n && j < H) {
         const unsigned long long* P = b.part_S + I->part_off + j;
         int q = cc;
-        for (; q + 3 * kFoldChunks < nit; q += 4 * kFoldChunks) {
+        for (; q + 7 * kFoldChunks < nit; q += 8 * kFoldChunks) {
             a0 += P[(size_t)q * H];
             a1 += P[(size_t)(q + kFoldChunks) * H];
             a2 += P[(size_t)(q + 2 * kFoldChunks) * H];
             a3 += P[(size_t)(q + 3 * kFoldChunks) * H];
+            a4 += P[(size_t)(q + 4 * kFoldChunks) * H];
+            a5 += P[(size_t)(q + 5 * kFoldChunks) * H];
+            a6 += P[(size_t)(q + 6 * kFoldChunks) * H];
+            a7 += P[(size_t)(q + 7 * kFoldChunks) * H];
         }
         for (; q < nit; q += kFoldChunks) a0 += P[(size_t)q * H];
     }
-    red[cc][jj] = (a0 + a1) + (a2 + a3);
+    red[cc][jj] = ((a0 + a1) + (a2 + a3)) + ((a4 + a5) + (a6 + a7));
     const long long cnt1 = I->st[current(I->st)].cnt + 1;
     __syncthreads();
     double x[NR];

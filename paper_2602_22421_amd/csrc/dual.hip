@@ -36,21 +36,26 @@ __global__ void __launch_bounds__(kFoldThreads) k_fold(PhaseArgs a)
     const int tid = threadIdx.x;
     const int jj = tid % kFoldProducts, cc = tid / kFoldProducts;
     const int64_t j = (int64_t)blockIdx.x * kFoldProducts + jj;
-    // integer sums: four independent accumulators keep four loads in flight
+    // integer sums: eight independent accumulators keep eight loads in flight
     unsigned long long a0 = 0ull, a1 = 0ull, a2 = 0ull, a3 = 0ull;
+    unsigned long long a4 = 0ull, a5 = 0ull, a6 = 0ull, a7 = 0ull;
     if (j < a.n && j < a.H) {
         const unsigned long long* P = a.part_S + j;
         const size_t H = (size_t)a.H;
         int b = cc;
-        for (; b + 3 * kFoldChunks < a.nseg; b += 4 * kFoldChunks) {
+        for (; b + 7 * kFoldChunks < a.nseg; b += 8 * kFoldChunks) {
             a0 += P[(size_t)b * H];
             a1 += P[(size_t)(b + kFoldChunks) * H];
             a2 += P[(size_t)(b + 2 * kFoldChunks) * H];
             a3 += P[(size_t)(b + 3 * kFoldChunks) * H];
+            a4 += P[(size_t)(b + 4 * kFoldChunks) * H];
+            a5 += P[(size_t)(b + 5 * kFoldChunks) * H];
+            a6 += P[(size_t)(b + 6 * kFoldChunks) * H];
+            a7 += P[(size_t)(b + 7 * kFoldChunks) * H];
         }
         for (; b < a.nseg; b += kFoldChunks) a0 += P[(size_t)b * H];
     }
-    red[cc][jj] = (a0 + a1) + (a2 + a3);
+    red[cc][jj] = ((a0 + a1) + (a2 + a3)) + ((a4 + a5) + (a6 + a7));
     const long long cnt1 = a.mode == 0 ? a.st[a.par].cnt + 1 : 1;
     __syncthreads();
     double x[NR];
