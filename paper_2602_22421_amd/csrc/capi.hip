@@ -363,7 +363,8 @@ int create_impl(cblp_instance* h, hipStream_t s)
     h->seg_variant = sizeof(T) == 4 ? (prices_fit ? kSegSlots + 1 : 6) : kSegSlots + 3;
     if (const char* ev = std::getenv("CBLP_SEG_VARIANT")) {
         const int x = std::atoi(ev);
-        if (x >= 0 && x < kSegVariants && (!seg_lds_prices(x) || prices_fit)) h->seg_variant = x;
+        if (x >= 0 && x < kSegVariants && (!seg_lds_prices(x) || prices_fit || x == kSegSplit))
+            h->seg_variant = x;
     }
     h->hp = h->seg_variant == kSegSplit ? (int)std::min<int64_t>(h->n, kSplitPrices) : 0;
     const int64_t price_bytes = h->seg_variant == kSegSplit ? (int64_t)h->hp * (int64_t)sizeof(T)

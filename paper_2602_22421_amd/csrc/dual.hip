@@ -73,6 +73,20 @@ __global__ void __launch_bounds__(kFoldThreads) k_fold(PhaseArgs a)
     if (tid == 0) store_part(a.bpart + (size_t)blockIdx.x * 8, x);
 }
 
+// u_i = sum_j a_ij S_j, one wave per resource row: lanes stride over the row's
+// products, then a fixed shuffle tree (the result does not depend on timing)
+__global__ void __launch_bounds__(256) k_rows_sum(PhaseArgs a)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (i >= a.m) return;
+    double u = 0.0;
+    for (int64_t q = a.at_ptr[i] + lane; q < a.at_ptr[i + 1]; q += 64)
+        u += a.at_val[q] * a.S_d[a.at_prod[q]];
+    for (int o = 32; o > 0; o >>= 1) u += __shfl_down(u, o, 64);
+    if (lane == 0) a.u_d[i] = u;
+}
+
 template <typename T>
 __global__ void __launch_bounds__(kRowThreads) k_rows(PhaseArgs a)
 {
@@ -81,12 +95,7 @@ __global__ void __launch_bounds__(kRowThreads) k_rows(PhaseArgs a)
     const long long cnt1 = a.mode == 0 ? a.st[a.par].cnt + 1 : 1;
     double x[NR];
     clear(x);
-    if (i < a.m) {
-        double u = 0.0;
-        for (int64_t q = a.at_ptr[i]; q < a.at_ptr[i + 1]; ++q)
-            u += a.at_val[q] * a.S_d[a.at_prod[q]];
-        row_work<T>(a, i, u, cnt1, x);
-    }
+    if (i < a.m) row_work<T>(a, i, a.u_d[i], cnt1, x);
     block_reduce(x, sh);
     if (threadIdx.x == 0) store_part(a.bpart2 + (size_t)blockIdx.x * 8, x);
 }
@@ -201,6 +210,7 @@ hipError_t launch_phase(const PhaseArgs& a, bool identity, hipStream_t s)
         hipLaunchKernelGGL((k_update<T, true>), dim3(row_grid), dim3(kRowThreads), 0, s, a);
     } else {
         hipLaunchKernelGGL((k_fold<T, false>), dim3(fold_grid), dim3(kFoldThreads), 0, s, a);
+        hipLaunchKernelGGL(k_rows_sum, dim3((unsigned)((a.m + 3) / 4)), dim3(256), 0, s, a);
         hipLaunchKernelGGL(k_rows<T>, dim3(row_grid), dim3(kRowThreads), 0, s, a);
         hipLaunchKernelGGL((k_update<T, false>), dim3(row_grid), dim3(kRowThreads), 0, s, a);
         if (a.mode == 0) {
