@@ -360,7 +360,7 @@ int create_impl(cblp_instance* h, hipStream_t s)
     // kernel variant and bin count may be overridden for tuning runs.  The
     // prices go to LDS when they take at most half of it.
     const bool prices_fit = (int64_t)h->n * (int64_t)sizeof(T) * 2 <= (int64_t)lds_block;
-    h->seg_variant = sizeof(T) == 4 ? (prices_fit ? kSegSlots + 1 : 6) : kSegSlots + 3;
+    h->seg_variant = sizeof(T) == 4 ? (prices_fit ? kSegSlots + 1 : kSegSplit) : kSegSlots + 3;
     if (const char* ev = std::getenv("CBLP_SEG_VARIANT")) {
         const int x = std::atoi(ev);
         if (x >= 0 && x < kSegVariants && (!seg_lds_prices(x) || prices_fit || x == kSegSplit))

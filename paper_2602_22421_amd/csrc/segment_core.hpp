@@ -38,6 +38,11 @@
 namespace cblp {
 namespace seg {
 
+// Every product and sum below is rounded as written (no contraction into
+// fused multiply-adds except the explicit ones), so all kernel variants - and
+// register slots and streamed slots within one - give the same bits.
+#pragma clang fp contract(off)
+
 // 8-lane sum with DPP inside half rows: mirror, then swap pairs, then swap
 // neighbours.  Every lane of the group ends with the same bits: each step
 // adds two values that the other lane of the pair adds in the opposite
@@ -320,10 +325,9 @@ __device__ __forceinline__ void process_tiles(const SegArgs& a, int64_t tile, in
                 for (int q = kGroup * J + g; q < k; q += kGroup) {
                     const T nn = rho[idx[b + q]] * vg[b + q];
                     const T dd = dg[b + q];
-                    if (nn > R * dd) {
-                        n_ += nn;
-                        d_ += dd;
-                    }
+                    const T w = nn > R * dd ? T(1) : T(0);
+                    n_ = fmadd(w, nn, n_);
+                    d_ = fmadd(w, dd, d_);
                 }
                 N = group_sum(n_);
                 Dn = group_sum(d_);
@@ -587,10 +591,9 @@ __device__ __forceinline__ void process_tiles_slots(const SegArgs& a, int64_t ti
                 const int64_t e = base + 64 * s + lane;
                 const T nn = rho[i3[e]] * v3[e];
                 const T dd = d3[e];
-                if (nn > R * dd) {
-                    n_ += nn;
-                    d_ += dd;
-                }
+                const T w = nn > R * dd ? T(1) : T(0);
+                n_ = fmadd(w, nn, n_);
+                d_ = fmadd(w, dd, d_);
             }
             N = group_sum(n_);
             Dn = group_sum(d_);
