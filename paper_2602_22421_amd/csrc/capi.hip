@@ -158,7 +158,7 @@ int run_segments(cblp_instance* h, void* seg_R, hipStream_t s)
     a.n = h->n;
     a.H = h->H;
     a.hp = h->hp;
-    a.part_S = h->part_S;
+    a.part_S = h->flush_atomic ? nullptr : h->part_S;
     a.S_fx = h->S_fx;
     a.fx_scale = h->fx_scale;
     a.zpart = h->zpart;
@@ -192,7 +192,7 @@ int run_phase(cblp_instance* h, void* eta, const spfom_params* p, int mode, doub
     a.zpart = h->zpart;
     a.nz = h->seg_grid;
     a.part_S = h->part_S;
-    a.nseg = h->seg_grid;
+    a.nseg = h->flush_atomic ? 0 : h->seg_grid;   // no partial rows to fold
     a.H = h->H;
     a.S_fx = h->S_fx;
     a.inv_fx = 1.0 / h->fx_scale;
@@ -211,7 +211,8 @@ int run_phase(cblp_instance* h, void* eta, const spfom_params* p, int mode, doub
     a.sum_u = h->sum_u;
     a.bpart = h->bpart;
     a.bpart2 = h->bpart2;
-    a.fold_blocks = h->fold_blocks;
+    // without partial rows the fold takes 256 products per block
+    a.fold_blocks = h->flush_atomic ? (int)((h->n + 255) / 256) : h->fold_blocks;
     a.st = h->st;
     a.par = (int)(h->t & 1);
     a.row = row;
@@ -371,6 +372,8 @@ int create_impl(cblp_instance* h, hipStream_t s)
                                 : seg_lds_prices(h->seg_variant) ? h->n * (int64_t)sizeof(T) : 0;
     const int64_t lds_bins = ((int64_t)lds_block - 1024 - price_bytes) / 8;
     h->H = (int)std::max<int64_t>(1, std::min<int64_t>({h->n, (int64_t)kMaxBins, lds_bins}));
+    // CBLP_FLUSH=rows: per-block partial rows of the bins, folded in block order
+    if (const char* ef = std::getenv("CBLP_FLUSH")) h->flush_atomic = std::string(ef) != "rows";
     if (const char* eb = std::getenv("CBLP_SEG_BINS")) {
         const long x = std::atol(eb);
         if (x >= 1 && x <= h->H) h->H = (int)x;
@@ -497,7 +500,9 @@ int create_impl(cblp_instance* h, hipStream_t s)
         }
         HIP_TRY(hipStreamSynchronize(s));   // the host vectors die here
     }
-    if ((rc = dalloc(&h->part_S, (size_t)h->seg_grid * std::max(h->H, 1) * 8))) return rc;
+    if (!h->flush_atomic &&
+        (rc = dalloc(&h->part_S, (size_t)h->seg_grid * std::max(h->H, 1) * 8)))
+        return rc;
     if ((rc = dalloc(&h->zpart, (size_t)h->seg_grid * 8))) return rc;
 
     // fixed-point scale of the sales sums from the arrival rates

@@ -1,9 +1,11 @@
 // Dual phase of one iteration: sales totals, FP64 reductions, certified
 // bound and the projected dual step (eq. 16).
 //
-//   k_fold    per product: S_j = (sum of the per-block LDS bin rows + the
-//             global tail accumulator) / 2^bits and P = sum r_j S_j; with
-//             A = I also the per-row work below
+//   k_fold    per product: S_j = (global 64-bit accumulator, which the
+//             segment blocks fed by integer atomics) / 2^bits and
+//             P = sum r_j S_j; with A = I also the per-row work below
+//             (k_fold_lite); the partial-row build instead sums the
+//             per-block LDS bin rows in block order (k_fold)
 //   k_rows    (general A) per resource: u_i = sum_j a_ij S_j through A^T
 //   per row   g_i = u_i - c_i; c.eta, sum (g)^+, the Polyak norm
 //             sum tau_i g_i^2 (g zeroed where the projection binds), ||eta||^2
@@ -27,6 +29,30 @@ namespace cblp {
 namespace {
 
 using namespace dual;
+
+// Fold when the segment blocks added their bins to S_fx themselves (no
+// partial rows): one product per thread, 256 threads per block.
+constexpr int kFoldLite = 256;
+
+template <typename T, bool IDENT>
+__global__ void __launch_bounds__(kFoldLite) k_fold_lite(PhaseArgs a)
+{
+    __shared__ double sh[NR * 16];
+    const int64_t j = (int64_t)blockIdx.x * kFoldLite + threadIdx.x;
+    const long long cnt1 = a.mode == 0 ? a.st[a.par].cnt + 1 : 1;
+    double x[NR];
+    clear(x);
+    if (j < a.n) {
+        const unsigned long long tot = a.S_fx[j];
+        a.S_fx[j] = 0ull;
+        const double sj = (double)(long long)tot * a.inv_fx;
+        a.S_d[j] = sj;
+        x[R_P] = (double)((const T*)a.r)[j] * sj;
+        if (IDENT) row_work<T>(a, j, sj, cnt1, x);
+    }
+    block_reduce(x, sh);
+    if (threadIdx.x == 0) store_part(a.bpart + (size_t)blockIdx.x * 8, x);
+}
 
 template <typename T, bool IDENT>
 __global__ void __launch_bounds__(kFoldThreads) k_fold(PhaseArgs a)
@@ -205,11 +231,18 @@ hipError_t launch_phase(const PhaseArgs& a, bool identity, hipStream_t s)
 {
     const unsigned fold_grid = (unsigned)a.fold_blocks;
     const unsigned row_grid = (unsigned)((a.m + kRowThreads - 1) / kRowThreads);
+    const bool lite = a.nseg == 0;   // bins already in S_fx: fold_blocks counts kFoldLite products
     if (identity) {
-        hipLaunchKernelGGL((k_fold<T, true>), dim3(fold_grid), dim3(kFoldThreads), 0, s, a);
+        if (lite)
+            hipLaunchKernelGGL((k_fold_lite<T, true>), dim3(fold_grid), dim3(kFoldLite), 0, s, a);
+        else
+            hipLaunchKernelGGL((k_fold<T, true>), dim3(fold_grid), dim3(kFoldThreads), 0, s, a);
         hipLaunchKernelGGL((k_update<T, true>), dim3(row_grid), dim3(kRowThreads), 0, s, a);
     } else {
-        hipLaunchKernelGGL((k_fold<T, false>), dim3(fold_grid), dim3(kFoldThreads), 0, s, a);
+        if (lite)
+            hipLaunchKernelGGL((k_fold_lite<T, false>), dim3(fold_grid), dim3(kFoldLite), 0, s, a);
+        else
+            hipLaunchKernelGGL((k_fold<T, false>), dim3(fold_grid), dim3(kFoldThreads), 0, s, a);
         hipLaunchKernelGGL(k_rows_sum, dim3((unsigned)((a.m + 3) / 4)), dim3(256), 0, s, a);
         hipLaunchKernelGGL(k_rows<T>, dim3(row_grid), dim3(kRowThreads), 0, s, a);
         hipLaunchKernelGGL((k_update<T, false>), dim3(row_grid), dim3(kRowThreads), 0, s, a);

@@ -55,6 +55,8 @@ struct cblp_instance {
     int seg_variant = 0;
     int H = 0;
     int hp = 0;                     // split-price kernel: prices held in LDS
+    bool flush_atomic = true;       // segment blocks add their bins to S_fx by atomics
+                                    // (false: per-block partial rows folded by k_fold)
     int fold_blocks = 1;
     double fx_scale = 1.0;
     int64_t t = 0;

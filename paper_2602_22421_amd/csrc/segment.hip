@@ -6,6 +6,20 @@
 namespace cblp {
 namespace {
 
+// The block's bins go out as one partial row (folded in block order by the
+// dual phase) or, when a.part_S is null, straight into the global 64-bit
+// accumulators by atomics (integer sums: the order does not matter).
+__device__ __forceinline__ void flush_bins(const SegArgs& a, const unsigned long long* bins)
+{
+    if (a.part_S) {
+        unsigned long long* out = a.part_S + (size_t)blockIdx.x * (size_t)a.H;
+        for (int j = threadIdx.x; j < a.H; j += kSegThreads) out[j] = bins[j];
+    } else {
+        for (int j = threadIdx.x; j < a.H; j += kSegThreads)
+            if (bins[j]) atomicAdd(&a.S_fx[j], bins[j]);
+    }
+}
+
 // LDSP: copy the n prices into LDS behind the bins and gather from there
 // (random 4-byte reads that would otherwise each take a cache-line lookup in
 // the vector memory path, which the CSR stream already keeps busy).
@@ -28,8 +42,7 @@ __global__ void __launch_bounds__(kSegThreads) k_segments(SegArgs a)
     seg::process_tiles<T, J, DEPTH>(a, blockIdx.x, tiles, gridDim.x, bins, pr, zacc);
 
     __syncthreads();
-    unsigned long long* out = a.part_S + (size_t)blockIdx.x * (size_t)H;
-    for (int j = threadIdx.x; j < H; j += kSegThreads) out[j] = bins[j];
+    flush_bins(a, bins);
 
     // block partial of sum lambda R*: fixed shuffle tree, waves in order
     for (int o = 32; o > 0; o >>= 1) zacc += __shfl_down(zacc, o, 64);
@@ -62,8 +75,7 @@ __global__ void __launch_bounds__(kSegThreads) k_segments_split(SegArgs a)
     seg::process_tiles<T, J, 3>(a, blockIdx.x, tiles, gridDim.x, bins, pr, zacc);
 
     __syncthreads();
-    unsigned long long* out = a.part_S + (size_t)blockIdx.x * (size_t)H;
-    for (int j = threadIdx.x; j < H; j += kSegThreads) out[j] = bins[j];
+    flush_bins(a, bins);
     for (int o = 32; o > 0; o >>= 1) zacc += __shfl_down(zacc, o, 64);
     if ((threadIdx.x & 63) == 0) zsh[threadIdx.x >> 6] = zacc;
     __syncthreads();
@@ -95,8 +107,7 @@ __global__ void __launch_bounds__(kSegThreads) k_segments_slots(SegArgs a)
                                                                  bins, pr, zacc);
 
     __syncthreads();
-    unsigned long long* out = a.part_S + (size_t)blockIdx.x * (size_t)H;
-    for (int j = threadIdx.x; j < H; j += kSegThreads) out[j] = bins[j];
+    flush_bins(a, bins);
     for (int o = 32; o > 0; o >>= 1) zacc += __shfl_down(zacc, o, 64);
     if ((threadIdx.x & 63) == 0) zsh[threadIdx.x >> 6] = zacc;
     __syncthreads();
@@ -147,8 +158,7 @@ __global__ void __launch_bounds__(kSegThreads) k_segments_cls(SegArgs a)
     }
 
     __syncthreads();
-    unsigned long long* out = a.part_S + (size_t)blockIdx.x * (size_t)H;
-    for (int j = threadIdx.x; j < H; j += kSegThreads) out[j] = bins[j];
+    flush_bins(a, bins);
     for (int o = 32; o > 0; o >>= 1) zacc += __shfl_down(zacc, o, 64);
     if ((threadIdx.x & 63) == 0) zsh[threadIdx.x >> 6] = zacc;
     __syncthreads();

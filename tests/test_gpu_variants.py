@@ -54,3 +54,21 @@ def test_all_variants_agree(cb, dtype, monkeypatch):
         got, info = _run(cb, inst, dt, v, monkeypatch)
         for k, (a, b) in enumerate(zip(ref, got)):
             assert np.array_equal(a, b), (v, k, info)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_flush_modes_agree(cb, dtype, monkeypatch):
+    """Sales bins added to the global accumulators by integer atomics (the
+    default) and per-block partial rows folded in block order give the same
+    exact integer totals, hence identical results."""
+    dt = torch.float32 if dtype == "f32" else torch.float64
+    inst = make_instance(30000, 3000, size_lo=1, size_hi=60, zipf=1.1, cap_lo=0.2, cap_hi=0.5,
+                         seed=23).cast(np.float32 if dtype == "f32" else np.float64)
+    for v in (None, 6, 13, 17, 19, 23):
+        monkeypatch.delenv("CBLP_FLUSH", raising=False)
+        ref, _ = _run(cb, inst, dt, v, monkeypatch)
+        monkeypatch.setenv("CBLP_FLUSH", "rows")
+        got, info = _run(cb, inst, dt, v, monkeypatch)
+        for k, (a, b) in enumerate(zip(ref, got)):
+            assert np.array_equal(a, b), (v, k, info)
+    monkeypatch.delenv("CBLP_FLUSH", raising=False)
