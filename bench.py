@@ -323,6 +323,9 @@ def main():
     ap.add_argument("--ws-epochs", type=int, default=40)
     ap.add_argument("--ws-tau0", type=float, default=1e-3)
     ap.add_argument("--ws-eval-seeds", type=int, nargs="+", default=[101, 102])
+    ap.add_argument("--shuffle-products", action="store_true",
+                    help="number the products in random order (the generator numbers them by "
+                         "popularity); the library renumbers them by degree unless CBLP_RELABEL=0")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device-to-device copy: the reference kernel whose "
                          "FETCH_SIZE / WRITE_SIZE counters scale the traffic figures")
@@ -334,7 +337,8 @@ def main():
 
     import torch
     from paper_2602_22421_amd import cblp
-    from paper_2602_22421_amd.instances import CONFIG_NAMES, config_instance, step_scale
+    from paper_2602_22421_amd.instances import (CONFIG_NAMES, config_instance, shuffle_products,
+                                                step_scale)
 
     cblp.load()
     if not torch.cuda.is_available():
@@ -357,10 +361,14 @@ def main():
         return
     t0 = time.perf_counter()
     inst = config_instance(args.config)
+    workload = CONFIG_NAMES[args.config]
+    if args.shuffle_products:
+        inst = shuffle_products(inst, seed=1)[0]
+        workload += "-shuffled-ids"
     npdt = np.float32 if args.dtype == "f32" else np.float64
     dt = torch.float32 if args.dtype == "f32" else torch.float64
     inst = inst.cast(npdt)
-    log(f"generated {CONFIG_NAMES[args.config]}: L={inst.L} n={inst.n} m={inst.m} "
+    log(f"generated {workload}: L={inst.L} n={inst.n} m={inst.m} "
         f"nnz={inst.nnz} in {time.perf_counter() - t0:.1f} s")
     prob = cblp.Problem(inst, dtype=dt)
     tau = prob.tensor(step_scale(inst, 0.001))
@@ -392,7 +400,7 @@ def main():
         achieved = nbytes / seg_avg
         roof = {"bound": "hbm", "kernel": "k_segments", "achieved": achieved / 1e9,
                 "peak": HBM_PEAK / 1e9, "unit": "GB/s", "frac": achieved / HBM_PEAK,
-                "traffic": profiled_traffic(CONFIG_NAMES[args.config]) if args.dtype == "f32" else None,
+                "traffic": profiled_traffic(workload) if args.dtype == "f32" else None,
                 "bytes_per_launch": nbytes, "per_unit_bytes": per,
                 "kernel_avg_us": seg_avg * 1e6,
                 "dual_phase_avg_us": dual_ms * 1e3 / max(dual_n, 1),
@@ -412,7 +420,7 @@ def main():
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": wall * 1e3 / args.steps, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": args.dtype, "data": "synthetic",
-        "config": {"workload": CONFIG_NAMES[args.config], "L": inst.L, "n": inst.n,
+        "config": {"workload": workload, "L": inst.L, "n": inst.n,
                    "m": inst.m, "nnz": inst.nnz,
                    "iterate": args.dtype, "reductions": "f64", "step_rule": "const",
                    "dual_bound_after": st["D"]},

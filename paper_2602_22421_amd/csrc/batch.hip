@@ -57,8 +57,9 @@ struct BInst {
     int item0, item1;          // work items of this instance
     int64_t part_off;          // first entry of its LDS-bin rows in part_S
     int fold0, fold1;          // its fold blocks
-    int H;                     // LDS bins (products [0, H))
+    int H;                     // LDS bins (library products [0, H))
     int active;
+    const int32_t* pnew;       // [n] library id of caller product j; NULL: j
 };
 
 struct BItem {
@@ -159,12 +160,13 @@ __global__ void __launch_bounds__(kFoldThreads) k_bfold(BArgs b)
     const int tid = threadIdx.x;
     const int jj = tid % kFoldProducts, cc = tid / kFoldProducts;
     const int64_t j = f.j0 + jj;
+    const int64_t jq = j < I->n && I->pnew ? I->pnew[j] : j;   // library id of product j
     const int H = I->H;
     const int nit = I->item1 - I->item0;
     unsigned long long a0 = 0ull, a1 = 0ull, a2 = 0ull, a3 = 0ull;
     unsigned long long a4 = 0ull, a5 = 0ull, a6 = 0ull, a7 = 0ull;
-    if (j < I->n && j < H) {
-        const unsigned long long* P = b.part_S + I->part_off + j;
+    if (j < I->n && jq < H) {
+        const unsigned long long* P = b.part_S + I->part_off + jq;
         int q = cc;
         for (; q + 7 * kFoldChunks < nit; q += 8 * kFoldChunks) {
             a0 += P[(size_t)q * H];
@@ -184,8 +186,8 @@ __global__ void __launch_bounds__(kFoldThreads) k_bfold(BArgs b)
     double x[NR];
     clear(x);
     if (cc == 0 && j < I->n) {
-        unsigned long long tot = I->S_fx[j];
-        I->S_fx[j] = 0ull;
+        unsigned long long tot = I->S_fx[jq];
+        I->S_fx[jq] = 0ull;
         for (int q = 0; q < kFoldChunks; ++q) tot += red[q][jj];
         const double sj = (double)(long long)tot * I->inv_fx;
         I->S_d[j] = sj;
@@ -276,7 +278,7 @@ __global__ void __launch_bounds__(kRowThreads) k_bupdate(BArgs b)
         const T et = (T)e;
         eta[i] = et;
         if (restart) I->sum_u[i] = 0.0;
-        ((T*)I->rho)[i] = ((const T*)I->r)[i] - et;
+        ((T*)I->rho)[I->pnew ? I->pnew[i] : i] = ((const T*)I->r)[i] - et;
     }
 }
 
@@ -287,7 +289,8 @@ __global__ void __launch_bounds__(kRowThreads) k_bprices(const BInst* inst, cons
     const BChunk rc = rows[blockIdx.x];
     const BInst* I = inst + rc.inst;
     const int64_t i = rc.j0 + threadIdx.x;
-    if (i < I->n) ((T*)I->rho)[i] = ((const T*)I->r)[i] - ((const T*)I->eta)[i];
+    if (i < I->n)
+        ((T*)I->rho)[I->pnew ? I->pnew[i] : i] = ((const T*)I->r)[i] - ((const T*)I->eta)[i];
 }
 
 // Batched variants 0-6 as the single-instance ones (prices from global
@@ -658,6 +661,7 @@ int cblp_batch_create(cblp_batch_t* out, int32_t count, const cblp_t* handles, v
         I.sum_u = h->sum_u;
         I.H = h->H;
         I.active = 1;
+        I.pnew = h->pnew;
         const int64_t tiles = (h->L + kSegsPerTile - 1) / kSegsPerTile;
         I.item0 = (int)items.size();
         for (int64_t t0 = 0; t0 < tiles; t0 += per_item)

@@ -79,6 +79,7 @@ void release(cblp_instance* h)
 {
     if (!h) return;
     void* ptrs[] = {h->ptr2, h->idx2, h->v2, h->den2, h->vt0, h->lam2, h->Rwarm, h->v0c, h->perm,
+                    h->pnew,
                     h->seg_blk, h->woff, h->idx3, h->v3, h->den3,
                     h->rho, h->S_fx, h->part_S, h->S_d, h->u_d, h->sum_u, h->zpart,
                     h->bpart, h->bpart2, h->st, h->trace, h->at_ptr,
@@ -213,6 +214,7 @@ int run_phase(cblp_instance* h, void* eta, const spfom_params* p, int mode, doub
     a.bpart2 = h->bpart2;
     // without partial rows the fold takes 256 products per block
     a.fold_blocks = h->flush_atomic ? (int)((h->n + 255) / 256) : h->fold_blocks;
+    a.pnew = h->pnew;
     a.st = h->st;
     a.par = (int)(h->t & 1);
     a.row = row;
@@ -227,7 +229,7 @@ template <typename T>
 int iterate_impl(cblp_instance* h, void* eta, const spfom_params* p, int64_t iters,
                  bool keep_trace, hipStream_t s)
 {
-    HIP_TRY(launch_prices<T>(h->n, h->r, eta, h->a_ptr, h->a_idx, h->a_val, h->rho, s));
+    HIP_TRY(launch_prices<T>(h->n, h->r, eta, h->a_ptr, h->a_idx, h->a_val, h->pnew, h->rho, s));
     int rc;
     for (int64_t it = 0; it < iters; ++it) {
         double* row = h->trace + (keep_trace ? it : 0) * SPFOM_NTRACE;
@@ -241,7 +243,7 @@ int iterate_impl(cblp_instance* h, void* eta, const spfom_params* p, int64_t ite
 template <typename T>
 int evaluate_impl(cblp_instance* h, const void* eta, void* seg_R, hipStream_t s)
 {
-    HIP_TRY(launch_prices<T>(h->n, h->r, eta, h->a_ptr, h->a_idx, h->a_val, h->rho, s));
+    HIP_TRY(launch_prices<T>(h->n, h->r, eta, h->a_ptr, h->a_idx, h->a_val, h->pnew, h->rho, s));
     int rc = run_segments<T>(h, seg_R, s);
     if (rc) return rc;
     // evaluation leaves eta and the solver state untouched
@@ -399,6 +401,37 @@ int create_impl(cblp_instance* h, hipStream_t s)
     if (hipHostMalloc((void**)&h->pinned, SPFOM_NTRACE * sizeof(double), hipHostMallocDefault) != hipSuccess)
         return fail(CBLP_ENOMEM, "hipHostMalloc failed");
 
+    // product ids by falling degree (ties keep their order), unless the
+    // caller's numbering already is that order or CBLP_RELABEL=0
+    {
+        const char* er = std::getenv("CBLP_RELABEL");
+        if (!(er && std::string(er) == "0") && h->n > 1 && h->nnz > 0) {
+            unsigned long long* ddeg = nullptr;
+            if ((rc = dalloc(&ddeg, (size_t)h->n * 8))) return rc;
+            std::vector<unsigned long long> deg((size_t)h->n);
+            hipError_t d1 = launch_degree(h->nnz, h->idx, h->n, ddeg, s);
+            hipError_t d2 = d1 == hipSuccess ? hipMemcpyAsync(deg.data(), ddeg, (size_t)h->n * 8,
+                                                              hipMemcpyDeviceToHost, s)
+                                             : d1;
+            hipError_t d3 = hipStreamSynchronize(s);
+            (void)hipFree(ddeg);
+            if (d2 != hipSuccess || d3 != hipSuccess) return fail(CBLP_EHIP, "degree kernel failed");
+            bool sorted = true;
+            for (int64_t j = 1; j < h->n && sorted; ++j) sorted = deg[j] <= deg[j - 1];
+            if (!sorted) {
+                std::vector<int32_t> order((size_t)h->n), pnew((size_t)h->n);
+                for (int64_t j = 0; j < h->n; ++j) order[j] = (int32_t)j;
+                std::stable_sort(order.begin(), order.end(),
+                                 [&](int32_t x, int32_t y) { return deg[x] > deg[y]; });
+                for (int64_t q = 0; q < h->n; ++q) pnew[order[q]] = (int32_t)q;
+                if ((rc = dalloc(&h->pnew, (size_t)h->n * 4))) return rc;
+                HIP_TRY(hipMemcpyAsync(h->pnew, pnew.data(), (size_t)h->n * 4,
+                                       hipMemcpyHostToDevice, s));
+                HIP_TRY(hipStreamSynchronize(s));
+            }
+        }
+    }
+
     // size-sorted copy of the segments: a stable counting sort by row length
     {
         std::vector<int64_t> sp((size_t)h->L + 1);
@@ -475,7 +508,7 @@ int create_impl(cblp_instance* h, hipStream_t s)
         HIP_TRY(hipMemcpyAsync(h->perm, perm.data(), L1 * 4, hipMemcpyHostToDevice, s));
         if (h->L > 0)
             HIP_TRY(launch_relayout<T>(h->L, h->seg_ptr, h->idx, h->v, h->w, h->v0, h->lam,
-                                       h->perm, h->ptr2, h->idx2, h->v2, h->den2, h->vt0,
+                                       h->perm, h->pnew, h->ptr2, h->idx2, h->v2, h->den2, h->vt0,
                                        h->lam2, h->Rwarm, h->v0c, s));
         if (seg_slot_major(h->seg_variant)) {
             // slot-major copy: wave-tile w (positions 8w..8w+7) gets 64 entries per

@@ -33,7 +33,10 @@ struct DevState {
 
 // The segment kernel reads the library's own copy of the instance, with
 // segments reordered by consideration-set size (position p holds original
-// segment perm[p]) so that neighbouring groups have equal-length rows.
+// segment perm[p]) so that neighbouring groups have equal-length rows, and
+// products renumbered by falling degree (caller product j is pnew[j]), so
+// that the LDS bins and LDS prices of the low ids serve most entries.  The
+// price vector rho and the sales accumulators are indexed by these ids.
 struct SegArgs {
     int64_t L;
     const int64_t* ptr;            // [L+1] row pointers of the sorted layout
@@ -92,6 +95,7 @@ struct PhaseArgs {
     double* bpart;                 // [fold blocks][8]
     double* bpart2;                // [row blocks][8]
     int fold_blocks;
+    const int32_t* pnew;           // [n] library product id of caller product j; NULL: j
     DevState* st;                  // [2]: read st[par], write st[par ^ 1]
     int par;
     double* row;                   // trace row of this iteration
@@ -110,9 +114,12 @@ hipError_t launch_prepare(int64_t L, const void* lam, double* lam_part, int bloc
 template <typename T>
 hipError_t launch_relayout(int64_t L, const int64_t* seg_ptr, const int32_t* idx,
                            const void* v, const void* w, const void* v0, const void* lam,
-                           const int32_t* perm, const int64_t* ptr, int32_t* idx2, void* v2,
-                           void* den2, void* vt0, void* lam2, void* Rwarm, void* v0c,
-                           hipStream_t s);
+                           const int32_t* perm, const int32_t* pnew, const int64_t* ptr,
+                           int32_t* idx2, void* v2, void* den2, void* vt0, void* lam2, void* Rwarm,
+                           void* v0c, hipStream_t s);
+// deg[j] = number of entries with product j (zeroes deg first)
+hipError_t launch_degree(int64_t nnz, const int32_t* idx, int64_t n, unsigned long long* deg,
+                         hipStream_t s);
 template <typename T>
 hipError_t launch_relayout_slots(int64_t L, const int64_t* ptr, const int32_t* idx2,
                                  const void* v2, const void* den2, const int64_t* woff,
@@ -120,7 +127,8 @@ hipError_t launch_relayout_slots(int64_t L, const int64_t* ptr, const int32_t* i
                                  hipStream_t s);
 template <typename T>
 hipError_t launch_prices(int64_t n, const void* r, const void* eta, const int64_t* a_ptr,
-                         const int32_t* a_idx, const void* a_val, void* rho, hipStream_t s);
+                         const int32_t* a_idx, const void* a_val, const int32_t* pnew, void* rho,
+                         hipStream_t s);
 // Segment-kernel variants 0-9 gather prices from global memory; variants
 // kSegLdsPrices and up first copy the n prices into LDS after the H bins.
 // Variants kSegClassLds (prices in LDS) and kSegClassGlobal take the slot

@@ -43,8 +43,9 @@ __global__ void __launch_bounds__(kFoldLite) k_fold_lite(PhaseArgs a)
     double x[NR];
     clear(x);
     if (j < a.n) {
-        const unsigned long long tot = a.S_fx[j];
-        a.S_fx[j] = 0ull;
+        const int64_t jq = a.pnew ? a.pnew[j] : j;   // library id of product j
+        const unsigned long long tot = a.S_fx[jq];
+        a.S_fx[jq] = 0ull;
         const double sj = (double)(long long)tot * a.inv_fx;
         a.S_d[j] = sj;
         x[R_P] = (double)((const T*)a.r)[j] * sj;
@@ -62,11 +63,12 @@ __global__ void __launch_bounds__(kFoldThreads) k_fold(PhaseArgs a)
     const int tid = threadIdx.x;
     const int jj = tid % kFoldProducts, cc = tid / kFoldProducts;
     const int64_t j = (int64_t)blockIdx.x * kFoldProducts + jj;
+    const int64_t jq = j < a.n && a.pnew ? a.pnew[j] : j;   // library id of product j
     // integer sums: eight independent accumulators keep eight loads in flight
     unsigned long long a0 = 0ull, a1 = 0ull, a2 = 0ull, a3 = 0ull;
     unsigned long long a4 = 0ull, a5 = 0ull, a6 = 0ull, a7 = 0ull;
-    if (j < a.n && j < a.H) {
-        const unsigned long long* P = a.part_S + j;
+    if (j < a.n && jq < a.H) {
+        const unsigned long long* P = a.part_S + jq;
         const size_t H = (size_t)a.H;
         int b = cc;
         for (; b + 7 * kFoldChunks < a.nseg; b += 8 * kFoldChunks) {
@@ -87,8 +89,8 @@ __global__ void __launch_bounds__(kFoldThreads) k_fold(PhaseArgs a)
     double x[NR];
     clear(x);
     if (cc == 0 && j < a.n) {
-        unsigned long long tot = a.S_fx[j];
-        a.S_fx[j] = 0ull;
+        unsigned long long tot = a.S_fx[jq];
+        a.S_fx[jq] = 0ull;
         for (int q = 0; q < kFoldChunks; ++q) tot += red[q][jj];
         const double sj = (double)(long long)tot * a.inv_fx;
         a.S_d[j] = sj;
@@ -209,19 +211,20 @@ __global__ void __launch_bounds__(kRowThreads) k_update(PhaseArgs a)
         const T et = (T)e;
         eta[i] = et;
         if (restart) a.sum_u[i] = 0.0;
-        if (IDENT) ((T*)a.rho)[i] = ((const T*)a.r)[i] - et;
+        if (IDENT) ((T*)a.rho)[a.pnew ? a.pnew[i] : i] = ((const T*)a.r)[i] - et;
     }
 }
 
 template <typename T>
 __global__ void k_prices_after(int64_t n, const T* r, const T* eta, const int64_t* a_ptr,
-                               const int32_t* a_idx, const T* a_val, T* rho)
+                               const int32_t* a_idx, const T* a_val, const int32_t* pnew,
+                               T* rho)
 {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= n) return;
     T x = r[j];
     for (int64_t q = a_ptr[j]; q < a_ptr[j + 1]; ++q) x -= a_val[q] * eta[a_idx[q]];
-    rho[j] = x;
+    rho[pnew ? pnew[j] : j] = x;
 }
 
 }  // namespace
@@ -250,7 +253,7 @@ hipError_t launch_phase(const PhaseArgs& a, bool identity, hipStream_t s)
             const unsigned pg = (unsigned)((a.n + 255) / 256);
             hipLaunchKernelGGL(k_prices_after<T>, dim3(pg), dim3(256), 0, s, a.n,
                                (const T*)a.r, (const T*)a.eta, a.a_ptr, a.a_idx,
-                               (const T*)a.a_val, (T*)a.rho);
+                               (const T*)a.a_val, a.pnew, (T*)a.rho);
         }
     }
     return hipGetLastError();

@@ -37,6 +37,7 @@ struct cblp_instance {
     // owned workspace
     void* rho = nullptr;
     unsigned long long* S_fx = nullptr;
+    int32_t* pnew = nullptr;        // [n] library id of caller product j (null: ids kept)
     unsigned long long* part_S = nullptr;
     double* S_d = nullptr;
     double* u_d = nullptr;

@@ -90,6 +90,7 @@ struct FeatArgs {
     int H;                         // LDS-binned products
     unsigned long long* part;      // [grid][3][H]: demand, attraction, degree
     unsigned long long* tail;      // [3][n] for products >= H
+    const int32_t* pnew;           // [n] library id of caller product j; NULL: j
 };
 
 template <typename T>
@@ -136,13 +137,14 @@ __global__ void k_feat_fold(FeatArgs a, int nblocks, const T* r, const T* c, con
 {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= a.n) return;
-    unsigned long long d = a.tail[j], at = a.tail[a.n + j], dg = a.tail[2 * a.n + j];
-    if (j < a.H)
+    const int64_t jq = a.pnew ? a.pnew[j] : j;   // the sorted copy's id of product j
+    unsigned long long d = a.tail[jq], at = a.tail[a.n + jq], dg = a.tail[2 * a.n + jq];
+    if (jq < a.H)
         for (int b = 0; b < nblocks; ++b) {
             const unsigned long long* pr = a.part + (size_t)b * 3 * a.H;
-            d += pr[j];
-            at += pr[a.H + j];
-            dg += pr[2 * a.H + j];
+            d += pr[jq];
+            at += pr[a.H + jq];
+            dg += pr[2 * a.H + jq];
         }
     const double dem = (double)(long long)d / a.dscale;
     const double att = (double)(long long)at / a.ascale;
@@ -681,6 +683,7 @@ int features_impl(cblp_instance* h, float* X, hipStream_t s)
     a.n = h->n;
     a.ptr = h->ptr2;
     a.idx = h->idx2;
+    a.pnew = h->pnew;
     a.v = h->v2;
     a.v0 = h->v0c;
     a.lam = h->lam2;

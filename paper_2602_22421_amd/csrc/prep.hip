@@ -2,6 +2,8 @@
 // bounds and the price step.
 #include "common.hpp"
 
+#include <algorithm>
+
 namespace cblp {
 namespace {
 
@@ -80,12 +82,13 @@ __global__ void k_prepare(int64_t L, const T* lam, double* lam_part)
 }
 
 // Copy the caller's CSR into the library's layout: position p takes
-// segment perm[p]; entries keep their order within a row; den = v - w.
+// segment perm[p]; entries keep their order within a row; den = v - w;
+// product ids become pnew[id] (nullable: ids kept).
 template <typename T>
 __global__ void k_relayout(int64_t L, const int64_t* seg_ptr, const int32_t* idx, const T* v,
                            const T* w, const T* v0, const T* lam, const int32_t* perm,
-                           const int64_t* ptr, int32_t* idx2, T* v2, T* den2, T* vt0, T* lam2,
-                           T* Rwarm, T* v0c)
+                           const int32_t* pnew, const int64_t* ptr, int32_t* idx2, T* v2,
+                           T* den2, T* vt0, T* lam2, T* Rwarm, T* v0c)
 {
     for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < L;
          p += (int64_t)gridDim.x * blockDim.x) {
@@ -94,7 +97,8 @@ __global__ void k_relayout(int64_t L, const int64_t* seg_ptr, const int32_t* idx
         double s = (double)v0[l];
         for (int64_t q = 0; q < k; ++q) {
             const T x = v[b + q], y = w[b + q];
-            idx2[d + q] = idx[b + q];
+            const int32_t id = idx[b + q];
+            idx2[d + q] = pnew ? pnew[id] : id;
             v2[d + q] = x;
             den2[d + q] = x - y;
             s += (double)y;
@@ -135,10 +139,31 @@ __global__ void k_relayout_slots(int64_t L, const int64_t* ptr, const int32_t* i
     }
 }
 
-// rho_j = r_j - sum_i a_ij eta_i  (identity: r_j - eta_j)
+// Degrees of the products [lo, lo + kDegBins): per-block LDS counts over the
+// block's share of the entries, then one global atomic per nonzero bin.
+constexpr int kDegBins = 16384;
+
+__global__ void __launch_bounds__(1024) k_degree(int64_t nnz, const int32_t* idx, int64_t lo,
+                                                 int64_t hi, unsigned long long* deg)
+{
+    __shared__ unsigned cnt[kDegBins];
+    for (int j = threadIdx.x; j < kDegBins; j += blockDim.x) cnt[j] = 0u;
+    __syncthreads();
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nnz;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t id = idx[e];
+        if (id >= lo && id < hi) atomicAdd(&cnt[id - lo], 1u);
+    }
+    __syncthreads();
+    for (int j = threadIdx.x; j < kDegBins && lo + j < hi; j += blockDim.x)
+        if (cnt[j]) atomicAdd(&deg[lo + j], (unsigned long long)cnt[j]);
+}
+
+// rho_j = r_j - sum_i a_ij eta_i  (identity: r_j - eta_j), stored at the
+// library's product id pnew[j] (nullable: j)
 template <typename T>
 __global__ void k_prices(int64_t n, const T* r, const T* eta, const int64_t* a_ptr,
-                         const int32_t* a_idx, const T* a_val, T* rho)
+                         const int32_t* a_idx, const T* a_val, const int32_t* pnew, T* rho)
 {
     for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n;
          j += (int64_t)gridDim.x * blockDim.x) {
@@ -148,11 +173,23 @@ __global__ void k_prices(int64_t n, const T* r, const T* eta, const int64_t* a_p
         } else {
             for (int64_t q = a_ptr[j]; q < a_ptr[j + 1]; ++q) x -= a_val[q] * eta[a_idx[q]];
         }
-        rho[j] = x;
+        rho[pnew ? pnew[j] : j] = x;
     }
 }
 
 }  // namespace
+
+hipError_t launch_degree(int64_t nnz, const int32_t* idx, int64_t n, unsigned long long* deg,
+                         hipStream_t s)
+{
+    hipError_t e = hipMemsetAsync(deg, 0, (size_t)n * 8, s);
+    if (e != hipSuccess) return e;
+    const int64_t blocks = std::min<int64_t>(1024, std::max<int64_t>(1, (nnz + 1023) / 1024));
+    for (int64_t lo = 0; lo < n; lo += kDegBins)
+        hipLaunchKernelGGL(k_degree, dim3((unsigned)blocks), dim3(1024), 0, s, nnz, idx, lo,
+                           std::min<int64_t>(n, lo + kDegBins), deg);
+    return hipGetLastError();
+}
 
 template <typename T>
 hipError_t launch_validate(int64_t L, int64_t n, int64_t m, int64_t nnz, int64_t nnzA,
@@ -177,12 +214,12 @@ hipError_t launch_prepare(int64_t L, const void* lam, double* lam_part, int bloc
 template <typename T>
 hipError_t launch_relayout(int64_t L, const int64_t* seg_ptr, const int32_t* idx,
                            const void* v, const void* w, const void* v0, const void* lam,
-                           const int32_t* perm, const int64_t* ptr, int32_t* idx2, void* v2,
-                           void* den2, void* vt0, void* lam2, void* Rwarm, void* v0c,
-                           hipStream_t s)
+                           const int32_t* perm, const int32_t* pnew, const int64_t* ptr,
+                           int32_t* idx2, void* v2, void* den2, void* vt0, void* lam2, void* Rwarm,
+                           void* v0c, hipStream_t s)
 {
     hipLaunchKernelGGL(k_relayout<T>, dim3(2048), dim3(256), 0, s, L, seg_ptr, idx,
-                       (const T*)v, (const T*)w, (const T*)v0, (const T*)lam, perm, ptr, idx2,
+                       (const T*)v, (const T*)w, (const T*)v0, (const T*)lam, perm, pnew, ptr, idx2,
                        (T*)v2, (T*)den2, (T*)vt0, (T*)lam2, (T*)Rwarm, (T*)v0c);
     return hipGetLastError();
 }
@@ -204,12 +241,13 @@ hipError_t launch_relayout_slots(int64_t L, const int64_t* ptr, const int32_t* i
 
 template <typename T>
 hipError_t launch_prices(int64_t n, const void* r, const void* eta, const int64_t* a_ptr,
-                         const int32_t* a_idx, const void* a_val, void* rho, hipStream_t s)
+                         const int32_t* a_idx, const void* a_val, const int32_t* pnew, void* rho,
+                         hipStream_t s)
 {
     const int64_t blocks = (n + 255) / 256;
     hipLaunchKernelGGL(k_prices<T>, dim3((unsigned)(blocks < 1 ? 1 : blocks > 4096 ? 4096 : blocks)),
                        dim3(256), 0, s, n, (const T*)r, (const T*)eta, a_ptr, a_idx,
-                       (const T*)a_val, (T*)rho);
+                       (const T*)a_val, pnew, (T*)rho);
     return hipGetLastError();
 }
 
@@ -221,11 +259,13 @@ hipError_t launch_prices(int64_t n, const void* r, const void* eta, const int64_
                                            const void*, unsigned*, hipStream_t);               \
     template hipError_t launch_prepare<T>(int64_t, const void*, double*, int, hipStream_t);    \
     template hipError_t launch_prices<T>(int64_t, const void*, const void*, const int64_t*,    \
-                                         const int32_t*, const void*, void*, hipStream_t);     \
+                                         const int32_t*, const void*, const int32_t*, void*,   \
+                                         hipStream_t);                                         \
     template hipError_t launch_relayout<T>(int64_t, const int64_t*, const int32_t*,            \
                                            const void*, const void*, const void*, const void*, \
-                                           const int32_t*, const int64_t*, int32_t*, void*,    \
-                                           void*, void*, void*, void*, void*, hipStream_t);   \
+                                           const int32_t*, const int32_t*, const int64_t*,     \
+                                           int32_t*, void*, void*, void*, void*, void*, void*, \
+                                           hipStream_t);                                       \
     template hipError_t launch_relayout_slots<T>(int64_t, const int64_t*, const int32_t*,      \
                                                  const void*, const void*, const int64_t*,     \
                                                  int64_t, int32_t*, void*, void*, hipStream_t);

@@ -289,6 +289,38 @@ def tiny_instance(L: int, n: int, *, m: Optional[int] = None, size_lo=1,
                          **kw)
 
 
+def shuffle_products(inst: Instance, seed: int = 0):
+    """The same instance with its products renumbered by a random permutation
+    pi (product j becomes pi[j]; rows re-sorted by the new ids; r, the
+    consumption columns of A, and for A = I the capacities move with their
+    product).  Returns (instance, pi).  Generated instances number products
+    by popularity; this one does not."""
+    rng = np.random.default_rng(seed)
+    pi = rng.permutation(inst.n).astype(np.int32)
+    new = pi[inst.idx]
+    order = np.lexsort((new, _row_ids(inst.seg_ptr)))
+    r = np.empty_like(inst.r)
+    r[pi] = inst.r
+    kw = {}
+    if inst.identity:
+        c = np.empty_like(inst.c)
+        c[pi] = inst.c
+        kw["c"] = c
+    else:
+        old = np.argsort(pi)                      # old id of each new id
+        cnt = np.diff(inst.a_ptr)[old]
+        a_ptr = np.zeros(inst.n + 1, dtype=np.int64)
+        np.cumsum(cnt, out=a_ptr[1:])
+        take = np.concatenate([np.arange(inst.a_ptr[j], inst.a_ptr[j + 1]) for j in old]) \
+            if inst.n else np.zeros(0, dtype=np.int64)
+        kw.update(a_ptr=a_ptr, a_idx=inst.a_idx[take].copy(), a_val=inst.a_val[take].copy())
+    out = dataclasses.replace(inst, idx=np.ascontiguousarray(new[order]),
+                              v=np.ascontiguousarray(inst.v[order]),
+                              w=np.ascontiguousarray(inst.w[order]), r=r,
+                              name=(inst.name + "-shuffled") if inst.name else "shuffled", **kw)
+    return out, pi
+
+
 def step_scale(inst: Instance, tau0: float) -> np.ndarray:
     """Per-row dual step tau_i = tau0 * max_j r_j / c_i: revenue units per unit
     of capacity, so tau0 is dimensionless.  Rows with c_i = 0 get the step of
