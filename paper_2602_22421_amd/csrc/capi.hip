@@ -360,17 +360,32 @@ int create_impl(cblp_instance* h, hipStream_t s)
         if (prop.multiProcessorCount > 0) cus = prop.multiProcessorCount;
         if (prop.sharedMemPerBlock > 0) lds_block = prop.sharedMemPerBlock;
     }
+    // row pointers on the host: the longest row picks the register slots, and
+    // the size-sorted copy below is built from them
+    std::vector<int64_t> sp((size_t)h->L + 1);
+    HIP_TRY(hipMemcpyAsync(sp.data(), h->seg_ptr, (h->L + 1) * sizeof(int64_t),
+                           hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    int64_t kmax = 0;
+    for (int64_t l = 0; l < h->L; ++l) kmax = std::max(kmax, sp[l + 1] - sp[l]);
+    const bool short_rows = kmax <= 4 * kGroup;   // every row fits 4 register slots
+
     // kernel variant and bin count may be overridden for tuning runs.  The
-    // prices go to LDS when they take at most half of it.
+    // prices go to LDS when they take at most half of it, else the popular
+    // head of them does.
     const bool prices_fit = (int64_t)h->n * (int64_t)sizeof(T) * 2 <= (int64_t)lds_block;
-    h->seg_variant = sizeof(T) == 4 ? (prices_fit ? kSegSlots + 1 : kSegSplit) : kSegSlots + 3;
+    if (sizeof(T) == 4)
+        h->seg_variant = prices_fit ? (short_rows ? kSegSlotsJ4 : kSegSlots + 1)
+                                    : (short_rows ? kSegSlotsSplit + 1 : kSegSlotsSplit);
+    else
+        h->seg_variant = kSegSlots + 3;
     if (const char* ev = std::getenv("CBLP_SEG_VARIANT")) {
         const int x = std::atoi(ev);
-        if (x >= 0 && x < kSegVariants && (!seg_lds_prices(x) || prices_fit || x == kSegSplit))
+        if (x >= 0 && x < kSegVariants && (!seg_lds_prices(x) || prices_fit || seg_split(x)))
             h->seg_variant = x;
     }
-    h->hp = h->seg_variant == kSegSplit ? (int)std::min<int64_t>(h->n, kSplitPrices) : 0;
-    const int64_t price_bytes = h->seg_variant == kSegSplit ? (int64_t)h->hp * (int64_t)sizeof(T)
+    h->hp = seg_split(h->seg_variant) ? (int)std::min<int64_t>(h->n, kSplitPrices) : 0;
+    const int64_t price_bytes = seg_split(h->seg_variant) ? (int64_t)h->hp * (int64_t)sizeof(T)
                                 : seg_lds_prices(h->seg_variant) ? h->n * (int64_t)sizeof(T) : 0;
     const int64_t lds_bins = ((int64_t)lds_block - 1024 - price_bytes) / 8;
     h->H = (int)std::max<int64_t>(1, std::min<int64_t>({h->n, (int64_t)kMaxBins, lds_bins}));
@@ -381,7 +396,7 @@ int create_impl(cblp_instance* h, hipStream_t s)
         if (x >= 1 && x <= h->H) h->H = (int)x;
     }
     const int per_cu = segment_blocks_per_cu<T>(
-        h->H, h->seg_variant == kSegSplit ? (int64_t)h->hp : h->n, h->seg_variant);
+        h->H, seg_split(h->seg_variant) ? (int64_t)h->hp : h->n, h->seg_variant);
     const int64_t tiles = (h->L + kSegsPerTile - 1) / kSegsPerTile;
     h->seg_grid = (int)std::max<int64_t>(1, std::min<int64_t>(tiles, (int64_t)cus * per_cu));
     h->fold_blocks = (int)((h->n + kFoldProducts - 1) / kFoldProducts);
@@ -434,12 +449,6 @@ int create_impl(cblp_instance* h, hipStream_t s)
 
     // size-sorted copy of the segments: a stable counting sort by row length
     {
-        std::vector<int64_t> sp((size_t)h->L + 1);
-        HIP_TRY(hipMemcpyAsync(sp.data(), h->seg_ptr, (h->L + 1) * sizeof(int64_t),
-                               hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipStreamSynchronize(s));
-        int64_t kmax = 0;
-        for (int64_t l = 0; l < h->L; ++l) kmax = std::max(kmax, sp[l + 1] - sp[l]);
         std::vector<int64_t> start((size_t)kmax + 2, 0);
         for (int64_t l = 0; l < h->L; ++l) start[sp[l + 1] - sp[l] + 1]++;
         for (int64_t k = 0; k <= kmax; ++k) start[k + 1] += start[k];

@@ -134,13 +134,20 @@ hipError_t launch_prices(int64_t n, const void* r, const void* eta, const int64_
 // Variants kSegClassLds (prices in LDS) and kSegClassGlobal take the slot
 // count of each block from a table: blocks own runs of tiles of one size class.
 // Variant kSegSplit holds the prices of products [0, hp) in LDS.  Variants
-// kSegSlots and up read the slot-major copy (see SegArgs::woff).
-constexpr int kSegVariants = 26;
+// kSegSlots and up read the slot-major copy (see SegArgs::woff); of these,
+// kSegSlotsSplit and kSegSlotsSplit + 1 hold the prices as kSegSplit does.
+constexpr int kSegVariants = 29;
 constexpr int kSegSlots = 20;
+constexpr int kSegSlotsSplit = 26;
+constexpr int kSegSlotsJ4 = 28;        // 4 register slots, prices in LDS
 inline bool seg_slot_major(int variant) { return variant >= kSegSlots; }
 constexpr int kSegLdsPrices = 10;
 constexpr int kSegClassLds = 17, kSegClassGlobal = 18, kSegSplit = 19;
 constexpr int kSplitPrices = 8192;     // head prices of the split kernel
+inline bool seg_split(int variant)
+{
+    return variant == kSegSplit || variant == kSegSlotsSplit || variant == kSegSlotsSplit + 1;
+}
 inline bool seg_class(int variant) { return variant == kSegClassLds || variant == kSegClassGlobal; }
 // most register slots of the size-class kernels per element size
 inline int seg_class_max_slots(size_t esz) { return esz == 4 ? 7 : 4; }

@@ -118,6 +118,37 @@ __global__ void __launch_bounds__(kSegThreads) k_segments_slots(SegArgs a)
     }
 }
 
+// Slot-major kernel with split prices (head [0, a.hp) in LDS, the rest from
+// global memory), for instances whose prices do not fit in LDS.
+template <typename T, int J>
+__global__ void __launch_bounds__(kSegThreads) k_segments_slots_split(SegArgs a)
+{
+    extern __shared__ unsigned long long bins[];   // [a.H], then [a.hp] prices
+    __shared__ double zsh[kSegThreads / 64];
+    const int H = a.H;
+    T* lprice = (T*)(bins + H);
+    for (int j = threadIdx.x; j < H; j += kSegThreads) bins[j] = 0ull;
+    for (int j = threadIdx.x; j < a.hp; j += kSegThreads) lprice[j] = ((const T*)a.rho)[j];
+    __syncthreads();
+
+    double zacc = 0.0;
+    const int64_t tiles = (a.L + kSegsPerTile - 1) / kSegsPerTile;
+    const seg::SplitPrices<T> pr{(const T*)lprice, (const T*)a.rho, a.hp};
+    seg::process_tiles_slots<T, J, false, seg::SplitPrices<T>>(a, blockIdx.x, tiles, gridDim.x,
+                                                              bins, pr, zacc);
+
+    __syncthreads();
+    flush_bins(a, bins);
+    for (int o = 32; o > 0; o >>= 1) zacc += __shfl_down(zacc, o, 64);
+    if ((threadIdx.x & 63) == 0) zsh[threadIdx.x >> 6] = zacc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double z = zsh[0];
+        for (int q = 1; q < kSegThreads / 64; ++q) z += zsh[q];
+        a.zpart[blockIdx.x] = z;
+    }
+}
+
 // Size-class kernel: block b solves tiles [blk[b][1], blk[b][2]) with
 // blk[b][0] register slots per lane.  The layout is sorted by row length, so
 // a run of tiles has one slot count, and loading every slot of it wastes no
@@ -206,6 +237,9 @@ const void* SegVariant<T>::fn(int variant)
     case kSegSlots + 3: return (const void*)k_segments_slots<T, 4, true, false>;
     case kSegSlots + 4: return (const void*)k_segments_slots<T, 7, false, true, true>;
     case kSegSlots + 5: return (const void*)k_segments_slots<T, 4, false, false, true>;
+    case kSegSlotsSplit: return (const void*)k_segments_slots_split<T, 7>;
+    case kSegSlotsSplit + 1: return (const void*)k_segments_slots_split<T, 4>;
+    case kSegSlotsJ4: return (const void*)k_segments_slots<T, 4, false, true>;
     default: return (const void*)k_segments<T, 4, 1, false>;
     }
 }
@@ -213,7 +247,7 @@ const void* SegVariant<T>::fn(int variant)
 template <typename T>
 hipError_t launch_segments(const SegArgs& a, int grid, int variant, hipStream_t s)
 {
-    const size_t lds = seg_lds_bytes(a.H, variant == kSegSplit ? a.hp : a.n, sizeof(T), variant);
+    const size_t lds = seg_lds_bytes(a.H, seg_split(variant) ? a.hp : a.n, sizeof(T), variant);
     void* args[] = {(void*)&a};
     return hipLaunchKernel(SegVariant<T>::fn(variant), dim3(grid), dim3(kSegThreads), args, lds,
                            s);
