@@ -352,7 +352,7 @@ struct cblp_batch {
     int variant = 6;
     int Hmax = 1;
     int64_t nmax = 1;               // most products of any instance
-    bool slots_ok = false;          // every handle has its slot-major copy
+    bool slots_ok = false;          // every handle has a slot-major copy with 32-bit ids
     hipStream_t stream = nullptr;    // the batch's own stream (graph capture needs one)
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -579,7 +579,7 @@ int cblp_batch_create(cblp_batch_t* out, int32_t count, const cblp_t* handles, v
     b->slots_ok = true;
     for (int q = 0; q < count; ++q) {
         b->nmax = std::max<int64_t>(b->nmax, b->hs[q]->n);
-        b->slots_ok = b->slots_ok && b->hs[q]->woff != nullptr;
+        b->slots_ok = b->slots_ok && b->hs[q]->woff != nullptr && !b->hs[q]->idx16;
     }
     if (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming) != hipSuccess ||

@@ -374,16 +374,21 @@ int create_impl(cblp_instance* h, hipStream_t s)
     // prices go to LDS when they take at most half of it, else the popular
     // head of them does.
     const bool prices_fit = (int64_t)h->n * (int64_t)sizeof(T) * 2 <= (int64_t)lds_block;
+    // 16-bit product ids in the slot-major copy when they fit
+    const bool ids16 = h->n <= 65536;
     if (sizeof(T) == 4)
-        h->seg_variant = prices_fit ? (short_rows ? kSegSlotsJ4 : kSegSlots + 1)
+        h->seg_variant = prices_fit ? (short_rows ? (ids16 ? kSegSlots16 + 1 : kSegSlotsJ4)
+                                                  : (ids16 ? kSegSlots16 : kSegSlots + 1))
                                     : (short_rows ? kSegSlotsSplit + 1 : kSegSlotsSplit);
     else
         h->seg_variant = kSegSlots + 3;
     if (const char* ev = std::getenv("CBLP_SEG_VARIANT")) {
         const int x = std::atoi(ev);
-        if (x >= 0 && x < kSegVariants && (!seg_lds_prices(x) || prices_fit || seg_split(x)))
+        if (x >= 0 && x < kSegVariants && (!seg_lds_prices(x) || prices_fit || seg_split(x)) &&
+            (!seg_idx16(x) || ids16))
             h->seg_variant = x;
     }
+    h->idx16 = seg_idx16(h->seg_variant);
     h->hp = seg_split(h->seg_variant) ? (int)std::min<int64_t>(h->n, kSplitPrices) : 0;
     const int64_t price_bytes = seg_split(h->seg_variant) ? (int64_t)h->hp * (int64_t)sizeof(T)
                                 : seg_lds_prices(h->seg_variant) ? h->n * (int64_t)sizeof(T) : 0;
@@ -533,12 +538,12 @@ int create_impl(cblp_instance* h, hipStream_t s)
             const int64_t entries = woff[W] + 64 * kMaxJ;   // loads may run J slots past the end
             woff[W + 1] = woff[W];
             if ((rc = dalloc(&h->woff, (size_t)(W + 2) * 8))) return rc;
-            if ((rc = dalloc(&h->idx3, (size_t)entries * 4))) return rc;
+            if ((rc = dalloc(&h->idx3, (size_t)entries * (h->idx16 ? 2 : 4)))) return rc;
             if ((rc = dalloc(&h->v3, (size_t)entries * esz))) return rc;
             if ((rc = dalloc(&h->den3, (size_t)entries * esz))) return rc;
             HIP_TRY(hipMemcpyAsync(h->woff, woff.data(), (W + 2) * 8, hipMemcpyHostToDevice, s));
             HIP_TRY(launch_relayout_slots<T>(h->L, h->ptr2, h->idx2, h->v2, h->den2, h->woff,
-                                             entries, h->idx3, h->v3, h->den3, s));
+                                             entries, h->idx3, h->idx16, h->v3, h->den3, s));
         }
         HIP_TRY(hipStreamSynchronize(s));   // the host vectors die here
     }

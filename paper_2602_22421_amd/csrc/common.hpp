@@ -61,7 +61,7 @@ struct SegArgs {
     // slot-major copy (slot-major kernels): wave-tile w (positions 8w..8w+7)
     // holds (woff[w+1] - woff[w]) / 64 slots of 64 entries from woff[w]
     const int64_t* woff;           // [ceil(L/8) + 2], the last entry repeats the total
-    const int32_t* idx3;
+    const void* idx3;              // int32 ids, or uint16 for the 16-bit-id kernels
     const void* v3;
     const void* den3;
 };
@@ -123,7 +123,7 @@ hipError_t launch_degree(int64_t nnz, const int32_t* idx, int64_t n, unsigned lo
 template <typename T>
 hipError_t launch_relayout_slots(int64_t L, const int64_t* ptr, const int32_t* idx2,
                                  const void* v2, const void* den2, const int64_t* woff,
-                                 int64_t entries, int32_t* idx3, void* v3, void* den3,
+                                 int64_t entries, void* idx3, bool idx16, void* v3, void* den3,
                                  hipStream_t s);
 template <typename T>
 hipError_t launch_prices(int64_t n, const void* r, const void* eta, const int64_t* a_ptr,
@@ -136,10 +136,14 @@ hipError_t launch_prices(int64_t n, const void* r, const void* eta, const int64_
 // Variant kSegSplit holds the prices of products [0, hp) in LDS.  Variants
 // kSegSlots and up read the slot-major copy (see SegArgs::woff); of these,
 // kSegSlotsSplit and kSegSlotsSplit + 1 hold the prices as kSegSplit does.
-constexpr int kSegVariants = 29;
+constexpr int kSegVariants = 31;
 constexpr int kSegSlots = 20;
 constexpr int kSegSlotsSplit = 26;
 constexpr int kSegSlotsJ4 = 28;        // 4 register slots, prices in LDS
+// as kSegSlots + 1 and kSegSlotsJ4 with 16-bit product ids in the slot-major
+// copy (n <= 65536): 10 bytes per FP32 entry instead of 12
+constexpr int kSegSlots16 = 29;
+inline bool seg_idx16(int variant) { return variant == kSegSlots16 || variant == kSegSlots16 + 1; }
 inline bool seg_slot_major(int variant) { return variant >= kSegSlots; }
 constexpr int kSegLdsPrices = 10;
 constexpr int kSegClassLds = 17, kSegClassGlobal = 18, kSegSplit = 19;

@@ -31,7 +31,8 @@ struct cblp_instance {
     int32_t* perm = nullptr;
     int64_t* seg_blk = nullptr;     // [seg_grid][3] size-class block table (class variants)
     int64_t* woff = nullptr;        // slot-major copy (slot-major variants): wave-tile offsets
-    int32_t* idx3 = nullptr;
+    void* idx3 = nullptr;           // int32, or uint16 when idx16
+    bool idx16 = false;
     void* v3 = nullptr;
     void* den3 = nullptr;
     // owned workspace

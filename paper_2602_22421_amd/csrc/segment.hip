@@ -88,7 +88,7 @@ __global__ void __launch_bounds__(kSegThreads) k_segments_split(SegArgs a)
 
 // Slot-major kernel: the per-segment step over the slot-major copy (one
 // contiguous 256-byte read per slot and array for a whole wave).
-template <typename T, int J, bool ALL, bool LDSP, bool TOUCH = false>
+template <typename T, int J, bool ALL, bool LDSP, bool TOUCH = false, typename IdxT = int32_t>
 __global__ void __launch_bounds__(kSegThreads) k_segments_slots(SegArgs a)
 {
     extern __shared__ unsigned long long bins[];   // [a.H], then [a.n] prices if LDSP
@@ -103,8 +103,8 @@ __global__ void __launch_bounds__(kSegThreads) k_segments_slots(SegArgs a)
     double zacc = 0.0;
     const int64_t tiles = (a.L + kSegsPerTile - 1) / kSegsPerTile;
     const seg::FlatPrices<T> pr{LDSP ? (const T*)lprice : (const T*)a.rho};
-    seg::process_tiles_slots<T, J, ALL, seg::FlatPrices<T>, TOUCH>(a, blockIdx.x, tiles, gridDim.x,
-                                                                 bins, pr, zacc);
+    seg::process_tiles_slots<T, J, ALL, seg::FlatPrices<T>, TOUCH, IdxT>(a, blockIdx.x, tiles,
+                                                                       gridDim.x, bins, pr, zacc);
 
     __syncthreads();
     flush_bins(a, bins);
@@ -240,6 +240,8 @@ const void* SegVariant<T>::fn(int variant)
     case kSegSlotsSplit: return (const void*)k_segments_slots_split<T, 7>;
     case kSegSlotsSplit + 1: return (const void*)k_segments_slots_split<T, 4>;
     case kSegSlotsJ4: return (const void*)k_segments_slots<T, 4, false, true>;
+    case kSegSlots16: return (const void*)k_segments_slots<T, 7, false, true, false, uint16_t>;
+    case kSegSlots16 + 1: return (const void*)k_segments_slots<T, 4, false, true, false, uint16_t>;
     default: return (const void*)k_segments<T, 4, 1, false>;
     }
 }

@@ -488,19 +488,20 @@ __device__ __forceinline__ int wave_jw(const WaveBounds<T>& B)
     return __builtin_amdgcn_readfirstlane(B.wlive ? (int)((B.b1 - B.b0) >> 6) : 0);
 }
 
-template <typename T, int J, bool ALL>
+// IdxT: the slot-major copy's product ids, int32_t or uint16_t (n <= 65536)
+template <typename T, int J, bool ALL, typename IdxT = int32_t>
 __device__ __forceinline__ Raw<T, J> load_slots(const SegArgs& a, const WaveBounds<T>& B, int lane)
 {
     Raw<T, J> R;
     const int64_t base = wave_base(B);
     const int jw = ALL ? J : wave_jw(B);
-    const int32_t* pi = a.idx3 + base + lane;
+    const IdxT* pi = (const IdxT*)a.idx3 + base + lane;
     const T* pv = (const T*)a.v3 + base + lane;
     const T* pd = (const T*)a.den3 + base + lane;
 #pragma unroll
     for (int s = 0; s < J; ++s) {
         if (ALL || s < jw) {
-            R.id[s] = pi[64 * s];
+            R.id[s] = (int32_t)pi[64 * s];
             R.v[s] = pv[64 * s];
             R.den[s] = pd[64 * s];
         } else {
@@ -531,7 +532,7 @@ __device__ __forceinline__ unsigned touch_tile(const SegArgs& a, const WaveBound
     return x;
 }
 
-template <typename T, int J, bool ALL, typename PR, bool TOUCH = false>
+template <typename T, int J, bool ALL, typename PR, bool TOUCH = false, typename IdxT = int32_t>
 __device__ __forceinline__ void process_tiles_slots(const SegArgs& a, int64_t tile, int64_t tiles,
                                                     int64_t stride, unsigned long long* bins,
                                                     const PR& rho, double& zacc)
@@ -539,7 +540,7 @@ __device__ __forceinline__ void process_tiles_slots(const SegArgs& a, int64_t ti
     unsigned sink = 0u;
     const T* __restrict__ v3 = (const T*)a.v3;
     const T* __restrict__ d3 = (const T*)a.den3;
-    const int32_t* __restrict__ i3 = a.idx3;
+    const IdxT* __restrict__ i3 = (const IdxT*)a.idx3;
     const int H = a.H;
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
@@ -547,7 +548,7 @@ __device__ __forceinline__ void process_tiles_slots(const SegArgs& a, int64_t ti
     if (tile >= tiles) return;
 
     WaveBounds<T> Bc = load_wave_bounds<T>(a, tile, wv, q);
-    Raw<T, J> Rc = load_slots<T, J, ALL>(a, Bc, lane);
+    Raw<T, J> Rc = load_slots<T, J, ALL, IdxT>(a, Bc, lane);
     WaveBounds<T> B1 = load_wave_bounds<T>(a, tile + stride, wv, q);
     WaveBounds<T> B2;
     if (TOUCH) B2 = load_wave_bounds<T>(a, tile + 2 * stride, wv, q);
@@ -555,7 +556,7 @@ __device__ __forceinline__ void process_tiles_slots(const SegArgs& a, int64_t ti
     for (; tile < tiles; tile += stride) {
         gather<T, J, true, PR>(rho, Rc, Pc, J);
         __builtin_amdgcn_sched_barrier(0);
-        const Raw<T, J> R1 = load_slots<T, J, ALL>(a, B1, lane);
+        const Raw<T, J> R1 = load_slots<T, J, ALL, IdxT>(a, B1, lane);
         WaveBounds<T> B3;
         if (TOUCH) {
             sink ^= touch_tile<T>(a, B2, lane);
@@ -661,7 +662,7 @@ __device__ __forceinline__ void process_tiles_slots(const SegArgs& a, int64_t ti
         for (int s = J; s < jw; ++s) {
             const int64_t e = base + 64 * s + lane;
             const T x = v3[e];
-            const int32_t j = i3[e];
+            const int32_t j = (int32_t)i3[e];
             if (rho[j] * x > R * d3[e]) {
                 const unsigned long long qq = quantum(lamD, x);
                 if (j < H)

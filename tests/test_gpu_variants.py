@@ -11,7 +11,7 @@ pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
 
-N_VARIANTS = 29
+N_VARIANTS = 31
 
 
 @pytest.fixture(scope="module")
