@@ -381,7 +381,7 @@ int create_impl(cblp_instance* h, hipStream_t s)
                                                   : (ids16 ? kSegSlots16 : kSegSlots + 1))
                                     : (short_rows ? kSegSlotsSplit + 1 : kSegSlotsSplit);
     else
-        h->seg_variant = kSegSlots + 3;
+        h->seg_variant = ids16 ? kSegSlots16 + 2 : kSegSlots + 3;
     if (const char* ev = std::getenv("CBLP_SEG_VARIANT")) {
         const int x = std::atoi(ev);
         if (x >= 0 && x < kSegVariants && (!seg_lds_prices(x) || prices_fit || seg_split(x)) &&

@@ -136,14 +136,15 @@ hipError_t launch_prices(int64_t n, const void* r, const void* eta, const int64_
 // Variant kSegSplit holds the prices of products [0, hp) in LDS.  Variants
 // kSegSlots and up read the slot-major copy (see SegArgs::woff); of these,
 // kSegSlotsSplit and kSegSlotsSplit + 1 hold the prices as kSegSplit does.
-constexpr int kSegVariants = 31;
+constexpr int kSegVariants = 32;
 constexpr int kSegSlots = 20;
 constexpr int kSegSlotsSplit = 26;
 constexpr int kSegSlotsJ4 = 28;        // 4 register slots, prices in LDS
-// as kSegSlots + 1 and kSegSlotsJ4 with 16-bit product ids in the slot-major
-// copy (n <= 65536): 10 bytes per FP32 entry instead of 12
+// as kSegSlots + 1, kSegSlotsJ4 and kSegSlots + 3 with 16-bit product ids in
+// the slot-major copy (n <= 65536): 10 bytes per FP32 entry instead of 12,
+// 18 per FP64 entry instead of 20
 constexpr int kSegSlots16 = 29;
-inline bool seg_idx16(int variant) { return variant == kSegSlots16 || variant == kSegSlots16 + 1; }
+inline bool seg_idx16(int variant) { return variant >= kSegSlots16 && variant <= kSegSlots16 + 2; }
 inline bool seg_slot_major(int variant) { return variant >= kSegSlots; }
 constexpr int kSegLdsPrices = 10;
 constexpr int kSegClassLds = 17, kSegClassGlobal = 18, kSegSplit = 19;
@@ -158,7 +159,7 @@ inline int seg_class_max_slots(size_t esz) { return esz == 4 ? 7 : 4; }
 inline bool seg_lds_prices(int variant)
 {
     return variant >= kSegLdsPrices && variant != kSegClassGlobal && variant != kSegSlots + 3 &&
-           variant != kSegSlots + 5;
+           variant != kSegSlots + 5 && variant != kSegSlots16 + 2;
 }
 // dynamic LDS bytes of a segment block: H bins, then the prices if in LDS
 inline size_t seg_lds_bytes(int H, int64_t n, size_t esz, int variant)

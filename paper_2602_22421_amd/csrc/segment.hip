@@ -242,6 +242,7 @@ const void* SegVariant<T>::fn(int variant)
     case kSegSlotsJ4: return (const void*)k_segments_slots<T, 4, false, true>;
     case kSegSlots16: return (const void*)k_segments_slots<T, 7, false, true, false, uint16_t>;
     case kSegSlots16 + 1: return (const void*)k_segments_slots<T, 4, false, true, false, uint16_t>;
+    case kSegSlots16 + 2: return (const void*)k_segments_slots<T, 4, true, false, false, uint16_t>;
     default: return (const void*)k_segments<T, 4, 1, false>;
     }
 }

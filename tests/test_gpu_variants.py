@@ -11,7 +11,7 @@ pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
 
-N_VARIANTS = 31
+N_VARIANTS = 32
 
 
 @pytest.fixture(scope="module")
