@@ -102,8 +102,8 @@ __global__ void k_reset_counter(unsigned* counter) { *counter = 0u; }
 
 // MODE 0: prices gathered from global memory; 1: the item's instance prices
 // copied into LDS behind the largest instance's bins (Hmax), then gathered
-// there; 2: as 1 over the slot-major copies.
-template <typename T, int J, int DEPTH, int MODE>
+// there; 2: as 1 over the slot-major copies (IdxT: their product id type).
+template <typename T, int J, int DEPTH, int MODE, typename IdxT = int32_t>
 __global__ void __launch_bounds__(kSegThreads)
 k_bsegments(const BInst* inst, const BItem* items, int nitems, unsigned* counter,
             unsigned long long* part_S, double* zpart, int Hmax)
@@ -131,7 +131,8 @@ k_bsegments(const BInst* inst, const BItem* items, int nitems, unsigned* counter
         double zacc = 0.0;
         const seg::FlatPrices<T> pr{MODE > 0 ? (const T*)lprice : (const T*)a.rho};
         if (MODE == 2)
-            seg::process_tiles_slots<T, J, false>(a, w.t0, w.t1, 1, bins, pr, zacc);
+            seg::process_tiles_slots<T, J, false, seg::FlatPrices<T>, false, IdxT>(a, w.t0, w.t1, 1,
+                                                                                  bins, pr, zacc);
         else
             seg::process_tiles<T, J, DEPTH>(a, w.t0, w.t1, 1, bins, pr, zacc);
         __syncthreads();
@@ -295,8 +296,9 @@ __global__ void __launch_bounds__(kRowThreads) k_bprices(const BInst* inst, cons
 
 // Batched variants 0-6 as the single-instance ones (prices from global
 // memory); 7: ordered pipeline with the prices in LDS; 8: slot-major copies
-// with the prices in LDS (needs every handle's slot-major copy).
-constexpr int kBatchVariants = 9;
+// with the prices in LDS (needs every handle's slot-major copy with 32-bit
+// ids); 9: the same over 16-bit-id copies.
+constexpr int kBatchVariants = 10;
 inline bool bseg_lds_prices(int variant) { return variant >= 7; }
 
 template <typename T>
@@ -311,6 +313,7 @@ const void* bseg_fn(int variant)
     case 6: return (const void*)k_bsegments<T, 7, 1, 0>;
     case 7: return (const void*)k_bsegments<T, sizeof(T) == 4 ? 7 : 4, 3, 1>;
     case 8: return (const void*)k_bsegments<T, sizeof(T) == 4 ? 7 : 4, 3, 2>;
+    case 9: return (const void*)k_bsegments<T, sizeof(T) == 4 ? 7 : 4, 3, 2, uint16_t>;
     default: return (const void*)k_bsegments<T, 4, 1, 0>;
     }
 }
@@ -353,6 +356,7 @@ struct cblp_batch {
     int Hmax = 1;
     int64_t nmax = 1;               // most products of any instance
     bool slots_ok = false;          // every handle has a slot-major copy with 32-bit ids
+    bool slots16_ok = false;        // every handle has one with 16-bit ids
     hipStream_t stream = nullptr;    // the batch's own stream (graph capture needs one)
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -516,6 +520,7 @@ bool bseg_usable(const cblp_batch* b, int variant)
 {
     if (variant < 0 || variant >= kBatchVariants) return false;
     if (variant == 8 && !b->slots_ok) return false;
+    if (variant == 9 && !b->slots16_ok) return false;
     const void* f = b->dtype == CBLP_F32 ? bseg_fn<float>(variant) : bseg_fn<double>(variant);
     const size_t lds = bseg_lds(b, variant);
     int per_cu = 0;
@@ -577,9 +582,11 @@ int cblp_batch_create(cblp_batch_t* out, int32_t count, const cblp_t* handles, v
     }
     b->Hmax = (int)Hmax;
     b->slots_ok = true;
+    b->slots16_ok = true;
     for (int q = 0; q < count; ++q) {
         b->nmax = std::max<int64_t>(b->nmax, b->hs[q]->n);
         b->slots_ok = b->slots_ok && b->hs[q]->woff != nullptr && !b->hs[q]->idx16;
+        b->slots16_ok = b->slots16_ok && b->hs[q]->woff != nullptr && b->hs[q]->idx16;
     }
     if (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming) != hipSuccess ||
@@ -593,7 +600,7 @@ int cblp_batch_create(cblp_batch_t* out, int32_t count, const cblp_t* handles, v
         cus = prop.multiProcessorCount;
     // default: slot-major copies with LDS prices when every instance has them
     // and they fit, else the spill-free global-price variant
-    b->variant = bseg_usable(b, 8) ? 8 : bseg_usable(b, 7) ? 7 : 5;
+    b->variant = bseg_usable(b, 9) ? 9 : bseg_usable(b, 8) ? 8 : bseg_usable(b, 7) ? 7 : 5;
     if (const char* ev = std::getenv("CBLP_BATCH_VARIANT")) {
         const int x = std::atoi(ev);
         if (x >= 0 && x < kBatchVariants && bseg_usable(b, x)) b->variant = x;
@@ -809,7 +816,7 @@ int cblp_batch_tune(cblp_batch_t b, void* const* etas, const void* const* tau_ve
     if ((rc = enter(b, caller))) return rc;
     if ((rc = bind(b, etas, tau_vecs, p, b->stream))) return rc;
     if ((rc = run_prices(b, b->stream))) return rc;
-    const int candidates[] = {5, 6, 0, 4, 7, 8};
+    const int candidates[] = {5, 6, 0, 4, 7, 8, 9};
     double best = INFINITY;
     int best_v = b->variant;
     hipEvent_t e0, e1;

@@ -121,8 +121,39 @@ def test_batch_tune_picks_a_variant(cb):
     etas = [p.zeros_eta() for p in probs]
     params = cb.make_params(rule=0, tau=1.0, check_every=5)
     v = batch.tune(etas, params, iters=3, tau_vecs=taus)
-    assert v in (0, 4, 5, 6, 7, 8)
+    assert v in (0, 4, 5, 6, 7, 8, 9)
     assert batch.info()["variant"] == v
     rows = batch.iterate([p.zeros_eta() for p in probs], 5, params, tau_vecs=taus)
     assert np.all(np.isfinite(rows))
     batch.close()
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_batch_variants_agree(cb, dtype, monkeypatch):
+    """Every batched segment-kernel variant the batch can run gives the same
+    duals bit for bit (16-bit-id slot-major copies, 32-bit ones, row-major
+    copy with prices in LDS or from global memory)."""
+    dt = torch.float64 if dtype == "f64" else torch.float32
+    base = [batch_instance(b, scale=0.004) for b in range(4)]
+    ref = None
+    seen = []
+    for v in range(10):
+        monkeypatch.setenv("CBLP_BATCH_VARIANT", str(v))
+        _, probs, taus = _setup(cb, base, dt)
+        batch = cb.Batch(probs)
+        got_v = batch.info()["variant"]
+        etas = [p.zeros_eta() for p in probs]
+        batch.iterate(etas, 12, cb.make_params(rule=0, tau=1.0, check_every=4), tau_vecs=taus)
+        out = [e.cpu().numpy() for e in etas]
+        batch.close()
+        for p in probs:
+            p.close()
+        if got_v != v:
+            continue                            # not usable on these handles
+        seen.append(v)
+        if ref is None:
+            ref = out
+        for q, (a, b) in enumerate(zip(ref, out)):
+            assert np.array_equal(a, b), (v, q)
+    monkeypatch.delenv("CBLP_BATCH_VARIANT", raising=False)
+    assert 9 in seen and 7 in seen and 5 in seen, seen

@@ -248,3 +248,35 @@ def test_full_size_zipf_sampled(cb):
     assert g["Z"] == pytest.approx(float(np.dot(inst.lam.astype(np.float64), R)), rel=1e-6)
     Sg = S.cpu().numpy()
     assert np.all(Sg >= 0) and g["P"] == pytest.approx(float(np.dot(inst.r, Sg)), rel=1e-9)
+
+
+def test_resources_full_n_sampled(cb):
+    """The resource workload's product and resource counts (n = 1e5, m = 2e3:
+    prices past LDS, so the split-price slot kernel runs, with 32-bit ids) on
+    a quarter of its segments: R* of sampled segments against the oracle, and
+    u = A S, Z and P against host sums of the returned values."""
+    inst = config_instance(2, scale=0.25, n=100_000, m=2_000).cast(np.float32)
+    assert inst.n == 100_000 and inst.m == 2_000
+    prob = cb.Problem(inst, dtype=torch.float32)
+    rng = np.random.default_rng(9)
+    eta = rng.uniform(0, 30, inst.m).astype(np.float32)
+    S, u, R = prob.sales(prob.tensor(eta), seg_R=True)
+    R = R.double().cpu().numpy()
+    Sg = S.cpu().numpy()
+    rho = inst.r.astype(np.float64).copy()
+    for j in range(inst.n):
+        a, b = inst.a_ptr[j], inst.a_ptr[j + 1]
+        rho[j] -= float(np.dot(inst.a_val[a:b].astype(np.float64), eta[inst.a_idx[a:b]]))
+    for l in rng.choice(inst.L, 1500, replace=False):
+        b, e = inst.seg_ptr[l], inst.seg_ptr[l + 1]
+        Ro, _, _ = oracle.segment_response(rho[inst.idx[b:e]], inst.v[b:e], inst.w[b:e],
+                                           float(inst.v0[l]), float(inst.lam[l]))
+        assert R[l] == pytest.approx(Ro, rel=2e-5, abs=1e-5), l
+    u_host = np.zeros(inst.m)
+    np.add.at(u_host, inst.a_idx,
+              inst.a_val.astype(np.float64) * np.repeat(Sg, np.diff(inst.a_ptr)))
+    np.testing.assert_allclose(u.cpu().numpy(), u_host, rtol=1e-9, atol=1e-9)
+    g = prob.gap(prob.tensor(eta))
+    assert g["Z"] == pytest.approx(float(np.dot(inst.lam.astype(np.float64), R)), rel=1e-6)
+    assert np.all(Sg >= 0) and g["P"] == pytest.approx(float(np.dot(inst.r, Sg)), rel=1e-9)
+    prob.close()
