@@ -172,7 +172,23 @@ int run_segments(cblp_instance* h, void* seg_R, hipStream_t s)
     size_t slot;
     int rc = timed_begin(h, 0, s, &slot);
     if (rc) return rc;
-    HIP_TRY(launch_segments<T>(a, h->seg_grid, h->seg_variant, s));
+    if (seg_mixed(h->seg_variant)) {
+        // the quad part, positions [0, P), and the rest viewed from P
+        const int64_t P = h->quad_end;
+        const size_t esz = h->esz;
+        SegArgs b = a;
+        a.L = P;
+        b.L = h->L - P;
+        b.ptr = h->ptr2 + P;
+        b.vt0 = (const char*)h->vt0 + P * esz;
+        b.lam = (const char*)h->lam2 + P * esz;
+        b.Rwarm = (char*)h->Rwarm + P * esz;
+        b.perm = h->perm + P;
+        b.woff = h->woff + h->woff_b;
+        HIP_TRY(launch_segments_mixed<T>(a, b, h->seg_grid, h->seg_variant, s));
+    } else {
+        HIP_TRY(launch_segments<T>(a, h->seg_grid, h->seg_variant, s));
+    }
     return timed_end(h, slot, s);
 }
 
@@ -368,7 +384,7 @@ int create_impl(cblp_instance* h, hipStream_t s)
     HIP_TRY(hipStreamSynchronize(s));
     int64_t kmax = 0;
     for (int64_t l = 0; l < h->L; ++l) kmax = std::max(kmax, sp[l + 1] - sp[l]);
-    const bool short_rows = kmax <= 4 * kGroup;   // every row fits 4 register slots
+    const bool short_rows = kmax <= kQuadMaxRow;   // every row fits the quad kernels' registers
 
     // kernel variant and bin count may be overridden for tuning runs.  The
     // prices go to LDS when they take at most half of it, else the popular
@@ -376,10 +392,12 @@ int create_impl(cblp_instance* h, hipStream_t s)
     const bool prices_fit = (int64_t)h->n * (int64_t)sizeof(T) * 2 <= (int64_t)lds_block;
     // 16-bit product ids in the slot-major copy when they fit
     const bool ids16 = h->n <= 65536;
+    // FP32: rows of at most kQuadMaxRow entries go to 4-lane groups (the quad
+    // kernels when every row is that short, else the mixed ones)
     if (sizeof(T) == 4)
-        h->seg_variant = prices_fit ? (short_rows ? (ids16 ? kSegSlots16 + 1 : kSegSlotsJ4)
-                                                  : (ids16 ? kSegSlots16 : kSegSlots + 1))
-                                    : (short_rows ? kSegSlotsSplit + 1 : kSegSlotsSplit);
+        h->seg_variant = prices_fit ? (short_rows ? (ids16 ? kSegQuad : kSegQuad + 2)
+                                                  : (ids16 ? kSegMixed : kSegMixed + 1))
+                                    : (short_rows ? kSegQuad + 1 : kSegSlotsSplit);
     else
         h->seg_variant = ids16 ? kSegSlots16 + 2 : kSegSlots + 3;
     if (const char* ev = std::getenv("CBLP_SEG_VARIANT")) {
@@ -389,7 +407,12 @@ int create_impl(cblp_instance* h, hipStream_t s)
             h->seg_variant = x;
     }
     h->idx16 = seg_idx16(h->seg_variant);
-    h->hp = seg_split(h->seg_variant) ? (int)std::min<int64_t>(h->n, kSplitPrices) : 0;
+    int64_t split = kSplitPrices;   // head prices held in LDS by the split kernels
+    if (const char* es = std::getenv("CBLP_SPLIT_PRICES")) {
+        const long x = std::atol(es);
+        if (x >= 1 && x * (int64_t)sizeof(T) * 2 <= (int64_t)lds_block) split = x;
+    }
+    h->hp = seg_split(h->seg_variant) ? (int)std::min<int64_t>(h->n, split) : 0;
     const int64_t price_bytes = seg_split(h->seg_variant) ? (int64_t)h->hp * (int64_t)sizeof(T)
                                 : seg_lds_prices(h->seg_variant) ? h->n * (int64_t)sizeof(T) : 0;
     const int64_t lds_bins = ((int64_t)lds_block - 1024 - price_bytes) / 8;
@@ -525,25 +548,56 @@ int create_impl(cblp_instance* h, hipStream_t s)
                                        h->perm, h->pnew, h->ptr2, h->idx2, h->v2, h->den2, h->vt0,
                                        h->lam2, h->Rwarm, h->v0c, s));
         if (seg_slot_major(h->seg_variant)) {
-            // slot-major copy: wave-tile w (positions 8w..8w+7) gets 64 entries per
-            // slot for as many slots as its longest row needs (at least one)
-            const int64_t W = (h->L + kGroup - 1) / kGroup;
-            std::vector<int64_t> woff((size_t)W + 2, 0);   // one spare entry
-            for (int64_t w = 0; w < W; ++w) {
-                int64_t kw = 0;
-                for (int64_t p = w * kGroup; p < std::min(h->L, (w + 1) * kGroup); ++p)
-                    kw = std::max(kw, ptr[p + 1] - ptr[p]);
-                woff[w + 1] = woff[w] + 64 * std::max<int64_t>(1, (kw + kGroup - 1) / kGroup);
+            // slot-major copy: wave-tile w (positions Rw..Rw+R-1, R = 64 / G rows
+            // of G lanes) gets 64 entries per slot for as many slots as its
+            // longest row needs (at least one).  Mixed variants: positions
+            // [0, P) (rows of at most kQuadMaxRow entries; rows ascend) in the
+            // quad layout, the rest in the 8-lane one behind it, each with its
+            // own offsets (one spare entry each)
+            const bool mixed = seg_mixed(h->seg_variant);
+            int64_t P = seg_quad(h->seg_variant) ? h->L : 0;
+            if (mixed)
+                while (P < h->L && ptr[P + 1] - ptr[P] <= kQuadMaxRow) ++P;
+            h->quad_end = P;
+            std::vector<int64_t> woff;
+            auto part = [&](int64_t p0, int64_t p1, int64_t G) {
+                const int64_t R = 64 / G, W = (p1 - p0 + R - 1) / R;
+                const size_t w0 = woff.size();
+                woff.push_back(w0 == 0 ? 0 : woff.back());
+                for (int64_t w = 0; w < W; ++w) {
+                    int64_t kw = 0;
+                    for (int64_t p = p0 + w * R; p < std::min(p1, p0 + (w + 1) * R); ++p)
+                        kw = std::max(kw, ptr[p + 1] - ptr[p]);
+                    woff.push_back(woff.back() + 64 * std::max<int64_t>(1, (kw + G - 1) / G));
+                }
+                woff.push_back(woff.back());
+                return w0;
+            };
+            const bool quad = seg_quad(h->seg_variant);
+            if (mixed) {
+                part(0, P, 4);
+                h->woff_b = (int64_t)part(P, h->L, kGroup);
+            } else {
+                part(0, h->L, quad ? 4 : kGroup);
             }
-            const int64_t entries = woff[W] + 64 * kMaxJ;   // loads may run J slots past the end
-            woff[W + 1] = woff[W];
-            if ((rc = dalloc(&h->woff, (size_t)(W + 2) * 8))) return rc;
+            const int64_t entries = woff.back() + 64 * kMaxJ;   // loads may run J slots past the end
+            if ((rc = dalloc(&h->woff, woff.size() * 8))) return rc;
             if ((rc = dalloc(&h->idx3, (size_t)entries * (h->idx16 ? 2 : 4)))) return rc;
             if ((rc = dalloc(&h->v3, (size_t)entries * esz))) return rc;
             if ((rc = dalloc(&h->den3, (size_t)entries * esz))) return rc;
-            HIP_TRY(hipMemcpyAsync(h->woff, woff.data(), (W + 2) * 8, hipMemcpyHostToDevice, s));
-            HIP_TRY(launch_relayout_slots<T>(h->L, h->ptr2, h->idx2, h->v2, h->den2, h->woff,
-                                             entries, h->idx3, h->idx16, h->v3, h->den3, s));
+            HIP_TRY(hipMemcpyAsync(h->woff, woff.data(), woff.size() * 8, hipMemcpyHostToDevice, s));
+            if (mixed) {
+                HIP_TRY(launch_relayout_slots<T>(P, h->ptr2, h->idx2, h->v2, h->den2, h->woff,
+                                                 entries, h->idx3, h->idx16, true, h->v3, h->den3,
+                                                 s));
+                HIP_TRY(launch_relayout_slots<T>(h->L - P, h->ptr2 + P, h->idx2, h->v2, h->den2,
+                                                 h->woff + h->woff_b, 0, h->idx3, h->idx16, false,
+                                                 h->v3, h->den3, s));
+            } else {
+                HIP_TRY(launch_relayout_slots<T>(h->L, h->ptr2, h->idx2, h->v2, h->den2, h->woff,
+                                                 entries, h->idx3, h->idx16, quad, h->v3, h->den3,
+                                                 s));
+            }
         }
         HIP_TRY(hipStreamSynchronize(s));   // the host vectors die here
     }

@@ -121,10 +121,11 @@ hipError_t launch_relayout(int64_t L, const int64_t* seg_ptr, const int32_t* idx
 hipError_t launch_degree(int64_t nnz, const int32_t* idx, int64_t n, unsigned long long* deg,
                          hipStream_t s);
 template <typename T>
+// quad: the 4-lane layout of the quad kernels, else the 8-lane one
 hipError_t launch_relayout_slots(int64_t L, const int64_t* ptr, const int32_t* idx2,
                                  const void* v2, const void* den2, const int64_t* woff,
-                                 int64_t entries, void* idx3, bool idx16, void* v3, void* den3,
-                                 hipStream_t s);
+                                 int64_t entries, void* idx3, bool idx16, bool quad, void* v3,
+                                 void* den3, hipStream_t s);
 template <typename T>
 hipError_t launch_prices(int64_t n, const void* r, const void* eta, const int64_t* a_ptr,
                          const int32_t* a_idx, const void* a_val, const int32_t* pnew, void* rho,
@@ -136,7 +137,7 @@ hipError_t launch_prices(int64_t n, const void* r, const void* eta, const int64_
 // Variant kSegSplit holds the prices of products [0, hp) in LDS.  Variants
 // kSegSlots and up read the slot-major copy (see SegArgs::woff); of these,
 // kSegSlotsSplit and kSegSlotsSplit + 1 hold the prices as kSegSplit does.
-constexpr int kSegVariants = 32;
+constexpr int kSegVariants = 37;
 constexpr int kSegSlots = 20;
 constexpr int kSegSlotsSplit = 26;
 constexpr int kSegSlotsJ4 = 28;        // 4 register slots, prices in LDS
@@ -144,14 +145,29 @@ constexpr int kSegSlotsJ4 = 28;        // 4 register slots, prices in LDS
 // the slot-major copy (n <= 65536): 10 bytes per FP32 entry instead of 12,
 // 18 per FP64 entry instead of 20
 constexpr int kSegSlots16 = 29;
-inline bool seg_idx16(int variant) { return variant >= kSegSlots16 && variant <= kSegSlots16 + 2; }
+// quad layout (4-lane groups, 16 rows per wave; rows of at most 32 entries
+// in registers): 32 16-bit ids and LDS prices, 33 32-bit ids and split
+// prices, 34 32-bit ids and LDS prices
+constexpr int kSegQuad = 32;
+inline bool seg_quad(int variant) { return variant >= kSegQuad && variant <= kSegQuad + 2; }
+// mixed: rows of at most 32 entries in the quad layout, longer rows in the
+// 8-lane one, prices in LDS (35: 16-bit ids, 36: 32-bit ids)
+constexpr int kSegMixed = 35;
+constexpr int kQuadMaxRow = 32;        // rows held in registers by the quad kernels
+inline bool seg_mixed(int variant) { return variant == kSegMixed || variant == kSegMixed + 1; }
+inline bool seg_idx16(int variant)
+{
+    return (variant >= kSegSlots16 && variant <= kSegSlots16 + 2) || variant == kSegQuad ||
+           variant == kSegMixed;
+}
 inline bool seg_slot_major(int variant) { return variant >= kSegSlots; }
 constexpr int kSegLdsPrices = 10;
 constexpr int kSegClassLds = 17, kSegClassGlobal = 18, kSegSplit = 19;
 constexpr int kSplitPrices = 8192;     // head prices of the split kernel
 inline bool seg_split(int variant)
 {
-    return variant == kSegSplit || variant == kSegSlotsSplit || variant == kSegSlotsSplit + 1;
+    return variant == kSegSplit || variant == kSegSlotsSplit || variant == kSegSlotsSplit + 1 ||
+           variant == kSegQuad + 1;
 }
 inline bool seg_class(int variant) { return variant == kSegClassLds || variant == kSegClassGlobal; }
 // most register slots of the size-class kernels per element size
@@ -168,6 +184,10 @@ inline size_t seg_lds_bytes(int H, int64_t n, size_t esz, int variant)
 }
 template <typename T>
 hipError_t launch_segments(const SegArgs& a, int grid, int variant, hipStream_t s);
+// mixed variants: a = the quad part (positions [0, P)), b = the rest
+template <typename T>
+hipError_t launch_segments_mixed(const SegArgs& a, const SegArgs& b, int grid, int variant,
+                                 hipStream_t s);
 template <typename T>
 int segment_blocks_per_cu(int H, int64_t n, int variant);   // resident blocks per CU
 template <typename T>

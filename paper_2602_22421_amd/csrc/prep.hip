@@ -121,17 +121,20 @@ __global__ void k_fill(T* p, int64_t n, T val)
 // Slot-major copy: the eight rows of wave-tile w = p / 8 occupy woff[w] ..
 // woff[w + 1] (64 entries per slot); entry t of row p goes to slot t / 8 at
 // lane 8 (p % 8) + t % 8.  Unused places keep (product 0, v 0, den 1).
-template <typename T, typename IdxT>
+// G = 4 (quad layout): rows 16w..16w+15 per wave-tile, entry t of row p at
+// slot t / 4, lane 4 (p % 16) + t % 4.
+template <typename T, typename IdxT, int G>
 __global__ void k_relayout_slots(int64_t L, const int64_t* ptr, const int32_t* idx2,
                                  const T* v2, const T* den2, const int64_t* woff, IdxT* idx3,
                                  T* v3, T* den3)
 {
+    constexpr int R = 64 / G;   // rows per wave-tile
     for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < L;
          p += (int64_t)gridDim.x * blockDim.x) {
         const int64_t b = ptr[p], k = ptr[p + 1] - b;
-        const int64_t base = woff[p >> 3] + 8 * (p & 7);
+        const int64_t base = woff[p / R] + G * (p % R);
         for (int64_t t = 0; t < k; ++t) {
-            const int64_t d = base + 64 * (t >> 3) + (t & 7);
+            const int64_t d = base + 64 * (t / G) + (t % G);
             idx3[d] = (IdxT)idx2[b + t];
             v3[d] = v2[b + t];
             den3[d] = den2[b + t];
@@ -227,8 +230,8 @@ hipError_t launch_relayout(int64_t L, const int64_t* seg_ptr, const int32_t* idx
 template <typename T>
 hipError_t launch_relayout_slots(int64_t L, const int64_t* ptr, const int32_t* idx2,
                                  const void* v2, const void* den2, const int64_t* woff,
-                                 int64_t entries, void* idx3, bool idx16, void* v3, void* den3,
-                                 hipStream_t s)
+                                 int64_t entries, void* idx3, bool idx16, bool quad, void* v3,
+                                 void* den3, hipStream_t s)
 {
     if (idx16)
         hipLaunchKernelGGL(k_fill<uint16_t>, dim3(1024), dim3(256), 0, s, (uint16_t*)idx3, entries,
@@ -237,12 +240,20 @@ hipError_t launch_relayout_slots(int64_t L, const int64_t* ptr, const int32_t* i
         hipLaunchKernelGGL(k_fill<int32_t>, dim3(1024), dim3(256), 0, s, (int32_t*)idx3, entries, 0);
     hipLaunchKernelGGL(k_fill<T>, dim3(1024), dim3(256), 0, s, (T*)v3, entries, T(0));
     hipLaunchKernelGGL(k_fill<T>, dim3(1024), dim3(256), 0, s, (T*)den3, entries, T(1));
-    if (L > 0 && idx16)
-        hipLaunchKernelGGL((k_relayout_slots<T, uint16_t>), dim3(2048), dim3(256), 0, s, L, ptr,
+    if (L > 0 && idx16 && quad)
+        hipLaunchKernelGGL((k_relayout_slots<T, uint16_t, 4>), dim3(2048), dim3(256), 0, s, L, ptr,
+                           idx2, (const T*)v2, (const T*)den2, woff, (uint16_t*)idx3, (T*)v3,
+                           (T*)den3);
+    else if (L > 0 && quad)
+        hipLaunchKernelGGL((k_relayout_slots<T, int32_t, 4>), dim3(2048), dim3(256), 0, s, L, ptr,
+                           idx2, (const T*)v2, (const T*)den2, woff, (int32_t*)idx3, (T*)v3,
+                           (T*)den3);
+    else if (L > 0 && idx16)
+        hipLaunchKernelGGL((k_relayout_slots<T, uint16_t, 8>), dim3(2048), dim3(256), 0, s, L, ptr,
                            idx2, (const T*)v2, (const T*)den2, woff, (uint16_t*)idx3, (T*)v3,
                            (T*)den3);
     else if (L > 0)
-        hipLaunchKernelGGL((k_relayout_slots<T, int32_t>), dim3(2048), dim3(256), 0, s, L, ptr,
+        hipLaunchKernelGGL((k_relayout_slots<T, int32_t, 8>), dim3(2048), dim3(256), 0, s, L, ptr,
                            idx2, (const T*)v2, (const T*)den2, woff, (int32_t*)idx3, (T*)v3,
                            (T*)den3);
     return hipGetLastError();
@@ -277,7 +288,8 @@ hipError_t launch_prices(int64_t n, const void* r, const void* eta, const int64_
                                            hipStream_t);                                       \
     template hipError_t launch_relayout_slots<T>(int64_t, const int64_t*, const int32_t*,      \
                                                  const void*, const void*, const int64_t*,     \
-                                                 int64_t, void*, bool, void*, void*, hipStream_t);
+                                                 int64_t, void*, bool, bool, void*, void*,       \
+                                                 hipStream_t);
 CBLP_INST(float)
 CBLP_INST(double)
 #undef CBLP_INST

@@ -149,6 +149,81 @@ __global__ void __launch_bounds__(kSegThreads) k_segments_slots_split(SegArgs a)
     }
 }
 
+// Quad-layout kernel (4-lane groups, 16 rows per wave) over the slot-major
+// copy in quad layout; prices all in LDS, or split (head [0, a.hp) in LDS).
+template <typename T, int J, typename IdxT, bool SPLIT>
+__global__ void __launch_bounds__(kSegThreads) k_segments_quad(SegArgs a)
+{
+    extern __shared__ unsigned long long bins[];   // [a.H], then the LDS prices
+    __shared__ double zsh[kSegThreads / 64];
+    const int H = a.H;
+    T* lprice = (T*)(bins + H);
+    for (int j = threadIdx.x; j < H; j += kSegThreads) bins[j] = 0ull;
+    const int64_t np = SPLIT ? (int64_t)a.hp : a.n;
+    for (int64_t j = threadIdx.x; j < np; j += kSegThreads) lprice[j] = ((const T*)a.rho)[j];
+    __syncthreads();
+
+    double zacc = 0.0;
+    const int64_t tiles = (a.L + seg::kQuadTileRows - 1) / seg::kQuadTileRows;
+    if (SPLIT) {
+        const seg::SplitPrices<T> pr{(const T*)lprice, (const T*)a.rho, a.hp};
+        seg::process_tiles_quad<T, J, seg::SplitPrices<T>, IdxT>(a, blockIdx.x, tiles, gridDim.x,
+                                                                 bins, pr, zacc);
+    } else {
+        const seg::FlatPrices<T> pr{(const T*)lprice};
+        seg::process_tiles_quad<T, J, seg::FlatPrices<T>, IdxT>(a, blockIdx.x, tiles, gridDim.x,
+                                                                bins, pr, zacc);
+    }
+
+    __syncthreads();
+    flush_bins(a, bins);
+    for (int o = 32; o > 0; o >>= 1) zacc += __shfl_down(zacc, o, 64);
+    if ((threadIdx.x & 63) == 0) zsh[threadIdx.x >> 6] = zacc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double z = zsh[0];
+        for (int q = 1; q < kSegThreads / 64; ++q) z += zsh[q];
+        a.zpart[blockIdx.x] = z;
+    }
+}
+
+// Mixed kernel: positions [0, P) (rows of at most 32 entries) in the quad
+// layout, solved by 4-lane groups (args a, L = P), then positions [P, L) in
+// the 8-lane slot-major layout (args b: the same instance viewed from P).
+// One launch: the blocks share the LDS prices and bins over both parts.
+template <typename T, typename IdxT>
+__global__ void __launch_bounds__(kSegThreads) k_segments_mixed(SegArgs a, SegArgs b)
+{
+    extern __shared__ unsigned long long bins[];   // [a.H], then [a.n] prices
+    __shared__ double zsh[kSegThreads / 64];
+    const int H = a.H;
+    T* lprice = (T*)(bins + H);
+    for (int j = threadIdx.x; j < H; j += kSegThreads) bins[j] = 0ull;
+    for (int64_t j = threadIdx.x; j < a.n; j += kSegThreads) lprice[j] = ((const T*)a.rho)[j];
+    __syncthreads();
+
+    double zacc = 0.0;
+    const seg::FlatPrices<T> pr{(const T*)lprice};
+    const int64_t ta = (a.L + seg::kQuadTileRows - 1) / seg::kQuadTileRows;
+    seg::process_tiles_quad<T, 8, seg::FlatPrices<T>, IdxT>(a, blockIdx.x, ta, gridDim.x, bins, pr,
+                                                            zacc);
+    const int64_t tb = (b.L + kSegsPerTile - 1) / kSegsPerTile;
+    seg::process_tiles_slots<T, 7, false, seg::FlatPrices<T>, false, IdxT>(b, blockIdx.x, tb,
+                                                                          gridDim.x, bins, pr,
+                                                                          zacc);
+
+    __syncthreads();
+    flush_bins(a, bins);
+    for (int o = 32; o > 0; o >>= 1) zacc += __shfl_down(zacc, o, 64);
+    if ((threadIdx.x & 63) == 0) zsh[threadIdx.x >> 6] = zacc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double z = zsh[0];
+        for (int q = 1; q < kSegThreads / 64; ++q) z += zsh[q];
+        a.zpart[blockIdx.x] = z;
+    }
+}
+
 // Size-class kernel: block b solves tiles [blk[b][1], blk[b][2]) with
 // blk[b][0] register slots per lane.  The layout is sorted by row length, so
 // a run of tiles has one slot count, and loading every slot of it wastes no
@@ -243,8 +318,23 @@ const void* SegVariant<T>::fn(int variant)
     case kSegSlots16: return (const void*)k_segments_slots<T, 7, false, true, false, uint16_t>;
     case kSegSlots16 + 1: return (const void*)k_segments_slots<T, 4, false, true, false, uint16_t>;
     case kSegSlots16 + 2: return (const void*)k_segments_slots<T, 4, true, false, false, uint16_t>;
+    case kSegQuad: return (const void*)k_segments_quad<T, 8, uint16_t, false>;
+    case kSegQuad + 1: return (const void*)k_segments_quad<T, 8, int32_t, true>;
+    case kSegQuad + 2: return (const void*)k_segments_quad<T, 8, int32_t, false>;
+    case kSegMixed: return (const void*)k_segments_mixed<T, uint16_t>;
+    case kSegMixed + 1: return (const void*)k_segments_mixed<T, int32_t>;
     default: return (const void*)k_segments<T, 4, 1, false>;
     }
+}
+
+template <typename T>
+hipError_t launch_segments_mixed(const SegArgs& a, const SegArgs& b, int grid, int variant,
+                                 hipStream_t s)
+{
+    const size_t lds = seg_lds_bytes(a.H, a.n, sizeof(T), variant);
+    void* args[] = {(void*)&a, (void*)&b};
+    return hipLaunchKernel(SegVariant<T>::fn(variant), dim3(grid), dim3(kSegThreads), args, lds,
+                           s);
 }
 
 template <typename T>
@@ -269,6 +359,10 @@ int segment_blocks_per_cu(int H, int64_t n, int variant)   // n: prices held in 
 }
 
 template hipError_t launch_segments<float>(const SegArgs&, int, int, hipStream_t);
+template hipError_t launch_segments_mixed<float>(const SegArgs&, const SegArgs&, int, int,
+                                                 hipStream_t);
+template hipError_t launch_segments_mixed<double>(const SegArgs&, const SegArgs&, int, int,
+                                                  hipStream_t);
 template hipError_t launch_segments<double>(const SegArgs&, int, int, hipStream_t);
 template int segment_blocks_per_cu<float>(int, int64_t, int);
 template int segment_blocks_per_cu<double>(int, int64_t, int);

@@ -685,5 +685,202 @@ __device__ __forceinline__ void process_tiles_slots(const SegArgs& a, int64_t ti
     if (TOUCH && sink == 0x9E3779B9u && a.L < 0) a.zpart[0] = 0.0;   // keeps the touches
 }
 
+// ---------------------------------------------------------------------------
+// Quad layout: 4-lane groups, 16 rows per wave (wave-tile w = positions
+// 16w..16w+15, woff in units of these wave-tiles), entry t of row 16w+q at
+// slot t / 4, lane 4q + t % 4.  For short rows this halves the per-row share
+// of every per-tile step.  A lane keeps two partial sums, one for the slots of
+// even index (the entries an 8-lane group's lane l = t % 8 < 4 would hold) and
+// one for the odd slots (lane l + 4), and the quad sum below adds them in the
+// order of group_sum, so the results are the 8-lane kernels' bits.
+constexpr int kQuad = 4;
+constexpr int kQuadRows = 64 / kQuad;                         // rows per wave-tile
+constexpr int kQuadTileRows = kSegThreads / 64 * kQuadRows;   // rows per block step
+
+template <typename X>
+__device__ __forceinline__ X quad_sum(X lo, X hi)
+{
+    // lane j of the quad: x_j + x_(7-j) of the 8-lane sum is lo_j + hi_(3-j)
+    X x = lo + dpp_move<0x1B>(hi);
+    x += dpp_move<kQuadSwap2>(x);
+    x += dpp_move<kQuadSwap1>(x);
+    return x;
+}
+
+template <typename T>
+__device__ __forceinline__ WaveBounds<T> load_wave_bounds_quad(const SegArgs& a, int64_t t, int wv,
+                                                              int q)
+{
+    const int64_t W = (a.L + kQuadRows - 1) / kQuadRows;
+    const int64_t w = t * (kSegThreads / 64) + wv;
+    const int64_t wc = w < W ? w : 0;
+    WaveBounds<T> B;
+    B.b0 = a.woff[wc];
+    B.b1 = a.woff[wc + 1];
+    B.wlive = w < W;
+    const int64_t p = w * kQuadRows + q;
+    const int64_t pc = p < a.L ? p : 0;
+    B.vt0 = ((const T*)a.vt0)[pc];
+    B.lam = ((const T*)a.lam)[pc];
+    B.R0 = ((const T*)a.Rwarm)[pc];
+    B.live = p < a.L;
+    return B;
+}
+
+template <typename T, int J, typename PR, typename IdxT>
+__device__ __forceinline__ void process_tiles_quad(const SegArgs& a, int64_t tile, int64_t tiles,
+                                                   int64_t stride, unsigned long long* bins,
+                                                   const PR& rho, double& zacc)
+{
+    const T* __restrict__ v3 = (const T*)a.v3;
+    const T* __restrict__ d3 = (const T*)a.den3;
+    const IdxT* __restrict__ i3 = (const IdxT*)a.idx3;
+    const int H = a.H;
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    const int q = lane / kQuad;
+    if (tile >= tiles) return;
+
+    WaveBounds<T> Bc = load_wave_bounds_quad<T>(a, tile, wv, q);
+    Raw<T, J> Rc = load_slots<T, J, false, IdxT>(a, Bc, lane);
+    WaveBounds<T> B1 = load_wave_bounds_quad<T>(a, tile + stride, wv, q);
+    WaveBounds<T> B2;
+    T Pc[J];
+    for (; tile < tiles; tile += stride) {
+        gather<T, J, true, PR>(rho, Rc, Pc, J);
+        __builtin_amdgcn_sched_barrier(0);
+        const Raw<T, J> R1 = load_slots<T, J, false, IdxT>(a, B1, lane);
+        B2 = load_wave_bounds_quad<T>(a, tile + 2 * stride, wv, q);
+
+        const int jw = wave_jw(Bc);
+        const int64_t base = wave_base(Bc);
+        const int js = jw < J ? jw : J;
+        const T vt0 = Bc.vt0;
+        T num[J], den[J];
+#pragma unroll
+        for (int s = 0; s < J; ++s) {
+            num[s] = s < js ? Pc[s] * Rc.v[s] : T(0);
+            den[s] = Rc.den[s];
+        }
+        unsigned long long mask[J];
+        auto full = [&](T R, T& N, T& Dn) {
+            T n0 = T(0), n1 = T(0), d0 = T(0), d1 = T(0);
+#pragma unroll
+            for (int s = 0; s < J; ++s) {
+                mask[s] = 0ull;
+                if (s >= js) continue;
+                const bool in = num[s] > R * den[s];
+                mask[s] = __ballot(in);
+                const T w = in ? T(1) : T(0);
+                if (s & 1) {
+                    n1 = fmadd(w, num[s], n1);
+                    d1 = fmadd(w, den[s], d1);
+                } else {
+                    n0 = fmadd(w, num[s], n0);
+                    d0 = fmadd(w, den[s], d0);
+                }
+            }
+            for (int s = J; s < jw; ++s) {            // slots past the registers
+                const int64_t e = base + 64 * s + lane;
+                const T nn = rho[i3[e]] * v3[e];
+                const T dd = d3[e];
+                const T w = nn > R * dd ? T(1) : T(0);
+                if (s & 1) {
+                    n1 = fmadd(w, nn, n1);
+                    d1 = fmadd(w, dd, d1);
+                } else {
+                    n0 = fmadd(w, nn, n0);
+                    d0 = fmadd(w, dd, d0);
+                }
+            }
+            N = quad_sum(n0, n1);
+            Dn = quad_sum(d0, d1);
+        };
+        auto changed = [&](T R, T Rn) {
+            unsigned long long diff = 0ull;
+#pragma unroll
+            for (int s = 0; s < J; ++s) {
+                if (s >= js) break;
+                diff |= __ballot(num[s] > Rn * den[s]) ^ mask[s];
+            }
+            if (jw > J) {
+                bool t = false;
+                for (int s = J; s < jw; ++s) {
+                    const int64_t e = base + 64 * s + lane;
+                    const T nn = rho[i3[e]] * v3[e];
+                    const T dd = d3[e];
+                    t = t || ((nn > Rn * dd) != (nn > R * dd));
+                }
+                diff |= __ballot(t);
+            }
+            return diff;
+        };
+        // Dinkelbach with the same start, round cap (in entries of the wave's
+        // longest row, rounded to 8) and cycle rule as the 8-lane kernels
+        T R = Bc.R0, N, Dn;
+        full(R, N, Dn);
+        T Rs = N > T(0) ? ratio(N, vt0 + Dn) : T(0);
+        T pR = R, pN = N, pD = Dn, pRs = Rs;
+        unsigned long long diff = 0ull;
+        const int cap = kGroup * ((kQuad * jw + kGroup - 1) / kGroup) + 1;
+        for (int round = 0; round <= cap; ++round) {
+            diff = changed(R, Rs);
+            if (diff == 0ull) break;
+            pR = R;
+            pN = N;
+            pD = Dn;
+            pRs = Rs;
+            R = Rs;
+            full(R, N, Dn);
+            Rs = N > T(0) ? ratio(N, vt0 + Dn) : T(0);
+        }
+        if (diff != 0ull) {
+            const unsigned long long now = changed(R, Rs);
+            const bool cycling = ((now >> (threadIdx.x & 60)) & 0xFull) != 0ull;
+            if (cycling && pRs > Rs) {
+                R = pR;
+                N = pN;
+                Dn = pD;
+                Rs = pRs;
+            }
+        }
+        const T Rstar = Rs;
+        const T lamD = ratio(Bc.lam, vt0 + Dn) * (T)a.fx_scale;
+#pragma unroll
+        for (int s = 0; s < J; ++s) {
+            if (s >= js) break;
+            if (num[s] > R * den[s]) {
+                const unsigned long long qv = quantum(lamD, Rc.v[s]);
+                const int32_t j = Rc.id[s];
+                if (j < H)
+                    atomicAdd(&bins[j], qv);
+                else
+                    atomicAdd(&a.S_fx[j], qv);
+            }
+        }
+        for (int s = J; s < jw; ++s) {
+            const int64_t e = base + 64 * s + lane;
+            const T x = v3[e];
+            const int32_t j = (int32_t)i3[e];
+            if (rho[j] * x > R * d3[e]) {
+                const unsigned long long qq = quantum(lamD, x);
+                if (j < H)
+                    atomicAdd(&bins[j], qq);
+                else
+                    atomicAdd(&a.S_fx[j], qq);
+            }
+        }
+        if ((lane & (kQuad - 1)) == 0 && Bc.live) {
+            const int64_t p = (tile * (kSegThreads / 64) + wv) * kQuadRows + q;
+            zacc += (double)Bc.lam * (double)Rstar;
+            ((T*)a.Rwarm)[p] = Rstar;
+            if (a.seg_R) ((T*)a.seg_R)[a.perm[p]] = Rstar;
+        }
+        Bc = B1;
+        Rc = R1;
+        B1 = B2;
+    }
+}
+
 }  // namespace seg
 }  // namespace cblp

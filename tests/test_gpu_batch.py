@@ -135,6 +135,10 @@ def test_batch_variants_agree(cb, dtype, monkeypatch):
     copy with prices in LDS or from global memory)."""
     dt = torch.float64 if dtype == "f64" else torch.float32
     base = [batch_instance(b, scale=0.004) for b in range(4)]
+    # handles with the 8-lane slot-major copy with 16-bit ids (the FP64
+    # default; FP32 defaults to the 4-lane layouts, which the batch does not read)
+    if dtype == "f32":
+        monkeypatch.setenv("CBLP_SEG_VARIANT", "29")
     ref = None
     seen = []
     for v in range(10):
@@ -156,4 +160,5 @@ def test_batch_variants_agree(cb, dtype, monkeypatch):
         for q, (a, b) in enumerate(zip(ref, out)):
             assert np.array_equal(a, b), (v, q)
     monkeypatch.delenv("CBLP_BATCH_VARIANT", raising=False)
+    monkeypatch.delenv("CBLP_SEG_VARIANT", raising=False)
     assert 9 in seen and 7 in seen and 5 in seen, seen
