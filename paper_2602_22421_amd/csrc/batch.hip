@@ -586,7 +586,8 @@ int cblp_batch_create(cblp_batch_t* out, int32_t count, const cblp_t* handles, v
     for (int q = 0; q < count; ++q) {
         b->nmax = std::max<int64_t>(b->nmax, b->hs[q]->n);
         const bool slots8 = b->hs[q]->woff != nullptr && !seg_quad(b->hs[q]->seg_variant) &&
-                            !seg_mixed(b->hs[q]->seg_variant);
+                            !seg_mixed(b->hs[q]->seg_variant) &&
+                            !seg_mixed3(b->hs[q]->seg_variant);
         b->slots_ok = b->slots_ok && slots8 && !b->hs[q]->idx16;
         b->slots16_ok = b->slots16_ok && slots8 && b->hs[q]->idx16;
     }

@@ -172,7 +172,25 @@ int run_segments(cblp_instance* h, void* seg_R, hipStream_t s)
     size_t slot;
     int rc = timed_begin(h, 0, s, &slot);
     if (rc) return rc;
-    if (seg_mixed(h->seg_variant)) {
+    if (seg_mixed3(h->seg_variant)) {
+        // views of the pair part [0, P2), the quad part [P2, P4) and the rest
+        const int64_t P2 = h->pair_end, P4 = h->quad_end;
+        const size_t esz = h->esz;
+        auto view = [&](int64_t p0, int64_t p1, int64_t wo) {
+            SegArgs v = a;
+            v.L = p1 - p0;
+            v.ptr = h->ptr2 + p0;
+            v.vt0 = (const char*)h->vt0 + p0 * esz;
+            v.lam = (const char*)h->lam2 + p0 * esz;
+            v.Rwarm = (char*)h->Rwarm + p0 * esz;
+            v.perm = h->perm + p0;
+            v.woff = h->woff + wo;
+            return v;
+        };
+        const SegArgs a2 = view(0, P2, 0), a4 = view(P2, P4, h->woff_q),
+                      a8 = view(P4, h->L, h->woff_b);
+        HIP_TRY(launch_segments_mixed3<T>(a2, a4, a8, h->seg_grid, h->seg_variant, s));
+    } else if (seg_mixed(h->seg_variant)) {
         // the quad part, positions [0, P), and the rest viewed from P
         const int64_t P = h->quad_end;
         const size_t esz = h->esz;
@@ -392,11 +410,12 @@ int create_impl(cblp_instance* h, hipStream_t s)
     const bool prices_fit = (int64_t)h->n * (int64_t)sizeof(T) * 2 <= (int64_t)lds_block;
     // 16-bit product ids in the slot-major copy when they fit
     const bool ids16 = h->n <= 65536;
-    // FP32: rows of at most kQuadMaxRow entries go to 4-lane groups (the quad
-    // kernels when every row is that short, else the mixed ones)
+    // FP32: rows of at most kPairMaxRow entries go to 2-lane groups, of at most
+    // kQuadMaxRow to 4-lane groups, longer ones to 8-lane groups (the
+    // three-part mixed kernels); with split prices, the quad kernel when every
+    // row fits it
     if (sizeof(T) == 4)
-        h->seg_variant = prices_fit ? (short_rows ? (ids16 ? kSegQuad : kSegQuad + 2)
-                                                  : (ids16 ? kSegMixed : kSegMixed + 1))
+        h->seg_variant = prices_fit ? (ids16 ? kSegMixed3 : kSegMixed3 + 1)
                                     : (short_rows ? kSegQuad + 1 : kSegSlotsSplit);
     else
         h->seg_variant = ids16 ? kSegSlots16 + 2 : kSegSlots + 3;
@@ -554,10 +573,15 @@ int create_impl(cblp_instance* h, hipStream_t s)
             // [0, P) (rows of at most kQuadMaxRow entries; rows ascend) in the
             // quad layout, the rest in the 8-lane one behind it, each with its
             // own offsets (one spare entry each)
-            const bool mixed = seg_mixed(h->seg_variant);
-            int64_t P = seg_quad(h->seg_variant) ? h->L : 0;
-            if (mixed)
+            const bool mixed = seg_mixed(h->seg_variant), mixed3 = seg_mixed3(h->seg_variant);
+            int64_t P2 = 0, P = seg_quad(h->seg_variant) ? h->L : 0;
+            if (mixed3)
+                while (P2 < h->L && ptr[P2 + 1] - ptr[P2] <= kPairMaxRow) ++P2;
+            if (mixed || mixed3) {
+                P = P2;
                 while (P < h->L && ptr[P + 1] - ptr[P] <= kQuadMaxRow) ++P;
+            }
+            h->pair_end = P2;
             h->quad_end = P;
             std::vector<int64_t> woff;
             auto part = [&](int64_t p0, int64_t p1, int64_t G) {
@@ -574,7 +598,11 @@ int create_impl(cblp_instance* h, hipStream_t s)
                 return w0;
             };
             const bool quad = seg_quad(h->seg_variant);
-            if (mixed) {
+            if (mixed3) {
+                part(0, P2, 2);
+                h->woff_q = (int64_t)part(P2, P, 4);
+                h->woff_b = (int64_t)part(P, h->L, kGroup);
+            } else if (mixed) {
                 part(0, P, 4);
                 h->woff_b = (int64_t)part(P, h->L, kGroup);
             } else {
@@ -586,17 +614,25 @@ int create_impl(cblp_instance* h, hipStream_t s)
             if ((rc = dalloc(&h->v3, (size_t)entries * esz))) return rc;
             if ((rc = dalloc(&h->den3, (size_t)entries * esz))) return rc;
             HIP_TRY(hipMemcpyAsync(h->woff, woff.data(), woff.size() * 8, hipMemcpyHostToDevice, s));
-            if (mixed) {
-                HIP_TRY(launch_relayout_slots<T>(P, h->ptr2, h->idx2, h->v2, h->den2, h->woff,
-                                                 entries, h->idx3, h->idx16, true, h->v3, h->den3,
-                                                 s));
+            if (mixed3) {
+                HIP_TRY(launch_relayout_slots<T>(P2, h->ptr2, h->idx2, h->v2, h->den2, h->woff,
+                                                 entries, h->idx3, h->idx16, 2, h->v3, h->den3, s));
+                HIP_TRY(launch_relayout_slots<T>(P - P2, h->ptr2 + P2, h->idx2, h->v2, h->den2,
+                                                 h->woff + h->woff_q, 0, h->idx3, h->idx16, 4,
+                                                 h->v3, h->den3, s));
                 HIP_TRY(launch_relayout_slots<T>(h->L - P, h->ptr2 + P, h->idx2, h->v2, h->den2,
-                                                 h->woff + h->woff_b, 0, h->idx3, h->idx16, false,
+                                                 h->woff + h->woff_b, 0, h->idx3, h->idx16, kGroup,
+                                                 h->v3, h->den3, s));
+            } else if (mixed) {
+                HIP_TRY(launch_relayout_slots<T>(P, h->ptr2, h->idx2, h->v2, h->den2, h->woff,
+                                                 entries, h->idx3, h->idx16, 4, h->v3, h->den3, s));
+                HIP_TRY(launch_relayout_slots<T>(h->L - P, h->ptr2 + P, h->idx2, h->v2, h->den2,
+                                                 h->woff + h->woff_b, 0, h->idx3, h->idx16, kGroup,
                                                  h->v3, h->den3, s));
             } else {
                 HIP_TRY(launch_relayout_slots<T>(h->L, h->ptr2, h->idx2, h->v2, h->den2, h->woff,
-                                                 entries, h->idx3, h->idx16, quad, h->v3, h->den3,
-                                                 s));
+                                                 entries, h->idx3, h->idx16, quad ? 4 : kGroup,
+                                                 h->v3, h->den3, s));
             }
         }
         HIP_TRY(hipStreamSynchronize(s));   // the host vectors die here

@@ -121,10 +121,10 @@ hipError_t launch_relayout(int64_t L, const int64_t* seg_ptr, const int32_t* idx
 hipError_t launch_degree(int64_t nnz, const int32_t* idx, int64_t n, unsigned long long* deg,
                          hipStream_t s);
 template <typename T>
-// quad: the 4-lane layout of the quad kernels, else the 8-lane one
+// G: lanes per row of the layout (8, 4: quad, 2: pair)
 hipError_t launch_relayout_slots(int64_t L, const int64_t* ptr, const int32_t* idx2,
                                  const void* v2, const void* den2, const int64_t* woff,
-                                 int64_t entries, void* idx3, bool idx16, bool quad, void* v3,
+                                 int64_t entries, void* idx3, bool idx16, int G, void* v3,
                                  void* den3, hipStream_t s);
 template <typename T>
 hipError_t launch_prices(int64_t n, const void* r, const void* eta, const int64_t* a_ptr,
@@ -137,7 +137,7 @@ hipError_t launch_prices(int64_t n, const void* r, const void* eta, const int64_
 // Variant kSegSplit holds the prices of products [0, hp) in LDS.  Variants
 // kSegSlots and up read the slot-major copy (see SegArgs::woff); of these,
 // kSegSlotsSplit and kSegSlotsSplit + 1 hold the prices as kSegSplit does.
-constexpr int kSegVariants = 37;
+constexpr int kSegVariants = 39;
 constexpr int kSegSlots = 20;
 constexpr int kSegSlotsSplit = 26;
 constexpr int kSegSlotsJ4 = 28;        // 4 register slots, prices in LDS
@@ -155,10 +155,15 @@ inline bool seg_quad(int variant) { return variant >= kSegQuad && variant <= kSe
 constexpr int kSegMixed = 35;
 constexpr int kQuadMaxRow = 32;        // rows held in registers by the quad kernels
 inline bool seg_mixed(int variant) { return variant == kSegMixed || variant == kSegMixed + 1; }
+// three-part mixed: rows of at most 16 entries in the pair layout (2-lane
+// groups), then quad, then 8-lane (37: 16-bit ids, 38: 32-bit ids)
+constexpr int kSegMixed3 = 37;
+constexpr int kPairMaxRow = 16;
+inline bool seg_mixed3(int variant) { return variant == kSegMixed3 || variant == kSegMixed3 + 1; }
 inline bool seg_idx16(int variant)
 {
     return (variant >= kSegSlots16 && variant <= kSegSlots16 + 2) || variant == kSegQuad ||
-           variant == kSegMixed;
+           variant == kSegMixed || variant == kSegMixed3;
 }
 inline bool seg_slot_major(int variant) { return variant >= kSegSlots; }
 constexpr int kSegLdsPrices = 10;
@@ -188,6 +193,10 @@ hipError_t launch_segments(const SegArgs& a, int grid, int variant, hipStream_t 
 template <typename T>
 hipError_t launch_segments_mixed(const SegArgs& a, const SegArgs& b, int grid, int variant,
                                  hipStream_t s);
+// three-part mixed variants: pair, quad and 8-lane parts
+template <typename T>
+hipError_t launch_segments_mixed3(const SegArgs& a2, const SegArgs& a4, const SegArgs& a8, int grid,
+                                  int variant, hipStream_t s);
 template <typename T>
 int segment_blocks_per_cu(int H, int64_t n, int variant);   // resident blocks per CU
 template <typename T>

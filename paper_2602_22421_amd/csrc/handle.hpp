@@ -32,8 +32,10 @@ struct cblp_instance {
     int64_t* seg_blk = nullptr;     // [seg_grid][3] size-class block table (class variants)
     int64_t* woff = nullptr;        // slot-major copy (slot-major variants): wave-tile offsets
     void* idx3 = nullptr;           // int32, or uint16 when idx16
-    int64_t quad_end = 0;           // mixed variants: positions [0, quad_end) in the quad layout
-    int64_t woff_b = 0;             // mixed variants: index in woff of the 8-lane part's offsets
+    int64_t pair_end = 0;           // three-part mixed: positions [0, pair_end) in the pair layout
+    int64_t quad_end = 0;           // mixed: positions [pair_end, quad_end) in the quad layout
+    int64_t woff_q = 0;             // three-part mixed: index in woff of the quad part's offsets
+    int64_t woff_b = 0;             // mixed: index in woff of the 8-lane part's offsets
     bool idx16 = false;
     void* v3 = nullptr;
     void* den3 = nullptr;

@@ -121,8 +121,8 @@ __global__ void k_fill(T* p, int64_t n, T val)
 // Slot-major copy: the eight rows of wave-tile w = p / 8 occupy woff[w] ..
 // woff[w + 1] (64 entries per slot); entry t of row p goes to slot t / 8 at
 // lane 8 (p % 8) + t % 8.  Unused places keep (product 0, v 0, den 1).
-// G = 4 (quad layout): rows 16w..16w+15 per wave-tile, entry t of row p at
-// slot t / 4, lane 4 (p % 16) + t % 4.
+// G lanes per row (8, 4: quad layout, 2: pair layout): rows Rw..Rw+R-1 per
+// wave-tile (R = 64 / G), entry t of row p at slot t / G, lane G (p % R) + t % G.
 template <typename T, typename IdxT, int G>
 __global__ void k_relayout_slots(int64_t L, const int64_t* ptr, const int32_t* idx2,
                                  const T* v2, const T* den2, const int64_t* woff, IdxT* idx3,
@@ -230,7 +230,7 @@ hipError_t launch_relayout(int64_t L, const int64_t* seg_ptr, const int32_t* idx
 template <typename T>
 hipError_t launch_relayout_slots(int64_t L, const int64_t* ptr, const int32_t* idx2,
                                  const void* v2, const void* den2, const int64_t* woff,
-                                 int64_t entries, void* idx3, bool idx16, bool quad, void* v3,
+                                 int64_t entries, void* idx3, bool idx16, int G, void* v3,
                                  void* den3, hipStream_t s)
 {
     if (idx16)
@@ -240,11 +240,19 @@ hipError_t launch_relayout_slots(int64_t L, const int64_t* ptr, const int32_t* i
         hipLaunchKernelGGL(k_fill<int32_t>, dim3(1024), dim3(256), 0, s, (int32_t*)idx3, entries, 0);
     hipLaunchKernelGGL(k_fill<T>, dim3(1024), dim3(256), 0, s, (T*)v3, entries, T(0));
     hipLaunchKernelGGL(k_fill<T>, dim3(1024), dim3(256), 0, s, (T*)den3, entries, T(1));
-    if (L > 0 && idx16 && quad)
+    if (L > 0 && idx16 && G == 2)
+        hipLaunchKernelGGL((k_relayout_slots<T, uint16_t, 2>), dim3(2048), dim3(256), 0, s, L, ptr,
+                           idx2, (const T*)v2, (const T*)den2, woff, (uint16_t*)idx3, (T*)v3,
+                           (T*)den3);
+    else if (L > 0 && G == 2)
+        hipLaunchKernelGGL((k_relayout_slots<T, int32_t, 2>), dim3(2048), dim3(256), 0, s, L, ptr,
+                           idx2, (const T*)v2, (const T*)den2, woff, (int32_t*)idx3, (T*)v3,
+                           (T*)den3);
+    else if (L > 0 && idx16 && G == 4)
         hipLaunchKernelGGL((k_relayout_slots<T, uint16_t, 4>), dim3(2048), dim3(256), 0, s, L, ptr,
                            idx2, (const T*)v2, (const T*)den2, woff, (uint16_t*)idx3, (T*)v3,
                            (T*)den3);
-    else if (L > 0 && quad)
+    else if (L > 0 && G == 4)
         hipLaunchKernelGGL((k_relayout_slots<T, int32_t, 4>), dim3(2048), dim3(256), 0, s, L, ptr,
                            idx2, (const T*)v2, (const T*)den2, woff, (int32_t*)idx3, (T*)v3,
                            (T*)den3);
@@ -288,7 +296,7 @@ hipError_t launch_prices(int64_t n, const void* r, const void* eta, const int64_
                                            hipStream_t);                                       \
     template hipError_t launch_relayout_slots<T>(int64_t, const int64_t*, const int32_t*,      \
                                                  const void*, const void*, const int64_t*,     \
-                                                 int64_t, void*, bool, bool, void*, void*,       \
+                                                 int64_t, void*, bool, int, void*, void*,        \
                                                  hipStream_t);
 CBLP_INST(float)
 CBLP_INST(double)

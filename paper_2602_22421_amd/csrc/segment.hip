@@ -224,6 +224,46 @@ __global__ void __launch_bounds__(kSegThreads) k_segments_mixed(SegArgs a, SegAr
     }
 }
 
+// Three-part mixed kernel: positions [0, P2) (rows of at most 16 entries) in
+// the pair layout, solved by 2-lane groups (args a2), [P2, P4) (rows of at
+// most 32) in the quad layout by 4-lane groups (a4), the rest in the 8-lane
+// layout (a8); each view starts at its first position.
+template <typename T, typename IdxT>
+__global__ void __launch_bounds__(kSegThreads) k_segments_mixed3(SegArgs a2, SegArgs a4, SegArgs a8)
+{
+    extern __shared__ unsigned long long bins[];   // [a2.H], then [a2.n] prices
+    __shared__ double zsh[kSegThreads / 64];
+    const int H = a2.H;
+    T* lprice = (T*)(bins + H);
+    for (int j = threadIdx.x; j < H; j += kSegThreads) bins[j] = 0ull;
+    for (int64_t j = threadIdx.x; j < a2.n; j += kSegThreads) lprice[j] = ((const T*)a2.rho)[j];
+    __syncthreads();
+
+    double zacc = 0.0;
+    const seg::FlatPrices<T> pr{(const T*)lprice};
+    const int64_t t2 = (a2.L + seg::kPairTileRows - 1) / seg::kPairTileRows;
+    seg::process_tiles_pair<T, 8, seg::FlatPrices<T>, IdxT>(a2, blockIdx.x, t2, gridDim.x, bins, pr,
+                                                            zacc);
+    const int64_t t4 = (a4.L + seg::kQuadTileRows - 1) / seg::kQuadTileRows;
+    seg::process_tiles_quad<T, 8, seg::FlatPrices<T>, IdxT>(a4, blockIdx.x, t4, gridDim.x, bins, pr,
+                                                            zacc);
+    const int64_t t8 = (a8.L + kSegsPerTile - 1) / kSegsPerTile;
+    seg::process_tiles_slots<T, 7, false, seg::FlatPrices<T>, false, IdxT>(a8, blockIdx.x, t8,
+                                                                          gridDim.x, bins, pr,
+                                                                          zacc);
+
+    __syncthreads();
+    flush_bins(a2, bins);
+    for (int o = 32; o > 0; o >>= 1) zacc += __shfl_down(zacc, o, 64);
+    if ((threadIdx.x & 63) == 0) zsh[threadIdx.x >> 6] = zacc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double z = zsh[0];
+        for (int q = 1; q < kSegThreads / 64; ++q) z += zsh[q];
+        a2.zpart[blockIdx.x] = z;
+    }
+}
+
 // Size-class kernel: block b solves tiles [blk[b][1], blk[b][2]) with
 // blk[b][0] register slots per lane.  The layout is sorted by row length, so
 // a run of tiles has one slot count, and loading every slot of it wastes no
@@ -323,6 +363,8 @@ const void* SegVariant<T>::fn(int variant)
     case kSegQuad + 2: return (const void*)k_segments_quad<T, 8, int32_t, false>;
     case kSegMixed: return (const void*)k_segments_mixed<T, uint16_t>;
     case kSegMixed + 1: return (const void*)k_segments_mixed<T, int32_t>;
+    case kSegMixed3: return (const void*)k_segments_mixed3<T, uint16_t>;
+    case kSegMixed3 + 1: return (const void*)k_segments_mixed3<T, int32_t>;
     default: return (const void*)k_segments<T, 4, 1, false>;
     }
 }
@@ -333,6 +375,16 @@ hipError_t launch_segments_mixed(const SegArgs& a, const SegArgs& b, int grid, i
 {
     const size_t lds = seg_lds_bytes(a.H, a.n, sizeof(T), variant);
     void* args[] = {(void*)&a, (void*)&b};
+    return hipLaunchKernel(SegVariant<T>::fn(variant), dim3(grid), dim3(kSegThreads), args, lds,
+                           s);
+}
+
+template <typename T>
+hipError_t launch_segments_mixed3(const SegArgs& a2, const SegArgs& a4, const SegArgs& a8, int grid,
+                                  int variant, hipStream_t s)
+{
+    const size_t lds = seg_lds_bytes(a2.H, a2.n, sizeof(T), variant);
+    void* args[] = {(void*)&a2, (void*)&a4, (void*)&a8};
     return hipLaunchKernel(SegVariant<T>::fn(variant), dim3(grid), dim3(kSegThreads), args, lds,
                            s);
 }
@@ -363,6 +415,10 @@ template hipError_t launch_segments_mixed<float>(const SegArgs&, const SegArgs&,
                                                  hipStream_t);
 template hipError_t launch_segments_mixed<double>(const SegArgs&, const SegArgs&, int, int,
                                                   hipStream_t);
+template hipError_t launch_segments_mixed3<float>(const SegArgs&, const SegArgs&, const SegArgs&, int,
+                                                  int, hipStream_t);
+template hipError_t launch_segments_mixed3<double>(const SegArgs&, const SegArgs&, const SegArgs&,
+                                                   int, int, hipStream_t);
 template hipError_t launch_segments<double>(const SegArgs&, int, int, hipStream_t);
 template int segment_blocks_per_cu<float>(int, int64_t, int);
 template int segment_blocks_per_cu<double>(int, int64_t, int);

@@ -882,5 +882,202 @@ __device__ __forceinline__ void process_tiles_quad(const SegArgs& a, int64_t til
     }
 }
 
+// Pair layout: 2-lane groups, 32 rows per wave (entry t of row q at slot
+// t / 2, lane 2q + t % 2), for rows of at most 16 entries.  Lane l of a pair
+// keeps four partial sums, slots s = 0, 1, 2, 3 (mod 4): the sums of the
+// 8-lane lanes l, l + 2, l + 4, l + 6; pair_sum adds them in group_sum's order
+// ((x0 + x7) + (x2 + x5)) + ((x1 + x6) + (x3 + x4)), the same on both lanes.
+constexpr int kPair = 2;
+constexpr int kPairRows = 64 / kPair;
+constexpr int kPairTileRows = kSegThreads / 64 * kPairRows;
+
+template <typename X>
+__device__ __forceinline__ X pair_sum(const X (&c)[4], int lane)
+{
+    const bool l0 = (lane & 1) == 0;
+    X A[4], B[4];   // the even lane's and the odd lane's partial sums
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const X o = dpp_move<kQuadSwap1>(c[k]);
+        A[k] = l0 ? c[k] : o;
+        B[k] = l0 ? o : c[k];
+    }
+    // x(l + 2k) is A[k] for l = 0 and B[k] for l = 1
+    const X y0 = A[0] + B[3];   // x0 + x7
+    const X y2 = A[1] + B[2];   // x2 + x5
+    const X y1 = B[0] + A[3];   // x1 + x6
+    const X y3 = B[1] + A[2];   // x3 + x4
+    return (y0 + y2) + (y1 + y3);
+}
+
+template <typename T>
+__device__ __forceinline__ WaveBounds<T> load_wave_bounds_pair(const SegArgs& a, int64_t t, int wv,
+                                                              int q)
+{
+    const int64_t W = (a.L + kPairRows - 1) / kPairRows;
+    const int64_t w = t * (kSegThreads / 64) + wv;
+    const int64_t wc = w < W ? w : 0;
+    WaveBounds<T> B;
+    B.b0 = a.woff[wc];
+    B.b1 = a.woff[wc + 1];
+    B.wlive = w < W;
+    const int64_t p = w * kPairRows + q;
+    const int64_t pc = p < a.L ? p : 0;
+    B.vt0 = ((const T*)a.vt0)[pc];
+    B.lam = ((const T*)a.lam)[pc];
+    B.R0 = ((const T*)a.Rwarm)[pc];
+    B.live = p < a.L;
+    return B;
+}
+
+template <typename T, int J, typename PR, typename IdxT>
+__device__ __forceinline__ void process_tiles_pair(const SegArgs& a, int64_t tile, int64_t tiles,
+                                                   int64_t stride, unsigned long long* bins,
+                                                   const PR& rho, double& zacc)
+{
+    const T* __restrict__ v3 = (const T*)a.v3;
+    const T* __restrict__ d3 = (const T*)a.den3;
+    const IdxT* __restrict__ i3 = (const IdxT*)a.idx3;
+    const int H = a.H;
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    const int q = lane / kPair;
+    if (tile >= tiles) return;
+
+    WaveBounds<T> Bc = load_wave_bounds_pair<T>(a, tile, wv, q);
+    Raw<T, J> Rc = load_slots<T, J, false, IdxT>(a, Bc, lane);
+    WaveBounds<T> B1 = load_wave_bounds_pair<T>(a, tile + stride, wv, q);
+    WaveBounds<T> B2;
+    T Pc[J];
+    for (; tile < tiles; tile += stride) {
+        gather<T, J, true, PR>(rho, Rc, Pc, J);
+        __builtin_amdgcn_sched_barrier(0);
+        const Raw<T, J> R1 = load_slots<T, J, false, IdxT>(a, B1, lane);
+        B2 = load_wave_bounds_pair<T>(a, tile + 2 * stride, wv, q);
+
+        const int jw = wave_jw(Bc);
+        const int64_t base = wave_base(Bc);
+        const int js = jw < J ? jw : J;
+        const T vt0 = Bc.vt0;
+        T num[J], den[J];
+#pragma unroll
+        for (int s = 0; s < J; ++s) {
+            num[s] = s < js ? Pc[s] * Rc.v[s] : T(0);
+            den[s] = Rc.den[s];
+        }
+        unsigned long long mask[J];
+        auto full = [&](T R, T& N, T& Dn) {
+            T nc[4] = {T(0), T(0), T(0), T(0)}, dc[4] = {T(0), T(0), T(0), T(0)};
+#pragma unroll
+            for (int s = 0; s < J; ++s) {
+                mask[s] = 0ull;
+                if (s >= js) continue;
+                const bool in = num[s] > R * den[s];
+                mask[s] = __ballot(in);
+                const T w = in ? T(1) : T(0);
+                nc[s & 3] = fmadd(w, num[s], nc[s & 3]);
+                dc[s & 3] = fmadd(w, den[s], dc[s & 3]);
+            }
+            for (int s = J; s < jw; ++s) {            // slots past the registers
+                const int64_t e = base + 64 * s + lane;
+                const T nn = rho[i3[e]] * v3[e];
+                const T dd = d3[e];
+                const T w = nn > R * dd ? T(1) : T(0);
+                switch (s & 3) {                     // the class of the slot, as a constant index
+                case 0: nc[0] = fmadd(w, nn, nc[0]); dc[0] = fmadd(w, dd, dc[0]); break;
+                case 1: nc[1] = fmadd(w, nn, nc[1]); dc[1] = fmadd(w, dd, dc[1]); break;
+                case 2: nc[2] = fmadd(w, nn, nc[2]); dc[2] = fmadd(w, dd, dc[2]); break;
+                default: nc[3] = fmadd(w, nn, nc[3]); dc[3] = fmadd(w, dd, dc[3]); break;
+                }
+            }
+            N = pair_sum(nc, lane);
+            Dn = pair_sum(dc, lane);
+        };
+        auto changed = [&](T R, T Rn) {
+            unsigned long long diff = 0ull;
+#pragma unroll
+            for (int s = 0; s < J; ++s) {
+                if (s >= js) break;
+                diff |= __ballot(num[s] > Rn * den[s]) ^ mask[s];
+            }
+            if (jw > J) {
+                bool t = false;
+                for (int s = J; s < jw; ++s) {
+                    const int64_t e = base + 64 * s + lane;
+                    const T nn = rho[i3[e]] * v3[e];
+                    const T dd = d3[e];
+                    t = t || ((nn > Rn * dd) != (nn > R * dd));
+                }
+                diff |= __ballot(t);
+            }
+            return diff;
+        };
+        // Dinkelbach with the same start, round cap (in entries of the wave's
+        // longest row, rounded to 8) and cycle rule as the 8-lane kernels
+        T R = Bc.R0, N, Dn;
+        full(R, N, Dn);
+        T Rs = N > T(0) ? ratio(N, vt0 + Dn) : T(0);
+        T pR = R, pN = N, pD = Dn, pRs = Rs;
+        unsigned long long diff = 0ull;
+        const int cap = kGroup * ((kPair * jw + kGroup - 1) / kGroup) + 1;
+        for (int round = 0; round <= cap; ++round) {
+            diff = changed(R, Rs);
+            if (diff == 0ull) break;
+            pR = R;
+            pN = N;
+            pD = Dn;
+            pRs = Rs;
+            R = Rs;
+            full(R, N, Dn);
+            Rs = N > T(0) ? ratio(N, vt0 + Dn) : T(0);
+        }
+        if (diff != 0ull) {
+            const unsigned long long now = changed(R, Rs);
+            const bool cycling = ((now >> (threadIdx.x & 62)) & 0x3ull) != 0ull;
+            if (cycling && pRs > Rs) {
+                R = pR;
+                N = pN;
+                Dn = pD;
+                Rs = pRs;
+            }
+        }
+        const T Rstar = Rs;
+        const T lamD = ratio(Bc.lam, vt0 + Dn) * (T)a.fx_scale;
+#pragma unroll
+        for (int s = 0; s < J; ++s) {
+            if (s >= js) break;
+            if (num[s] > R * den[s]) {
+                const unsigned long long qv = quantum(lamD, Rc.v[s]);
+                const int32_t j = Rc.id[s];
+                if (j < H)
+                    atomicAdd(&bins[j], qv);
+                else
+                    atomicAdd(&a.S_fx[j], qv);
+            }
+        }
+        for (int s = J; s < jw; ++s) {
+            const int64_t e = base + 64 * s + lane;
+            const T x = v3[e];
+            const int32_t j = (int32_t)i3[e];
+            if (rho[j] * x > R * d3[e]) {
+                const unsigned long long qq = quantum(lamD, x);
+                if (j < H)
+                    atomicAdd(&bins[j], qq);
+                else
+                    atomicAdd(&a.S_fx[j], qq);
+            }
+        }
+        if ((lane & (kPair - 1)) == 0 && Bc.live) {
+            const int64_t p = (tile * (kSegThreads / 64) + wv) * kPairRows + q;
+            zacc += (double)Bc.lam * (double)Rstar;
+            ((T*)a.Rwarm)[p] = Rstar;
+            if (a.seg_R) ((T*)a.seg_R)[a.perm[p]] = Rstar;
+        }
+        Bc = B1;
+        Rc = R1;
+        B1 = B2;
+    }
+}
+
 }  // namespace seg
 }  // namespace cblp
