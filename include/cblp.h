@@ -217,9 +217,12 @@ int spfom_batch_solve(cblp_batch_t b, void* const* etas, const void* const* tau_
                       const spfom_params* p, spfom_stats* outs, void* stream);
 
 /* Autotune the segment-kernel variant (register slots per lane, pipeline
- * depth) by timing iters iterations of each candidate on this batch; the
- * duals in etas change and the solver state is reset afterwards.  chosen
- * [host] nullable receives the variant kept. */
+ * depth, copy layout) by timing iters iterations of each candidate on this
+ * batch; the duals in etas change, the solver state is reset afterwards and
+ * the handles' per-segment warm starts are restored (so a later solve
+ * follows the same iterates as on untouched handles).  chosen [host]
+ * nullable receives the variant kept.  CBLP_ENOMEM if the copy of the warm
+ * starts (4 or 8 bytes per segment) cannot be allocated. */
 int cblp_batch_tune(cblp_batch_t b, void* const* etas, const void* const* tau_vecs,
                     const spfom_params* p, int32_t iters, int32_t* chosen, void* stream);
 

@@ -40,6 +40,8 @@ namespace {
 
 struct BInst {
     SegArgs seg;               // this instance's sorted copy and tail accumulator
+    SegArgs pseg[3];           // its pair, quad and 8-lane parts (slot-major copies),
+    int64_t pstart[3];         // each viewed from its first position pstart[k]
     int64_t n, m;
     const void* r;
     const void* c;
@@ -64,8 +66,8 @@ struct BInst {
 
 struct BItem {
     int inst;
-    int pad;
-    int64_t t0, t1;            // tiles [t0, t1)
+    int part;                  // 0 pair, 1 quad, 2 8-lane part of the slot-major copy
+    int64_t p0, p1;            // positions [p0, p1) (p0 a multiple of kPartAlign)
 };
 
 struct BChunk {
@@ -102,7 +104,9 @@ __global__ void k_reset_counter(unsigned* counter) { *counter = 0u; }
 
 // MODE 0: prices gathered from global memory; 1: the item's instance prices
 // copied into LDS behind the largest instance's bins (Hmax), then gathered
-// there; 2: as 1 over the slot-major copies (IdxT: their product id type).
+// there; 2: as 1 over the 8-lane slot-major copies (IdxT: their product id
+// type); 3: as 1 over the handles' own slot-major copies, each part by the
+// groups of its width (2, 4 or 8 lanes; FP32, else 8 lanes only).
 template <typename T, int J, int DEPTH, int MODE, typename IdxT = int32_t>
 __global__ void __launch_bounds__(kSegThreads)
 k_bsegments(const BInst* inst, const BItem* items, int nitems, unsigned* counter,
@@ -130,11 +134,34 @@ k_bsegments(const BInst* inst, const BItem* items, int nitems, unsigned* counter
         __syncthreads();
         double zacc = 0.0;
         const seg::FlatPrices<T> pr{MODE > 0 ? (const T*)lprice : (const T*)a.rho};
-        if (MODE == 2)
-            seg::process_tiles_slots<T, J, false, seg::FlatPrices<T>, false, IdxT>(a, w.t0, w.t1, 1,
+        const int64_t t0 = w.p0 / kSegsPerTile, t1 = (w.p1 + kSegsPerTile - 1) / kSegsPerTile;
+        if constexpr (MODE == 3) {
+            const SegArgs& ap = I->pseg[w.part];   // fields read where used: fewer live registers
+            const int64_t q0 = w.p0 - I->pstart[w.part], q1 = w.p1 - I->pstart[w.part];
+            bool done = false;
+            if constexpr (sizeof(T) == 4) {
+                if (w.part == 0) {
+                    seg::process_tiles_pair<T, 8, seg::FlatPrices<T>, IdxT>(
+                        ap, q0 / seg::kPairTileRows,
+                        (q1 + seg::kPairTileRows - 1) / seg::kPairTileRows, 1, bins, pr, zacc);
+                    done = true;
+                } else if (w.part == 1) {
+                    seg::process_tiles_quad<T, 8, seg::FlatPrices<T>, IdxT>(
+                        ap, q0 / seg::kQuadTileRows,
+                        (q1 + seg::kQuadTileRows - 1) / seg::kQuadTileRows, 1, bins, pr, zacc);
+                    done = true;
+                }
+            }
+            if (!done)   // the 8-lane part (FP64 handles have no other)
+                seg::process_tiles_slots<T, J, false, seg::FlatPrices<T>, false, IdxT>(
+                    ap, q0 / kSegsPerTile, (q1 + kSegsPerTile - 1) / kSegsPerTile, 1, bins, pr,
+                    zacc);
+        } else if (MODE == 2) {
+            seg::process_tiles_slots<T, J, false, seg::FlatPrices<T>, false, IdxT>(a, t0, t1, 1,
                                                                                   bins, pr, zacc);
-        else
-            seg::process_tiles<T, J, DEPTH>(a, w.t0, w.t1, 1, bins, pr, zacc);
+        } else {
+            seg::process_tiles<T, J, DEPTH>(a, t0, t1, 1, bins, pr, zacc);
+        }
         __syncthreads();
         unsigned long long* out = part_S + I->part_off + (size_t)(it - I->item0) * (size_t)H;
         for (int j = threadIdx.x; j < H; j += kSegThreads) out[j] = bins[j];
@@ -297,8 +324,9 @@ __global__ void __launch_bounds__(kRowThreads) k_bprices(const BInst* inst, cons
 // Batched variants 0-6 as the single-instance ones (prices from global
 // memory); 7: ordered pipeline with the prices in LDS; 8: slot-major copies
 // with the prices in LDS (needs every handle's slot-major copy with 32-bit
-// ids); 9: the same over 16-bit-id copies.
-constexpr int kBatchVariants = 10;
+// ids); 9: the same over 16-bit-id copies; 10, 11: the handles' own
+// slot-major copies part by part (16- and 32-bit ids).
+constexpr int kBatchVariants = 12;
 inline bool bseg_lds_prices(int variant) { return variant >= 7; }
 
 template <typename T>
@@ -314,6 +342,8 @@ const void* bseg_fn(int variant)
     case 7: return (const void*)k_bsegments<T, sizeof(T) == 4 ? 7 : 4, 3, 1>;
     case 8: return (const void*)k_bsegments<T, sizeof(T) == 4 ? 7 : 4, 3, 2>;
     case 9: return (const void*)k_bsegments<T, sizeof(T) == 4 ? 7 : 4, 3, 2, uint16_t>;
+    case 10: return (const void*)k_bsegments<T, sizeof(T) == 4 ? 7 : 4, 3, 3, uint16_t>;
+    case 11: return (const void*)k_bsegments<T, sizeof(T) == 4 ? 7 : 4, 3, 3, int32_t>;
     default: return (const void*)k_bsegments<T, 4, 1, 0>;
     }
 }
@@ -357,6 +387,8 @@ struct cblp_batch {
     int64_t nmax = 1;               // most products of any instance
     bool slots_ok = false;          // every handle has a slot-major copy with 32-bit ids
     bool slots16_ok = false;        // every handle has one with 16-bit ids
+    bool parts16_ok = false;        // every handle has a slot-major copy (any parts), 16-bit ids
+    bool parts32_ok = false;        // the same with 32-bit ids
     hipStream_t stream = nullptr;    // the batch's own stream (graph capture needs one)
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -521,6 +553,8 @@ bool bseg_usable(const cblp_batch* b, int variant)
     if (variant < 0 || variant >= kBatchVariants) return false;
     if (variant == 8 && !b->slots_ok) return false;
     if (variant == 9 && !b->slots16_ok) return false;
+    if (variant == 10 && !b->parts16_ok) return false;
+    if (variant == 11 && !b->parts32_ok) return false;
     const void* f = b->dtype == CBLP_F32 ? bseg_fn<float>(variant) : bseg_fn<double>(variant);
     const size_t lds = bseg_lds(b, variant);
     int per_cu = 0;
@@ -583,6 +617,8 @@ int cblp_batch_create(cblp_batch_t* out, int32_t count, const cblp_t* handles, v
     b->Hmax = (int)Hmax;
     b->slots_ok = true;
     b->slots16_ok = true;
+    b->parts16_ok = true;
+    b->parts32_ok = true;
     for (int q = 0; q < count; ++q) {
         b->nmax = std::max<int64_t>(b->nmax, b->hs[q]->n);
         const bool slots8 = b->hs[q]->woff != nullptr && !seg_quad(b->hs[q]->seg_variant) &&
@@ -590,6 +626,11 @@ int cblp_batch_create(cblp_batch_t* out, int32_t count, const cblp_t* handles, v
                             !seg_mixed3(b->hs[q]->seg_variant);
         b->slots_ok = b->slots_ok && slots8 && !b->hs[q]->idx16;
         b->slots16_ok = b->slots16_ok && slots8 && b->hs[q]->idx16;
+        // FP64 handles take part 2 only (the narrow groups are FP32 kernels)
+        const bool parts = b->hs[q]->woff != nullptr &&
+                           (b->dtype == CBLP_F32 || b->hs[q]->quad_end == 0);
+        b->parts16_ok = b->parts16_ok && parts && b->hs[q]->idx16;
+        b->parts32_ok = b->parts32_ok && parts && !b->hs[q]->idx16;
     }
     if (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming) != hipSuccess ||
@@ -603,7 +644,8 @@ int cblp_batch_create(cblp_batch_t* out, int32_t count, const cblp_t* handles, v
         cus = prop.multiProcessorCount;
     // default: slot-major copies with LDS prices when every instance has them
     // and they fit, else the spill-free global-price variant
-    b->variant = bseg_usable(b, 9) ? 9 : bseg_usable(b, 8) ? 8 : bseg_usable(b, 7) ? 7 : 5;
+    b->variant = bseg_usable(b, 10) ? 10 : bseg_usable(b, 11) ? 11 : bseg_usable(b, 9) ? 9
+               : bseg_usable(b, 8) ? 8 : bseg_usable(b, 7) ? 7 : 5;
     if (const char* ev = std::getenv("CBLP_BATCH_VARIANT")) {
         const int x = std::atoi(ev);
         if (x >= 0 && x < kBatchVariants && bseg_usable(b, x)) b->variant = x;
@@ -627,6 +669,9 @@ int cblp_batch_create(cblp_batch_t* out, int32_t count, const cblp_t* handles, v
     int64_t total_tiles = 0;
     for (int q = 0; q < count; ++q) total_tiles += (b->hs[q]->L + kSegsPerTile - 1) / kSegsPerTile;
     const int64_t per_item = std::max<int64_t>(1, total_tiles / ((int64_t)b->grid * 4));
+    // item length in positions: a multiple of kPartAlign, so that items start on
+    // a tile of every layout
+    const int64_t per_rows = (per_item * kSegsPerTile + kPartAlign - 1) / kPartAlign * kPartAlign;
     std::vector<BItem> items;
     std::vector<BChunk> fold, rows;
     b->h_inst.assign(count, BInst());
@@ -672,10 +717,27 @@ int cblp_batch_create(cblp_batch_t* out, int32_t count, const cblp_t* handles, v
         I.H = h->H;
         I.active = 1;
         I.pnew = h->pnew;
-        const int64_t tiles = (h->L + kSegsPerTile - 1) / kSegsPerTile;
+        // the parts of the slot-major copy: pair [0, P2), quad [P2, P4), 8-lane [P4, L)
+        const int64_t P2 = h->pair_end, P4 = h->quad_end;
+        const int64_t pb[4] = {0, P2, P4, h->L};
+        const int64_t wo[3] = {0, h->woff_q, h->woff_b};
+        for (int k = 0; k < 3; ++k) {
+            SegArgs v = a;
+            const size_t esz = h->esz;
+            v.L = pb[k + 1] - pb[k];
+            v.ptr = h->ptr2 + pb[k];
+            v.vt0 = (const char*)h->vt0 + pb[k] * esz;
+            v.lam = (const char*)h->lam2 + pb[k] * esz;
+            v.Rwarm = (char*)h->Rwarm + pb[k] * esz;
+            v.perm = h->perm + pb[k];
+            v.woff = h->woff ? h->woff + wo[k] : nullptr;
+            I.pseg[k] = v;
+            I.pstart[k] = pb[k];
+        }
         I.item0 = (int)items.size();
-        for (int64_t t0 = 0; t0 < tiles; t0 += per_item)
-            items.push_back(BItem{q, 0, t0, std::min(tiles, t0 + per_item)});
+        for (int k = 0; k < 3; ++k)
+            for (int64_t p0 = pb[k]; p0 < pb[k + 1]; p0 += per_rows)
+                items.push_back(BItem{q, k, p0, std::min(pb[k + 1], p0 + per_rows)});
         I.item1 = (int)items.size();
         I.part_off = part;
         part += (int64_t)(I.item1 - I.item0) * h->H;
@@ -819,14 +881,29 @@ int cblp_batch_tune(cblp_batch_t b, void* const* etas, const void* const* tau_ve
     if ((rc = enter(b, caller))) return rc;
     if ((rc = bind(b, etas, tau_vecs, p, b->stream))) return rc;
     if ((rc = run_prices(b, b->stream))) return rc;
-    const int candidates[] = {5, 6, 0, 4, 7, 8, 9};
+    const int candidates[] = {5, 6, 0, 4, 7, 8, 9, 10, 11};
     double best = INFINITY;
     int best_v = b->variant;
+    // the trial iterations move every handle's warm-start R*: keep a copy and
+    // put it back, so that tuning leaves the handles as it found them
+    std::vector<void*> saved(b->count, nullptr);
+    for (int q = 0; q < b->count && !rc; ++q) {
+        const cblp_instance* h = b->hs[q];
+        const size_t bytes = (size_t)std::max<int64_t>(h->L, 1) * h->esz;
+        if (hipMalloc(&saved[q], bytes) != hipSuccess) {
+            saved[q] = nullptr;
+            rc = bfail(CBLP_ENOMEM, "no memory for the warm starts");
+        } else if (hipMemcpyAsync(saved[q], h->Rwarm, bytes, hipMemcpyDeviceToDevice, b->stream) !=
+                   hipSuccess) {
+            rc = bfail(CBLP_EHIP, "saving the warm starts failed");
+        }
+    }
     hipEvent_t e0, e1;
     BHIP(hipEventCreate(&e0));
     BHIP(hipEventCreate(&e1));
     const int keep = b->variant;
     for (int v : candidates) {
+        if (rc) break;
         if (!bseg_usable(b, v)) continue;
         b->variant = v;
         if ((rc = run_iters(b, p, 1, b->stream))) break;   // warm the variant
@@ -843,6 +920,17 @@ int cblp_batch_tune(cblp_batch_t b, void* const* etas, const void* const* tau_ve
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
+    for (int q = 0; q < b->count; ++q) {
+        if (!saved[q]) continue;
+        const cblp_instance* h = b->hs[q];
+        const size_t bytes = (size_t)std::max<int64_t>(h->L, 1) * h->esz;
+        if (hipMemcpyAsync(h->Rwarm, saved[q], bytes, hipMemcpyDeviceToDevice, b->stream) !=
+                hipSuccess && !rc)
+            rc = bfail(CBLP_EHIP, "restoring the warm starts failed");
+    }
+    (void)hipStreamSynchronize(b->stream);
+    for (void* ptr : saved)
+        if (ptr) (void)hipFree(ptr);
     b->variant = rc ? keep : best_v;
     if (b->exec) {
         (void)hipGraphExecDestroy(b->exec);

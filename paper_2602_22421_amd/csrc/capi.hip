@@ -573,6 +573,9 @@ int create_impl(cblp_instance* h, hipStream_t s)
             // [0, P) (rows of at most kQuadMaxRow entries; rows ascend) in the
             // quad layout, the rest in the 8-lane one behind it, each with its
             // own offsets (one spare entry each)
+            // (part boundaries are rounded down to multiples of kPartAlign
+            // positions, so that every part starts on a tile of every layout;
+            // a row just below a boundary goes to the wider groups)
             const bool mixed = seg_mixed(h->seg_variant), mixed3 = seg_mixed3(h->seg_variant);
             int64_t P2 = 0, P = seg_quad(h->seg_variant) ? h->L : 0;
             if (mixed3)
@@ -580,6 +583,8 @@ int create_impl(cblp_instance* h, hipStream_t s)
             if (mixed || mixed3) {
                 P = P2;
                 while (P < h->L && ptr[P + 1] - ptr[P] <= kQuadMaxRow) ++P;
+                P2 = P2 / kPartAlign * kPartAlign;
+                P = P / kPartAlign * kPartAlign;
             }
             h->pair_end = P2;
             h->quad_end = P;

@@ -7,6 +7,13 @@
 
 #include "common.hpp"
 
+namespace cblp {
+// Part boundaries of the mixed slot-major copies are multiples of this many
+// positions (a tile of the pair layout), so that every part, and every batch
+// work item, starts on a tile of every layout.
+constexpr int64_t kPartAlign = 512;
+}  // namespace cblp
+
 struct cblp_instance {
     int device = 0;
     int dtype = CBLP_F32;

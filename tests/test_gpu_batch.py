@@ -121,27 +121,28 @@ def test_batch_tune_picks_a_variant(cb):
     etas = [p.zeros_eta() for p in probs]
     params = cb.make_params(rule=0, tau=1.0, check_every=5)
     v = batch.tune(etas, params, iters=3, tau_vecs=taus)
-    assert v in (0, 4, 5, 6, 7, 8, 9)
+    assert v in (0, 4, 5, 6, 7, 8, 9, 10, 11)
     assert batch.info()["variant"] == v
     rows = batch.iterate([p.zeros_eta() for p in probs], 5, params, tau_vecs=taus)
     assert np.all(np.isfinite(rows))
     batch.close()
 
 
-@pytest.mark.parametrize("dtype", ["f32", "f64"])
-def test_batch_variants_agree(cb, dtype, monkeypatch):
+@pytest.mark.parametrize("dtype,handles", [("f32", None), ("f32", "29"), ("f64", None)])
+def test_batch_variants_agree(cb, dtype, handles, monkeypatch):
     """Every batched segment-kernel variant the batch can run gives the same
-    duals bit for bit (16-bit-id slot-major copies, 32-bit ones, row-major
-    copy with prices in LDS or from global memory)."""
+    duals bit for bit: the handles' own slot-major copies part by part (2-, 4-
+    and 8-lane groups), the 8-lane copies with 16- or 32-bit ids, the
+    row-major copy with prices in LDS or from global memory.  handles: the
+    single-instance variant the handles are built for (default: FP32 three
+    parts, FP64 8-lane)."""
     dt = torch.float64 if dtype == "f64" else torch.float32
     base = [batch_instance(b, scale=0.004) for b in range(4)]
-    # handles with the 8-lane slot-major copy with 16-bit ids (the FP64
-    # default; FP32 defaults to the 4-lane layouts, which the batch does not read)
-    if dtype == "f32":
-        monkeypatch.setenv("CBLP_SEG_VARIANT", "29")
+    if handles is not None:
+        monkeypatch.setenv("CBLP_SEG_VARIANT", handles)
     ref = None
     seen = []
-    for v in range(10):
+    for v in range(12):
         monkeypatch.setenv("CBLP_BATCH_VARIANT", str(v))
         _, probs, taus = _setup(cb, base, dt)
         batch = cb.Batch(probs)
@@ -161,4 +162,6 @@ def test_batch_variants_agree(cb, dtype, monkeypatch):
             assert np.array_equal(a, b), (v, q)
     monkeypatch.delenv("CBLP_BATCH_VARIANT", raising=False)
     monkeypatch.delenv("CBLP_SEG_VARIANT", raising=False)
-    assert 9 in seen and 7 in seen and 5 in seen, seen
+    assert 10 in seen and 7 in seen and 5 in seen, seen
+    if handles == "29" or dtype == "f64":
+        assert 9 in seen, seen

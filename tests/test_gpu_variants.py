@@ -72,3 +72,25 @@ def test_flush_modes_agree(cb, dtype, monkeypatch):
         for k, (a, b) in enumerate(zip(ref, got)):
             assert np.array_equal(a, b), (v, k, info)
     monkeypatch.delenv("CBLP_FLUSH", raising=False)
+
+
+def test_narrow_groups_match_8_lane_over_many_iterations(cb, monkeypatch):
+    """The 2- and 4-lane kernels (three-part default) against the 8-lane one
+    over many iterations on uneven instances: the duals stay identical.  (A
+    narrow group caps a row's Dinkelbach rounds by the longest row of its 16-
+    or 32-row wave, an 8-lane wave by its 8 rows; only a row that reaches
+    the cap without converging could tell them apart.)"""
+    from paper_2602_22421_amd.instances import batch_instance
+    for b in range(0, 48, 3):
+        inst = batch_instance(b, scale=0.004).cast(np.float32)
+        outs = []
+        for v in ("29", "37"):
+            monkeypatch.setenv("CBLP_SEG_VARIANT", v)
+            prob = cb.Problem(inst, dtype=torch.float32)
+            tau = prob.tensor(step_scale(inst, 2e-3).astype(np.float32))
+            eta = prob.zeros_eta()
+            prob.iterate(eta, 300, cb.make_params(rule=0, tau_vec=tau, check_every=10), trace=False)
+            outs.append(eta.cpu().numpy())
+            prob.close()
+        assert np.array_equal(outs[0], outs[1]), b
+    monkeypatch.delenv("CBLP_SEG_VARIANT", raising=False)
