@@ -82,7 +82,7 @@ void release(cblp_instance* h)
                     h->pnew,
                     h->seg_blk, h->woff, h->idx3, h->v3, h->den3,
                     h->rho, h->S_fx, h->part_S, h->S_d, h->u_d, h->sum_u, h->zpart,
-                    h->bpart, h->bpart2, h->st, h->trace, h->at_ptr,
+                    h->bpart, h->bpart2, h->st, h->arrive, h->trace, h->at_ptr,
                     h->at_prod, h->at_val};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
@@ -249,6 +249,7 @@ int run_phase(cblp_instance* h, void* eta, const spfom_params* p, int mode, doub
     // without partial rows the fold takes 256 products per block
     a.fold_blocks = h->flush_atomic ? (int)((h->n + 255) / 256) : h->fold_blocks;
     a.pnew = h->pnew;
+    a.arrive = h->arrive;
     a.st = h->st;
     a.par = (int)(h->t & 1);
     a.row = row;
@@ -459,6 +460,8 @@ int create_impl(cblp_instance* h, hipStream_t s)
     if ((rc = dalloc(&h->bpart, (size_t)h->fold_blocks * 8 * 8))) return rc;
     if ((rc = dalloc(&h->bpart2, (size_t)std::max<int64_t>(row_blocks, 1) * 8 * 8))) return rc;
     if ((rc = dalloc(&h->st, 2 * sizeof(DevState)))) return rc;
+    if ((rc = dalloc(&h->arrive, sizeof(unsigned)))) return rc;
+    HIP_TRY(hipMemsetAsync(h->arrive, 0, sizeof(unsigned), s));   // the last block resets it
     if ((rc = ensure_trace(h, 64))) return rc;
     if (hipHostMalloc((void**)&h->pinned, SPFOM_NTRACE * sizeof(double), hipHostMallocDefault) != hipSuccess)
         return fail(CBLP_ENOMEM, "hipHostMalloc failed");

@@ -96,6 +96,7 @@ struct PhaseArgs {
     double* bpart2;                // [row blocks][8]
     int fold_blocks;
     const int32_t* pnew;           // [n] library product id of caller product j; NULL: j
+    unsigned* arrive;              // blocks of the fused fold-and-step kernel done (0 between launches)
     DevState* st;                  // [2]: read st[par], write st[par ^ 1]
     int par;
     double* row;                   // trace row of this iteration

@@ -10,6 +10,8 @@
 //   per row   g_i = u_i - c_i; c.eta, sum (g)^+, the Polyak norm
 //             sum tau_i g_i^2 (g zeroed where the projection binds), ||eta||^2
 //             and the window sums of u for the certified bound
+//   k_fold_step  (A = I, constant step) the fold, the row work and the dual
+//             step in one launch; the last block does k_update's state work
 //   k_update  every block folds the partials in the same fixed order, so all
 //             blocks agree on D = c.eta + sum lambda R*, Dbest, the bound
 //             LB = max over checks of theta * Pbar (theta = min_i min(1,
@@ -53,6 +55,99 @@ __global__ void __launch_bounds__(kFoldLite) k_fold_lite(PhaseArgs a)
     }
     block_reduce(x, sh);
     if (threadIdx.x == 0) store_part(a.bpart + (size_t)blockIdx.x * 8, x);
+}
+
+// A = I with a constant step while iterating: the step needs no global value
+// (the multiplier is 1), so each block also takes the dual step (eq. 16) of
+// its own products, and the last block to arrive (a counter; its partials are
+// published before it counts) folds every block's partials, in k_update's
+// order, into the solver state and the trace row.  One launch instead of two,
+// with the same bits.
+template <typename T>
+__global__ void __launch_bounds__(kFoldLite) k_fold_step(PhaseArgs a)
+{
+    __shared__ double sh[NR * 16];
+    __shared__ int s_last;
+    const int tid = threadIdx.x;
+    const int64_t j = (int64_t)blockIdx.x * kFoldLite + tid;
+    DevState st = a.st[a.par];
+    const long long t1 = st.t + 1, cnt1 = st.cnt + 1;
+    const bool restart = t1 == 1 || t1 == 2 * st.t0;   // averaging window restarts
+    double x[NR];
+    clear(x);
+    if (j < a.n) {
+        const int64_t jq = a.pnew ? a.pnew[j] : j;   // library id of product j
+        const unsigned long long tot = a.S_fx[jq];
+        a.S_fx[jq] = 0ull;
+        const double sj = (double)(long long)tot * a.inv_fx;
+        a.S_d[j] = sj;
+        x[R_P] = (double)((const T*)a.r)[j] * sj;
+        row_work<T>(a, j, sj, cnt1, x);
+        T* eta = (T*)a.eta;
+        const T* tauv = (const T*)a.tau_vec;
+        const double ti = 1.0 * (tauv ? (double)tauv[j] : a.tau_s);
+        double e = (double)eta[j];
+        e = (1.0 - ti * a.mu) * e + ti * (sj - (double)((const T*)a.c)[j]);
+        if (!(e > 0.0)) e = (e != e) ? e : 0.0;   // projection; NaN stays visible
+        const T et = (T)e;
+        eta[j] = et;
+        if (restart) a.sum_u[j] = 0.0;
+        ((T*)a.rho)[jq] = ((const T*)a.r)[j] - et;
+    }
+    block_reduce(x, sh);
+    if (tid == 0) {
+        store_part(a.bpart + (size_t)blockIdx.x * 8, x);
+        __threadfence();
+        s_last = atomicAdd(a.arrive, 1u) == gridDim.x - 1 ? 1 : 0;
+    }
+    __syncthreads();
+    if (!s_last) return;
+    __threadfence();
+    clear(x);
+    for (int q = tid; q < a.nz; q += kFoldLite) x[R_Z] += a.zpart[q];
+    for (int q = tid; q < (int)gridDim.x; q += kFoldLite) x[R_P] += a.bpart[(size_t)q * 8 + R_P];
+    for (int q = tid; q < (int)gridDim.x; q += kFoldLite) {
+        const double* p = a.bpart + (size_t)q * 8;
+        x[R_CETA] += p[R_CETA];
+        x[R_INF] += p[R_INF];
+        x[R_G] += p[R_G];
+        x[R_TH] = fmin(x[R_TH], p[R_TH]);
+        x[R_E2] += p[R_E2];
+    }
+    block_reduce(x, sh);
+    if (tid != 0) return;
+    const double D = x[R_CETA] + x[R_Z];
+    double th = x[R_TH];
+    st.t = t1;
+    if (D < st.dbest) st.dbest = D;
+    st.sum_p += x[R_P];
+    st.cnt = cnt1;
+    if (t1 % a.check_every == 0) {
+        const double cand = th * (st.sum_p / (double)cnt1);
+        if (cand > st.lb) st.lb = cand;
+    } else {
+        th = 1.0;
+    }
+    st.scale = 1.0;
+    if (restart) {
+        st.t0 = t1;
+        st.cnt = 0;
+        st.sum_p = 0.0;
+    }
+    st.restart = restart ? 1 : 0;
+    double* row = a.row;
+    row[SPFOM_TR_DUAL] = D;
+    row[SPFOM_TR_PRIMAL] = x[R_P];
+    row[SPFOM_TR_Z] = x[R_Z];
+    row[SPFOM_TR_ETA2] = x[R_E2];
+    row[SPFOM_TR_INFEAS] = x[R_INF];
+    row[SPFOM_TR_DBEST] = st.dbest;
+    row[SPFOM_TR_LB] = st.lb;
+    row[SPFOM_TR_GAP] = (st.dbest - st.lb) / fmax(fabs(st.dbest), DBL_MIN);
+    row[SPFOM_TR_STEP] = 1.0;
+    row[SPFOM_TR_THETA] = th;
+    a.st[a.par ^ 1] = st;
+    *a.arrive = 0u;   // ready for the next launch
 }
 
 template <typename T, bool IDENT>
@@ -235,7 +330,9 @@ hipError_t launch_phase(const PhaseArgs& a, bool identity, hipStream_t s)
     const unsigned fold_grid = (unsigned)a.fold_blocks;
     const unsigned row_grid = (unsigned)((a.m + kRowThreads - 1) / kRowThreads);
     const bool lite = a.nseg == 0;   // bins already in S_fx: fold_blocks counts kFoldLite products
-    if (identity) {
+    if (identity && lite && a.mode == 0 && a.rule != SPFOM_STEP_POLYAK && a.arrive) {
+        hipLaunchKernelGGL((k_fold_step<T>), dim3(fold_grid), dim3(kFoldLite), 0, s, a);
+    } else if (identity) {
         if (lite)
             hipLaunchKernelGGL((k_fold_lite<T, true>), dim3(fold_grid), dim3(kFoldLite), 0, s, a);
         else

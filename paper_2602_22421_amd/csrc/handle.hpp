@@ -57,6 +57,7 @@ struct cblp_instance {
     double* zpart = nullptr;
     double* bpart = nullptr;
     double* bpart2 = nullptr;
+    unsigned* arrive = nullptr;     // arrival counter of the fused fold-and-step kernel
     cblp::DevState* st = nullptr;   // [2], double-buffered
     double* trace = nullptr;
     int64_t trace_rows = 0;
