@@ -413,11 +413,10 @@ int create_impl(cblp_instance* h, hipStream_t s)
     const bool ids16 = h->n <= 65536;
     // FP32: rows of at most kPairMaxRow entries go to 2-lane groups, of at most
     // kQuadMaxRow to 4-lane groups, longer ones to 8-lane groups (the
-    // three-part mixed kernels); with split prices, the quad kernel when every
-    // row fits it
+    // three-part mixed kernels, with all prices or the head of them in LDS)
     if (sizeof(T) == 4)
         h->seg_variant = prices_fit ? (ids16 ? kSegMixed3 : kSegMixed3 + 1)
-                                    : (short_rows ? kSegQuad + 1 : kSegSlotsSplit);
+                                    : (ids16 ? kSegMixed3 + 3 : kSegMixed3 + 2);
     else
         h->seg_variant = ids16 ? kSegSlots16 + 2 : kSegSlots + 3;
     if (const char* ev = std::getenv("CBLP_SEG_VARIANT")) {

@@ -138,7 +138,7 @@ hipError_t launch_prices(int64_t n, const void* r, const void* eta, const int64_
 // Variant kSegSplit holds the prices of products [0, hp) in LDS.  Variants
 // kSegSlots and up read the slot-major copy (see SegArgs::woff); of these,
 // kSegSlotsSplit and kSegSlotsSplit + 1 hold the prices as kSegSplit does.
-constexpr int kSegVariants = 39;
+constexpr int kSegVariants = 41;
 constexpr int kSegSlots = 20;
 constexpr int kSegSlotsSplit = 26;
 constexpr int kSegSlotsJ4 = 28;        // 4 register slots, prices in LDS
@@ -157,14 +157,15 @@ constexpr int kSegMixed = 35;
 constexpr int kQuadMaxRow = 32;        // rows held in registers by the quad kernels
 inline bool seg_mixed(int variant) { return variant == kSegMixed || variant == kSegMixed + 1; }
 // three-part mixed: rows of at most 16 entries in the pair layout (2-lane
-// groups), then quad, then 8-lane (37: 16-bit ids, 38: 32-bit ids)
+// groups), then quad, then 8-lane (37: 16-bit ids, 38: 32-bit ids; 39, 40:
+// the same with split prices, 32- and 16-bit ids)
 constexpr int kSegMixed3 = 37;
 constexpr int kPairMaxRow = 16;
-inline bool seg_mixed3(int variant) { return variant == kSegMixed3 || variant == kSegMixed3 + 1; }
+inline bool seg_mixed3(int variant) { return variant >= kSegMixed3 && variant <= kSegMixed3 + 3; }
 inline bool seg_idx16(int variant)
 {
     return (variant >= kSegSlots16 && variant <= kSegSlots16 + 2) || variant == kSegQuad ||
-           variant == kSegMixed || variant == kSegMixed3;
+           variant == kSegMixed || variant == kSegMixed3 || variant == kSegMixed3 + 3;
 }
 inline bool seg_slot_major(int variant) { return variant >= kSegSlots; }
 constexpr int kSegLdsPrices = 10;
@@ -173,7 +174,7 @@ constexpr int kSplitPrices = 8192;     // head prices of the split kernel
 inline bool seg_split(int variant)
 {
     return variant == kSegSplit || variant == kSegSlotsSplit || variant == kSegSlotsSplit + 1 ||
-           variant == kSegQuad + 1;
+           variant == kSegQuad + 1 || variant == kSegMixed3 + 2 || variant == kSegMixed3 + 3;
 }
 inline bool seg_class(int variant) { return variant == kSegClassLds || variant == kSegClassGlobal; }
 // most register slots of the size-class kernels per element size

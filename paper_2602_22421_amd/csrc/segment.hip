@@ -3,6 +3,8 @@
 // segment_core.hpp).
 #include "segment_core.hpp"
 
+#include <type_traits>
+
 namespace cblp {
 namespace {
 
@@ -228,29 +230,33 @@ __global__ void __launch_bounds__(kSegThreads) k_segments_mixed(SegArgs a, SegAr
 // the pair layout, solved by 2-lane groups (args a2), [P2, P4) (rows of at
 // most 32) in the quad layout by 4-lane groups (a4), the rest in the 8-lane
 // layout (a8); each view starts at its first position.
-template <typename T, typename IdxT>
+// SPLIT: prices [0, a2.hp) in LDS, the rest from global memory.
+template <typename T, typename IdxT, bool SPLIT = false>
 __global__ void __launch_bounds__(kSegThreads) k_segments_mixed3(SegArgs a2, SegArgs a4, SegArgs a8)
 {
-    extern __shared__ unsigned long long bins[];   // [a2.H], then [a2.n] prices
+    extern __shared__ unsigned long long bins[];   // [a2.H], then the LDS prices
     __shared__ double zsh[kSegThreads / 64];
     const int H = a2.H;
     T* lprice = (T*)(bins + H);
     for (int j = threadIdx.x; j < H; j += kSegThreads) bins[j] = 0ull;
-    for (int64_t j = threadIdx.x; j < a2.n; j += kSegThreads) lprice[j] = ((const T*)a2.rho)[j];
+    const int64_t np = SPLIT ? (int64_t)a2.hp : a2.n;
+    for (int64_t j = threadIdx.x; j < np; j += kSegThreads) lprice[j] = ((const T*)a2.rho)[j];
     __syncthreads();
 
     double zacc = 0.0;
-    const seg::FlatPrices<T> pr{(const T*)lprice};
+    using PR = typename std::conditional<SPLIT, seg::SplitPrices<T>, seg::FlatPrices<T>>::type;
+    PR pr;
+    if constexpr (SPLIT)
+        pr = PR{(const T*)lprice, (const T*)a2.rho, a2.hp};
+    else
+        pr = PR{(const T*)lprice};
     const int64_t t2 = (a2.L + seg::kPairTileRows - 1) / seg::kPairTileRows;
-    seg::process_tiles_pair<T, 8, seg::FlatPrices<T>, IdxT>(a2, blockIdx.x, t2, gridDim.x, bins, pr,
-                                                            zacc);
+    seg::process_tiles_pair<T, 8, PR, IdxT>(a2, blockIdx.x, t2, gridDim.x, bins, pr, zacc);
     const int64_t t4 = (a4.L + seg::kQuadTileRows - 1) / seg::kQuadTileRows;
-    seg::process_tiles_quad<T, 8, seg::FlatPrices<T>, IdxT>(a4, blockIdx.x, t4, gridDim.x, bins, pr,
-                                                            zacc);
+    seg::process_tiles_quad<T, 8, PR, IdxT>(a4, blockIdx.x, t4, gridDim.x, bins, pr, zacc);
     const int64_t t8 = (a8.L + kSegsPerTile - 1) / kSegsPerTile;
-    seg::process_tiles_slots<T, 7, false, seg::FlatPrices<T>, false, IdxT>(a8, blockIdx.x, t8,
-                                                                          gridDim.x, bins, pr,
-                                                                          zacc);
+    seg::process_tiles_slots<T, 7, false, PR, false, IdxT>(a8, blockIdx.x, t8, gridDim.x, bins, pr,
+                                                         zacc);
 
     __syncthreads();
     flush_bins(a2, bins);
@@ -365,6 +371,8 @@ const void* SegVariant<T>::fn(int variant)
     case kSegMixed + 1: return (const void*)k_segments_mixed<T, int32_t>;
     case kSegMixed3: return (const void*)k_segments_mixed3<T, uint16_t>;
     case kSegMixed3 + 1: return (const void*)k_segments_mixed3<T, int32_t>;
+    case kSegMixed3 + 2: return (const void*)k_segments_mixed3<T, int32_t, true>;
+    case kSegMixed3 + 3: return (const void*)k_segments_mixed3<T, uint16_t, true>;
     default: return (const void*)k_segments<T, 4, 1, false>;
     }
 }
@@ -383,7 +391,7 @@ template <typename T>
 hipError_t launch_segments_mixed3(const SegArgs& a2, const SegArgs& a4, const SegArgs& a8, int grid,
                                   int variant, hipStream_t s)
 {
-    const size_t lds = seg_lds_bytes(a2.H, a2.n, sizeof(T), variant);
+    const size_t lds = seg_lds_bytes(a2.H, seg_split(variant) ? a2.hp : a2.n, sizeof(T), variant);
     void* args[] = {(void*)&a2, (void*)&a4, (void*)&a8};
     return hipLaunchKernel(SegVariant<T>::fn(variant), dim3(grid), dim3(kSegThreads), args, lds,
                            s);

@@ -61,6 +61,7 @@ CASES = [
     ("f32", 20000, None, {"CBLP_SEG_VARIANT": "19"}),    # split prices: head of 8192 in LDS
     ("f32", 20000, None, {"CBLP_SEG_VARIANT": "26"}),    # the same over the slot-major copy
     ("f32", 20000, None, {"CBLP_SEG_VARIANT": "27"}),
+    ("f32", 70000, None, {"CBLP_SEG_VARIANT": "39"}),    # three parts, split prices, 32-bit ids
     ("f32", 3000, 40, {}),                               # general A
     ("f64", 3000, 40, {"CBLP_SEG_BINS": "300"}),
 ]

@@ -11,7 +11,7 @@ pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
 
-N_VARIANTS = 39
+N_VARIANTS = 41
 
 
 @pytest.fixture(scope="module")
