@@ -31,7 +31,10 @@ def algorithmic_bytes(inst, esz):
     """Bytes one segment-kernel launch must move: the CSR entries (product id
     4 B, v and w esz each), per segment the row pointer (8 B), vt0 and lambda
     (esz each), per product the price read (esz) and the sales
-    accumulator (8 B)."""
+    accumulator (8 B).  Left out on purpose: what the library's own layout
+    adds (the warm-start R* per segment it reads and writes, the padding of
+    its slot-major copy, reported separately as slot_entries) - those are
+    this implementation's choices, not bytes the method must move."""
     nnz, L, n = inst.nnz, inst.L, inst.n
     per_nnz = 4 + 2 * esz
     per_seg = 8 + 2 * esz
@@ -67,36 +70,75 @@ def profiled_traffic(workload):
     return traffic if rec == sha else None
 
 
-def cpu_baseline(inst, budget_s=15.0):
-    """Time the FP64 oracle (single thread) on a prefix of the same workload."""
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _slice(inst, lo, hi):
     import dataclasses
+    e0, e1 = int(inst.seg_ptr[lo]), int(inst.seg_ptr[hi])
+    return dataclasses.replace(inst, L=hi - lo, seg_ptr=inst.seg_ptr[lo:hi + 1] - e0,
+                               idx=inst.idx[e0:e1], v=inst.v[e0:e1], w=inst.w[e0:e1],
+                               v0=inst.v0[lo:hi], lam=inst.lam[lo:hi])
+
+
+def cpu_baseline(inst, tau, iters):
+    """The FP64 oracle as it stands (single-threaded C) on the whole instance:
+    `iters` iterations from eta = 0.  Returns the baseline record and the
+    oracle's duals and trace (for the GPU's error at the same iteration)."""
     import oracle
-    from paper_2602_22421_amd.instances import step_scale
-
-    def prefix(Ls):
-        e = int(inst.seg_ptr[Ls])
-        return dataclasses.replace(inst, L=Ls, seg_ptr=inst.seg_ptr[: Ls + 1].copy(),
-                                   idx=inst.idx[:e], v=inst.v[:e], w=inst.w[:e],
-                                   v0=inst.v0[:Ls], lam=inst.lam[:Ls])
-
-    Ls = min(inst.L, 20000)
-    sub = prefix(Ls)
-    s = oracle.Solver(sub, tau=step_scale(inst, 0.001))
+    s = oracle.Solver(inst, tau=tau, check_every=10)
     t0 = time.perf_counter()
-    s.iterate(np.zeros(inst.m), 1, trace=False)
-    one = time.perf_counter() - t0
-    Ls2 = int(min(inst.L, max(Ls, Ls * budget_s / 3.0 / max(one, 1e-6))))
-    sub = prefix(Ls2)
-    s = oracle.Solver(sub, tau=step_scale(inst, 0.001))
-    iters = max(3, int(budget_s / max(one * Ls2 / Ls, 1e-6)))
-    t0 = time.perf_counter()
-    s.iterate(np.zeros(inst.m), iters, trace=False)
+    eta, tr = s.iterate(np.zeros(inst.m), iters, trace=True)
     dt = time.perf_counter() - t0
-    return {"value": Ls2 * iters / dt, "unit": "segment-updates/s", "cores": 1,
+    rec = {"value": inst.L * iters / dt, "unit": "segment-updates/s", "cores": 1,
+           "kind": "oracle",
+           "sample": f"{iters} FP64 iterations over all {inst.L} segments ({inst.nnz} CSR "
+                     f"entries) of the same instance, single-threaded C, {dt:.1f} s",
+           "cpu_model": cpu_model(), "nproc": os.cpu_count()}
+    return rec, eta, tr
+
+
+_POOL_INST = None
+
+
+def _pool_leg(task):
+    lo, hi, reps, tau = task
+    import oracle
+    sub = _slice(_POOL_INST, lo, hi)
+    s = oracle.Solver(sub, tau=tau, check_every=10)
+    t0 = time.perf_counter()
+    s.iterate(np.zeros(sub.m), reps, trace=False)
+    return hi - lo, reps, time.perf_counter() - t0
+
+
+def cpu_baseline_all_cores(inst, tau, reps, workers):
+    """The same oracle run by `workers` processes at once, each over its own
+    contiguous share of the segments (the method's segments are independent
+    within an iteration; each process also takes the cheap dual step on its
+    share).  Throughput = all segments x reps / the slowest process's time."""
+    import multiprocessing as mp
+    global _POOL_INST
+    _POOL_INST = inst
+    cuts = [inst.L * k // workers for k in range(workers + 1)]
+    tasks = [(cuts[k], cuts[k + 1], reps, tau) for k in range(workers)]
+    with mp.get_context("fork").Pool(workers) as pool:
+        out = pool.map(_pool_leg, tasks)
+    _POOL_INST = None
+    slowest = max(t for _, _, t in out)
+    segs = sum(n for n, _, _ in out)
+    return {"value": segs * reps / slowest, "unit": "segment-updates/s", "cores": workers,
             "kind": "oracle",
-            "sample": f"{iters} FP64 iterations over the first {Ls2} segments "
-                      f"({int(sub.seg_ptr[-1])} CSR entries) of the same instance, "
-                      f"single-threaded C, {dt:.1f} s"}
+            "sample": f"{reps} FP64 iterations over all {inst.L} segments split into {workers} "
+                      f"contiguous shares, one single-threaded oracle process per share, "
+                      f"slowest share {slowest:.1f} s",
+            "cpu_model": cpu_model(), "nproc": os.cpu_count()}
 
 
 def batched(args):
@@ -325,7 +367,13 @@ def main():
     ap.add_argument("--ws-eval-seeds", type=int, nargs="+", default=[101, 102])
     ap.add_argument("--shuffle-products", action="store_true",
                     help="number the products in random order (the generator numbers them by "
-                         "popularity); the library renumbers them by degree unless CBLP_RELABEL=0")
+                         "popularity; the library renumbers them by degree)")
+    ap.add_argument("--oracle-seconds", type=float, default=13.0,
+                    help="about how long the single-threaded oracle leg runs (whole iterations "
+                         "over the whole instance, at least one)")
+    ap.add_argument("--time-to-gap", action="store_true",
+                    help="wall time and iterations to each certified gap level: cold, warm "
+                         "and batched solves against plain cold ones")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device-to-device copy: the reference kernel whose "
                          "FETCH_SIZE / WRITE_SIZE counters scale the traffic figures")
@@ -335,23 +383,22 @@ def main():
               f"(the multi-GPU sharding is a design, not a build)", file=sys.stderr)
         sys.exit(2)
 
-    import torch
-    from paper_2602_22421_amd import cblp
-    from paper_2602_22421_amd.instances import (CONFIG_NAMES, config_instance, shuffle_products,
-                                                step_scale)
-
-    cblp.load()
-    if not torch.cuda.is_available():
-        print("bench.py needs a GPU", file=sys.stderr)
-        sys.exit(1)
-    torch.cuda.set_device(0)
-    if args.batched:
-        return batched(args)
-    if args.warmstart:
-        if args.max_iters == 2000 and "--max-iters" not in sys.argv:
-            args.max_iters = 3000
-        return warmstart_bench(args)
-    if args.copy_calibration:
+    if args.batched or args.warmstart or args.copy_calibration or args.time_to_gap:
+        import torch
+        from paper_2602_22421_amd import cblp
+        cblp.load()
+        if not torch.cuda.is_available():
+            print("bench.py needs a GPU", file=sys.stderr)
+            sys.exit(1)
+        torch.cuda.set_device(0)
+        if args.batched:
+            return batched(args)
+        if args.time_to_gap:
+            return time_to_gap(args)
+        if args.warmstart:
+            if args.max_iters == 2000 and "--max-iters" not in sys.argv:
+                args.max_iters = 3000
+            return warmstart_bench(args)
         x = torch.ones(1 << 28, dtype=torch.float32, device="cuda")   # 1 GiB
         y = torch.empty_like(x)
         for _ in range(5):
@@ -359,6 +406,16 @@ def main():
         torch.cuda.synchronize()
         log("copied 1 GiB five times (read 1 GiB + write 1 GiB per copy)")
         return
+    return throughput(args)
+
+
+def throughput(args):
+    """Whole SPFOM iterations per second on one workload (the default: the
+    L=2e6, n=2e4 Zipf instance, FP32 iterate, FP64 reductions).  The CPU
+    legs run first, before anything touches the GPU (their worker processes
+    are forked)."""
+    from paper_2602_22421_amd.instances import (CONFIG_NAMES, config_instance, shuffle_products,
+                                                step_scale)
     t0 = time.perf_counter()
     inst = config_instance(args.config)
     workload = CONFIG_NAMES[args.config]
@@ -366,15 +423,57 @@ def main():
         inst = shuffle_products(inst, seed=1)[0]
         workload += "-shuffled-ids"
     npdt = np.float32 if args.dtype == "f32" else np.float64
-    dt = torch.float32 if args.dtype == "f32" else torch.float64
     inst = inst.cast(npdt)
     log(f"generated {workload}: L={inst.L} n={inst.n} m={inst.m} "
         f"nnz={inst.nnz} in {time.perf_counter() - t0:.1f} s")
-    prob = cblp.Problem(inst, dtype=dt)
-    tau = prob.tensor(step_scale(inst, 0.001))
-    params = cblp.make_params(rule=cblp.SPFOM_STEP_CONST, tau_vec=tau, check_every=10)
-    eta = prob.zeros_eta()
+    tau_np = step_scale(inst, 0.001).astype(npdt)
 
+    # CPU legs: the oracle (FP64, the same dtype-rounded inputs) on the whole
+    # instance for a few iterations (its duals are also the reference of the
+    # GPU's error), then the same oracle in one process per core share
+    cpu = cpu_all = None
+    orc_eta = orc_tr = None
+    oracle_iters = max(1, int(round(args.oracle_seconds * 1.2e6 / max(inst.L, 1))))
+    if not args.no_cpu_baseline:
+        log(f"CPU oracle: {oracle_iters} iterations over the whole instance ...")
+        cpu, orc_eta, orc_tr = cpu_baseline(inst, tau_np.astype(np.float64), oracle_iters)
+        log(f"cpu baseline {cpu['value']:.3e} segment-updates/s ({cpu['sample']})")
+        workers = max(1, min(16, os.cpu_count() or 1))
+        reps = max(1, oracle_iters * workers // 2)
+        log(f"CPU oracle on {workers} processes, {reps} iterations each over its share ...")
+        cpu_all = cpu_baseline_all_cores(inst, tau_np.astype(np.float64), reps, workers)
+        log(f"all-core baseline {cpu_all['value']:.3e} segment-updates/s ({cpu_all['sample']})")
+
+    import torch
+    from paper_2602_22421_amd import cblp
+    cblp.load()
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    dt = torch.float32 if args.dtype == "f32" else torch.float64
+    prob = cblp.Problem(inst, dtype=dt)
+    tau = prob.tensor(tau_np)
+    params = cblp.make_params(rule=cblp.SPFOM_STEP_CONST, tau_vec=tau, check_every=10)
+
+    # the GPU's error against the oracle at the same iteration, from eta = 0
+    err = None
+    if orc_eta is not None:
+        e0 = prob.zeros_eta()
+        trg, _ = prob.iterate(e0, oracle_iters, params)
+        eg = e0.double().cpu().numpy()
+        err = {"iterations": oracle_iters,
+               "eta_rel_l2": float(np.linalg.norm(eg - orc_eta) / max(np.linalg.norm(orc_eta), 1e-300)),
+               "eta_max_abs_over_max": float(np.max(np.abs(eg - orc_eta)) /
+                                            max(np.max(np.abs(orc_eta)), 1e-300)),
+               "dual_bound_rel": float(abs(trg[-1, 0] - orc_tr[-1, 0]) / abs(orc_tr[-1, 0])),
+               "primal_rel": float(abs(trg[-1, 1] - orc_tr[-1, 1]) /
+                                   max(abs(orc_tr[-1, 1]), 1e-300)),
+               "reference": "FP64 CPU oracle on the same dtype-rounded inputs"}
+        log(f"error vs oracle after {oracle_iters} iterations: {err}")
+        prob.reset()
+
+    eta = prob.zeros_eta()
     cblp.spfom_iterate(prob.h, eta, params, args.warmup)
     torch.cuda.synchronize()
     log(f"warmup {args.warmup} steps done")
@@ -388,9 +487,10 @@ def main():
     wall = time.perf_counter() - t0
     log(f"timed {args.steps} steps: {wall * 1e3 / args.steps:.3f} ms/step")
     roof = None
+    launch = cblp.cblp_launch_info(prob.h)
     if not args.no_timing:
         cblp.cblp_timing(prob.h, True)
-        cblp.spfom_iterate(prob.h, eta, params, max(args.steps // 2, 1))
+        cblp.spfom_iterate(prob.h, eta, params, max(args.steps, 1))
         torch.cuda.synchronize()
         (seg_ms, dual_ms), (seg_n, dual_n) = cblp.cblp_timing_read(prob.h)
         cblp.cblp_timing(prob.h, False)
@@ -404,16 +504,13 @@ def main():
                 "bytes_per_launch": nbytes, "per_unit_bytes": per,
                 "kernel_avg_us": seg_avg * 1e6,
                 "dual_phase_avg_us": dual_ms * 1e3 / max(dual_n, 1),
-                "launch": cblp.cblp_launch_info(prob.h)}
+                "timing": "HIP events around each launch on the launch stream, over "
+                          f"{seg_n} further steps after the timed ones",
+                "launch": launch}
         log(f"segment kernel {seg_avg * 1e6:.1f} us/launch, {achieved / 1e9:.0f} GB/s "
             f"({100 * achieved / HBM_PEAK:.1f}% of HBM peak); dual phase "
             f"{dual_ms * 1e3 / max(dual_n, 1):.1f} us/launch")
     st = prob.gap(eta)
-    cpu = None
-    if not args.no_cpu_baseline:
-        log("timing the CPU oracle on a bounded sample ...")
-        cpu = cpu_baseline(inst)
-        log(f"cpu baseline {cpu['value']:.3e} segment-updates/s ({cpu['sample']})")
     value = inst.L * args.steps / wall
     out = {
         "metric": "segment-updates/s", "value": value, "unit": "segment-updates/s",
@@ -424,7 +521,8 @@ def main():
                    "m": inst.m, "nnz": inst.nnz,
                    "iterate": args.dtype, "reductions": "f64", "step_rule": "const",
                    "dual_bound_after": st["D"]},
-        "roofline": roof, "cpu_baseline": cpu,
+        "roofline": roof, "cpu_baseline": cpu, "cpu_baseline_all_cores": cpu_all,
+        "error_vs_oracle": err,
     }
     print(json.dumps(out), flush=True)
     prob.close()

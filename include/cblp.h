@@ -64,14 +64,27 @@ enum {
     SPFOM_TR_PRIMAL = 1,    /* P^t = sum_j r_j S^t_j, revenue of the best responses */
     SPFOM_TR_Z = 2,         /* sum_l lambda_l R*_l */
     SPFOM_TR_ETA2 = 3,      /* ||eta^{t-1}||^2, the duals the pass was taken at */
-    SPFOM_TR_INFEAS = 4,    /* sum_i (u^t_i - c_i)^+ */
+    SPFOM_TR_INFEAS = 4,    /* sum_i (u^t_i - c_i)^+ / sum_i c_i (the plain sum when sum c = 0) */
     SPFOM_TR_DBEST = 5,     /* min_{s<=t} D^s (upper bound on the LP optimum) */
-    SPFOM_TR_LB = 6,        /* best certified feasible revenue (lower bound) */
+    SPFOM_TR_LB = 6,        /* best certified feasible revenue (lower bound, see SPFOM_BOUND_*) */
     SPFOM_TR_GAP = 7,       /* (DBEST - LB) / |DBEST| */
     SPFOM_TR_STEP = 8,      /* step multiplier (1 for CONST) */
     SPFOM_TR_THETA = 9,     /* min_i min(1, c_i / ubar_i) at the last check */
     SPFOM_NTRACE = 10
 };
+
+/* Certified lower bounds (spfom_params.bound).  Both scale the primal
+ * average of the current window (the window restarts at t = 1 and whenever t
+ * doubles its start): offering segment l its averaged sales a fraction
+ * theta_l of the time and the empty assortment otherwise keeps every
+ * resource within capacity when theta_l <= c_i / ubar_i for each resource i
+ * that a product of N_l uses, so sum_l theta_l pbar_l <= OPT.
+ *   GLOBAL:  theta_l = min_i min(1, c_i / ubar_i) for every segment
+ *   SEGMENT: theta_l = min over the resources of N_l (tighter; keeps a
+ *            running FP64 revenue sum per segment, 8 bytes per segment, and
+ *            takes one pass over the consideration sets at each check)
+ * LB is the largest such bound over the checks so far. */
+enum { SPFOM_BOUND_GLOBAL = 0, SPFOM_BOUND_SEGMENT = 1 };
 
 typedef struct cblp_instance* cblp_t;
 
@@ -85,6 +98,7 @@ typedef struct {
     double mu;              /* regularisation mu >= 0 of eq. 15/16 (0: Algorithm 2) */
     double tol;             /* spfom_solve: stop when the certified gap <= tol */
     int64_t max_iters;      /* spfom_solve: iteration cap */
+    int32_t bound;          /* SPFOM_BOUND_GLOBAL or SPFOM_BOUND_SEGMENT */
 } spfom_params;
 
 /* Result summary (host struct, FP64). */
@@ -156,21 +170,34 @@ int spfom_solve(cblp_t h, void* eta, const spfom_params* p, spfom_stats* out, vo
 int cblp_gap(cblp_t h, const void* eta, spfom_stats* out, void* stream);
 
 /*
- * cblp_sales - best responses at fixed eta [dev] [m].
+ * cblp_sales - best responses at fixed eta [dev] [m] (the per-segment inner
+ * problem of Section 4.1 in its GAM form, solved exactly).
  * S_out [dev] double [n] nullable: product sales S_j = sum_l s_lj.
  * u_out [dev] double [m] nullable: resource usage u = A S.
  * seg_R_out [dev] [L] nullable, instance dtype: R*_l per segment.
+ * s_out [dev] double [nnz] nullable: per-entry sales s_lj in the caller's CSR
+ *         order (entry q of seg_ptr[l]..seg_ptr[l+1]); 0 for products outside
+ *         the best response S*_l.  Each value is the one the library summed
+ *         into S (a multiple of its fixed-point quantum), so S_j is exactly
+ *         the sum of s_lj over l.
+ * Synchronises the stream.
  */
 int cblp_sales(cblp_t h, const void* eta, double* S_out, double* u_out, void* seg_R_out,
-               void* stream);
+               double* s_out, void* stream);
 
 /*
  * cblp_launch_info - the launch shape chosen at cblp_create: number of
  * segment-kernel blocks, number of LDS sales bins per block (products
- * [0, bins) are accumulated in LDS) and the fixed-point fraction bits of the
- * sales accumulators.  Each [host] pointer is nullable.
+ * [0, bins) are accumulated in LDS), the fixed-point fraction bits of the
+ * sales accumulators, the segment kernel (0: FP32 three-part kernel with all
+ * prices in LDS; 1, 2: the same with the popular head of the prices in LDS,
+ * 16- or 32-bit product ids; 3, 4: FP64 8-lane kernel, 16- or 32-bit ids)
+ * and the places of its slot-major copy of the consideration sets (each row
+ * padded to its wave-tile's longest, in units of entries).  Each [host]
+ * pointer is nullable.
  */
-int cblp_launch_info(cblp_t h, int32_t* seg_grid, int32_t* bins, int32_t* fx_bits);
+int cblp_launch_info(cblp_t h, int32_t* seg_grid, int32_t* bins, int32_t* fx_bits,
+                     int32_t* kernel, int64_t* slot_entries);
 
 /*
  * cblp_timing - enable (1) or disable (0) per-launch timing: while enabled,
@@ -210,7 +237,10 @@ int spfom_batch_iterate(cblp_batch_t b, void* const* etas, const void* const* ta
 
 /* Reset every instance and iterate until each one's certified gap <= p->tol
  * or p->max_iters: p->check_every iterations are captured once in a hipGraph
- * and replayed; converged instances drop out of the work list.  outs [host]
+ * and replayed; converged instances drop out of the work list.  As in
+ * spfom_solve, the last block is cut to the iterations left below max_iters
+ * (run without the graph), and the gap is tested only after a whole block of
+ * check_every iterations.  p->bound must be SPFOM_BOUND_GLOBAL.  outs [host]
  * [count] receives each instance's iterations, last trace row, elapsed
  * seconds and status.  Returns CBLP_OK if every instance converged. */
 int spfom_batch_solve(cblp_batch_t b, void* const* etas, const void* const* tau_vecs,
@@ -229,12 +259,19 @@ int cblp_batch_tune(cblp_batch_t b, void* const* etas, const void* const* tau_ve
 /* Work items, persistent grid and kernel variant of the batch ([host], nullable). */
 int cblp_batch_info(cblp_batch_t b, int32_t* items, int32_t* grid, int32_t* variant);
 
+/* Select the batched segment-kernel variant (one of the autotuner's
+ * candidates, 0-3; every variant gives the same duals bit for bit).
+ * CBLP_EINVAL if the variant cannot run on this batch. */
+int cblp_batch_select(cblp_batch_t b, int32_t variant);
+
 /* ---------------------------------------------------------- learned warm start
  * A small network maps four features of each product to a starting capacity
  * dual for spfom_solve (identity resource matrix, m = n).  Not part of the
  * paper's method, which leaves learned starts to future work (Section 7); it
- * only changes the first iterate eta^0 of Algorithm 1, so every certificate
- * (the dual bound D and the averaged-primal lower bound) keeps its meaning.
+ * only changes the initial duals eta^0 that SPFOM takes as an input
+ * (Algorithm 2, Section 4.1; its parallel form Algorithm 3, Section 4.3), so
+ * every certificate (the dual bound D and the averaged-primal lower bound)
+ * keeps its meaning.
  *
  * Features per product j, written as X[j*4 + k] (FP32, [n x 4] row-major):
  *   k=0  min(c_j / d_j, 4), d_j = sum_l lambda_l v_lj / (v_l0 + sum_{i in N_l} v_li),
@@ -307,6 +344,15 @@ int wsnet_targets(cblp_t h, const void* eta, float* Y, void* stream);
 /* Predicted duals of the instance behind h into eta [dev] [n] (h's dtype);
  * CBLP_EINVAL unless A = identity. */
 int wsnet_predict(wsnet_t w, cblp_t h, void* eta, void* stream);
+
+/* The warm start with its cold fallback: predict eta as wsnet_predict does,
+ * then keep the prediction only if its dual bound D(eta) is below D(0) (the
+ * dual bound of the cold start); otherwise eta is set to 0.  used [host]
+ * nullable receives 1 if the prediction was kept, 0 otherwise; d_pred and
+ * d_zero [host] nullable receive the two bounds.  Leaves the handle's solver
+ * state as it found it.  Synchronises the stream. */
+int wsnet_start(wsnet_t w, cblp_t h, void* eta, int32_t* used, double* d_pred, double* d_zero,
+                void* stream);
 
 /* Describe the last failure on this thread ("" if none). */
 const char* cblp_last_error(void);

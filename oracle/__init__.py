@@ -4,9 +4,10 @@ Only the tests, the package smoke check and the benchmark's CPU-baseline leg
 use this package; the solver library never imports, links or runs it.  The
 arithmetic lives in ``spfom_oracle.c`` (plain C, FP64, compiled with gcc);
 this module marshals numpy arrays through ctypes.  ``lp`` formulates the
-sales-based and choice-based LPs for an independent LP solver, and
-``fast_inner`` restates the paper's greedy inner solve with golden-section
-search as a cross-check.
+sales-based and choice-based LPs for an independent LP solver and ``mlp``
+holds the warm-start network's FP64 reference.  (The paper's own greedy inner
+solve with golden-section search is restated as a cross-check in
+``tests/test_oracle_pins.py``.)
 
 Every function here has a pin in ``tests/test_oracle_*.py`` except the ones
 the header of ``spfom_oracle.c`` marks as the build's own readings (the

@@ -37,12 +37,22 @@
  *   the projection is active); the paper fixes a constant step and stops on
  *   stagnation, this rule is the build's way to reach a certified tolerance.
  *
+ *   Trace per iteration: D^t, P^t = sum_l p_l, Z^t = sum_l z_l, the squared
+ *   norm of eta^{t-1} (the duals the pass was taken at, as D^t), the
+ *   relative infeasibility ||(u^t - c)^+||_1 / ||c||_1 of the best
+ *   responses, Dbest, LB, the gap, the step multiplier and theta.
+ *
  *   Certified gap (the paper defines none): Dbest = min_t D^t >= OPT.  The
  *   primal average over the current window (window restarts at t = 1 and
  *   whenever t doubles the window start) has usage ubar and revenue Pbar;
  *   offering it a fraction theta = min(1, min_i c_i / ubar_i) of the time and
  *   the empty assortment otherwise is feasible, so LB = max over checks of
- *   theta * Pbar <= OPT.  gap = (Dbest - LB) / |Dbest| (0 when both are 0).
+ *   theta * Pbar <= OPT.  With perseg, each segment l may instead be scaled
+ *   by its own theta_l = min of c_i / ubar_i (and 1) over the resources i that
+ *   a product of N_l uses: resource i then carries sum_l theta_l ubar_li <=
+ *   (c_i / ubar_i) ubar_i = c_i, so sum_l theta_l pbar_l <= OPT as well (pbar_l
+ *   the window average of p_l).  gap = (Dbest - LB) / |Dbest| (0 when both
+ *   are 0).
  */
 #include <float.h>
 #include <math.h>
@@ -282,8 +292,9 @@ int orc_iterate(const orc_instance* I, const orc_params* prm, orc_state* st,
             double excess = D - st->lb;
             scale = (G > 0.0 && excess > 0.0) ? prm->gamma * excess / G : 0.0;
         }
-        double infeas = 0.0, e2 = 0.0;
+        double infeas = 0.0, e2 = 0.0, csum = 0.0;
         for (int64_t i = 0; i < m; ++i) {
+            csum += I->c[i];
             double ti = scale * prm->tau[i];
             double g = u[i] - I->c[i];
             e2 += eta[i] * eta[i];          /* the duals the pass was taken at */
@@ -297,7 +308,7 @@ int orc_iterate(const orc_instance* I, const orc_params* prm, orc_state* st,
             tr[TR_P] = P;
             tr[TR_Z] = Z;
             tr[TR_ETA2] = e2;
-            tr[TR_INFEAS] = infeas;
+            tr[TR_INFEAS] = csum > 0.0 ? infeas / csum : infeas;   /* ||(u - c)^+||_1 / ||c||_1 */
             tr[TR_DBEST] = st->dbest;
             tr[TR_LB] = st->lb;
             tr[TR_GAP] = (st->dbest - st->lb) / fmax(fabs(st->dbest), DBL_MIN);

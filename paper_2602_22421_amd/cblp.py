@@ -20,22 +20,24 @@ _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libcblp.so
 CBLP_OK, CBLP_EINVAL, CBLP_ENOMEM, CBLP_EHIP, CBLP_ENONFINITE, CBLP_ENOTCONVERGED = range(6)
 CBLP_F32, CBLP_F64 = 1, 2
 SPFOM_STEP_CONST, SPFOM_STEP_POLYAK = 0, 1
+SPFOM_BOUND_GLOBAL, SPFOM_BOUND_SEGMENT = 0, 1
 NTRACE = 10
 TRACE_COLS = ("D", "P", "Z", "eta2", "infeas", "dbest", "lb", "gap", "step", "theta")
 EXPORTS = ("cblp_create", "cblp_destroy", "spfom_reset", "spfom_iterate", "spfom_solve",
            "cblp_gap", "cblp_sales", "cblp_launch_info", "cblp_timing", "cblp_timing_read",
            "cblp_last_error", "cblp_batch_create", "cblp_batch_destroy", "spfom_batch_iterate",
-           "spfom_batch_solve", "cblp_batch_tune", "cblp_batch_info", "wsnet_num_params",
-           "wsnet_create", "wsnet_destroy", "wsnet_params", "wsnet_features", "wsnet_forward",
-           "wsnet_gradients", "wsnet_train_step", "wsnet_train_epochs", "wsnet_targets",
-           "wsnet_predict")
+           "spfom_batch_solve", "cblp_batch_tune", "cblp_batch_info", "cblp_batch_select",
+           "wsnet_num_params", "wsnet_create", "wsnet_destroy", "wsnet_params", "wsnet_features",
+           "wsnet_forward", "wsnet_gradients", "wsnet_train_step", "wsnet_train_epochs",
+           "wsnet_targets", "wsnet_predict", "wsnet_start")
 
 
 class SpfomParams(ctypes.Structure):
     _fields_ = [("rule", ctypes.c_int32), ("check_every", ctypes.c_int32),
                 ("tau", ctypes.c_double), ("tau_vec", ctypes.c_void_p),
                 ("gamma", ctypes.c_double), ("mu", ctypes.c_double),
-                ("tol", ctypes.c_double), ("max_iters", ctypes.c_int64)]
+                ("tol", ctypes.c_double), ("max_iters", ctypes.c_int64),
+                ("bound", ctypes.c_int32)]
 
 
 class SpfomStats(ctypes.Structure):
@@ -81,10 +83,11 @@ def load(path: str = _LIB_PATH) -> ctypes.CDLL:
     lib.cblp_gap.restype = ctypes.c_int
     lib.cblp_gap.argtypes = [vp, vp, ctypes.POINTER(SpfomStats), vp]
     lib.cblp_sales.restype = ctypes.c_int
-    lib.cblp_sales.argtypes = [vp, vp, vp, vp, vp, vp]
+    lib.cblp_sales.argtypes = [vp, vp, vp, vp, vp, vp, vp]
     lib.cblp_launch_info.restype = ctypes.c_int
     lib.cblp_launch_info.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32),
-                                     ctypes.POINTER(i32)]
+                                     ctypes.POINTER(i32), ctypes.POINTER(i32),
+                                     ctypes.POINTER(ctypes.c_int64)]
     lib.cblp_timing.restype = ctypes.c_int
     lib.cblp_timing.argtypes = [vp, i32]
     lib.cblp_timing_read.restype = ctypes.c_int
@@ -106,6 +109,8 @@ def load(path: str = _LIB_PATH) -> ctypes.CDLL:
     lib.cblp_batch_info.restype = ctypes.c_int
     lib.cblp_batch_info.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32),
                                     ctypes.POINTER(i32)]
+    lib.cblp_batch_select.restype = ctypes.c_int
+    lib.cblp_batch_select.argtypes = [vp, i32]
     lib.cblp_last_error.restype = ctypes.c_char_p
     lib.cblp_last_error.argtypes = []
     lib.wsnet_num_params.restype = i64
@@ -132,6 +137,9 @@ def load(path: str = _LIB_PATH) -> ctypes.CDLL:
     lib.wsnet_targets.argtypes = [vp, vp, vp, vp]
     lib.wsnet_predict.restype = ctypes.c_int
     lib.wsnet_predict.argtypes = [vp, vp, vp, vp]
+    lib.wsnet_start.restype = ctypes.c_int
+    lib.wsnet_start.argtypes = [vp, vp, vp, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double),
+                                ctypes.POINTER(ctypes.c_double), vp]
     _lib = lib
     return lib
 
@@ -201,16 +209,22 @@ def cblp_gap(h, eta, stream=None) -> SpfomStats:
     return st
 
 
-def cblp_sales(h, eta, S_out=None, u_out=None, seg_R_out=None, stream=None) -> None:
+def cblp_sales(h, eta, S_out=None, u_out=None, seg_R_out=None, s_out=None, stream=None) -> None:
     _check(load().cblp_sales(ctypes.c_void_p(h), _ptr(eta), _ptr(S_out), _ptr(u_out),
-                             _ptr(seg_R_out), _stream(stream)))
+                             _ptr(seg_R_out), _ptr(s_out), _stream(stream)))
+
+
+SEG_KERNELS = ("f32-three-part-lds-prices", "f32-three-part-split-prices-ids16",
+               "f32-three-part-split-prices-ids32", "f64-8-lane-ids16", "f64-8-lane-ids32")
 
 
 def cblp_launch_info(h) -> dict:
-    g, b, f = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    g, b, f, k = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    e = ctypes.c_int64()
     _check(load().cblp_launch_info(ctypes.c_void_p(h), ctypes.byref(g), ctypes.byref(b),
-                                   ctypes.byref(f)))
-    return {"seg_grid": g.value, "lds_bins": b.value, "fx_bits": f.value}
+                                   ctypes.byref(f), ctypes.byref(k), ctypes.byref(e)))
+    return {"seg_grid": g.value, "lds_bins": b.value, "fx_bits": f.value,
+            "kernel": SEG_KERNELS[k.value], "slot_entries": e.value}
 
 
 def cblp_timing(h, enable: bool) -> None:
@@ -229,10 +243,11 @@ def cblp_timing_read(h, stream=None):
 
 def make_params(*, rule: int = SPFOM_STEP_CONST, check_every: int = 10, tau: float = 1.0,
                 tau_vec: Optional[torch.Tensor] = None, gamma: float = 1.0, mu: float = 0.0,
-                tol: float = 1e-4, max_iters: int = 10000) -> SpfomParams:
+                tol: float = 1e-4, max_iters: int = 10000,
+                bound: int = SPFOM_BOUND_GLOBAL) -> SpfomParams:
     p = SpfomParams(int(rule), int(check_every), float(tau),
                     None if tau_vec is None else tau_vec.data_ptr(), float(gamma), float(mu),
-                    float(tol), int(max_iters))
+                    float(tol), int(max_iters), int(bound))
     p._keep = tau_vec  # keep the tensor alive with the struct
     return p
 
@@ -298,12 +313,15 @@ class Problem:
     def gap(self, eta: torch.Tensor) -> dict:
         return cblp_gap(self.h, eta).as_dict()
 
-    def sales(self, eta: torch.Tensor, seg_R: bool = False):
+    def sales(self, eta: torch.Tensor, seg_R: bool = False, entries: bool = False):
+        """(S, u, R) at fixed eta; with entries=True also the per-entry sales
+        s [nnz] in the instance's CSR order, as a fourth value."""
         S = torch.zeros(self.n, dtype=torch.float64, device=self.device)
         u = torch.zeros(self.m, dtype=torch.float64, device=self.device)
         R = torch.zeros(self.L, dtype=self.dtype, device=self.device) if seg_R else None
-        cblp_sales(self.h, eta, S, u, R)
-        return S, u, R
+        s = torch.zeros(self.nnz, dtype=torch.float64, device=self.device) if entries else None
+        cblp_sales(self.h, eta, S, u, R, s)
+        return (S, u, R, s) if entries else (S, u, R)
 
 
 # ------------------------------------------------------------------ batches
@@ -352,6 +370,10 @@ def cblp_batch_tune(b, etas, tau_vecs, params: SpfomParams, iters: int, stream=N
     return chosen.value
 
 
+def cblp_batch_select(b, variant: int) -> None:
+    _check(load().cblp_batch_select(ctypes.c_void_p(b), int(variant)))
+
+
 def cblp_batch_info(b) -> dict:
     it, g, v = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
     _check(load().cblp_batch_info(ctypes.c_void_p(b), ctypes.byref(it), ctypes.byref(g),
@@ -391,6 +413,9 @@ class Batch:
 
     def info(self) -> dict:
         return cblp_batch_info(self.b)
+
+    def select(self, variant: int) -> None:
+        cblp_batch_select(self.b, variant)
 
 
 # ------------------------------------------------------------ learned warm start
@@ -478,6 +503,14 @@ def wsnet_predict(w, h, eta: torch.Tensor, stream=None) -> None:
                                 _stream(stream)))
 
 
+def wsnet_start(w, h, eta: torch.Tensor, stream=None) -> dict:
+    used = ctypes.c_int32()
+    dp, d0 = ctypes.c_double(), ctypes.c_double()
+    _check(load().wsnet_start(ctypes.c_void_p(w), ctypes.c_void_p(h), _ptr(eta), ctypes.byref(used),
+                              ctypes.byref(dp), ctypes.byref(d0), _stream(stream)))
+    return {"used": bool(used.value), "D_pred": dp.value, "D0": d0.value}
+
+
 class WarmStartNet:
     """The warm-start network (owns its device parameters)."""
 
@@ -526,6 +559,13 @@ class WarmStartNet:
         eta = prob.zeros_eta()
         wsnet_predict(self.w, prob.h, eta)
         return eta
+
+    def start(self, prob: "Problem"):
+        """The warm start with its cold fallback (decided in the library):
+        returns (eta, info) with info = {used, D_pred, D0}."""
+        eta = prob.zeros_eta()
+        info = wsnet_start(self.w, prob.h, eta)
+        return eta, info
 
 
 def targets(prob: "Problem", eta: torch.Tensor) -> torch.Tensor:

@@ -40,7 +40,7 @@ namespace {
 
 struct BInst {
     SegArgs seg;               // this instance's sorted copy and tail accumulator
-    SegArgs pseg[3];           // its pair, quad and 8-lane parts (slot-major copies),
+    SegArgs part_args[3];           // its pair, quad and 8-lane parts (slot-major copies),
     int64_t pstart[3];         // each viewed from its first position pstart[k]
     int64_t n, m;
     const void* r;
@@ -104,9 +104,9 @@ __global__ void k_reset_counter(unsigned* counter) { *counter = 0u; }
 
 // MODE 0: prices gathered from global memory; 1: the item's instance prices
 // copied into LDS behind the largest instance's bins (Hmax), then gathered
-// there; 2: as 1 over the 8-lane slot-major copies (IdxT: their product id
-// type); 3: as 1 over the handles' own slot-major copies, each part by the
-// groups of its width (2, 4 or 8 lanes; FP32, else 8 lanes only).
+// there; 3: as 1 over the handles' own slot-major copies, each part by the
+// groups of its width (2, 4 or 8 lanes; FP32, else 8 lanes only; IdxT: the
+// copies' product id type).
 template <typename T, int J, int DEPTH, int MODE, typename IdxT = int32_t>
 __global__ void __launch_bounds__(kSegThreads)
 k_bsegments(const BInst* inst, const BItem* items, int nitems, unsigned* counter,
@@ -136,7 +136,7 @@ k_bsegments(const BInst* inst, const BItem* items, int nitems, unsigned* counter
         const seg::FlatPrices<T> pr{MODE > 0 ? (const T*)lprice : (const T*)a.rho};
         const int64_t t0 = w.p0 / kSegsPerTile, t1 = (w.p1 + kSegsPerTile - 1) / kSegsPerTile;
         if constexpr (MODE == 3) {
-            const SegArgs& ap = I->pseg[w.part];   // fields read where used: fewer live registers
+            const SegArgs& ap = I->part_args[w.part];   // fields read where used: fewer live registers
             const int64_t q0 = w.p0 - I->pstart[w.part], q1 = w.p1 - I->pstart[w.part];
             bool done = false;
             if constexpr (sizeof(T) == 4) {
@@ -153,12 +153,9 @@ k_bsegments(const BInst* inst, const BItem* items, int nitems, unsigned* counter
                 }
             }
             if (!done)   // the 8-lane part (FP64 handles have no other)
-                seg::process_tiles_slots<T, J, false, seg::FlatPrices<T>, false, IdxT>(
+                seg::process_tiles_slots<T, J, false, seg::FlatPrices<T>, IdxT>(
                     ap, q0 / kSegsPerTile, (q1 + kSegsPerTile - 1) / kSegsPerTile, 1, bins, pr,
                     zacc);
-        } else if (MODE == 2) {
-            seg::process_tiles_slots<T, J, false, seg::FlatPrices<T>, false, IdxT>(a, t0, t1, 1,
-                                                                                  bins, pr, zacc);
         } else {
             seg::process_tiles<T, J, DEPTH>(a, t0, t1, 1, bins, pr, zacc);
         }
@@ -250,6 +247,7 @@ __global__ void __launch_bounds__(kRowThreads) k_bupdate(BArgs b)
         x[R_G] += p[R_G];
         x[R_TH] = fmin(x[R_TH], p[R_TH]);
         x[R_E2] += p[R_E2];
+        x[R_CS] += p[R_CS];
     }
     block_reduce(x, sh);
     const double D = x[R_CETA] + x[R_Z];
@@ -287,7 +285,7 @@ __global__ void __launch_bounds__(kRowThreads) k_bupdate(BArgs b)
         row[SPFOM_TR_PRIMAL] = x[R_P];
         row[SPFOM_TR_Z] = x[R_Z];
         row[SPFOM_TR_ETA2] = x[R_E2];
-        row[SPFOM_TR_INFEAS] = x[R_INF];
+        row[SPFOM_TR_INFEAS] = rel_infeas(x);
         row[SPFOM_TR_DBEST] = st.dbest;
         row[SPFOM_TR_LB] = st.lb;
         row[SPFOM_TR_GAP] = (st.dbest - st.lb) / fmax(fabs(st.dbest), DBL_MIN);
@@ -321,30 +319,25 @@ __global__ void __launch_bounds__(kRowThreads) k_bprices(const BInst* inst, cons
         ((T*)I->rho)[I->pnew ? I->pnew[i] : i] = ((const T*)I->r)[i] - ((const T*)I->eta)[i];
 }
 
-// Batched variants 0-6 as the single-instance ones (prices from global
-// memory); 7: ordered pipeline with the prices in LDS; 8: slot-major copies
-// with the prices in LDS (needs every handle's slot-major copy with 32-bit
-// ids); 9: the same over 16-bit-id copies; 10, 11: the handles' own
-// slot-major copies part by part (16- and 32-bit ids).
-constexpr int kBatchVariants = 12;
-inline bool bseg_lds_prices(int variant) { return variant >= 7; }
+// Batched variants (the autotuner's candidates):
+//   0  the row-major copies, prices gathered from global memory, no
+//      cross-tile prefetch (no register spills)
+//   1  the row-major copies, the item's instance prices copied into LDS,
+//      ordered one-tile pipeline
+//   2  the handles' own slot-major copies part by part, each part by the
+//      groups of its width (2, 4 or 8 lanes), prices in LDS, 16-bit ids
+//   3  the same over copies with 32-bit ids
+constexpr int kBatchVariants = 4;
+inline bool bseg_lds_prices(int variant) { return variant >= 1; }
 
 template <typename T>
 const void* bseg_fn(int variant)
 {
     switch (variant) {
-    case 0: return (const void*)k_bsegments<T, 8, 1, 0>;
-    case 1: return (const void*)k_bsegments<T, 6, 2, 0>;
-    case 2: return (const void*)k_bsegments<T, 4, 2, 0>;
-    case 3: return (const void*)k_bsegments<T, 8, 2, 0>;
-    case 5: return (const void*)k_bsegments<T, 8, 0, 0>;
-    case 6: return (const void*)k_bsegments<T, 7, 1, 0>;
-    case 7: return (const void*)k_bsegments<T, sizeof(T) == 4 ? 7 : 4, 3, 1>;
-    case 8: return (const void*)k_bsegments<T, sizeof(T) == 4 ? 7 : 4, 3, 2>;
-    case 9: return (const void*)k_bsegments<T, sizeof(T) == 4 ? 7 : 4, 3, 2, uint16_t>;
-    case 10: return (const void*)k_bsegments<T, sizeof(T) == 4 ? 7 : 4, 3, 3, uint16_t>;
-    case 11: return (const void*)k_bsegments<T, sizeof(T) == 4 ? 7 : 4, 3, 3, int32_t>;
-    default: return (const void*)k_bsegments<T, 4, 1, 0>;
+    case 1: return (const void*)k_bsegments<T, sizeof(T) == 4 ? 7 : 4, 3, 1>;
+    case 2: return (const void*)k_bsegments<T, sizeof(T) == 4 ? 7 : 4, 3, 3, uint16_t>;
+    case 3: return (const void*)k_bsegments<T, sizeof(T) == 4 ? 7 : 4, 3, 3, int32_t>;
+    default: return (const void*)k_bsegments<T, 8, 0, 0>;
     }
 }
 
@@ -382,11 +375,9 @@ struct cblp_batch {
     unsigned* counter = nullptr;
     double* pinned = nullptr;
     int grid = 1;
-    int variant = 6;
+    int variant = 0;
     int Hmax = 1;
     int64_t nmax = 1;               // most products of any instance
-    bool slots_ok = false;          // every handle has a slot-major copy with 32-bit ids
-    bool slots16_ok = false;        // every handle has one with 16-bit ids
     bool parts16_ok = false;        // every handle has a slot-major copy (any parts), 16-bit ids
     bool parts32_ok = false;        // the same with 32-bit ids
     hipStream_t stream = nullptr;    // the batch's own stream (graph capture needs one)
@@ -441,6 +432,8 @@ int check_bparams(const spfom_params* p)
     if (!(p->mu >= 0.0) || !std::isfinite(p->mu)) return bfail(CBLP_EINVAL, "mu must be >= 0");
     if (p->rule == SPFOM_STEP_POLYAK && !(p->gamma > 0.0 && p->gamma <= 2.0))
         return bfail(CBLP_EINVAL, "gamma must be in (0, 2]");
+    if (p->bound != SPFOM_BOUND_GLOBAL)
+        return bfail(CBLP_EINVAL, "batches certify with the global bound only");
     return CBLP_OK;
 }
 
@@ -551,10 +544,8 @@ size_t bseg_lds(const cblp_batch* b, int variant)
 bool bseg_usable(const cblp_batch* b, int variant)
 {
     if (variant < 0 || variant >= kBatchVariants) return false;
-    if (variant == 8 && !b->slots_ok) return false;
-    if (variant == 9 && !b->slots16_ok) return false;
-    if (variant == 10 && !b->parts16_ok) return false;
-    if (variant == 11 && !b->parts32_ok) return false;
+    if (variant == 2 && !b->parts16_ok) return false;
+    if (variant == 3 && !b->parts32_ok) return false;
     const void* f = b->dtype == CBLP_F32 ? bseg_fn<float>(variant) : bseg_fn<double>(variant);
     const size_t lds = bseg_lds(b, variant);
     int per_cu = 0;
@@ -615,18 +606,11 @@ int cblp_batch_create(cblp_batch_t* out, int32_t count, const cblp_t* handles, v
         Hmax = std::max<int64_t>(Hmax, h->H);
     }
     b->Hmax = (int)Hmax;
-    b->slots_ok = true;
-    b->slots16_ok = true;
     b->parts16_ok = true;
     b->parts32_ok = true;
     for (int q = 0; q < count; ++q) {
         b->nmax = std::max<int64_t>(b->nmax, b->hs[q]->n);
-        const bool slots8 = b->hs[q]->woff != nullptr && !seg_quad(b->hs[q]->seg_variant) &&
-                            !seg_mixed(b->hs[q]->seg_variant) &&
-                            !seg_mixed3(b->hs[q]->seg_variant);
-        b->slots_ok = b->slots_ok && slots8 && !b->hs[q]->idx16;
-        b->slots16_ok = b->slots16_ok && slots8 && b->hs[q]->idx16;
-        // FP64 handles take part 2 only (the narrow groups are FP32 kernels)
+        // FP64 handles have one 8-lane part (the narrow groups are FP32 kernels)
         const bool parts = b->hs[q]->woff != nullptr &&
                            (b->dtype == CBLP_F32 || b->hs[q]->quad_end == 0);
         b->parts16_ok = b->parts16_ok && parts && b->hs[q]->idx16;
@@ -642,14 +626,9 @@ int cblp_batch_create(cblp_batch_t* out, int32_t count, const cblp_t* handles, v
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, b->hs[0]->device) == hipSuccess && prop.multiProcessorCount > 0)
         cus = prop.multiProcessorCount;
-    // default: slot-major copies with LDS prices when every instance has them
-    // and they fit, else the spill-free global-price variant
-    b->variant = bseg_usable(b, 10) ? 10 : bseg_usable(b, 11) ? 11 : bseg_usable(b, 9) ? 9
-               : bseg_usable(b, 8) ? 8 : bseg_usable(b, 7) ? 7 : 5;
-    if (const char* ev = std::getenv("CBLP_BATCH_VARIANT")) {
-        const int x = std::atoi(ev);
-        if (x >= 0 && x < kBatchVariants && bseg_usable(b, x)) b->variant = x;
-    }
+    // default: the handles' slot-major copies with LDS prices when every
+    // instance has them and they fit, else the spill-free global-price variant
+    b->variant = bseg_usable(b, 2) ? 2 : bseg_usable(b, 3) ? 3 : bseg_usable(b, 1) ? 1 : 0;
     const size_t lds = bseg_lds(b, b->variant);
     int per_cu = 1;
     {
@@ -694,12 +673,10 @@ int cblp_batch_create(cblp_batch_t* out, int32_t count, const cblp_t* handles, v
         a.n = h->n;
         a.H = h->H;
         a.hp = 0;
-        a.blk = nullptr;
         a.woff = h->woff;
         a.idx3 = h->idx3;
         a.v3 = h->v3;
         a.den3 = h->den3;
-        a.part_S = nullptr;
         a.S_fx = h->S_fx;
         a.fx_scale = h->fx_scale;
         a.zpart = nullptr;
@@ -731,7 +708,7 @@ int cblp_batch_create(cblp_batch_t* out, int32_t count, const cblp_t* handles, v
             v.Rwarm = (char*)h->Rwarm + pb[k] * esz;
             v.perm = h->perm + pb[k];
             v.woff = h->woff ? h->woff + wo[k] : nullptr;
-            I.pseg[k] = v;
+            I.part_args[k] = v;
             I.pstart[k] = pb[k];
         }
         I.item0 = (int)items.size();
@@ -827,10 +804,19 @@ int spfom_batch_solve(cblp_batch_t b, void* const* etas, const void* const* tau_
         std::memset(&outs[q], 0, sizeof(spfom_stats));
         outs[q].status = CBLP_ENOTCONVERGED;
     }
+    // every active instance has done the same number of iterations t: run
+    // blocks of K (the graph), the last one cut to max_iters - t (eager), and
+    // test the gap after whole blocks only, as spfom_solve does
     const int64_t K = p->check_every;
     int live = b->count;
-    while (live > 0) {
-        BHIP(hipGraphLaunch(b->exec, b->stream));
+    int64_t t = 0;
+    while (live > 0 && t < p->max_iters) {
+        const int64_t k = std::min<int64_t>(K, p->max_iters - t);
+        if (k == K)
+            BHIP(hipGraphLaunch(b->exec, b->stream));
+        else if ((rc = run_iters(b, p, k, b->stream)))
+            return rc;
+        t += k;
         BHIP(hipMemcpyAsync(b->pinned, b->rows, (size_t)b->count * SPFOM_NTRACE * 8,
                             hipMemcpyDeviceToHost, b->stream));
         BHIP(hipStreamSynchronize(b->stream));
@@ -838,7 +824,7 @@ int spfom_batch_solve(cblp_batch_t b, void* const* etas, const void* const* tau_
         bool changed = false;
         for (int q = 0; q < b->count; ++q) {
             if (!b->h_inst[q].active) continue;
-            b->t[q] += K;
+            b->t[q] += k;
             spfom_stats& o = outs[q];
             o.iters = b->t[q];
             std::memcpy(o.trace, b->pinned + (size_t)q * SPFOM_NTRACE, sizeof(o.trace));
@@ -847,9 +833,9 @@ int spfom_batch_solve(cblp_batch_t b, void* const* etas, const void* const* tau_
             for (int c = 0; c < SPFOM_NTRACE; ++c) finite = finite && std::isfinite(o.trace[c]);
             if (!finite) {
                 o.status = CBLP_ENONFINITE;
-            } else if (o.trace[SPFOM_TR_GAP] <= p->tol) {
+            } else if (t % K == 0 && o.trace[SPFOM_TR_GAP] <= p->tol) {
                 o.status = CBLP_OK;
-            } else if (b->t[q] + K <= p->max_iters) {
+            } else if (t < p->max_iters) {
                 continue;
             }
             b->h_inst[q].active = 0;
@@ -881,7 +867,7 @@ int cblp_batch_tune(cblp_batch_t b, void* const* etas, const void* const* tau_ve
     if ((rc = enter(b, caller))) return rc;
     if ((rc = bind(b, etas, tau_vecs, p, b->stream))) return rc;
     if ((rc = run_prices(b, b->stream))) return rc;
-    const int candidates[] = {5, 6, 0, 4, 7, 8, 9, 10, 11};
+    const int candidates[] = {0, 1, 2, 3};
     double best = INFINITY;
     int best_v = b->variant;
     // the trial iterations move every handle's warm-start R*: keep a copy and
@@ -940,6 +926,20 @@ int cblp_batch_tune(cblp_batch_t b, void* const* etas, const void* const* tau_ve
     if (!rc) rc = reset_states(b, b->stream);
     const int rc2 = leave(b, caller);
     return rc ? rc : rc2;
+}
+
+int cblp_batch_select(cblp_batch_t b, int32_t variant)
+{
+    set_error(CBLP_OK, "");
+    if (!b) return bfail(CBLP_EINVAL, "NULL batch");
+    if (!bseg_usable(b, variant))
+        return bfail(CBLP_EINVAL, "batch variant " + std::to_string(variant) + " cannot run on this batch");
+    if (variant != b->variant && b->exec) {
+        (void)hipGraphExecDestroy(b->exec);   // the captured graph holds the old kernel
+        b->exec = nullptr;
+    }
+    b->variant = variant;
+    return CBLP_OK;
 }
 
 int cblp_batch_info(cblp_batch_t b, int32_t* items, int32_t* grid, int32_t* variant)

@@ -1,25 +1,45 @@
-"""Compile libcblp.so for gfx950 with hipcc (in-tree)."""
+"""Compile libcblp.so for gfx950 with hipcc (in-tree).
+
+Each source is compiled to an object of its own in parallel, then the
+objects are linked into the shared library.
+"""
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 PKG = os.path.dirname(HERE)
 ROOT = os.path.dirname(PKG)
 LIB = os.path.join(PKG, "libcblp.so")
-SOURCES = [os.path.join(HERE, f) for f in ("capi.hip", "prep.hip", "segment.hip", "dual.hip", "batch.hip", "mlp.hip")]
+OBJDIR = os.path.join(HERE, "_build")
+NAMES = ("capi", "prep", "segment", "dual", "batch", "mlp", "recover", "minibatch")
+SOURCES = [os.path.join(HERE, f + ".hip") for f in NAMES
+           if os.path.exists(os.path.join(HERE, f + ".hip"))]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [
-    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I", os.path.join(ROOT, "include"),
 ]
 
 
-def build(verbose: bool = False, extra=()) -> str:
+def build(verbose: bool = False, extra=(), jobs: int = 8) -> str:
+    os.makedirs(OBJDIR, exist_ok=True)
+
+    def compile_one(src):
+        obj = os.path.join(OBJDIR, os.path.basename(src)[:-4] + ".o")
+        cmd = [HIPCC, *FLAGS, *extra, "-c", src, "-o", obj]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.run(cmd, check=True)
+        return obj
+
+    with ThreadPoolExecutor(max_workers=max(1, min(jobs, len(SOURCES)))) as ex:
+        objs = list(ex.map(compile_one, SOURCES))
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, *FLAGS, *extra, *SOURCES, "-o", tmp]
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
@@ -28,5 +48,5 @@ def build(verbose: bool = False, extra=()) -> str:
 
 
 if __name__ == "__main__":
-    build(verbose=True)
+    build(verbose="-v" in sys.argv)
     print(LIB)

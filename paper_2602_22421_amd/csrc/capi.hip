@@ -80,10 +80,11 @@ void release(cblp_instance* h)
     if (!h) return;
     void* ptrs[] = {h->ptr2, h->idx2, h->v2, h->den2, h->vt0, h->lam2, h->Rwarm, h->v0c, h->perm,
                     h->pnew,
-                    h->seg_blk, h->woff, h->idx3, h->v3, h->den3,
-                    h->rho, h->S_fx, h->part_S, h->S_d, h->u_d, h->sum_u, h->zpart,
+                    h->woff, h->idx3, h->v3, h->den3,
+                    h->rho, h->S_fx, h->S_d, h->u_d, h->sum_u, h->zpart,
                     h->bpart, h->bpart2, h->st, h->arrive, h->trace, h->at_ptr,
-                    h->at_prod, h->at_val};
+                    h->at_prod, h->at_val, h->rlib, h->psum, h->theta_prod, h->pseg_part,
+                    h->eval_thr, h->eval_lamD};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     if (h->pinned) (void)hipHostFree(h->pinned);
@@ -139,11 +140,41 @@ int check_params(const spfom_params* p)
     if (!(p->mu >= 0.0) || !std::isfinite(p->mu)) return fail(CBLP_EINVAL, "mu must be >= 0");
     if (p->rule == SPFOM_STEP_POLYAK && !(p->gamma > 0.0 && p->gamma <= 2.0))
         return fail(CBLP_EINVAL, "gamma must be in (0, 2]");
+    if (p->bound != SPFOM_BOUND_GLOBAL && p->bound != SPFOM_BOUND_SEGMENT)
+        return fail(CBLP_EINVAL, "unknown bound");
     return CBLP_OK;
 }
 
+// Buffers of the per-segment bound, made on first use: revenues by library
+// product id (r - A^T 0 through the price kernel), the running revenue sums
+// by position, theta by library id and the k_pseg partials.
 template <typename T>
-int run_segments(cblp_instance* h, void* seg_R, hipStream_t s)
+int ensure_pseg(cblp_instance* h, hipStream_t s)
+{
+    if (h->psum) return CBLP_OK;
+    int rc;
+    void* zeros = nullptr;
+    if ((rc = dalloc(&zeros, (size_t)h->m * h->esz))) return rc;
+    if ((rc = dalloc(&h->rlib, (size_t)h->n * h->esz)) ||
+        (rc = dalloc(&h->theta_prod, (size_t)h->n * 8)) ||
+        (rc = dalloc(&h->pseg_part, (size_t)kPsegBlocks * 8)) ||
+        (rc = dalloc(&h->psum, (size_t)std::max<int64_t>(h->L, 1) * 8))) {
+        (void)hipFree(zeros);
+        return rc;
+    }
+    hipError_t e = hipMemsetAsync(zeros, 0, (size_t)h->m * h->esz, s);
+    if (e == hipSuccess)
+        e = launch_prices<T>(h->n, h->r, zeros, h->a_ptr, h->a_idx, h->a_val, h->pnew, h->rlib, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)hipFree(zeros);
+    if (e != hipSuccess) return fail(CBLP_EHIP, std::string("revenue copy: ") + hipGetErrorString(e));
+    return CBLP_OK;
+}
+
+// pseg: add each segment's revenue to h->psum (per-segment bound);
+// eval_out: store each position's threshold and (lambda / D) 2^bits
+template <typename T>
+int run_segments(cblp_instance* h, void* seg_R, bool pseg, bool eval_out, hipStream_t s)
 {
     SegArgs a;
     a.L = h->L;
@@ -159,12 +190,16 @@ int run_segments(cblp_instance* h, void* seg_R, hipStream_t s)
     a.n = h->n;
     a.H = h->H;
     a.hp = h->hp;
-    a.part_S = h->flush_atomic ? nullptr : h->part_S;
     a.S_fx = h->S_fx;
     a.fx_scale = h->fx_scale;
     a.zpart = h->zpart;
     a.seg_R = seg_R;
-    a.blk = h->seg_blk;
+    a.seg_thr = eval_out ? h->eval_thr : nullptr;
+    a.seg_lamD = eval_out ? h->eval_lamD : nullptr;
+    a.psum = pseg ? h->psum : nullptr;
+    a.rlib = h->rlib;
+    a.inv_fx = 1.0 / h->fx_scale;
+    a.psum_reset = h->psum_reset_next ? 1 : 0;
     a.woff = h->woff;
     a.idx3 = h->idx3;
     a.v3 = h->v3;
@@ -172,41 +207,29 @@ int run_segments(cblp_instance* h, void* seg_R, hipStream_t s)
     size_t slot;
     int rc = timed_begin(h, 0, s, &slot);
     if (rc) return rc;
-    if (seg_mixed3(h->seg_variant)) {
-        // views of the pair part [0, P2), the quad part [P2, P4) and the rest
-        const int64_t P2 = h->pair_end, P4 = h->quad_end;
-        const size_t esz = h->esz;
-        auto view = [&](int64_t p0, int64_t p1, int64_t wo) {
-            SegArgs v = a;
-            v.L = p1 - p0;
-            v.ptr = h->ptr2 + p0;
-            v.vt0 = (const char*)h->vt0 + p0 * esz;
-            v.lam = (const char*)h->lam2 + p0 * esz;
-            v.Rwarm = (char*)h->Rwarm + p0 * esz;
-            v.perm = h->perm + p0;
-            v.woff = h->woff + wo;
-            return v;
-        };
-        const SegArgs a2 = view(0, P2, 0), a4 = view(P2, P4, h->woff_q),
-                      a8 = view(P4, h->L, h->woff_b);
-        HIP_TRY(launch_segments_mixed3<T>(a2, a4, a8, h->seg_grid, h->seg_variant, s));
-    } else if (seg_mixed(h->seg_variant)) {
-        // the quad part, positions [0, P), and the rest viewed from P
-        const int64_t P = h->quad_end;
-        const size_t esz = h->esz;
-        SegArgs b = a;
-        a.L = P;
-        b.L = h->L - P;
-        b.ptr = h->ptr2 + P;
-        b.vt0 = (const char*)h->vt0 + P * esz;
-        b.lam = (const char*)h->lam2 + P * esz;
-        b.Rwarm = (char*)h->Rwarm + P * esz;
-        b.perm = h->perm + P;
-        b.woff = h->woff + h->woff_b;
-        HIP_TRY(launch_segments_mixed<T>(a, b, h->seg_grid, h->seg_variant, s));
-    } else {
-        HIP_TRY(launch_segments<T>(a, h->seg_grid, h->seg_variant, s));
-    }
+    // views of the pair part [0, P2), the quad part [P2, P4) and the rest
+    // (the FP64 kernels have only the 8-lane part: P2 = P4 = 0)
+    const int64_t P2 = h->pair_end, P4 = h->quad_end;
+    const size_t esz = h->esz;
+    auto view = [&](int64_t p0, int64_t p1, int64_t wo) {
+        SegArgs v = a;
+        v.L = p1 - p0;
+        v.ptr = h->ptr2 + p0;
+        v.vt0 = (const char*)h->vt0 + p0 * esz;
+        v.lam = (const char*)h->lam2 + p0 * esz;
+        v.Rwarm = (char*)h->Rwarm + p0 * esz;
+        v.perm = h->perm + p0;
+        v.woff = h->woff + wo;
+        if (v.seg_thr) {
+            v.seg_thr = (char*)h->eval_thr + p0 * esz;
+            v.seg_lamD = (char*)h->eval_lamD + p0 * esz;
+        }
+        if (v.psum) v.psum = h->psum + p0;
+        return v;
+    };
+    const SegArgs a2 = view(0, P2, 0), a4 = view(P2, P4, h->woff_q),
+                  a8 = view(P4, h->L, h->woff_b);
+    HIP_TRY(launch_segments<T>(a2, a4, a8, h->seg_grid, h->seg_variant, pseg, s));
     return timed_end(h, slot, s);
 }
 
@@ -226,9 +249,6 @@ int run_phase(cblp_instance* h, void* eta, const spfom_params* p, int mode, doub
     a.tau_vec = p ? p->tau_vec : nullptr;
     a.zpart = h->zpart;
     a.nz = h->seg_grid;
-    a.part_S = h->part_S;
-    a.nseg = h->flush_atomic ? 0 : h->seg_grid;   // no partial rows to fold
-    a.H = h->H;
     a.S_fx = h->S_fx;
     a.inv_fx = 1.0 / h->fx_scale;
     a.r = h->r;
@@ -246,13 +266,22 @@ int run_phase(cblp_instance* h, void* eta, const spfom_params* p, int mode, doub
     a.sum_u = h->sum_u;
     a.bpart = h->bpart;
     a.bpart2 = h->bpart2;
-    // without partial rows the fold takes 256 products per block
-    a.fold_blocks = h->flush_atomic ? (int)((h->n + 255) / 256) : h->fold_blocks;
+    a.fold_blocks = h->fold_blocks;
     a.pnew = h->pnew;
     a.arrive = h->arrive;
     a.st = h->st;
     a.par = (int)(h->t & 1);
     a.row = row;
+    // the per-segment bound at a check of a window that accumulated psum
+    const bool check = p && mode == 0 && (h->t + 1) % p->check_every == 0;
+    const bool pseg = check && p->bound == SPFOM_BOUND_SEGMENT && h->pseg_window_ok;
+    a.theta_prod = h->theta_prod;
+    a.L = h->L;
+    a.ptr2 = h->ptr2;
+    a.idx2 = h->idx2;
+    a.psum = h->psum;
+    a.pseg_part = pseg ? h->pseg_part : nullptr;
+    a.pseg_blocks = kPsegBlocks;
     size_t slot;
     int rc = timed_begin(h, 1, s, &slot);
     if (rc) return rc;
@@ -264,23 +293,41 @@ template <typename T>
 int iterate_impl(cblp_instance* h, void* eta, const spfom_params* p, int64_t iters,
                  bool keep_trace, hipStream_t s)
 {
-    HIP_TRY(launch_prices<T>(h->n, h->r, eta, h->a_ptr, h->a_idx, h->a_val, h->pnew, h->rho, s));
+    const bool pseg = p->bound == SPFOM_BOUND_SEGMENT;
     int rc;
+    if (pseg && (rc = ensure_pseg<T>(h, s))) return rc;
+    HIP_TRY(launch_prices<T>(h->n, h->r, eta, h->a_ptr, h->a_idx, h->a_val, h->pnew, h->rho, s));
     for (int64_t it = 0; it < iters; ++it) {
         double* row = h->trace + (keep_trace ? it : 0) * SPFOM_NTRACE;
-        if ((rc = run_segments<T>(h, nullptr, s))) return rc;
+        if ((rc = run_segments<T>(h, nullptr, pseg, false, s))) return rc;
         if ((rc = run_phase<T>(h, eta, p, 0, row, s))) return rc;
         h->t += 1;
+        // the averaging window restarts after t = 1 and whenever t doubles its
+        // start (the device state does the same)
+        const bool restart = h->t == 1 || h->t == 2 * h->t0h;
+        if (restart) h->t0h = h->t;
+        if (!pseg) h->pseg_window_ok = false;
+        if (restart) h->pseg_window_ok = true;
+        if (pseg) h->psum_reset_next = false;
+        if (restart) h->psum_reset_next = true;
     }
     return CBLP_OK;
 }
 
 template <typename T>
-int evaluate_impl(cblp_instance* h, const void* eta, void* seg_R, hipStream_t s)
+int evaluate_impl(cblp_instance* h, const void* eta, void* seg_R, double* s_out, hipStream_t s)
 {
+    int rc;
+    if (s_out && !h->eval_thr) {
+        const size_t bytes = (size_t)std::max<int64_t>(h->L, 1) * h->esz;
+        if ((rc = dalloc(&h->eval_thr, bytes)) || (rc = dalloc(&h->eval_lamD, bytes))) return rc;
+    }
     HIP_TRY(launch_prices<T>(h->n, h->r, eta, h->a_ptr, h->a_idx, h->a_val, h->pnew, h->rho, s));
-    int rc = run_segments<T>(h, seg_R, s);
-    if (rc) return rc;
+    if ((rc = run_segments<T>(h, seg_R, false, s_out != nullptr, s))) return rc;
+    if (s_out)
+        HIP_TRY(launch_entry_sales<T>(h->L, h->perm, h->seg_ptr, h->idx, h->v, h->w, h->pnew,
+                                      h->rho, h->eval_thr, h->eval_lamD, 1.0 / h->fx_scale, s_out,
+                                      s));
     // evaluation leaves eta and the solver state untouched
     return run_phase<T>(h, const_cast<void*>(eta), nullptr, 1, h->trace, s);
 }
@@ -310,6 +357,9 @@ int reset_state(cblp_instance* h, hipStream_t s)
     HIP_TRY(hipMemsetAsync(h->sum_u, 0, (size_t)h->m * sizeof(double), s));
     HIP_TRY(hipStreamSynchronize(s));
     h->t = 0;
+    h->t0h = 0;
+    h->psum_reset_next = true;
+    h->pseg_window_ok = true;
     return CBLP_OK;
 }
 
@@ -403,50 +453,30 @@ int create_impl(cblp_instance* h, hipStream_t s)
     HIP_TRY(hipStreamSynchronize(s));
     int64_t kmax = 0;
     for (int64_t l = 0; l < h->L; ++l) kmax = std::max(kmax, sp[l + 1] - sp[l]);
-    const bool short_rows = kmax <= kQuadMaxRow;   // every row fits the quad kernels' registers
 
-    // kernel variant and bin count may be overridden for tuning runs.  The
-    // prices go to LDS when they take at most half of it, else the popular
-    // head of them does.
+    // The kernel follows from the dtype and the shape.  FP32: rows of at most
+    // kPairMaxRow entries go to 2-lane groups, of at most kQuadMaxRow to
+    // 4-lane groups, longer ones to 8-lane groups; the prices go to LDS when
+    // they take at most half of it, else the popular head of them does.
+    // FP64: 8-lane groups with the prices in global memory.  Product ids are
+    // stored in 16 bits when they fit.
     const bool prices_fit = (int64_t)h->n * (int64_t)sizeof(T) * 2 <= (int64_t)lds_block;
-    // 16-bit product ids in the slot-major copy when they fit
     const bool ids16 = h->n <= 65536;
-    // FP32: rows of at most kPairMaxRow entries go to 2-lane groups, of at most
-    // kQuadMaxRow to 4-lane groups, longer ones to 8-lane groups (the
-    // three-part mixed kernels, with all prices or the head of them in LDS)
     if (sizeof(T) == 4)
-        h->seg_variant = prices_fit ? (ids16 ? kSegMixed3 : kSegMixed3 + 1)
-                                    : (ids16 ? kSegMixed3 + 3 : kSegMixed3 + 2);
+        h->seg_variant = (prices_fit && ids16) ? kSegMixed3
+                         : ids16 ? kSegMixed3Split16 : kSegMixed3Split32;
     else
-        h->seg_variant = ids16 ? kSegSlots16 + 2 : kSegSlots + 3;
-    if (const char* ev = std::getenv("CBLP_SEG_VARIANT")) {
-        const int x = std::atoi(ev);
-        if (x >= 0 && x < kSegVariants && (!seg_lds_prices(x) || prices_fit || seg_split(x)) &&
-            (!seg_idx16(x) || ids16))
-            h->seg_variant = x;
-    }
+        h->seg_variant = ids16 ? kSegSlots16 : kSegSlots32;
     h->idx16 = seg_idx16(h->seg_variant);
-    int64_t split = kSplitPrices;   // head prices held in LDS by the split kernels
-    if (const char* es = std::getenv("CBLP_SPLIT_PRICES")) {
-        const long x = std::atol(es);
-        if (x >= 1 && x * (int64_t)sizeof(T) * 2 <= (int64_t)lds_block) split = x;
-    }
-    h->hp = seg_split(h->seg_variant) ? (int)std::min<int64_t>(h->n, split) : 0;
+    h->hp = seg_split(h->seg_variant) ? (int)std::min<int64_t>(h->n, kSplitPrices) : 0;
     const int64_t price_bytes = seg_split(h->seg_variant) ? (int64_t)h->hp * (int64_t)sizeof(T)
                                 : seg_lds_prices(h->seg_variant) ? h->n * (int64_t)sizeof(T) : 0;
     const int64_t lds_bins = ((int64_t)lds_block - 1024 - price_bytes) / 8;
     h->H = (int)std::max<int64_t>(1, std::min<int64_t>({h->n, (int64_t)kMaxBins, lds_bins}));
-    // CBLP_FLUSH=rows: per-block partial rows of the bins, folded in block order
-    if (const char* ef = std::getenv("CBLP_FLUSH")) h->flush_atomic = std::string(ef) != "rows";
-    if (const char* eb = std::getenv("CBLP_SEG_BINS")) {
-        const long x = std::atol(eb);
-        if (x >= 1 && x <= h->H) h->H = (int)x;
-    }
-    const int per_cu = segment_blocks_per_cu<T>(
-        h->H, seg_split(h->seg_variant) ? (int64_t)h->hp : h->n, h->seg_variant);
+    const int per_cu = segment_blocks_per_cu<T>(h->H, h->n, h->hp, h->seg_variant);
     const int64_t tiles = (h->L + kSegsPerTile - 1) / kSegsPerTile;
     h->seg_grid = (int)std::max<int64_t>(1, std::min<int64_t>(tiles, (int64_t)cus * per_cu));
-    h->fold_blocks = (int)((h->n + kFoldProducts - 1) / kFoldProducts);
+    h->fold_blocks = (int)((h->n + kFoldLite - 1) / kFoldLite);
     const int64_t row_blocks = (h->m + kRowThreads - 1) / kRowThreads;
 
     const size_t esz = h->esz;
@@ -466,10 +496,9 @@ int create_impl(cblp_instance* h, hipStream_t s)
         return fail(CBLP_ENOMEM, "hipHostMalloc failed");
 
     // product ids by falling degree (ties keep their order), unless the
-    // caller's numbering already is that order or CBLP_RELABEL=0
+    // caller's numbering already is that order
     {
-        const char* er = std::getenv("CBLP_RELABEL");
-        if (!(er && std::string(er) == "0") && h->n > 1 && h->nnz > 0) {
+        if (h->n > 1 && h->nnz > 0) {
             unsigned long long* ddeg = nullptr;
             if ((rc = dalloc(&ddeg, (size_t)h->n * 8))) return rc;
             std::vector<unsigned long long> deg((size_t)h->n);
@@ -505,44 +534,6 @@ int create_impl(cblp_instance* h, hipStream_t s)
         for (int64_t l = 0; l < h->L; ++l) perm[start[sp[l + 1] - sp[l]]++] = (int32_t)l;
         std::vector<int64_t> ptr((size_t)h->L + 1, 0);
         for (int64_t p = 0; p < h->L; ++p) ptr[p + 1] = ptr[p] + (sp[perm[p] + 1] - sp[perm[p]]);
-        if (seg_class(h->seg_variant)) {
-            // runs of tiles with one slot count (rows ascend, so a tile's last
-            // row is its longest); blocks per run in proportion to its entries
-            std::vector<int64_t> blk;
-            const int64_t grid0 = h->seg_grid;
-            // cost of a run: its entries plus alpha per segment
-            double alpha = 8.0;
-            if (const char* ea = std::getenv("CBLP_CLASS_ALPHA")) alpha = std::atof(ea);
-            const double total = (double)h->nnz + alpha * (double)h->L;
-            int64_t t = 0;
-            while (t < tiles) {
-                auto slots = [&](int64_t tt) {
-                    const int64_t last = std::min(h->L, (tt + 1) * kSegsPerTile) - 1;
-                    const int64_t len = ptr[last + 1] - ptr[last];
-                    return std::min<int64_t>(seg_class_max_slots(sizeof(T)),
-                                             std::max<int64_t>(1, (len + kGroup - 1) / kGroup));
-                };
-                const int64_t J = slots(t);
-                int64_t u = t + 1;
-                while (u < tiles && slots(u) == J) ++u;
-                const int64_t e0 = ptr[t * kSegsPerTile];
-                const int64_t e1 = ptr[std::min(h->L, u * kSegsPerTile)];
-                const int64_t s0 = t * kSegsPerTile, s1 = std::min(h->L, u * kSegsPerTile);
-                const double share =
-                    total > 0 ? ((double)(e1 - e0) + alpha * (double)(s1 - s0)) / total : 1.0;
-                const int64_t g = std::max<int64_t>(1, std::min<int64_t>(u - t, std::llround(share * (double)grid0)));
-                for (int64_t i = 0; i < g; ++i) {
-                    blk.push_back(J);
-                    blk.push_back(t + (u - t) * i / g);
-                    blk.push_back(t + (u - t) * (i + 1) / g);
-                }
-                t = u;
-            }
-            if (blk.empty()) blk = {1, 0, 0};
-            h->seg_grid = (int)(blk.size() / 3);
-            if ((rc = dalloc(&h->seg_blk, blk.size() * 8))) return rc;
-            HIP_TRY(hipMemcpyAsync(h->seg_blk, blk.data(), blk.size() * 8, hipMemcpyHostToDevice, s));
-        }
         if ((rc = dalloc(&h->ptr2, (size_t)(h->L + 1) * 8))) return rc;
         if ((rc = dalloc(&h->perm, (size_t)L1 * 4))) return rc;
         // the copy is followed by kPad entries (product 0, v = 0, den = 1)
@@ -568,21 +559,21 @@ int create_impl(cblp_instance* h, hipStream_t s)
             HIP_TRY(launch_relayout<T>(h->L, h->seg_ptr, h->idx, h->v, h->w, h->v0, h->lam,
                                        h->perm, h->pnew, h->ptr2, h->idx2, h->v2, h->den2, h->vt0,
                                        h->lam2, h->Rwarm, h->v0c, s));
-        if (seg_slot_major(h->seg_variant)) {
-            // slot-major copy: wave-tile w (positions Rw..Rw+R-1, R = 64 / G rows
-            // of G lanes) gets 64 entries per slot for as many slots as its
-            // longest row needs (at least one).  Mixed variants: positions
-            // [0, P) (rows of at most kQuadMaxRow entries; rows ascend) in the
-            // quad layout, the rest in the 8-lane one behind it, each with its
-            // own offsets (one spare entry each)
-            // (part boundaries are rounded down to multiples of kPartAlign
-            // positions, so that every part starts on a tile of every layout;
-            // a row just below a boundary goes to the wider groups)
-            const bool mixed = seg_mixed(h->seg_variant), mixed3 = seg_mixed3(h->seg_variant);
-            int64_t P2 = 0, P = seg_quad(h->seg_variant) ? h->L : 0;
-            if (mixed3)
+        {
+            // slot-major copy: wave-tile w of a part (positions Rw..Rw+R-1 of
+            // it, R = 64 / G rows of G lanes) gets 64 entries per slot for as
+            // many slots as its longest row needs (at least one).  FP32:
+            // positions [0, P2) (rows of at most kPairMaxRow entries; rows
+            // ascend) in the pair layout, [P2, P) (at most kQuadMaxRow) in the
+            // quad layout, the rest in the 8-lane one, each part with its own
+            // offsets (one spare entry each).  Part boundaries are rounded down
+            // to multiples of kPartAlign positions, so that every part starts
+            // on a tile of every layout; a row just below a boundary goes to
+            // the wider groups.  FP64: one 8-lane part.
+            const bool mixed3 = seg_mixed3(h->seg_variant);
+            int64_t P2 = 0, P = 0;
+            if (mixed3) {
                 while (P2 < h->L && ptr[P2 + 1] - ptr[P2] <= kPairMaxRow) ++P2;
-            if (mixed || mixed3) {
                 P = P2;
                 while (P < h->L && ptr[P + 1] - ptr[P] <= kQuadMaxRow) ++P;
                 P2 = P2 / kPartAlign * kPartAlign;
@@ -604,49 +595,27 @@ int create_impl(cblp_instance* h, hipStream_t s)
                 woff.push_back(woff.back());
                 return w0;
             };
-            const bool quad = seg_quad(h->seg_variant);
-            if (mixed3) {
-                part(0, P2, 2);
-                h->woff_q = (int64_t)part(P2, P, 4);
-                h->woff_b = (int64_t)part(P, h->L, kGroup);
-            } else if (mixed) {
-                part(0, P, 4);
-                h->woff_b = (int64_t)part(P, h->L, kGroup);
-            } else {
-                part(0, h->L, quad ? 4 : kGroup);
-            }
+            part(0, P2, 2);
+            h->woff_q = (int64_t)part(P2, P, 4);
+            h->woff_b = (int64_t)part(P, h->L, kGroup);
             const int64_t entries = woff.back() + 64 * kMaxJ;   // loads may run J slots past the end
+            h->slot_entries = woff.back();
             if ((rc = dalloc(&h->woff, woff.size() * 8))) return rc;
             if ((rc = dalloc(&h->idx3, (size_t)entries * (h->idx16 ? 2 : 4)))) return rc;
             if ((rc = dalloc(&h->v3, (size_t)entries * esz))) return rc;
             if ((rc = dalloc(&h->den3, (size_t)entries * esz))) return rc;
             HIP_TRY(hipMemcpyAsync(h->woff, woff.data(), woff.size() * 8, hipMemcpyHostToDevice, s));
-            if (mixed3) {
-                HIP_TRY(launch_relayout_slots<T>(P2, h->ptr2, h->idx2, h->v2, h->den2, h->woff,
-                                                 entries, h->idx3, h->idx16, 2, h->v3, h->den3, s));
-                HIP_TRY(launch_relayout_slots<T>(P - P2, h->ptr2 + P2, h->idx2, h->v2, h->den2,
-                                                 h->woff + h->woff_q, 0, h->idx3, h->idx16, 4,
-                                                 h->v3, h->den3, s));
-                HIP_TRY(launch_relayout_slots<T>(h->L - P, h->ptr2 + P, h->idx2, h->v2, h->den2,
-                                                 h->woff + h->woff_b, 0, h->idx3, h->idx16, kGroup,
-                                                 h->v3, h->den3, s));
-            } else if (mixed) {
-                HIP_TRY(launch_relayout_slots<T>(P, h->ptr2, h->idx2, h->v2, h->den2, h->woff,
-                                                 entries, h->idx3, h->idx16, 4, h->v3, h->den3, s));
-                HIP_TRY(launch_relayout_slots<T>(h->L - P, h->ptr2 + P, h->idx2, h->v2, h->den2,
-                                                 h->woff + h->woff_b, 0, h->idx3, h->idx16, kGroup,
-                                                 h->v3, h->den3, s));
-            } else {
-                HIP_TRY(launch_relayout_slots<T>(h->L, h->ptr2, h->idx2, h->v2, h->den2, h->woff,
-                                                 entries, h->idx3, h->idx16, quad ? 4 : kGroup,
-                                                 h->v3, h->den3, s));
-            }
+            HIP_TRY(launch_relayout_slots<T>(P2, h->ptr2, h->idx2, h->v2, h->den2, h->woff,
+                                             entries, h->idx3, h->idx16, 2, h->v3, h->den3, s));
+            HIP_TRY(launch_relayout_slots<T>(P - P2, h->ptr2 + P2, h->idx2, h->v2, h->den2,
+                                             h->woff + h->woff_q, 0, h->idx3, h->idx16, 4,
+                                             h->v3, h->den3, s));
+            HIP_TRY(launch_relayout_slots<T>(h->L - P, h->ptr2 + P, h->idx2, h->v2, h->den2,
+                                             h->woff + h->woff_b, 0, h->idx3, h->idx16, kGroup,
+                                             h->v3, h->den3, s));
         }
         HIP_TRY(hipStreamSynchronize(s));   // the host vectors die here
     }
-    if (!h->flush_atomic &&
-        (rc = dalloc(&h->part_S, (size_t)h->seg_grid * std::max(h->H, 1) * 8)))
-        return rc;
     if ((rc = dalloc(&h->zpart, (size_t)h->seg_grid * 8))) return rc;
 
     // fixed-point scale of the sales sums from the arrival rates
@@ -832,8 +801,8 @@ int cblp_gap(cblp_t h, const void* eta, spfom_stats* out, void* stream)
     g_err.clear();
     if (!h || !eta || !out) return fail(CBLP_EINVAL, "NULL handle, eta or out");
     hipStream_t s = S(stream);
-    int rc = h->dtype == CBLP_F32 ? evaluate_impl<float>(h, eta, nullptr, s)
-                                  : evaluate_impl<double>(h, eta, nullptr, s);
+    int rc = h->dtype == CBLP_F32 ? evaluate_impl<float>(h, eta, nullptr, nullptr, s)
+                                  : evaluate_impl<double>(h, eta, nullptr, nullptr, s);
     if (rc) return rc;
     rc = fill_stats(h, out, s, h->trace);
     out->seconds = 0.0;
@@ -841,13 +810,13 @@ int cblp_gap(cblp_t h, const void* eta, spfom_stats* out, void* stream)
 }
 
 int cblp_sales(cblp_t h, const void* eta, double* S_out, double* u_out, void* seg_R_out,
-               void* stream)
+               double* s_out, void* stream)
 {
     g_err.clear();
     if (!h || !eta) return fail(CBLP_EINVAL, "NULL handle or eta");
     hipStream_t s = S(stream);
-    int rc = h->dtype == CBLP_F32 ? evaluate_impl<float>(h, eta, seg_R_out, s)
-                                  : evaluate_impl<double>(h, eta, seg_R_out, s);
+    int rc = h->dtype == CBLP_F32 ? evaluate_impl<float>(h, eta, seg_R_out, s_out, s)
+                                  : evaluate_impl<double>(h, eta, seg_R_out, s_out, s);
     if (rc) return rc;
     if (S_out) HIP_TRY(hipMemcpyAsync(S_out, h->S_d, h->n * sizeof(double), hipMemcpyDeviceToDevice, s));
     if (u_out) HIP_TRY(hipMemcpyAsync(u_out, h->u_d, h->m * sizeof(double), hipMemcpyDeviceToDevice, s));
@@ -855,7 +824,8 @@ int cblp_sales(cblp_t h, const void* eta, double* S_out, double* u_out, void* se
     return CBLP_OK;
 }
 
-int cblp_launch_info(cblp_t h, int32_t* seg_grid, int32_t* bins, int32_t* fx_bits)
+int cblp_launch_info(cblp_t h, int32_t* seg_grid, int32_t* bins, int32_t* fx_bits,
+                     int32_t* kernel, int64_t* slot_entries)
 {
     g_err.clear();
     if (!h) return fail(CBLP_EINVAL, "handle is NULL");
@@ -866,6 +836,8 @@ int cblp_launch_info(cblp_t h, int32_t* seg_grid, int32_t* bins, int32_t* fx_bit
         std::frexp(h->fx_scale, &e);
         *fx_bits = e - 1;
     }
+    if (kernel) *kernel = h->seg_variant;
+    if (slot_entries) *slot_entries = h->slot_entries;
     return CBLP_OK;
 }
 

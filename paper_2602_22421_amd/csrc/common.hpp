@@ -20,8 +20,9 @@ constexpr int kSegThreads = 1024;
 constexpr int kSegsPerTile = kSegThreads / kGroup;
 
 // Dual-phase kernels.
-constexpr int kFoldProducts = 64;          // products per fold block
-constexpr int kFoldChunks = 16;            // partial rows split 16 ways
+constexpr int kFoldLite = 256;             // products per fold block
+constexpr int kFoldProducts = 64;          // products per batched fold block
+constexpr int kFoldChunks = 16;            // batched fold: partial rows split 16 ways
 constexpr int kFoldThreads = kFoldProducts * kFoldChunks;
 constexpr int kRowThreads = 256;
 
@@ -51,13 +52,20 @@ struct SegArgs {
     int64_t n;                     // products (length of rho)
     int H;                         // products [0, H) are summed in LDS bins
     int hp;                        // split-price kernel: prices [0, hp) held in LDS
-    unsigned long long* part_S;    // [gridDim.x][H] per-block bin totals
     unsigned long long* S_fx;      // [n] fixed-point sales of products >= H
     double fx_scale;               // 2^bits; one segment's sale * 2^bits < 2^31 for FP32
     double* zpart;                 // [gridDim.x] FP64 partials of sum lambda R*
     void* seg_R;                   // [L] nullable, original segment order
-    const int64_t* blk;            // [grid][3] (slots J, first tile, end tile) of each
-                                   // block for the size-class kernels, else unused
+    void* seg_thr;                 // [L] nullable, by position: the threshold R of S* =
+                                   // {rho v > R den} (evaluation, per-entry sales)
+    void* seg_lamD;                // [L] with seg_thr: (lambda / D) 2^bits of the position
+    // per-segment certified bound: revenue of each position's best response
+    // added to psum[p] (overwritten instead when psum_reset), in the kernels
+    // instantiated for it; rlib [n] holds the revenues by library product id
+    double* psum;
+    const void* rlib;
+    double inv_fx;                 // 2^-bits
+    int psum_reset;
     // slot-major copy (slot-major kernels): wave-tile w (positions 8w..8w+7)
     // holds (woff[w+1] - woff[w]) / 64 slots of 64 entries from woff[w]
     const int64_t* woff;           // [ceil(L/8) + 2], the last entry repeats the total
@@ -74,9 +82,6 @@ struct PhaseArgs {
     const void* tau_vec;           // [m] nullable
     const double* zpart;
     int nz;
-    const unsigned long long* part_S;
-    int nseg;
-    int H;
     unsigned long long* S_fx;
     double inv_fx;
     const void* r;
@@ -100,6 +105,16 @@ struct PhaseArgs {
     DevState* st;                  // [2]: read st[par], write st[par ^ 1]
     int par;
     double* row;                   // trace row of this iteration
+    // per-segment bound (check iterations only; pseg_part NULL otherwise):
+    // theta_prod [n] by library id, the position-ordered copy (L, ptr2,
+    // idx2 with library ids) and psum [L]; one partial per k_pseg block
+    double* theta_prod;
+    int64_t L;
+    const int64_t* ptr2;
+    const int32_t* idx2;
+    const double* psum;
+    double* pseg_part;
+    int pseg_blocks;
 };
 
 // Launchers (one per kernel family), defined next to their kernels.
@@ -131,78 +146,59 @@ template <typename T>
 hipError_t launch_prices(int64_t n, const void* r, const void* eta, const int64_t* a_ptr,
                          const int32_t* a_idx, const void* a_val, const int32_t* pnew, void* rho,
                          hipStream_t s);
-// Segment-kernel variants 0-9 gather prices from global memory; variants
-// kSegLdsPrices and up first copy the n prices into LDS after the H bins.
-// Variants kSegClassLds (prices in LDS) and kSegClassGlobal take the slot
-// count of each block from a table: blocks own runs of tiles of one size class.
-// Variant kSegSplit holds the prices of products [0, hp) in LDS.  Variants
-// kSegSlots and up read the slot-major copy (see SegArgs::woff); of these,
-// kSegSlotsSplit and kSegSlotsSplit + 1 hold the prices as kSegSplit does.
-constexpr int kSegVariants = 41;
-constexpr int kSegSlots = 20;
-constexpr int kSegSlotsSplit = 26;
-constexpr int kSegSlotsJ4 = 28;        // 4 register slots, prices in LDS
-// as kSegSlots + 1, kSegSlotsJ4 and kSegSlots + 3 with 16-bit product ids in
-// the slot-major copy (n <= 65536): 10 bytes per FP32 entry instead of 12,
-// 18 per FP64 entry instead of 20
-constexpr int kSegSlots16 = 29;
-// quad layout (4-lane groups, 16 rows per wave; rows of at most 32 entries
-// in registers): 32 16-bit ids and LDS prices, 33 32-bit ids and split
-// prices, 34 32-bit ids and LDS prices
-constexpr int kSegQuad = 32;
-inline bool seg_quad(int variant) { return variant >= kSegQuad && variant <= kSegQuad + 2; }
-// mixed: rows of at most 32 entries in the quad layout, longer rows in the
-// 8-lane one, prices in LDS (35: 16-bit ids, 36: 32-bit ids)
-constexpr int kSegMixed = 35;
-constexpr int kQuadMaxRow = 32;        // rows held in registers by the quad kernels
-inline bool seg_mixed(int variant) { return variant == kSegMixed || variant == kSegMixed + 1; }
-// three-part mixed: rows of at most 16 entries in the pair layout (2-lane
-// groups), then quad, then 8-lane (37: 16-bit ids, 38: 32-bit ids; 39, 40:
-// the same with split prices, 32- and 16-bit ids)
-constexpr int kSegMixed3 = 37;
-constexpr int kPairMaxRow = 16;
-inline bool seg_mixed3(int variant) { return variant >= kSegMixed3 && variant <= kSegMixed3 + 3; }
-inline bool seg_idx16(int variant)
-{
-    return (variant >= kSegSlots16 && variant <= kSegSlots16 + 2) || variant == kSegQuad ||
-           variant == kSegMixed || variant == kSegMixed3 || variant == kSegMixed3 + 3;
-}
-inline bool seg_slot_major(int variant) { return variant >= kSegSlots; }
-constexpr int kSegLdsPrices = 10;
-constexpr int kSegClassLds = 17, kSegClassGlobal = 18, kSegSplit = 19;
-constexpr int kSplitPrices = 8192;     // head prices of the split kernel
+// Segment kernels (segment.hip).  Every one reads the slot-major copy (see
+// SegArgs::woff) and gives the same bits as the others.
+//   kSegMixed3         FP32, three parts (2-, 4- and 8-lane groups), all n
+//                      prices in LDS, 16-bit product ids (n <= 65536)
+//   kSegMixed3Split16  the same with only the prices of products [0, hp) in
+//                      LDS, the rest read from global memory
+//   kSegMixed3Split32  the same with 32-bit product ids
+//   kSegSlots16        FP64, 8-lane groups, 4 register slots, prices from
+//                      global memory, 16-bit ids
+//   kSegSlots32        the same with 32-bit ids
+enum {
+    kSegMixed3 = 0,
+    kSegMixed3Split16 = 1,
+    kSegMixed3Split32 = 2,
+    kSegSlots16 = 3,
+    kSegSlots32 = 4,
+    kSegVariants = 5
+};
+constexpr int kQuadMaxRow = 32;        // rows held in registers by the 4-lane groups
+constexpr int kPairMaxRow = 16;        // rows held in registers by the 2-lane groups
+constexpr int kSplitPrices = 8192;     // head prices held in LDS by the split kernels
+inline bool seg_mixed3(int variant) { return variant <= kSegMixed3Split32; }
 inline bool seg_split(int variant)
 {
-    return variant == kSegSplit || variant == kSegSlotsSplit || variant == kSegSlotsSplit + 1 ||
-           variant == kSegQuad + 1 || variant == kSegMixed3 + 2 || variant == kSegMixed3 + 3;
+    return variant == kSegMixed3Split16 || variant == kSegMixed3Split32;
 }
-inline bool seg_class(int variant) { return variant == kSegClassLds || variant == kSegClassGlobal; }
-// most register slots of the size-class kernels per element size
-inline int seg_class_max_slots(size_t esz) { return esz == 4 ? 7 : 4; }
-inline bool seg_lds_prices(int variant)
+inline bool seg_idx16(int variant) { return variant != kSegMixed3Split32 && variant != kSegSlots32; }
+inline bool seg_lds_prices(int variant) { return seg_mixed3(variant); }
+// dynamic LDS bytes of a segment block: H bins, then the prices held in LDS
+// (n of them, or hp for the split kernels)
+inline size_t seg_lds_bytes(int H, int64_t n, int hp, size_t esz, int variant)
 {
-    return variant >= kSegLdsPrices && variant != kSegClassGlobal && variant != kSegSlots + 3 &&
-           variant != kSegSlots + 5 && variant != kSegSlots16 + 2;
+    const size_t np = seg_split(variant) ? (size_t)hp : seg_lds_prices(variant) ? (size_t)n : 0;
+    return (size_t)H * 8 + np * esz;
 }
-// dynamic LDS bytes of a segment block: H bins, then the prices if in LDS
-inline size_t seg_lds_bytes(int H, int64_t n, size_t esz, int variant)
-{
-    return (size_t)H * 8 + (seg_lds_prices(variant) ? (size_t)n * esz : 0);
-}
+// a2, a4, a8: views of the pair, quad and 8-lane parts of the slot-major
+// copy (the FP64 kernels take a8 only, viewing the whole instance)
+// pseg: the kernels that also add each segment's revenue to a2.psum etc.
 template <typename T>
-hipError_t launch_segments(const SegArgs& a, int grid, int variant, hipStream_t s);
-// mixed variants: a = the quad part (positions [0, P)), b = the rest
+hipError_t launch_segments(const SegArgs& a2, const SegArgs& a4, const SegArgs& a8, int grid,
+                           int variant, bool pseg, hipStream_t s);
+// s_out [nnz] (caller's CSR order) from the thresholds and (lambda / D) 2^bits
+// that a segment pass stored by position (thr, lamD)
 template <typename T>
-hipError_t launch_segments_mixed(const SegArgs& a, const SegArgs& b, int grid, int variant,
-                                 hipStream_t s);
-// three-part mixed variants: pair, quad and 8-lane parts
+hipError_t launch_entry_sales(int64_t L, const int32_t* perm, const int64_t* seg_ptr,
+                              const int32_t* idx, const void* v, const void* w,
+                              const int32_t* pnew, const void* rho, const void* thr,
+                              const void* lamD, double inv_fx, double* s_out, hipStream_t s);
 template <typename T>
-hipError_t launch_segments_mixed3(const SegArgs& a2, const SegArgs& a4, const SegArgs& a8, int grid,
-                                  int variant, hipStream_t s);
-template <typename T>
-int segment_blocks_per_cu(int H, int64_t n, int variant);   // resident blocks per CU
+int segment_blocks_per_cu(int H, int64_t n, int hp, int variant);   // resident blocks per CU
 template <typename T>
 hipError_t launch_phase(const PhaseArgs& a, bool identity, hipStream_t s);
+constexpr int kPsegBlocks = 256;   // blocks of the per-segment bound pass
 
 // Record a failure for cblp_last_error() on this thread; returns code.
 int set_error(int code, const std::string& msg);

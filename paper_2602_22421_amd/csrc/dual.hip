@@ -1,11 +1,9 @@
 // Dual phase of one iteration: sales totals, FP64 reductions, certified
 // bound and the projected dual step (eq. 16).
 //
-//   k_fold    per product: S_j = (global 64-bit accumulator, which the
+//   k_fold_lite  per product: S_j = (global 64-bit accumulator, which the
 //             segment blocks fed by integer atomics) / 2^bits and
 //             P = sum r_j S_j; with A = I also the per-row work below
-//             (k_fold_lite); the partial-row build instead sums the
-//             per-block LDS bin rows in block order (k_fold)
 //   k_rows    (general A) per resource: u_i = sum_j a_ij S_j through A^T
 //   per row   g_i = u_i - c_i; c.eta, sum (g)^+, the Polyak norm
 //             sum tau_i g_i^2 (g zeroed where the projection binds), ||eta||^2
@@ -32,9 +30,8 @@ namespace {
 
 using namespace dual;
 
-// Fold when the segment blocks added their bins to S_fx themselves (no
-// partial rows): one product per thread, 256 threads per block.
-constexpr int kFoldLite = 256;
+// Fold: one product per thread, kFoldLite threads per block (the segment
+// blocks added their bins to S_fx themselves).
 
 template <typename T, bool IDENT>
 __global__ void __launch_bounds__(kFoldLite) k_fold_lite(PhaseArgs a)
@@ -113,6 +110,7 @@ __global__ void __launch_bounds__(kFoldLite) k_fold_step(PhaseArgs a)
         x[R_G] += p[R_G];
         x[R_TH] = fmin(x[R_TH], p[R_TH]);
         x[R_E2] += p[R_E2];
+        x[R_CS] += p[R_CS];
     }
     block_reduce(x, sh);
     if (tid != 0) return;
@@ -140,7 +138,7 @@ __global__ void __launch_bounds__(kFoldLite) k_fold_step(PhaseArgs a)
     row[SPFOM_TR_PRIMAL] = x[R_P];
     row[SPFOM_TR_Z] = x[R_Z];
     row[SPFOM_TR_ETA2] = x[R_E2];
-    row[SPFOM_TR_INFEAS] = x[R_INF];
+    row[SPFOM_TR_INFEAS] = rel_infeas(x);
     row[SPFOM_TR_DBEST] = st.dbest;
     row[SPFOM_TR_LB] = st.lb;
     row[SPFOM_TR_GAP] = (st.dbest - st.lb) / fmax(fabs(st.dbest), DBL_MIN);
@@ -148,52 +146,6 @@ __global__ void __launch_bounds__(kFoldLite) k_fold_step(PhaseArgs a)
     row[SPFOM_TR_THETA] = th;
     a.st[a.par ^ 1] = st;
     *a.arrive = 0u;   // ready for the next launch
-}
-
-template <typename T, bool IDENT>
-__global__ void __launch_bounds__(kFoldThreads) k_fold(PhaseArgs a)
-{
-    __shared__ unsigned long long red[kFoldChunks][kFoldProducts];
-    __shared__ double sh[NR * 16];
-    const int tid = threadIdx.x;
-    const int jj = tid % kFoldProducts, cc = tid / kFoldProducts;
-    const int64_t j = (int64_t)blockIdx.x * kFoldProducts + jj;
-    const int64_t jq = j < a.n && a.pnew ? a.pnew[j] : j;   // library id of product j
-    // integer sums: eight independent accumulators keep eight loads in flight
-    unsigned long long a0 = 0ull, a1 = 0ull, a2 = 0ull, a3 = 0ull;
-    unsigned long long a4 = 0ull, a5 = 0ull, a6 = 0ull, a7 = 0ull;
-    if (j < a.n && jq < a.H) {
-        const unsigned long long* P = a.part_S + jq;
-        const size_t H = (size_t)a.H;
-        int b = cc;
-        for (; b + 7 * kFoldChunks < a.nseg; b += 8 * kFoldChunks) {
-            a0 += P[(size_t)b * H];
-            a1 += P[(size_t)(b + kFoldChunks) * H];
-            a2 += P[(size_t)(b + 2 * kFoldChunks) * H];
-            a3 += P[(size_t)(b + 3 * kFoldChunks) * H];
-            a4 += P[(size_t)(b + 4 * kFoldChunks) * H];
-            a5 += P[(size_t)(b + 5 * kFoldChunks) * H];
-            a6 += P[(size_t)(b + 6 * kFoldChunks) * H];
-            a7 += P[(size_t)(b + 7 * kFoldChunks) * H];
-        }
-        for (; b < a.nseg; b += kFoldChunks) a0 += P[(size_t)b * H];
-    }
-    red[cc][jj] = ((a0 + a1) + (a2 + a3)) + ((a4 + a5) + (a6 + a7));
-    const long long cnt1 = a.mode == 0 ? a.st[a.par].cnt + 1 : 1;
-    __syncthreads();
-    double x[NR];
-    clear(x);
-    if (cc == 0 && j < a.n) {
-        unsigned long long tot = a.S_fx[jq];
-        a.S_fx[jq] = 0ull;
-        for (int q = 0; q < kFoldChunks; ++q) tot += red[q][jj];
-        const double sj = (double)(long long)tot * a.inv_fx;
-        a.S_d[j] = sj;
-        x[R_P] = (double)((const T*)a.r)[j] * sj;
-        if (IDENT) row_work<T>(a, j, sj, cnt1, x);
-    }
-    block_reduce(x, sh);
-    if (tid == 0) store_part(a.bpart + (size_t)blockIdx.x * 8, x);
 }
 
 // u_i = sum_j a_ij S_j, one wave per resource row: lanes stride over the row's
@@ -223,6 +175,49 @@ __global__ void __launch_bounds__(kRowThreads) k_rows(PhaseArgs a)
     if (threadIdx.x == 0) store_part(a.bpart2 + (size_t)blockIdx.x * 8, x);
 }
 
+// Per-segment bound, step 1: theta of each product j (library id), the
+// smallest c_i / ubar_i (at most 1) over the resources j uses; ubar is the
+// window average including this iteration (row work has added u to sum_u).
+template <typename T>
+__global__ void __launch_bounds__(256) k_theta(PhaseArgs a)
+{
+    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (j >= a.n) return;
+    const double cnt1 = (double)(a.st[a.par].cnt + 1);
+    const T* c = (const T*)a.c;
+    auto theta_i = [&](int64_t i) {
+        const double ub = a.sum_u[i] / cnt1, ci = (double)c[i];
+        return ub > ci ? ci / ub : 1.0;
+    };
+    double th = 1.0;
+    if (!a.a_ptr) {
+        th = theta_i(j);
+    } else {
+        for (int64_t q = a.a_ptr[j]; q < a.a_ptr[j + 1]; ++q) th = fmin(th, theta_i(a.a_idx[q]));
+    }
+    a.theta_prod[a.pnew ? a.pnew[j] : j] = th;
+}
+
+// Per-segment bound, step 2: sum over positions of theta_l pbar_l with
+// theta_l the smallest theta of the products in N_l (1 for an empty set)
+// and pbar_l = psum / (window length); one partial per block, fixed order.
+__global__ void __launch_bounds__(256) k_pseg(PhaseArgs a)
+{
+    __shared__ double sh[4];
+    const double cnt1 = (double)(a.st[a.par].cnt + 1);
+    double acc = 0.0;
+    for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < a.L;
+         p += (int64_t)gridDim.x * 256) {
+        double tl = 1.0;
+        for (int64_t q = a.ptr2[p]; q < a.ptr2[p + 1]; ++q) tl = fmin(tl, a.theta_prod[a.idx2[q]]);
+        acc += tl * (a.psum[p] / cnt1);
+    }
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_down(acc, o, 64);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) a.pseg_part[blockIdx.x] = ((sh[0] + sh[1]) + sh[2]) + sh[3];
+}
+
 template <typename T, bool IDENT>
 __global__ void __launch_bounds__(kRowThreads) k_update(PhaseArgs a)
 {
@@ -242,6 +237,7 @@ __global__ void __launch_bounds__(kRowThreads) k_update(PhaseArgs a)
         x[R_G] += p[R_G];
         x[R_TH] = fmin(x[R_TH], p[R_TH]);
         x[R_E2] += p[R_E2];
+        x[R_CS] += p[R_CS];
     }
     block_reduce(x, sh);
     const double D = x[R_CETA] + x[R_Z];
@@ -259,6 +255,11 @@ __global__ void __launch_bounds__(kRowThreads) k_update(PhaseArgs a)
         if (t1 % a.check_every == 0) {
             const double cand = th * (st.sum_p / (double)cnt1);
             if (cand > st.lb) st.lb = cand;
+            if (a.pseg_part) {   // the per-segment bound, its partials in block order
+                double ps = 0.0;
+                for (int q = 0; q < a.pseg_blocks; ++q) ps += a.pseg_part[q];
+                if (ps > st.lb) st.lb = ps;
+            }
         } else {
             th = 1.0;
         }
@@ -282,7 +283,7 @@ __global__ void __launch_bounds__(kRowThreads) k_update(PhaseArgs a)
         row[SPFOM_TR_PRIMAL] = x[R_P];
         row[SPFOM_TR_Z] = x[R_Z];
         row[SPFOM_TR_ETA2] = x[R_E2];
-        row[SPFOM_TR_INFEAS] = x[R_INF];
+        row[SPFOM_TR_INFEAS] = rel_infeas(x);
         if (iter) {
             row[SPFOM_TR_DBEST] = st.dbest;
             row[SPFOM_TR_LB] = st.lb;
@@ -329,22 +330,24 @@ hipError_t launch_phase(const PhaseArgs& a, bool identity, hipStream_t s)
 {
     const unsigned fold_grid = (unsigned)a.fold_blocks;
     const unsigned row_grid = (unsigned)((a.m + kRowThreads - 1) / kRowThreads);
-    const bool lite = a.nseg == 0;   // bins already in S_fx: fold_blocks counts kFoldLite products
-    if (identity && lite && a.mode == 0 && a.rule != SPFOM_STEP_POLYAK && a.arrive) {
+    // per-segment bound at a check: theta per product, then per segment,
+    // between the row work and the update (the two-kernel path)
+    auto pseg = [&]() {
+        if (!a.pseg_part) return;
+        hipLaunchKernelGGL(k_theta<T>, dim3((unsigned)((a.n + 255) / 256)), dim3(256), 0, s, a);
+        hipLaunchKernelGGL(k_pseg, dim3((unsigned)a.pseg_blocks), dim3(256), 0, s, a);
+    };
+    if (identity && a.mode == 0 && a.rule != SPFOM_STEP_POLYAK && a.arrive && !a.pseg_part) {
         hipLaunchKernelGGL((k_fold_step<T>), dim3(fold_grid), dim3(kFoldLite), 0, s, a);
     } else if (identity) {
-        if (lite)
-            hipLaunchKernelGGL((k_fold_lite<T, true>), dim3(fold_grid), dim3(kFoldLite), 0, s, a);
-        else
-            hipLaunchKernelGGL((k_fold<T, true>), dim3(fold_grid), dim3(kFoldThreads), 0, s, a);
+        hipLaunchKernelGGL((k_fold_lite<T, true>), dim3(fold_grid), dim3(kFoldLite), 0, s, a);
+        pseg();
         hipLaunchKernelGGL((k_update<T, true>), dim3(row_grid), dim3(kRowThreads), 0, s, a);
     } else {
-        if (lite)
-            hipLaunchKernelGGL((k_fold_lite<T, false>), dim3(fold_grid), dim3(kFoldLite), 0, s, a);
-        else
-            hipLaunchKernelGGL((k_fold<T, false>), dim3(fold_grid), dim3(kFoldThreads), 0, s, a);
+        hipLaunchKernelGGL((k_fold_lite<T, false>), dim3(fold_grid), dim3(kFoldLite), 0, s, a);
         hipLaunchKernelGGL(k_rows_sum, dim3((unsigned)((a.m + 3) / 4)), dim3(256), 0, s, a);
         hipLaunchKernelGGL(k_rows<T>, dim3(row_grid), dim3(kRowThreads), 0, s, a);
+        pseg();
         hipLaunchKernelGGL((k_update<T, false>), dim3(row_grid), dim3(kRowThreads), 0, s, a);
         if (a.mode == 0) {
             const unsigned pg = (unsigned)((a.n + 255) / 256);

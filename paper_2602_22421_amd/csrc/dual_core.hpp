@@ -9,8 +9,14 @@
 namespace cblp {
 namespace dual {
 
-constexpr int NR = 7;   // P, c.eta, infeasibility, Polyak norm, theta, ||eta||^2, Z
-enum { R_P = 0, R_CETA, R_INF, R_G, R_TH, R_E2, R_Z };
+constexpr int NR = 8;   // P, c.eta, infeasibility, Polyak norm, theta, ||eta||^2, Z, sum c
+enum { R_P = 0, R_CETA, R_INF, R_G, R_TH, R_E2, R_Z, R_CS };
+
+// relative infeasibility sum (u - c)^+ / sum c (the plain sum when sum c = 0)
+__device__ __forceinline__ double rel_infeas(const double (&x)[NR])
+{
+    return x[R_CS] > 0.0 ? x[R_INF] / x[R_CS] : x[R_INF];
+}
 
 // Deterministic block reduction of NR values (R_TH is a minimum, the rest
 // sums): a shuffle tree inside each wave, then every thread folds the wave
@@ -56,6 +62,7 @@ __device__ __forceinline__ void row_work(const Args& a, int64_t i, double u, lon
     const double ci = (double)c[i], ei = (double)eta[i];
     const double g = u - ci;
     x[R_CETA] += ci * ei;
+    x[R_CS] += ci;
     x[R_E2] += ei * ei;
     if (g > 0.0) x[R_INF] += g;
     const double ti = tauv ? (double)tauv[i] : a.tau_s;

@@ -36,21 +36,20 @@ struct cblp_instance {
     void* Rwarm = nullptr;
     void* v0c = nullptr;            // v0 per position (features only)
     int32_t* perm = nullptr;
-    int64_t* seg_blk = nullptr;     // [seg_grid][3] size-class block table (class variants)
-    int64_t* woff = nullptr;        // slot-major copy (slot-major variants): wave-tile offsets
+    int64_t* woff = nullptr;        // slot-major copy: wave-tile offsets
     void* idx3 = nullptr;           // int32, or uint16 when idx16
     int64_t pair_end = 0;           // three-part mixed: positions [0, pair_end) in the pair layout
-    int64_t quad_end = 0;           // mixed: positions [pair_end, quad_end) in the quad layout
+    int64_t quad_end = 0;           // three-part mixed: positions [pair_end, quad_end) in the quad layout
     int64_t woff_q = 0;             // three-part mixed: index in woff of the quad part's offsets
-    int64_t woff_b = 0;             // mixed: index in woff of the 8-lane part's offsets
+    int64_t woff_b = 0;             // three-part mixed: index in woff of the 8-lane part's offsets
     bool idx16 = false;
+    int64_t slot_entries = 0;       // places of the slot-major copy (rows padded to their wave-tile)
     void* v3 = nullptr;
     void* den3 = nullptr;
     // owned workspace
     void* rho = nullptr;
     unsigned long long* S_fx = nullptr;
     int32_t* pnew = nullptr;        // [n] library id of caller product j (null: ids kept)
-    unsigned long long* part_S = nullptr;
     double* S_d = nullptr;
     double* u_d = nullptr;
     double* sum_u = nullptr;
@@ -65,12 +64,23 @@ struct cblp_instance {
     int32_t* at_prod = nullptr;
     double* at_val = nullptr;
     double* pinned = nullptr;
+    // per-segment bound (allocated on first use): revenues by library id,
+    // running revenue sums by position, theta by library id, k_pseg partials
+    void* rlib = nullptr;
+    double* psum = nullptr;
+    double* theta_prod = nullptr;
+    double* pseg_part = nullptr;
+    int64_t t0h = 0;                // start of the current averaging window (host copy)
+    bool psum_reset_next = true;    // the next accumulating pass starts a new window
+    bool pseg_window_ok = true;     // every pass of the current window accumulated psum
+    // per-entry sales (allocated on first use): threshold and (lambda / D) 2^bits
+    // by position
+    void* eval_thr = nullptr;
+    void* eval_lamD = nullptr;
     int seg_grid = 1;
     int seg_variant = 0;
     int H = 0;
     int hp = 0;                     // split-price kernel: prices held in LDS
-    bool flush_atomic = true;       // segment blocks add their bins to S_fx by atomics
-                                    // (false: per-block partial rows folded by k_fold)
     int fold_blocks = 1;
     double fx_scale = 1.0;
     int64_t t = 0;

@@ -932,4 +932,40 @@ int wsnet_predict(wsnet_t w, cblp_t h, void* eta, void* stream)
     return CBLP_OK;
 }
 
+int wsnet_start(wsnet_t w, cblp_t h, void* eta, int32_t* used, double* d_pred, double* d_zero,
+                void* stream)
+{
+    int rc = wsnet_predict(w, h, eta, stream);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    spfom_stats st;
+    if ((rc = cblp_gap(h, eta, &st, stream))) return rc;
+    const double dp = st.trace[SPFOM_TR_DUAL];
+    void* zeros = nullptr;
+    const size_t bytes = (size_t)h->m * h->esz;
+    if (hipMalloc(&zeros, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return mfail(CBLP_ENOMEM, "no memory for the cold-start duals");
+    }
+    if (hipMemsetAsync(zeros, 0, bytes, s) != hipSuccess) {
+        (void)hipFree(zeros);
+        return mfail(CBLP_EHIP, "clearing the cold-start duals failed");
+    }
+    rc = cblp_gap(h, zeros, &st, stream);
+    (void)hipFree(zeros);
+    if (rc) return rc;
+    const double d0 = st.trace[SPFOM_TR_DUAL];
+    // both are upper bounds on the LP optimum: keep the prediction only if its
+    // bound is the tighter one
+    const bool keep = dp < d0;
+    if (!keep) {
+        MHIP(hipMemsetAsync(eta, 0, bytes, s));
+        MHIP(hipStreamSynchronize(s));
+    }
+    if (used) *used = keep ? 1 : 0;
+    if (d_pred) *d_pred = dp;
+    if (d_zero) *d_zero = d0;
+    return CBLP_OK;
+}
+
 }  // extern "C"

@@ -1,6 +1,12 @@
-// Single-instance segment kernel: the per-segment primal step over every
-// segment and the per-block LDS-bin rows of product sales (device code in
-// segment_core.hpp).
+// Single-instance segment kernels: the per-segment primal step over every
+// segment of the library's slot-major copy and the sales scatter (device
+// code in segment_core.hpp).  Two kernels ship:
+//   k_segments_mixed3  FP32: rows of at most 16 entries solved by 2-lane
+//                      groups, of at most 32 by 4-lane groups, longer ones
+//                      by 8-lane groups; the prices in LDS, or only the
+//                      popular head of them when all do not fit (SPLIT)
+//   k_segments_slots   FP64: 8-lane groups, 4 register slots per lane, the
+//                      prices gathered from global memory
 #include "segment_core.hpp"
 
 #include <type_traits>
@@ -8,89 +14,17 @@
 namespace cblp {
 namespace {
 
-// The block's bins go out as one partial row (folded in block order by the
-// dual phase) or, when a.part_S is null, straight into the global 64-bit
-// accumulators by atomics (integer sums: the order does not matter).
+// The block's nonzero bins go straight into the global 64-bit accumulators
+// by atomics (integer sums: the order of the blocks does not matter).
 __device__ __forceinline__ void flush_bins(const SegArgs& a, const unsigned long long* bins)
 {
-    if (a.part_S) {
-        unsigned long long* out = a.part_S + (size_t)blockIdx.x * (size_t)a.H;
-        for (int j = threadIdx.x; j < a.H; j += kSegThreads) out[j] = bins[j];
-    } else {
-        for (int j = threadIdx.x; j < a.H; j += kSegThreads)
-            if (bins[j]) atomicAdd(&a.S_fx[j], bins[j]);
-    }
-}
-
-// LDSP: copy the n prices into LDS behind the bins and gather from there
-// (random 4-byte reads that would otherwise each take a cache-line lookup in
-// the vector memory path, which the CSR stream already keeps busy).
-template <typename T, int J, int DEPTH, bool LDSP>
-__global__ void __launch_bounds__(kSegThreads) k_segments(SegArgs a)
-{
-    extern __shared__ unsigned long long bins[];   // [a.H], then [a.n] prices if LDSP
-    __shared__ double zsh[kSegThreads / 64];
-    const int H = a.H;
-    T* lprice = (T*)(bins + H);
-    for (int j = threadIdx.x; j < H; j += kSegThreads) bins[j] = 0ull;
-    if (LDSP)
-        for (int64_t j = threadIdx.x; j < a.n; j += kSegThreads) lprice[j] = ((const T*)a.rho)[j];
-    __syncthreads();
-
-    double zacc = 0.0;
-    const int64_t tiles = (a.L + kSegsPerTile - 1) / kSegsPerTile;
-    // the grid never exceeds the tile count, except for L = 0 (one block)
-    const seg::FlatPrices<T> pr{LDSP ? (const T*)lprice : (const T*)a.rho};
-    seg::process_tiles<T, J, DEPTH>(a, blockIdx.x, tiles, gridDim.x, bins, pr, zacc);
-
-    __syncthreads();
-    flush_bins(a, bins);
-
-    // block partial of sum lambda R*: fixed shuffle tree, waves in order
-    for (int o = 32; o > 0; o >>= 1) zacc += __shfl_down(zacc, o, 64);
-    if ((threadIdx.x & 63) == 0) zsh[threadIdx.x >> 6] = zacc;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double z = zsh[0];
-        for (int q = 1; q < kSegThreads / 64; ++q) z += zsh[q];
-        a.zpart[blockIdx.x] = z;
-    }
-}
-
-// Split-price kernel: the prices of the popular head [0, a.hp) are copied
-// into LDS behind the bins, the rest are gathered from global memory; the
-// smaller copy leaves room for more bins, so fewer sales take global atomics.
-template <typename T, int J>
-__global__ void __launch_bounds__(kSegThreads) k_segments_split(SegArgs a)
-{
-    extern __shared__ unsigned long long bins[];   // [a.H], then [a.hp] prices
-    __shared__ double zsh[kSegThreads / 64];
-    const int H = a.H;
-    T* lprice = (T*)(bins + H);
-    for (int j = threadIdx.x; j < H; j += kSegThreads) bins[j] = 0ull;
-    for (int j = threadIdx.x; j < a.hp; j += kSegThreads) lprice[j] = ((const T*)a.rho)[j];
-    __syncthreads();
-
-    double zacc = 0.0;
-    const int64_t tiles = (a.L + kSegsPerTile - 1) / kSegsPerTile;
-    const seg::SplitPrices<T> pr{(const T*)lprice, (const T*)a.rho, a.hp};
-    seg::process_tiles<T, J, 3>(a, blockIdx.x, tiles, gridDim.x, bins, pr, zacc);
-
-    __syncthreads();
-    flush_bins(a, bins);
-    for (int o = 32; o > 0; o >>= 1) zacc += __shfl_down(zacc, o, 64);
-    if ((threadIdx.x & 63) == 0) zsh[threadIdx.x >> 6] = zacc;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double z = zsh[0];
-        for (int q = 1; q < kSegThreads / 64; ++q) z += zsh[q];
-        a.zpart[blockIdx.x] = z;
-    }
+    for (int j = threadIdx.x; j < a.H; j += kSegThreads)
+        if (bins[j]) atomicAdd(&a.S_fx[j], bins[j]);
 }
 
 // Slot-major kernel: the per-segment step over the slot-major copy (one
 // contiguous 256-byte read per slot and array for a whole wave).
-template <typename T, int J, bool ALL, bool LDSP, bool TOUCH = false, typename IdxT = int32_t>
+template <typename T, int J, bool ALL, bool LDSP, typename IdxT = int32_t, bool PSEG = false>
 __global__ void __launch_bounds__(kSegThreads) k_segments_slots(SegArgs a)
 {
     extern __shared__ unsigned long long bins[];   // [a.H], then [a.n] prices if LDSP
@@ -105,114 +39,8 @@ __global__ void __launch_bounds__(kSegThreads) k_segments_slots(SegArgs a)
     double zacc = 0.0;
     const int64_t tiles = (a.L + kSegsPerTile - 1) / kSegsPerTile;
     const seg::FlatPrices<T> pr{LDSP ? (const T*)lprice : (const T*)a.rho};
-    seg::process_tiles_slots<T, J, ALL, seg::FlatPrices<T>, TOUCH, IdxT>(a, blockIdx.x, tiles,
-                                                                       gridDim.x, bins, pr, zacc);
-
-    __syncthreads();
-    flush_bins(a, bins);
-    for (int o = 32; o > 0; o >>= 1) zacc += __shfl_down(zacc, o, 64);
-    if ((threadIdx.x & 63) == 0) zsh[threadIdx.x >> 6] = zacc;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double z = zsh[0];
-        for (int q = 1; q < kSegThreads / 64; ++q) z += zsh[q];
-        a.zpart[blockIdx.x] = z;
-    }
-}
-
-// Slot-major kernel with split prices (head [0, a.hp) in LDS, the rest from
-// global memory), for instances whose prices do not fit in LDS.
-template <typename T, int J>
-__global__ void __launch_bounds__(kSegThreads) k_segments_slots_split(SegArgs a)
-{
-    extern __shared__ unsigned long long bins[];   // [a.H], then [a.hp] prices
-    __shared__ double zsh[kSegThreads / 64];
-    const int H = a.H;
-    T* lprice = (T*)(bins + H);
-    for (int j = threadIdx.x; j < H; j += kSegThreads) bins[j] = 0ull;
-    for (int j = threadIdx.x; j < a.hp; j += kSegThreads) lprice[j] = ((const T*)a.rho)[j];
-    __syncthreads();
-
-    double zacc = 0.0;
-    const int64_t tiles = (a.L + kSegsPerTile - 1) / kSegsPerTile;
-    const seg::SplitPrices<T> pr{(const T*)lprice, (const T*)a.rho, a.hp};
-    seg::process_tiles_slots<T, J, false, seg::SplitPrices<T>>(a, blockIdx.x, tiles, gridDim.x,
-                                                              bins, pr, zacc);
-
-    __syncthreads();
-    flush_bins(a, bins);
-    for (int o = 32; o > 0; o >>= 1) zacc += __shfl_down(zacc, o, 64);
-    if ((threadIdx.x & 63) == 0) zsh[threadIdx.x >> 6] = zacc;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double z = zsh[0];
-        for (int q = 1; q < kSegThreads / 64; ++q) z += zsh[q];
-        a.zpart[blockIdx.x] = z;
-    }
-}
-
-// Quad-layout kernel (4-lane groups, 16 rows per wave) over the slot-major
-// copy in quad layout; prices all in LDS, or split (head [0, a.hp) in LDS).
-template <typename T, int J, typename IdxT, bool SPLIT>
-__global__ void __launch_bounds__(kSegThreads) k_segments_quad(SegArgs a)
-{
-    extern __shared__ unsigned long long bins[];   // [a.H], then the LDS prices
-    __shared__ double zsh[kSegThreads / 64];
-    const int H = a.H;
-    T* lprice = (T*)(bins + H);
-    for (int j = threadIdx.x; j < H; j += kSegThreads) bins[j] = 0ull;
-    const int64_t np = SPLIT ? (int64_t)a.hp : a.n;
-    for (int64_t j = threadIdx.x; j < np; j += kSegThreads) lprice[j] = ((const T*)a.rho)[j];
-    __syncthreads();
-
-    double zacc = 0.0;
-    const int64_t tiles = (a.L + seg::kQuadTileRows - 1) / seg::kQuadTileRows;
-    if (SPLIT) {
-        const seg::SplitPrices<T> pr{(const T*)lprice, (const T*)a.rho, a.hp};
-        seg::process_tiles_quad<T, J, seg::SplitPrices<T>, IdxT>(a, blockIdx.x, tiles, gridDim.x,
-                                                                 bins, pr, zacc);
-    } else {
-        const seg::FlatPrices<T> pr{(const T*)lprice};
-        seg::process_tiles_quad<T, J, seg::FlatPrices<T>, IdxT>(a, blockIdx.x, tiles, gridDim.x,
-                                                                bins, pr, zacc);
-    }
-
-    __syncthreads();
-    flush_bins(a, bins);
-    for (int o = 32; o > 0; o >>= 1) zacc += __shfl_down(zacc, o, 64);
-    if ((threadIdx.x & 63) == 0) zsh[threadIdx.x >> 6] = zacc;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double z = zsh[0];
-        for (int q = 1; q < kSegThreads / 64; ++q) z += zsh[q];
-        a.zpart[blockIdx.x] = z;
-    }
-}
-
-// Mixed kernel: positions [0, P) (rows of at most 32 entries) in the quad
-// layout, solved by 4-lane groups (args a, L = P), then positions [P, L) in
-// the 8-lane slot-major layout (args b: the same instance viewed from P).
-// One launch: the blocks share the LDS prices and bins over both parts.
-template <typename T, typename IdxT>
-__global__ void __launch_bounds__(kSegThreads) k_segments_mixed(SegArgs a, SegArgs b)
-{
-    extern __shared__ unsigned long long bins[];   // [a.H], then [a.n] prices
-    __shared__ double zsh[kSegThreads / 64];
-    const int H = a.H;
-    T* lprice = (T*)(bins + H);
-    for (int j = threadIdx.x; j < H; j += kSegThreads) bins[j] = 0ull;
-    for (int64_t j = threadIdx.x; j < a.n; j += kSegThreads) lprice[j] = ((const T*)a.rho)[j];
-    __syncthreads();
-
-    double zacc = 0.0;
-    const seg::FlatPrices<T> pr{(const T*)lprice};
-    const int64_t ta = (a.L + seg::kQuadTileRows - 1) / seg::kQuadTileRows;
-    seg::process_tiles_quad<T, 8, seg::FlatPrices<T>, IdxT>(a, blockIdx.x, ta, gridDim.x, bins, pr,
-                                                            zacc);
-    const int64_t tb = (b.L + kSegsPerTile - 1) / kSegsPerTile;
-    seg::process_tiles_slots<T, 7, false, seg::FlatPrices<T>, false, IdxT>(b, blockIdx.x, tb,
-                                                                          gridDim.x, bins, pr,
-                                                                          zacc);
+    seg::process_tiles_slots<T, J, ALL, seg::FlatPrices<T>, IdxT, PSEG>(a, blockIdx.x, tiles,
+                                                                        gridDim.x, bins, pr, zacc);
 
     __syncthreads();
     flush_bins(a, bins);
@@ -231,7 +59,8 @@ __global__ void __launch_bounds__(kSegThreads) k_segments_mixed(SegArgs a, SegAr
 // most 32) in the quad layout by 4-lane groups (a4), the rest in the 8-lane
 // layout (a8); each view starts at its first position.
 // SPLIT: prices [0, a2.hp) in LDS, the rest from global memory.
-template <typename T, typename IdxT, bool SPLIT = false>
+// PSEG: also add each segment's revenue to psum (the per-segment bound).
+template <typename T, typename IdxT, bool SPLIT = false, bool PSEG = false>
 __global__ void __launch_bounds__(kSegThreads) k_segments_mixed3(SegArgs a2, SegArgs a4, SegArgs a8)
 {
     extern __shared__ unsigned long long bins[];   // [a2.H], then the LDS prices
@@ -251,12 +80,12 @@ __global__ void __launch_bounds__(kSegThreads) k_segments_mixed3(SegArgs a2, Seg
     else
         pr = PR{(const T*)lprice};
     const int64_t t2 = (a2.L + seg::kPairTileRows - 1) / seg::kPairTileRows;
-    seg::process_tiles_pair<T, 8, PR, IdxT>(a2, blockIdx.x, t2, gridDim.x, bins, pr, zacc);
+    seg::process_tiles_pair<T, 8, PR, IdxT, PSEG>(a2, blockIdx.x, t2, gridDim.x, bins, pr, zacc);
     const int64_t t4 = (a4.L + seg::kQuadTileRows - 1) / seg::kQuadTileRows;
-    seg::process_tiles_quad<T, 8, PR, IdxT>(a4, blockIdx.x, t4, gridDim.x, bins, pr, zacc);
+    seg::process_tiles_quad<T, 8, PR, IdxT, PSEG>(a4, blockIdx.x, t4, gridDim.x, bins, pr, zacc);
     const int64_t t8 = (a8.L + kSegsPerTile - 1) / kSegsPerTile;
-    seg::process_tiles_slots<T, 7, false, PR, false, IdxT>(a8, blockIdx.x, t8, gridDim.x, bins, pr,
-                                                         zacc);
+    seg::process_tiles_slots<T, 7, false, PR, IdxT, PSEG>(a8, blockIdx.x, t8, gridDim.x, bins, pr,
+                                                          zacc);
 
     __syncthreads();
     flush_bins(a2, bins);
@@ -270,165 +99,111 @@ __global__ void __launch_bounds__(kSegThreads) k_segments_mixed3(SegArgs a2, Seg
     }
 }
 
-// Size-class kernel: block b solves tiles [blk[b][1], blk[b][2]) with
-// blk[b][0] register slots per lane.  The layout is sorted by row length, so
-// a run of tiles has one slot count, and loading every slot of it wastes no
-// more than the rounding of the longest row to a multiple of 8.
-template <typename T, bool LDSP>
-__global__ void __launch_bounds__(kSegThreads) k_segments_cls(SegArgs a)
+// Per-entry sales in the caller's CSR order from a pass that stored each
+// position's threshold R and (lambda / D) 2^bits: an entry is in S* exactly
+// when the segment kernel found it so (the same products and compares, in
+// the same precision), and its sale is the quantum the kernel summed.
+template <typename T>
+__global__ void k_entry_sales(int64_t L, const int32_t* perm, const int64_t* seg_ptr,
+                              const int32_t* idx, const T* v, const T* w, const int32_t* pnew,
+                              const T* rho, const T* thr, const T* lamD, double inv_fx,
+                              double* s_out)
 {
-    extern __shared__ unsigned long long bins[];   // [a.H], then [a.n] prices if LDSP
-    __shared__ double zsh[kSegThreads / 64];
-    const int H = a.H;
-    T* lprice = (T*)(bins + H);
-    for (int j = threadIdx.x; j < H; j += kSegThreads) bins[j] = 0ull;
-    if (LDSP)
-        for (int64_t j = threadIdx.x; j < a.n; j += kSegThreads) lprice[j] = ((const T*)a.rho)[j];
-    __syncthreads();
-
-    double zacc = 0.0;
-    const int64_t* e = a.blk + 3 * (size_t)blockIdx.x;
-    const int J = (int)e[0];
-    const int64_t t0 = e[1], t1 = e[2];
-    const seg::FlatPrices<T> pr{LDSP ? (const T*)lprice : (const T*)a.rho};
-    // FP64 holds at most 4 slots in registers, FP32 7 (longer rows stream
-    // the rest from memory in each round)
-    switch (J) {
-    case 1: seg::process_tiles<T, 1, 3>(a, t0, t1, 1, bins, pr, zacc); break;
-    case 2: seg::process_tiles<T, 2, 3>(a, t0, t1, 1, bins, pr, zacc); break;
-    case 3: seg::process_tiles<T, 3, 3>(a, t0, t1, 1, bins, pr, zacc); break;
-    case 4: seg::process_tiles<T, 4, 3>(a, t0, t1, 1, bins, pr, zacc); break;
-    case 5:
-        if (sizeof(T) == 4) seg::process_tiles<T, sizeof(T) == 4 ? 5 : 4, 3>(a, t0, t1, 1, bins, pr, zacc);
-        break;
-    case 6:
-        if (sizeof(T) == 4) seg::process_tiles<T, sizeof(T) == 4 ? 6 : 4, 3>(a, t0, t1, 1, bins, pr, zacc);
-        break;
-    default:
-        if (sizeof(T) == 4) seg::process_tiles<T, sizeof(T) == 4 ? 7 : 4, 3>(a, t0, t1, 1, bins, pr, zacc);
-        break;
-    }
-
-    __syncthreads();
-    flush_bins(a, bins);
-    for (int o = 32; o > 0; o >>= 1) zacc += __shfl_down(zacc, o, 64);
-    if ((threadIdx.x & 63) == 0) zsh[threadIdx.x >> 6] = zacc;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double z = zsh[0];
-        for (int q = 1; q < kSegThreads / 64; ++q) z += zsh[q];
-        a.zpart[blockIdx.x] = z;
+#pragma clang fp contract(off)
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < L;
+         p += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t l = perm[p];
+        const T R = thr[p], ls = lamD[p];
+        for (int64_t q = seg_ptr[l]; q < seg_ptr[l + 1]; ++q) {
+            const int32_t id = idx[q];
+            const T x = v[q];
+            const T den = x - w[q];
+            const T num = rho[pnew ? pnew[id] : id] * x;
+            s_out[q] = num > R * den ? (double)(long long)seg::quantum(ls, x) * inv_fx : 0.0;
+        }
     }
 }
 
 }  // namespace
 
-// Segment-kernel variants: (products per lane in registers, pipeline depth).
 template <typename T>
-struct SegVariant {
-    static const void* fn(int variant);
-};
+hipError_t launch_entry_sales(int64_t L, const int32_t* perm, const int64_t* seg_ptr,
+                              const int32_t* idx, const void* v, const void* w,
+                              const int32_t* pnew, const void* rho, const void* thr,
+                              const void* lamD, double inv_fx, double* s_out, hipStream_t s)
+{
+    if (L > 0)
+        hipLaunchKernelGGL(k_entry_sales<T>, dim3(2048), dim3(256), 0, s, L, perm, seg_ptr, idx,
+                           (const T*)v, (const T*)w, pnew, (const T*)rho, (const T*)thr,
+                           (const T*)lamD, inv_fx, s_out);
+    return hipGetLastError();
+}
 
 template <typename T>
-const void* SegVariant<T>::fn(int variant)
+const void* segment_kernel(int variant, bool pseg)
 {
-    switch (variant) {
-    case 0: return (const void*)k_segments<T, 8, 1, false>;
-    case 1: return (const void*)k_segments<T, 6, 2, false>;
-    case 2: return (const void*)k_segments<T, 4, 2, false>;
-    case 3: return (const void*)k_segments<T, 8, 2, false>;
-    case 5: return (const void*)k_segments<T, 8, 0, false>;
-    case 6: return (const void*)k_segments<T, 7, 1, false>;
-    case 7: return (const void*)k_segments<T, 7, 3, false>;
-    case 8: return (const void*)k_segments<T, 8, 3, false>;
-    case 9: return (const void*)k_segments<T, 4, 3, false>;
-    case 10: return (const void*)k_segments<T, 7, 1, true>;
-    case 11: return (const void*)k_segments<T, 8, 1, true>;
-    case 12: return (const void*)k_segments<T, 4, 1, true>;
-    case 13: return (const void*)k_segments<T, 7, 3, true>;
-    case 14: return (const void*)k_segments<T, 6, 1, true>;
-    case 15: return (const void*)k_segments<T, 7, 4, true>;
-    case 16: return (const void*)k_segments<T, 8, 4, true>;
-    case kSegClassLds: return (const void*)k_segments_cls<T, true>;
-    case kSegClassGlobal: return (const void*)k_segments_cls<T, false>;
-    case kSegSplit: return (const void*)k_segments_split<T, 7>;
-    case kSegSlots: return (const void*)k_segments_slots<T, 7, true, true>;
-    case kSegSlots + 1: return (const void*)k_segments_slots<T, 7, false, true>;
-    case kSegSlots + 2: return (const void*)k_segments_slots<T, 8, true, true>;
-    case kSegSlots + 3: return (const void*)k_segments_slots<T, 4, true, false>;
-    case kSegSlots + 4: return (const void*)k_segments_slots<T, 7, false, true, true>;
-    case kSegSlots + 5: return (const void*)k_segments_slots<T, 4, false, false, true>;
-    case kSegSlotsSplit: return (const void*)k_segments_slots_split<T, 7>;
-    case kSegSlotsSplit + 1: return (const void*)k_segments_slots_split<T, 4>;
-    case kSegSlotsJ4: return (const void*)k_segments_slots<T, 4, false, true>;
-    case kSegSlots16: return (const void*)k_segments_slots<T, 7, false, true, false, uint16_t>;
-    case kSegSlots16 + 1: return (const void*)k_segments_slots<T, 4, false, true, false, uint16_t>;
-    case kSegSlots16 + 2: return (const void*)k_segments_slots<T, 4, true, false, false, uint16_t>;
-    case kSegQuad: return (const void*)k_segments_quad<T, 8, uint16_t, false>;
-    case kSegQuad + 1: return (const void*)k_segments_quad<T, 8, int32_t, true>;
-    case kSegQuad + 2: return (const void*)k_segments_quad<T, 8, int32_t, false>;
-    case kSegMixed: return (const void*)k_segments_mixed<T, uint16_t>;
-    case kSegMixed + 1: return (const void*)k_segments_mixed<T, int32_t>;
-    case kSegMixed3: return (const void*)k_segments_mixed3<T, uint16_t>;
-    case kSegMixed3 + 1: return (const void*)k_segments_mixed3<T, int32_t>;
-    case kSegMixed3 + 2: return (const void*)k_segments_mixed3<T, int32_t, true>;
-    case kSegMixed3 + 3: return (const void*)k_segments_mixed3<T, uint16_t, true>;
-    default: return (const void*)k_segments<T, 4, 1, false>;
+    // the narrow groups are FP32 kernels (eight slots of doubles would spill)
+    if constexpr (sizeof(T) == 4) {
+        switch (variant) {
+        case kSegMixed3:
+            return pseg ? (const void*)k_segments_mixed3<T, uint16_t, false, true>
+                        : (const void*)k_segments_mixed3<T, uint16_t>;
+        case kSegMixed3Split16:
+            return pseg ? (const void*)k_segments_mixed3<T, uint16_t, true, true>
+                        : (const void*)k_segments_mixed3<T, uint16_t, true>;
+        case kSegMixed3Split32:
+            return pseg ? (const void*)k_segments_mixed3<T, int32_t, true, true>
+                        : (const void*)k_segments_mixed3<T, int32_t, true>;
+        default: break;
+        }
     }
+    if (variant == kSegSlots16)
+        return pseg ? (const void*)k_segments_slots<T, 4, true, false, uint16_t, true>
+                    : (const void*)k_segments_slots<T, 4, true, false, uint16_t>;
+    return pseg ? (const void*)k_segments_slots<T, 4, true, false, int32_t, true>
+                : (const void*)k_segments_slots<T, 4, true, false, int32_t>;
 }
 
 template <typename T>
-hipError_t launch_segments_mixed(const SegArgs& a, const SegArgs& b, int grid, int variant,
-                                 hipStream_t s)
+hipError_t launch_segments(const SegArgs& a2, const SegArgs& a4, const SegArgs& a8, int grid,
+                           int variant, bool pseg, hipStream_t s)
 {
-    const size_t lds = seg_lds_bytes(a.H, a.n, sizeof(T), variant);
-    void* args[] = {(void*)&a, (void*)&b};
-    return hipLaunchKernel(SegVariant<T>::fn(variant), dim3(grid), dim3(kSegThreads), args, lds,
-                           s);
+    const size_t lds = seg_lds_bytes(a2.H, a2.n, a2.hp, sizeof(T), variant);
+    const void* f = segment_kernel<T>(variant, pseg);
+    if (pseg) (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (seg_mixed3(variant)) {
+        void* args[] = {(void*)&a2, (void*)&a4, (void*)&a8};
+        return hipLaunchKernel(f, dim3(grid), dim3(kSegThreads), args, lds, s);
+    }
+    void* args[] = {(void*)&a8};
+    return hipLaunchKernel(f, dim3(grid), dim3(kSegThreads), args, lds, s);
 }
 
 template <typename T>
-hipError_t launch_segments_mixed3(const SegArgs& a2, const SegArgs& a4, const SegArgs& a8, int grid,
-                                  int variant, hipStream_t s)
-{
-    const size_t lds = seg_lds_bytes(a2.H, seg_split(variant) ? a2.hp : a2.n, sizeof(T), variant);
-    void* args[] = {(void*)&a2, (void*)&a4, (void*)&a8};
-    return hipLaunchKernel(SegVariant<T>::fn(variant), dim3(grid), dim3(kSegThreads), args, lds,
-                           s);
-}
-
-template <typename T>
-hipError_t launch_segments(const SegArgs& a, int grid, int variant, hipStream_t s)
-{
-    const size_t lds = seg_lds_bytes(a.H, seg_split(variant) ? a.hp : a.n, sizeof(T), variant);
-    void* args[] = {(void*)&a};
-    return hipLaunchKernel(SegVariant<T>::fn(variant), dim3(grid), dim3(kSegThreads), args, lds,
-                           s);
-}
-
-template <typename T>
-int segment_blocks_per_cu(int H, int64_t n, int variant)   // n: prices held in LDS
+int segment_blocks_per_cu(int H, int64_t n, int hp, int variant)
 {
     int blocks = 0;
-    const size_t lds = seg_lds_bytes(H, n, sizeof(T), variant);
-    const void* f = SegVariant<T>::fn(variant);
+    const size_t lds = seg_lds_bytes(H, n, hp, sizeof(T), variant);
+    const void* f = segment_kernel<T>(variant, false);
     (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, f, kSegThreads, lds) != hipSuccess)
         return 1;
     return blocks < 1 ? 1 : blocks;
 }
 
-template hipError_t launch_segments<float>(const SegArgs&, int, int, hipStream_t);
-template hipError_t launch_segments_mixed<float>(const SegArgs&, const SegArgs&, int, int,
-                                                 hipStream_t);
-template hipError_t launch_segments_mixed<double>(const SegArgs&, const SegArgs&, int, int,
-                                                  hipStream_t);
-template hipError_t launch_segments_mixed3<float>(const SegArgs&, const SegArgs&, const SegArgs&, int,
-                                                  int, hipStream_t);
-template hipError_t launch_segments_mixed3<double>(const SegArgs&, const SegArgs&, const SegArgs&,
-                                                   int, int, hipStream_t);
-template hipError_t launch_segments<double>(const SegArgs&, int, int, hipStream_t);
-template int segment_blocks_per_cu<float>(int, int64_t, int);
-template int segment_blocks_per_cu<double>(int, int64_t, int);
+template hipError_t launch_segments<float>(const SegArgs&, const SegArgs&, const SegArgs&, int, int,
+                                           bool, hipStream_t);
+template hipError_t launch_segments<double>(const SegArgs&, const SegArgs&, const SegArgs&, int,
+                                            int, bool, hipStream_t);
+template hipError_t launch_entry_sales<float>(int64_t, const int32_t*, const int64_t*,
+                                              const int32_t*, const void*, const void*,
+                                              const int32_t*, const void*, const void*,
+                                              const void*, double, double*, hipStream_t);
+template hipError_t launch_entry_sales<double>(int64_t, const int32_t*, const int64_t*,
+                                               const int32_t*, const void*, const void*,
+                                               const int32_t*, const void*, const void*,
+                                               const void*, double, double*, hipStream_t);
+template int segment_blocks_per_cu<float>(int, int64_t, int, int);
+template int segment_blocks_per_cu<double>(int, int64_t, int, int);
 
 }  // namespace cblp

@@ -513,31 +513,11 @@ __device__ __forceinline__ Raw<T, J> load_slots(const SegArgs& a, const WaveBoun
     return R;
 }
 
-// One load per 128-byte line of a wave-tile's entries (three arrays), whose
-// values are only folded into a sink: it starts the HBM reads of the tile two
-// steps ahead so that its real loads, a step later, find the lines in L2.
-template <typename T>
-__device__ __forceinline__ unsigned touch_tile(const SegArgs& a, const WaveBounds<T>& B, int lane)
-{
-    const int64_t b0 = wave_base(B);
-    const int lines = (int)((B.wlive ? (B.b1 - B.b0) : 0) >> 5);   // 32 entries per line
-    const int arr = lane / 21, ln = lane % 21;                      // 3 arrays x 21 lines
-    const int64_t e = b0 + 32 * (int64_t)ln;
-    unsigned x = 0u;
-    if (arr < 3 && ln < lines) {
-        const unsigned* base = arr == 0 ? (const unsigned*)a.idx3
-                             : arr == 1 ? (const unsigned*)a.v3 : (const unsigned*)a.den3;
-        x = base[e * (arr == 0 ? 1 : (int64_t)(sizeof(T) / 4))];
-    }
-    return x;
-}
-
-template <typename T, int J, bool ALL, typename PR, bool TOUCH = false, typename IdxT = int32_t>
+template <typename T, int J, bool ALL, typename PR, typename IdxT = int32_t, bool PSEG = false>
 __device__ __forceinline__ void process_tiles_slots(const SegArgs& a, int64_t tile, int64_t tiles,
                                                     int64_t stride, unsigned long long* bins,
                                                     const PR& rho, double& zacc)
 {
-    unsigned sink = 0u;
     const T* __restrict__ v3 = (const T*)a.v3;
     const T* __restrict__ d3 = (const T*)a.den3;
     const IdxT* __restrict__ i3 = (const IdxT*)a.idx3;
@@ -551,19 +531,12 @@ __device__ __forceinline__ void process_tiles_slots(const SegArgs& a, int64_t ti
     Raw<T, J> Rc = load_slots<T, J, ALL, IdxT>(a, Bc, lane);
     WaveBounds<T> B1 = load_wave_bounds<T>(a, tile + stride, wv, q);
     WaveBounds<T> B2;
-    if (TOUCH) B2 = load_wave_bounds<T>(a, tile + 2 * stride, wv, q);
     T Pc[J];
     for (; tile < tiles; tile += stride) {
         gather<T, J, true, PR>(rho, Rc, Pc, J);
         __builtin_amdgcn_sched_barrier(0);
         const Raw<T, J> R1 = load_slots<T, J, ALL, IdxT>(a, B1, lane);
-        WaveBounds<T> B3;
-        if (TOUCH) {
-            sink ^= touch_tile<T>(a, B2, lane);
-            B3 = load_wave_bounds<T>(a, tile + 3 * stride, wv, q);
-        } else {
-            B2 = load_wave_bounds<T>(a, tile + 2 * stride, wv, q);
-        }
+        B2 = load_wave_bounds<T>(a, tile + 2 * stride, wv, q);
 
         const int jw = wave_jw(Bc);
         const int64_t base = wave_base(Bc);
@@ -647,12 +620,14 @@ __device__ __forceinline__ void process_tiles_slots(const SegArgs& a, int64_t ti
         }
         const T Rstar = Rs;
         const T lamD = ratio(Bc.lam, vt0 + Dn) * (T)a.fx_scale;
+        double pl = 0.0;   // PSEG: sum r_j q_lj over this lane's sales (q in quanta)
 #pragma unroll
         for (int s = 0; s < J; ++s) {
             if (s >= js) break;
             if (num[s] > R * den[s]) {
                 const unsigned long long qv = quantum(lamD, Rc.v[s]);
                 const int32_t j = Rc.id[s];
+                if constexpr (PSEG) pl += (double)((const T*)a.rlib)[j] * (double)(long long)qv;
                 if (j < H)
                     atomicAdd(&bins[j], qv);
                 else
@@ -665,24 +640,29 @@ __device__ __forceinline__ void process_tiles_slots(const SegArgs& a, int64_t ti
             const int32_t j = (int32_t)i3[e];
             if (rho[j] * x > R * d3[e]) {
                 const unsigned long long qq = quantum(lamD, x);
+                if constexpr (PSEG) pl += (double)((const T*)a.rlib)[j] * (double)(long long)qq;
                 if (j < H)
                     atomicAdd(&bins[j], qq);
                 else
                     atomicAdd(&a.S_fx[j], qq);
             }
         }
+        if constexpr (PSEG) pl = group_sum(pl);
         if ((lane & (kGroup - 1)) == 0 && Bc.live) {
             const int64_t p = (tile * (kSegsPerTile / kGroup) + wv) * kGroup + q;
             zacc += (double)Bc.lam * (double)Rstar;
             ((T*)a.Rwarm)[p] = Rstar;
             if (a.seg_R) ((T*)a.seg_R)[a.perm[p]] = Rstar;
+            if (a.seg_thr) {
+                ((T*)a.seg_thr)[p] = R;
+                ((T*)a.seg_lamD)[p] = lamD;
+            }
+            if constexpr (PSEG) a.psum[p] = (a.psum_reset ? 0.0 : a.psum[p]) + pl * a.inv_fx;
         }
         Bc = B1;
         Rc = R1;
         B1 = B2;
-        if (TOUCH) B2 = B3;
     }
-    if (TOUCH && sink == 0x9E3779B9u && a.L < 0) a.zpart[0] = 0.0;   // keeps the touches
 }
 
 // ---------------------------------------------------------------------------
@@ -707,6 +687,13 @@ __device__ __forceinline__ X quad_sum(X lo, X hi)
     return x;
 }
 
+// Plain sum over the four lanes of a quad (the same on every lane of it).
+__device__ __forceinline__ double quad_total(double x)
+{
+    x += dpp_move<kQuadSwap2>(x);
+    return x + dpp_move<kQuadSwap1>(x);
+}
+
 template <typename T>
 __device__ __forceinline__ WaveBounds<T> load_wave_bounds_quad(const SegArgs& a, int64_t t, int wv,
                                                               int q)
@@ -727,7 +714,7 @@ __device__ __forceinline__ WaveBounds<T> load_wave_bounds_quad(const SegArgs& a,
     return B;
 }
 
-template <typename T, int J, typename PR, typename IdxT>
+template <typename T, int J, typename PR, typename IdxT, bool PSEG = false>
 __device__ __forceinline__ void process_tiles_quad(const SegArgs& a, int64_t tile, int64_t tiles,
                                                    int64_t stride, unsigned long long* bins,
                                                    const PR& rho, double& zacc)
@@ -846,12 +833,14 @@ __device__ __forceinline__ void process_tiles_quad(const SegArgs& a, int64_t til
         }
         const T Rstar = Rs;
         const T lamD = ratio(Bc.lam, vt0 + Dn) * (T)a.fx_scale;
+        double pl = 0.0;   // PSEG: sum r_j q_lj over this lane's sales (q in quanta)
 #pragma unroll
         for (int s = 0; s < J; ++s) {
             if (s >= js) break;
             if (num[s] > R * den[s]) {
                 const unsigned long long qv = quantum(lamD, Rc.v[s]);
                 const int32_t j = Rc.id[s];
+                if constexpr (PSEG) pl += (double)((const T*)a.rlib)[j] * (double)(long long)qv;
                 if (j < H)
                     atomicAdd(&bins[j], qv);
                 else
@@ -864,17 +853,24 @@ __device__ __forceinline__ void process_tiles_quad(const SegArgs& a, int64_t til
             const int32_t j = (int32_t)i3[e];
             if (rho[j] * x > R * d3[e]) {
                 const unsigned long long qq = quantum(lamD, x);
+                if constexpr (PSEG) pl += (double)((const T*)a.rlib)[j] * (double)(long long)qq;
                 if (j < H)
                     atomicAdd(&bins[j], qq);
                 else
                     atomicAdd(&a.S_fx[j], qq);
             }
         }
+        if constexpr (PSEG) pl = quad_total(pl);
         if ((lane & (kQuad - 1)) == 0 && Bc.live) {
             const int64_t p = (tile * (kSegThreads / 64) + wv) * kQuadRows + q;
             zacc += (double)Bc.lam * (double)Rstar;
             ((T*)a.Rwarm)[p] = Rstar;
             if (a.seg_R) ((T*)a.seg_R)[a.perm[p]] = Rstar;
+            if (a.seg_thr) {
+                ((T*)a.seg_thr)[p] = R;
+                ((T*)a.seg_lamD)[p] = lamD;
+            }
+            if constexpr (PSEG) a.psum[p] = (a.psum_reset ? 0.0 : a.psum[p]) + pl * a.inv_fx;
         }
         Bc = B1;
         Rc = R1;
@@ -930,7 +926,7 @@ __device__ __forceinline__ WaveBounds<T> load_wave_bounds_pair(const SegArgs& a,
     return B;
 }
 
-template <typename T, int J, typename PR, typename IdxT>
+template <typename T, int J, typename PR, typename IdxT, bool PSEG = false>
 __device__ __forceinline__ void process_tiles_pair(const SegArgs& a, int64_t tile, int64_t tiles,
                                                    int64_t stride, unsigned long long* bins,
                                                    const PR& rho, double& zacc)
@@ -1043,12 +1039,14 @@ __device__ __forceinline__ void process_tiles_pair(const SegArgs& a, int64_t til
         }
         const T Rstar = Rs;
         const T lamD = ratio(Bc.lam, vt0 + Dn) * (T)a.fx_scale;
+        double pl = 0.0;   // PSEG: sum r_j q_lj over this lane's sales (q in quanta)
 #pragma unroll
         for (int s = 0; s < J; ++s) {
             if (s >= js) break;
             if (num[s] > R * den[s]) {
                 const unsigned long long qv = quantum(lamD, Rc.v[s]);
                 const int32_t j = Rc.id[s];
+                if constexpr (PSEG) pl += (double)((const T*)a.rlib)[j] * (double)(long long)qv;
                 if (j < H)
                     atomicAdd(&bins[j], qv);
                 else
@@ -1061,17 +1059,24 @@ __device__ __forceinline__ void process_tiles_pair(const SegArgs& a, int64_t til
             const int32_t j = (int32_t)i3[e];
             if (rho[j] * x > R * d3[e]) {
                 const unsigned long long qq = quantum(lamD, x);
+                if constexpr (PSEG) pl += (double)((const T*)a.rlib)[j] * (double)(long long)qq;
                 if (j < H)
                     atomicAdd(&bins[j], qq);
                 else
                     atomicAdd(&a.S_fx[j], qq);
             }
         }
+        if constexpr (PSEG) pl = pl + dpp_move<kQuadSwap1>(pl);
         if ((lane & (kPair - 1)) == 0 && Bc.live) {
             const int64_t p = (tile * (kSegThreads / 64) + wv) * kPairRows + q;
             zacc += (double)Bc.lam * (double)Rstar;
             ((T*)a.Rwarm)[p] = Rstar;
             if (a.seg_R) ((T*)a.seg_R)[a.perm[p]] = Rstar;
+            if (a.seg_thr) {
+                ((T*)a.seg_thr)[p] = R;
+                ((T*)a.seg_lamD)[p] = lamD;
+            }
+            if constexpr (PSEG) a.psum[p] = (a.psum_reset ? 0.0 : a.psum[p]) + pl * a.inv_fx;
         }
         Bc = B1;
         Rc = R1;

@@ -107,12 +107,8 @@ def warm_solve(net: "cblp.WarmStartNet", prob: "cblp.Problem", inst, spec: Solve
     dict with 'warm' (bool), 'D0', 'D_pred', 'predict_seconds'; eta)."""
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    eta = net.predict(prob)
-    d_pred = prob.gap(eta)["D"]
-    d_cold = prob.gap(prob.zeros_eta())["D"]
-    warm = bool(np.isfinite(d_pred) and d_pred < d_cold)
-    if not warm:
-        eta.zero_()
+    eta, info = net.start(prob)   # prediction and cold fallback, in the library
+    warm, d_pred, d_cold = info["used"], info["D_pred"], info["D0"]
     t_pred = time.perf_counter() - t0
     st = prob.solve(eta, spec.params(prob, inst, **kw)).as_dict()
     st.update(warm=warm, D0=d_cold, D_pred=d_pred, predict_seconds=t_pred)

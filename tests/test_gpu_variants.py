@@ -1,7 +1,14 @@
-"""Every segment-kernel variant (register slots, load pipeline, price table in
-LDS or global memory, row-major, size-class or slot-major copy) computes the
-same per-segment answers: sales, usage and R* agree bit for bit with the
-default kernel, and so do the duals after a few iterations."""
+"""The segment kernels the library chooses from the shape agree bit for bit.
+
+FP32 instances take the three-part kernel (2-, 4- and 8-lane groups) with all
+prices in LDS when they fit, else with the popular head of them in LDS and
+16-bit product ids (n <= 65,536) or 32-bit ids; FP64 instances take the
+8-lane kernel with 16- or 32-bit ids.  Padding an instance with products that
+no segment considers changes which kernel runs (and how many sales bins sit
+in LDS) but not the answer for the real products, so each padded run must
+give the unpadded run's sales, usage, R* and duals bit for bit."""
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -10,8 +17,6 @@ from paper_2602_22421_amd.instances import make_instance, step_scale
 pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
-
-N_VARIANTS = 41
 
 
 @pytest.fixture(scope="module")
@@ -23,74 +28,50 @@ def cb():
     return cblp
 
 
-def _run(cb, inst, dt, variant, monkeypatch):
-    if variant is None:
-        monkeypatch.delenv("CBLP_SEG_VARIANT", raising=False)
-    else:
-        monkeypatch.setenv("CBLP_SEG_VARIANT", str(variant))
+def _pad(inst, n):
+    """The instance with products [inst.n, n) added; no segment considers them."""
+    extra = n - inst.n
+    rng = np.random.default_rng(n)
+    r = np.concatenate([inst.r, rng.uniform(1, 100, extra).astype(inst.r.dtype)])
+    c = np.concatenate([inst.c, np.ones(extra, dtype=inst.c.dtype)])
+    return dataclasses.replace(inst, n=n, m=n, r=r, c=c)
+
+
+def _run(cb, inst, dt, n0, tau0):
     prob = cb.Problem(inst, dtype=dt)
     rng = np.random.default_rng(11)
-    eta = prob.tensor(rng.uniform(0, 1, inst.m) * inst.r * 0.5)
-    S, u, R = prob.sales(eta, seg_R=True)
-    out = [S.cpu().numpy(), u.cpu().numpy(), R.cpu().numpy()]
+    eta0 = np.zeros(inst.m)
+    eta0[:n0] = rng.uniform(0, 1, n0) * inst.r[:n0] * 0.5
+    S, u, R = prob.sales(prob.tensor(eta0), seg_R=True)
+    out = [S.cpu().numpy()[:n0], u.cpu().numpy()[:n0], R.cpu().numpy()]
     npdt = np.float32 if dt == torch.float32 else np.float64
-    tau = prob.tensor(step_scale(inst, 1e-3).astype(npdt))
+    tau = np.concatenate([tau0, np.ones(inst.m - n0)]).astype(npdt)
     e2 = prob.zeros_eta()
-    prob.iterate(e2, 5, cb.make_params(rule=0, tau_vec=tau, check_every=5), trace=False)
-    out.append(e2.cpu().numpy())
+    tr, _ = prob.iterate(e2, 5, cb.make_params(rule=0, tau_vec=prob.tensor(tau), check_every=5))
+    out.append(e2.cpu().numpy()[:n0])
     info = cb.cblp_launch_info(prob.h)
     prob.close()
-    return out, info
+    return out, tr, info
 
 
-@pytest.mark.parametrize("dtype", ["f32", "f64"])
-def test_all_variants_agree(cb, dtype, monkeypatch):
+@pytest.mark.parametrize("dtype,sizes", [("f32", (600, 30000, 70000)), ("f64", (600, 70000))])
+def test_shape_chosen_kernels_agree(cb, dtype, sizes):
     dt = torch.float32 if dtype == "f32" else torch.float64
-    # rows up to 80 entries: past the register slots of every variant
-    inst = make_instance(30000, 600, size_lo=1, size_hi=80, zipf=1.1, cap_lo=0.2, cap_hi=0.5,
-                         seed=21).cast(np.float32 if dtype == "f32" else np.float64)
-    ref, _ = _run(cb, inst, dt, None, monkeypatch)
-    for v in range(N_VARIANTS):
-        got, info = _run(cb, inst, dt, v, monkeypatch)
+    npdt = np.float32 if dtype == "f32" else np.float64
+    # rows of 1..80 entries: every group width, and rows past the register slots
+    base = make_instance(30000, 600, size_lo=1, size_hi=80, zipf=1.1, cap_lo=0.2, cap_hi=0.5,
+                         seed=21).cast(npdt)
+    tau0 = step_scale(base, 1e-3)
+    ref, tr_ref, info_ref = _run(cb, base, dt, base.n, tau0)
+    bins = [info_ref["lds_bins"]]
+    for n in sizes[1:]:
+        got, tr, info = _run(cb, _pad(base, n), dt, base.n, tau0)
+        bins.append(info["lds_bins"])
         for k, (a, b) in enumerate(zip(ref, got)):
-            assert np.array_equal(a, b), (v, k, info)
-
-
-@pytest.mark.parametrize("dtype", ["f32", "f64"])
-def test_flush_modes_agree(cb, dtype, monkeypatch):
-    """Sales bins added to the global accumulators by integer atomics (the
-    default) and per-block partial rows folded in block order give the same
-    exact integer totals, hence identical results."""
-    dt = torch.float32 if dtype == "f32" else torch.float64
-    inst = make_instance(30000, 3000, size_lo=1, size_hi=60, zipf=1.1, cap_lo=0.2, cap_hi=0.5,
-                         seed=23).cast(np.float32 if dtype == "f32" else np.float64)
-    for v in (None, 6, 13, 17, 19, 23):
-        monkeypatch.delenv("CBLP_FLUSH", raising=False)
-        ref, _ = _run(cb, inst, dt, v, monkeypatch)
-        monkeypatch.setenv("CBLP_FLUSH", "rows")
-        got, info = _run(cb, inst, dt, v, monkeypatch)
-        for k, (a, b) in enumerate(zip(ref, got)):
-            assert np.array_equal(a, b), (v, k, info)
-    monkeypatch.delenv("CBLP_FLUSH", raising=False)
-
-
-def test_narrow_groups_match_8_lane_over_many_iterations(cb, monkeypatch):
-    """The 2- and 4-lane kernels (three-part default) against the 8-lane one
-    over many iterations on uneven instances: the duals stay identical.  (A
-    narrow group caps a row's Dinkelbach rounds by the longest row of its 16-
-    or 32-row wave, an 8-lane wave by its 8 rows; only a row that reaches
-    the cap without converging could tell them apart.)"""
-    from paper_2602_22421_amd.instances import batch_instance
-    for b in range(0, 48, 3):
-        inst = batch_instance(b, scale=0.004).cast(np.float32)
-        outs = []
-        for v in ("29", "37"):
-            monkeypatch.setenv("CBLP_SEG_VARIANT", v)
-            prob = cb.Problem(inst, dtype=torch.float32)
-            tau = prob.tensor(step_scale(inst, 2e-3).astype(np.float32))
-            eta = prob.zeros_eta()
-            prob.iterate(eta, 300, cb.make_params(rule=0, tau_vec=tau, check_every=10), trace=False)
-            outs.append(eta.cpu().numpy())
-            prob.close()
-        assert np.array_equal(outs[0], outs[1]), b
-    monkeypatch.delenv("CBLP_SEG_VARIANT", raising=False)
+            assert np.array_equal(a, b), (n, k, info)
+        # the FP64 sums over products only gain exact zeros
+        np.testing.assert_allclose(tr[:, :3], tr_ref[:, :3], rtol=1e-14)
+    if dtype == "f32":
+        # all 600 prices and bins in LDS; then the 8,192 head prices and fewer
+        # bins than products (the rest of the sales take global atomics)
+        assert bins[0] == 600 and 600 < bins[1] < 30000 and bins[2] == bins[1], bins

@@ -117,6 +117,115 @@ def test_gradients_match_reference(cb, rows):
     net.close()
 
 
+# ------------------------------------------------ against the exact network
+#
+# The GPU network works with BF16 operands (8 significant bits, so each
+# rounding to nearest is a relative error of at most U = 2^-8) and FP32
+# sums.  Its answer is compared with the exact FP64 network (oracle.mlp with
+# bf=False) within the spread that BF16 rounding produces: the exact network
+# is evaluated SAMPLES times with every weight and every intermediate array
+# (z1, h1, z2, h2, y and, backward, dZ2, dH1, dZ1) multiplied by independent
+# factors 1 + U xi, xi uniform in [-1, 1] - wherever an implementation might
+# round, not only where this one does - and the tolerance of each output
+# entry is K standard deviations of those samples plus 2^-20 of the sum of
+# |terms| for the FP32 sums.  Weight perturbations are shared by all rows of
+# a sample, so errors that add up coherently over rows are covered.
+
+U = 2.0 ** -8
+F32 = 2.0 ** -20
+K = 8.0
+SAMPLES = 48
+
+
+def _perturbed(p, X, Y, rng):
+    """Exact network output and gradient with every array perturbed (rng:
+    None for the unperturbed network)."""
+    def f(a):
+        a = np.asarray(a, dtype=np.float64)
+        return a if rng is None else a * (1.0 + U * rng.uniform(-1.0, 1.0, a.shape))
+    q = om.unpack(p.astype(np.float64))
+    X = X.astype(np.float64)
+    W1, W2, w3 = f(q["W1"]), f(q["W2"]), f(q["w3"])
+    z1 = f(X @ W1 + q["b1"])
+    h1 = f(om.gelu(z1))
+    z2 = f(h1 @ W2 + q["b2"])
+    h2 = f(om.gelu(z2))
+    y = f(h2 @ w3 + q["b3"][0])
+    if Y is None:
+        return y, None
+    e = 2.0 * (y - Y.astype(np.float64)) / X.shape[0]
+    D2 = f(np.outer(e, w3) * om.gelu_prime(z2))
+    dH1 = f(D2 @ W2.T)
+    D1 = f(dH1 * om.gelu_prime(z1))
+    g = dict(b3=np.array([e.sum()]), w3=h2.T @ e, b2=D2.sum(0), W2=h1.T @ D2,
+             b1=D1.sum(0), W1=X.T @ D1)
+    return y, om.pack(g)
+
+
+def _exact_bounds(p, X, Y, seed=0):
+    """(y, y_tol) and, with targets Y, (g, g_tol) of the exact network."""
+    y, g = _perturbed(p, X, Y, None)
+    rng = np.random.default_rng(seed)
+    ys, gs = [], []
+    for _ in range(SAMPLES):
+        yp, gp = _perturbed(p, X, Y, rng)
+        ys.append(yp)
+        gs.append(gp)
+    q = om.unpack(p.astype(np.float64))
+    h1 = np.abs(om.gelu(X.astype(np.float64) @ q["W1"] + q["b1"]))
+    mag_y = (h1 @ np.abs(q["W2"]) + np.abs(q["b2"])) @ np.abs(q["w3"]) + abs(q["b3"][0])
+    ytol = K * np.std(ys, axis=0) + F32 * mag_y
+    if Y is None:
+        return (y, ytol), None
+    gmag = np.abs(np.asarray(gs)).max(axis=0)
+    gtol = K * np.std(gs, axis=0) + F32 * X.shape[0] * gmag
+    return (y, ytol), (g, gtol)
+
+
+@pytest.mark.parametrize("rows", [37, 1000])
+def test_forward_matches_exact_network(cb, rows):
+    net = cb.WarmStartNet(seed=1)
+    p = _params(3)
+    net.params = p
+    X, _ = _rows(rows + 5, rows)
+    y = net.forward(torch.from_numpy(X).cuda()).cpu().numpy().astype(np.float64)
+    (ye, tol), _ = _exact_bounds(p, X, None)
+    ye2, _ = om.forward(p.astype(np.float64), X.astype(np.float64), bf=False)
+    np.testing.assert_allclose(ye, ye2, rtol=1e-12)
+    err = np.abs(y - ye)
+    assert np.all(err <= tol), (np.max(err / tol), int(np.argmax(err / tol)))
+    # the bound is not vacuous: it is a small fraction of the output scale
+    assert np.median(tol) <= 0.1 * np.median(np.abs(ye))
+    net.close()
+
+
+@pytest.mark.parametrize("rows", [37, 700])
+def test_gradients_match_exact_network(cb, rows):
+    """Every gradient entry against the exact FP64 network's, within the
+    bound carried from the BF16 roundings (row counts that leave partial
+    MFMA tiles)."""
+    net = cb.WarmStartNet(seed=2)
+    p = _params(5)
+    net.params = p
+    X, Y = _rows(11 + rows, rows)
+    loss, g = net.gradients(torch.from_numpy(X).cuda(), torch.from_numpy(Y).cuda())
+    g = g.cpu().numpy().astype(np.float64)
+    _, (ge, tol) = _exact_bounds(p, X, Y)
+    _, gref = om.gradients(p.astype(np.float64), X.astype(np.float64), Y.astype(np.float64),
+                           bf=False)
+    np.testing.assert_allclose(ge, gref, rtol=1e-9, atol=1e-14)
+    err = np.abs(g - ge)
+    for name, sl in _blocks().items():
+        bad = np.nonzero(err[sl] > tol[sl])[0]
+        assert bad.size == 0, (name, bad[:5], err[sl][bad[:5]], tol[sl][bad[:5]])
+    # a sign error or a transposed index in any block would exceed the bound
+    # on its larger entries: the bound is well below them
+    for name, sl in _blocks().items():
+        big = np.abs(ge[sl]) >= 0.5 * np.abs(ge[sl]).max()
+        assert np.all(tol[sl][big] < 0.5 * np.abs(ge[sl][big])), name
+    net.close()
+
+
 def test_adam_step_matches_reference(cb):
     net = cb.WarmStartNet(seed=3)
     p = _params(9)

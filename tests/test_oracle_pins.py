@@ -239,11 +239,61 @@ def test_dual_step_hand_worked():
     inst.lam[:] = 1.0
     inst.r[:] = 10.0
     inst.c[:] = 0.2
-    s = oracle.Solver(inst, tau=np.array([0.5]), mu=0.1)
+    s = oracle.Solver(inst, tau=np.array([0.5]), mu=0.1, check_every=1)
     eta, tr = s.iterate(np.zeros(1), 2)
     assert tr[0, 0] == pytest.approx(20.0 / 3.0, rel=1e-14)
     assert tr[1, 0] == pytest.approx(0.2 * 7 / 30 + 293 / 45, rel=1e-14)
     assert eta[0] == pytest.approx(0.455, rel=1e-14)
+    # the other trace columns, worked by hand:
+    #   P: revenue r * sales = 10 * 2/3 at both steps (the product stays offered)
+    #   Z: lambda R* = 20/3, then 293/45
+    #   eta2: ||eta^{t-1}||^2 = 0, then (7/30)^2 (the duals each pass was taken at)
+    #   infeas: (u - c)^+ / c = (2/3 - 0.2) / 0.2 = 7/3 at both steps
+    #   dbest: min(20/3, 6.5577...) = the second bound
+    #   theta: c / ubar = 0.2 / (2/3) = 0.3 at both checks (K = 1), so the
+    #     bound LB = 0.3 * 20/3 = 2 (each window holds one step: it restarts
+    #     after t = 1 and t = 2)
+    #   step: 1 for the constant rule; gap = (dbest - 2) / dbest
+    np.testing.assert_allclose(tr[:, 1], [20 / 3, 20 / 3], rtol=1e-14)
+    np.testing.assert_allclose(tr[:, 2], [20 / 3, 293 / 45], rtol=1e-14)
+    np.testing.assert_allclose(tr[:, 3], [0.0, (7 / 30) ** 2], rtol=1e-14, atol=0)
+    np.testing.assert_allclose(tr[:, 4], [7 / 3, 7 / 3], rtol=1e-13)
+    d2 = 0.2 * 7 / 30 + 293 / 45
+    np.testing.assert_allclose(tr[:, 5], [20 / 3, d2], rtol=1e-14)
+    np.testing.assert_allclose(tr[:, 9], [0.3, 0.3], rtol=1e-14)
+    np.testing.assert_allclose(tr[:, 6], [2.0, 2.0], rtol=1e-14)
+    np.testing.assert_allclose(tr[:, 8], [1.0, 1.0], rtol=0)
+    np.testing.assert_allclose(tr[:, 7], [(20 / 3 - 2) / (20 / 3), (d2 - 2) / d2], rtol=1e-13)
+
+
+def test_per_segment_bound_hand_worked():
+    """Two segments with one product each (MNL, w = 0): segment 0 considers
+    product 0 (v=1, v0=1, lambda=1, r=10, c=0.25), segment 1 product 1 (v=1,
+    v0=1, lambda=1, r=4, c=1).  At eta = 0 each offers its product: sales
+    1/2 each, revenues p = 5 and 2, P = 7.  Product 0 is over its capacity
+    (ubar = 1/2 > 0.25: theta_0 = 1/2), product 1 is not (theta_1 = 1).
+    With one step and K = 1: global bound theta P = 1/2 * 7 = 3.5; the
+    per-segment bound scales only segment 0: 1/2 * 5 + 1 * 2 = 4.5."""
+    inst = make_instance(2, 2, size_lo=1, size_hi=1, seed=0)
+    inst.seg_ptr[:] = [0, 1, 2]
+    inst.idx[:] = [0, 1]
+    inst.v[:] = 1.0
+    inst.w[:] = 0.0
+    inst.v0[:] = 1.0
+    inst.lam[:] = 1.0
+    inst.r[:] = [10.0, 4.0]
+    inst.c[:] = [0.25, 1.0]
+    for perseg, lb in ((False, 3.5), (True, 4.5)):
+        s = oracle.Solver(inst, tau=np.array([1e-9, 1e-9]), check_every=1, perseg=perseg)
+        _, tr = s.iterate(np.zeros(2), 1)
+        assert tr[0, 1] == pytest.approx(7.0, rel=1e-15)
+        assert tr[0, 9] == pytest.approx(0.5, rel=1e-15)
+        assert tr[0, 6] == pytest.approx(lb, rel=1e-15), perseg
+        # the optimum lies inside [LB, D]: sell 0.25 of product 0 (its cap)
+        # by offering it 1/2 of the time, and product 1 always: 2.5 + 2 = 4.5
+        opt, _ = lp.sblp(inst)
+        assert opt == pytest.approx(4.5, rel=1e-9)
+        assert tr[0, 6] <= opt * (1 + 1e-12) <= tr[0, 0] * (1 + 1e-12)
 
 
 def _golden_opt(name):
