@@ -45,7 +45,8 @@ class _Inst(ctypes.Structure):
 
 class _Params(ctypes.Structure):
     _fields_ = [("rule", ctypes.c_int32), ("check_every", ctypes.c_int32),
-                ("perseg", ctypes.c_int32), ("gamma", ctypes.c_double), ("mu", ctypes.c_double), ("tau", _dp)]
+                ("perseg", ctypes.c_int32), ("gamma", ctypes.c_double), ("mu", ctypes.c_double),
+                ("tau", _dp), ("tau_decay", ctypes.c_double), ("decay_every", _i64)]
 
 
 class _State(ctypes.Structure):
@@ -84,6 +85,9 @@ def _load():
         lib.orc_iterate.restype = ctypes.c_int
         lib.orc_iterate.argtypes = [ctypes.POINTER(_Inst), ctypes.POINTER(_Params),
                                     ctypes.POINTER(_State), _i64, _dp, _dp]
+        lib.orc_minibatch.restype = ctypes.c_int
+        lib.orc_minibatch.argtypes = [ctypes.POINTER(_Inst), ctypes.POINTER(_Params), _i64, _i64,
+                                      _ip, _dp, _dp, _dp]
         _lib = lib
     return _lib
 
@@ -158,7 +162,8 @@ class Solver:
     """Full-batch SPFOM iterations with the certified-gap state."""
 
     def __init__(self, inst, *, tau=None, rule: int = RULE_CONST, gamma: float = 1.0,
-                 mu: float = 0.0, check_every: int = 10, perseg: bool = False):
+                 mu: float = 0.0, check_every: int = 10, perseg: bool = False,
+                 tau_decay: float = 1.0, decay_every: int = 1):
         self.b = _Bound(inst)
         m = self.b.m
         if tau is None:
@@ -166,7 +171,7 @@ class Solver:
         tau = np.broadcast_to(np.asarray(tau, dtype=np.float64), (m,)).copy()
         self.tau = tau
         self.prm = _Params(int(rule), int(check_every), int(bool(perseg)), float(gamma),
-                           float(mu), _d(self.tau))
+                           float(mu), _d(self.tau), float(tau_decay), int(decay_every))
         self.sum_u = np.zeros(max(m, 1))
         self.sum_pl = np.zeros(max(self.b.L, 1))
         self.st = _State(0, 0, 0, 0.0, 0.0, 0.0, _d(self.sum_u), _d(self.sum_pl))
@@ -201,3 +206,33 @@ class Solver:
             if self.t % K == 0 and last[7] <= tol:
                 return eta, last, True
         return eta, last, False
+
+
+class Minibatch:
+    """Stochastic minibatch SPFOM (Algorithm 2; Algorithm 3 with k B < L):
+    the per-segment sales y persist; each iteration re-solves the segments of
+    one row of ``batch`` and steps the duals with the sales of all segments."""
+
+    def __init__(self, inst, *, tau=None, mu: float = 0.0, y0=None):
+        self.b = _Bound(inst)
+        m = self.b.m
+        tau = np.ones(m) if tau is None else tau
+        self.tau = np.broadcast_to(np.asarray(tau, dtype=np.float64), (m,)).copy()
+        self.prm = _Params(RULE_CONST, 1, 0, 1.0, float(mu), _d(self.tau), 1.0, 1)
+        nnz = int(self.b.seg_ptr[-1])
+        self.y = np.zeros(nnz) if y0 is None else np.array(y0, dtype=np.float64, copy=True)
+
+    def iterate(self, eta, batch):
+        """Run len(batch) iterations; batch [iters, B] int segment ids (distinct
+        within a row).  Returns (eta, trace[iters, 10])."""
+        batch = np.ascontiguousarray(batch, dtype=np.int32)
+        iters, B = batch.shape
+        if iters and (batch.min() < 0 or batch.max() >= self.b.L):
+            raise ValueError("segment id out of range")
+        eta = np.array(eta, dtype=np.float64, copy=True)
+        tr = np.zeros((iters, NTRACE))
+        rc = _load().orc_minibatch(ctypes.byref(self.b.s), ctypes.byref(self.prm), iters, B,
+                                   batch.ctypes.data_as(_ip), _d(self.y), _d(eta), _d(tr))
+        if rc:
+            raise MemoryError("oracle minibatch")
+        return eta, tr

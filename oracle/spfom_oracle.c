@@ -32,7 +32,8 @@
  *   the minimax of Section 4.1, eqs. 10-14; >= OPT for any eta >= 0).
  *
  *   Step rules: CONST uses tau_i as given (the constant step of Algorithm 2,
- *   optionally one value per row).  POLYAK scales the given tau_i by
+ *   optionally one value per row; optionally shrunk by a factor tau_decay
+ *   every decay_every iterations, a schedule of the build's own).  POLYAK scales the given tau_i by
  *   gamma (D^t - LB) / sum_i tau_i g_i^2 with g_i = u_i - c_i (zeroed where
  *   the projection is active); the paper fixes a constant step and stops on
  *   stagnation, this rule is the build's way to reach a certified tolerance.
@@ -80,7 +81,19 @@ typedef struct {
     int32_t perseg;        /* 1: also the per-segment scaled bound */
     double gamma, mu;
     const double* tau;     /* [m] per-row step (CONST) or scaling (POLYAK) */
+    double tau_decay;      /* CONST: step tau_i * tau_decay^k in iterations k*E+1..(k+1)*E */
+    int64_t decay_every;   /* E (tau_decay 0 or 1: constant step) */
 } orc_params;
+
+/* The constant step's multiplier in iteration t (1-based): tau_decay^k with
+ * k = (t - 1) / decay_every, multiplied out one factor at a time. */
+static double orc_tau_mult(const orc_params* prm, int64_t t)
+{
+    if (prm->rule != 0 || !(prm->tau_decay > 0.0 && prm->tau_decay < 1.0)) return 1.0;
+    double m = 1.0;
+    for (int64_t q = 0; q < (t - 1) / prm->decay_every; ++q) m *= prm->tau_decay;
+    return m;
+}
 
 typedef struct {
     int64_t t;             /* iterations done */
@@ -281,7 +294,7 @@ int orc_iterate(const orc_instance* I, const orc_params* prm, orc_state* st,
             }
         }
         /* step */
-        double scale = 1.0;
+        double scale = orc_tau_mult(prm, st->t);
         if (prm->rule == 1) {
             double G = 0.0;
             for (int64_t i = 0; i < m; ++i) {
@@ -325,5 +338,85 @@ int orc_iterate(const orc_instance* I, const orc_params* prm, orc_state* st,
         }
     }
     free(u); free(pl); free(th);
+    return 0;
+}
+
+/*
+ * Stochastic minibatch SPFOM (Algorithm 2, Section 4.1; Algorithm 3 with
+ * k B < L, Section 4.3).  The primal state is every segment's sales y_l
+ * (y[nnz] in CSR order, caller-owned; y^0 as given, 0 for a cold start).
+ * Iteration t takes the B distinct segments batch[t*B .. t*B+B-1] (drawn by
+ * the caller), replaces their sales by the best response at eta^{t-1} and
+ * leaves every other segment's sales as they were; the dual step then uses
+ * the sales of ALL segments:
+ *     S^t_j = sum_l y^t_lj,   u^t = A S^t,
+ *     eta^t_i = max(0, (1 - tau_i mu) eta^{t-1}_i - tau_i (c_i - u^t_i)).
+ * With B = L every segment is re-solved and this is orc_iterate's iteration.
+ * Trace per iteration (other columns 0): P^t = sum_j r_j S^t_j, the squared
+ * norm of eta^{t-1}, the relative infeasibility of u^t and the step
+ * multiplier 1.  (No dual bound: that needs every segment's best response at
+ * one eta; a full pass, orc_pass, gives it when wanted.)
+ * Returns 0, or -1 on allocation failure.
+ */
+int orc_minibatch(const orc_instance* I, const orc_params* prm, int64_t iters, int64_t B,
+                  const int32_t* batch, double* y, double* eta, double* trace)
+{
+    const int64_t m = I->m, n = I->n;
+    int64_t kmax = 0;
+    for (int64_t l = 0; l < I->L; ++l) {
+        int64_t k = I->seg_ptr[l + 1] - I->seg_ptr[l];
+        if (k > kmax) kmax = k;
+    }
+    double* rho = (double*)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
+    double* S = (double*)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
+    double* u = (double*)malloc((size_t)(m > 0 ? m : 1) * sizeof(double));
+    double* rs = (double*)malloc((size_t)(kmax > 0 ? kmax : 1) * sizeof(double));
+    if (!rho || !S || !u || !rs) { free(rho); free(S); free(u); free(rs); return -1; }
+    for (int64_t it = 0; it < iters; ++it) {
+        orc_prices(I, eta, rho);
+        /* re-solve the sampled segments at eta^{t-1} */
+        for (int64_t q = 0; q < B; ++q) {
+            const int64_t l = batch[it * B + q];
+            const int64_t b = I->seg_ptr[l], k = I->seg_ptr[l + 1] - b;
+            for (int64_t e = 0; e < k; ++e) rs[e] = rho[I->idx[b + e]];
+            double R, D;
+            if (orc_segment(k, rs, I->v + b, I->w + b, I->v0[l], I->lam[l], &R, &D, y + b) < 0) {
+                free(rho); free(S); free(u); free(rs); return -1;
+            }
+        }
+        /* the sales of every segment, sampled or not */
+        for (int64_t j = 0; j < n; ++j) S[j] = 0.0;
+        for (int64_t l = 0; l < I->L; ++l)
+            for (int64_t e = I->seg_ptr[l]; e < I->seg_ptr[l + 1]; ++e) S[I->idx[e]] += y[e];
+        if (!I->a_ptr) {
+            memcpy(u, S, (size_t)m * sizeof(double));
+        } else {
+            for (int64_t i = 0; i < m; ++i) u[i] = 0.0;
+            for (int64_t j = 0; j < n; ++j)
+                for (int64_t e = I->a_ptr[j]; e < I->a_ptr[j + 1]; ++e)
+                    u[I->a_idx[e]] += I->a_val[e] * S[j];
+        }
+        double P = 0.0;
+        for (int64_t j = 0; j < n; ++j) P += I->r[j] * S[j];
+        double infeas = 0.0, e2 = 0.0, csum = 0.0;
+        for (int64_t i = 0; i < m; ++i) {
+            const double ti = prm->tau[i];
+            const double g = u[i] - I->c[i];
+            csum += I->c[i];
+            e2 += eta[i] * eta[i];
+            const double e = (1.0 - ti * prm->mu) * eta[i] + ti * g;
+            eta[i] = e > 0.0 ? e : 0.0;
+            if (g > 0.0) infeas += g;
+        }
+        if (trace) {
+            double* tr = trace + it * ORC_NTRACE;
+            for (int c = 0; c < ORC_NTRACE; ++c) tr[c] = 0.0;
+            tr[TR_P] = P;
+            tr[TR_ETA2] = e2;
+            tr[TR_INFEAS] = csum > 0.0 ? infeas / csum : infeas;
+            tr[TR_STEP] = 1.0;
+        }
+    }
+    free(rho); free(S); free(u); free(rs);
     return 0;
 }

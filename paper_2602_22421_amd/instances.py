@@ -37,7 +37,7 @@ from typing import Optional
 import numpy as np
 
 __all__ = ["Instance", "make_instance", "config_instance", "tiny_instance",
-           "batch_instance", "step_scale"]
+           "batch_instance", "step_scale", "minibatch_schedule"]
 
 
 @dataclasses.dataclass
@@ -319,6 +319,31 @@ def shuffle_products(inst: Instance, seed: int = 0):
                               w=np.ascontiguousarray(inst.w[order]), r=r,
                               name=(inst.name + "-shuffled") if inst.name else "shuffled", **kw)
     return out, pi
+
+
+def minibatch_schedule(L: int, B: int, iters: int, seed: int = 0,
+                       mode: str = "independent") -> np.ndarray:
+    """Segments sampled by the stochastic minibatch iterations: [iters, B]
+    int32, distinct within a row.  independent: each row a uniform B-subset
+    of [L] drawn afresh; epoch: consecutive rows walk through random
+    permutations of [L] (every segment once per L / B rows)."""
+    if not 0 < B <= L:
+        raise ValueError("need 0 < B <= L")
+    rng = np.random.default_rng(seed)
+    out = np.empty((iters, B), dtype=np.int32)
+    if mode == "independent":
+        for t in range(iters):
+            out[t] = rng.choice(L, B, replace=False)
+    elif mode == "epoch":
+        perm, pos = rng.permutation(L), 0
+        for t in range(iters):
+            if pos + B > L:
+                perm, pos = rng.permutation(L), 0
+            out[t] = perm[pos:pos + B]
+            pos += B
+    else:
+        raise ValueError(mode)
+    return out
 
 
 def step_scale(inst: Instance, tau0: float) -> np.ndarray:
