@@ -236,3 +236,24 @@ class Minibatch:
         if rc:
             raise MemoryError("oracle minibatch")
         return eta, tr
+
+
+def recover(inst, y):
+    """SBLP -> CBLP recovery (the nested sets of Section 4.4) from per-entry
+    sales y [nnz]: returns (rank [nnz] int32, alpha [nnz], alpha0 [L]); entry
+    e's alpha is the probability of offering the entries of its segment
+    ranked at most rank[e], alpha0 that of the empty set."""
+    b = _Bound(inst)
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    nnz = int(b.seg_ptr[-1])
+    rank = np.zeros(nnz, dtype=np.int32)
+    alpha = np.zeros(nnz)
+    alpha0 = np.zeros(b.L)
+    lib = _load()
+    if not hasattr(lib, "_rec_set"):
+        lib.orc_recover.restype = ctypes.c_int
+        lib.orc_recover.argtypes = [ctypes.POINTER(_Inst), _dp, _ip, _dp, _dp]
+        lib._rec_set = True
+    if lib.orc_recover(ctypes.byref(b.s), _d(y), rank.ctypes.data_as(_ip), _d(alpha), _d(alpha0)):
+        raise MemoryError("oracle recover")
+    return rank, alpha, alpha0

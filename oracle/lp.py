@@ -71,8 +71,9 @@ def cblp(inst):
     return -res.fun, -np.asarray(res.ineqlin.marginals)
 
 
-def sblp(inst):
-    """Solve the GAM sales-based LP.  Returns (OPT, capacity duals eta*[m])."""
+def sblp(inst, return_sales: bool = False):
+    """Solve the GAM sales-based LP.  Returns (OPT, capacity duals eta*[m]),
+    and with return_sales also the optimal per-entry sales s_lj [nnz]."""
     L, nnz = int(inst.L), int(inst.seg_ptr[-1])
     sizes = np.diff(inst.seg_ptr)
     seg = np.repeat(np.arange(L), sizes)
@@ -100,6 +101,8 @@ def sblp(inst):
                   method="highs")
     if res.status != 0:
         raise RuntimeError(res.message)
+    if return_sales:
+        return -res.fun, -np.asarray(res.ineqlin.marginals[: inst.m]), np.asarray(res.x[:nnz])
     return -res.fun, -np.asarray(res.ineqlin.marginals[: inst.m])
 
 

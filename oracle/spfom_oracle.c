@@ -420,3 +420,56 @@ int orc_minibatch(const orc_instance* I, const orc_params* prm, int64_t iters, i
     free(rho); free(S); free(u); free(rs);
     return 0;
 }
+
+/*
+ * SBLP -> CBLP recovery (Section 4.4, the recovery lemma), in the GAM form.
+ * Given per-entry sales y[nnz] that satisfy the SBLP rows of each segment
+ * (balance and scale), order each segment's products by y_lj / v_lj,
+ * decreasing (ties by CSR position); S_l,q is the set of the first q
+ * products.  Offering S with time share x(S) sells v_j / (vt_0 + sum_S vt)
+ * per unit of time of each j in S, so nested sets reproduce y exactly when
+ *     x(S_l,q) = (key_q - key_{q+1}) (vt_l0 + sum_{p<=q} vt_lp),
+ * key_q = y / v of the q-th product (key_{k+1} = 0).  The probability of
+ * offering S_l,q is alpha = x / lambda_l, and the empty set takes the rest.
+ * (The lemma as printed leaves out the no-purchase term of the sum and
+ * indexes the sets by [n]; both are read as above.)
+ * Outputs: rank[e] = position of entry e in its segment's order (0-based),
+ * alpha[e] = probability of the set of the entries ranked <= rank[e],
+ * alpha0[l] = probability of the empty set.  lambda_l = 0 gives alpha = 0,
+ * alpha0 = 1.  Returns 0, or -1 on allocation failure.
+ */
+int orc_recover(const orc_instance* I, const double* y, int32_t* rank, double* alpha,
+                double* alpha0)
+{
+    int64_t kmax = 0;
+    for (int64_t l = 0; l < I->L; ++l) {
+        int64_t k = I->seg_ptr[l + 1] - I->seg_ptr[l];
+        if (k > kmax) kmax = k;
+    }
+    orc_item* it = (orc_item*)malloc((size_t)(kmax > 0 ? kmax : 1) * sizeof(orc_item));
+    if (!it) return -1;
+    for (int64_t l = 0; l < I->L; ++l) {
+        const int64_t b = I->seg_ptr[l], k = I->seg_ptr[l + 1] - b;
+        double vt0 = I->v0[l];
+        for (int64_t q = 0; q < k; ++q) vt0 += I->w[b + q];
+        for (int64_t q = 0; q < k; ++q) {
+            it[q].key = y[b + q] / I->v[b + q];
+            it[q].pos = q;
+        }
+        qsort(it, (size_t)k, sizeof(orc_item), orc_cmp);
+        double W = vt0, total = 0.0;
+        for (int64_t q = 0; q < k; ++q) {
+            const int64_t p = it[q].pos;
+            W += I->v[b + p] - I->w[b + p];
+            const double next = q + 1 < k ? it[q + 1].key : 0.0;
+            const double x = (it[q].key - next) * W;
+            const double a = I->lam[l] > 0.0 ? x / I->lam[l] : 0.0;
+            rank[b + p] = (int32_t)q;
+            alpha[b + p] = a;
+            total += a;
+        }
+        alpha0[l] = I->lam[l] > 0.0 ? 1.0 - total : 1.0;
+    }
+    free(it);
+    return 0;
+}
