@@ -54,7 +54,8 @@ enum { CBLP_F32 = 1, CBLP_F64 = 2 };
 
 /* Step rules for the dual update eta_i <- max(0, (1 - t_i mu) eta_i - t_i (c_i - u_i)). */
 enum {
-    SPFOM_STEP_CONST = 0,   /* t_i = tau_i: the constant step of Algorithm 2 */
+    SPFOM_STEP_CONST = 0,   /* t_i = tau_i: the constant step of Algorithm 2 (optionally
+                               shrunk geometrically, see spfom_params.tau_decay) */
     SPFOM_STEP_POLYAK = 1   /* t_i = tau_i * gamma (D^t - LB) / sum_k tau_k g_k^2 */
 };
 
@@ -99,6 +100,10 @@ typedef struct {
     double tol;             /* spfom_solve: stop when the certified gap <= tol */
     int64_t max_iters;      /* spfom_solve: iteration cap */
     int32_t bound;          /* SPFOM_BOUND_GLOBAL or SPFOM_BOUND_SEGMENT */
+    double tau_decay;       /* CONST rule: the step is tau_i * tau_decay^k in iterations
+                               k*decay_every+1 .. (k+1)*decay_every (counted from the
+                               last reset); 0 or 1: constant.  In (0, 1]. */
+    int64_t decay_every;    /* >= 1 when tau_decay is used */
 } spfom_params;
 
 /* Result summary (host struct, FP64). */
@@ -161,6 +166,30 @@ int spfom_iterate(cblp_t h, void* eta, const spfom_params* p, int64_t iters,
  * eta [dev] [m] in/out: warm start (or zeros) in, final duals out.
  */
 int spfom_solve(cblp_t h, void* eta, const spfom_params* p, spfom_stats* out, void* stream);
+
+/*
+ * spfom_minibatch - `iters` iterations of stochastic minibatch SPFOM
+ * (Algorithm 2, Section 4.1; Algorithm 3 with k B < L, Section 4.3): the
+ * segments batch[t*B .. t*B+B-1] of iteration t re-solve their inner
+ * problems at the current duals, every other segment keeps the sales of the
+ * last pass that solved it (0 before its first), and the duals take the step
+ * of eq. 16 with the sales of ALL segments.  The per-segment sales persist in
+ * the handle between calls (made on first use: 4 bytes per consideration-set
+ * entry for CBLP_F32, 8 for CBLP_F64, plus 8 per product and 8 per segment)
+ * and restart from 0 at spfom_reset.
+ * eta [dev] [m] in/out.  p: rule CONST with constant tau (tau_decay 0 or 1);
+ * bound and the certificate fields are not used.
+ * batch [dev] int32 [iters x B]: caller segment ids, each in [0, L) and
+ * distinct within its iteration; an id out of range or listed twice returns
+ * CBLP_EINVAL and leaves the minibatch state undefined until spfom_reset.
+ * 1 <= B <= L.
+ * trace [host] nullable [iters x SPFOM_NTRACE]: PRIMAL (revenue of the kept
+ * sales), ETA2, INFEAS (of the kept sales) and STEP; the other columns are 0
+ * (a dual bound needs every segment at one eta: cblp_gap gives it).
+ * Synchronises the stream.
+ */
+int spfom_minibatch(cblp_t h, void* eta, const spfom_params* p, const int32_t* batch, int64_t B,
+                    int64_t iters, double* trace, void* stream);
 
 /*
  * cblp_gap - one best-response pass at fixed eta [dev] [m] (no dual step, no

@@ -25,6 +25,7 @@ NTRACE = 10
 TRACE_COLS = ("D", "P", "Z", "eta2", "infeas", "dbest", "lb", "gap", "step", "theta")
 EXPORTS = ("cblp_create", "cblp_destroy", "spfom_reset", "spfom_iterate", "spfom_solve",
            "cblp_gap", "cblp_sales", "cblp_launch_info", "cblp_timing", "cblp_timing_read",
+           "spfom_minibatch",
            "cblp_last_error", "cblp_batch_create", "cblp_batch_destroy", "spfom_batch_iterate",
            "spfom_batch_solve", "cblp_batch_tune", "cblp_batch_info", "cblp_batch_select",
            "wsnet_num_params", "wsnet_create", "wsnet_destroy", "wsnet_params", "wsnet_features",
@@ -37,7 +38,8 @@ class SpfomParams(ctypes.Structure):
                 ("tau", ctypes.c_double), ("tau_vec", ctypes.c_void_p),
                 ("gamma", ctypes.c_double), ("mu", ctypes.c_double),
                 ("tol", ctypes.c_double), ("max_iters", ctypes.c_int64),
-                ("bound", ctypes.c_int32)]
+                ("bound", ctypes.c_int32), ("tau_decay", ctypes.c_double),
+                ("decay_every", ctypes.c_int64)]
 
 
 class SpfomStats(ctypes.Structure):
@@ -78,6 +80,8 @@ def load(path: str = _LIB_PATH) -> ctypes.CDLL:
     lib.spfom_iterate.restype = ctypes.c_int
     lib.spfom_iterate.argtypes = [vp, vp, ctypes.POINTER(SpfomParams), i64, vp,
                                   ctypes.POINTER(SpfomStats), vp]
+    lib.spfom_minibatch.restype = ctypes.c_int
+    lib.spfom_minibatch.argtypes = [vp, vp, ctypes.POINTER(SpfomParams), vp, i64, i64, vp, vp]
     lib.spfom_solve.restype = ctypes.c_int
     lib.spfom_solve.argtypes = [vp, vp, ctypes.POINTER(SpfomParams), ctypes.POINTER(SpfomStats), vp]
     lib.cblp_gap.restype = ctypes.c_int
@@ -196,6 +200,21 @@ def spfom_iterate(h, eta, params: SpfomParams, iters: int, trace: Optional[np.nd
                                 _stream(stream)))
 
 
+def spfom_minibatch(h, eta, params: SpfomParams, batch, iters: int,
+                    trace: Optional[np.ndarray] = None, stream=None) -> None:
+    """batch: int32 device tensor [iters, B] of segment ids."""
+    assert batch.dtype == torch.int32 and batch.is_contiguous() and batch.dim() == 2
+    assert batch.shape[0] == iters
+    tp = None
+    if trace is not None:
+        assert trace.dtype == np.float64 and trace.flags.c_contiguous
+        assert trace.shape == (iters, NTRACE)
+        tp = ctypes.c_void_p(trace.ctypes.data)
+    _check(load().spfom_minibatch(ctypes.c_void_p(h), _ptr(eta), ctypes.byref(params),
+                                  _ptr(batch), int(batch.shape[1]), int(iters), tp,
+                                  _stream(stream)))
+
+
 def spfom_solve(h, eta, params: SpfomParams, stream=None) -> SpfomStats:
     st = SpfomStats()
     _check(load().spfom_solve(ctypes.c_void_p(h), _ptr(eta), ctypes.byref(params),
@@ -244,10 +263,11 @@ def cblp_timing_read(h, stream=None):
 def make_params(*, rule: int = SPFOM_STEP_CONST, check_every: int = 10, tau: float = 1.0,
                 tau_vec: Optional[torch.Tensor] = None, gamma: float = 1.0, mu: float = 0.0,
                 tol: float = 1e-4, max_iters: int = 10000,
-                bound: int = SPFOM_BOUND_GLOBAL) -> SpfomParams:
+                bound: int = SPFOM_BOUND_GLOBAL, tau_decay: float = 1.0,
+                decay_every: int = 1) -> SpfomParams:
     p = SpfomParams(int(rule), int(check_every), float(tau),
                     None if tau_vec is None else tau_vec.data_ptr(), float(gamma), float(mu),
-                    float(tol), int(max_iters), int(bound))
+                    float(tol), int(max_iters), int(bound), float(tau_decay), int(decay_every))
     p._keep = tau_vec  # keep the tensor alive with the struct
     return p
 
@@ -309,6 +329,16 @@ class Problem:
 
     def solve(self, eta: torch.Tensor, params: SpfomParams) -> SpfomStats:
         return spfom_solve(self.h, eta, params)
+
+    def minibatch(self, eta: torch.Tensor, batch, params: SpfomParams, trace: bool = True):
+        """Stochastic minibatch iterations over the rows of batch ([iters, B]
+        segment ids, numpy or a device int32 tensor)."""
+        if not isinstance(batch, torch.Tensor):
+            batch = torch.from_numpy(np.ascontiguousarray(batch, dtype=np.int32)).to(self.device)
+        iters = int(batch.shape[0])
+        tr = np.zeros((iters, NTRACE)) if trace else None
+        spfom_minibatch(self.h, eta, params, batch, iters, tr)
+        return tr
 
     def gap(self, eta: torch.Tensor) -> dict:
         return cblp_gap(self.h, eta).as_dict()

@@ -84,7 +84,8 @@ void release(cblp_instance* h)
                     h->rho, h->S_fx, h->S_d, h->u_d, h->sum_u, h->zpart,
                     h->bpart, h->bpart2, h->st, h->arrive, h->trace, h->at_ptr,
                     h->at_prod, h->at_val, h->rlib, h->psum, h->theta_prod, h->pseg_part,
-                    h->eval_thr, h->eval_lamD};
+                    h->eval_thr, h->eval_lamD, h->mb_yq, h->mb_S, h->mb_inv, h->mb_stamp,
+                    h->mb_err};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     if (h->pinned) (void)hipHostFree(h->pinned);
@@ -142,7 +143,24 @@ int check_params(const spfom_params* p)
         return fail(CBLP_EINVAL, "gamma must be in (0, 2]");
     if (p->bound != SPFOM_BOUND_GLOBAL && p->bound != SPFOM_BOUND_SEGMENT)
         return fail(CBLP_EINVAL, "unknown bound");
+    if (!(p->tau_decay >= 0.0 && p->tau_decay <= 1.0))
+        return fail(CBLP_EINVAL, "tau_decay must be in [0, 1]");
+    if (p->tau_decay > 0.0 && p->tau_decay < 1.0 && p->decay_every < 1)
+        return fail(CBLP_EINVAL, "decay_every must be >= 1");
     return CBLP_OK;
+}
+
+// The constant step's multiplier in iteration t1 (1-based, since the last
+// reset): tau_decay^k with k = (t1 - 1) / decay_every, by repeated FP64
+// multiplication (the oracle forms it the same way).
+double tau_multiplier(const spfom_params* p, int64_t t1)
+{
+    if (!p || p->rule != SPFOM_STEP_CONST || !(p->tau_decay > 0.0 && p->tau_decay < 1.0))
+        return 1.0;
+    const int64_t k = (t1 - 1) / p->decay_every;
+    double m = 1.0;
+    for (int64_t q = 0; q < k; ++q) m *= p->tau_decay;
+    return m;
 }
 
 // Buffers of the per-segment bound, made on first use: revenues by library
@@ -241,11 +259,13 @@ int run_phase(cblp_instance* h, void* eta, const spfom_params* p, int mode, doub
     a.n = h->n;
     a.m = h->m;
     a.mode = mode;
+    a.keep_sales = 0;
     a.rule = p ? p->rule : 0;
     a.check_every = p ? p->check_every : 1;
     a.gamma = p ? p->gamma : 1.0;
     a.mu = p ? p->mu : 0.0;
     a.tau_s = p ? p->tau : 1.0;
+    a.tau_mult = tau_multiplier(p, h->t + 1);
     a.tau_vec = p ? p->tau_vec : nullptr;
     a.zpart = h->zpart;
     a.nz = h->seg_grid;
@@ -272,6 +292,11 @@ int run_phase(cblp_instance* h, void* eta, const spfom_params* p, int mode, doub
     a.st = h->st;
     a.par = (int)(h->t & 1);
     a.row = row;
+    if (mode == 2) {   // minibatch: the running totals, kept; no dual bound
+        a.S_fx = h->mb_S;
+        a.keep_sales = 1;
+        a.nz = 0;
+    }
     // the per-segment bound at a check of a window that accumulated psum
     const bool check = p && mode == 0 && (h->t + 1) % p->check_every == 0;
     const bool pseg = check && p->bound == SPFOM_BOUND_SEGMENT && h->pseg_window_ok;
@@ -310,6 +335,72 @@ int iterate_impl(cblp_instance* h, void* eta, const spfom_params* p, int64_t ite
         if (restart) h->pseg_window_ok = true;
         if (pseg) h->psum_reset_next = false;
         if (restart) h->psum_reset_next = true;
+    }
+    return CBLP_OK;
+}
+
+// Stochastic minibatch iterations: the sampled segments' pass, then the dual
+// phase on the running sales totals (kept between iterations), dual step only.
+template <typename T>
+int minibatch_impl(cblp_instance* h, void* eta, const spfom_params* p, const int32_t* batch,
+                   int64_t B, int64_t iters, bool keep_trace, hipStream_t s)
+{
+    int rc;
+    if (!h->mb_S) {
+        const size_t qsz = sizeof(T) == 4 ? 4 : 8;
+        if ((rc = dalloc(&h->mb_yq, (size_t)std::max<int64_t>(h->nnz, 1) * qsz)) ||
+            (rc = dalloc(&h->mb_S, (size_t)h->n * 8)) ||
+            (rc = dalloc(&h->mb_inv, (size_t)std::max<int64_t>(h->L, 1) * 4)) ||
+            (rc = dalloc(&h->mb_stamp, (size_t)std::max<int64_t>(h->L, 1) * 4)) ||
+            (rc = dalloc(&h->mb_err, sizeof(unsigned))))
+            return rc;
+        HIP_TRY(launch_minibatch_init(h->L, h->perm, h->mb_inv, h->mb_stamp, s));
+        h->mb_clear = true;
+    }
+    if (h->mb_clear) {   // y^0 = 0
+        const size_t qsz = sizeof(T) == 4 ? 4 : 8;
+        HIP_TRY(hipMemsetAsync(h->mb_yq, 0, (size_t)h->nnz * qsz, s));
+        HIP_TRY(hipMemsetAsync(h->mb_S, 0, (size_t)h->n * 8, s));
+        h->mb_clear = false;
+    }
+    HIP_TRY(hipMemsetAsync(h->mb_err, 0, sizeof(unsigned), s));
+    HIP_TRY(launch_prices<T>(h->n, h->r, eta, h->a_ptr, h->a_idx, h->a_val, h->pnew, h->rho, s));
+    MbArgs a;
+    a.L = h->L;
+    a.B = B;
+    a.inv_perm = h->mb_inv;
+    a.ptr2 = h->ptr2;
+    a.idx2 = h->idx2;
+    a.v2 = h->v2;
+    a.den2 = h->den2;
+    a.vt0 = h->vt0;
+    a.lam = h->lam2;
+    a.Rwarm = h->Rwarm;
+    a.rho = h->rho;
+    a.fx_scale = h->fx_scale;
+    a.H = std::min(h->H, 8192);
+    a.S_run = h->mb_S;
+    a.yq = h->mb_yq;
+    a.wide = sizeof(T) == 8;
+    a.stamp = h->mb_stamp;
+    a.err = h->mb_err;
+    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((B + 31) / 32, 1024));
+    for (int64_t it = 0; it < iters; ++it) {
+        a.batch = batch + it * B;
+        a.it = h->mb_it;
+        h->mb_it = h->mb_it == INT32_MAX ? 0 : h->mb_it + 1;
+        HIP_TRY(launch_minibatch<T>(a, grid, s));
+        double* row = h->trace + (keep_trace ? it : 0) * SPFOM_NTRACE;
+        if ((rc = run_phase<T>(h, eta, p, 2, row, s))) return rc;
+        h->t += 1;
+    }
+    unsigned err = 0;
+    HIP_TRY(hipMemcpyAsync(&err, h->mb_err, sizeof(unsigned), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (err) {
+        h->mb_clear = true;
+        return fail(CBLP_EINVAL, (err & 1u) ? "batch holds a segment id outside [0, L)"
+                                            : "batch lists a segment twice in one iteration");
     }
     return CBLP_OK;
 }
@@ -360,6 +451,7 @@ int reset_state(cblp_instance* h, hipStream_t s)
     h->t0h = 0;
     h->psum_reset_next = true;
     h->pseg_window_ok = true;
+    h->mb_clear = true;   // the minibatch sales restart from 0
     return CBLP_OK;
 }
 
@@ -757,6 +849,31 @@ int spfom_iterate(cblp_t h, void* eta, const spfom_params* p, int64_t iters, dou
         rc = fill_stats(h, out, s, last);
         if (out) out->seconds = 0.0;
         return rc;
+    }
+    return CBLP_OK;
+}
+
+int spfom_minibatch(cblp_t h, void* eta, const spfom_params* p, const int32_t* batch, int64_t B,
+                    int64_t iters, double* trace, void* stream)
+{
+    g_err.clear();
+    if (!h || !eta || (!batch && iters > 0)) return fail(CBLP_EINVAL, "NULL handle, eta or batch");
+    if (iters < 0) return fail(CBLP_EINVAL, "iters < 0");
+    if (B < 1 || B > h->L) return fail(CBLP_EINVAL, "need 1 <= B <= L");
+    int rc = check_params(p);
+    if (rc) return rc;
+    if (p->rule != SPFOM_STEP_CONST || (p->tau_decay > 0.0 && p->tau_decay < 1.0))
+        return fail(CBLP_EINVAL, "minibatch iterations take the constant step");
+    if (iters == 0) return CBLP_OK;
+    hipStream_t s = S(stream);
+    if (trace && (rc = ensure_trace(h, iters))) return rc;
+    rc = h->dtype == CBLP_F32 ? minibatch_impl<float>(h, eta, p, batch, B, iters, trace != nullptr, s)
+                              : minibatch_impl<double>(h, eta, p, batch, B, iters, trace != nullptr, s);
+    if (rc) return rc;
+    if (trace) {
+        HIP_TRY(hipMemcpyAsync(trace, h->trace, iters * SPFOM_NTRACE * sizeof(double),
+                               hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
     }
     return CBLP_OK;
 }

@@ -76,9 +76,12 @@ struct SegArgs {
 
 struct PhaseArgs {
     int64_t n, m;
-    int mode;                      // 0: iterate, 1: evaluate at fixed eta
+    int mode;                      // 0: iterate, 1: evaluate at fixed eta, 2: minibatch
+                                   // iterate (dual step only, no certificate)
+    int keep_sales;                // the sales totals S_fx persist (minibatch running sums)
     int rule, check_every;
     double gamma, mu, tau_s;
+    double tau_mult;               // CONST: the step multiplier of this iteration (decay)
     const void* tau_vec;           // [m] nullable
     const double* zpart;
     int nz;
@@ -116,6 +119,35 @@ struct PhaseArgs {
     double* pseg_part;
     int pseg_blocks;
 };
+
+// Minibatch segment pass (minibatch.hip): re-solves the segments batch[0, B)
+// (caller ids) of iteration `it` over the row-major library copy and adds
+// each entry's change of sale to the running product totals S_run.
+struct MbArgs {
+    int64_t L, B;
+    int it;                        // iteration number (duplicate detection)
+    const int32_t* batch;          // [B] caller segment ids
+    const int32_t* inv_perm;       // [L] position of caller segment l
+    const int64_t* ptr2;           // [L+1] row pointers of the row-major copy
+    const int32_t* idx2;
+    const void* v2;
+    const void* den2;
+    const void* vt0;
+    const void* lam;
+    void* Rwarm;
+    const void* rho;
+    double fx_scale;
+    int H;                         // products [0, H) accumulate in LDS first
+    unsigned long long* S_run;     // [n] running totals (library ids)
+    void* yq;                      // [nnz] sales in quanta: uint32 (FP32) or uint64 (wide)
+    bool wide;
+    int* stamp;                    // [L] last iteration that sampled each segment
+    unsigned* err;                 // bit 0: id out of range, bit 1: id listed twice
+};
+template <typename T>
+hipError_t launch_minibatch(const MbArgs& a, int grid, hipStream_t s);
+hipError_t launch_minibatch_init(int64_t L, const int32_t* perm, int32_t* inv_perm, int* stamp,
+                                 hipStream_t s);
 
 // Launchers (one per kernel family), defined next to their kernels.
 template <typename T>

@@ -44,7 +44,7 @@ __global__ void __launch_bounds__(kFoldLite) k_fold_lite(PhaseArgs a)
     if (j < a.n) {
         const int64_t jq = a.pnew ? a.pnew[j] : j;   // library id of product j
         const unsigned long long tot = a.S_fx[jq];
-        a.S_fx[jq] = 0ull;
+        if (!a.keep_sales) a.S_fx[jq] = 0ull;
         const double sj = (double)(long long)tot * a.inv_fx;
         a.S_d[j] = sj;
         x[R_P] = (double)((const T*)a.r)[j] * sj;
@@ -82,7 +82,7 @@ __global__ void __launch_bounds__(kFoldLite) k_fold_step(PhaseArgs a)
         row_work<T>(a, j, sj, cnt1, x);
         T* eta = (T*)a.eta;
         const T* tauv = (const T*)a.tau_vec;
-        const double ti = 1.0 * (tauv ? (double)tauv[j] : a.tau_s);
+        const double ti = a.tau_mult * (tauv ? (double)tauv[j] : a.tau_s);
         double e = (double)eta[j];
         e = (1.0 - ti * a.mu) * e + ti * (sj - (double)((const T*)a.c)[j]);
         if (!(e > 0.0)) e = (e != e) ? e : 0.0;   // projection; NaN stays visible
@@ -126,7 +126,7 @@ __global__ void __launch_bounds__(kFoldLite) k_fold_step(PhaseArgs a)
     } else {
         th = 1.0;
     }
-    st.scale = 1.0;
+    st.scale = a.tau_mult;
     if (restart) {
         st.t0 = t1;
         st.cnt = 0;
@@ -142,7 +142,7 @@ __global__ void __launch_bounds__(kFoldLite) k_fold_step(PhaseArgs a)
     row[SPFOM_TR_DBEST] = st.dbest;
     row[SPFOM_TR_LB] = st.lb;
     row[SPFOM_TR_GAP] = (st.dbest - st.lb) / fmax(fabs(st.dbest), DBL_MIN);
-    row[SPFOM_TR_STEP] = 1.0;
+    row[SPFOM_TR_STEP] = a.tau_mult;
     row[SPFOM_TR_THETA] = th;
     a.st[a.par ^ 1] = st;
     *a.arrive = 0u;   // ready for the next launch
@@ -241,12 +241,17 @@ __global__ void __launch_bounds__(kRowThreads) k_update(PhaseArgs a)
     }
     block_reduce(x, sh);
     const double D = x[R_CETA] + x[R_Z];
-    const bool iter = a.mode == 0;
+    const bool iter = a.mode != 1;      // a dual step follows
+    const bool cert = a.mode == 0;      // full batch: dual bound and certificate
     double scale = 0.0;
     bool restart = false;
     DevState st = a.st[a.par];
     double th = x[R_TH];
-    if (iter) {
+    if (iter && !cert) {                // minibatch: the step only
+        st.t += 1;
+        scale = a.tau_mult;
+        st.scale = scale;
+    } else if (iter) {
         const long long t1 = st.t + 1, cnt1 = st.cnt + 1;
         st.t = t1;
         if (D < st.dbest) st.dbest = D;
@@ -263,7 +268,7 @@ __global__ void __launch_bounds__(kRowThreads) k_update(PhaseArgs a)
         } else {
             th = 1.0;
         }
-        scale = 1.0;
+        scale = a.tau_mult;
         if (a.rule == SPFOM_STEP_POLYAK) {
             const double ex = D - st.lb;
             scale = (x[R_G] > 0.0 && ex > 0.0) ? a.gamma * ex / x[R_G] : 0.0;
@@ -279,12 +284,16 @@ __global__ void __launch_bounds__(kRowThreads) k_update(PhaseArgs a)
     }
     if (blockIdx.x == 0 && tid == 0) {
         double* row = a.row;
-        row[SPFOM_TR_DUAL] = D;
+        row[SPFOM_TR_DUAL] = iter && !cert ? 0.0 : D;
         row[SPFOM_TR_PRIMAL] = x[R_P];
         row[SPFOM_TR_Z] = x[R_Z];
         row[SPFOM_TR_ETA2] = x[R_E2];
         row[SPFOM_TR_INFEAS] = rel_infeas(x);
-        if (iter) {
+        if (iter && !cert) {
+            for (int q = SPFOM_TR_DBEST; q < SPFOM_NTRACE; ++q) row[q] = 0.0;
+            row[SPFOM_TR_STEP] = scale;
+            a.st[a.par ^ 1] = st;
+        } else if (iter) {
             row[SPFOM_TR_DBEST] = st.dbest;
             row[SPFOM_TR_LB] = st.lb;
             row[SPFOM_TR_GAP] = (st.dbest - st.lb) / fmax(fabs(st.dbest), DBL_MIN);
@@ -349,7 +358,7 @@ hipError_t launch_phase(const PhaseArgs& a, bool identity, hipStream_t s)
         hipLaunchKernelGGL(k_rows<T>, dim3(row_grid), dim3(kRowThreads), 0, s, a);
         pseg();
         hipLaunchKernelGGL((k_update<T, false>), dim3(row_grid), dim3(kRowThreads), 0, s, a);
-        if (a.mode == 0) {
+        if (a.mode != 1) {   // a step was taken: rho = r - A^T eta
             const unsigned pg = (unsigned)((a.n + 255) / 256);
             hipLaunchKernelGGL(k_prices_after<T>, dim3(pg), dim3(256), 0, s, a.n,
                                (const T*)a.r, (const T*)a.eta, a.a_ptr, a.a_idx,

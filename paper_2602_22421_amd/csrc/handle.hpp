@@ -77,6 +77,15 @@ struct cblp_instance {
     // by position
     void* eval_thr = nullptr;
     void* eval_lamD = nullptr;
+    // stochastic minibatch state (allocated on first use): per-entry sales in
+    // quanta, running product totals, segment positions, sampling stamps
+    void* mb_yq = nullptr;
+    unsigned long long* mb_S = nullptr;
+    int32_t* mb_inv = nullptr;
+    int* mb_stamp = nullptr;
+    unsigned* mb_err = nullptr;
+    int mb_it = 0;                  // iterations run, for the stamps
+    bool mb_clear = true;           // the sales must be cleared before the next use
     int seg_grid = 1;
     int seg_variant = 0;
     int H = 0;
