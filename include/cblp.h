@@ -215,6 +215,28 @@ int cblp_sales(cblp_t h, const void* eta, double* S_out, double* u_out, void* se
                double* s_out, void* stream);
 
 /*
+ * cblp_recover - the choice-based LP solution behind per-entry sales
+ * (Section 4.4, the recovery lemma, in its GAM form).  y [dev] double [nnz]:
+ * sales s_lj in the caller's CSR order that satisfy each segment's SBLP rows
+ * (balance and scale) - a best response from cblp_sales, an average of
+ * several, or the kept sales of minibatch iterations.  Each segment's
+ * products are ordered by y_lj / v_lj, decreasing (ties by CSR position);
+ * the recovered solution offers only the nested sets S_q of the first q
+ * products, S_q a share of the time proportional to
+ * (key_q - key_{q+1}) (v_l0 + sum_{N_l} w + sum_{S_q} (v - w)), which
+ * reproduces y exactly.  (The lemma as printed leaves the no-purchase term
+ * out of this sum; it is needed for the sales to come out as y.)
+ * rank [dev] int32 [nnz]: position of each entry in its segment's order.
+ * alpha [dev] double [nnz]: probability of offering the set of the entries
+ *         ranked at or before this one.
+ * alpha0 [dev] double [L]: probability of offering nothing.
+ * A segment with lambda_l = 0 gets alpha 0 and alpha0 1.  Enqueued on the
+ * stream, no synchronisation.
+ */
+int cblp_recover(cblp_t h, const double* y, int32_t* rank, double* alpha, double* alpha0,
+                 void* stream);
+
+/*
  * cblp_launch_info - the launch shape chosen at cblp_create: number of
  * segment-kernel blocks, number of LDS sales bins per block (products
  * [0, bins) are accumulated in LDS), the fixed-point fraction bits of the

@@ -25,7 +25,7 @@ NTRACE = 10
 TRACE_COLS = ("D", "P", "Z", "eta2", "infeas", "dbest", "lb", "gap", "step", "theta")
 EXPORTS = ("cblp_create", "cblp_destroy", "spfom_reset", "spfom_iterate", "spfom_solve",
            "cblp_gap", "cblp_sales", "cblp_launch_info", "cblp_timing", "cblp_timing_read",
-           "spfom_minibatch",
+           "spfom_minibatch", "cblp_recover",
            "cblp_last_error", "cblp_batch_create", "cblp_batch_destroy", "spfom_batch_iterate",
            "spfom_batch_solve", "cblp_batch_tune", "cblp_batch_info", "cblp_batch_select",
            "wsnet_num_params", "wsnet_create", "wsnet_destroy", "wsnet_params", "wsnet_features",
@@ -80,6 +80,8 @@ def load(path: str = _LIB_PATH) -> ctypes.CDLL:
     lib.spfom_iterate.restype = ctypes.c_int
     lib.spfom_iterate.argtypes = [vp, vp, ctypes.POINTER(SpfomParams), i64, vp,
                                   ctypes.POINTER(SpfomStats), vp]
+    lib.cblp_recover.restype = ctypes.c_int
+    lib.cblp_recover.argtypes = [vp, vp, vp, vp, vp, vp]
     lib.spfom_minibatch.restype = ctypes.c_int
     lib.spfom_minibatch.argtypes = [vp, vp, ctypes.POINTER(SpfomParams), vp, i64, i64, vp, vp]
     lib.spfom_solve.restype = ctypes.c_int
@@ -237,6 +239,11 @@ SEG_KERNELS = ("f32-three-part-lds-prices", "f32-three-part-split-prices-ids16",
                "f32-three-part-split-prices-ids32", "f64-8-lane-ids16", "f64-8-lane-ids32")
 
 
+def cblp_recover(h, y, rank, alpha, alpha0, stream=None) -> None:
+    _check(load().cblp_recover(ctypes.c_void_p(h), _ptr(y), _ptr(rank), _ptr(alpha),
+                               _ptr(alpha0), _stream(stream)))
+
+
 def cblp_launch_info(h) -> dict:
     g, b, f, k = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
     e = ctypes.c_int64()
@@ -329,6 +336,16 @@ class Problem:
 
     def solve(self, eta: torch.Tensor, params: SpfomParams) -> SpfomStats:
         return spfom_solve(self.h, eta, params)
+
+    def recover(self, y: torch.Tensor):
+        """Nested assortments and their probabilities behind per-entry sales
+        y [nnz] (float64 device tensor): (rank, alpha, alpha0)."""
+        assert y.dtype == torch.float64 and y.numel() == self.nnz
+        rank = torch.empty(self.nnz, dtype=torch.int32, device=self.device)
+        alpha = torch.empty(self.nnz, dtype=torch.float64, device=self.device)
+        alpha0 = torch.empty(self.L, dtype=torch.float64, device=self.device)
+        cblp_recover(self.h, y.contiguous(), rank, alpha, alpha0)
+        return rank, alpha, alpha0
 
     def minibatch(self, eta: torch.Tensor, batch, params: SpfomParams, trace: bool = True):
         """Stochastic minibatch iterations over the rows of batch ([iters, B]
