@@ -405,6 +405,35 @@ int wsnet_predict(wsnet_t w, cblp_t h, void* eta, void* stream);
 int wsnet_start(wsnet_t w, cblp_t h, void* eta, int32_t* used, double* d_pred, double* d_zero,
                 void* stream);
 
+/* ------------------------------------------------------ without allocation
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.
+ *
+ * cblp_gap_static - cblp_gap and cblp_sales' product sales for an instance
+ * given by its arrays (cblp_create's arguments and their rules) instead of a
+ * handle: one best-response pass at eta [dev] [m].  Allocates nothing: every
+ * intermediate (prices, 64-bit sales sums, partial sums) lives in a static
+ * 8 MiB device array of the library, one per GPU, found once per device.
+ * S_out [dev] double [n] nullable: product sales S_j (the same bits as
+ *         cblp_sales' S for the same instance and eta).
+ * bounds [dev] double [2]: D(eta) = c . eta + sum_l lambda_l R*_l and
+ *         P = r . S; NaN when the data break cblp_create's index rules or
+ *         the arrival rates are too large for the fixed-point sums (the
+ *         call itself does not validate them otherwise).
+ * CBLP_EINVAL when n or m exceeds cblp_gap_static_max_products() (about
+ * 490,000) or an argument is NULL.  Enqueued on the stream; no
+ * synchronisation, no copy to the host, no memset (capturable).  Calls on
+ * one GPU share the static array: calls that overlap on one GPU (different
+ * streams or threads) race and must be ordered by the caller. */
+int cblp_gap_static(int64_t L, int64_t n, int64_t m, const int64_t* seg_ptr,
+                    const int32_t* prod_idx, const void* v, const void* w, const void* v0,
+                    const void* lambda, const void* r, const int64_t* a_ptr,
+                    const int32_t* a_idx, const void* a_val, const void* c, int32_t dtype,
+                    const void* eta, double* S_out, double* bounds, void* stream);
+
+/* The largest n (and m) cblp_gap_static accepts. */
+int64_t cblp_gap_static_max_products(void);
+
 /* Describe the last failure on this thread ("" if none). */
 const char* cblp_last_error(void);
 

@@ -25,7 +25,7 @@ NTRACE = 10
 TRACE_COLS = ("D", "P", "Z", "eta2", "infeas", "dbest", "lb", "gap", "step", "theta")
 EXPORTS = ("cblp_create", "cblp_destroy", "spfom_reset", "spfom_iterate", "spfom_solve",
            "cblp_gap", "cblp_sales", "cblp_launch_info", "cblp_timing", "cblp_timing_read",
-           "spfom_minibatch", "cblp_recover",
+           "spfom_minibatch", "cblp_recover", "cblp_gap_static", "cblp_gap_static_max_products",
            "cblp_last_error", "cblp_batch_create", "cblp_batch_destroy", "spfom_batch_iterate",
            "spfom_batch_solve", "cblp_batch_tune", "cblp_batch_info", "cblp_batch_select",
            "wsnet_num_params", "wsnet_create", "wsnet_destroy", "wsnet_params", "wsnet_features",
@@ -80,6 +80,11 @@ def load(path: str = _LIB_PATH) -> ctypes.CDLL:
     lib.spfom_iterate.restype = ctypes.c_int
     lib.spfom_iterate.argtypes = [vp, vp, ctypes.POINTER(SpfomParams), i64, vp,
                                   ctypes.POINTER(SpfomStats), vp]
+    lib.cblp_gap_static.restype = ctypes.c_int
+    lib.cblp_gap_static.argtypes = [i64, i64, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, i32,
+                                    vp, vp, vp, vp]
+    lib.cblp_gap_static_max_products.restype = i64
+    lib.cblp_gap_static_max_products.argtypes = []
     lib.cblp_recover.restype = ctypes.c_int
     lib.cblp_recover.argtypes = [vp, vp, vp, vp, vp, vp]
     lib.spfom_minibatch.restype = ctypes.c_int
@@ -237,6 +242,20 @@ def cblp_sales(h, eta, S_out=None, u_out=None, seg_R_out=None, s_out=None, strea
 
 SEG_KERNELS = ("f32-three-part-lds-prices", "f32-three-part-split-prices-ids16",
                "f32-three-part-split-prices-ids32", "f64-8-lane-ids16", "f64-8-lane-ids32")
+
+
+def cblp_gap_static(prob: "Problem", eta, S_out, bounds, stream=None) -> None:
+    """The allocation-free pass over prob's device arrays (not its handle)."""
+    _check(load().cblp_gap_static(prob.L, prob.n, prob.m, _ptr(prob.seg_ptr), _ptr(prob.idx),
+                                  _ptr(prob.v), _ptr(prob.w), _ptr(prob.v0), _ptr(prob.lam),
+                                  _ptr(prob.r), _ptr(prob.a_ptr), _ptr(prob.a_idx),
+                                  _ptr(prob.a_val), _ptr(prob.c),
+                                  CBLP_F32 if prob.dtype == torch.float32 else CBLP_F64,
+                                  _ptr(eta), _ptr(S_out), _ptr(bounds), _stream(stream)))
+
+
+def cblp_gap_static_max_products() -> int:
+    return int(load().cblp_gap_static_max_products())
 
 
 def cblp_recover(h, y, rank, alpha, alpha0, stream=None) -> None:
