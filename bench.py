@@ -141,6 +141,91 @@ def cpu_baseline_all_cores(inst, tau, reps, workers):
             "cpu_model": cpu_model(), "nproc": os.cpu_count()}
 
 
+GAP_LEVELS = (1e-1, 3e-2, 1e-2, 3e-3, 1e-3, 3e-4, 1e-4)
+
+
+def _run_to_levels(cblp, prob, eta, params, iters, chunk, t_start=0.0):
+    """Iterate `iters` times from eta in chunks, recording the wall time of
+    each chunk; returns (time and iterations to each certified gap level,
+    final trace row, seconds per iteration).  The gap is read at the checks
+    (every check_every iterations); a level's time is the chunk's start plus
+    its share of the chunk up to that check."""
+    import torch
+    K = int(params.check_every)
+    reach = {f"{lv:g}": None for lv in GAP_LEVELS}
+    t = 0
+    wall = t_start
+    last = None
+    while t < iters:
+        n = min(chunk, iters - t)
+        tr = np.zeros((n, cblp.NTRACE))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        cblp.spfom_iterate(prob.h, eta, params, n, tr)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        for k in range(n):
+            tt = t + k + 1
+            if tt % K:
+                continue
+            for lv in GAP_LEVELS:
+                key = f"{lv:g}"
+                if reach[key] is None and tr[k, 7] <= lv:
+                    reach[key] = {"iters": tt, "seconds": wall + dt * (k + 1) / n}
+        wall += dt
+        t += n
+        last = tr[-1]
+    return reach, last, (wall - t_start) / max(iters, 1)
+
+
+def _schedule_params(cblp, prob, inst, args, tau0=None):
+    from paper_2602_22421_amd.instances import step_scale
+    npdt = np.float32 if prob.dtype.itemsize == 4 else np.float64
+    tau = prob.tensor(step_scale(inst, args.tau0 if tau0 is None else tau0).astype(npdt))
+    return cblp.make_params(rule=cblp.SPFOM_STEP_CONST, tau_vec=tau, check_every=10,
+                            bound=cblp.SPFOM_BOUND_SEGMENT if args.bound == "segment"
+                            else cblp.SPFOM_BOUND_GLOBAL,
+                            tau_decay=args.tau_decay, decay_every=args.decay_every)
+
+
+def time_to_gap(args):
+    """Plain cold-start SPFOM on the L=2e6 workload: wall time and iterations
+    to each certified relative gap level (the dual bound Dbest against the
+    scaled averaged-primal bound), with the decaying constant step."""
+    import torch
+    from paper_2602_22421_amd import cblp
+    from paper_2602_22421_amd.instances import CONFIG_NAMES, config_instance
+    inst = config_instance(args.config).cast(np.float32)
+    prob = cblp.Problem(inst, dtype=torch.float32)
+    out_runs = []
+    for bound in args.bounds:
+        args.bound = bound
+        params = _schedule_params(cblp, prob, inst, args)
+        prob.reset()
+        eta = prob.zeros_eta()
+        reach, last, per = _run_to_levels(cblp, prob, eta, params, args.max_iters, 1000)
+        log(f"bound {bound}: final gap {last[7]:.3e} after {args.max_iters} iterations, "
+            f"{per * 1e3:.3f} ms/iteration; levels {reach}")
+        out_runs.append({"bound": bound, "reach": reach, "final_gap": float(last[7]),
+                         "dbest": float(last[5]), "lb": float(last[6]),
+                         "ms_per_iter": per * 1e3})
+    best = min(out_runs, key=lambda r: r["final_gap"])
+    lv = f"{args.gap:g}"
+    out = {
+        "metric": f"time to certified gap {args.gap:g}, plain cold start", "unit": "s",
+        "value": best["reach"][lv]["seconds"] if best["reach"].get(lv) else None,
+        "higher_is_better": False, "n_gpus": 1, "dtype": "f32", "data": "synthetic",
+        "vs_baseline": None,
+        "config": {"workload": CONFIG_NAMES[args.config], "L": inst.L, "n": inst.n,
+                   "nnz": inst.nnz, "step_rule": "const", "tau0": args.tau0,
+                   "tau_decay": args.tau_decay, "decay_every": args.decay_every,
+                   "check_every": 10, "max_iters": args.max_iters},
+        "tightest_gap": best["final_gap"], "runs": out_runs,
+    }
+    print(json.dumps(out), flush=True)
+    prob.close()
+
+
 def batched(args):
     """Time for every instance of a multi-period batch to reach the certified
     gap (or the iteration cap): one batch against the same instances solved
@@ -372,8 +457,16 @@ def main():
                     help="about how long the single-threaded oracle leg runs (whole iterations "
                          "over the whole instance, at least one)")
     ap.add_argument("--time-to-gap", action="store_true",
-                    help="wall time and iterations to each certified gap level: cold, warm "
-                         "and batched solves against plain cold ones")
+                    help="plain cold start: wall time and iterations to each certified gap "
+                         "level (with --warmstart / --batched for the other starts)")
+    ap.add_argument("--tau0", type=float, default=3e-3,
+                    help="step scale: tau_i = tau0 max_j r_j / c_i")
+    ap.add_argument("--tau-decay", type=float, default=0.7)
+    ap.add_argument("--decay-every", type=int, default=1000)
+    ap.add_argument("--bounds", nargs="+", default=["global", "segment"],
+                    choices=["global", "segment"])
+    ap.add_argument("--gap", type=float, default=1e-3,
+                    help="the level whose time is the line's value")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device-to-device copy: the reference kernel whose "
                          "FETCH_SIZE / WRITE_SIZE counters scale the traffic figures")
@@ -394,6 +487,8 @@ def main():
         if args.batched:
             return batched(args)
         if args.time_to_gap:
+            if "--max-iters" not in sys.argv:
+                args.max_iters = 20000
             return time_to_gap(args)
         if args.warmstart:
             if args.max_iters == 2000 and "--max-iters" not in sys.argv:
