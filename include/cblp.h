@@ -291,7 +291,9 @@ int spfom_batch_iterate(cblp_batch_t b, void* const* etas, const void* const* ta
  * and replayed; converged instances drop out of the work list.  As in
  * spfom_solve, the last block is cut to the iterations left below max_iters
  * (run without the graph), and the gap is tested only after a whole block of
- * check_every iterations.  p->bound must be SPFOM_BOUND_GLOBAL.  outs [host]
+ * check_every iterations.  p->bound must be SPFOM_BOUND_GLOBAL; the constant
+ * step may decay (p->tau_decay, p->decay_every) as in spfom_iterate, by each
+ * instance's own iteration count.  outs [host]
  * [count] receives each instance's iterations, last trace row, elapsed
  * seconds and status.  Returns CBLP_OK if every instance converged. */
 int spfom_batch_solve(cblp_batch_t b, void* const* etas, const void* const* tau_vecs,

@@ -85,6 +85,8 @@ struct BArgs {
     double* bpart;             // [fold blocks][8]
     int rule, check_every;
     double gamma, mu;
+    double tau_decay;          // CONST: step tau * tau_decay^k in iterations kE+1..(k+1)E
+    long long decay_every;     // E
 };
 
 // the fields row_work reads, for one instance
@@ -269,6 +271,11 @@ __global__ void __launch_bounds__(kRowThreads) k_bupdate(BArgs b)
     if (b.rule == SPFOM_STEP_POLYAK) {
         const double ex = D - st.lb;
         scale = (x[R_G] > 0.0 && ex > 0.0) ? b.gamma * ex / x[R_G] : 0.0;
+    } else if (b.tau_decay > 0.0 && b.tau_decay < 1.0) {
+        // the decaying constant step: tau_decay^k, k = (t - 1) / E, by
+        // repeated FP64 products as the single-instance path forms it
+        const long long k = (t1 - 1) / b.decay_every;
+        for (long long q = 0; q < k; ++q) scale *= b.tau_decay;
     }
     st.scale = scale;
     bool restart = false;
@@ -384,6 +391,7 @@ struct cblp_batch {
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
     hipGraphExec_t exec = nullptr;
     int graph_K = 0;
+    spfom_params graph_p{};          // the step parameters the graph was captured with
     std::vector<int64_t> t;          // per-instance iteration counts
 };
 
@@ -434,6 +442,10 @@ int check_bparams(const spfom_params* p)
         return bfail(CBLP_EINVAL, "gamma must be in (0, 2]");
     if (p->bound != SPFOM_BOUND_GLOBAL)
         return bfail(CBLP_EINVAL, "batches certify with the global bound only");
+    if (!(p->tau_decay >= 0.0 && p->tau_decay <= 1.0))
+        return bfail(CBLP_EINVAL, "tau_decay must be in [0, 1]");
+    if (p->tau_decay > 0.0 && p->tau_decay < 1.0 && p->decay_every < 1)
+        return bfail(CBLP_EINVAL, "decay_every must be >= 1");
     return CBLP_OK;
 }
 
@@ -484,6 +496,8 @@ int enqueue_iterations(cblp_batch* b, const spfom_params* p, int64_t iters, hipS
     a.check_every = p->check_every;
     a.gamma = p->gamma;
     a.mu = p->mu;
+    a.tau_decay = p->tau_decay;
+    a.decay_every = p->decay_every;
     const size_t lds = bseg_lds(b, b->variant);
     const void* segf = bseg_fn<T>(b->variant);
     for (int64_t it = 0; it < iters; ++it) {
@@ -556,7 +570,12 @@ bool bseg_usable(const cblp_batch* b, int variant)
 
 int ensure_graph(cblp_batch* b, const spfom_params* p)
 {
-    if (b->exec && b->graph_K == p->check_every) return CBLP_OK;
+    // the kernels' arguments hold the step rule's scalars: a graph serves only
+    // the parameters it was captured with
+    const spfom_params& g0 = b->graph_p;
+    if (b->exec && b->graph_K == p->check_every && g0.rule == p->rule && g0.gamma == p->gamma &&
+        g0.mu == p->mu && g0.tau_decay == p->tau_decay && g0.decay_every == p->decay_every)
+        return CBLP_OK;
     if (b->exec) {
         (void)hipGraphExecDestroy(b->exec);
         b->exec = nullptr;
@@ -574,6 +593,7 @@ int ensure_graph(cblp_batch* b, const spfom_params* p)
     (void)hipGraphDestroy(g);
     if (e != hipSuccess) return bfail(CBLP_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
     b->graph_K = p->check_every;
+    b->graph_p = *p;
     return CBLP_OK;
 }
 

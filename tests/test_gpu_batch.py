@@ -114,6 +114,56 @@ def test_batch_graph_replays_match_eager(cb):
     b2.close()
 
 
+def test_batch_decaying_step_matches_single(cb):
+    """The decaying constant step in a batch: each instance's duals equal its
+    own spfom_iterate bit for bit (the same multiplier tau_decay^k, formed by
+    repeated products, on exact integer sales sums)."""
+    base = [batch_instance(b, scale=0.004) for b in range(4)]
+    dt = torch.float32
+    _, singles, taus = _setup(cb, base, dt, tau0=0.004)
+    iters = 23
+    ref, steps = [], []
+    for p, t in zip(singles, taus):
+        params = cb.make_params(rule=0, tau_vec=t, check_every=5, tau_decay=0.5, decay_every=7)
+        eta = p.zeros_eta()
+        tr, _ = p.iterate(eta, iters, params)
+        ref.append(eta.cpu().numpy())
+        steps.append(tr[:, 8])
+    np.testing.assert_array_equal(steps[0][[0, 6, 7, 13, 14, 22]], [1, 1, 0.5, 0.5, 0.25, 0.125])
+    _, probs, taus2 = _setup(cb, base, dt, tau0=0.004)
+    batch = cb.Batch(probs)
+    etas = [p.zeros_eta() for p in probs]
+    params = cb.make_params(rule=0, tau=1.0, check_every=5, tau_decay=0.5, decay_every=7)
+    rows = batch.iterate(etas, iters, params, tau_vecs=taus2)
+    for q in range(len(base)):
+        assert np.array_equal(etas[q].cpu().numpy(), ref[q]), q
+        assert rows[q, 8] == 0.125
+    batch.close()
+
+
+def test_batch_graph_follows_step_parameters(cb):
+    """A solve whose step parameters differ from the previous solve's (same
+    check_every) captures a new graph: its duals equal eager iterations with
+    the new parameters."""
+    base = [batch_instance(b, scale=0.004) for b in range(3)]
+    _, p1, t1 = _setup(cb, base, torch.float32, tau0=0.004)
+    b1 = cb.Batch(p1)
+    plain = cb.make_params(rule=0, tau=1.0, check_every=10, tol=0.0, max_iters=20)
+    b1.solve([p.zeros_eta() for p in p1], plain, tau_vecs=t1)
+    decay = cb.make_params(rule=0, tau=1.0, check_every=10, tol=0.0, max_iters=30,
+                           tau_decay=0.5, decay_every=4)
+    e1 = [p.zeros_eta() for p in p1]
+    b1.solve(e1, decay, tau_vecs=t1)
+    _, p2, t2 = _setup(cb, base, torch.float32, tau0=0.004)
+    b2 = cb.Batch(p2)
+    e2 = [p.zeros_eta() for p in p2]
+    b2.iterate(e2, 30, decay, tau_vecs=t2)
+    for q in range(len(base)):
+        assert np.array_equal(e1[q].cpu().numpy(), e2[q].cpu().numpy()), q
+    b1.close()
+    b2.close()
+
+
 def test_batch_tune_picks_a_variant(cb):
     base = [batch_instance(b, scale=0.004) for b in range(3)]
     insts, probs, taus = _setup(cb, base, torch.float32, tau0=0.001)
