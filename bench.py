@@ -298,6 +298,95 @@ def batched(args):
         p.close()
 
 
+def minibatch_bench(args):
+    """Stochastic minibatch SPFOM on the L=2e6 workload: each iteration
+    re-solves B sampled segments (an epoch walk through random permutations)
+    and steps the duals with the kept sales of all segments.  Reports
+    sampled-segment updates per second for each B."""
+    import torch
+    from paper_2602_22421_amd import cblp
+    from paper_2602_22421_amd.instances import config_instance, minibatch_schedule, step_scale
+    inst = config_instance(args.config).cast(np.float32)
+    prob = cblp.Problem(inst, dtype=torch.float32)
+    tau = prob.tensor(step_scale(inst, args.tau0).astype(np.float32))
+    params = cblp.make_params(rule=cblp.SPFOM_STEP_CONST, tau_vec=tau, check_every=10)
+    runs = []
+    for frac in args.mb_fracs:
+        B = max(1, int(round(inst.L * float(frac))))
+        iters = args.steps
+        sched = torch.from_numpy(minibatch_schedule(inst.L, B, args.warmup + iters, seed=7,
+                                                    mode="epoch")).to(prob.device)
+        prob.reset()
+        eta = prob.zeros_eta()
+        warm = sched[:args.warmup].contiguous()
+        cblp.spfom_minibatch(prob.h, eta, params, warm, args.warmup)
+        timed = sched[args.warmup:].contiguous()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        cblp.spfom_minibatch(prob.h, eta, params, timed, iters)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / iters
+        gap = prob.gap(eta)
+        run = {"B": B, "fraction": float(frac), "ms_per_iter": dt * 1e3,
+               "sampled_segment_updates_per_s": B / dt,
+               "D_after": gap["D"], "iters": iters, "warmup": args.warmup}
+        log(f"minibatch B={B}: {dt * 1e3:.3f} ms/iteration, {B / dt:.3e} segment-updates/s, "
+            f"D {gap['D']:.6e}")
+        runs.append(run)
+    out = {"metric": "sampled segment-updates/s, stochastic minibatch SPFOM",
+           "value": runs[0]["sampled_segment_updates_per_s"], "unit": "segment-updates/s",
+           "higher_is_better": True, "n_gpus": 1, "dtype": "f32", "data": "synthetic",
+           "vs_baseline": None,
+           "config": {"workload": "plain-L2e6-n2e4-zipf-identity", "L": inst.L, "n": inst.n,
+                      "nnz": inst.nnz, "sampler": "epoch permutations", "step_rule": "const",
+                      "tau0": args.tau0},
+           "runs": runs}
+    print(json.dumps(out), flush=True)
+    prob.close()
+
+
+def recover_bench(args):
+    """SBLP -> CBLP recovery on the L=2e6 workload: nested assortments and
+    their probabilities from the per-entry sales of one best-response pass."""
+    import torch
+    from paper_2602_22421_amd import cblp
+    from paper_2602_22421_amd.instances import config_instance, step_scale
+    inst = config_instance(args.config).cast(np.float32)
+    prob = cblp.Problem(inst, dtype=torch.float32)
+    tau = prob.tensor(step_scale(inst, args.tau0).astype(np.float32))
+    params = cblp.make_params(rule=cblp.SPFOM_STEP_CONST, tau_vec=tau, check_every=10)
+    eta = prob.zeros_eta()
+    prob.iterate(eta, 50, params)
+    _, _, _, y = prob.sales(eta, entries=True)
+    rank = torch.empty(inst.nnz, dtype=torch.int32, device=prob.device)
+    alpha = torch.empty(inst.nnz, dtype=torch.float64, device=prob.device)
+    alpha0 = torch.empty(inst.L, dtype=torch.float64, device=prob.device)
+    for _ in range(3):
+        cblp.cblp_recover(prob.h, y, rank, alpha, alpha0)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    reps = 20
+    ev[0].record()
+    for _ in range(reps):
+        cblp.cblp_recover(prob.h, y, rank, alpha, alpha0)
+    ev[1].record()
+    torch.cuda.synchronize()
+    us = ev[0].elapsed_time(ev[1]) * 1e3 / reps
+    # bytes the recovery must move: y 8, v 4, w 4 in; rank 4, alpha 8 out per
+    # entry; row pointer 8, v0 4, lambda 4 in, alpha0 8 out per segment
+    nbytes = 28 * inst.nnz + 24 * inst.L
+    log(f"recover: {us:.1f} us/call, {nbytes / us / 1e3:.0f} GB/s of {nbytes / 1e6:.1f} MB")
+    out = {"metric": "SBLP to CBLP recovery time", "value": us, "unit": "us",
+           "higher_is_better": False, "n_gpus": 1, "dtype": "f64", "data": "synthetic",
+           "vs_baseline": None,
+           "config": {"workload": "plain-L2e6-n2e4-zipf-identity", "L": inst.L, "n": inst.n,
+                      "nnz": inst.nnz, "sales": "best response after 50 iterations"},
+           "roofline": {"bound": "hbm", "achieved": nbytes / us / 1e3, "peak": 8000.0,
+                        "unit": "GB/s", "frac": nbytes / us / 1e3 / 8000.0,
+                        "bytes_per_call": nbytes}}
+    print(json.dumps(out), flush=True)
+    prob.close()
+
+
 def warmstart_bench(args):
     """Learned warm start: train the network on the duals of solved L=1e5
     instances of the L=2e6 Zipf generator, then solve held-out L=2e6 instances
@@ -440,6 +529,12 @@ def main():
     ap.add_argument("--batch-scale", type=float, default=1.0,
                     help="scales every instance's segment count (1.0: L log-uniform in [1e3, 1e6])")
     ap.add_argument("--tol", type=float, default=2e-2)
+    ap.add_argument("--minibatch", action="store_true",
+                    help="stochastic minibatch SPFOM: sampled segment-updates/s per B")
+    ap.add_argument("--mb-fracs", nargs="+", default=["0.1", "0.01"],
+                    help="minibatch mode: B as fractions of L")
+    ap.add_argument("--recover", action="store_true",
+                    help="time the SBLP -> CBLP recovery of one pass's sales")
     ap.add_argument("--levels", nargs="+", default=["1e-2", "3e-3", "1e-3"],
                     help="batched mode: the certified gap levels timed")
     ap.add_argument("--max-iters", type=int, default=2000)
@@ -479,7 +574,8 @@ def main():
               f"(the multi-GPU sharding is a design, not a build)", file=sys.stderr)
         sys.exit(2)
 
-    if args.batched or args.warmstart or args.copy_calibration or args.time_to_gap:
+    if (args.batched or args.warmstart or args.copy_calibration or args.time_to_gap
+            or args.minibatch or args.recover):
         import torch
         from paper_2602_22421_amd import cblp
         cblp.load()
@@ -489,6 +585,10 @@ def main():
         torch.cuda.set_device(0)
         if args.batched:
             return batched(args)
+        if args.minibatch:
+            return minibatch_bench(args)
+        if args.recover:
+            return recover_bench(args)
         if args.time_to_gap:
             if "--max-iters" not in sys.argv:
                 args.max_iters = 20000
