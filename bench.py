@@ -43,7 +43,8 @@ def algorithmic_bytes(inst, esz):
                                                             per_prod=per_prod)
 
 
-PROFILE_OF = {"plain-L2e6-n2e4-zipf-identity": "k_segments-plain-L2e6-n2e4.md"}
+PROFILE_OF = {"plain-L2e6-n2e4-zipf-identity": "k_segments-plain-L2e6-n2e4.md",
+              "plain-L1e7-n1e5-m2e3-zipf-resources": "k_segments-plain-L1e7-n1e5-m2e3.md"}
 # the segment kernel's sources; the profile records their hash
 PROFILE_SOURCES = ("segment.hip", "segment_core.hpp", "common.hpp")
 
