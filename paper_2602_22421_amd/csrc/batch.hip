@@ -51,6 +51,7 @@ struct BInst {
     double tau_s;
     unsigned long long* S_fx;
     double inv_fx;
+    double inv_z;              // 1 / the Z fixed-point scale
     double* S_d;
     double* u_d;
     double* sum_u;
@@ -81,7 +82,7 @@ struct BArgs {
     const BChunk* fold;
     const BChunk* rows;
     const unsigned long long* part_S;
-    const double* zpart;
+    const long long* zpart;    // fixed-point Z partials per item
     double* bpart;             // [fold blocks][8]
     int rule, check_every;
     double gamma, mu;
@@ -112,10 +113,10 @@ __global__ void k_reset_counter(unsigned* counter) { *counter = 0u; }
 template <typename T, int J, int DEPTH, int MODE, typename IdxT = int32_t>
 __global__ void __launch_bounds__(kSegThreads)
 k_bsegments(const BInst* inst, const BItem* items, int nitems, unsigned* counter,
-            unsigned long long* part_S, double* zpart, int Hmax)
+            unsigned long long* part_S, long long* zpart, int Hmax)
 {
     extern __shared__ unsigned long long bins[];
-    __shared__ double zsh[kSegThreads / 64];
+    __shared__ long long zsh[kSegThreads / 64];
     __shared__ int s_item;
     T* lprice = (T*)(bins + Hmax);
     for (;;) {
@@ -134,7 +135,7 @@ k_bsegments(const BInst* inst, const BItem* items, int nitems, unsigned* counter
         if (MODE > 0)
             for (int64_t j = threadIdx.x; j < a.n; j += kSegThreads) lprice[j] = ((const T*)a.rho)[j];
         __syncthreads();
-        double zacc = 0.0;
+        ZAcc zacc;
         const seg::FlatPrices<T> pr{MODE > 0 ? (const T*)lprice : (const T*)a.rho};
         const int64_t t0 = w.p0 / kSegsPerTile, t1 = (w.p1 + kSegsPerTile - 1) / kSegsPerTile;
         if constexpr (MODE == 3) {
@@ -164,14 +165,8 @@ k_bsegments(const BInst* inst, const BItem* items, int nitems, unsigned* counter
         __syncthreads();
         unsigned long long* out = part_S + I->part_off + (size_t)(it - I->item0) * (size_t)H;
         for (int j = threadIdx.x; j < H; j += kSegThreads) out[j] = bins[j];
-        for (int o = 32; o > 0; o >>= 1) zacc += __shfl_down(zacc, o, 64);
-        if ((threadIdx.x & 63) == 0) zsh[threadIdx.x >> 6] = zacc;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            double z = zsh[0];
-            for (int q = 1; q < kSegThreads / 64; ++q) z += zsh[q];
-            zpart[it] = z;
-        }
+        const long long z = block_z(zacc, zsh);
+        if (threadIdx.x == 0) zpart[it] = z;
     }
 }
 
@@ -240,18 +235,31 @@ __global__ void __launch_bounds__(kRowThreads) k_bupdate(BArgs b)
     const int tid = threadIdx.x;
     double x[NR];
     clear(x);
-    for (int q = I->item0 + tid; q < I->item1; q += kRowThreads) x[R_Z] += b.zpart[q];
-    for (int q = I->fold0 + tid; q < I->fold1; q += kRowThreads) {
-        const double* p = b.bpart + (size_t)q * 8;
-        x[R_P] += p[R_P];
-        x[R_CETA] += p[R_CETA];
-        x[R_INF] += p[R_INF];
-        x[R_G] += p[R_G];
-        x[R_TH] = fmin(x[R_TH], p[R_TH]);
-        x[R_E2] += p[R_E2];
-        x[R_CS] += p[R_CS];
+    __shared__ long long zsh[kRowThreads / 64];
+    const double Zd = fold_z(b.zpart, I->item0, I->item1, I->inv_z, zsh);
+    // The partials of 64 products are combined four at a time in order, which
+    // gives the single-instance fold's 256-product block partials bit for bit
+    // (a block of 256 products adds its four waves' sums in that order); the
+    // rest of the fold is the single instance's too, so both paths certify
+    // the same gaps.
+    const int nf = I->fold1 - I->fold0;
+    for (int g = tid; g < (nf + 3) / 4; g += kRowThreads) {
+        double y[NR];
+        clear(y);
+        for (int k = 0; k < 4; ++k) {
+            const int q = 4 * g + k;
+            double p[NR];
+            clear(p);   // past the instance's last product: the values of empty waves
+            if (q < nf)
+                for (int r = 0; r < NR; ++r)
+                    if (r != R_Z) p[r] = b.bpart[(size_t)(I->fold0 + q) * 8 + r];
+            for (int r = 0; r < NR; ++r)
+                y[r] = k == 0 ? p[r] : r == R_TH ? fmin(y[r], p[r]) : y[r] + p[r];
+        }
+        for (int r = 0; r < NR; ++r) x[r] = r == R_TH ? fmin(x[r], y[r]) : x[r] + y[r];
     }
     block_reduce(x, sh);
+    x[R_Z] = Zd;   // the fixed-point sum, not the FP64 tree
     const double D = x[R_CETA] + x[R_Z];
     const int cur = current(I->st);
     DevState st = I->st[cur];
@@ -375,7 +383,7 @@ struct cblp_batch {
     BChunk* d_rows = nullptr;
     int nrows = 0;
     unsigned long long* part_S = nullptr;
-    double* zpart = nullptr;
+    long long* zpart = nullptr;
     double* bpart = nullptr;
     DevState* st = nullptr;
     double* rows = nullptr;
@@ -700,6 +708,8 @@ int cblp_batch_create(cblp_batch_t* out, int32_t count, const cblp_t* handles, v
         a.S_fx = h->S_fx;
         a.fx_scale = h->fx_scale;
         a.zpart = nullptr;
+        a.z_scale = h->z_scale;
+        a.z_rmax = h->z_rmax;
         a.seg_R = nullptr;
         I.n = h->n;
         I.m = h->m;
@@ -708,6 +718,7 @@ int cblp_batch_create(cblp_batch_t* out, int32_t count, const cblp_t* handles, v
         I.rho = h->rho;
         I.S_fx = h->S_fx;
         I.inv_fx = 1.0 / h->fx_scale;
+        I.inv_z = 1.0 / h->z_scale;
         I.S_d = h->S_d;
         I.u_d = h->u_d;
         I.sum_u = h->sum_u;

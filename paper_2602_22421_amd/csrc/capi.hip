@@ -211,6 +211,8 @@ int run_segments(cblp_instance* h, void* seg_R, bool pseg, bool eval_out, hipStr
     a.S_fx = h->S_fx;
     a.fx_scale = h->fx_scale;
     a.zpart = h->zpart;
+    a.z_scale = h->z_scale;
+    a.z_rmax = h->z_rmax;
     a.seg_R = seg_R;
     a.seg_thr = eval_out ? h->eval_thr : nullptr;
     a.seg_lamD = eval_out ? h->eval_lamD : nullptr;
@@ -268,6 +270,7 @@ int run_phase(cblp_instance* h, void* eta, const spfom_params* p, int mode, doub
     a.tau_mult = tau_multiplier(p, h->t + 1);
     a.tau_vec = p ? p->tau_vec : nullptr;
     a.zpart = h->zpart;
+    a.inv_z = 1.0 / h->z_scale;
     a.nz = h->seg_grid;
     a.S_fx = h->S_fx;
     a.inv_fx = 1.0 / h->fx_scale;
@@ -735,6 +738,22 @@ int create_impl(cblp_instance* h, hipStream_t s)
     if (h->dtype == CBLP_F32) bits = std::min(bits, 30 - e_hi);
     if (bits < 8) return fail(CBLP_EINVAL, "arrival rates too large for the fixed-point sales sums");
     h->fx_scale = std::ldexp(1.0, bits);
+
+    // fixed-point scale of Z = sum lambda R*: with duals >= 0, R* <= max r, so
+    // sum lambda max(r) (1 + 2^-20) 2^zb stays below 2^60
+    {
+        std::vector<T> hr((size_t)h->n);
+        HIP_TRY(hipMemcpyAsync(hr.data(), h->r, (size_t)h->n * sizeof(T), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        double rmax = 0.0;
+        for (const T x : hr) rmax = std::max(rmax, (double)x);
+        h->z_rmax = rmax * (1.0 + std::ldexp(1.0, -20));
+        int e_z = 0;
+        std::frexp(tot * h->z_rmax + 1.0, &e_z);
+        const int zb = std::min(60, 60 - e_z);
+        if (zb < 0) return fail(CBLP_EINVAL, "arrival rates times revenues too large for the fixed-point dual bound");
+        h->z_scale = std::ldexp(1.0, zb);
+    }
 
     if (!ident && (rc = build_transpose<T>(h, hap, s))) return rc;
 

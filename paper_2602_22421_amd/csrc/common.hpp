@@ -26,6 +26,59 @@ constexpr int kFoldChunks = 16;            // batched fold: partial rows split 1
 constexpr int kFoldThreads = kFoldProducts * kFoldChunks;
 constexpr int kRowThreads = 256;
 
+// Z = sum_l lambda_l R*_l is summed in 64-bit fixed point, so that its sum,
+// like the sales sums, does not depend on how segments are grouped into
+// blocks or work items.  With duals >= 0 every R*_l is at most the largest
+// revenue r_max, and the scale z_scale (a power of two chosen at creation)
+// keeps sum_l lambda_l r_max z_scale below 2^60, so no partial sum can
+// overflow.  A segment whose R* exceeds r_max (beyond rounding: negative
+// duals) or is NaN marks the sum invalid: its partials hold kZPoison and the
+// sum reads as NaN.
+constexpr long long kZPoison = -0x7fffffffffffffffll - 1;   // INT64_MIN
+struct ZAcc {
+    long long q = 0;
+    bool bad = false;
+    // v = lambda R*, ok: R* within [0, r_max (1 + 2^-20)]
+    __device__ __forceinline__ void add(double v, bool ok, double zs)
+    {
+        if (ok)
+            q += __double2ll_rn(v * zs);
+        else
+            bad = true;
+    }
+};
+__device__ __forceinline__ bool z_ok(double R, double rmax) { return R <= rmax; }
+
+// The block's sum of the threads' ZAcc (or kZPoison), returned to every
+// thread; sh holds one value per wave.  Integer sums: any order gives the
+// same value.
+__device__ __forceinline__ long long block_z(const ZAcc& z, long long* sh)
+{
+    long long q = z.q;
+    for (int o = 32; o > 0; o >>= 1) q += __shfl_down(q, o, 64);
+    const bool bad = __ballot(z.bad) != 0ull;
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = bad ? kZPoison : q;
+    __syncthreads();
+    long long t = 0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w)
+        t = (t == kZPoison || sh[w] == kZPoison) ? kZPoison : t + sh[w];
+    return t;
+}
+
+// Z from fixed-point partials [q0, q1) taken by the block's threads in
+// strides (every thread gets the value; NaN when a partial is kZPoison).
+__device__ __forceinline__ double fold_z(const long long* part, int q0, int q1, double inv_z,
+                                         long long* sh)
+{
+    ZAcc z;
+    for (int q = q0 + (int)threadIdx.x; q < q1; q += (int)blockDim.x) {
+        const long long v = part[q];
+        if (v == kZPoison) z.bad = true; else z.q += v;
+    }
+    const long long t = block_z(z, sh);
+    return t == kZPoison ? __longlong_as_double(0x7ff8000000000000ll) : (double)t * inv_z;
+}
+
 // Device-resident solver state (FP64), updated by the finalising block.
 struct DevState {
     double dbest, lb, sum_p, scale;
@@ -54,7 +107,9 @@ struct SegArgs {
     int hp;                        // split-price kernel: prices [0, hp) held in LDS
     unsigned long long* S_fx;      // [n] fixed-point sales of products >= H
     double fx_scale;               // 2^bits; one segment's sale * 2^bits < 2^31 for FP32
-    double* zpart;                 // [gridDim.x] FP64 partials of sum lambda R*
+    long long* zpart;              // [gridDim.x] fixed-point partials of sum lambda R* (or kZPoison)
+    double z_scale;                // their scale
+    double z_rmax;                 // r_max (1 + 2^-20): the largest R* of duals >= 0
     void* seg_R;                   // [L] nullable, original segment order
     void* seg_thr;                 // [L] nullable, by position: the threshold R of S* =
                                    // {rho v > R den} (evaluation, per-entry sales)
@@ -83,7 +138,8 @@ struct PhaseArgs {
     double gamma, mu, tau_s;
     double tau_mult;               // CONST: the step multiplier of this iteration (decay)
     const void* tau_vec;           // [m] nullable
-    const double* zpart;
+    const long long* zpart;        // fixed-point partials of Z (scale 1 / inv_z), kZPoison: invalid
+    double inv_z;
     int nz;
     unsigned long long* S_fx;
     double inv_fx;

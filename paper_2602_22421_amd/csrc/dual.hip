@@ -101,7 +101,8 @@ __global__ void __launch_bounds__(kFoldLite) k_fold_step(PhaseArgs a)
     if (!s_last) return;
     __threadfence();
     clear(x);
-    for (int q = tid; q < a.nz; q += kFoldLite) x[R_Z] += a.zpart[q];
+    __shared__ long long zsh[kFoldLite / 64];
+    const double Zd = fold_z(a.zpart, 0, a.nz, a.inv_z, zsh);
     for (int q = tid; q < (int)gridDim.x; q += kFoldLite) x[R_P] += a.bpart[(size_t)q * 8 + R_P];
     for (int q = tid; q < (int)gridDim.x; q += kFoldLite) {
         const double* p = a.bpart + (size_t)q * 8;
@@ -113,6 +114,7 @@ __global__ void __launch_bounds__(kFoldLite) k_fold_step(PhaseArgs a)
         x[R_CS] += p[R_CS];
     }
     block_reduce(x, sh);
+    x[R_Z] = Zd;   // the fixed-point sum, not the FP64 tree
     if (tid != 0) return;
     const double D = x[R_CETA] + x[R_Z];
     double th = x[R_TH];
@@ -226,7 +228,8 @@ __global__ void __launch_bounds__(kRowThreads) k_update(PhaseArgs a)
     // every block folds all partials in the same order
     double x[NR];
     clear(x);
-    for (int q = tid; q < a.nz; q += kRowThreads) x[R_Z] += a.zpart[q];
+    __shared__ long long zsh[kRowThreads / 64];
+    const double Zd = fold_z(a.zpart, 0, a.nz, a.inv_z, zsh);
     for (int q = tid; q < a.fold_blocks; q += kRowThreads) x[R_P] += a.bpart[(size_t)q * 8 + R_P];
     const double* rp = IDENT ? a.bpart : a.bpart2;
     const int nrow = IDENT ? a.fold_blocks : (int)gridDim.x;
@@ -240,6 +243,7 @@ __global__ void __launch_bounds__(kRowThreads) k_update(PhaseArgs a)
         x[R_CS] += p[R_CS];
     }
     block_reduce(x, sh);
+    x[R_Z] = Zd;   // the fixed-point sum, not the FP64 tree
     const double D = x[R_CETA] + x[R_Z];
     const bool iter = a.mode != 1;      // a dual step follows
     const bool cert = a.mode == 0;      // full batch: dual bound and certificate

@@ -53,7 +53,9 @@ struct cblp_instance {
     double* S_d = nullptr;
     double* u_d = nullptr;
     double* sum_u = nullptr;
-    double* zpart = nullptr;
+    long long* zpart = nullptr;     // fixed-point Z partials, one per segment block
+    double z_scale = 1.0;           // their scale (a power of two)
+    double z_rmax = 0.0;            // largest revenue times (1 + 2^-20)
     double* bpart = nullptr;
     double* bpart2 = nullptr;
     unsigned* arrive = nullptr;     // arrival counter of the fused fold-and-step kernel

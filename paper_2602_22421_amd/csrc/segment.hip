@@ -28,7 +28,7 @@ template <typename T, int J, bool ALL, bool LDSP, typename IdxT = int32_t, bool 
 __global__ void __launch_bounds__(kSegThreads) k_segments_slots(SegArgs a)
 {
     extern __shared__ unsigned long long bins[];   // [a.H], then [a.n] prices if LDSP
-    __shared__ double zsh[kSegThreads / 64];
+    __shared__ long long zsh[kSegThreads / 64];
     const int H = a.H;
     T* lprice = (T*)(bins + H);
     for (int j = threadIdx.x; j < H; j += kSegThreads) bins[j] = 0ull;
@@ -36,7 +36,7 @@ __global__ void __launch_bounds__(kSegThreads) k_segments_slots(SegArgs a)
         for (int64_t j = threadIdx.x; j < a.n; j += kSegThreads) lprice[j] = ((const T*)a.rho)[j];
     __syncthreads();
 
-    double zacc = 0.0;
+    ZAcc zacc;
     const int64_t tiles = (a.L + kSegsPerTile - 1) / kSegsPerTile;
     const seg::FlatPrices<T> pr{LDSP ? (const T*)lprice : (const T*)a.rho};
     seg::process_tiles_slots<T, J, ALL, seg::FlatPrices<T>, IdxT, PSEG>(a, blockIdx.x, tiles,
@@ -44,14 +44,8 @@ __global__ void __launch_bounds__(kSegThreads) k_segments_slots(SegArgs a)
 
     __syncthreads();
     flush_bins(a, bins);
-    for (int o = 32; o > 0; o >>= 1) zacc += __shfl_down(zacc, o, 64);
-    if ((threadIdx.x & 63) == 0) zsh[threadIdx.x >> 6] = zacc;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double z = zsh[0];
-        for (int q = 1; q < kSegThreads / 64; ++q) z += zsh[q];
-        a.zpart[blockIdx.x] = z;
-    }
+    const long long z = block_z(zacc, zsh);
+    if (threadIdx.x == 0) a.zpart[blockIdx.x] = z;
 }
 
 // Three-part mixed kernel: positions [0, P2) (rows of at most 16 entries) in
@@ -64,7 +58,7 @@ template <typename T, typename IdxT, bool SPLIT = false, bool PSEG = false>
 __global__ void __launch_bounds__(kSegThreads) k_segments_mixed3(SegArgs a2, SegArgs a4, SegArgs a8)
 {
     extern __shared__ unsigned long long bins[];   // [a2.H], then the LDS prices
-    __shared__ double zsh[kSegThreads / 64];
+    __shared__ long long zsh[kSegThreads / 64];
     const int H = a2.H;
     T* lprice = (T*)(bins + H);
     for (int j = threadIdx.x; j < H; j += kSegThreads) bins[j] = 0ull;
@@ -72,7 +66,7 @@ __global__ void __launch_bounds__(kSegThreads) k_segments_mixed3(SegArgs a2, Seg
     for (int64_t j = threadIdx.x; j < np; j += kSegThreads) lprice[j] = ((const T*)a2.rho)[j];
     __syncthreads();
 
-    double zacc = 0.0;
+    ZAcc zacc;
     using PR = typename std::conditional<SPLIT, seg::SplitPrices<T>, seg::FlatPrices<T>>::type;
     PR pr;
     if constexpr (SPLIT)
@@ -89,14 +83,8 @@ __global__ void __launch_bounds__(kSegThreads) k_segments_mixed3(SegArgs a2, Seg
 
     __syncthreads();
     flush_bins(a2, bins);
-    for (int o = 32; o > 0; o >>= 1) zacc += __shfl_down(zacc, o, 64);
-    if ((threadIdx.x & 63) == 0) zsh[threadIdx.x >> 6] = zacc;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double z = zsh[0];
-        for (int q = 1; q < kSegThreads / 64; ++q) z += zsh[q];
-        a2.zpart[blockIdx.x] = z;
-    }
+    const long long z = block_z(zacc, zsh);
+    if (threadIdx.x == 0) a2.zpart[blockIdx.x] = z;
 }
 
 // Per-entry sales in the caller's CSR order from a pass that stored each

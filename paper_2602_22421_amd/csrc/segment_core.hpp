@@ -224,14 +224,15 @@ __device__ __forceinline__ unsigned long long quantum(double ls, double v)
 // bounds of the tile after), so the solve waits for its gathers alone; DEPTH
 // 4 is the same order with only the wave's jw slots loaded.  The
 // block visits tiles tile, tile + stride, ... below `tiles`; sales go to the
-// LDS bins (products < a.H) or the global tail; lambda R* is added to zacc.
+// LDS bins (products < a.H) or the global tail; lambda R* is added to zacc (fixed
+// point).
 //
 // prices: the reduced revenues rho_j as a FlatPrices (a.rho itself or a copy
 // of it in LDS; the compiler sees which memory it is) or a SplitPrices.
 template <typename T, int J, int DEPTH, typename PR>
 __device__ __forceinline__ void process_tiles(const SegArgs& a, int64_t tile, int64_t tiles,
                                               int64_t stride, unsigned long long* bins,
-                                              const PR& prices, double& zacc)
+                                              const PR& prices, ZAcc& zacc)
 {
     constexpr bool ALL = DEPTH == 3;
     constexpr bool ORDERED = DEPTH >= 3;   // DEPTH 4: ordered issue, only jw slots loaded
@@ -409,7 +410,7 @@ __device__ __forceinline__ void process_tiles(const SegArgs& a, int64_t tile, in
                 }
             }
             if (g == 0 && p < a.L) {
-                zacc += (double)Bc.lam * (double)Rstar;
+                zacc.add((double)Bc.lam * (double)Rstar, z_ok((double)Rstar, a.z_rmax), a.z_scale);
                 ((T*)a.Rwarm)[p] = Rstar;
                 if (a.seg_R) ((T*)a.seg_R)[a.perm[p]] = Rstar;
             }
@@ -516,7 +517,7 @@ __device__ __forceinline__ Raw<T, J> load_slots(const SegArgs& a, const WaveBoun
 template <typename T, int J, bool ALL, typename PR, typename IdxT = int32_t, bool PSEG = false>
 __device__ __forceinline__ void process_tiles_slots(const SegArgs& a, int64_t tile, int64_t tiles,
                                                     int64_t stride, unsigned long long* bins,
-                                                    const PR& rho, double& zacc)
+                                                    const PR& rho, ZAcc& zacc)
 {
     const T* __restrict__ v3 = (const T*)a.v3;
     const T* __restrict__ d3 = (const T*)a.den3;
@@ -650,7 +651,7 @@ __device__ __forceinline__ void process_tiles_slots(const SegArgs& a, int64_t ti
         if constexpr (PSEG) pl = group_sum(pl);
         if ((lane & (kGroup - 1)) == 0 && Bc.live) {
             const int64_t p = (tile * (kSegsPerTile / kGroup) + wv) * kGroup + q;
-            zacc += (double)Bc.lam * (double)Rstar;
+            zacc.add((double)Bc.lam * (double)Rstar, z_ok((double)Rstar, a.z_rmax), a.z_scale);
             ((T*)a.Rwarm)[p] = Rstar;
             if (a.seg_R) ((T*)a.seg_R)[a.perm[p]] = Rstar;
             if (a.seg_thr) {
@@ -717,7 +718,7 @@ __device__ __forceinline__ WaveBounds<T> load_wave_bounds_quad(const SegArgs& a,
 template <typename T, int J, typename PR, typename IdxT, bool PSEG = false>
 __device__ __forceinline__ void process_tiles_quad(const SegArgs& a, int64_t tile, int64_t tiles,
                                                    int64_t stride, unsigned long long* bins,
-                                                   const PR& rho, double& zacc)
+                                                   const PR& rho, ZAcc& zacc)
 {
     const T* __restrict__ v3 = (const T*)a.v3;
     const T* __restrict__ d3 = (const T*)a.den3;
@@ -863,7 +864,7 @@ __device__ __forceinline__ void process_tiles_quad(const SegArgs& a, int64_t til
         if constexpr (PSEG) pl = quad_total(pl);
         if ((lane & (kQuad - 1)) == 0 && Bc.live) {
             const int64_t p = (tile * (kSegThreads / 64) + wv) * kQuadRows + q;
-            zacc += (double)Bc.lam * (double)Rstar;
+            zacc.add((double)Bc.lam * (double)Rstar, z_ok((double)Rstar, a.z_rmax), a.z_scale);
             ((T*)a.Rwarm)[p] = Rstar;
             if (a.seg_R) ((T*)a.seg_R)[a.perm[p]] = Rstar;
             if (a.seg_thr) {
@@ -929,7 +930,7 @@ __device__ __forceinline__ WaveBounds<T> load_wave_bounds_pair(const SegArgs& a,
 template <typename T, int J, typename PR, typename IdxT, bool PSEG = false>
 __device__ __forceinline__ void process_tiles_pair(const SegArgs& a, int64_t tile, int64_t tiles,
                                                    int64_t stride, unsigned long long* bins,
-                                                   const PR& rho, double& zacc)
+                                                   const PR& rho, ZAcc& zacc)
 {
     const T* __restrict__ v3 = (const T*)a.v3;
     const T* __restrict__ d3 = (const T*)a.den3;
@@ -1069,7 +1070,7 @@ __device__ __forceinline__ void process_tiles_pair(const SegArgs& a, int64_t til
         if constexpr (PSEG) pl = pl + dpp_move<kQuadSwap1>(pl);
         if ((lane & (kPair - 1)) == 0 && Bc.live) {
             const int64_t p = (tile * (kSegThreads / 64) + wv) * kPairRows + q;
-            zacc += (double)Bc.lam * (double)Rstar;
+            zacc.add((double)Bc.lam * (double)Rstar, z_ok((double)Rstar, a.z_rmax), a.z_scale);
             ((T*)a.Rwarm)[p] = Rstar;
             if (a.seg_R) ((T*)a.seg_R)[a.perm[p]] = Rstar;
             if (a.seg_thr) {

@@ -52,9 +52,36 @@ def test_batch_iterate_matches_single(cb, dtype):
     params = cb.make_params(rule=0, tau=1.0, check_every=5)
     rows = batch.iterate(etas, iters, params, tau_vecs=taus2)
     for q in range(len(base)):
-        # constant steps: the duals depend only on exact integer sales sums
+        # constant steps: the duals depend only on exact integer sales sums;
+        # Z is a fixed-point sum and the FP64 partials are folded in the
+        # single path's grouping, so every trace column agrees bit for bit
         assert np.array_equal(etas[q].cpu().numpy(), eta_single[q]), q
-        np.testing.assert_allclose(rows[q, :3], rows_single[q][:3], rtol=1e-12)
+        assert np.array_equal(rows[q], rows_single[q]), (q, rows[q], rows_single[q])
+    batch.close()
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_batch_solve_certifies_as_single(cb, dtype):
+    """spfom_batch_solve and spfom_solve stop every instance at the same
+    check with the same last trace row, bit for bit."""
+    dt = torch.float64 if dtype == "f64" else torch.float32
+    base = [batch_instance(b, scale=0.004) for b in range(6)] + \
+        [make_instance(800, 40, size_lo=3, size_hi=9, cap_lo=0.5, cap_hi=3.0, seed=s) for s in (1, 2)]
+    _, singles, taus = _setup(cb, base, dt, tau0=0.01)
+    single = []
+    for p, t in zip(singles, taus):
+        prm = cb.make_params(rule=0, tau_vec=t, check_every=10, tol=0.05, max_iters=400,
+                             tau_decay=0.7, decay_every=100)
+        single.append(p.solve(p.zeros_eta(), prm).as_dict())
+    _, probs, taus2 = _setup(cb, base, dt, tau0=0.01)
+    batch = cb.Batch(probs)
+    params = cb.make_params(rule=0, tau=1.0, check_every=10, tol=0.05, max_iters=400,
+                            tau_decay=0.7, decay_every=100)
+    outs = batch.solve([p.zeros_eta() for p in probs], params, tau_vecs=taus2)
+    for q, (o, r) in enumerate(zip(outs, single)):
+        assert o["iters"] == r["iters"] and o["status"] == r["status"], (q, o, r)
+        for k in cb.TRACE_COLS:
+            assert o[k] == r[k], (q, k, o[k], r[k])
     batch.close()
 
 
