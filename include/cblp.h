@@ -299,15 +299,26 @@ int spfom_batch_iterate(cblp_batch_t b, void* const* etas, const void* const* ta
 int spfom_batch_solve(cblp_batch_t b, void* const* etas, const void* const* tau_vecs,
                       const spfom_params* p, spfom_stats* outs, void* stream);
 
-/* Autotune the segment-kernel variant (register slots per lane, pipeline
- * depth, copy layout) by timing iters iterations of each candidate on this
- * batch; the duals in etas change, the solver state is reset afterwards and
- * the handles' per-segment warm starts are restored (so a later solve
- * follows the same iterates as on untouched handles).  chosen [host]
- * nullable receives the variant kept.  CBLP_ENOMEM if the copy of the warm
- * starts (4 or 8 bytes per segment) cannot be allocated. */
+/* Autotune the batched segment pass: every usable kernel variant (copy
+ * layout and group widths, price placement) with 2, 4, 8 and 16 work items
+ * per segment block, timing iters iterations of each pair on this batch, and
+ * keep the fastest.  The duals in etas change, the solver state is reset
+ * afterwards and the handles' per-segment warm starts are restored (so a
+ * later solve follows the same iterates as on untouched handles).  chosen
+ * [host] nullable receives the variant kept.  CBLP_ENOMEM if the copy of the
+ * warm starts (4 or 8 bytes per segment) cannot be allocated. */
 int cblp_batch_tune(cblp_batch_t b, void* const* etas, const void* const* tau_vecs,
                     const spfom_params* p, int32_t iters, int32_t* chosen, void* stream);
+
+/* cblp_batch_tune through a cache file (cache_path [host], a text file of
+ * lines "key variant items_per_block", appended to): the key is the GPU's
+ * architecture name, the dtype, the instance count and the power-of-two
+ * buckets of the total entries, total segments and largest product count.
+ * A hit applies the stored choice without timing; a miss tunes and appends
+ * the result.  chosen, items_per_block [host] nullable. */
+int cblp_batch_tune_cached(cblp_batch_t b, void* const* etas, const void* const* tau_vecs,
+                           const spfom_params* p, int32_t iters, const char* cache_path,
+                           int32_t* chosen, int32_t* items_per_block, void* stream);
 
 /* Work items, persistent grid and kernel variant of the batch ([host], nullable). */
 int cblp_batch_info(cblp_batch_t b, int32_t* items, int32_t* grid, int32_t* variant);

@@ -27,7 +27,8 @@ EXPORTS = ("cblp_create", "cblp_destroy", "spfom_reset", "spfom_iterate", "spfom
            "cblp_gap", "cblp_sales", "cblp_launch_info", "cblp_timing", "cblp_timing_read",
            "spfom_minibatch", "cblp_recover", "cblp_gap_static", "cblp_gap_static_max_products",
            "cblp_last_error", "cblp_batch_create", "cblp_batch_destroy", "spfom_batch_iterate",
-           "spfom_batch_solve", "cblp_batch_tune", "cblp_batch_info", "cblp_batch_select",
+           "spfom_batch_solve", "cblp_batch_tune", "cblp_batch_tune_cached", "cblp_batch_info",
+           "cblp_batch_select",
            "wsnet_num_params", "wsnet_create", "wsnet_destroy", "wsnet_params", "wsnet_features",
            "wsnet_forward", "wsnet_gradients", "wsnet_train_step", "wsnet_train_epochs",
            "wsnet_targets", "wsnet_predict", "wsnet_start")
@@ -117,6 +118,10 @@ def load(path: str = _LIB_PATH) -> ctypes.CDLL:
     lib.cblp_batch_tune.restype = ctypes.c_int
     lib.cblp_batch_tune.argtypes = [vp, pp, pp, ctypes.POINTER(SpfomParams), i32,
                                     ctypes.POINTER(i32), vp]
+    lib.cblp_batch_tune_cached.restype = ctypes.c_int
+    lib.cblp_batch_tune_cached.argtypes = [vp, pp, pp, ctypes.POINTER(SpfomParams), i32,
+                                           ctypes.c_char_p, ctypes.POINTER(i32),
+                                           ctypes.POINTER(i32), vp]
     lib.cblp_batch_info.restype = ctypes.c_int
     lib.cblp_batch_info.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32),
                                     ctypes.POINTER(i32)]
@@ -428,6 +433,17 @@ def spfom_batch_solve(b, etas, tau_vecs, params: SpfomParams, stream=None):
     return [o.as_dict() for o in outs]
 
 
+def cblp_batch_tune_cached(b, etas, tau_vecs, params: SpfomParams, iters: int, cache_path: str,
+                           stream=None):
+    chosen, ipb = ctypes.c_int32(), ctypes.c_int32()
+    tv = None if tau_vecs is None else _ptr_array(tau_vecs)
+    _check(load().cblp_batch_tune_cached(ctypes.c_void_p(b), _ptr_array(etas), tv,
+                                         ctypes.byref(params), int(iters),
+                                         os.fsencode(cache_path), ctypes.byref(chosen),
+                                         ctypes.byref(ipb), _stream(stream)))
+    return chosen.value, ipb.value
+
+
 def cblp_batch_tune(b, etas, tau_vecs, params: SpfomParams, iters: int, stream=None) -> int:
     chosen = ctypes.c_int32()
     tv = None if tau_vecs is None else _ptr_array(tau_vecs)
@@ -476,6 +492,11 @@ class Batch:
 
     def tune(self, etas, params: SpfomParams, iters: int = 5, tau_vecs=None) -> int:
         return cblp_batch_tune(self.b, etas, tau_vecs, params, iters)
+
+    def tune_cached(self, etas, params: SpfomParams, cache_path: str, iters: int = 5,
+                    tau_vecs=None):
+        """(variant, items per block) from the tuning cache, or tuned and stored."""
+        return cblp_batch_tune_cached(self.b, etas, tau_vecs, params, iters, cache_path)
 
     def info(self) -> dict:
         return cblp_batch_info(self.b)

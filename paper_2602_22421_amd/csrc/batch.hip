@@ -28,6 +28,7 @@
 #include <cstring>
 #include <fstream>
 #include <new>
+#include <cstdio>
 #include <string>
 #include <vector>
 
@@ -378,6 +379,9 @@ struct cblp_batch {
     BInst* d_inst = nullptr;
     BItem* d_items = nullptr;
     int nitems = 0;
+    int ipb = 4;                     // work items per segment block (the tuner may change it)
+    size_t items_cap = 0, part_cap = 0, zpart_cap = 0;   // allocated entries
+    std::vector<int> order;          // instances, largest first
     BChunk* d_fold = nullptr;
     int nfold = 0;
     BChunk* d_rows = nullptr;
@@ -576,6 +580,62 @@ bool bseg_usable(const cblp_batch* b, int variant)
            per_cu >= 1;
 }
 
+// The work list: each instance's parts cut into items of about equal tile
+// count, ipb items per segment block on average, largest instance first;
+// item lengths are multiples of kPartAlign positions, so that items start on
+// a tile of every layout.  Sizes the per-item LDS-bin rows and Z partials,
+// uploads the list and the instance table, and drops a captured graph (its
+// launches hold the item count).
+int build_items(cblp_batch* b, int ipb, hipStream_t s)
+{
+    int64_t total_tiles = 0;
+    for (int q = 0; q < b->count; ++q) total_tiles += (b->hs[q]->L + kSegsPerTile - 1) / kSegsPerTile;
+    const int64_t per_item = std::max<int64_t>(1, total_tiles / ((int64_t)b->grid * ipb));
+    const int64_t per_rows = (per_item * kSegsPerTile + kPartAlign - 1) / kPartAlign * kPartAlign;
+    std::vector<BItem> items;
+    int64_t part = 0;
+    for (int q : b->order) {
+        const cblp_instance* h = b->hs[q];
+        BInst& I = b->h_inst[q];
+        const int64_t pb[4] = {0, h->pair_end, h->quad_end, h->L};
+        I.item0 = (int)items.size();
+        for (int k = 0; k < 3; ++k)
+            for (int64_t p0 = pb[k]; p0 < pb[k + 1]; p0 += per_rows)
+                items.push_back(BItem{q, k, p0, std::min(pb[k + 1], p0 + per_rows)});
+        I.item1 = (int)items.size();
+        I.part_off = part;
+        part += (int64_t)(I.item1 - I.item0) * h->H;
+    }
+    auto grow = [&](void** ptr, size_t& cap, size_t need, size_t esz) -> int {
+        need = std::max<size_t>(need, 1);
+        if (need <= cap) return CBLP_OK;
+        if (*ptr) (void)hipFree(*ptr);
+        *ptr = nullptr;
+        cap = 0;
+        if (hipMalloc(ptr, need * esz) != hipSuccess) return bfail(CBLP_ENOMEM, "hipMalloc failed");
+        cap = need;
+        return CBLP_OK;
+    };
+    int rc;
+    if ((rc = grow((void**)&b->d_items, b->items_cap, items.size(), sizeof(BItem))) ||
+        (rc = grow((void**)&b->part_S, b->part_cap, (size_t)part, 8)) ||
+        (rc = grow((void**)&b->zpart, b->zpart_cap, items.size(), 8)))
+        return rc;
+    b->nitems = (int)items.size();
+    b->ipb = ipb;
+    if (!items.empty())
+        BHIP(hipMemcpyAsync(b->d_items, items.data(), items.size() * sizeof(BItem),
+                            hipMemcpyHostToDevice, s));
+    BHIP(hipMemcpyAsync(b->d_inst, b->h_inst.data(), b->count * sizeof(BInst), hipMemcpyHostToDevice, s));
+    BHIP(hipStreamSynchronize(s));
+    if (b->exec) {
+        (void)hipGraphExecDestroy(b->exec);
+        b->exec = nullptr;
+        b->graph_K = 0;
+    }
+    return CBLP_OK;
+}
+
 int ensure_graph(cblp_batch* b, const spfom_params* p)
 {
     // the kernels' arguments hold the step rule's scalars: a graph serves only
@@ -668,21 +728,14 @@ int cblp_batch_create(cblp_batch_t* out, int32_t count, const cblp_t* handles, v
     }
     b->grid = cus * per_cu;
 
-    // work items: instances largest first, tiles cut into items of about equal size
-    std::vector<int> order(count);
+    // instances largest first (the work list is built below, build_items)
+    std::vector<int>& order = b->order;
+    order.resize(count);
     for (int q = 0; q < count; ++q) order[q] = q;
     std::stable_sort(order.begin(), order.end(),
                      [&](int x, int y) { return b->hs[x]->nnz > b->hs[y]->nnz; });
-    int64_t total_tiles = 0;
-    for (int q = 0; q < count; ++q) total_tiles += (b->hs[q]->L + kSegsPerTile - 1) / kSegsPerTile;
-    const int64_t per_item = std::max<int64_t>(1, total_tiles / ((int64_t)b->grid * 4));
-    // item length in positions: a multiple of kPartAlign, so that items start on
-    // a tile of every layout
-    const int64_t per_rows = (per_item * kSegsPerTile + kPartAlign - 1) / kPartAlign * kPartAlign;
-    std::vector<BItem> items;
     std::vector<BChunk> fold, rows;
     b->h_inst.assign(count, BInst());
-    int64_t part = 0;
     for (int q : order) {
         cblp_instance* h = b->hs[q];
         BInst& I = b->h_inst[q];
@@ -742,28 +795,17 @@ int cblp_batch_create(cblp_batch_t* out, int32_t count, const cblp_t* handles, v
             I.part_args[k] = v;
             I.pstart[k] = pb[k];
         }
-        I.item0 = (int)items.size();
-        for (int k = 0; k < 3; ++k)
-            for (int64_t p0 = pb[k]; p0 < pb[k + 1]; p0 += per_rows)
-                items.push_back(BItem{q, k, p0, std::min(pb[k + 1], p0 + per_rows)});
-        I.item1 = (int)items.size();
-        I.part_off = part;
-        part += (int64_t)(I.item1 - I.item0) * h->H;
         I.fold0 = (int)fold.size();
         for (int64_t j = 0; j < h->n; j += kFoldProducts) fold.push_back(BChunk{q, 0, j});
         I.fold1 = (int)fold.size();
         for (int64_t i = 0; i < h->m; i += kRowThreads) rows.push_back(BChunk{q, 0, i});
     }
-    b->nitems = (int)items.size();
     b->nfold = (int)fold.size();
     b->nrows = (int)rows.size();
     int rc;
     if ((rc = balloc(&b->d_inst, count * sizeof(BInst)))) return bail(rc);
-    if ((rc = balloc(&b->d_items, std::max<size_t>(items.size(), 1) * sizeof(BItem)))) return bail(rc);
     if ((rc = balloc(&b->d_fold, std::max<size_t>(fold.size(), 1) * sizeof(BChunk)))) return bail(rc);
     if ((rc = balloc(&b->d_rows, std::max<size_t>(rows.size(), 1) * sizeof(BChunk)))) return bail(rc);
-    if ((rc = balloc(&b->part_S, (size_t)std::max<int64_t>(part, 1) * 8))) return bail(rc);
-    if ((rc = balloc(&b->zpart, std::max<size_t>(items.size(), 1) * 8))) return bail(rc);
     if ((rc = balloc(&b->bpart, std::max<size_t>(fold.size(), 1) * 8 * 8))) return bail(rc);
     if ((rc = balloc(&b->st, (size_t)count * 2 * sizeof(DevState)))) return bail(rc);
     if ((rc = balloc(&b->rows, (size_t)count * SPFOM_NTRACE * 8))) return bail(rc);
@@ -777,13 +819,12 @@ int cblp_batch_create(cblp_batch_t* out, int32_t count, const cblp_t* handles, v
     auto up = [&](void* d, const void* h, size_t n) {
         return n ? hipMemcpyAsync(d, h, n, hipMemcpyHostToDevice, s) : hipSuccess;
     };
-    if (up(b->d_items, items.data(), items.size() * sizeof(BItem)) != hipSuccess ||
-        up(b->d_fold, fold.data(), fold.size() * sizeof(BChunk)) != hipSuccess ||
+    if (up(b->d_fold, fold.data(), fold.size() * sizeof(BChunk)) != hipSuccess ||
         up(b->d_rows, rows.data(), rows.size() * sizeof(BChunk)) != hipSuccess ||
-        up(b->d_inst, b->h_inst.data(), count * sizeof(BInst)) != hipSuccess ||
         hipMemsetAsync(b->rows, 0, (size_t)count * SPFOM_NTRACE * 8, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess)
         return bail(bfail(CBLP_EHIP, "uploading the batch tables failed"));
+    if ((rc = build_items(b, b->ipb, s))) return bail(rc);
     if ((rc = reset_states(b, s))) return bail(rc);
     *out = b;
     return CBLP_OK;
@@ -899,8 +940,9 @@ int cblp_batch_tune(cblp_batch_t b, void* const* etas, const void* const* tau_ve
     if ((rc = bind(b, etas, tau_vecs, p, b->stream))) return rc;
     if ((rc = run_prices(b, b->stream))) return rc;
     const int candidates[] = {0, 1, 2, 3};
+    const int ipbs[] = {2, 4, 8, 16};   // work items per segment block
     double best = INFINITY;
-    int best_v = b->variant;
+    int best_v = b->variant, best_ipb = b->ipb;
     // the trial iterations move every handle's warm-start R*: keep a copy and
     // put it back, so that tuning leaves the handles as it found them
     std::vector<void*> saved(b->count, nullptr);
@@ -918,21 +960,26 @@ int cblp_batch_tune(cblp_batch_t b, void* const* etas, const void* const* tau_ve
     hipEvent_t e0, e1;
     BHIP(hipEventCreate(&e0));
     BHIP(hipEventCreate(&e1));
-    const int keep = b->variant;
-    for (int v : candidates) {
+    const int keep = b->variant, keep_ipb = b->ipb;
+    for (int ipb : ipbs) {
         if (rc) break;
-        if (!bseg_usable(b, v)) continue;
-        b->variant = v;
-        if ((rc = run_iters(b, p, 1, b->stream))) break;   // warm the variant
-        BHIP(hipEventRecord(e0, b->stream));
-        if ((rc = run_iters(b, p, iters, b->stream))) break;
-        BHIP(hipEventRecord(e1, b->stream));
-        BHIP(hipEventSynchronize(e1));
-        float ms = 0.0f;
-        BHIP(hipEventElapsedTime(&ms, e0, e1));
-        if (ms < best) {
-            best = ms;
-            best_v = v;
+        if ((rc = build_items(b, ipb, b->stream))) break;
+        for (int v : candidates) {
+            if (rc) break;
+            if (!bseg_usable(b, v)) continue;
+            b->variant = v;
+            if ((rc = run_iters(b, p, 1, b->stream))) break;   // warm the variant
+            BHIP(hipEventRecord(e0, b->stream));
+            if ((rc = run_iters(b, p, iters, b->stream))) break;
+            BHIP(hipEventRecord(e1, b->stream));
+            BHIP(hipEventSynchronize(e1));
+            float ms = 0.0f;
+            BHIP(hipEventElapsedTime(&ms, e0, e1));
+            if (ms < best) {
+                best = ms;
+                best_v = v;
+                best_ipb = ipb;
+            }
         }
     }
     (void)hipEventDestroy(e0);
@@ -949,10 +996,8 @@ int cblp_batch_tune(cblp_batch_t b, void* const* etas, const void* const* tau_ve
     for (void* ptr : saved)
         if (ptr) (void)hipFree(ptr);
     b->variant = rc ? keep : best_v;
-    if (b->exec) {
-        (void)hipGraphExecDestroy(b->exec);
-        b->exec = nullptr;
-    }
+    const int rc_items = build_items(b, rc ? keep_ipb : best_ipb, b->stream);   // drops the graph
+    if (!rc) rc = rc_items;
     if (chosen) *chosen = b->variant;
     if (!rc) rc = reset_states(b, b->stream);
     const int rc2 = leave(b, caller);
@@ -980,6 +1025,70 @@ int cblp_batch_info(cblp_batch_t b, int32_t* items, int32_t* grid, int32_t* vari
     if (items) *items = b->nitems;
     if (grid) *grid = b->grid;
     if (variant) *variant = b->variant;
+    return CBLP_OK;
+}
+
+int cblp_batch_tune_cached(cblp_batch_t b, void* const* etas, const void* const* tau_vecs,
+                           const spfom_params* p, int32_t iters, const char* cache_path,
+                           int32_t* chosen, int32_t* items_per_block, void* stream)
+{
+    set_error(CBLP_OK, "");
+    if (!b || !cache_path) return bfail(CBLP_EINVAL, "NULL batch or cache path");
+    // key: the device's architecture and the batch's shape bucket
+    std::string arch = "unknown";
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, b->hs[0]->device) == hipSuccess) arch = prop.gcnArchName;
+    for (char& ch : arch)
+        if (ch == ' ') ch = '_';
+    int64_t nnz = 0, L = 0, nmax = 0;
+    for (const cblp_instance* h : b->hs) {
+        nnz += h->nnz;
+        L += h->L;
+        nmax = std::max<int64_t>(nmax, h->n);
+    }
+    auto lg = [](int64_t x) { int e = 0; std::frexp((double)x + 1.0, &e); return e; };
+    const std::string key = arch + ":" + (b->dtype == CBLP_F32 ? "f32" : "f64") + ":count" +
+                            std::to_string(b->count) + ":nnz2^" + std::to_string(lg(nnz)) +
+                            ":L2^" + std::to_string(lg(L)) + ":n2^" + std::to_string(lg(nmax)) +
+                            ":parts" + std::to_string((b->parts16_ok ? 1 : 0) + (b->parts32_ok ? 2 : 0));
+    {
+        FILE* f = std::fopen(cache_path, "r");
+        if (f) {
+            char kbuf[512];
+            int v = -1, ipb = 0;
+            int found_v = -1, found_ipb = 0;
+            while (std::fscanf(f, "%511s %d %d", kbuf, &v, &ipb) == 3)
+                if (key == kbuf) {   // the last entry for the key wins
+                    found_v = v;
+                    found_ipb = ipb;
+                }
+            std::fclose(f);
+            if (found_v >= 0 && found_ipb >= 1 && found_ipb <= 64 && bseg_usable(b, found_v)) {
+                hipStream_t caller = (hipStream_t)stream;
+                int rc = enter(b, caller);
+                if (!rc && found_v != b->variant && b->exec) {
+                    (void)hipGraphExecDestroy(b->exec);
+                    b->exec = nullptr;
+                }
+                if (!rc) b->variant = found_v;
+                if (!rc) rc = build_items(b, found_ipb, b->stream);
+                const int rc2 = leave(b, caller);
+                if (rc || rc2) return rc ? rc : rc2;
+                if (chosen) *chosen = b->variant;
+                if (items_per_block) *items_per_block = b->ipb;
+                return CBLP_OK;
+            }
+        }
+    }
+    int32_t v = 0;
+    int rc = cblp_batch_tune(b, etas, tau_vecs, p, iters, &v, stream);
+    if (rc) return rc;
+    if (chosen) *chosen = v;
+    if (items_per_block) *items_per_block = b->ipb;
+    FILE* f = std::fopen(cache_path, "a");
+    if (!f) return bfail(CBLP_EINVAL, std::string("cannot append to the tuning cache ") + cache_path);
+    std::fprintf(f, "%s %d %d\n", key.c_str(), b->variant, b->ipb);
+    std::fclose(f);
     return CBLP_OK;
 }
 

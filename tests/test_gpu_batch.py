@@ -191,6 +191,42 @@ def test_batch_graph_follows_step_parameters(cb):
     b2.close()
 
 
+def test_batch_tune_cache_and_items_per_block(cb, tmp_path):
+    """The tuning cache: a miss tunes and appends one line, a hit applies the
+    stored variant and items per block without tuning; with 16 items per
+    block the batch still gives each instance's own duals and trace rows bit
+    for bit (integer sales, fixed-point Z, the single path's fold grouping)."""
+    base = [batch_instance(b, scale=0.004) for b in range(5)]
+    _, singles, taus = _setup(cb, base, torch.float32, tau0=0.004)
+    ref = []
+    for p, t in zip(singles, taus):
+        prm = cb.make_params(rule=0, tau_vec=t, check_every=5)
+        e = p.zeros_eta()
+        tr, _ = p.iterate(e, 15, prm)
+        ref.append((e.cpu().numpy(), tr[-1]))
+    cache = str(tmp_path / "tune.txt")
+    _, probs, taus2 = _setup(cb, base, torch.float32, tau0=0.004)
+    batch = cb.Batch(probs)
+    params = cb.make_params(rule=0, tau=1.0, check_every=5)
+    v, ipb = batch.tune_cached([p.zeros_eta() for p in probs], params, cache, iters=2,
+                               tau_vecs=taus2)
+    lines = [ln for ln in open(cache).read().split("\n") if ln]
+    assert len(lines) == 1 and lines[0].split()[1:] == [str(v), str(ipb)]
+    assert ipb in (2, 4, 8, 16)
+    key = lines[0].split()[0]
+    with open(cache, "a") as f:
+        f.write(f"{key} {v} 16\n")
+    assert batch.tune_cached([p.zeros_eta() for p in probs], params, cache, iters=2,
+                             tau_vecs=taus2) == (v, 16)
+    assert len([ln for ln in open(cache).read().split("\n") if ln]) == 2
+    etas = [p.zeros_eta() for p in probs]
+    rows = batch.iterate(etas, 15, params, tau_vecs=taus2)
+    for q in range(len(base)):
+        assert np.array_equal(etas[q].cpu().numpy(), ref[q][0]), q
+        assert np.array_equal(rows[q], ref[q][1]), q
+    batch.close()
+
+
 def test_batch_tune_picks_a_variant(cb):
     base = [batch_instance(b, scale=0.004) for b in range(3)]
     insts, probs, taus = _setup(cb, base, torch.float32, tau0=0.001)
