@@ -17,8 +17,8 @@ the solver library never imports or runs it.  It restates, in plain numpy:
 * one Adam step (Kingma and Ba, Algorithm 1).
 
 The learned warm start is not part of the paper's method (Section 7 lists
-learning components as future work); it changes only the starting dual of
-Algorithm 1.
+learning components as future work); it changes only the starting duals
+eta^0 that SPFOM (Algorithm 2, Algorithm 3) takes as an input.
 """
 from __future__ import annotations
 

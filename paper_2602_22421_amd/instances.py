@@ -37,7 +37,8 @@ from typing import Optional
 import numpy as np
 
 __all__ = ["Instance", "make_instance", "config_instance", "tiny_instance",
-           "batch_instance", "step_scale", "minibatch_schedule"]
+           "batch_instance", "step_scale", "minibatch_schedule", "Market",
+           "gosim_market", "market_instance"]
 
 
 @dataclasses.dataclass
@@ -354,3 +355,70 @@ def step_scale(inst: Instance, tau0: float) -> np.ndarray:
     pos = c > 0
     cmin = c[pos].min() if pos.any() else 1.0
     return tau0 * float(np.max(inst.r)) / np.where(pos, c, cmin)
+
+
+@dataclasses.dataclass
+class Market:
+    """Inputs of the bid-price policy simulation (Section 5.1, the synthetic
+    market of Figure 4) for ``runs`` independent runs: prices r [runs, n],
+    initial inventories inv0 [runs, n] (int64), each batch's customer
+    preferences prefs [periods, runs, N, n] and the uniforms u [periods,
+    runs, N] that decide the customers' choices."""
+    r: np.ndarray
+    inv0: np.ndarray
+    prefs: np.ndarray
+    u: np.ndarray
+
+    @property
+    def periods(self) -> int:
+        return int(self.prefs.shape[0])
+
+    @property
+    def runs(self) -> int:
+        return int(self.r.shape[0])
+
+    @property
+    def customers(self) -> int:
+        return int(self.prefs.shape[2])
+
+    @property
+    def n(self) -> int:
+        return int(self.r.shape[1])
+
+    def cast(self, dtype) -> "Market":
+        dt = np.dtype(dtype)
+        return dataclasses.replace(self, r=np.ascontiguousarray(self.r, dtype=dt),
+                                   prefs=np.ascontiguousarray(self.prefs, dtype=dt))
+
+
+def gosim_market(runs: int = 30, *, n: int = 40, periods: int = 100, customers: int = 1000,
+                 price_lo: float = 1.0, price_hi: float = 20.0, inv_lo: int = 1,
+                 inv_hi: int = 2000, seed: int = 0, dtype=np.float64) -> Market:
+    """The market of Figure 4: prices U[price_lo, price_hi], integer initial
+    inventories U{inv_lo..inv_hi}, every customer's preference for every
+    product U(0, 1] (strictly positive: it is an attraction), fresh customers
+    in every batch, and one U[0, 1) choice draw per customer."""
+    ss = np.random.SeedSequence(seed)
+    g_r, g_inv, g_pref, g_u = [np.random.Generator(np.random.PCG64(s)) for s in ss.spawn(4)]
+    r = g_r.uniform(price_lo, price_hi, size=(runs, n))
+    inv0 = g_inv.integers(inv_lo, inv_hi + 1, size=(runs, n), dtype=np.int64)
+    prefs = np.empty((periods, runs, customers, n), dtype=np.dtype(dtype))
+    for t in range(periods):
+        prefs[t] = 1.0 - g_pref.random((runs, customers, n))
+    u = g_u.random((periods, runs, customers))
+    return Market(r=np.ascontiguousarray(r, dtype=np.dtype(dtype)), inv0=inv0, prefs=prefs, u=u)
+
+
+def market_instance(prefs: np.ndarray, r: np.ndarray, c: np.ndarray, name: str = "") -> Instance:
+    """One batch's choice-based LP: every customer a segment of arrival rate 1
+    whose consideration set is every product (rows in product order),
+    nominal attraction = the customer's preference, no shadow attraction
+    (the basic attraction model), no-purchase attraction 1, capacities c."""
+    N, n = prefs.shape
+    dt = prefs.dtype
+    return Instance(L=N, n=n, m=n, seg_ptr=np.arange(N + 1, dtype=np.int64) * n,
+                    idx=np.tile(np.arange(n, dtype=np.int32), N),
+                    v=np.ascontiguousarray(prefs.ravel()), w=np.zeros(N * n, dtype=dt),
+                    v0=np.ones(N, dtype=dt), lam=np.ones(N, dtype=dt),
+                    r=np.ascontiguousarray(r, dtype=dt), c=np.ascontiguousarray(c, dtype=dt),
+                    name=name)
