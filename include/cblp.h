@@ -147,6 +147,21 @@ void cblp_destroy(cblp_t h);
 int spfom_reset(cblp_t h, void* stream);
 
 /*
+ * cblp_refresh - re-read new attractions and capacities into the handle: the
+ * re-solves of a multi-period problem (Section 5.1), where each period's
+ * customers bring their own preference weights and the remaining capacity
+ * shrinks.  The caller has overwritten, in place, the v, w and c arrays it
+ * gave cblp_create; the row pointers, product ids, v0, lambda, r and A must
+ * be those of creation (the copies and fixed-point scales built from them
+ * are kept).  The new values are validated as in cblp_create (CBLP_EINVAL
+ * leaves the handle's copies inconsistent until a valid refresh), the
+ * per-segment warm starts restart from 0 and the solver state is reset as by
+ * spfom_reset.  A batch over the handle follows the refresh (it reads the
+ * handle's buffers).  Synchronises the stream.
+ */
+int cblp_refresh(cblp_t h, void* stream);
+
+/*
  * spfom_iterate - run `iters` SPFOM iterations from eta, continuing the
  * handle's solver state (Algorithm 3 with every segment sampled; dual step
  * of eq. 16).
@@ -327,6 +342,73 @@ int cblp_batch_info(cblp_batch_t b, int32_t* items, int32_t* grid, int32_t* vari
  * candidates, 0-3; every variant gives the same duals bit for bit).
  * CBLP_EINVAL if the variant cannot run on this batch. */
 int cblp_batch_select(cblp_batch_t b, int32_t variant);
+
+/* Instances that take part in the batch's next spfom_batch_iterate and
+ * spfom_batch_solve calls: take_part [host] [count], nonzero = takes part;
+ * NULL = every instance (the state after cblp_batch_create).  The others
+ * keep their duals untouched; a solve still resets their state and reports
+ * them with iters 0 and status CBLP_OK. */
+int cblp_batch_mask(cblp_batch_t b, const int32_t* take_part);
+
+/* ------------------------------------------------- bid-price policy simulation
+ * The global optimisation (GO) policy of Section 5.1 with bid-price control,
+ * on the synthetic market of Figure 4, for `runs` independent runs at once.
+ * In every batch (period) t of T and run: products out of stock leave the
+ * offer; if at most K remain they are all offered; otherwise the batch's
+ * sales-based LP is re-solved by SPFOM from the previous batch's duals and
+ * the bid-price rule offers the products with r_j - eta_j >= 0, cut to the K
+ * largest margins (ties: lower j).  The batch's customers then choose under
+ * the basic attraction model (no-purchase attraction 1): customer i with
+ * uniform u_i buys the first offered product (ascending j) whose running
+ * preference sum exceeds u_i (1 + sum of the offered preferences), or
+ * nothing; product j sells min(its demand, its stock).  The batch LP has the
+ * batch's customers as segments (arrival rate 1, every product in the
+ * consideration set, preference = nominal attraction, no shadow attraction)
+ * and capacities c_j = stock_j / (T - t) (t counted from 0): the remaining
+ * stock spread evenly over the batches left.  Decisions are taken in FP64
+ * from the dtype's values; results are exact and reproducible.
+ *
+ * Layouts (row-major): r, eta, tau, c [runs x n] (dtype); inv [runs x n]
+ * int64 (stock, in/out); prefs [T x runs x N x n] (dtype); u [T x runs x N]
+ * double in [0, 1); offers [T x runs x K] int32 (ascending, -1 padded);
+ * sales [T x runs x n] int64; revenue [T x runs] double.  n <= 8192,
+ * 1 <= K <= 64.
+ */
+
+/* Capacities and dual steps of the current batch's LP, for every run:
+ * c_j = inv_j / periods_left and tau_j = tau0 max_k r_k / c_j (zero capacity:
+ * the smallest positive one's step, or capacity 1 if none), each rounded
+ * once to dtype (tau from the rounded c).  [dev] inv, r in; c, tau out. */
+int gosim_lp_inputs(int32_t runs, int64_t n, const int64_t* inv, int64_t periods_left,
+                    double tau0, const void* r, void* c, void* tau, int32_t dtype, void* stream);
+
+/* One batch of every run at the given duals: the offer, the N customers'
+ * choices, sales and the stock left.  [dev] eta, r, prefs [runs x N x n]
+ * (this batch's), u [runs x N] in; inv in/out; offer [runs x K], sales
+ * [runs x n], revenue [runs] out; in_stock [runs] (nullable) out: products
+ * still in stock afterwards. */
+int gosim_period(int32_t runs, int64_t N, int64_t n, int32_t K, const void* eta, const void* r,
+                 const void* prefs, const double* u, int64_t* inv, int32_t* offer,
+                 int64_t* sales, double* revenue, int32_t* in_stock, int32_t dtype, void* stream);
+
+/* T batches of the GO policy over the batch b of `runs` handles.  Handle q
+ * holds run q's batch LP: N segments listing products 0..n-1 in order,
+ * w = 0, v0 = lambda = 1, A = I, with its v, c and r at offset q of one
+ * [runs x N x n], [runs x n] and [runs x n] array each (r: the r argument);
+ * its v and c arrays are the simulation's work buffers (overwritten).
+ * Per batch: gosim_lp_inputs into the handles' c and tau_work [dev]
+ * [runs x n], this batch's preferences copied into the handles' v,
+ * cblp_refresh of the runs with more than K products in stock, one
+ * spfom_batch_solve of those runs (p: tol, max_iters, check_every, step
+ * rule; tau_vec unused - each run steps by its tau_work row; an instance
+ * that does not reach tol keeps its last duals) from eta [dev] [runs x n]
+ * (in/out: the duals carried from batch to batch), then gosim_period.
+ * lp_iters [host] [T x runs] (nullable): SPFOM iterations per batch and run
+ * (0: no LP solved).  The batch's participation mask is cleared on return. */
+int gosim_run(cblp_batch_t b, int32_t periods, int32_t K, const void* prefs, const double* u,
+              const void* r, int64_t* inv, void* eta, void* tau_work, const spfom_params* p,
+              double tau0, int32_t* offers, int64_t* sales, double* revenue, int64_t* lp_iters,
+              void* stream);
 
 /* ---------------------------------------------------------- learned warm start
  * A small network maps four features of each product to a starting capacity

@@ -28,7 +28,8 @@ EXPORTS = ("cblp_create", "cblp_destroy", "spfom_reset", "spfom_iterate", "spfom
            "spfom_minibatch", "cblp_recover", "cblp_gap_static", "cblp_gap_static_max_products",
            "cblp_last_error", "cblp_batch_create", "cblp_batch_destroy", "spfom_batch_iterate",
            "spfom_batch_solve", "cblp_batch_tune", "cblp_batch_tune_cached", "cblp_batch_info",
-           "cblp_batch_select",
+           "cblp_batch_select", "cblp_refresh", "cblp_batch_mask", "gosim_lp_inputs",
+           "gosim_period", "gosim_run",
            "wsnet_num_params", "wsnet_create", "wsnet_destroy", "wsnet_params", "wsnet_features",
            "wsnet_forward", "wsnet_gradients", "wsnet_train_step", "wsnet_train_epochs",
            "wsnet_targets", "wsnet_predict", "wsnet_start")
@@ -127,6 +128,17 @@ def load(path: str = _LIB_PATH) -> ctypes.CDLL:
                                     ctypes.POINTER(i32)]
     lib.cblp_batch_select.restype = ctypes.c_int
     lib.cblp_batch_select.argtypes = [vp, i32]
+    lib.cblp_refresh.restype = ctypes.c_int
+    lib.cblp_refresh.argtypes = [vp, vp]
+    lib.cblp_batch_mask.restype = ctypes.c_int
+    lib.cblp_batch_mask.argtypes = [vp, vp]
+    lib.gosim_lp_inputs.restype = ctypes.c_int
+    lib.gosim_lp_inputs.argtypes = [i32, i64, vp, i64, ctypes.c_double, vp, vp, vp, i32, vp]
+    lib.gosim_period.restype = ctypes.c_int
+    lib.gosim_period.argtypes = [i32, i64, i64, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, i32, vp]
+    lib.gosim_run.restype = ctypes.c_int
+    lib.gosim_run.argtypes = [vp, i32, i32, vp, vp, vp, vp, vp, vp, ctypes.POINTER(SpfomParams),
+                              ctypes.c_double, vp, vp, vp, vp, vp]
     lib.cblp_last_error.restype = ctypes.c_char_p
     lib.cblp_last_error.argtypes = []
     lib.wsnet_num_params.restype = i64
@@ -198,6 +210,10 @@ def cblp_destroy(h) -> None:
 
 def spfom_reset(h, stream=None) -> None:
     _check(load().spfom_reset(ctypes.c_void_p(h), _stream(stream)))
+
+
+def cblp_refresh(h, stream=None) -> None:
+    _check(load().cblp_refresh(ctypes.c_void_p(h), _stream(stream)))
 
 
 def spfom_iterate(h, eta, params: SpfomParams, iters: int, trace: Optional[np.ndarray] = None,
@@ -352,6 +368,15 @@ class Problem:
     def reset(self):
         spfom_reset(self.h)
 
+    def refresh(self, v=None, w=None, c=None):
+        """New attractions and capacities (numpy arrays or tensors) written into
+        this Problem's device arrays in place, then re-read by the handle."""
+        for dst, src in ((self.v, v), (self.w, w), (self.c, c)):
+            if src is not None:
+                dst.copy_(torch.as_tensor(np.asarray(src) if not isinstance(src, torch.Tensor)
+                                          else src, dtype=self.dtype))
+        cblp_refresh(self.h)
+
     def iterate(self, eta: torch.Tensor, iters: int, params: SpfomParams, trace: bool = True):
         tr = np.zeros((int(iters), NTRACE)) if trace else None
         st = SpfomStats()
@@ -456,6 +481,14 @@ def cblp_batch_select(b, variant: int) -> None:
     _check(load().cblp_batch_select(ctypes.c_void_p(b), int(variant)))
 
 
+def cblp_batch_mask(b, take_part=None) -> None:
+    arr = None
+    if take_part is not None:
+        arr = np.ascontiguousarray(np.asarray(take_part) != 0, dtype=np.int32)
+    _check(load().cblp_batch_mask(ctypes.c_void_p(b),
+                                  None if arr is None else arr.ctypes.data_as(ctypes.c_void_p)))
+
+
 def cblp_batch_info(b) -> dict:
     it, g, v = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
     _check(load().cblp_batch_info(ctypes.c_void_p(b), ctypes.byref(it), ctypes.byref(g),
@@ -503,6 +536,113 @@ class Batch:
 
     def select(self, variant: int) -> None:
         cblp_batch_select(self.b, variant)
+
+    def mask(self, take_part=None) -> None:
+        cblp_batch_mask(self.b, take_part)
+
+
+# ------------------------------------------------- bid-price policy simulation
+
+def _dt(t: torch.Tensor) -> int:
+    return CBLP_F32 if t.dtype == torch.float32 else CBLP_F64
+
+
+def gosim_lp_inputs(inv, periods_left: int, tau0: float, r, c, tau, stream=None) -> None:
+    """inv [runs, n] int64, r/c/tau [runs, n] (one dtype), device tensors."""
+    runs, n = r.shape
+    assert inv.dtype == torch.int64 and inv.shape == r.shape and c.dtype == tau.dtype == r.dtype
+    _check(load().gosim_lp_inputs(int(runs), int(n), _ptr(inv), int(periods_left), float(tau0),
+                                  _ptr(r), _ptr(c), _ptr(tau), _dt(r), _stream(stream)))
+
+
+def gosim_period(K: int, eta, r, prefs, u, inv, offer, sales, revenue, in_stock=None,
+                 stream=None) -> None:
+    """eta/r [runs, n], prefs [runs, N, n] (one dtype), u [runs, N] float64,
+    inv/sales [runs, n] int64, offer [runs, K] int32, revenue [runs] float64."""
+    runs, N, n = prefs.shape
+    assert eta.dtype == r.dtype == prefs.dtype and u.dtype == torch.float64
+    assert inv.dtype == sales.dtype == torch.int64 and offer.dtype == torch.int32
+    assert offer.shape == (runs, K) and sales.shape == (runs, n) and u.shape == (runs, N)
+    _check(load().gosim_period(int(runs), int(N), int(n), int(K), _ptr(eta), _ptr(r), _ptr(prefs),
+                               _ptr(u), _ptr(inv), _ptr(offer), _ptr(sales), _ptr(revenue),
+                               _ptr(in_stock), _dt(r), _stream(stream)))
+
+
+def gosim_run(b, periods: int, K: int, prefs, u, r, inv, eta, tau_work, params: SpfomParams,
+              tau0: float, offers, sales, revenue, lp_iters: Optional[np.ndarray] = None,
+              stream=None) -> None:
+    lp = None
+    if lp_iters is not None:
+        assert lp_iters.dtype == np.int64 and lp_iters.flags.c_contiguous
+        lp = ctypes.c_void_p(lp_iters.ctypes.data)
+    _check(load().gosim_run(ctypes.c_void_p(b), int(periods), int(K), _ptr(prefs), _ptr(u), _ptr(r),
+                            _ptr(inv), _ptr(eta), _ptr(tau_work), ctypes.byref(params), float(tau0),
+                            _ptr(offers), _ptr(sales), _ptr(revenue), lp, _stream(stream)))
+
+
+class GoSim:
+    """The GO bid-price policy on a market (``instances.Market``) for all its
+    runs: one handle per run over shared structure arrays and one
+    [runs, N, n] preference work buffer, batched together."""
+
+    def __init__(self, market, dtype=torch.float32, device="cuda"):
+        self.dtype, self.device = dtype, torch.device(device)
+        npdt = np.float32 if dtype == torch.float32 else np.float64
+        dev = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a, dtype=dt)).to(self.device)
+        R, T, N, n = market.runs, market.periods, market.customers, market.n
+        self.runs, self.periods, self.N, self.n = R, T, N, n
+        self.r = dev(market.r, npdt)
+        self.inv0 = np.ascontiguousarray(market.inv0, dtype=np.int64)
+        self.prefs = dev(market.prefs, npdt)
+        self.u = dev(market.u, np.float64)
+        self.seg_ptr = dev(np.arange(N + 1) * n, np.int64)
+        self.idx = dev(np.tile(np.arange(n), N), np.int32)
+        self.w = torch.zeros(N * n, dtype=dtype, device=self.device)
+        self.v0 = torch.ones(N, dtype=dtype, device=self.device)
+        self.lam = torch.ones(N, dtype=dtype, device=self.device)
+        self.v = self.prefs[0].clone() if T else torch.ones(R, N, n, dtype=dtype, device=self.device)
+        self.c = torch.zeros(R, n, dtype=dtype, device=self.device)
+        self.tau = torch.ones(R, n, dtype=dtype, device=self.device)
+        self.handles = []
+        try:
+            for q in range(R):
+                self.handles.append(cblp_create(N, n, n, self.seg_ptr, self.idx, self.v[q], self.w,
+                                                self.v0, self.lam, self.r[q], None, None, None,
+                                                self.c[q], _dt(self.r)))
+            self.b = cblp_batch_create(self.handles)
+        except Exception:
+            self.close()
+            raise
+
+    def close(self):
+        if getattr(self, "b", None):
+            cblp_batch_destroy(self.b)
+            self.b = None
+        for h in getattr(self, "handles", []):
+            cblp_destroy(h)
+        self.handles = []
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def run(self, K: int, params: SpfomParams, tau0: float, eta=None):
+        """All periods from the initial stock; returns a dict of offers
+        [T, runs, K], sales [T, runs, n], revenue [T, runs], lp_iters
+        [T, runs] (numpy), the final stock and the final duals (tensors)."""
+        T, R, n = self.periods, self.runs, self.n
+        inv = torch.from_numpy(self.inv0.copy()).to(self.device)
+        eta = torch.zeros(R, n, dtype=self.dtype, device=self.device) if eta is None else eta
+        offers = torch.empty(T, R, K, dtype=torch.int32, device=self.device)
+        sales = torch.empty(T, R, n, dtype=torch.int64, device=self.device)
+        revenue = torch.empty(T, R, dtype=torch.float64, device=self.device)
+        lp = np.zeros((T, R), dtype=np.int64)
+        gosim_run(self.b, T, K, self.prefs, self.u, self.r, inv, eta, self.tau, params, tau0,
+                  offers, sales, revenue, lp)
+        return {"offers": offers.cpu().numpy(), "sales": sales.cpu().numpy(),
+                "revenue": revenue.cpu().numpy(), "lp_iters": lp, "inv": inv, "eta": eta}
 
 
 # ------------------------------------------------------------ learned warm start

@@ -405,6 +405,7 @@ struct cblp_batch {
     int graph_K = 0;
     spfom_params graph_p{};          // the step parameters the graph was captured with
     std::vector<int64_t> t;          // per-instance iteration counts
+    std::vector<int> mask;           // 1: the instance takes part in iterate and solve calls
 };
 
 namespace {
@@ -667,6 +668,8 @@ int ensure_graph(cblp_batch* b, const spfom_params* p)
 
 }  // namespace
 
+const std::vector<cblp_instance*>& cblp::batch_handles(cblp_batch_t b) { return b->hs; }
+
 extern "C" {
 
 int cblp_batch_create(cblp_batch_t* out, int32_t count, const cblp_t* handles, void* stream)
@@ -685,6 +688,7 @@ int cblp_batch_create(cblp_batch_t* out, int32_t count, const cblp_t* handles, v
     b->hs.assign(handles, handles + count);
     b->dtype = b->hs[0]->dtype;
     b->t.assign(count, 0);
+    b->mask.assign(count, 1);
     int64_t Hmax = 1;
     for (int q = 0; q < count; ++q) {
         const cblp_instance* h = b->hs[q];
@@ -842,6 +846,7 @@ int spfom_batch_iterate(cblp_batch_t b, void* const* etas, const void* const* ta
     if (rc) return rc;
     hipStream_t caller = (hipStream_t)stream;
     if ((rc = enter(b, caller))) return rc;
+    for (int q = 0; q < b->count; ++q) b->h_inst[q].active = b->mask[q];
     if ((rc = bind(b, etas, tau_vecs, p, b->stream))) return rc;
     if ((rc = run_prices(b, b->stream))) return rc;
     if ((rc = run_iters(b, p, iters, b->stream))) return rc;
@@ -867,20 +872,21 @@ int spfom_batch_solve(cblp_batch_t b, void* const* etas, const void* const* tau_
     hipStream_t caller = (hipStream_t)stream;
     const auto t0 = std::chrono::steady_clock::now();
     if ((rc = enter(b, caller))) return rc;
-    for (int q = 0; q < b->count; ++q) b->h_inst[q].active = 1;
+    for (int q = 0; q < b->count; ++q) b->h_inst[q].active = b->mask[q];
     if ((rc = bind(b, etas, tau_vecs, p, b->stream))) return rc;
     if ((rc = reset_states(b, b->stream))) return rc;
     if ((rc = ensure_graph(b, p))) return rc;
     if ((rc = run_prices(b, b->stream))) return rc;
+    int live = 0;
     for (int q = 0; q < b->count; ++q) {
         std::memset(&outs[q], 0, sizeof(spfom_stats));
-        outs[q].status = CBLP_ENOTCONVERGED;
+        outs[q].status = b->mask[q] ? CBLP_ENOTCONVERGED : CBLP_OK;
+        live += b->mask[q];
     }
     // every active instance has done the same number of iterations t: run
     // blocks of K (the graph), the last one cut to max_iters - t (eager), and
     // test the gap after whole blocks only, as spfom_solve does
     const int64_t K = p->check_every;
-    int live = b->count;
     int64_t t = 0;
     while (live > 0 && t < p->max_iters) {
         const int64_t k = std::min<int64_t>(K, p->max_iters - t);
@@ -918,7 +924,7 @@ int spfom_batch_solve(cblp_batch_t b, void* const* etas, const void* const* tau_
             BHIP(hipMemcpyAsync(b->d_inst, b->h_inst.data(), b->count * sizeof(BInst),
                                 hipMemcpyHostToDevice, b->stream));
     }
-    for (int q = 0; q < b->count; ++q) b->h_inst[q].active = 1;
+    for (int q = 0; q < b->count; ++q) b->h_inst[q].active = b->mask[q];
     BHIP(hipMemcpyAsync(b->d_inst, b->h_inst.data(), b->count * sizeof(BInst),
                         hipMemcpyHostToDevice, b->stream));
     if ((rc = leave(b, caller))) return rc;
@@ -1002,6 +1008,14 @@ int cblp_batch_tune(cblp_batch_t b, void* const* etas, const void* const* tau_ve
     if (!rc) rc = reset_states(b, b->stream);
     const int rc2 = leave(b, caller);
     return rc ? rc : rc2;
+}
+
+int cblp_batch_mask(cblp_batch_t b, const int32_t* take_part)
+{
+    set_error(CBLP_OK, "");
+    if (!b) return bfail(CBLP_EINVAL, "batch is NULL");
+    for (int q = 0; q < b->count; ++q) b->mask[q] = take_part ? (take_part[q] != 0) : 1;
+    return CBLP_OK;
 }
 
 int cblp_batch_select(cblp_batch_t b, int32_t variant)

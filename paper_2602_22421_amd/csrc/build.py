@@ -13,7 +13,7 @@ PKG = os.path.dirname(HERE)
 ROOT = os.path.dirname(PKG)
 LIB = os.path.join(PKG, "libcblp.so")
 OBJDIR = os.path.join(HERE, "_build")
-NAMES = ("capi", "prep", "segment", "dual", "batch", "mlp", "recover", "minibatch", "noalloc")
+NAMES = ("capi", "prep", "segment", "dual", "batch", "mlp", "recover", "minibatch", "noalloc", "gosim")
 SOURCES = [os.path.join(HERE, f + ".hip") for f in NAMES
            if os.path.exists(os.path.join(HERE, f + ".hip"))]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

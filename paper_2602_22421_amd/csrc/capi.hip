@@ -525,10 +525,7 @@ int create_impl(cblp_instance* h, hipStream_t s)
     (void)hipFree(dflags);
     if (e2 != hipSuccess || e3 != hipSuccess) return fail(CBLP_EHIP, "validation kernel failed");
     if (flags) {
-        std::string msg = "invalid instance:";
-        for (int b = 0; b < V_NBITS; ++b)
-            if (flags & (1u << b)) msg += std::string(" ") + kValidationText[b] + ";";
-        return fail(CBLP_EINVAL, msg);
+        return fail(CBLP_EINVAL, cblp::validation_message(flags));
     }
 
     // launch shape: every resident 1024-thread segment block of every CU, each
@@ -763,6 +760,24 @@ int create_impl(cblp_instance* h, hipStream_t s)
 
 }  // namespace
 
+std::string cblp::validation_message(unsigned flags)
+{
+    std::string msg = "invalid instance:";
+    for (int b = 0; b < V_NBITS; ++b)
+        if (flags & (1u << b)) msg += std::string(" ") + kValidationText[b] + ";";
+    return msg;
+}
+
+int cblp::reset_handle_state(cblp_instance* h, hipStream_t s) { return reset_state(h, s); }
+
+int cblp::refresh_launch(cblp_instance* h, unsigned* flags, hipStream_t s)
+{
+    HIP_TRY(h->dtype == CBLP_F32 ? launch_refresh<float>(h, flags, s)
+                                 : launch_refresh<double>(h, flags, s));
+    h->mb_clear = true;
+    return CBLP_OK;
+}
+
 extern "C" {
 
 const char* cblp_last_error(void) { return g_err.c_str(); }
@@ -830,6 +845,28 @@ int cblp_create(cblp_t* out, int64_t L, int64_t n, int64_t m, const int64_t* seg
 }
 
 void cblp_destroy(cblp_t h) { release(h); }
+
+int cblp_refresh(cblp_t h, void* stream)
+{
+    g_err.clear();
+    if (!h) return fail(CBLP_EINVAL, "handle is NULL");
+    hipStream_t s = S(stream);
+    unsigned* dflags = nullptr;
+    int rc;
+    if ((rc = dalloc(&dflags, sizeof(unsigned)))) return rc;
+    unsigned flags = 0;
+    hipError_t e0 = hipMemsetAsync(dflags, 0, sizeof(unsigned), s);
+    rc = e0 == hipSuccess ? refresh_launch(h, dflags, s) : fail(CBLP_EHIP, "hipMemsetAsync failed");
+    hipError_t e1 = rc == CBLP_OK ? hipMemcpyAsync(&flags, dflags, sizeof(unsigned),
+                                                   hipMemcpyDeviceToHost, s)
+                                  : hipSuccess;
+    hipError_t e2 = hipStreamSynchronize(s);
+    (void)hipFree(dflags);
+    if (rc) return rc;
+    if (e1 != hipSuccess || e2 != hipSuccess) return fail(CBLP_EHIP, "refresh kernel failed");
+    if (flags) return fail(CBLP_EINVAL, validation_message(flags));
+    return reset_state(h, s);
+}
 
 int spfom_reset(cblp_t h, void* stream)
 {

@@ -101,3 +101,19 @@ struct cblp_instance {
     std::vector<std::pair<int, size_t>> ev_marks;
 };
 
+
+namespace cblp {
+// Re-read the caller's v, w (and check c) into the handle's copies, on the
+// structure of creation; invalid values set validation bits in *flags.
+template <typename T>
+hipError_t launch_refresh(const cblp_instance* h, unsigned* flags, hipStream_t s);
+// Launch the refresh of h on s (flags: a device word the caller clears and
+// reads); also marks the handle's kept per-entry minibatch sales stale.
+int refresh_launch(cblp_instance* h, unsigned* flags, hipStream_t s);
+// Reset the handle's solver state (as spfom_reset).
+int reset_handle_state(cblp_instance* h, hipStream_t s);
+// The text of validation bits, for error messages.
+std::string validation_message(unsigned flags);
+// The handles a batch was built over, in order.
+const std::vector<cblp_instance*>& batch_handles(cblp_batch_t b);
+}  // namespace cblp

@@ -1,6 +1,6 @@
 // Instance validation, the library's sorted copy of the instance, arrival-rate
 // bounds and the price step.
-#include "common.hpp"
+#include "handle.hpp"
 
 #include <algorithm>
 
@@ -142,6 +142,61 @@ __global__ void k_relayout_slots(int64_t L, const int64_t* ptr, const int32_t* i
     }
 }
 
+// New attractions and capacities on the structure of creation: re-read the
+// caller's v and w (the row pointers, product ids, arrival rates and
+// no-purchase attractions are those the copies were built from) into the
+// sorted copy (v2, den2, vt0 as k_relayout writes them) and into the
+// slot-major copy of whichever part holds each position (the places
+// k_relayout_slots gives them); warm starts go back to zero.  Flags invalid
+// v, w and c as k_validate does.
+template <typename T>
+__global__ void k_refresh(int64_t L, int64_t m, const int64_t* seg_ptr, const T* v, const T* w,
+                          const T* v0, const T* c, const int32_t* perm, const int64_t* ptr2,
+                          const int64_t* woff, int64_t pair_end, int64_t quad_end,
+                          int64_t woff_q, int64_t woff_b, T* v2, T* den2, T* vt0, T* Rwarm,
+                          T* v3, T* den3, unsigned* flags)
+{
+    unsigned bad = 0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (int64_t p = tid; p < L; p += stride) {
+        const int64_t l = perm[p];
+        const int64_t b = seg_ptr[l], k = seg_ptr[l + 1] - b, d = ptr2[p];
+        int64_t G, base;
+        if (p < pair_end) {
+            G = 2;
+            base = woff[p / 32] + 2 * (p % 32);
+        } else if (p < quad_end) {
+            const int64_t q = p - pair_end;
+            G = 4;
+            base = woff[woff_q + q / 16] + 4 * (q % 16);
+        } else {
+            const int64_t q = p - quad_end;
+            G = kGroup;
+            base = woff[woff_b + q / kGroup] + kGroup * (q % kGroup);
+        }
+        double s = (double)v0[l];
+        for (int64_t t = 0; t < k; ++t) {
+            const T x = v[b + t], y = w[b + t];
+            if (!(x > T(0)) || !isfinite(x)) bad |= V_V;
+            if (!(y >= T(0)) || !(y < x)) bad |= V_W;
+            v2[d + t] = x;
+            den2[d + t] = x - y;
+            s += (double)y;
+            const int64_t e = base + 64 * (t / G) + t % G;
+            v3[e] = x;
+            den3[e] = x - y;
+        }
+        vt0[p] = (T)s;
+        Rwarm[p] = T(0);
+    }
+    for (int64_t i = tid; i < m; i += stride) {
+        const T x = c[i];
+        if (!(x >= T(0)) || !isfinite(x)) bad |= V_C;
+    }
+    if (bad) atomicOr(flags, bad);
+}
+
 // Degrees of the products [lo, lo + kDegBins): per-block LDS counts over the
 // block's share of the entries, then one global atomic per nonzero bin.
 constexpr int kDegBins = 16384;
@@ -268,6 +323,18 @@ hipError_t launch_relayout_slots(int64_t L, const int64_t* ptr, const int32_t* i
 }
 
 template <typename T>
+hipError_t launch_refresh(const cblp_instance* h, unsigned* flags, hipStream_t s)
+{
+    const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>(2048, (h->L + 255) / 256));
+    hipLaunchKernelGGL(k_refresh<T>, dim3((unsigned)blocks), dim3(256), 0, s, h->L, h->m,
+                       h->seg_ptr, (const T*)h->v, (const T*)h->w, (const T*)h->v0,
+                       (const T*)h->c, h->perm, h->ptr2, h->woff, h->pair_end, h->quad_end,
+                       h->woff_q, h->woff_b, (T*)h->v2, (T*)h->den2, (T*)h->vt0, (T*)h->Rwarm,
+                       (T*)h->v3, (T*)h->den3, flags);
+    return hipGetLastError();
+}
+
+template <typename T>
 hipError_t launch_prices(int64_t n, const void* r, const void* eta, const int64_t* a_ptr,
                          const int32_t* a_idx, const void* a_val, const int32_t* pnew, void* rho,
                          hipStream_t s)
@@ -297,7 +364,8 @@ hipError_t launch_prices(int64_t n, const void* r, const void* eta, const int64_
     template hipError_t launch_relayout_slots<T>(int64_t, const int64_t*, const int32_t*,      \
                                                  const void*, const void*, const int64_t*,     \
                                                  int64_t, void*, bool, int, void*, void*,        \
-                                                 hipStream_t);
+                                                 hipStream_t);                                 \
+    template hipError_t launch_refresh<T>(const cblp_instance*, unsigned*, hipStream_t);
 CBLP_INST(float)
 CBLP_INST(double)
 #undef CBLP_INST
