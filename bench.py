@@ -388,6 +388,92 @@ def recover_bench(args):
     prob.close()
 
 
+def gosim_bench(args):
+    """The GO bid-price policy on the market of Figure 4 (Section 5.1): runs
+    independent runs of T batches of N customers over n products, K offered
+    per batch; every batch with more than K products in stock re-solves its
+    LP by SPFOM (all runs in one batched solve, warm-started from the
+    previous batch's duals).  Reports simulated customers per second, the
+    time per batch and the LP iterations; the oracle's closed loop, timed on
+    a bounded sample, is the CPU baseline."""
+    import torch
+    from paper_2602_22421_amd import cblp
+    from paper_2602_22421_amd.instances import gosim_market
+    dt = torch.float32 if args.dtype == "f32" else torch.float64
+    npdt = np.float32 if args.dtype == "f32" else np.float64
+    t0 = time.perf_counter()
+    mk = gosim_market(args.gs_runs, n=args.gs_products, periods=args.gs_periods,
+                      customers=args.gs_customers, seed=0, dtype=npdt)
+    log(f"market: {mk.runs} runs x {mk.periods} batches x {mk.customers} customers x "
+        f"{mk.n} products in {time.perf_counter() - t0:.1f} s")
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle import gosim as ogs
+        kw = dict(tau0=args.gs_tau0, tol=args.gs_tol, max_iters=args.gs_max_iters,
+                  check_every=10, rule=1 if args.gs_rule == "polyak" else 0,
+                  tau_decay=args.gs_decay, decay_every=args.gs_decay_every)
+        t0 = time.perf_counter()
+        ogs.simulate(mk.r[0], mk.inv0[0], mk.prefs[:, 0], mk.u[:, 0], args.gs_k, batches=1, **kw)
+        first = time.perf_counter() - t0
+        done = int(max(1, min(mk.periods, args.oracle_seconds / max(first, 1e-3))))
+        t0 = time.perf_counter()
+        ogs.simulate(mk.r[0], mk.inv0[0], mk.prefs[:, 0], mk.u[:, 0], args.gs_k, batches=done,
+                     **kw)
+        el = time.perf_counter() - t0
+        cpu = {"value": done * mk.customers / el, "unit": "customers/s", "cores": 1,
+               "kind": "oracle",
+               "sample": f"run 0 of the market, its first {done} of {mk.periods} batches "
+                         f"({el:.1f} s, FP64)"}
+        log(f"oracle: {cpu['value']:.3e} customers/s")
+    sim = cblp.GoSim(mk, dtype=dt)
+    rule = cblp.SPFOM_STEP_POLYAK if args.gs_rule == "polyak" else cblp.SPFOM_STEP_CONST
+    params = cblp.make_params(rule=rule, tau=1.0, check_every=10, tol=args.gs_tol,
+                              max_iters=args.gs_max_iters, tau_decay=args.gs_decay,
+                              decay_every=args.gs_decay_every)
+    sim.run(args.gs_k, params, args.gs_tau0)          # warm-up: graph capture
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = sim.run(args.gs_k, params, args.gs_tau0)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    customers = mk.runs * mk.periods * mk.customers
+    solved = out["lp_iters"] > 0
+    cum = out["revenue"].sum(axis=0)
+    # the same market without bid prices (duals held at zero: the K highest
+    # prices in stock offered every batch), for scale
+    zero = cblp.make_params(rule=cblp.SPFOM_STEP_CONST, tau=1.0, check_every=10, tol=0.0,
+                            max_iters=0)
+    flat = sim.run(args.gs_k, zero, args.gs_tau0)["revenue"].sum(axis=0)
+    log(f"GO: {el:.2f} s for {mk.periods} batches x {mk.runs} runs ({customers / el:.3e} "
+        f"customers/s); LPs solved in {solved.mean():.0%} of batches, "
+        f"{out['lp_iters'][solved].mean() if solved.any() else 0:.0f} iterations each, median "
+        f"gap {np.median(out['lp_gap'][solved]) if solved.any() else 0:.2e}; "
+        f"revenue per run {cum.mean():.1f} (zero duals: {flat.mean():.1f})")
+    res = {"metric": "simulated customers/s, GO bid-price policy with batched SPFOM re-solves",
+           "value": customers / el, "unit": "customers/s", "higher_is_better": True,
+           "n_gpus": 1, "dtype": args.dtype, "data": "synthetic", "vs_baseline": None,
+           "ms_per_batch": el / mk.periods * 1e3,
+           "config": {"workload": f"go-bid-price-{mk.runs}runs-{mk.periods}x{mk.customers}-"
+                                  f"n{mk.n}-K{args.gs_k}",
+                      "runs": mk.runs, "batches": mk.periods, "customers": mk.customers,
+                      "products": mk.n, "K": args.gs_k, "tol": args.gs_tol,
+                      "max_iters": args.gs_max_iters, "tau0": args.gs_tau0,
+                      "step_rule": args.gs_rule, "tau_decay": args.gs_decay,
+                      "decay_every": args.gs_decay_every},
+           "lp": {"solved_fraction": float(solved.mean()),
+                  "median_gap": float(np.median(out["lp_gap"][solved])) if solved.any() else 0.0,
+                  "converged_fraction": float((out["lp_gap"][solved] <= args.gs_tol).mean())
+                  if solved.any() else 0.0,
+                  "mean_iters": float(out["lp_iters"][solved].mean()) if solved.any() else 0.0,
+                  "max_iters_hit": int((out["lp_iters"] >= args.gs_max_iters).sum())},
+           "revenue": {"mean_per_run": float(cum.mean()), "std_per_run": float(cum.std()),
+                       "zero_duals_mean_per_run": float(flat.mean()),
+                       "per_batch_mean": out["revenue"].mean(axis=1).round(3).tolist()},
+           "cpu_baseline": cpu}
+    print(json.dumps(res), flush=True)
+    sim.close()
+
+
 def warmstart_bench(args):
     """Learned warm start: train the network on the duals of solved L=1e5
     instances of the L=2e6 Zipf generator, then solve held-out L=2e6 instances
@@ -534,6 +620,19 @@ def main():
                     help="stochastic minibatch SPFOM: sampled segment-updates/s per B")
     ap.add_argument("--mb-fracs", nargs="+", default=["0.1", "0.01"],
                     help="minibatch mode: B as fractions of L")
+    ap.add_argument("--gosim", action="store_true",
+                    help="the GO bid-price policy simulation on the market of Figure 4")
+    ap.add_argument("--gs-runs", type=int, default=30)
+    ap.add_argument("--gs-periods", type=int, default=100)
+    ap.add_argument("--gs-customers", type=int, default=1000)
+    ap.add_argument("--gs-products", type=int, default=40)
+    ap.add_argument("--gs-k", type=int, default=2)
+    ap.add_argument("--gs-tol", type=float, default=1e-2)
+    ap.add_argument("--gs-max-iters", type=int, default=1000)
+    ap.add_argument("--gs-tau0", type=float, default=0.03)
+    ap.add_argument("--gs-rule", default="const", choices=["const", "polyak"])
+    ap.add_argument("--gs-decay", type=float, default=0.7)
+    ap.add_argument("--gs-decay-every", type=int, default=100)
     ap.add_argument("--recover", action="store_true",
                     help="time the SBLP -> CBLP recovery of one pass's sales")
     ap.add_argument("--levels", nargs="+", default=["1e-2", "3e-3", "1e-3"],
@@ -576,7 +675,7 @@ def main():
         sys.exit(2)
 
     if (args.batched or args.warmstart or args.copy_calibration or args.time_to_gap
-            or args.minibatch or args.recover):
+            or args.minibatch or args.recover or args.gosim):
         import torch
         from paper_2602_22421_amd import cblp
         cblp.load()
@@ -590,6 +689,8 @@ def main():
             return minibatch_bench(args)
         if args.recover:
             return recover_bench(args)
+        if args.gosim:
+            return gosim_bench(args)
         if args.time_to_gap:
             if "--max-iters" not in sys.argv:
                 args.max_iters = 20000

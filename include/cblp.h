@@ -354,7 +354,7 @@ int cblp_batch_mask(cblp_batch_t b, const int32_t* take_part);
  * The global optimisation (GO) policy of Section 5.1 with bid-price control,
  * on the synthetic market of Figure 4, for `runs` independent runs at once.
  * In every batch (period) t of T and run: products out of stock leave the
- * offer; if at most K remain they are all offered; otherwise the batch's
+ * offer and the LP; if at most K remain they are all offered; otherwise the batch's
  * sales-based LP is re-solved by SPFOM from the previous batch's duals and
  * the bid-price rule offers the products with r_j - eta_j >= 0, cut to the K
  * largest margins (ties: lower j).  The batch's customers then choose under
@@ -375,12 +375,17 @@ int cblp_batch_mask(cblp_batch_t b, const int32_t* take_part);
  * 1 <= K <= 64.
  */
 
-/* Capacities and dual steps of the current batch's LP, for every run:
- * c_j = inv_j / periods_left and tau_j = tau0 max_k r_k / c_j (zero capacity:
- * the smallest positive one's step, or capacity 1 if none), each rounded
- * once to dtype (tau from the rounded c).  [dev] inv, r in; c, tau out. */
+/* Capacities, dual steps and starting duals of the current batch's LP, for
+ * every run: c_j = inv_j / periods_left and tau_j = tau0 max_k r_k / c_j
+ * (zero capacity: the smallest positive one's step, or capacity 1 if none),
+ * each rounded once to dtype (tau from the rounded c); a product out of
+ * stock leaves the LP - its dual is raised to at least r_j, where its
+ * margin r_j - eta_j <= 0 keeps it out of every segment's assortment (zero
+ * sales at zero capacity, no term in c . eta), and the step leaves it there.
+ * [dev] inv, r in; c, tau out; eta (nullable) in/out. */
 int gosim_lp_inputs(int32_t runs, int64_t n, const int64_t* inv, int64_t periods_left,
-                    double tau0, const void* r, void* c, void* tau, int32_t dtype, void* stream);
+                    double tau0, const void* r, void* c, void* tau, void* eta, int32_t dtype,
+                    void* stream);
 
 /* One batch of every run at the given duals: the offer, the N customers'
  * choices, sales and the stock left.  [dev] eta, r, prefs [runs x N x n]
@@ -403,12 +408,13 @@ int gosim_period(int32_t runs, int64_t N, int64_t n, int32_t K, const void* eta,
  * rule; tau_vec unused - each run steps by its tau_work row; an instance
  * that does not reach tol keeps its last duals) from eta [dev] [runs x n]
  * (in/out: the duals carried from batch to batch), then gosim_period.
- * lp_iters [host] [T x runs] (nullable): SPFOM iterations per batch and run
- * (0: no LP solved).  The batch's participation mask is cleared on return. */
+ * lp_iters, lp_gap [host] [T x runs] (nullable): SPFOM iterations and the
+ * last certified gap per batch and run (0: no LP solved).  The batch's
+ * participation mask is cleared on return. */
 int gosim_run(cblp_batch_t b, int32_t periods, int32_t K, const void* prefs, const double* u,
               const void* r, int64_t* inv, void* eta, void* tau_work, const spfom_params* p,
               double tau0, int32_t* offers, int64_t* sales, double* revenue, int64_t* lp_iters,
-              void* stream);
+              double* lp_gap, void* stream);
 
 /* ---------------------------------------------------------- learned warm start
  * A small network maps four features of each product to a starting capacity

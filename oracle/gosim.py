@@ -27,7 +27,9 @@ readings):
   min(demand, inventory) units (the later customers of a sold-out product go
   without);
 * the LP of each batch starts from the previous batch's duals (zero in the
-  first), with the solver state reset.
+  first), with the solver state reset; a product out of stock leaves that LP
+  by a dual raised to its revenue (no assortment then holds it, which is the
+  LP with the product removed).
 """
 from __future__ import annotations
 
@@ -51,6 +53,18 @@ def lp_inputs(inv, periods_left: int, r, tau0: float, dtype=np.float64):
     rmax = float(np.max(np.asarray(r, dtype=np.float64)))
     tau = (tau0 * rmax / np.where(pos, cd, cmin)).astype(dt)
     return c, tau
+
+
+def sold_out_duals(inv, eta, r):
+    """The LP without the products out of stock: each such product's dual is
+    raised to at least its revenue, so its margin r_j - eta_j <= 0 keeps it
+    out of every segment's best response (zero sales at zero capacity) and
+    c_j eta_j = 0 adds nothing to the dual value."""
+    eta = np.array(eta, dtype=np.float64, copy=True)
+    r = np.asarray(r, dtype=np.float64)
+    out = np.asarray(inv) == 0
+    eta[out] = np.maximum(eta[out], r[out])
+    return eta
 
 
 def offer(inv, eta, r, K: int):
@@ -102,24 +116,28 @@ def period(inv, eta, r, prefs, u, K: int):
 
 def simulate(r, inv0, prefs, u, K: int, *, tau0: float, tol: float, max_iters: int,
              check_every: int = 10, tau_decay: float = 1.0, decay_every: int = 1,
-             eta0=None):
-    """The GO policy over the batches of one run.  prefs [T, N, n], u [T, N].
+             rule: int = oracle.RULE_CONST, gamma: float = 1.0, eta0=None, batches=None):
+    """The GO policy over the batches of one run.  prefs [T, N, n], u [T, N];
+    ``batches`` stops after that many of the T batches (the horizon stays T).
     Returns a dict of per-batch offers, sales, revenue, inventory after the
-    batch, LP iterations (0 where the LP was not solved) and the duals used."""
+    batch, LP iterations and last certified gap (0 where the LP was not
+    solved) and the duals used."""
     T, N, n = prefs.shape
     inv = np.asarray(inv0, dtype=np.int64).copy()
     eta = np.zeros(n) if eta0 is None else np.array(eta0, dtype=np.float64)
     out = dict(offers=[], sales=np.zeros((T, n), dtype=np.int64), revenue=np.zeros(T),
                inv=np.zeros((T, n), dtype=np.int64), iters=np.zeros(T, dtype=np.int64),
-               eta=np.zeros((T, n)))
-    for t in range(T):
+               gap=np.zeros(T), eta=np.zeros((T, n)))
+    for t in range(T if batches is None else min(T, int(batches))):
         if int(np.count_nonzero(inv > 0)) > K:
             c, tau = lp_inputs(inv, T - t, r, tau0, prefs.dtype)
+            eta = sold_out_duals(inv, eta, r)
             inst = market_instance(np.asarray(prefs[t]), np.asarray(r), c)
-            s = oracle.Solver(inst, tau=tau, check_every=check_every,
+            s = oracle.Solver(inst, tau=tau, rule=rule, gamma=gamma, check_every=check_every,
                               tau_decay=tau_decay, decay_every=decay_every)
-            eta, _, _ = s.solve(eta, tol, max_iters)
+            eta, last, _ = s.solve(eta, tol, max_iters)
             out["iters"][t] = s.t
+            out["gap"][t] = last[7] if last is not None else 0.0
         S, sales, inv, rev = period(inv, eta, r, prefs[t], u[t], K)
         out["offers"].append(S)
         out["sales"][t] = sales

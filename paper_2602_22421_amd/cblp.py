@@ -133,12 +133,12 @@ def load(path: str = _LIB_PATH) -> ctypes.CDLL:
     lib.cblp_batch_mask.restype = ctypes.c_int
     lib.cblp_batch_mask.argtypes = [vp, vp]
     lib.gosim_lp_inputs.restype = ctypes.c_int
-    lib.gosim_lp_inputs.argtypes = [i32, i64, vp, i64, ctypes.c_double, vp, vp, vp, i32, vp]
+    lib.gosim_lp_inputs.argtypes = [i32, i64, vp, i64, ctypes.c_double, vp, vp, vp, vp, i32, vp]
     lib.gosim_period.restype = ctypes.c_int
     lib.gosim_period.argtypes = [i32, i64, i64, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, i32, vp]
     lib.gosim_run.restype = ctypes.c_int
     lib.gosim_run.argtypes = [vp, i32, i32, vp, vp, vp, vp, vp, vp, ctypes.POINTER(SpfomParams),
-                              ctypes.c_double, vp, vp, vp, vp, vp]
+                              ctypes.c_double, vp, vp, vp, vp, vp, vp]
     lib.cblp_last_error.restype = ctypes.c_char_p
     lib.cblp_last_error.argtypes = []
     lib.wsnet_num_params.restype = i64
@@ -547,12 +547,14 @@ def _dt(t: torch.Tensor) -> int:
     return CBLP_F32 if t.dtype == torch.float32 else CBLP_F64
 
 
-def gosim_lp_inputs(inv, periods_left: int, tau0: float, r, c, tau, stream=None) -> None:
-    """inv [runs, n] int64, r/c/tau [runs, n] (one dtype), device tensors."""
+def gosim_lp_inputs(inv, periods_left: int, tau0: float, r, c, tau, eta=None,
+                    stream=None) -> None:
+    """inv [runs, n] int64, r/c/tau/eta [runs, n] (one dtype), device tensors."""
     runs, n = r.shape
     assert inv.dtype == torch.int64 and inv.shape == r.shape and c.dtype == tau.dtype == r.dtype
+    assert eta is None or (eta.dtype == r.dtype and eta.shape == r.shape)
     _check(load().gosim_lp_inputs(int(runs), int(n), _ptr(inv), int(periods_left), float(tau0),
-                                  _ptr(r), _ptr(c), _ptr(tau), _dt(r), _stream(stream)))
+                                  _ptr(r), _ptr(c), _ptr(tau), _ptr(eta), _dt(r), _stream(stream)))
 
 
 def gosim_period(K: int, eta, r, prefs, u, inv, offer, sales, revenue, in_stock=None,
@@ -570,14 +572,17 @@ def gosim_period(K: int, eta, r, prefs, u, inv, offer, sales, revenue, in_stock=
 
 def gosim_run(b, periods: int, K: int, prefs, u, r, inv, eta, tau_work, params: SpfomParams,
               tau0: float, offers, sales, revenue, lp_iters: Optional[np.ndarray] = None,
-              stream=None) -> None:
-    lp = None
+              lp_gap: Optional[np.ndarray] = None, stream=None) -> None:
+    lp = gp = None
     if lp_iters is not None:
         assert lp_iters.dtype == np.int64 and lp_iters.flags.c_contiguous
         lp = ctypes.c_void_p(lp_iters.ctypes.data)
+    if lp_gap is not None:
+        assert lp_gap.dtype == np.float64 and lp_gap.flags.c_contiguous
+        gp = ctypes.c_void_p(lp_gap.ctypes.data)
     _check(load().gosim_run(ctypes.c_void_p(b), int(periods), int(K), _ptr(prefs), _ptr(u), _ptr(r),
                             _ptr(inv), _ptr(eta), _ptr(tau_work), ctypes.byref(params), float(tau0),
-                            _ptr(offers), _ptr(sales), _ptr(revenue), lp, _stream(stream)))
+                            _ptr(offers), _ptr(sales), _ptr(revenue), lp, gp, _stream(stream)))
 
 
 class GoSim:
@@ -630,8 +635,9 @@ class GoSim:
 
     def run(self, K: int, params: SpfomParams, tau0: float, eta=None):
         """All periods from the initial stock; returns a dict of offers
-        [T, runs, K], sales [T, runs, n], revenue [T, runs], lp_iters
-        [T, runs] (numpy), the final stock and the final duals (tensors)."""
+        [T, runs, K], sales [T, runs, n], revenue [T, runs], lp_iters and
+        lp_gap [T, runs] (numpy), the final stock and the final duals
+        (tensors)."""
         T, R, n = self.periods, self.runs, self.n
         inv = torch.from_numpy(self.inv0.copy()).to(self.device)
         eta = torch.zeros(R, n, dtype=self.dtype, device=self.device) if eta is None else eta
@@ -639,10 +645,12 @@ class GoSim:
         sales = torch.empty(T, R, n, dtype=torch.int64, device=self.device)
         revenue = torch.empty(T, R, dtype=torch.float64, device=self.device)
         lp = np.zeros((T, R), dtype=np.int64)
+        gap = np.zeros((T, R))
         gosim_run(self.b, T, K, self.prefs, self.u, self.r, inv, eta, self.tau, params, tau0,
-                  offers, sales, revenue, lp)
+                  offers, sales, revenue, lp, gap)
         return {"offers": offers.cpu().numpy(), "sales": sales.cpu().numpy(),
-                "revenue": revenue.cpu().numpy(), "lp_iters": lp, "inv": inv, "eta": eta}
+                "revenue": revenue.cpu().numpy(), "lp_iters": lp, "lp_gap": gap, "inv": inv,
+                "eta": eta}
 
 
 # ------------------------------------------------------------ learned warm start

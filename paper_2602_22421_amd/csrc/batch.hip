@@ -89,6 +89,7 @@ struct BArgs {
     double gamma, mu;
     double tau_decay;          // CONST: step tau * tau_decay^k in iterations kE+1..(k+1)E
     long long decay_every;     // E
+    unsigned* counter;         // the segment kernel's work counter, cleared by k_bfold
 };
 
 // the fields row_work reads, for one instance
@@ -104,7 +105,6 @@ struct RowView {
 
 __device__ __forceinline__ int current(const DevState* st) { return st[0].t >= st[1].t ? 0 : 1; }
 
-__global__ void k_reset_counter(unsigned* counter) { *counter = 0u; }
 
 // MODE 0: prices gathered from global memory; 1: the item's instance prices
 // copied into LDS behind the largest instance's bins (Hmax), then gathered
@@ -177,6 +177,9 @@ __global__ void __launch_bounds__(kFoldThreads) k_bfold(BArgs b)
     using namespace dual;
     __shared__ unsigned long long red[kFoldChunks][kFoldProducts];
     __shared__ double sh[NR * 16];
+    // the segment pass of this iteration has ended: its work counter starts
+    // the next one from zero
+    if (blockIdx.x == 0 && threadIdx.x == 0) *b.counter = 0u;
     const BChunk f = b.fold[blockIdx.x];   // blockIdx-indexed: scalar loads
     const BInst* I = b.inst + f.inst;
     if (!I->active) return;
@@ -511,10 +514,10 @@ int enqueue_iterations(cblp_batch* b, const spfom_params* p, int64_t iters, hipS
     a.mu = p->mu;
     a.tau_decay = p->tau_decay;
     a.decay_every = p->decay_every;
+    a.counter = b->counter;
     const size_t lds = bseg_lds(b, b->variant);
     const void* segf = bseg_fn<T>(b->variant);
     for (int64_t it = 0; it < iters; ++it) {
-        hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(1), 0, s, b->counter);
         void* sargs[] = {(void*)&b->d_inst, (void*)&b->d_items, (void*)&b->nitems,
                          (void*)&b->counter, (void*)&b->part_S, (void*)&b->zpart,
                          (void*)&b->Hmax};
@@ -814,6 +817,8 @@ int cblp_batch_create(cblp_batch_t* out, int32_t count, const cblp_t* handles, v
     if ((rc = balloc(&b->st, (size_t)count * 2 * sizeof(DevState)))) return bail(rc);
     if ((rc = balloc(&b->rows, (size_t)count * SPFOM_NTRACE * 8))) return bail(rc);
     if ((rc = balloc(&b->counter, 16))) return bail(rc);
+    if (hipMemsetAsync(b->counter, 0, 16, s) != hipSuccess)   // then cleared by every k_bfold
+        return bail(bfail(CBLP_EHIP, "hipMemsetAsync of the work counter failed"));
     if (hipHostMalloc((void**)&b->pinned, (size_t)count * SPFOM_NTRACE * 8, hipHostMallocDefault) != hipSuccess)
         return bail(bfail(CBLP_ENOMEM, "hipHostMalloc failed"));
     for (int q = 0; q < count; ++q) {

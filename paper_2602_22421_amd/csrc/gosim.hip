@@ -1,9 +1,10 @@
 // Bid-price control with the global optimisation (GO) policy of Section 5.1,
 // simulated for many independent runs at once on the market of Figure 4.
 //
-// Per batch of customers and run: products out of stock leave the offer; if
-// at most K remain they are all offered, otherwise the batch's sales-based LP
-// (its customers as segments, capacities = stock spread over the batches
+// Per batch of customers and run: products out of stock leave the offer (and
+// the LP: their duals start at their revenue, so no assortment holds them);
+// if at most K remain they are all offered, otherwise the batch's sales-based
+// LP (its customers as segments, capacities = stock spread over the batches
 // left) is re-solved by SPFOM from the previous batch's duals - all runs
 // together as one batched solve - and the bid-price rule offers the products
 // with r_j - eta_j >= 0, cut to the K largest margins.  Customers then choose
@@ -46,11 +47,12 @@ __device__ __noinline__ double add_product(double acc, double a, double b)
 
 // c_j = inv_j / periods_left rounded once to T; tau_j = tau0 max_k r_k / c_j
 // from the rounded capacities (zero capacity: the smallest positive one, or
-// 1 if there is none), rounded once to T.  Block q handles run q.
+// 1 if there is none), rounded once to T; a product out of stock has its dual
+// raised to at least its revenue (eta nullable).  Block q handles run q.
 template <typename T>
 __global__ void __launch_bounds__(256) k_lp_inputs(int64_t n, const int64_t* inv,
                                                    double periods_left, double tau0, const T* r,
-                                                   T* c, T* tau)
+                                                   T* c, T* tau, T* eta)
 {
     __shared__ double smax[256], smin[256];
     const int64_t off = (int64_t)blockIdx.x * n;
@@ -58,6 +60,7 @@ __global__ void __launch_bounds__(256) k_lp_inputs(int64_t n, const int64_t* inv
     for (int64_t j = threadIdx.x; j < n; j += 256) {
         const T cj = (T)((double)inv[off + j] / periods_left);
         c[off + j] = cj;
+        if (eta && inv[off + j] == 0 && eta[off + j] < r[off + j]) eta[off + j] = r[off + j];
         rmax = fmax(rmax, (double)r[off + j]);
         if ((double)cj > 0.0) cmin = fmin(cmin, (double)cj);
     }
@@ -257,11 +260,12 @@ int check_sizes(int32_t runs, int64_t N, int64_t n, int32_t K, int32_t dtype)
 
 template <typename T>
 hipError_t launch_lp_inputs(int32_t runs, int64_t n, const int64_t* inv, int64_t periods_left,
-                            double tau0, const void* r, void* c, void* tau, hipStream_t s)
+                            double tau0, const void* r, void* c, void* tau, void* eta,
+                            hipStream_t s)
 {
     if (runs > 0)
         hipLaunchKernelGGL(k_lp_inputs<T>, dim3(runs), dim3(256), 0, s, n, inv,
-                           (double)periods_left, tau0, (const T*)r, (T*)c, (T*)tau);
+                           (double)periods_left, tau0, (const T*)r, (T*)c, (T*)tau, (T*)eta);
     return hipGetLastError();
 }
 
@@ -286,7 +290,8 @@ using namespace cblp;
 extern "C" {
 
 int gosim_lp_inputs(int32_t runs, int64_t n, const int64_t* inv, int64_t periods_left,
-                    double tau0, const void* r, void* c, void* tau, int32_t dtype, void* stream)
+                    double tau0, const void* r, void* c, void* tau, void* eta, int32_t dtype,
+                    void* stream)
 {
     set_error(CBLP_OK, "");
     int rc = check_sizes(runs, 0, n, 1, dtype);
@@ -295,8 +300,8 @@ int gosim_lp_inputs(int32_t runs, int64_t n, const int64_t* inv, int64_t periods
     if (!(tau0 > 0.0)) return set_error(CBLP_EINVAL, "tau0 must be > 0");
     if (runs > 0 && (!inv || !r || !c || !tau)) return set_error(CBLP_EINVAL, "NULL array");
     hipStream_t s = (hipStream_t)stream;
-    GS_TRY(dtype == CBLP_F32 ? launch_lp_inputs<float>(runs, n, inv, periods_left, tau0, r, c, tau, s)
-                             : launch_lp_inputs<double>(runs, n, inv, periods_left, tau0, r, c, tau, s));
+    GS_TRY(dtype == CBLP_F32 ? launch_lp_inputs<float>(runs, n, inv, periods_left, tau0, r, c, tau, eta, s)
+                             : launch_lp_inputs<double>(runs, n, inv, periods_left, tau0, r, c, tau, eta, s));
     return CBLP_OK;
 }
 
@@ -319,7 +324,7 @@ int gosim_period(int32_t runs, int64_t N, int64_t n, int32_t K, const void* eta,
 int gosim_run(cblp_batch_t b, int32_t periods, int32_t K, const void* prefs, const double* u,
               const void* r, int64_t* inv, void* eta, void* tau_work, const spfom_params* p,
               double tau0, int32_t* offers, int64_t* sales, double* revenue, int64_t* lp_iters,
-              void* stream)
+              double* lp_gap, void* stream)
 {
     set_error(CBLP_OK, "");
     if (!b || !p) return set_error(CBLP_EINVAL, "NULL batch or params");
@@ -399,8 +404,8 @@ int gosim_run(cblp_batch_t b, int32_t periods, int32_t K, const void* prefs, con
         for (int32_t t = 0; t < periods; ++t) {
             // this batch's LP: capacities, steps and the customers' preferences
             GS_TRY(dtype == CBLP_F32
-                       ? launch_lp_inputs<float>(runs, n, inv, periods - t, tau0, r, (void*)h0->c, tau_work, s)
-                       : launch_lp_inputs<double>(runs, n, inv, periods - t, tau0, r, (void*)h0->c, tau_work, s));
+                       ? launch_lp_inputs<float>(runs, n, inv, periods - t, tau0, r, (void*)h0->c, tau_work, eta, s)
+                       : launch_lp_inputs<double>(runs, n, inv, periods - t, tau0, r, (void*)h0->c, tau_work, eta, s));
             GS_TRY(hipMemcpyAsync((void*)h0->v, (const char*)prefs + (size_t)t * runs * vrun,
                                   (size_t)runs * vrun, hipMemcpyDeviceToDevice, s));
             int any = 0;
@@ -427,8 +432,10 @@ int gosim_run(cblp_batch_t b, int32_t periods, int32_t K, const void* prefs, con
                 if (e == CBLP_ENONFINITE || (e && e != CBLP_ENOTCONVERGED)) return e;
                 set_error(CBLP_OK, "");
             }
-            if (lp_iters)
-                for (int q = 0; q < runs; ++q) lp_iters[(size_t)t * runs + q] = take[q] ? outs[q].iters : 0;
+            for (int q = 0; q < runs; ++q) {
+                if (lp_iters) lp_iters[(size_t)t * runs + q] = take[q] ? outs[q].iters : 0;
+                if (lp_gap) lp_gap[(size_t)t * runs + q] = take[q] ? outs[q].trace[SPFOM_TR_GAP] : 0.0;
+            }
             GS_TRY(dtype == CBLP_F32
                        ? launch_period<float>(runs, N, n, K, eta, r, (const char*)prefs + (size_t)t * runs * vrun,
                                               u + (size_t)t * runs * N, inv, offers + (size_t)t * runs * K,

@@ -125,13 +125,17 @@ def test_lp_inputs_match_oracle(cb, dtype):
     dev = lambda a, t: torch.from_numpy(np.ascontiguousarray(a)).to("cuda", t)
     c = torch.empty(runs, n, dtype=dt, device="cuda")
     tau = torch.empty_like(c)
+    eta0 = (rng.uniform(0, 1.5, (runs, n)) * r).astype(npdt)   # some above r already
     for left in (1, 7, 100):
-        cb.gosim_lp_inputs(dev(inv, torch.int64), left, 0.003, dev(r, dt), c, tau)
+        eta = dev(eta0, dt)
+        cb.gosim_lp_inputs(dev(inv, torch.int64), left, 0.003, dev(r, dt), c, tau, eta)
         torch.cuda.synchronize()
         for q in range(runs):
             c_ref, tau_ref = ogs.lp_inputs(inv[q], left, r[q], 0.003, npdt)
             assert np.array_equal(c[q].cpu().numpy(), c_ref), (left, q)
             assert np.array_equal(tau[q].cpu().numpy(), tau_ref), (left, q)
+            eta_ref = ogs.sold_out_duals(inv[q], eta0[q], r[q]).astype(npdt)
+            assert np.array_equal(eta[q].cpu().numpy(), eta_ref), (left, q)
 
 
 @pytest.mark.parametrize("dtype", ["f32", "f64"])
@@ -181,6 +185,7 @@ def test_run_matches_oracle_f64(cb):
         ref = ogs.simulate(mk.r[q], mk.inv0[q], mk.prefs[:, q], mk.u[:, q], K, tau0=tau0, tol=tol,
                            max_iters=mx, check_every=ce)
         assert np.array_equal(out["lp_iters"][:, q], ref["iters"]), q
+        np.testing.assert_allclose(out["lp_gap"][:, q], ref["gap"], rtol=1e-9, atol=1e-12)
         for t in range(5):
             got = [j for j in out["offers"][t, q].tolist() if j >= 0]
             assert got == ref["offers"][t], (q, t)
@@ -215,7 +220,7 @@ def test_run_f32_is_its_steps(cb):
         r = prob.r.view(1, 9)
         for t in range(4):
             stock = int((inv > 0).sum().item())
-            cb.gosim_lp_inputs(inv, 4 - t, tau0, r, c, tau)
+            cb.gosim_lp_inputs(inv, 4 - t, tau0, r, c, tau, eta.view(1, 9))
             iters = 0
             if stock > K:
                 prob.refresh(v=mk.prefs[t, q].ravel(), c=c[0])

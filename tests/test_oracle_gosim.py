@@ -13,6 +13,8 @@ policy on the market of Figure 4) (CPU only).
   has T' times the optimum of one batch with capacity c / T' (HiGHS);
 * the bid-price rule never withholds a product that the batch's LP optimum
   sells (HiGHS duals and sales);
+* a sold-out product's dual raised to its revenue gives the LP without the
+  product (the same dual value and sales);
 * closed-loop special cases: abundant stock keeps every dual at zero, so
   the K highest prices are offered in every batch; with at most K products
   no LP is solved.
@@ -38,6 +40,29 @@ def test_lp_inputs_hand_worked():
     assert c32.dtype == np.float32 and tau32.dtype == np.float32
     assert c32[0] == np.float32(1.0 / 3.0)
     assert tau32[1] == np.float32(0.1 * 2.0 / float(np.float32(7.0 / 3.0)))
+
+
+def test_sold_out_dual_removes_the_product():
+    """Raising a sold-out product's dual to its revenue is the LP without it:
+    the same dual value and sales as the instance whose consideration sets
+    omit the product (no shadow attraction, so an absent product and an
+    unoffered one weigh the same)."""
+    mk = gosim_market(1, n=6, periods=1, customers=25, seed=4)
+    inv = mk.inv0[0].copy()
+    inv[[1, 4]] = 0
+    c, _ = gosim.lp_inputs(inv // 30, 1, mk.r[0], 0.1)
+    eta = np.random.default_rng(0).uniform(0, 0.5, 6) * mk.r[0]
+    eta2 = gosim.sold_out_duals(inv, eta, mk.r[0])
+    assert np.all(eta2[[1, 4]] >= mk.r[0][[1, 4]])
+    np.testing.assert_array_equal(np.delete(eta2, [1, 4]), np.delete(eta, [1, 4]))
+    full = market_instance(mk.prefs[0, 0], mk.r[0], c)
+    keep = [0, 2, 3, 5]
+    part = market_instance(mk.prefs[0, 0][:, keep], mk.r[0][keep], c[keep])
+    a = oracle.best_response(full, eta2)
+    b = oracle.best_response(part, eta2[keep])
+    assert a["S"][1] == 0.0 and a["S"][4] == 0.0
+    np.testing.assert_allclose(a["S"][keep], b["S"], rtol=1e-12)
+    assert a["D"] == pytest.approx(b["D"], rel=1e-12)
 
 
 def test_offer_hand_worked():
