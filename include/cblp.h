@@ -283,8 +283,9 @@ int cblp_timing_read(cblp_t h, double* ms, int64_t* launches, void* stream);
  * of a multi-period problem (Section 5.1), each with its own remaining
  * capacities.  One iteration of every active instance is one persistent
  * segment launch (a shared work list of tile ranges) plus two dual-phase
- * launches; results equal those of the instances' own spfom_iterate up to
- * FP64 summation order of sum lambda R*.  Identity resource matrix only.
+ * launches; the duals and trace rows equal those of the instances' own
+ * spfom_iterate bit for bit (integer sales and Z sums, the single path's
+ * grouping of the FP64 partials).  Identity resource matrix only.
  */
 typedef struct cblp_batch* cblp_batch_t;
 

@@ -20,9 +20,10 @@
 // product accumulates in FP32; biases, GELU and the loss are FP32.
 //
 // The 256 x 256 products (forward Z2 = H1 W2, backward dW2 = H1^T dZ2 and
-// dH1 = dZ2 W2^T) run on v_mfma_f32_16x16x16_bf16: each wave owns a 16 x 16
-// output tile; lane l holds A[l % 16][4 (l / 16) + i], B[4 (l / 16) + i][l % 16]
-// and D[4 (l / 16) + i][l % 16], i = 0..3.
+// dH1 = dZ2 W2^T) run on gfx950's v_mfma_f32_16x16x32_bf16.  A training step
+// is two launches: k_train (forward, loss and backward of 64-row chunks per
+// block, partial gradients per block) and k_train_reduce (the blocks' sum in
+// a fixed order, Adam, the BF16 copies of W2).
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -42,7 +43,6 @@ constexpr int64_t OFF_W1 = 0, OFF_B1 = OFF_W1 + IN * HID, OFF_W2 = OFF_B1 + HID,
                   OFF_B2 = OFF_W2 + HID * HID, OFF_W3 = OFF_B2 + HID, OFF_B3 = OFF_W3 + HID,
                   NPARAM = OFF_B3 + 1;
 constexpr int kFeatBins = 2048;
-constexpr int kColRows = 256;     // rows per column-sum block
 
 typedef short v4s __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
@@ -57,11 +57,19 @@ __device__ __forceinline__ unsigned short f2bf(float x)
 __device__ __forceinline__ float bf2f(unsigned short h) { return __uint_as_float((unsigned)h << 16); }
 __device__ __forceinline__ float bfr(float x) { return bf2f(f2bf(x)); }
 
-__device__ __forceinline__ float gelu(float x) { return 0.5f * x * (1.0f + erff(x * 0.70710678118654752f)); }
-__device__ __forceinline__ float gelu_d(float x)
+// GELU(z) = z Phi(z) and GELU'(z) = Phi(z) + z phi(z), Phi(z) = (1 + erf(z / sqrt 2)) / 2,
+// phi(z) = exp(-z^2 / 2) / sqrt(2 pi): one erf for both
+__device__ __forceinline__ void gelu2(float z, float& g, float& d)
 {
-    return 0.5f * (1.0f + erff(x * 0.70710678118654752f)) +
-           x * 0.39894228040143268f * expf(-0.5f * x * x);
+    const float cdf = 0.5f * (1.0f + erff(z * 0.70710678118654752f));
+    g = z * cdf;
+    d = cdf + z * 0.39894228040143268f * __expf(-0.5f * z * z);
+}
+__device__ __forceinline__ float gelu(float z)
+{
+    float g, d;
+    gelu2(z, g, d);
+    return g;
 }
 
 // ------------------------------------------------------------ features
@@ -160,271 +168,409 @@ __global__ void k_feat_fold(FeatArgs a, int nblocks, const T* r, const T* c, con
 
 // ------------------------------------------------------------ MLP layers
 
-// z1 = X W1 + b1, h1 = GELU(z1) stored as BF16; rows past `rows` are zero
-__global__ void __launch_bounds__(HID) k_l1_fwd(const float* X, int64_t rows, const float* P,
-                                                float* z1, unsigned short* h1b)
+// MFMA operands: v_mfma_f32_16x16x32_bf16 (gfx950).  Lane l holds
+// A[l % 16][8 (l / 16) + i] and B[8 (l / 16) + i][l % 16], i = 0..7, and
+// receives D[4 (l / 16) + i][l % 16], i = 0..3.
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+
+// eight consecutive BF16 values (16-byte aligned)
+__device__ __forceinline__ v8bf ld8(const unsigned short* p)
 {
-    const int64_t r = blockIdx.x;
-    const int u = threadIdx.x;
-    float z = 0.0f;
-    if (r < rows) {
-        z = P[OFF_B1 + u];
-        for (int k = 0; k < IN; ++k) z += X[r * IN + k] * bfr(P[OFF_W1 + k * HID + u]);
-    }
-    z1[r * HID + u] = z;
-    h1b[r * HID + u] = f2bf(r < rows ? gelu(z) : 0.0f);
+    v8bf x;
+    __builtin_memcpy(&x, p, 16);
+    return x;
 }
 
-// C(m, n) = sum_k A(m, k) B(k, n), BF16 operands, FP32 accumulation.
-// A(m, k) = TA ? A[k lda + m] : A[m lda + k];  B(k, n) = TB ? B[n ldb + k] : B[k ldb + n].
-// EPI 0 stores C; EPI 1 stores z = C + bias[n] and h = GELU(z).
-template <bool TA, bool TB, int EPI>
-__global__ void __launch_bounds__(256) k_gemm(const unsigned short* A, const unsigned short* B,
-                                              float* C, int N, int K, int lda, int ldb,
-                                              const float* bias, float* hout)
+// eight BF16 values `stride` elements apart (LDS columns)
+__device__ __forceinline__ v8bf ld8s(const unsigned short* p, int stride)
 {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int m0 = blockIdx.y * 16, n0 = blockIdx.x * 64 + wave * 16;
-    const int r = lane & 15, kq = (lane >> 4) * 4;
-    v4f acc = {0.0f, 0.0f, 0.0f, 0.0f};
-    for (int k0 = 0; k0 < K; k0 += 16) {
-        v4s a, b;
+    unsigned short u[8];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int k = k0 + kq + i;
-            a[i] = (short)(TA ? A[(size_t)k * lda + m0 + r] : A[(size_t)(m0 + r) * lda + k]);
-            b[i] = (short)(TB ? B[(size_t)(n0 + r) * ldb + k] : B[(size_t)k * ldb + n0 + r]);
-        }
-        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
-    }
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const size_t o = (size_t)(m0 + kq + i) * N + n0 + r;
-        if (EPI == 0) {
-            C[o] = acc[i];
-        } else {
-            const float z = acc[i] + bias[n0 + r];
-            C[o] = z;
-            hout[o] = gelu(z);
-        }
-    }
+    for (int i = 0; i < 8; ++i) u[i] = p[i * stride];
+    v8bf x;
+    __builtin_memcpy(&x, u, 16);
+    return x;
 }
 
-// Row-block product for operands whose k index is contiguous in memory:
-// C(m, n) = sum_k A[m lda + k] Bt[n ldb + k] over all N = 256 columns.  A
-// block of four waves owns 16 rows; each wave owns 64 columns (four 16 x 16
-// tiles) and reuses its A fragment, one 8-byte load per k step, for the four
-// products.  EPI as k_gemm.
-template <int EPI>
-__global__ void __launch_bounds__(256) k_gemm_rows(const unsigned short* A, const unsigned short* Bt,
-                                                   float* C, int N, int K, int lda, int ldb,
-                                                   const float* bias, float* hout)
+__device__ __forceinline__ v4f mfma32(v8bf a, v8bf b, v4f c)
 {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int m0 = blockIdx.x * 16, n0 = wave * 64;
-    const int r = lane & 15, kq = (lane >> 4) * 4;
-    v4f acc[4];
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+// h1 = GELU(x W1 + b1) of kRows rows into LDS as BF16 (zero past `valid`
+// rows); thread u computes hidden unit u.  z1 is formed as the backward pass
+// re-forms it.
+constexpr int kRows = 64;
+
+__device__ __forceinline__ float z1_of(const float (*xs)[IN], int r, float b1, const float* w1)
+{
+    float z = b1;
 #pragma unroll
-    for (int t = 0; t < 4; ++t) acc[t] = (v4f){0.0f, 0.0f, 0.0f, 0.0f};
-    const unsigned short* pa = A + (size_t)(m0 + r) * lda + kq;
-    const unsigned short* pb = Bt + (size_t)(n0 + r) * ldb + kq;
-    for (int k0 = 0; k0 < K; k0 += 16) {
-        const v4s a = *(const v4s*)(pa + k0);
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            const v4s b = *(const v4s*)(pb + (size_t)16 * t * ldb + k0);
-            acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[t], 0, 0, 0);
-        }
-    }
-#pragma unroll
-    for (int t = 0; t < 4; ++t)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int n = n0 + 16 * t + r;
-            const size_t o = (size_t)(m0 + kq + i) * N + n;
-            if (EPI == 0) {
-                C[o] = acc[t][i];
-            } else {
-                const float z = acc[t][i] + bias[n];
-                C[o] = z;
-                hout[o] = gelu(z);
-            }
-        }
+    for (int k = 0; k < IN; ++k) z += xs[r][k] * w1[k];
+    return z;
 }
 
 // Fused inference: y for 64 rows per block of four waves with no activation
-// leaving the chip.  h1 = GELU(x W1 + b1) is formed in LDS as BF16 (same
-// operations as k_l1_fwd); each wave multiplies the four 16-row tiles by its
-// 64 columns of W2 on the matrix cores, loading each B fragment once for the
-// four tiles; then b2, GELU and the dot with BF16(w3) over its columns; the
-// four waves' partial sums are added in wave order.
-constexpr int kInferRows = 64;
-
+// leaving the chip.  h1 is formed in LDS as BF16; each wave multiplies the
+// four 16-row tiles by its 64 columns of W2 on the matrix cores, loading each
+// B fragment once for the four tiles; then b2, GELU and the dot with BF16(w3)
+// over its columns; the four waves' partial sums are added in wave order.
 __global__ void __launch_bounds__(256) k_mlp_infer(const float* X, int64_t rows, const float* P,
                                                    const unsigned short* W2t, float* y)
 {
-    constexpr int RT = kInferRows / 16;
-    __shared__ __attribute__((aligned(16))) unsigned short h1[kInferRows * HID];
-    __shared__ float part[4][kInferRows];
+    constexpr int RT = kRows / 16;
+    __shared__ __attribute__((aligned(16))) unsigned short h1[kRows * HID];
+    __shared__ float xs[kRows][IN];
+    __shared__ float part[4][kRows];
     const int tid = threadIdx.x;
-    const int64_t m0 = (int64_t)blockIdx.x * kInferRows;
+    const int64_t m0 = (int64_t)blockIdx.x * kRows;
+    if (tid < kRows) {
+        const int64_t row = m0 + tid;
+#pragma unroll
+        for (int k = 0; k < IN; ++k) xs[tid][k] = row < rows ? X[row * IN + k] : 0.0f;
+    }
+    __syncthreads();
     {
         const int u = tid;
         const float b1 = P[OFF_B1 + u];
         float w1[IN];
 #pragma unroll
         for (int k = 0; k < IN; ++k) w1[k] = bfr(P[OFF_W1 + k * HID + u]);
-        for (int r = 0; r < kInferRows; ++r) {
-            const int64_t row = m0 + r;
-            float v = 0.0f;
-            if (row < rows) {
-                float z = b1;
-#pragma unroll
-                for (int k = 0; k < IN; ++k) z += X[row * IN + k] * w1[k];
-                v = gelu(z);
-            }
-            h1[r * HID + u] = f2bf(v);
-        }
+        for (int r = 0; r < kRows; ++r)
+            h1[r * HID + u] = f2bf(m0 + r < rows ? gelu(z1_of(xs, r, b1, w1)) : 0.0f);
     }
     __syncthreads();
     const int lane = tid & 63, wave = tid >> 6;
     const int n0 = wave * 64;
-    const int r = lane & 15, kq = (lane >> 4) * 4;
+    const int r16 = lane & 15, g4 = lane >> 4;
     v4f acc[RT][4];
 #pragma unroll
     for (int m = 0; m < RT; ++m)
 #pragma unroll
         for (int t = 0; t < 4; ++t) acc[m][t] = (v4f){0.0f, 0.0f, 0.0f, 0.0f};
-    const unsigned short* pb = W2t + (size_t)(n0 + r) * HID + kq;
-    for (int k0 = 0; k0 < HID; k0 += 16) {
-        v4s bfr4[4];
+    const unsigned short* pb = W2t + (size_t)(n0 + r16) * HID + 8 * g4;
+    for (int k0 = 0; k0 < HID; k0 += 32) {
+        v8bf b[4];
 #pragma unroll
-        for (int t = 0; t < 4; ++t) bfr4[t] = *(const v4s*)(pb + (size_t)16 * t * HID + k0);
+        for (int t = 0; t < 4; ++t) b[t] = ld8(pb + (size_t)16 * t * HID + k0);
 #pragma unroll
         for (int m = 0; m < RT; ++m) {
-            const v4s a = *(const v4s*)(h1 + (16 * m + r) * HID + k0 + kq);
+            const v8bf a = ld8(h1 + (16 * m + r16) * HID + k0 + 8 * g4);
 #pragma unroll
-            for (int t = 0; t < 4; ++t)
-                acc[m][t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bfr4[t], acc[m][t], 0, 0, 0);
+            for (int t = 0; t < 4; ++t) acc[m][t] = mfma32(a, b[t], acc[m][t]);
         }
     }
     float b2[4], w3[4];
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
-        b2[t] = P[OFF_B2 + n0 + 16 * t + r];
-        w3[t] = bfr(P[OFF_W3 + n0 + 16 * t + r]);
+        b2[t] = P[OFF_B2 + n0 + 16 * t + r16];
+        w3[t] = bfr(P[OFF_W3 + n0 + 16 * t + r16]);
     }
 #pragma unroll
     for (int m = 0; m < RT; ++m) {
-        float py[4] = {0.0f, 0.0f, 0.0f, 0.0f};   // rows 16 m + kq + i, this lane's columns
+        float py[4] = {0.0f, 0.0f, 0.0f, 0.0f};   // rows 16 m + 4 g4 + i, this lane's columns
 #pragma unroll
         for (int t = 0; t < 4; ++t)
 #pragma unroll
             for (int i = 0; i < 4; ++i) py[i] += gelu(acc[m][t][i] + b2[t]) * w3[t];
-        // sum over the 16 lanes of each row group (same kq)
 #pragma unroll
         for (int i = 0; i < 4; ++i)
             for (int o = 1; o < 16; o <<= 1) py[i] += __shfl_xor(py[i], o, 64);
-        if (r == 0)
+        if (r16 == 0)
 #pragma unroll
-            for (int i = 0; i < 4; ++i) part[wave][16 * m + kq + i] = py[i];
+            for (int i = 0; i < 4; ++i) part[wave][16 * m + 4 * g4 + i] = py[i];
     }
     __syncthreads();
-    if (tid < kInferRows && m0 + tid < rows)
+    if (tid < kRows && m0 + tid < rows)
         y[m0 + tid] = ((part[0][tid] + part[1][tid]) + (part[2][tid] + part[3][tid])) + P[OFF_B3];
 }
 
-// y = h2 . w3 + b3, one wave per row
-__global__ void __launch_bounds__(256) k_l3_fwd(const float* h2, const float* P, int64_t rpad,
-                                                float* y)
+// One fused training pass (forward, mean-squared-error loss, backward) over
+// the rows of a minibatch: rows r < cnt are (X, Y)[perm ? perm[r] : r].  A
+// block of 16 waves takes chunks of kTRows rows (chunk c = block, block +
+// grid, ...) and writes its partial gradient (the sum over its rows) to its
+// own NPARAM slot of Gpart and its squared error to lpart, so k_train_reduce
+// can add the blocks in a fixed order.  Per chunk:
+//   h1 = GELU(z1), z1 = x W1 + b1             LDS, BF16 (and GELU'(z1), FP32)
+//   Z2 = H1 W2                                matrix cores; wave w: columns 16w..
+//   h2 = GELU(Z2 + b2), y = h2 . BF16(w3) + b3
+//   dy = 2 (y - t) / cnt
+//   dZ2 = dy BF16(w3) GELU'(Z2)               FP32 for the b2 sum, BF16 in LDS
+//   dH1 = dZ2 W2^T                            matrix cores; wave w: units 16w..
+//   dZ1 = dH1 GELU'(z1)
+//   dW2 += H1^T dZ2                           matrix cores; wave w: rows 16w..
+// and the column sums of h2 dy (w3), dy (b3), dZ2 (b2), dZ1 (b1), x_k dZ1
+// (W1): thread (u, q) adds rows q, q + 4, ... of column u, and the four
+// threads of a column are added in q order at the end.  GELU and its
+// derivative share one erf per element.  The four waves of a SIMD hide each
+// other's LDS and memory latency.
+constexpr int kTRows = 32;
+constexpr int kTThreads = 1024;
+constexpr int64_t kGStride = (NPARAM + 3) / 4 * 4;   // partial slots on 16-byte boundaries
+
+struct TrainArgs {
+    const float* X;
+    const float* Y;
+    const int32_t* perm;
+    int64_t cnt;
+    float inv2;                    // 2 / cnt
+    const float* P;
+    const unsigned short* W2b;     // BF16 W2, [in][out]
+    const unsigned short* W2t;     // BF16 W2 transposed, [out][in]
+    float* Gpart;                  // [grid][kGStride]
+    double* lpart;                 // [grid]
+};
+
+__global__ void __launch_bounds__(kTThreads) k_train(TrainArgs a)
 {
-    const int lane = threadIdx.x & 63;
-    const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (r >= rpad) return;
-    float s = 0.0f;
+    constexpr int RT = kTRows / 16;
+    constexpr int RQ = kTThreads / HID;           // threads per column (4)
+    constexpr int SEG = kTThreads / kTRows;       // column segments of the y sums (32)
+    constexpr int SW = HID / SEG;                 // columns per segment (8)
+    __shared__ __attribute__((aligned(16))) unsigned short h1[kTRows * HID];
+    __shared__ __attribute__((aligned(16))) unsigned short dz[kTRows * HID];
+    __shared__ float zs[kTRows * HID];    // z2 = Z2 + b2, then GELU'(z2)
+    __shared__ float hs[kTRows * HID];    // h2, then dH1
+    __shared__ float g1[kTRows * HID];    // GELU'(z1)
+    __shared__ float xs[kTRows][IN];
+    __shared__ float ys[kTRows];
+    __shared__ float dys[kTRows];
+    __shared__ double es[kTRows];         // squared errors
+    __shared__ float w3s[HID];            // BF16(w3)
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int r16 = lane & 15, g4 = lane >> 4;
+    float* G = a.Gpart + (size_t)blockIdx.x * kGStride;
+    const int n0 = wave * 16;      // this wave's columns / hidden units / dW2 rows
+    const int u = tid % HID, q = tid / HID;   // elementwise: column u, rows q, q + RQ, ...
+    const float b1u = a.P[OFF_B1 + u], w3u = bfr(a.P[OFF_W3 + u]);
+    const float b2w = a.P[OFF_B2 + n0 + r16];
+    const float b3 = a.P[OFF_B3];
+    float w1u[IN];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) s += h2[r * HID + lane * 4 + i] * bfr(P[OFF_W3 + lane * 4 + i]);
-    for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
-    if (lane == 0) y[r] = s + P[OFF_B3];
-}
-
-// dy = 2 (y - t) / rows on real rows, 0 on padding; per-block squared error
-__global__ void __launch_bounds__(256) k_dy(const float* y, const float* t, int64_t rows,
-                                            int64_t rpad, float* dy, double* lpart)
-{
-    __shared__ double sh[256];
-    const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    double e2 = 0.0;
-    if (r < rpad) {
-        float g = 0.0f;
-        if (r < rows) {
-            const float d = y[r] - t[r];
-            g = 2.0f * d / (float)rows;
-            e2 = (double)d * (double)d;
+    for (int k = 0; k < IN; ++k) w1u[k] = bfr(a.P[OFF_W1 + k * HID + u]);
+    if (tid < HID) w3s[tid] = w3u;
+    float gw3 = 0.0f, gb2 = 0.0f, gb1 = 0.0f, gb3 = 0.0f;
+    float gW1[IN] = {0.0f, 0.0f, 0.0f, 0.0f};
+    double esum = 0.0;
+    for (int64_t c = blockIdx.x; c * kTRows < a.cnt; c += gridDim.x) {
+        const bool first = c == (int64_t)blockIdx.x;
+        const int64_t m0 = c * kTRows;
+        __syncthreads();           // the previous chunk is done with the LDS
+        if (tid < kTRows) {
+            const int64_t row = m0 + tid;
+            if (row < a.cnt) {
+                const int64_t qq = a.perm ? (int64_t)a.perm[row] : row;
+#pragma unroll
+                for (int k = 0; k < IN; ++k) xs[tid][k] = a.X[qq * IN + k];
+                ys[tid] = a.Y[qq];
+            } else {
+#pragma unroll
+                for (int k = 0; k < IN; ++k) xs[tid][k] = 0.0f;
+                ys[tid] = 0.0f;
+            }
         }
-        dy[r] = g;
-    }
-    sh[threadIdx.x] = e2;
-    __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
-        if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
         __syncthreads();
+#pragma unroll 2
+        for (int r = q; r < kTRows; r += RQ) {
+            float g = 0.0f, d = 0.0f;
+            if (m0 + r < a.cnt) gelu2(z1_of(xs, r, b1u, w1u), g, d);
+            h1[r * HID + u] = f2bf(g);
+            g1[r * HID + u] = d;
+        }
+        __syncthreads();
+        // Z2 = H1 W2, plus b2, into zs
+        {
+            v4f acc[RT];
+#pragma unroll
+            for (int m = 0; m < RT; ++m) acc[m] = (v4f){0.0f, 0.0f, 0.0f, 0.0f};
+            // the wave's eight W2 fragments in flight at once
+            const unsigned short* pb = a.W2t + (size_t)(n0 + r16) * HID + 8 * g4;
+            v8bf b[HID / 32];
+#pragma unroll
+            for (int kk = 0; kk < HID / 32; ++kk) b[kk] = ld8(pb + 32 * kk);
+#pragma unroll
+            for (int kk = 0; kk < HID / 32; ++kk)
+#pragma unroll
+                for (int m = 0; m < RT; ++m)
+                    acc[m] = mfma32(ld8(h1 + (16 * m + r16) * HID + 32 * kk + 8 * g4), b[kk], acc[m]);
+#pragma unroll
+            for (int m = 0; m < RT; ++m)
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    zs[(16 * m + 4 * g4 + i) * HID + n0 + r16] = acc[m][i] + b2w;
+        }
+        __syncthreads();
+        // h2 = GELU(z2) and GELU'(z2); y: thread (row, segment) sums its 8
+        // columns, the 32 segments of a row (half a wave) are added by shuffles
+        {
+            const int row = tid / SEG, sg = tid % SEG;
+            float py = 0.0f;
+#pragma unroll
+            for (int k = 0; k < SW; ++k) {
+                const int o = row * HID + SW * sg + k;
+                float g, d;
+                gelu2(zs[o], g, d);
+                hs[o] = g;
+                zs[o] = d;
+                py += g * w3s[SW * sg + k];
+            }
+#pragma unroll
+            for (int o = 1; o < SEG; o <<= 1) py += __shfl_xor(py, o, 64);
+            if (sg == 0) {
+                float g = 0.0f;
+                double e2 = 0.0;
+                if (m0 + row < a.cnt) {
+                    const float d = (py + b3) - ys[row];
+                    g = d * a.inv2;
+                    e2 = (double)d * (double)d;
+                }
+                dys[row] = g;
+                es[row] = e2;
+            }
+        }
+        __syncthreads();
+        if (tid == 0)
+            for (int r = 0; r < kTRows; ++r) {
+                gb3 += dys[r];
+                esum += es[r];
+            }
+        // dZ2 = dy BF16(w3) GELU'(z2) (BF16 into LDS); the w3 and b2 sums
+#pragma unroll 2
+        for (int r = q; r < kTRows; r += RQ) {
+            const float dy = dys[r];
+            const float g = dy * w3u * zs[r * HID + u];
+            gw3 += hs[r * HID + u] * dy;
+            gb2 += g;
+            dz[r * HID + u] = f2bf(g);
+        }
+        __syncthreads();
+        // dH1 = dZ2 W2^T into hs: B(n, k) = W2[k][n] = W2b[k HID + n]
+        {
+            v4f acc[RT];
+#pragma unroll
+            for (int m = 0; m < RT; ++m) acc[m] = (v4f){0.0f, 0.0f, 0.0f, 0.0f};
+            const unsigned short* pw = a.W2b + (size_t)(n0 + r16) * HID + 8 * g4;
+            v8bf b[HID / 32];
+#pragma unroll
+            for (int kk = 0; kk < HID / 32; ++kk) b[kk] = ld8(pw + 32 * kk);
+#pragma unroll
+            for (int kk = 0; kk < HID / 32; ++kk)
+#pragma unroll
+                for (int m = 0; m < RT; ++m)
+                    acc[m] = mfma32(ld8(dz + (16 * m + r16) * HID + 32 * kk + 8 * g4), b[kk], acc[m]);
+#pragma unroll
+            for (int m = 0; m < RT; ++m)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) hs[(16 * m + 4 * g4 + i) * HID + n0 + r16] = acc[m][i];
+        }
+        // dW2 += H1^T dZ2 over the chunk's 32 rows, formed as its transpose
+        // dZ2^T H1 (A(n, r) = dZ2[r][n], B(r, k) = h1[r][k]) so that each lane
+        // holds four consecutive n of one row k of dW2: one 16-byte store
+        {
+            const v8bf bk = ld8s(h1 + (8 * g4) * HID + n0 + r16, HID);
+            float* o = G + OFF_W2 + (size_t)(n0 + r16) * HID + 4 * g4;
+#pragma unroll 2
+            for (int nt = 0; nt < HID / 16; ++nt) {
+                const v4f d = mfma32(ld8s(dz + (8 * g4) * HID + 16 * nt + r16, HID), bk,
+                                     (v4f){0.0f, 0.0f, 0.0f, 0.0f});
+                v4f* po = (v4f*)(o + 16 * nt);
+                *po = first ? d : *po + d;
+            }
+        }
+        __syncthreads();
+        // dZ1 = dH1 GELU'(z1): the b1 and W1 sums
+#pragma unroll 2
+        for (int r = q; r < kTRows; r += RQ) {
+            const float d1 = hs[r * HID + u] * g1[r * HID + u];
+            gb1 += d1;
+#pragma unroll
+            for (int k = 0; k < IN; ++k) gW1[k] += xs[r][k] * d1;
+        }
     }
-    if (threadIdx.x == 0) lpart[blockIdx.x] = sh[0];
+    // the RQ threads of each column, added in q order
+    __syncthreads();
+    float* red = zs;               // [7][RQ][HID]
+    red[(0 * RQ + q) * HID + u] = gw3;
+    red[(1 * RQ + q) * HID + u] = gb2;
+    red[(2 * RQ + q) * HID + u] = gb1;
+#pragma unroll
+    for (int k = 0; k < IN; ++k) red[((3 + k) * RQ + q) * HID + u] = gW1[k];
+    __syncthreads();
+    if (tid < HID) {
+        float v[3 + IN];
+#pragma unroll
+        for (int x = 0; x < 3 + IN; ++x) {
+            float t = red[(x * RQ) * HID + tid];
+#pragma unroll
+            for (int qq = 1; qq < RQ; ++qq) t += red[(x * RQ + qq) * HID + tid];
+            v[x] = t;
+        }
+        G[OFF_W3 + tid] = v[0];
+        G[OFF_B2 + tid] = v[1];
+        G[OFF_B1 + tid] = v[2];
+#pragma unroll
+        for (int k = 0; k < IN; ++k) G[OFF_W1 + k * HID + tid] = v[3 + k];
+    }
+    if (tid == 0) {
+        G[OFF_B3] = gb3;
+        a.lpart[blockIdx.x] = esum;
+    }
 }
 
-// dz2 = dy w3 GELU'(z2), kept in FP32 and BF16
-__global__ void __launch_bounds__(HID) k_l3_bwd(const float* dy, const float* z2, const float* P,
-                                                float* dz2, unsigned short* dz2b)
+// The gradient: the nb block partials added in block order (FP64); with
+// adam set, one Adam step (Kingma and Ba) on the FP32 master parameters and
+// the BF16 copies of W2 re-rounded.  Thread i takes parameters 4i .. 4i + 3
+// (16-byte loads, four blocks' loads in flight).  loss_acc (nullable) += the
+// blocks' squared errors, added in block order by thread 0.
+__global__ void __launch_bounds__(256) k_train_reduce(const float* Gpart, int nb,
+                                                      const double* lpart, float* G, float* P,
+                                                      float* M, float* V, int adam, float lr,
+                                                      float b1, float b2, float eps, float c1,
+                                                      float c2, unsigned short* W2b,
+                                                      unsigned short* W2t, double* loss_acc)
 {
-    const int64_t r = blockIdx.x;
-    const int u = threadIdx.x;
-    const float g = dy[r] * bfr(P[OFF_W3 + u]) * gelu_d(z2[r * HID + u]);
-    dz2[r * HID + u] = g;
-    dz2b[r * HID + u] = f2bf(g);
-}
-
-// dz1 = dh1 GELU'(z1)
-__global__ void __launch_bounds__(HID) k_l1_bwd(const float* dh1, const float* z1, float* dz1)
-{
-    const int64_t o = (int64_t)blockIdx.x * HID + threadIdx.x;
-    dz1[o] = dh1[o] * gelu_d(z1[o]);
-}
-
-// out[u] = sum_r M[r ld + u] (s ? s[r sst] : 1) over rows [0, rpad): blocks of
-// kColRows rows write FP64 partials; k_colsum_final adds them in block order.
-__global__ void k_colsum(const float* M, int64_t ld, int64_t rpad, int ncols, const float* s,
-                         int64_t sst, double* part)
-{
-    const int u = threadIdx.x;
-    if (u >= ncols) return;
-    const int64_t r0 = (int64_t)blockIdx.x * kColRows;
-    const int64_t r1 = min(rpad, r0 + (int64_t)kColRows);
-    double acc = 0.0;
-    for (int64_t r = r0; r < r1; ++r) acc += (double)M[r * ld + u] * (s ? (double)s[r * sst] : 1.0);
-    part[(size_t)blockIdx.x * ncols + u] = acc;
-}
-
-__global__ void k_colsum_final(const double* part, int nb, int ncols, float* out)
-{
-    const int u = blockIdx.x * blockDim.x + threadIdx.x;
-    if (u >= ncols) return;
-    double acc = 0.0;
-    for (int b = 0; b < nb; ++b) acc += part[(size_t)b * ncols + u];
-    out[u] = (float)acc;
-}
-
-__global__ void k_adam(float* P, const float* G, float* M, float* V, int64_t n, float lr, float b1,
-                       float b2, float eps, float c1, float c2)
-{
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const float g = G[i];
-    const float m = b1 * M[i] + (1.0f - b1) * g;
-    const float v = b2 * V[i] + (1.0f - b2) * g * g;
-    M[i] = m;
-    V[i] = v;
-    P[i] -= lr * (m / c1) / (sqrtf(v / c2) + eps);
+    const int64_t i4 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i4 == 0 && loss_acc) {
+        double e = 0.0;
+        for (int b = 0; b < nb; ++b) e += lpart[b];
+        loss_acc[0] += e;
+    }
+    if (4 * i4 >= NPARAM) return;
+    constexpr int64_t S4 = kGStride / 4;
+    const v4f* src = (const v4f*)Gpart + i4;
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    int b = 0;
+    for (; b + 4 <= nb; b += 4) {
+        const v4f x0 = src[(size_t)b * S4], x1 = src[(size_t)(b + 1) * S4];
+        const v4f x2 = src[(size_t)(b + 2) * S4], x3 = src[(size_t)(b + 3) * S4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) s[k] = (((s[k] + (double)x0[k]) + (double)x1[k]) + (double)x2[k]) + (double)x3[k];
+    }
+    for (; b < nb; ++b) {
+        const v4f x = src[(size_t)b * S4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) s[k] += (double)x[k];
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int64_t i = 4 * i4 + k;
+        if (i >= NPARAM) break;
+        const float g = (float)s[k];
+        G[i] = g;
+        if (!adam) continue;
+        const float m = b1 * M[i] + (1.0f - b1) * g;
+        const float v = b2 * V[i] + (1.0f - b2) * g * g;
+        M[i] = m;
+        V[i] = v;
+        const float p = P[i] - lr * (m / c1) / (sqrtf(v / c2) + eps);
+        P[i] = p;
+        if (i >= OFF_W2 && i < OFF_W2 + HID * HID) {
+            const int64_t q = i - OFF_W2;
+            const unsigned short x = f2bf(p);
+            W2b[q] = x;
+            W2t[(q % HID) * HID + q / HID] = x;
+        }
+    }
 }
 
 // BF16 copies of W2 [256 x 256]: as stored (row i = input unit i) and transposed
@@ -451,33 +597,6 @@ __global__ void k_targets(const T* eta, const T* r, int64_t n, float* Y)
     if (j < n) Y[j] = r[j] > (T)0 ? (float)((double)eta[j] / (double)r[j]) : 0.0f;
 }
 
-// minibatch rows perm[0..cnt) of (X, Y) into (Xb, Yb), zero padding up to rpad
-__global__ void k_gather(const float* X, const float* Y, const int32_t* perm, int64_t cnt,
-                         int64_t rpad, float* Xb, float* Yb)
-{
-    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= rpad) return;
-    if (r < cnt) {
-        const int64_t q = perm[r];
-#pragma unroll
-        for (int k = 0; k < IN; ++k) Xb[r * IN + k] = X[q * IN + k];
-        Yb[r] = Y[q];
-    } else {
-#pragma unroll
-        for (int k = 0; k < IN; ++k) Xb[r * IN + k] = 0.0f;
-        Yb[r] = 0.0f;
-    }
-}
-
-// acc[0] += sum of the nb loss partials (one thread, fixed order)
-__global__ void k_loss_add(const double* part, int nb, double* acc)
-{
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    double a = 0.0;
-    for (int b = 0; b < nb; ++b) a += part[b];
-    acc[0] += a;
-}
-
 __global__ void k_fill_f64(double* p, int64_t n, double v)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -497,12 +616,12 @@ struct wsnet {
     unsigned short* W2b = nullptr; // BF16 copy of W2
     unsigned short* W2t = nullptr; // BF16 copy of W2 transposed
     int64_t step = 0;
-    int64_t cap = 0;               // padded rows the scratch holds
-    float *z1 = nullptr, *z2 = nullptr, *h2 = nullptr, *y = nullptr, *dy = nullptr;
-    float *dz2 = nullptr, *dh1 = nullptr, *dz1 = nullptr, *X = nullptr, *Yb = nullptr;
-    unsigned short *h1b = nullptr, *dz2b = nullptr;
-    double* part = nullptr;        // column-sum partials
-    double* lpart = nullptr;       // loss partials
+    int64_t cap = 0;               // rows the prediction scratch holds
+    float *X = nullptr, *y = nullptr;   // prediction: features and outputs
+    int gcap = 0;                  // training blocks the partials hold
+    float* Gpart = nullptr;        // [gcap][kGStride] per-block gradient partials
+    double* lpart = nullptr;       // [gcap] per-block squared errors
+    double* lacc = nullptr;        // loss accumulator
     double* pinned = nullptr;
 };
 
@@ -517,16 +636,17 @@ int mfail(int code, const std::string& m) { return set_error(code, m); }
             return mfail(CBLP_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
     } while (0)
 
+constexpr int kTrainBlocks = 256;   // most blocks of one training pass
+
 void net_free_scratch(wsnet* w)
 {
-    void* ptrs[] = {w->z1, w->z2, w->h2, w->y, w->dy, w->dz2, w->dh1, w->dz1, w->X, w->Yb,
-                    w->h1b, w->dz2b, w->part, w->lpart};
+    void* ptrs[] = {w->X, w->y, w->Gpart, w->lpart, w->lacc};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
-    w->z1 = w->z2 = w->h2 = w->y = w->dy = w->dz2 = w->dh1 = w->dz1 = w->X = w->Yb = nullptr;
-    w->h1b = w->dz2b = nullptr;
-    w->part = w->lpart = nullptr;
+    w->X = w->y = w->Gpart = nullptr;
+    w->lpart = w->lacc = nullptr;
     w->cap = 0;
+    w->gcap = 0;
 }
 
 void net_release(wsnet* w)
@@ -551,109 +671,91 @@ int malloc_d(P** p, size_t bytes)
     return CBLP_OK;
 }
 
-int64_t pad16(int64_t x) { return (x + 15) / 16 * 16; }
-
-int ensure_scratch(wsnet* w, int64_t rows)
+// prediction scratch for `rows` rows
+int ensure_rows(wsnet* w, int64_t rows)
 {
-    const int64_t need = pad16(std::max<int64_t>(rows, 16));
+    const int64_t need = std::max<int64_t>(rows, 64);
     if (need <= w->cap) return CBLP_OK;
-    net_free_scratch(w);
-    const size_t a = (size_t)need * HID;
+    if (w->X) (void)hipFree(w->X);
+    if (w->y) (void)hipFree(w->y);
+    w->X = w->y = nullptr;
+    w->cap = 0;
     int rc;
-    if ((rc = malloc_d(&w->z1, a * 4)) || (rc = malloc_d(&w->z2, a * 4)) ||
-        (rc = malloc_d(&w->h2, a * 4)) || (rc = malloc_d(&w->dz2, a * 4)) ||
-        (rc = malloc_d(&w->dh1, a * 4)) || (rc = malloc_d(&w->dz1, a * 4)) ||
-        (rc = malloc_d(&w->h1b, a * 2)) || (rc = malloc_d(&w->dz2b, a * 2)) ||
-        (rc = malloc_d(&w->y, need * 4)) || (rc = malloc_d(&w->dy, need * 4)) ||
-        (rc = malloc_d(&w->Yb, need * 4)) ||
-        (rc = malloc_d(&w->X, need * IN * 4)) ||
-        (rc = malloc_d(&w->part, (size_t)((need + kColRows - 1) / kColRows) * HID * 8)) ||
-        (rc = malloc_d(&w->lpart, (size_t)((need + 255) / 256) * 8))) {
-        net_free_scratch(w);
+    if ((rc = malloc_d(&w->X, (size_t)need * IN * 4)) || (rc = malloc_d(&w->y, (size_t)need * 4)))
         return rc;
-    }
     w->cap = need;
     return CBLP_OK;
 }
 
-// forward over rpad rows of w->X (rows real): y, and the activations backward needs
-int forward(wsnet* w, int64_t rows, int64_t rpad, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_l1_fwd, dim3((unsigned)rpad), dim3(HID), 0, s, w->X, rows, w->P, w->z1,
-                       w->h1b);
-    // Z2 = H1 W2: B(k, n) = W2[k][n] = W2t[n][k], contiguous in k
-    hipLaunchKernelGGL(k_gemm_rows<1>, dim3((unsigned)(rpad / 16)), dim3(256), 0, s, w->h1b,
-                       w->W2t, w->z2, HID, HID, HID, HID, w->P + OFF_B2, w->h2);
-    hipLaunchKernelGGL(k_l3_fwd, dim3((unsigned)((rpad + 3) / 4)), dim3(256), 0, s, w->h2, w->P,
-                       rpad, w->y);
-    MHIP(hipGetLastError());
-    return CBLP_OK;
-}
+int train_blocks(int64_t rows) { return (int)std::min<int64_t>(kTrainBlocks, (rows + kTRows - 1) / kTRows); }
 
-int colsum(wsnet* w, const float* M, int64_t ld, int64_t rpad, int ncols, const float* sc,
-           int64_t sst, float* out, hipStream_t s)
+// training partials for a pass over `rows` rows
+int ensure_train(wsnet* w, int64_t rows)
 {
-    const int nb = (int)((rpad + kColRows - 1) / kColRows);
-    hipLaunchKernelGGL(k_colsum, dim3(nb), dim3(HID), 0, s, M, ld, rpad, ncols, sc, sst, w->part);
-    hipLaunchKernelGGL(k_colsum_final, dim3((ncols + 255) / 256), dim3(256), 0, s, w->part, nb,
-                       ncols, out);
-    MHIP(hipGetLastError());
-    return CBLP_OK;
-}
-
-// loss and gradients into w->G for rows of (X, Y); X already in w->X
-int backward(wsnet* w, const float* Y, int64_t rows, int64_t rpad, double* loss, hipStream_t s,
-             double* loss_acc = nullptr)
-{
-    int rc;
-    if ((rc = forward(w, rows, rpad, s))) return rc;
-    const int lb = (int)((rpad + 255) / 256);
-    hipLaunchKernelGGL(k_dy, dim3(lb), dim3(256), 0, s, w->y, Y, rows, rpad, w->dy, w->lpart);
-    hipLaunchKernelGGL(k_l3_bwd, dim3((unsigned)rpad), dim3(HID), 0, s, w->dy, w->z2, w->P, w->dz2,
-                       w->dz2b);
-    // dW2 = H1^T dZ2 (K = rows), dH1 = dZ2 W2^T
-    hipLaunchKernelGGL((k_gemm<true, false, 0>), dim3(HID / 64, HID / 16), dim3(256), 0, s, w->h1b,
-                       w->dz2b, w->G + OFF_W2, HID, (int)rpad, HID, HID, nullptr, nullptr);
-    // dH1 = dZ2 W2^T: B(k, n) = W2[n][k], contiguous in k
-    hipLaunchKernelGGL(k_gemm_rows<0>, dim3((unsigned)(rpad / 16)), dim3(256), 0, s, w->dz2b,
-                       w->W2b, w->dh1, HID, HID, HID, HID, nullptr, nullptr);
-    hipLaunchKernelGGL(k_l1_bwd, dim3((unsigned)rpad), dim3(HID), 0, s, w->dh1, w->z1, w->dz1);
-    MHIP(hipGetLastError());
-    if ((rc = colsum(w, w->h2, HID, rpad, HID, w->dy, 1, w->G + OFF_W3, s))) return rc;
-    if ((rc = colsum(w, w->dy, 1, rpad, 1, nullptr, 0, w->G + OFF_B3, s))) return rc;
-    if ((rc = colsum(w, w->dz2, HID, rpad, HID, nullptr, 0, w->G + OFF_B2, s))) return rc;
-    if ((rc = colsum(w, w->dz1, HID, rpad, HID, nullptr, 0, w->G + OFF_B1, s))) return rc;
-    if (loss_acc) hipLaunchKernelGGL(k_loss_add, dim3(1), dim3(64), 0, s, w->lpart, lb, loss_acc);
-    for (int k = 0; k < IN; ++k)
-        if ((rc = colsum(w, w->dz1, HID, rpad, HID, w->X + k, IN, w->G + OFF_W1 + k * HID, s)))
-            return rc;
-    if (loss) {
-        std::vector<double> lp(lb);
-        MHIP(hipMemcpyAsync(lp.data(), w->lpart, lb * sizeof(double), hipMemcpyDeviceToHost, s));
-        MHIP(hipStreamSynchronize(s));
-        double acc = 0.0;
-        for (double x : lp) acc += x;
-        *loss = rows > 0 ? acc / (double)rows : 0.0;
+    const int nb = train_blocks(rows);
+    if (!w->lacc) {
+        int rc;
+        if ((rc = malloc_d(&w->lacc, 8))) return rc;
     }
+    if (nb <= w->gcap) return CBLP_OK;
+    if (w->Gpart) (void)hipFree(w->Gpart);
+    if (w->lpart) (void)hipFree(w->lpart);
+    w->Gpart = nullptr;
+    w->lpart = nullptr;
+    w->gcap = 0;
+    int rc;
+    if ((rc = malloc_d(&w->Gpart, (size_t)nb * kGStride * 4)) || (rc = malloc_d(&w->lpart, (size_t)nb * 8)))
+        return rc;
+    w->gcap = nb;
     return CBLP_OK;
 }
 
-int adam(wsnet* w, float lr, hipStream_t s)
+// one training pass over rows (X, Y)[perm ? perm[r] : r], r < rows: the
+// gradient into w->G, the squared error added to w->lacc, and with lr > 0 an
+// Adam step.  Two launches.
+int train_pass(wsnet* w, const float* X, const float* Y, const int32_t* perm, int64_t rows, float lr,
+               hipStream_t s)
 {
-    w->step += 1;
+    const int nb = train_blocks(rows);
+    TrainArgs a;
+    a.X = X;
+    a.Y = Y;
+    a.perm = perm;
+    a.cnt = rows;
+    a.inv2 = 2.0f / (float)rows;
+    a.P = w->P;
+    a.W2b = w->W2b;
+    a.W2t = w->W2t;
+    a.Gpart = w->Gpart;
+    a.lpart = w->lpart;
+    hipLaunchKernelGGL(k_train, dim3(nb), dim3(kTThreads), 0, s, a);
+    float c1 = 1.0f, c2 = 1.0f;
     const float b1 = 0.9f, b2 = 0.999f;
-    const float c1 = 1.0f - std::pow(b1, (float)w->step), c2 = 1.0f - std::pow(b2, (float)w->step);
-    hipLaunchKernelGGL(k_adam, dim3((unsigned)((NPARAM + 255) / 256)), dim3(256), 0, s, w->P, w->G,
-                       w->M, w->V, NPARAM, lr, b1, b2, 1e-8f, c1, c2);
-    hipLaunchKernelGGL(k_round_w2, dim3(HID), dim3(HID), 0, s, w->P + OFF_W2, w->W2b, w->W2t);
+    if (lr > 0.0f) {
+        w->step += 1;
+        c1 = 1.0f - std::pow(b1, (float)w->step);
+        c2 = 1.0f - std::pow(b2, (float)w->step);
+    }
+    hipLaunchKernelGGL(k_train_reduce, dim3((unsigned)((NPARAM + 1023) / 1024)), dim3(256), 0, s,
+                       w->Gpart, nb, w->lpart, w->G, w->P, w->M, w->V, lr > 0.0f ? 1 : 0, lr, b1, b2,
+                       1e-8f, c1, c2, w->W2b, w->W2t, w->lacc);
     MHIP(hipGetLastError());
     return CBLP_OK;
 }
 
-int load_rows(wsnet* w, const float* X, int64_t rows, int64_t rpad, hipStream_t s)
+// the loss accumulator: cleared / read back (synchronises)
+int loss_clear(wsnet* w, hipStream_t s)
 {
-    MHIP(hipMemcpyAsync(w->X, X, (size_t)rows * IN * 4, hipMemcpyDeviceToDevice, s));
-    if (rpad > rows) MHIP(hipMemsetAsync(w->X + rows * IN, 0, (size_t)(rpad - rows) * IN * 4, s));
+    hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(64), 0, s, w->lacc, (int64_t)1, 0.0);
+    MHIP(hipGetLastError());
+    return CBLP_OK;
+}
+
+int loss_read(wsnet* w, double* out, hipStream_t s)
+{
+    MHIP(hipMemcpyAsync(w->pinned, w->lacc, 8, hipMemcpyDeviceToHost, s));
+    MHIP(hipStreamSynchronize(s));
+    *out = w->pinned[0];
     return CBLP_OK;
 }
 
@@ -800,7 +902,7 @@ int wsnet_forward(wsnet_t w, const float* X, int64_t rows, float* y, void* strea
     if (!w || !X || !y || rows < 0) return mfail(CBLP_EINVAL, "NULL argument or rows < 0");
     if (rows == 0) return CBLP_OK;
     hipStream_t s = (hipStream_t)stream;
-    hipLaunchKernelGGL(k_mlp_infer, dim3((unsigned)((rows + kInferRows - 1) / kInferRows)),
+    hipLaunchKernelGGL(k_mlp_infer, dim3((unsigned)((rows + kRows - 1) / kRows)),
                        dim3(256), 0, s, X, rows,
                        w->P, w->W2t, y);
     MHIP(hipGetLastError());
@@ -814,12 +916,13 @@ int wsnet_gradients(wsnet_t w, const float* X, const float* Y, int64_t rows, flo
     if (!w || !X || !Y || rows < 1) return mfail(CBLP_EINVAL, "NULL argument or rows < 1");
     hipStream_t s = (hipStream_t)stream;
     int rc;
-    if ((rc = ensure_scratch(w, rows))) return rc;
-    const int64_t rpad = pad16(rows);
-    if ((rc = load_rows(w, X, rows, rpad, s))) return rc;
-    if ((rc = backward(w, Y, rows, rpad, loss, s))) return rc;
+    if ((rc = ensure_train(w, rows)) || (rc = loss_clear(w, s)) ||
+        (rc = train_pass(w, X, Y, nullptr, rows, 0.0f, s)))
+        return rc;
     if (grads) MHIP(hipMemcpyAsync(grads, w->G, NPARAM * 4, hipMemcpyDeviceToDevice, s));
-    MHIP(hipStreamSynchronize(s));
+    double e = 0.0;
+    if ((rc = loss_read(w, &e, s))) return rc;
+    if (loss) *loss = e / (double)rows;
     return CBLP_OK;
 }
 
@@ -830,11 +933,15 @@ int wsnet_train_step(wsnet_t w, const float* X, const float* Y, int64_t rows, fl
     if (!w || !X || !Y || rows < 1 || !(lr > 0.0f)) return mfail(CBLP_EINVAL, "bad argument");
     hipStream_t s = (hipStream_t)stream;
     int rc;
-    if ((rc = ensure_scratch(w, rows))) return rc;
-    const int64_t rpad = pad16(rows);
-    if ((rc = load_rows(w, X, rows, rpad, s))) return rc;
-    if ((rc = backward(w, Y, rows, rpad, loss, s))) return rc;
-    return adam(w, lr, s);
+    if ((rc = ensure_train(w, rows))) return rc;
+    if (loss && (rc = loss_clear(w, s))) return rc;
+    if ((rc = train_pass(w, X, Y, nullptr, rows, lr, s))) return rc;
+    if (loss) {
+        double e = 0.0;
+        if ((rc = loss_read(w, &e, s))) return rc;
+        *loss = e / (double)rows;
+    }
+    return CBLP_OK;
 }
 
 int wsnet_train_epochs(wsnet_t w, const float* X, const float* Y, int64_t rows, int64_t batch,
@@ -847,13 +954,9 @@ int wsnet_train_epochs(wsnet_t w, const float* X, const float* Y, int64_t rows, 
     hipStream_t s = (hipStream_t)stream;
     batch = std::min(batch, rows);
     int rc;
-    if ((rc = ensure_scratch(w, batch))) return rc;
+    if ((rc = ensure_train(w, batch))) return rc;
     int32_t* perm = nullptr;
-    double* acc = nullptr;
-    if ((rc = malloc_d(&perm, (size_t)rows * 4)) || (rc = malloc_d(&acc, 8))) {
-        if (perm) (void)hipFree(perm);
-        return rc;
-    }
+    if ((rc = malloc_d(&perm, (size_t)rows * 4))) return rc;
     std::vector<int32_t> hp(rows);
     std::mt19937_64 rng(seed);
     for (int32_t e = 0; e < epochs && rc == CBLP_OK; ++e) {
@@ -866,28 +969,18 @@ int wsnet_train_epochs(wsnet_t w, const float* X, const float* Y, int64_t rows, 
             rc = mfail(CBLP_EHIP, "uploading the minibatch order failed");
             break;
         }
-        hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(64), 0, s, acc, (int64_t)1, 0.0);
-        for (int64_t b0 = 0; b0 < rows && rc == CBLP_OK; b0 += batch) {
-            const int64_t cnt = std::min(batch, rows - b0);
-            const int64_t rpad = pad16(cnt);
-            hipLaunchKernelGGL(k_gather, dim3((unsigned)((rpad + 255) / 256)), dim3(256), 0, s, X, Y,
-                               perm + b0, cnt, rpad, w->X, w->Yb);
-            // each batch's mean loss weighted by its rows: acc gets sum of squared errors
-            if ((rc = backward(w, w->Yb, cnt, rpad, nullptr, s, acc))) break;
-            rc = adam(w, lr, s);
-        }
+        if ((rc = loss_clear(w, s))) break;
+        // each minibatch's mean loss weighted by its rows: the accumulator gets
+        // the sum of squared errors
+        for (int64_t b0 = 0; b0 < rows && rc == CBLP_OK; b0 += batch)
+            rc = train_pass(w, X, Y, perm + b0, std::min(batch, rows - b0), lr, s);
         if (rc) break;
         double h = 0.0;
-        if (hipMemcpyAsync(&h, acc, 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
-            hipStreamSynchronize(s) != hipSuccess) {
-            rc = mfail(CBLP_EHIP, "reading the epoch loss failed");
-            break;
-        }
+        if ((rc = loss_read(w, &h, s))) break;
         if (losses) losses[e] = h / (double)rows;
     }
     (void)hipStreamSynchronize(s);
     (void)hipFree(perm);
-    (void)hipFree(acc);
     return rc;
 }
 
@@ -915,10 +1008,10 @@ int wsnet_predict(wsnet_t w, cblp_t h, void* eta, void* stream)
     if (h->a_ptr) return mfail(CBLP_EINVAL, "warm start needs the identity resource matrix");
     hipStream_t s = (hipStream_t)stream;
     int rc;
-    if ((rc = ensure_scratch(w, h->n))) return rc;
+    if ((rc = ensure_rows(w, h->n))) return rc;
     rc = h->dtype == CBLP_F32 ? features_impl<float>(h, w->X, s) : features_impl<double>(h, w->X, s);
     if (rc) return rc;
-    hipLaunchKernelGGL(k_mlp_infer, dim3((unsigned)((h->n + kInferRows - 1) / kInferRows)),
+    hipLaunchKernelGGL(k_mlp_infer, dim3((unsigned)((h->n + kRows - 1) / kRows)),
                        dim3(256), 0, s, w->X, h->n,
                        w->P, w->W2t, w->y);
     const unsigned g = (unsigned)((h->n + 255) / 256);
