@@ -474,37 +474,65 @@ def gosim_bench(args):
     sim.close()
 
 
+def _ws_train_instance(job):
+    """One training instance of the learned warm start (run in a worker process)."""
+    from paper_2602_22421_amd.instances import config_instance
+    seed, L, caps = job
+    return config_instance(1, seed=seed, L=L, cap_lo=caps[0], cap_hi=caps[1],
+                           name=f"ws-train-{seed}").cast(np.float32)
+
+
 def warmstart_bench(args):
-    """Learned warm start: train the network on the duals of solved L=1e5
-    instances of the L=2e6 Zipf generator, then solve held-out L=2e6 instances
-    from its prediction and from zero with the same constant step, recording
-    the iterations and seconds each start needs to certify each gap level
-    (prediction and fallback check included in the warm time)."""
+    """Learned warm start on its stated workload: generate --ws-train
+    instances of the L=2e6 Zipf generator at L=1e5 (n=2e4 products, the same
+    capacity law), solve each from zero (decaying constant step, FP32
+    iterate) and collect every product's features and dual; train the network
+    on the GPU; then solve held-out L=2e6 instances from its prediction (the
+    library's fallback to zero included) and from zero with the same step,
+    recording the iterations and seconds each start needs to certify each gap
+    level.  Instances are generated by worker processes (started fresh, not
+    forked) while the GPU solves."""
+    import multiprocessing as mp
     import torch
     from paper_2602_22421_amd import cblp, warmstart
     from paper_2602_22421_amd.instances import config_instance, step_scale
 
     caps = {"tight": (0.2, 0.5), "loose": (0.5, 3.0)}[args.ws_caps]
-    stages = [(3e-3, 1500), (1e-3, 1000), (3e-4, 1000)]
-    spec = warmstart.SolveSpec(rule=cblp.SPFOM_STEP_CONST, tau0=args.ws_tau0, check_every=10,
-                               tol=0.0, max_iters=args.max_iters)
+    train_L = 100_000
     t0 = time.perf_counter()
-    train_insts = (config_instance(1, seed=10_000 + s, scale=0.05, cap_lo=caps[0], cap_hi=caps[1])
-                   .cast(np.float32) for s in range(args.ws_train))
-    X, Y = warmstart.collect(train_insts, spec, dtype=torch.float32, stages=stages)
+    jobs = [(10_000 + s, train_L, caps) for s in range(args.ws_train)]
+    xs, ys, gaps = [], [], []
+    workers = max(1, min(16, (os.cpu_count() or 2) - 1))
+    with mp.get_context("spawn").Pool(workers) as pool:
+        for k, inst in enumerate(pool.imap(_ws_train_instance, jobs)):
+            prob = cblp.Problem(inst, dtype=torch.float32)
+            tau = prob.tensor(step_scale(inst, args.ws_tau0).astype(np.float32))
+            prm = cblp.make_params(rule=cblp.SPFOM_STEP_CONST, tau_vec=tau, check_every=10,
+                                   tau_decay=args.tau_decay, decay_every=args.decay_every)
+            eta = prob.zeros_eta()
+            _, st = prob.iterate(eta, args.ws_target_iters, prm, trace=False)
+            gaps.append(st.as_dict()["gap"])
+            xs.append(cblp.features(prob))
+            ys.append(cblp.targets(prob, eta))
+            prob.close()
+            if k % 64 == 0:
+                log(f"collect {k}: gap {gaps[-1]:.3e} after {args.ws_target_iters} iterations "
+                    f"({time.perf_counter() - t0:.1f} s)")
+    X, Y = torch.cat(xs).contiguous(), torch.cat(ys).contiguous()
+    del xs, ys
     t_collect = time.perf_counter() - t0
-    log(f"collected {X.shape[0]} products from {args.ws_train} solved L=1e5 instances "
-        f"in {t_collect:.1f} s")
+    log(f"collected {X.shape[0]} products from {args.ws_train} solved L=1e5, n=2e4 instances "
+        f"in {t_collect:.1f} s (median target gap {np.median(gaps):.3e})")
     net = cblp.WarmStartNet(seed=0)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    losses = warmstart.train(net, X, Y, epochs=args.ws_epochs, batch=2048, lr=3e-4)
+    losses = warmstart.train(net, X, Y, epochs=args.ws_epochs, batch=16384, lr=3e-4)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
     log(f"trained {args.ws_epochs} epochs in {t_train:.1f} s: loss {losses[0]:.3e} -> "
         f"{losses[-1]:.3e} (target variance {float(Y.var()):.3e})")
     # matrix-core throughput of the network: forward over every training row,
-    # and one epoch of training steps (forward, two backward products, Adam)
+    # and one epoch of training steps (2 launches each)
     rows = X.shape[0]
     flops_fwd = 2.0 * rows * (4 * 256 + 256 * 256 + 256)
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
@@ -514,40 +542,44 @@ def warmstart_bench(args):
         net.forward(X)
     ev[1].record()
     ev[2].record()
-    net.train(X, Y, epochs=1, batch=2048, lr=1e-6, seed=1)
+    net.train(X, Y, epochs=1, batch=16384, lr=1e-6, seed=1)
     ev[3].record()
     torch.cuda.synchronize()
     fwd_s = ev[0].elapsed_time(ev[1]) / 5e3
     ep_s = ev[2].elapsed_time(ev[3]) / 1e3
-    # inference (wsnet_forward) is one fused kernel: 16 B in and 4 B out per row
     mlp = {"rows": rows, "forward_ms": fwd_s * 1e3,
            "forward_tflops": flops_fwd / fwd_s / 1e12,
            "forward_frac_bf16_peak": flops_fwd / fwd_s / BF16_PEAK,
-           "train_epoch_ms": ep_s * 1e3,
+           "train_epoch_ms": ep_s * 1e3, "train_batch": 16384,
            "train_tflops": 3.0 * flops_fwd / ep_s / 1e12,
            "train_frac_bf16_peak": 3.0 * flops_fwd / ep_s / BF16_PEAK}
     log(f"network: forward {fwd_s * 1e3:.2f} ms over {rows} rows "
-        f"({mlp['forward_tflops']:.1f} TFLOP/s), training epoch {ep_s * 1e3:.1f} ms")
-    levels = (1e-1, 3e-2, 2e-2, 1e-2, 1e-3, 1e-4)
+        f"({mlp['forward_tflops']:.1f} TFLOP/s), training epoch {ep_s * 1e3:.1f} ms "
+        f"({mlp['train_tflops']:.1f} TFLOP/s)")
+    levels = (1e-1, 3e-2, 1e-2, 3e-3, 1e-3, 1e-4)
     results = []
     for seed in args.ws_eval_seeds:
         inst = config_instance(1, seed=seed, cap_lo=caps[0], cap_hi=caps[1]).cast(np.float32)
         prob = cblp.Problem(inst, dtype=torch.float32)
         tau = prob.tensor(step_scale(inst, args.ws_tau0).astype(np.float32))
-        params = cblp.make_params(rule=cblp.SPFOM_STEP_CONST, tau_vec=tau, check_every=10)
+        params = cblp.make_params(rule=cblp.SPFOM_STEP_CONST, tau_vec=tau, check_every=10,
+                                  tau_decay=args.tau_decay, decay_every=args.decay_every)
         row = {"seed": seed}
-        for start in ("cold", "warm"):
+        starts = ([f"cold-x{f:g}" for f in args.ws_cold_tau] +
+                  [f"warm-x{f:g}" for f in args.ws_warm_tau])
+        for start in starts:
+            scale = float(start[6:])
+            params = cblp.make_params(rule=cblp.SPFOM_STEP_CONST, tau_vec=tau * scale,
+                                      check_every=10, tau_decay=args.tau_decay,
+                                      decay_every=args.decay_every)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             info = {}
-            if start == "warm":
-                eta = net.predict(prob)
-                d_pred, d0 = prob.gap(eta)["D"], prob.gap(prob.zeros_eta())["D"]
-                info = {"D_pred": d_pred, "D0": d0, "used": bool(d_pred < d0)}
-                if not info["used"]:
-                    eta.zero_()
+            if start.startswith("warm"):
+                eta, info = net.start(prob)    # prediction and fallback, in the library
             else:
                 eta = prob.zeros_eta()
+            torch.cuda.synchronize()
             t_start = time.perf_counter() - t0
             prob.reset()
             tr = np.zeros((args.max_iters, cblp.NTRACE))
@@ -562,38 +594,51 @@ def warmstart_bench(args):
                 it = int((k[0] + 1) * 10) if len(k) else None
                 reach[f"{lv:g}"] = None if it is None else {
                     "iters": it, "seconds": t_start + it * per_iter}
-            row[start] = dict(info, reach=reach, final_gap=float(gaps[-1]),
+            row[start] = dict(info, reach=reach, final_gap=float(gaps.min()),
                               dbest=float(tr[-1, 5]), start_seconds=t_start,
                               ms_per_iter=per_iter * 1e3)
-            log(f"seed {seed} {start}: final gap {gaps[-1]:.3e}, reach {reach}")
+            log(f"seed {seed} {start}: best gap {gaps.min():.3e}, reach {reach}")
         results.append(row)
         prob.close()
 
-    def speedup(lv):
-        r = []
-        for row in results:
-            c, w = row["cold"]["reach"][lv], row["warm"]["reach"][lv]
-            if c and w:
-                r.append(c["seconds"] / w["seconds"])
-        return float(np.mean(r)) if r else None
+    colds = [f"cold-x{f:g}" for f in args.ws_cold_tau]
+    warms = [f"warm-x{f:g}" for f in args.ws_warm_tau]
 
-    head = f"{3e-2:g}"
+    def mean_seconds(start, lv):
+        v = [r[start]["reach"][lv] for r in results]
+        return float(np.mean([x["seconds"] for x in v])) if all(v) else None
+
+    def best_cold(lv):
+        v = [x for x in (mean_seconds(c, lv) for c in colds) if x is not None]
+        return min(v) if v else None
+
+    def speedup(lv, warm):
+        c, w = best_cold(lv), mean_seconds(warm, lv)
+        return c / w if c and w else None
+
+    reached = [f"{lv:g}" for lv in levels if best_cold(f"{lv:g}") and mean_seconds(warms[0], f"{lv:g}")]
+    head = reached[-1] if reached else None
     out = {
-        "metric": "time to certified gap 3e-2, warm start vs cold", "unit": "s",
-        "value": float(np.mean([r["warm"]["reach"][head]["seconds"] for r in results
-                                if r["warm"]["reach"][head]])) if all(
-            r["warm"]["reach"][head] for r in results) else None,
+        "metric": f"time to certified gap {head}, warm start ({warms[0]}) vs the fastest cold "
+                  f"start of steps x{args.ws_cold_tau} (the tightest level both reach on every "
+                  f"held-out instance)", "unit": "s",
+        "value": mean_seconds(warms[0], head) if head else None,
+        "cold_value": best_cold(head) if head else None,
+        "levels_only_warm": [f"{lv:g}" for lv in levels
+                             if mean_seconds(warms[0], f"{lv:g}") and not best_cold(f"{lv:g}")],
         "higher_is_better": False, "n_gpus": 1, "dtype": "f32", "data": "synthetic",
         "vs_baseline": None,
         "config": {"workload": f"warm-start-L2e6-n2e4-zipf-caps-{args.ws_caps}",
-                   "train": f"{args.ws_train} instances L=1e5 n=4472, targets after "
-                            f"{sum(k for _, k in stages)} staged iterations",
-                   "epochs": args.ws_epochs, "tau0": args.ws_tau0,
-                   "max_iters": args.max_iters, "caps": caps},
-        "speedup_by_level": {f"{lv:g}": speedup(f"{lv:g}") for lv in levels},
+                   "train": f"{args.ws_train} instances L=1e5 n=2e4 (the L=2e6 generator at "
+                            f"L=1e5), targets after {args.ws_target_iters} iterations",
+                   "epochs": args.ws_epochs, "tau0": args.ws_tau0, "tau_decay": args.tau_decay,
+                   "decay_every": args.decay_every, "max_iters": args.max_iters, "caps": caps},
+        "speedup_by_level": {w: {f"{lv:g}": speedup(f"{lv:g}", w) for lv in levels}
+                             for w in warms},
         "network": mlp,
         "collect_s": t_collect, "train_s": t_train, "loss_first": losses[0],
-        "loss_last": losses[-1], "target_variance": float(Y.var()), "eval": results,
+        "loss_last": losses[-1], "target_variance": float(Y.var()),
+        "target_gap_median": float(np.median(gaps)), "eval": results,
     }
     print(json.dumps(out), flush=True)
     net.close()
@@ -644,9 +689,14 @@ def main():
     ap.add_argument("--ws-caps", default="tight", choices=["tight", "loose"],
                     help="capacities 0.2-0.5x (tight, the L=2e6 workload's) or 0.5-3x (loose) "
                          "of the full-offer demand")
-    ap.add_argument("--ws-train", type=int, default=64)
-    ap.add_argument("--ws-epochs", type=int, default=40)
-    ap.add_argument("--ws-tau0", type=float, default=1e-3)
+    ap.add_argument("--ws-train", type=int, default=512)
+    ap.add_argument("--ws-target-iters", type=int, default=4000)
+    ap.add_argument("--ws-epochs", type=int, default=30)
+    ap.add_argument("--ws-tau0", type=float, default=3e-3)
+    ap.add_argument("--ws-warm-tau", type=float, nargs="+", default=[0.1],
+                    help="warm solves: their steps as multiples of tau0")
+    ap.add_argument("--ws-cold-tau", type=float, nargs="+", default=[1.0, 0.3, 0.1],
+                    help="cold solves: their steps as multiples of tau0")
     ap.add_argument("--ws-eval-seeds", type=int, nargs="+", default=[101, 102])
     ap.add_argument("--shuffle-products", action="store_true",
                     help="number the products in random order (the generator numbers them by "
@@ -696,8 +746,8 @@ def main():
                 args.max_iters = 20000
             return time_to_gap(args)
         if args.warmstart:
-            if args.max_iters == 2000 and "--max-iters" not in sys.argv:
-                args.max_iters = 3000
+            if "--max-iters" not in sys.argv:
+                args.max_iters = 12000
             return warmstart_bench(args)
         x = torch.ones(1 << 28, dtype=torch.float32, device="cuda")   # 1 GiB
         y = torch.empty_like(x)
