@@ -587,17 +587,17 @@ def warmstart_bench(args):
             cblp.spfom_iterate(prob.h, eta, params, args.max_iters, tr)
             torch.cuda.synchronize()
             per_iter = (time.perf_counter() - t1) / args.max_iters
-            gaps = tr[9::10, 7]
+            cgaps = tr[9::10, 7]
             reach = {}
             for lv in levels:
-                k = np.nonzero(gaps <= lv)[0]
+                k = np.nonzero(cgaps <= lv)[0]
                 it = int((k[0] + 1) * 10) if len(k) else None
                 reach[f"{lv:g}"] = None if it is None else {
                     "iters": it, "seconds": t_start + it * per_iter}
-            row[start] = dict(info, reach=reach, final_gap=float(gaps.min()),
+            row[start] = dict(info, reach=reach, final_gap=float(cgaps.min()),
                               dbest=float(tr[-1, 5]), start_seconds=t_start,
                               ms_per_iter=per_iter * 1e3)
-            log(f"seed {seed} {start}: best gap {gaps.min():.3e}, reach {reach}")
+            log(f"seed {seed} {start}: best gap {cgaps.min():.3e}, reach {reach}")
         results.append(row)
         prob.close()
 
