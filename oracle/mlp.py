@@ -3,9 +3,10 @@
 Only the tests, the package smoke check and the benchmark may use this module;
 the solver library never imports or runs it.  It restates, in plain numpy:
 
-* the per-product features the warm start reads (definitions in the library
-  header: capacity over full-offer demand, normalised revenue, attraction mass
-  and degree), computed straight from the instance's CSR rows;
+* the features the warm start reads for each dual's row (definitions in the
+  library header: capacity over full-offer demand, normalised revenue,
+  attraction mass and degree; per product for A = I, per resource through the
+  weights a_ij otherwise), computed straight from the instance's CSR rows;
 * the network y = w3 . GELU(W2^T GELU(W1^T x + b1) + b2) + b3 and its
   mean-squared-error gradient by backpropagation, in FP64, with BF16 rounding
   (round to nearest even) applied at the points the GPU kernels round: every
@@ -117,8 +118,9 @@ def adam_step(p, g, m, v, step: int, lr: float, b1=0.9, b2=0.999, eps=1e-8):
     return p - lr * mh / (np.sqrt(vh) + eps), m, v
 
 
-def features(inst) -> np.ndarray:
-    """Per-product features [n, 4] straight from the CSR rows (identity A)."""
+def _product_sums(inst):
+    """Per product: sales with every set offered whole (d), attraction mass
+    and the number of segments holding it."""
     L, n = int(inst.L), int(inst.n)
     ptr = np.asarray(inst.seg_ptr, dtype=np.int64)
     idx = np.asarray(inst.idx, dtype=np.int64)
@@ -129,17 +131,57 @@ def features(inst) -> np.ndarray:
     d = np.bincount(idx, weights=share, minlength=n)
     att = np.bincount(idx, weights=v, minlength=n)
     deg = np.bincount(idx, minlength=n).astype(np.float64)
-    c = np.asarray(inst.c, dtype=np.float64)
+    return d, att, deg
+
+
+def resource_scale(inst) -> np.ndarray:
+    """The scale of each dual: r_j for A = I; for a resource matrix, the
+    largest revenue per unit of resource i over the products that use it,
+    max r_j / a_ij over a_ij > 0 (0 if no product uses it)."""
     r = np.asarray(inst.r, dtype=np.float64)
-    X = np.empty((n, IN))
+    if inst.a_ptr is None:
+        return r.copy()
+    out = np.full(int(inst.m), -np.inf)
+    prod = np.repeat(np.arange(int(inst.n)), np.diff(np.asarray(inst.a_ptr)))
+    ai = np.asarray(inst.a_idx, dtype=np.int64)
+    av = np.asarray(inst.a_val, dtype=np.float64)
+    use = av > 0
+    np.maximum.at(out, ai[use], r[prod[use]] / av[use])
+    return np.where(np.isfinite(out), out, 0.0)
+
+
+def features(inst) -> np.ndarray:
+    """Features [m, 4] of every dual's row, straight from the CSR rows: per
+    product for A = I (m = n); per resource i otherwise, from the product sums
+    weighted by a_ij: D_i = sum_j a_ij d_j, mass sum_j a_ij att_j, and the
+    entries touching i sum_j deg_j (over the stored entries of row i)."""
+    L, m = int(inst.L), int(inst.m)
+    d, att, deg = _product_sums(inst)
+    if inst.a_ptr is not None:
+        prod = np.repeat(np.arange(int(inst.n)), np.diff(np.asarray(inst.a_ptr)))
+        ai = np.asarray(inst.a_idx, dtype=np.int64)
+        av = np.asarray(inst.a_val, dtype=np.float64)
+        d = np.bincount(ai, weights=av * d[prod], minlength=m)
+        att = np.bincount(ai, weights=av * att[prod], minlength=m)
+        deg = np.bincount(ai, weights=deg[prod], minlength=m)
+    c = np.asarray(inst.c, dtype=np.float64)
+    r = resource_scale(inst)
+    X = np.empty((m, IN))
     with np.errstate(divide="ignore", invalid="ignore"):
         X[:, 0] = np.where(d > 0, np.minimum(c / np.where(d > 0, d, 1.0), 4.0), 4.0)
-    rmax = max(float(r.max()) if n else 0.0, 0.0)
+    rmax = max(float(r.max()) if m else 0.0, 0.0)
     X[:, 1] = r / rmax if rmax > 0 else 0.0
-    s = n / L if L > 0 else 0.0
+    s = m / L if L > 0 else 0.0
     X[:, 2] = np.log1p(att * s)
     X[:, 3] = np.log1p(deg * s)
     return X
+
+
+def targets(inst, eta) -> np.ndarray:
+    """What the network predicts: eta_i / scale_i (0 where the scale is <= 0)."""
+    sc = resource_scale(inst)
+    eta = np.asarray(eta, dtype=np.float64)
+    return np.where(sc > 0, eta / np.where(sc > 0, sc, 1.0), 0.0)
 
 
 def init_params(seed: int) -> np.ndarray:

@@ -10,8 +10,10 @@ setup): customer segments l in [L] with arrival rates lambda_l, products j in
 nominal attractions v_lj and shadow attractions w_lj of the generalized
 attraction model (Section 3, GAM choice probability), a no-purchase attraction
 v_l0, and capacitated resources i in [m] with capacities c_i.  Products consume
-resources through a 0/1 matrix A (Section 5.2, NRM with bundling); A = identity
-(m == n) is the plain single-resource-per-product case of Sections 3-4.
+resources through a matrix A (Section 5.2, NRM with bundling: a bundle uses
+a_ij units of base product i; 0/1 in the paper, any nonnegative weight
+here); A = identity (m == n) is the plain single-resource-per-product case of
+Sections 3-4.
 
 Notation: the paper names customers i in [n], products j in [m] and writes w for
 the nominal and v for the shadow attraction.  Here segments are l in [L],
@@ -159,10 +161,14 @@ def make_instance(L: int, n: int, *, m: Optional[int] = None, size_lo: int = 5,
                   lam_dist: str = "uniform", cap_lo: float = 0.3,
                   cap_hi: Optional[float] = None, cap_scale: float = 1.0,
                   res_lo: int = 1, res_hi: int = 3, shadow_hi: float = 0.5,
+                  a_lo: float = 1.0, a_hi: Optional[float] = None, a_int: bool = False,
                   seed: int = 0, chunk: int = 1 << 20, name: str = "") -> Instance:
     """Draw one instance.  ``m`` None means A = identity (m = n); otherwise
-    every product consumes res_lo..res_hi distinct random resources at unit
-    weight.  ``cap_hi`` None means the capacity factor is exactly ``cap_lo``."""
+    every product (a bundle, Section 5.2) consumes res_lo..res_hi distinct
+    random resources (base products), at unit weight when ``a_hi`` is None,
+    else at weights U(a_lo, a_hi) (``a_int``: integers U{a_lo..a_hi}, units
+    of the base product per bundle).  ``cap_hi`` None means the capacity
+    factor is exactly ``cap_lo``."""
     if L < 0 or n <= 0:
         raise ValueError("need L >= 0 and n > 0")
     size_hi = min(size_hi, n)
@@ -211,9 +217,14 @@ def make_instance(L: int, n: int, *, m: Optional[int] = None, size_lo: int = 5,
         np.cumsum(cnt, out=a_ptr[1:])
         dd = _draw_sets(g_res, cnt, m, None)
         a_idx = dd[dd < m].astype(np.int32)
-        a_val = np.ones(a_idx.shape[0])
+        if a_hi is None:
+            a_val = np.ones(a_idx.shape[0])
+        elif a_int:
+            a_val = g_res.integers(int(a_lo), int(a_hi) + 1, size=a_idx.shape[0]).astype(np.float64)
+        else:
+            a_val = g_res.uniform(a_lo, a_hi, size=a_idx.shape[0])
         prod_of = _row_ids(a_ptr)
-        row_demand = np.bincount(a_idx, weights=demand[prod_of], minlength=m)
+        row_demand = np.bincount(a_idx, weights=demand[prod_of] * a_val, minlength=m)
 
     if cap_hi is None:
         f = np.full(m, cap_lo)

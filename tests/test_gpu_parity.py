@@ -198,15 +198,38 @@ def test_iterate_fp32_scaled_zipf(cb):
             assert rel(trg[:, col], tro[:, col]) <= 1e-5, (t, col)
 
 
+@pytest.mark.parametrize("weights", ["unit", "int", "real"])
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
-def test_iterate_resources(cb, dtype):
+def test_iterate_resources(cb, dtype, weights):
+    """The resource matrix of bundles (Section 5.2): unit weights as in the
+    paper, and bundles using several units (integers 1-3) or any positive
+    amount (U(0.5, 2)) of a base product."""
     dt = torch.float64 if dtype == "f64" else torch.float32
-    inst = config_instance(2, scale=0.002)
+    kw = {"unit": {}, "int": {"a_lo": 1, "a_hi": 3, "a_int": True},
+          "real": {"a_lo": 0.5, "a_hi": 2.0}}[weights]
+    inst = config_instance(2, scale=0.002, **kw)
     prob, params, orc, _ = _pair(cb, inst, dt, tau0=0.001, rule=0, mu=0.01)
     bar = 1e-8 if dtype == "f64" else 1e-5
     for t, eg, eo, trg, tro in _run_both(prob, params, orc, [1, 10, 60]):
         assert rel(eg, eo) <= bar, (t, rel(eg, eo))
         assert rel(trg[-1, 0], tro[-1, 0]) <= bar
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_weighted_resource_usage_matches_oracle(cb, dtype):
+    """u = A S with non-unit weights, element by element, at a fixed eta."""
+    dt = torch.float64 if dtype == "f64" else torch.float32
+    npdt = np.float64 if dtype == "f64" else np.float32
+    inst = config_instance(2, scale=0.002, a_lo=0.5, a_hi=2.0).cast(npdt)
+    prob = cb.Problem(inst, dtype=dt)
+    rng = np.random.default_rng(8)
+    eta = (rng.uniform(0, 0.3, inst.m) * float(inst.r.max()) / 3).astype(npdt)
+    S, u, _ = prob.sales(prob.tensor(eta))
+    ref = oracle.best_response(inst, eta.astype(np.float64))
+    tol = 1e-12 if dtype == "f64" else 2e-5
+    assert rel(S.cpu().numpy(), ref["S"]) <= tol
+    assert rel(u.cpu().numpy(), ref["u"]) <= tol
+    prob.close()
 
 
 def test_bitwise_deterministic(cb):

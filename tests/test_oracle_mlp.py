@@ -162,3 +162,61 @@ def test_features_brute_force_loops():
         x0 = min(inst.c[j] / d[j], 4.0) if d[j] > 0 else 4.0
         assert X[j, 0] == pytest.approx(x0, rel=1e-13)
         assert X[j, 2] == pytest.approx(np.log1p(a[j] * inst.n / inst.L), rel=1e-13)
+
+
+def test_resource_features_capacity_ratio_is_generator_factor():
+    """Resources: c_i = f (A d)_i with the weights, so feature 0 is f."""
+    inst = make_instance(3000, 200, m=40, size_lo=3, size_hi=12, zipf=1.1, cap_lo=0.35,
+                         a_lo=1, a_hi=3, a_int=True, seed=9)
+    X = om.features(inst)
+    assert X.shape == (40, 4)
+    prod = np.repeat(np.arange(inst.n), np.diff(inst.a_ptr))
+    deg = np.bincount(inst.idx, minlength=inst.n).astype(float)
+    hit = np.bincount(inst.a_idx, weights=deg[prod], minlength=inst.m) > 0
+    np.testing.assert_allclose(X[hit, 0], 0.35, rtol=1e-12)
+    assert np.all(X[~hit, 0] == 4.0)
+
+
+def test_resource_features_brute_force_loops():
+    inst = tiny_instance(9, 6, m=4, size_lo=1, size_hi=4, seed=3, cap_lo=0.3, cap_hi=0.6,
+                         a_lo=0.5, a_hi=2.0)
+    d = [0.0] * inst.n
+    a = [0.0] * inst.n
+    g = [0.0] * inst.n
+    for l in range(inst.L):
+        lo, hi = inst.seg_ptr[l], inst.seg_ptr[l + 1]
+        tot = inst.v0[l] + sum(inst.v[lo:hi])
+        for q in range(lo, hi):
+            d[inst.idx[q]] += inst.lam[l] * inst.v[q] / tot
+            a[inst.idx[q]] += inst.v[q]
+            g[inst.idx[q]] += 1.0
+    D, M, G = [0.0] * inst.m, [0.0] * inst.m, [0.0] * inst.m
+    rb = [None] * inst.m
+    for j in range(inst.n):
+        for q in range(inst.a_ptr[j], inst.a_ptr[j + 1]):
+            i, w = inst.a_idx[q], inst.a_val[q]
+            D[i] += w * d[j]
+            M[i] += w * a[j]
+            G[i] += g[j]
+            if w > 0:
+                rb[i] = inst.r[j] / w if rb[i] is None else max(rb[i], inst.r[j] / w)
+    rb = [0.0 if x is None else x for x in rb]
+    X = om.features(inst)
+    for i in range(inst.m):
+        x0 = min(inst.c[i] / D[i], 4.0) if D[i] > 0 else 4.0
+        assert X[i, 0] == pytest.approx(x0, rel=1e-13)
+        assert X[i, 1] == pytest.approx(rb[i] / max(rb), rel=1e-13)
+        assert X[i, 2] == pytest.approx(np.log1p(M[i] * inst.m / inst.L), rel=1e-13)
+        assert X[i, 3] == pytest.approx(np.log1p(G[i] * inst.m / inst.L), rel=1e-13)
+    np.testing.assert_allclose(om.resource_scale(inst), rb, rtol=1e-15)
+
+
+def test_identity_as_a_matrix_gives_product_features():
+    """A = I written out as a matrix gives the per-product features."""
+    import dataclasses
+    inst = make_instance(500, 30, size_lo=2, size_hi=8, seed=4, cap_lo=0.2, cap_hi=0.5)
+    eye = dataclasses.replace(inst, a_ptr=np.arange(inst.n + 1, dtype=np.int64),
+                              a_idx=np.arange(inst.n, dtype=np.int32), a_val=np.ones(inst.n))
+    np.testing.assert_allclose(om.features(eye), om.features(inst), rtol=1e-14)
+    eta = np.random.default_rng(0).uniform(0, 1, inst.n) * inst.r
+    np.testing.assert_allclose(om.targets(eye, eta), om.targets(inst, eta), rtol=1e-15)

@@ -160,11 +160,12 @@ def test_paper_fast_inner_with_golden_section(seed):
 
 
 def _tiny(seed, resources):
+    kw = {"a_lo": 0.5, "a_hi": 2.5} if resources == "weighted" else {}
     return tiny_instance(3, 5, m=3 if resources else None, seed=seed, size_lo=1,
-                         size_hi=5, cap_lo=0.3)
+                         size_hi=5, cap_lo=0.3, **kw)
 
 
-@pytest.mark.parametrize("resources", [False, True])
+@pytest.mark.parametrize("resources", [False, True, "weighted"])
 @pytest.mark.parametrize("seed", range(6))
 def test_cblp_equals_sblp_and_dual_is_tight(seed, resources):
     inst = _tiny(seed, resources)
@@ -326,9 +327,13 @@ def test_iteration_reaches_lp_optimum_config0():
     assert abs(dbest - opt) / opt <= 1e-4 and abs(opt - lb) / opt <= 1e-4
 
 
+@pytest.mark.parametrize("weights", [None, "int"])
 @pytest.mark.parametrize("seed", range(3))
-def test_iteration_brackets_lp_optimum_with_resources(seed):
-    inst = make_instance(60, 12, m=5, size_lo=2, size_hi=6, seed=seed, cap_lo=0.3)
+def test_iteration_brackets_lp_optimum_with_resources(seed, weights):
+    kw = {"a_lo": 1, "a_hi": 3, "a_int": True} if weights else {}
+    inst = make_instance(60, 12, m=5, size_lo=2, size_hi=6, seed=seed, cap_lo=0.3, **kw)
+    if weights:
+        assert np.any(inst.a_val > 1)
     opt, _ = lp.sblp(inst)
     s = oracle.Solver(inst, tau=step_scale(inst, 1.0), rule=oracle.RULE_POLYAK, gamma=1.0,
                       check_every=5, perseg=True)
