@@ -418,22 +418,29 @@ int gosim_run(cblp_batch_t b, int32_t periods, int32_t K, const void* prefs, con
               double* lp_gap, void* stream);
 
 /* ---------------------------------------------------------- learned warm start
- * A small network maps four features of each product to a starting capacity
- * dual for spfom_solve (identity resource matrix, m = n).  Not part of the
- * paper's method, which leaves learned starts to future work (Section 7); it
- * only changes the initial duals eta^0 that SPFOM takes as an input
- * (Algorithm 2, Section 4.1; its parallel form Algorithm 3, Section 4.3), so
- * every certificate (the dual bound D and the averaged-primal lower bound)
- * keeps its meaning.
+ * A small network maps four features of each dual's row (a product for the
+ * identity resource matrix, m = n; a resource - a base product of the
+ * bundles of Section 5.2 - otherwise) to a starting capacity dual for
+ * spfom_solve.  Not part of the paper's method, which leaves learned starts
+ * to future work (Section 7); it only changes the initial duals eta^0 that
+ * SPFOM takes as an input (Algorithm 2, Section 4.1; its parallel form
+ * Algorithm 3, Section 4.3), so every certificate (the dual bound D and the
+ * averaged-primal lower bound) keeps its meaning.
  *
- * Features per product j, written as X[j*4 + k] (FP32, [n x 4] row-major):
- *   k=0  min(c_j / d_j, 4), d_j = sum_l lambda_l v_lj / (v_l0 + sum_{i in N_l} v_li),
- *        the sales of j when every segment is offered its whole consideration
- *        set (4 where d_j = 0)
- *   k=1  r_j / max_i r_i  (0 if no revenue is positive)
- *   k=2  log1p((sum_l v_lj) * n / L)
- *   k=3  log1p(deg_j * n / L), deg_j = number of segments whose set holds j
- * The sums are taken in 64-bit fixed point, so X is bitwise reproducible.
+ * Per product j: d_j = sum_l lambda_l v_lj / (v_l0 + sum_{i in N_l} v_li),
+ * the sales of j when every segment is offered its whole consideration set;
+ * mass_j = sum_l v_lj; deg_j = number of segments whose set holds j.  For a
+ * resource i these become D_i = sum_j a_ij d_j, M_i = sum_j a_ij mass_j and
+ * G_i = sum_j deg_j over the products j with an entry in row i of A.  The
+ * scale of a dual is r_j (A = I) or s_i = max r_j / a_ij over the entries of
+ * row i with a_ij > 0 (0 if none): the largest revenue per unit of the
+ * resource.  Features, written as X[i*4 + k] (FP32, [m x 4] row-major):
+ *   k=0  min(c_i / D_i, 4)  (4 where D_i = 0)
+ *   k=1  s_i / max_k s_k    (0 if no scale is positive)
+ *   k=2  log1p(M_i * m / L)
+ *   k=3  log1p(G_i * m / L)
+ * The product sums are taken in 64-bit fixed point (then FP64 over each
+ * resource's entries in a fixed order), so X is bitwise reproducible.
  *
  * Network: y = w3 . GELU(W2^T GELU(W1^T x + b1) + b2) + b3 with hidden width
  * 256, GELU(z) = z Phi(z) (exact, erf form).  Parameters are one FP32 vector
@@ -441,17 +448,19 @@ int gosim_run(cblp_batch_t b, int32_t periods, int32_t K, const void* prefs, con
  * the weights of input k), b1 [256], W2 [256 x 256] (row i = hidden unit i of
  * the first layer), b2 [256], w3 [256], b3 [1].  Every weight is used rounded
  * to BF16 (nearest even); the second layer multiplies BF16(h1) by BF16(W2) on
- * the matrix cores with FP32 accumulation; everything else is FP32.  The
- * predicted dual is eta_j = max(0, y_j) * r_j.
+ * the matrix cores (16x16x32 BF16) with FP32 accumulation; everything else is
+ * FP32.  The predicted dual is eta_i = max(0, y_i) * scale_i.
  *
  * Training: mean squared error over rows, L = (1/rows) sum (y - t)^2, minimised
  * by Adam (beta1 0.9, beta2 0.999, eps 1e-8) on the FP32 parameters.  Backward
- * uses BF16(dZ2) against BF16(H1) and BF16(W2) on the matrix cores; parameter
- * gradients are summed over rows in FP64 in a fixed order.
+ * uses BF16(dZ2) against BF16(H1) and BF16(W2) on the matrix cores.  A step is
+ * two launches: blocks of 16 waves take 32-row chunks through forward, loss
+ * and backward and write per-block gradient sums (FP32 over their rows), which
+ * the second launch adds in block order in FP64 before the Adam update.
  *
- * All pointers named X, Y, y, grads, eta are [dev]; rows are padded inside to
- * a multiple of 16.  The net owns its parameters and a row-sized workspace it
- * grows on demand (calls on one net must not overlap).
+ * All pointers named X, Y, y, grads, eta are [dev].  The net owns its
+ * parameters and workspaces it grows on demand (calls on one net must not
+ * overlap).
  */
 typedef struct wsnet* wsnet_t;
 
@@ -465,7 +474,7 @@ void wsnet_destroy(wsnet_t w);
  * them (and clears the Adam state).  Synchronises the stream. */
 int wsnet_params(wsnet_t w, float* get, const float* set, void* stream);
 
-/* Features of the instance behind h into X [dev] [n x 4].  Synchronises. */
+/* Features of the instance behind h into X [dev] [m x 4].  Synchronises. */
 int wsnet_features(cblp_t h, float* X, void* stream);
 
 /* y [dev] [rows] = network(X [dev] [rows x 4]). */
@@ -490,12 +499,11 @@ int wsnet_train_step(wsnet_t w, const float* X, const float* Y, int64_t rows, fl
 int wsnet_train_epochs(wsnet_t w, const float* X, const float* Y, int64_t rows, int64_t batch,
                        int32_t epochs, float lr, uint64_t seed, double* losses, void* stream);
 
-/* Training targets of the instance behind h: Y [dev] [n] = eta_j / r_j, 0
- * where r_j <= 0 (eta [dev] [n], h's dtype); CBLP_EINVAL unless A = identity. */
+/* Training targets of the instance behind h: Y [dev] [m] = eta_i / scale_i,
+ * 0 where scale_i <= 0 (eta [dev] [m], h's dtype). */
 int wsnet_targets(cblp_t h, const void* eta, float* Y, void* stream);
 
-/* Predicted duals of the instance behind h into eta [dev] [n] (h's dtype);
- * CBLP_EINVAL unless A = identity. */
+/* Predicted duals of the instance behind h into eta [dev] [m] (h's dtype). */
 int wsnet_predict(wsnet_t w, cblp_t h, void* eta, void* stream);
 
 /* The warm start with its cold fallback: predict eta as wsnet_predict does,

@@ -804,12 +804,14 @@ class WarmStartNet:
 
 
 def targets(prob: "Problem", eta: torch.Tensor) -> torch.Tensor:
-    Y = torch.empty(prob.n, dtype=torch.float32, device=prob.device)
+    """What the network predicts for each dual's row ([m]; m = n for A = I)."""
+    Y = torch.empty(prob.m, dtype=torch.float32, device=prob.device)
     wsnet_targets(prob.h, eta, Y)
     return Y
 
 
 def features(prob: "Problem") -> torch.Tensor:
-    X = torch.empty((prob.n, 4), dtype=torch.float32, device=prob.device)
+    """Features of each dual's row ([m, 4]: per product for A = I, per resource otherwise)."""
+    X = torch.empty((prob.m, 4), dtype=torch.float32, device=prob.device)
     wsnet_features(prob.h, X)
     return X

@@ -166,6 +166,78 @@ __global__ void k_feat_fold(FeatArgs a, int nblocks, const T* r, const T* c, con
     x[3] = (float)log1p((double)dg * scale);
 }
 
+// Per product (caller id j): demand, attraction mass and degree in FP64 from
+// the fixed-point sums, for the resource features.
+__global__ void k_feat_prod(FeatArgs a, int nblocks, double* prod3)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= a.n) return;
+    const int64_t jq = a.pnew ? a.pnew[j] : j;
+    unsigned long long d = a.tail[jq], at = a.tail[a.n + jq], dg = a.tail[2 * a.n + jq];
+    if (jq < a.H)
+        for (int b = 0; b < nblocks; ++b) {
+            const unsigned long long* pr = a.part + (size_t)b * 3 * a.H;
+            d += pr[jq];
+            at += pr[a.H + jq];
+            dg += pr[2 * a.H + jq];
+        }
+    prod3[j] = (double)(long long)d / a.dscale;
+    prod3[a.n + j] = (double)(long long)at / a.ascale;
+    prod3[2 * a.n + j] = (double)dg;
+}
+
+// The scale of each resource's dual: the largest revenue per unit of the
+// resource, max r_j / a_ij over its entries with a_ij > 0 (0 if none); the
+// largest positive scale goes to *mx (non-negative doubles order like their
+// bit patterns).
+template <typename T>
+__global__ void k_res_scale(int64_t m, const int64_t* at_ptr, const int32_t* at_prod,
+                            const double* at_val, const T* r, double* scale,
+                            unsigned long long* mx)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    double best = 0.0;
+    bool any = false;
+    for (int64_t q = at_ptr[i]; q < at_ptr[i + 1]; ++q) {
+        const double w = at_val[q];
+        if (!(w > 0.0)) continue;
+        const double x = (double)r[at_prod[q]] / w;
+        best = any ? fmax(best, x) : x;
+        any = true;
+    }
+    scale[i] = best;
+    if (mx) atomicMax(mx, (unsigned long long)__double_as_longlong(fmax(best, 0.0)));
+}
+
+// Features of resource i from the product sums weighted by its entries:
+// capacity over sum_j a_ij d_j, scale over the largest scale, and the
+// attraction mass and entry count of its products, size-normalised by m / L.
+template <typename T>
+__global__ void k_feat_res(int64_t m, int64_t L, const int64_t* at_ptr, const int32_t* at_prod,
+                           const double* at_val, int64_t n, const double* prod3,
+                           const double* scale, const unsigned long long* mx, const T* c, float* X)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    double D = 0.0, M = 0.0, G = 0.0;
+    for (int64_t q = at_ptr[i]; q < at_ptr[i + 1]; ++q) {
+        const int64_t j = at_prod[q];
+        const double w = at_val[q];
+        D += w * prod3[j];
+        M += w * prod3[n + j];
+        G += prod3[2 * n + j];
+    }
+    const double smax = __longlong_as_double((long long)*mx);
+    const double sz = L > 0 ? (double)m / (double)L : 0.0;
+    const double ci = (double)c[i];
+    float* x = X + i * IN;
+    x[0] = (float)(D > 0.0 ? fmin(ci / D, 4.0) : 4.0);
+    x[1] = (float)(smax > 0.0 ? scale[i] / smax : 0.0);
+    x[2] = (float)log1p(M * sz);
+    x[3] = (float)log1p(G * sz);
+}
+
 // ------------------------------------------------------------ MLP layers
 
 // MFMA operands: v_mfma_f32_16x16x32_bf16 (gfx950).  Lane l holds
@@ -582,19 +654,20 @@ __global__ void k_round_w2(const float* W2, unsigned short* out, unsigned short*
     outT[u * HID + i] = x;
 }
 
-template <typename T>
-__global__ void k_eta_from_y(const float* y, const T* r, int64_t n, T* eta)
+// eta_i = max(y_i, 0) scale_i (scale: r for A = I, the resource scale otherwise)
+template <typename T, typename S>
+__global__ void k_eta_from_y(const float* y, const S* r, int64_t n, T* eta)
 {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j < n) eta[j] = (T)(fmaxf(y[j], 0.0f) * (float)r[j]);
 }
 
-// y_j = eta_j / r_j (0 where r_j <= 0): the quantity the network predicts
-template <typename T>
-__global__ void k_targets(const T* eta, const T* r, int64_t n, float* Y)
+// y_i = eta_i / scale_i (0 where scale_i <= 0): the quantity the network predicts
+template <typename T, typename S>
+__global__ void k_targets(const T* eta, const S* r, int64_t n, float* Y)
 {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j < n) Y[j] = r[j] > (T)0 ? (float)((double)eta[j] / (double)r[j]) : 0.0f;
+    if (j < n) Y[j] = r[j] > (S)0 ? (float)((double)eta[j] / (double)r[j]) : 0.0f;
 }
 
 __global__ void k_fill_f64(double* p, int64_t n, double v)
@@ -804,18 +877,58 @@ int features_impl(cblp_instance* h, float* X, hipStream_t s)
     }
     a.part = part;
     a.tail = tail;
+    // a resource matrix: product sums, resource scales and their largest
+    double *prod3 = nullptr, *scale = nullptr;
+    unsigned long long* smax = nullptr;
+    if (h->a_ptr && ((rc = malloc_d(&prod3, (size_t)3 * h->n * 8)) ||
+                     (rc = malloc_d(&scale, (size_t)h->m * 8)) || (rc = malloc_d(&smax, 8)))) {
+        void* ptrs[] = {mx, part, tail, prod3, scale};
+        for (void* q : ptrs)
+            if (q) (void)hipFree(q);
+        return rc;
+    }
     e = hipMemsetAsync(tail, 0, (size_t)3 * h->n * 8, s);
+    if (e == hipSuccess && smax) e = hipMemsetAsync(smax, 0, 8, s);
     if (e == hipSuccess) {
         hipLaunchKernelGGL(k_feat_seg<T>, dim3(grid), dim3(256), 0, s, a);
-        hipLaunchKernelGGL(k_feat_fold<T>, dim3((unsigned)((h->n + 255) / 256)), dim3(256), 0, s, a,
-                           grid, (const T*)h->r, (const T*)h->c, mx, X);
+        if (!h->a_ptr) {
+            hipLaunchKernelGGL(k_feat_fold<T>, dim3((unsigned)((h->n + 255) / 256)), dim3(256), 0, s,
+                               a, grid, (const T*)h->r, (const T*)h->c, mx, X);
+        } else {
+            const unsigned gm = (unsigned)((h->m + 255) / 256);
+            hipLaunchKernelGGL(k_feat_prod, dim3((unsigned)((h->n + 255) / 256)), dim3(256), 0, s, a,
+                               grid, prod3);
+            hipLaunchKernelGGL(k_res_scale<T>, dim3(gm), dim3(256), 0, s, h->m, h->at_ptr,
+                               h->at_prod, h->at_val, (const T*)h->r, scale, smax);
+            hipLaunchKernelGGL(k_feat_res<T>, dim3(gm), dim3(256), 0, s, h->m, h->L, h->at_ptr,
+                               h->at_prod, h->at_val, h->n, prod3, scale, smax,
+                               (const T*)h->c, X);
+        }
         e = hipGetLastError();
     }
     if (e == hipSuccess) e = hipStreamSynchronize(s);
-    (void)hipFree(mx);
-    (void)hipFree(part);
-    (void)hipFree(tail);
+    void* ptrs[] = {mx, part, tail, prod3, scale, smax};
+    for (void* q : ptrs)
+        if (q) (void)hipFree(q);
     if (e != hipSuccess) return mfail(CBLP_EHIP, std::string("features: ") + hipGetErrorString(e));
+    return CBLP_OK;
+}
+
+// the scale of every dual of h (resource matrix) into a fresh device array
+// the caller frees
+template <typename T>
+int res_scale(cblp_instance* h, double** out, hipStream_t s)
+{
+    int rc;
+    if ((rc = malloc_d(out, (size_t)h->m * 8))) return rc;
+    hipLaunchKernelGGL(k_res_scale<T>, dim3((unsigned)((h->m + 255) / 256)), dim3(256), 0, s, h->m,
+                       h->at_ptr, h->at_prod, h->at_val, (const T*)h->r, *out,
+                       (unsigned long long*)nullptr);
+    if (hipGetLastError() != hipSuccess) {
+        (void)hipFree(*out);
+        *out = nullptr;
+        return mfail(CBLP_EHIP, "resource scale kernel failed");
+    }
     return CBLP_OK;
 }
 
@@ -988,16 +1101,31 @@ int wsnet_targets(cblp_t h, const void* eta, float* Y, void* stream)
 {
     set_error(CBLP_OK, "");
     if (!h || !eta || !Y) return mfail(CBLP_EINVAL, "NULL argument");
-    if (h->a_ptr) return mfail(CBLP_EINVAL, "warm start needs the identity resource matrix");
     hipStream_t s = (hipStream_t)stream;
-    const unsigned g = (unsigned)((h->n + 255) / 256);
+    const unsigned g = (unsigned)((h->m + 255) / 256);
+    if (!h->a_ptr) {
+        if (h->dtype == CBLP_F32)
+            hipLaunchKernelGGL((k_targets<float, float>), dim3(g), dim3(256), 0, s, (const float*)eta,
+                               (const float*)h->r, h->m, Y);
+        else
+            hipLaunchKernelGGL((k_targets<double, double>), dim3(g), dim3(256), 0, s,
+                               (const double*)eta, (const double*)h->r, h->m, Y);
+        MHIP(hipGetLastError());
+        return CBLP_OK;
+    }
+    double* scale = nullptr;
+    int rc = h->dtype == CBLP_F32 ? res_scale<float>(h, &scale, s) : res_scale<double>(h, &scale, s);
+    if (rc) return rc;
     if (h->dtype == CBLP_F32)
-        hipLaunchKernelGGL(k_targets<float>, dim3(g), dim3(256), 0, s, (const float*)eta,
-                           (const float*)h->r, h->n, Y);
+        hipLaunchKernelGGL((k_targets<float, double>), dim3(g), dim3(256), 0, s, (const float*)eta,
+                           scale, h->m, Y);
     else
-        hipLaunchKernelGGL(k_targets<double>, dim3(g), dim3(256), 0, s, (const double*)eta,
-                           (const double*)h->r, h->n, Y);
-    MHIP(hipGetLastError());
+        hipLaunchKernelGGL((k_targets<double, double>), dim3(g), dim3(256), 0, s, (const double*)eta,
+                           scale, h->m, Y);
+    const hipError_t e1 = hipGetLastError();
+    const hipError_t e2 = hipStreamSynchronize(s);
+    (void)hipFree(scale);
+    if (e1 != hipSuccess || e2 != hipSuccess) return mfail(CBLP_EHIP, "targets kernel failed");
     return CBLP_OK;
 }
 
@@ -1005,23 +1133,38 @@ int wsnet_predict(wsnet_t w, cblp_t h, void* eta, void* stream)
 {
     set_error(CBLP_OK, "");
     if (!w || !h || !eta) return mfail(CBLP_EINVAL, "NULL argument");
-    if (h->a_ptr) return mfail(CBLP_EINVAL, "warm start needs the identity resource matrix");
     hipStream_t s = (hipStream_t)stream;
     int rc;
-    if ((rc = ensure_rows(w, h->n))) return rc;
+    if ((rc = ensure_rows(w, h->m))) return rc;
     rc = h->dtype == CBLP_F32 ? features_impl<float>(h, w->X, s) : features_impl<double>(h, w->X, s);
     if (rc) return rc;
-    hipLaunchKernelGGL(k_mlp_infer, dim3((unsigned)((h->n + kRows - 1) / kRows)),
-                       dim3(256), 0, s, w->X, h->n,
+    hipLaunchKernelGGL(k_mlp_infer, dim3((unsigned)((h->m + kRows - 1) / kRows)),
+                       dim3(256), 0, s, w->X, h->m,
                        w->P, w->W2t, w->y);
-    const unsigned g = (unsigned)((h->n + 255) / 256);
+    const unsigned g = (unsigned)((h->m + 255) / 256);
+    if (!h->a_ptr) {
+        if (h->dtype == CBLP_F32)
+            hipLaunchKernelGGL((k_eta_from_y<float, float>), dim3(g), dim3(256), 0, s, w->y,
+                               (const float*)h->r, h->m, (float*)eta);
+        else
+            hipLaunchKernelGGL((k_eta_from_y<double, double>), dim3(g), dim3(256), 0, s, w->y,
+                               (const double*)h->r, h->m, (double*)eta);
+        MHIP(hipGetLastError());
+        return CBLP_OK;
+    }
+    double* scale = nullptr;
+    rc = h->dtype == CBLP_F32 ? res_scale<float>(h, &scale, s) : res_scale<double>(h, &scale, s);
+    if (rc) return rc;
     if (h->dtype == CBLP_F32)
-        hipLaunchKernelGGL(k_eta_from_y<float>, dim3(g), dim3(256), 0, s, w->y, (const float*)h->r,
-                           h->n, (float*)eta);
+        hipLaunchKernelGGL((k_eta_from_y<float, double>), dim3(g), dim3(256), 0, s, w->y, scale,
+                           h->m, (float*)eta);
     else
-        hipLaunchKernelGGL(k_eta_from_y<double>, dim3(g), dim3(256), 0, s, w->y, (const double*)h->r,
-                           h->n, (double*)eta);
-    MHIP(hipGetLastError());
+        hipLaunchKernelGGL((k_eta_from_y<double, double>), dim3(g), dim3(256), 0, s, w->y, scale,
+                           h->m, (double*)eta);
+    const hipError_t e1 = hipGetLastError();
+    const hipError_t e2 = hipStreamSynchronize(s);
+    (void)hipFree(scale);
+    if (e1 != hipSuccess || e2 != hipSuccess) return mfail(CBLP_EHIP, "prediction kernels failed");
     return CBLP_OK;
 }
 

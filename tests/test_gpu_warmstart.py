@@ -4,6 +4,7 @@ training, and the gain over the cold start with its fallback."""
 import numpy as np
 import pytest
 
+import oracle
 import oracle.mlp as om
 from paper_2602_22421_amd.instances import config_instance, make_instance
 
@@ -279,6 +280,54 @@ def test_features_match_reference(cb, dtype, kind):
     # deterministic: a second call is bitwise equal
     X2 = cb.features(prob).cpu().numpy().astype(np.float64)
     assert np.array_equal(X, X2)
+    prob.close()
+
+
+def _resource_instance(weights):
+    kw = {"unit": {}, "int": {"a_lo": 1, "a_hi": 3, "a_int": True},
+          "real": {"a_lo": 0.5, "a_hi": 2.0}}[weights]
+    return make_instance(4000, 600, m=90, res_lo=1, res_hi=3, size_lo=3, size_hi=20, zipf=1.1,
+                         cap_lo=0.2, cap_hi=0.5, seed=6, **kw)
+
+
+@pytest.mark.parametrize("weights", ["unit", "int", "real"])
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_resource_features_and_targets_match_reference(cb, dtype, weights):
+    """Bundles over base products (Section 5.2): one feature row and one
+    target per resource, from the product sums weighted by a_ij."""
+    dt = torch.float32 if dtype == "f32" else torch.float64
+    npdt = np.float32 if dtype == "f32" else np.float64
+    inst = _resource_instance(weights).cast(npdt)
+    prob = cb.Problem(inst, dtype=dt)
+    X = cb.features(prob).cpu().numpy().astype(np.float64)
+    assert X.shape == (inst.m, 4)
+    np.testing.assert_allclose(X, om.features(inst), rtol=2e-6, atol=1e-7)
+    assert np.array_equal(X, cb.features(prob).cpu().numpy().astype(np.float64))
+    eta = (np.random.default_rng(3).uniform(0, 1, inst.m) * om.resource_scale(inst)).astype(npdt)
+    Y = cb.targets(prob, prob.tensor(eta)).cpu().numpy().astype(np.float64)
+    np.testing.assert_allclose(Y, om.targets(inst, eta.astype(np.float64)), rtol=1e-6, atol=1e-7)
+    prob.close()
+
+
+def test_resource_prediction_and_fallback(cb):
+    """wsnet_predict on a resource matrix gives max(y, 0) times each
+    resource's scale, y the network on the resource features; wsnet_start
+    keeps it only when its dual bound beats the cold start's."""
+    inst = _resource_instance("int")
+    prob = cb.Problem(inst, dtype=torch.float64)
+    net = cb.WarmStartNet(seed=5)
+    y = net.forward(cb.features(prob)).cpu().numpy().astype(np.float64)
+    eta = net.predict(prob).cpu().numpy()
+    np.testing.assert_allclose(eta, np.maximum(y, 0.0) * om.resource_scale(inst), rtol=2e-7)
+    e2, info = net.start(prob)
+    d0 = oracle.dual_value(inst, np.zeros(inst.m))
+    dp = oracle.dual_value(inst, eta)
+    assert info["D0"] == pytest.approx(d0, rel=1e-10)
+    assert info["D_pred"] == pytest.approx(dp, rel=1e-10)
+    assert info["used"] == (dp < d0)
+    if not info["used"]:
+        assert torch.all(e2 == 0)
+    net.close()
     prob.close()
 
 
