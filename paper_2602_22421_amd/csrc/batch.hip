@@ -113,7 +113,7 @@ __device__ __forceinline__ int current(const DevState* st) { return st[0].t >= s
 // copies' product id type).
 template <typename T, int J, int DEPTH, int MODE, typename IdxT = int32_t>
 __global__ void __launch_bounds__(kSegThreads)
-k_bsegments(const BInst* inst, const BItem* items, int nitems, unsigned* counter,
+k_bsegments(const BInst* __restrict__ inst, const BItem* __restrict__ items, int nitems, unsigned* counter,
             unsigned long long* part_S, long long* zpart, int Hmax)
 {
     extern __shared__ unsigned long long bins[];
