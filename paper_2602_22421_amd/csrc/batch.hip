@@ -8,10 +8,10 @@
 // Work list.  Each instance's size-sorted tiles (128 positions) are cut into
 // work items of about the same size; items are ordered largest instance first
 // and handed out through an atomic counter, so large and small instances share
-// the machine without a static schedule.  Every item has its own LDS-bin row
-// and its own partial of sum lambda R*, so the results do not depend on which
-// block ran which item: integer sales sums are exact and the FP64 partials
-// are folded per instance in item order.
+// the machine without a static schedule.  An item adds its LDS bins to its
+// instance's 64-bit sales sums with integer atomics and writes its own
+// fixed-point partial of sum lambda R*, so the results do not depend on which
+// block ran which item.
 //
 // Dual phase.  Fold blocks (64 products of one instance) and row blocks (256
 // rows of one instance) come from flattened tables; every row block of an
@@ -59,7 +59,6 @@ struct BInst {
     DevState* st;              // [2]
     double* row;               // [SPFOM_NTRACE]
     int item0, item1;          // work items of this instance
-    int64_t part_off;          // first entry of its LDS-bin rows in part_S
     int fold0, fold1;          // its fold blocks
     int H;                     // LDS bins (library products [0, H))
     int active;
@@ -82,7 +81,6 @@ struct BArgs {
     const BInst* inst;
     const BChunk* fold;
     const BChunk* rows;
-    const unsigned long long* part_S;
     const long long* zpart;    // fixed-point Z partials per item
     double* bpart;             // [fold blocks][8]
     int rule, check_every;
@@ -114,7 +112,7 @@ __device__ __forceinline__ int current(const DevState* st) { return st[0].t >= s
 template <typename T, int J, int DEPTH, int MODE, typename IdxT = int32_t>
 __global__ void __launch_bounds__(kSegThreads)
 k_bsegments(const BInst* __restrict__ inst, const BItem* __restrict__ items, int nitems, unsigned* counter,
-            unsigned long long* part_S, long long* zpart, int Hmax)
+            long long* zpart, int Hmax)
 {
     extern __shared__ unsigned long long bins[];
     __shared__ long long zsh[kSegThreads / 64];
@@ -164,8 +162,10 @@ k_bsegments(const BInst* __restrict__ inst, const BItem* __restrict__ items, int
             seg::process_tiles<T, J, DEPTH>(a, t0, t1, 1, bins, pr, zacc);
         }
         __syncthreads();
-        unsigned long long* out = part_S + I->part_off + (size_t)(it - I->item0) * (size_t)H;
-        for (int j = threadIdx.x; j < H; j += kSegThreads) out[j] = bins[j];
+        // the item's bins into the instance's 64-bit sales sums: integer adds,
+        // so the sums do not depend on which block ran which item
+        for (int j = threadIdx.x; j < H; j += kSegThreads)
+            if (bins[j]) atomicAdd(&I->S_fx[j], bins[j]);
         const long long z = block_z(zacc, zsh);
         if (threadIdx.x == 0) zpart[it] = z;
     }
@@ -175,7 +175,6 @@ template <typename T>
 __global__ void __launch_bounds__(kFoldThreads) k_bfold(BArgs b)
 {
     using namespace dual;
-    __shared__ unsigned long long red[kFoldChunks][kFoldProducts];
     __shared__ double sh[NR * 16];
     // the segment pass of this iteration has ended: its work counter starts
     // the next one from zero
@@ -187,34 +186,12 @@ __global__ void __launch_bounds__(kFoldThreads) k_bfold(BArgs b)
     const int jj = tid % kFoldProducts, cc = tid / kFoldProducts;
     const int64_t j = f.j0 + jj;
     const int64_t jq = j < I->n && I->pnew ? I->pnew[j] : j;   // library id of product j
-    const int H = I->H;
-    const int nit = I->item1 - I->item0;
-    unsigned long long a0 = 0ull, a1 = 0ull, a2 = 0ull, a3 = 0ull;
-    unsigned long long a4 = 0ull, a5 = 0ull, a6 = 0ull, a7 = 0ull;
-    if (j < I->n && jq < H) {
-        const unsigned long long* P = b.part_S + I->part_off + jq;
-        int q = cc;
-        for (; q + 7 * kFoldChunks < nit; q += 8 * kFoldChunks) {
-            a0 += P[(size_t)q * H];
-            a1 += P[(size_t)(q + kFoldChunks) * H];
-            a2 += P[(size_t)(q + 2 * kFoldChunks) * H];
-            a3 += P[(size_t)(q + 3 * kFoldChunks) * H];
-            a4 += P[(size_t)(q + 4 * kFoldChunks) * H];
-            a5 += P[(size_t)(q + 5 * kFoldChunks) * H];
-            a6 += P[(size_t)(q + 6 * kFoldChunks) * H];
-            a7 += P[(size_t)(q + 7 * kFoldChunks) * H];
-        }
-        for (; q < nit; q += kFoldChunks) a0 += P[(size_t)q * H];
-    }
-    red[cc][jj] = ((a0 + a1) + (a2 + a3)) + ((a4 + a5) + (a6 + a7));
     const long long cnt1 = I->st[current(I->st)].cnt + 1;
-    __syncthreads();
     double x[NR];
     clear(x);
     if (cc == 0 && j < I->n) {
-        unsigned long long tot = I->S_fx[jq];
+        const unsigned long long tot = I->S_fx[jq];
         I->S_fx[jq] = 0ull;
-        for (int q = 0; q < kFoldChunks; ++q) tot += red[q][jj];
         const double sj = (double)(long long)tot * I->inv_fx;
         I->S_d[j] = sj;
         x[R_P] = (double)((const T*)I->r)[j] * sj;
@@ -383,13 +360,12 @@ struct cblp_batch {
     BItem* d_items = nullptr;
     int nitems = 0;
     int ipb = 4;                     // work items per segment block (the tuner may change it)
-    size_t items_cap = 0, part_cap = 0, zpart_cap = 0;   // allocated entries
+    size_t items_cap = 0, zpart_cap = 0;   // allocated entries
     std::vector<int> order;          // instances, largest first
     BChunk* d_fold = nullptr;
     int nfold = 0;
     BChunk* d_rows = nullptr;
     int nrows = 0;
-    unsigned long long* part_S = nullptr;
     long long* zpart = nullptr;
     double* bpart = nullptr;
     DevState* st = nullptr;
@@ -422,7 +398,7 @@ bool bseg_usable(const cblp_batch* b, int variant);
 void batch_release(cblp_batch* b)
 {
     if (!b) return;
-    void* ptrs[] = {b->d_inst, b->d_items, b->d_fold, b->d_rows, b->part_S, b->zpart,
+    void* ptrs[] = {b->d_inst, b->d_items, b->d_fold, b->d_rows, b->zpart,
                     b->bpart, b->st, b->rows, b->counter};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
@@ -505,7 +481,6 @@ int enqueue_iterations(cblp_batch* b, const spfom_params* p, int64_t iters, hipS
     a.inst = b->d_inst;
     a.fold = b->d_fold;
     a.rows = b->d_rows;
-    a.part_S = b->part_S;
     a.zpart = b->zpart;
     a.bpart = b->bpart;
     a.rule = p->rule;
@@ -519,7 +494,7 @@ int enqueue_iterations(cblp_batch* b, const spfom_params* p, int64_t iters, hipS
     const void* segf = bseg_fn<T>(b->variant);
     for (int64_t it = 0; it < iters; ++it) {
         void* sargs[] = {(void*)&b->d_inst, (void*)&b->d_items, (void*)&b->nitems,
-                         (void*)&b->counter, (void*)&b->part_S, (void*)&b->zpart,
+                         (void*)&b->counter, (void*)&b->zpart,
                          (void*)&b->Hmax};
         BHIP(hipLaunchKernel(segf, dim3(b->grid), dim3(kSegThreads), sargs, lds, s));
         hipLaunchKernelGGL(k_bfold<T>, dim3(b->nfold), dim3(kFoldThreads), 0, s, a);
@@ -597,7 +572,6 @@ int build_items(cblp_batch* b, int ipb, hipStream_t s)
     const int64_t per_item = std::max<int64_t>(1, total_tiles / ((int64_t)b->grid * ipb));
     const int64_t per_rows = (per_item * kSegsPerTile + kPartAlign - 1) / kPartAlign * kPartAlign;
     std::vector<BItem> items;
-    int64_t part = 0;
     for (int q : b->order) {
         const cblp_instance* h = b->hs[q];
         BInst& I = b->h_inst[q];
@@ -607,8 +581,6 @@ int build_items(cblp_batch* b, int ipb, hipStream_t s)
             for (int64_t p0 = pb[k]; p0 < pb[k + 1]; p0 += per_rows)
                 items.push_back(BItem{q, k, p0, std::min(pb[k + 1], p0 + per_rows)});
         I.item1 = (int)items.size();
-        I.part_off = part;
-        part += (int64_t)(I.item1 - I.item0) * h->H;
     }
     auto grow = [&](void** ptr, size_t& cap, size_t need, size_t esz) -> int {
         need = std::max<size_t>(need, 1);
@@ -622,7 +594,6 @@ int build_items(cblp_batch* b, int ipb, hipStream_t s)
     };
     int rc;
     if ((rc = grow((void**)&b->d_items, b->items_cap, items.size(), sizeof(BItem))) ||
-        (rc = grow((void**)&b->part_S, b->part_cap, (size_t)part, 8)) ||
         (rc = grow((void**)&b->zpart, b->zpart_cap, items.size(), 8)))
         return rc;
     b->nitems = (int)items.size();
