@@ -172,7 +172,10 @@ k_bsegments(const BInst* __restrict__ inst, const BItem* __restrict__ items, int
 }
 
 template <typename T>
-__global__ void __launch_bounds__(kFoldThreads) k_bfold(BArgs b)
+// One wave per fold block: thread jj owns product j0 + jj (the single
+// instance's fold takes the same per-product values through the same wave
+// reduction, its other waves adding zeros).
+__global__ void __launch_bounds__(kFoldProducts) k_bfold(BArgs b)
 {
     using namespace dual;
     __shared__ double sh[NR * 16];
@@ -183,13 +186,13 @@ __global__ void __launch_bounds__(kFoldThreads) k_bfold(BArgs b)
     const BInst* I = b.inst + f.inst;
     if (!I->active) return;
     const int tid = threadIdx.x;
-    const int jj = tid % kFoldProducts, cc = tid / kFoldProducts;
+    const int jj = tid;
     const int64_t j = f.j0 + jj;
     const int64_t jq = j < I->n && I->pnew ? I->pnew[j] : j;   // library id of product j
     const long long cnt1 = I->st[current(I->st)].cnt + 1;
     double x[NR];
     clear(x);
-    if (cc == 0 && j < I->n) {
+    if (j < I->n) {
         const unsigned long long tot = I->S_fx[jq];
         I->S_fx[jq] = 0ull;
         const double sj = (double)(long long)tot * I->inv_fx;
@@ -497,7 +500,7 @@ int enqueue_iterations(cblp_batch* b, const spfom_params* p, int64_t iters, hipS
                          (void*)&b->counter, (void*)&b->zpart,
                          (void*)&b->Hmax};
         BHIP(hipLaunchKernel(segf, dim3(b->grid), dim3(kSegThreads), sargs, lds, s));
-        hipLaunchKernelGGL(k_bfold<T>, dim3(b->nfold), dim3(kFoldThreads), 0, s, a);
+        hipLaunchKernelGGL(k_bfold<T>, dim3(b->nfold), dim3(kFoldProducts), 0, s, a);
         hipLaunchKernelGGL(k_bupdate<T>, dim3(b->nrows), dim3(kRowThreads), 0, s, a);
         BHIP(hipGetLastError());
     }

@@ -22,8 +22,6 @@ constexpr int kSegsPerTile = kSegThreads / kGroup;
 // Dual-phase kernels.
 constexpr int kFoldLite = 256;             // products per fold block
 constexpr int kFoldProducts = 64;          // products per batched fold block
-constexpr int kFoldChunks = 16;            // batched fold: partial rows split 16 ways
-constexpr int kFoldThreads = kFoldProducts * kFoldChunks;
 constexpr int kRowThreads = 256;
 
 // Z = sum_l lambda_l R*_l is summed in 64-bit fixed point, so that its sum,
