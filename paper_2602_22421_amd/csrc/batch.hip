@@ -68,7 +68,7 @@ struct BInst {
 struct BItem {
     int inst;
     int part;                  // 0 pair, 1 quad, 2 8-lane part of the slot-major copy
-    int64_t p0, p1;            // positions [p0, p1) (p0 a multiple of kPartAlign)
+    int64_t p0, p1;            // positions [p0, p1) (p0 on a block tile of the part's layout)
 };
 
 struct BChunk {
@@ -564,25 +564,29 @@ bool bseg_usable(const cblp_batch* b, int variant)
 
 // The work list: each instance's parts cut into items of about equal tile
 // count, ipb items per segment block on average, largest instance first;
-// item lengths are multiples of kPartAlign positions, so that items start on
-// a tile of every layout.  Sizes the per-item LDS-bin rows and Z partials,
-// uploads the list and the instance table, and drops a captured graph (its
-// launches hold the item count).
+// an item's length is a multiple of its part's block tile (512 positions in
+// the pair layout, 256 in the quad layout, 128 in the 8-lane and row-major
+// ones; parts start on multiples of 512), so that every item starts on a
+// tile of its layout.  Sizes the Z partials, uploads the list and the
+// instance table, and drops a captured graph (its launches hold the item
+// count).
 int build_items(cblp_batch* b, int ipb, hipStream_t s)
 {
     int64_t total_tiles = 0;
     for (int q = 0; q < b->count; ++q) total_tiles += (b->hs[q]->L + kSegsPerTile - 1) / kSegsPerTile;
     const int64_t per_item = std::max<int64_t>(1, total_tiles / ((int64_t)b->grid * ipb));
-    const int64_t per_rows = (per_item * kSegsPerTile + kPartAlign - 1) / kPartAlign * kPartAlign;
+    const int64_t align[3] = {seg::kPairTileRows, seg::kQuadTileRows, kSegsPerTile};
     std::vector<BItem> items;
     for (int q : b->order) {
         const cblp_instance* h = b->hs[q];
         BInst& I = b->h_inst[q];
         const int64_t pb[4] = {0, h->pair_end, h->quad_end, h->L};
         I.item0 = (int)items.size();
-        for (int k = 0; k < 3; ++k)
+        for (int k = 0; k < 3; ++k) {
+            const int64_t per_rows = (per_item * kSegsPerTile + align[k] - 1) / align[k] * align[k];
             for (int64_t p0 = pb[k]; p0 < pb[k + 1]; p0 += per_rows)
                 items.push_back(BItem{q, k, p0, std::min(pb[k + 1], p0 + per_rows)});
+        }
         I.item1 = (int)items.size();
     }
     auto grow = [&](void** ptr, size_t& cap, size_t need, size_t esz) -> int {
