@@ -254,7 +254,9 @@ int cblp_recover(cblp_t h, const double* y, int32_t* rank, double* alpha, double
 /*
  * cblp_launch_info - the launch shape chosen at cblp_create: number of
  * segment-kernel blocks, number of LDS sales bins per block (products
- * [0, bins) are accumulated in LDS), the fixed-point fraction bits of the
+ * [0, bins) are accumulated in LDS, the others by global atomics), how many
+ * of them are 64-bit (products [0, bins64); the rest are 32-bit bins whose
+ * wraps are carried to the global sums), the fixed-point fraction bits of the
  * sales accumulators, the segment kernel (0: FP32 three-part kernel with all
  * prices in LDS; 1, 2: the same with the popular head of the prices in LDS,
  * 16- or 32-bit product ids; 3, 4: FP64 8-lane kernel, 16- or 32-bit ids)
@@ -262,8 +264,8 @@ int cblp_recover(cblp_t h, const double* y, int32_t* rank, double* alpha, double
  * padded to its wave-tile's longest, in units of entries).  Each [host]
  * pointer is nullable.
  */
-int cblp_launch_info(cblp_t h, int32_t* seg_grid, int32_t* bins, int32_t* fx_bits,
-                     int32_t* kernel, int64_t* slot_entries);
+int cblp_launch_info(cblp_t h, int32_t* seg_grid, int32_t* bins, int32_t* bins64,
+                     int32_t* fx_bits, int32_t* kernel, int64_t* slot_entries);
 
 /*
  * cblp_timing - enable (1) or disable (0) per-launch timing: while enabled,

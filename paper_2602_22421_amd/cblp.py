@@ -100,7 +100,7 @@ def load(path: str = _LIB_PATH) -> ctypes.CDLL:
     lib.cblp_launch_info.restype = ctypes.c_int
     lib.cblp_launch_info.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32),
                                      ctypes.POINTER(i32), ctypes.POINTER(i32),
-                                     ctypes.POINTER(ctypes.c_int64)]
+                                     ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_int64)]
     lib.cblp_timing.restype = ctypes.c_int
     lib.cblp_timing.argtypes = [vp, i32]
     lib.cblp_timing_read.restype = ctypes.c_int
@@ -285,12 +285,14 @@ def cblp_recover(h, y, rank, alpha, alpha0, stream=None) -> None:
 
 
 def cblp_launch_info(h) -> dict:
-    g, b, f, k = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    g, b, b64 = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    f, k = ctypes.c_int32(), ctypes.c_int32()
     e = ctypes.c_int64()
     _check(load().cblp_launch_info(ctypes.c_void_p(h), ctypes.byref(g), ctypes.byref(b),
-                                   ctypes.byref(f), ctypes.byref(k), ctypes.byref(e)))
-    return {"seg_grid": g.value, "lds_bins": b.value, "fx_bits": f.value,
-            "kernel": SEG_KERNELS[k.value], "slot_entries": e.value}
+                                   ctypes.byref(b64), ctypes.byref(f), ctypes.byref(k),
+                                   ctypes.byref(e)))
+    return {"seg_grid": g.value, "lds_bins": b.value, "lds_bins64": b64.value,
+            "fx_bits": f.value, "kernel": SEG_KERNELS[k.value], "slot_entries": e.value}
 
 
 def cblp_timing(h, enable: bool) -> None:

@@ -63,6 +63,7 @@ struct BInst {
     int H;                     // LDS bins (library products [0, H))
     int active;
     const int32_t* pnew;       // [n] library id of caller product j; NULL: j
+    const int32_t* pinv;       // [n] caller product of library id q; NULL: q
 };
 
 struct BItem {
@@ -172,9 +173,9 @@ k_bsegments(const BInst* __restrict__ inst, const BItem* __restrict__ items, int
 }
 
 template <typename T>
-// One wave per fold block: thread jj owns product j0 + jj (the single
-// instance's fold takes the same per-product values through the same wave
-// reduction, its other waves adding zeros).
+// One wave per fold block: thread jj owns library product j0 + jj (caller
+// product pinv[j0 + jj]); the single instance's fold takes the same
+// per-product values through the same wave reduction.
 __global__ void __launch_bounds__(kFoldProducts) k_bfold(BArgs b)
 {
     using namespace dual;
@@ -187,14 +188,14 @@ __global__ void __launch_bounds__(kFoldProducts) k_bfold(BArgs b)
     if (!I->active) return;
     const int tid = threadIdx.x;
     const int jj = tid;
-    const int64_t j = f.j0 + jj;
-    const int64_t jq = j < I->n && I->pnew ? I->pnew[j] : j;   // library id of product j
+    const int64_t q = f.j0 + jj;   // library id
     const long long cnt1 = I->st[current(I->st)].cnt + 1;
     double x[NR];
     clear(x);
-    if (j < I->n) {
-        const unsigned long long tot = I->S_fx[jq];
-        I->S_fx[jq] = 0ull;
+    if (q < I->n) {
+        const int64_t j = I->pinv ? I->pinv[q] : q;   // caller product
+        const unsigned long long tot = I->S_fx[q];
+        I->S_fx[q] = 0ull;
         const double sj = (double)(long long)tot * I->inv_fx;
         I->S_d[j] = sj;
         x[R_P] = (double)((const T*)I->r)[j] * sj;
@@ -676,7 +677,7 @@ int cblp_batch_create(cblp_batch_t* out, int32_t count, const cblp_t* handles, v
         if (!h) return bail(bfail(CBLP_EINVAL, "NULL handle " + std::to_string(q)));
         if (h->dtype != b->dtype) return bail(bfail(CBLP_EINVAL, "all instances need the same dtype"));
         if (h->a_ptr) return bail(bfail(CBLP_EINVAL, "batched solves need the identity resource matrix"));
-        Hmax = std::max<int64_t>(Hmax, h->H);
+        Hmax = std::max<int64_t>(Hmax, h->Hb);
     }
     b->Hmax = (int)Hmax;
     b->parts16_ok = true;
@@ -737,7 +738,8 @@ int cblp_batch_create(cblp_batch_t* out, int32_t count, const cblp_t* handles, v
         a.perm = h->perm;
         a.rho = h->rho;
         a.n = h->n;
-        a.H = h->H;
+        a.H = h->Hb;
+        a.H64 = h->Hb;
         a.hp = 0;
         a.woff = h->woff;
         a.idx3 = h->idx3;
@@ -760,9 +762,10 @@ int cblp_batch_create(cblp_batch_t* out, int32_t count, const cblp_t* handles, v
         I.S_d = h->S_d;
         I.u_d = h->u_d;
         I.sum_u = h->sum_u;
-        I.H = h->H;
+        I.H = h->Hb;
         I.active = 1;
         I.pnew = h->pnew;
+        I.pinv = h->pinv;
         // the parts of the slot-major copy: pair [0, P2), quad [P2, P4), 8-lane [P4, L)
         const int64_t P2 = h->pair_end, P4 = h->quad_end;
         const int64_t pb[4] = {0, P2, P4, h->L};

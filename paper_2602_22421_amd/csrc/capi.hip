@@ -79,9 +79,9 @@ void release(cblp_instance* h)
 {
     if (!h) return;
     void* ptrs[] = {h->ptr2, h->idx2, h->v2, h->den2, h->vt0, h->lam2, h->Rwarm, h->v0c, h->perm,
-                    h->pnew,
+                    h->pnew, h->pinv,
                     h->woff, h->idx3, h->v3, h->den3,
-                    h->rho, h->S_fx, h->S_d, h->u_d, h->sum_u, h->zpart,
+                    h->rho, h->S_fx, h->S_d, h->u_d, h->sum_u, h->zpart, h->brow,
                     h->bpart, h->bpart2, h->st, h->arrive, h->trace, h->at_ptr,
                     h->at_prod, h->at_val, h->rlib, h->psum, h->theta_prod, h->pseg_part,
                     h->eval_thr, h->eval_lamD, h->mb_yq, h->mb_S, h->mb_inv, h->mb_stamp,
@@ -191,9 +191,53 @@ int ensure_pseg(cblp_instance* h, hipStream_t s)
 
 // pseg: add each segment's revenue to h->psum (per-segment bound);
 // eval_out: store each position's threshold and (lambda / D) 2^bits
+// The LDS bins of the segment kernel (FP32 handles with more products than
+// 64-bit bins): the products whose sales within every segment block are
+// bounded below 2^32 quanta may take 32-bit bins, so the block holds 64-bit
+// bins for products [0, need) (the most popular ids), 32-bit ones after them
+// up to what its LDS holds; the 64-bit layout stays when that covers more
+// products.  Run once the values are known, again after a refresh.
+template <typename T>
+int choose_bins(cblp_instance* h, hipStream_t s)
+{
+    h->bins_stale = false;
+    h->H = h->Hb;
+    h->H64 = h->Hb;
+    if (sizeof(T) != 4 || h->n <= h->Hb || h->L == 0) return CBLP_OK;
+    const int64_t Hc = std::min<int64_t>(h->n, h->bin_bytes / 4);
+    const int G = h->seg_grid;
+    unsigned long long* Ub = nullptr;
+    int* dneed = nullptr;
+    int rc;
+    if ((rc = dalloc(&Ub, (size_t)Hc * G * 8))) return rc;
+    if ((rc = dalloc(&dneed, sizeof(int)))) {
+        (void)hipFree(Ub);
+        return rc;
+    }
+    int need = 0;
+    hipError_t e = hipMemsetAsync(Ub, 0, (size_t)Hc * G * 8, s);
+    if (e == hipSuccess) e = hipMemsetAsync(dneed, 0, sizeof(int), s);
+    if (e == hipSuccess)
+        e = launch_bin_bound(h->L, h->pair_end, h->quad_end, G, h->ptr2, h->idx2, h->v2, h->den2,
+                             h->vt0, h->lam2, h->fx_scale, (int)Hc, Ub, dneed, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(&need, dneed, sizeof(int), hipMemcpyDeviceToHost, s);
+    const hipError_t e2 = hipStreamSynchronize(s);
+    (void)hipFree(Ub);
+    (void)hipFree(dneed);
+    if (e != hipSuccess || e2 != hipSuccess) return fail(CBLP_EHIP, "bin bound kernels failed");
+    const int64_t H = std::min<int64_t>(h->n, (h->bin_bytes - 4 * (int64_t)need) / 4);
+    if (H > h->Hb && H >= need) {
+        h->H = (int)H;
+        h->H64 = need;
+    }
+    return CBLP_OK;
+}
+
 template <typename T>
 int run_segments(cblp_instance* h, void* seg_R, bool pseg, bool eval_out, hipStream_t s)
 {
+    int rc0;
+    if (h->bins_stale && (rc0 = choose_bins<T>(h, s))) return rc0;
     SegArgs a;
     a.L = h->L;
     a.ptr = h->ptr2;
@@ -207,8 +251,11 @@ int run_segments(cblp_instance* h, void* seg_R, bool pseg, bool eval_out, hipStr
     a.rho = h->rho;
     a.n = h->n;
     a.H = h->H;
+    a.H64 = h->H64;
     a.hp = h->hp;
     a.S_fx = h->S_fx;
+    a.brow = h->brow;
+    a.row_words = h->row_words;
     a.fx_scale = h->fx_scale;
     a.zpart = h->zpart;
     a.z_scale = h->z_scale;
@@ -250,6 +297,7 @@ int run_segments(cblp_instance* h, void* seg_R, bool pseg, bool eval_out, hipStr
     const SegArgs a2 = view(0, P2, 0), a4 = view(P2, P4, h->woff_q),
                   a8 = view(P4, h->L, h->woff_b);
     HIP_TRY(launch_segments<T>(a2, a4, a8, h->seg_grid, h->seg_variant, pseg, s));
+    h->fold_pending = true;
     return timed_end(h, slot, s);
 }
 
@@ -291,6 +339,13 @@ int run_phase(cblp_instance* h, void* eta, const spfom_params* p, int mode, doub
     a.bpart2 = h->bpart2;
     a.fold_blocks = h->fold_blocks;
     a.pnew = h->pnew;
+    a.pinv = h->pinv;
+    a.brow = h->brow;
+    a.row_words = h->row_words;
+    a.nrows = h->fold_pending ? h->seg_grid : 0;   // the segment pass's rows, added once
+    a.rows_H = h->H;
+    a.rows_H64 = h->H64;
+    h->fold_pending = false;
     a.arrive = h->arrive;
     a.st = h->st;
     a.par = (int)(h->t & 1);
@@ -381,7 +436,7 @@ int minibatch_impl(cblp_instance* h, void* eta, const spfom_params* p, const int
     a.Rwarm = h->Rwarm;
     a.rho = h->rho;
     a.fx_scale = h->fx_scale;
-    a.H = std::min(h->H, 8192);
+    a.H = std::min(h->Hb, 8192);
     a.S_run = h->mb_S;
     a.yq = h->mb_yq;
     a.wide = sizeof(T) == 8;
@@ -563,9 +618,14 @@ int create_impl(cblp_instance* h, hipStream_t s)
     h->hp = seg_split(h->seg_variant) ? (int)std::min<int64_t>(h->n, kSplitPrices) : 0;
     const int64_t price_bytes = seg_split(h->seg_variant) ? (int64_t)h->hp * (int64_t)sizeof(T)
                                 : seg_lds_prices(h->seg_variant) ? h->n * (int64_t)sizeof(T) : 0;
-    const int64_t lds_bins = ((int64_t)lds_block - 1024 - price_bytes) / 8;
-    h->H = (int)std::max<int64_t>(1, std::min<int64_t>({h->n, (int64_t)kMaxBins, lds_bins}));
-    const int per_cu = segment_blocks_per_cu<T>(h->H, h->n, h->hp, h->seg_variant);
+    h->bin_bytes = ((int64_t)lds_block - 1024 - price_bytes) & ~(int64_t)7;
+    // 64-bit bins for the most popular products; the FP32 segment kernel may
+    // trade them for more 32-bit ones once the values are known (choose_bins)
+    h->Hb = (int)std::max<int64_t>(1, std::min<int64_t>({h->n, (int64_t)kMaxBins, h->bin_bytes / 8}));
+    h->H = h->Hb;
+    h->H64 = h->Hb;
+    h->bins_stale = true;
+    const int per_cu = segment_blocks_per_cu<T>(h->H, h->H64, h->n, h->hp, h->seg_variant);
     const int64_t tiles = (h->L + kSegsPerTile - 1) / kSegsPerTile;
     h->seg_grid = (int)std::max<int64_t>(1, std::min<int64_t>(tiles, (int64_t)cus * per_cu));
     h->fold_blocks = (int)((h->n + kFoldLite - 1) / kFoldLite);
@@ -578,7 +638,8 @@ int create_impl(cblp_instance* h, hipStream_t s)
     if ((rc = dalloc(&h->S_d, (size_t)h->n * 8))) return rc;
     if ((rc = dalloc(&h->u_d, (size_t)h->m * 8))) return rc;
     if ((rc = dalloc(&h->sum_u, (size_t)h->m * 8))) return rc;
-    if ((rc = dalloc(&h->bpart, (size_t)h->fold_blocks * 8 * 8))) return rc;
+    // fold partials: one per 256 products, or per 64 in the fused step
+    if ((rc = dalloc(&h->bpart, (size_t)((h->n + 63) / 64 + 1) * 8 * 8))) return rc;
     if ((rc = dalloc(&h->bpart2, (size_t)std::max<int64_t>(row_blocks, 1) * 8 * 8))) return rc;
     if ((rc = dalloc(&h->st, 2 * sizeof(DevState)))) return rc;
     if ((rc = dalloc(&h->arrive, sizeof(unsigned)))) return rc;
@@ -610,7 +671,10 @@ int create_impl(cblp_instance* h, hipStream_t s)
                                  [&](int32_t x, int32_t y) { return deg[x] > deg[y]; });
                 for (int64_t q = 0; q < h->n; ++q) pnew[order[q]] = (int32_t)q;
                 if ((rc = dalloc(&h->pnew, (size_t)h->n * 4))) return rc;
+                if ((rc = dalloc(&h->pinv, (size_t)h->n * 4))) return rc;
                 HIP_TRY(hipMemcpyAsync(h->pnew, pnew.data(), (size_t)h->n * 4,
+                                       hipMemcpyHostToDevice, s));
+                HIP_TRY(hipMemcpyAsync(h->pinv, order.data(), (size_t)h->n * 4,
                                        hipMemcpyHostToDevice, s));
                 HIP_TRY(hipStreamSynchronize(s));
             }
@@ -709,6 +773,9 @@ int create_impl(cblp_instance* h, hipStream_t s)
         HIP_TRY(hipStreamSynchronize(s));   // the host vectors die here
     }
     if ((rc = dalloc(&h->zpart, (size_t)h->seg_grid * 8))) return rc;
+    // one row of bins per segment block, as long as the largest layout
+    h->row_words = (h->bin_bytes + 255) / 256 * 32;
+    if ((rc = dalloc(&h->brow, (size_t)h->seg_grid * (size_t)h->row_words * 8))) return rc;
 
     // fixed-point scale of the sales sums from the arrival rates
     const int pblocks = 256;
@@ -775,6 +842,7 @@ int cblp::refresh_launch(cblp_instance* h, unsigned* flags, hipStream_t s)
     HIP_TRY(h->dtype == CBLP_F32 ? launch_refresh<float>(h, flags, s)
                                  : launch_refresh<double>(h, flags, s));
     h->mb_clear = true;
+    h->bins_stale = true;   // the bin bounds follow the values
     return CBLP_OK;
 }
 
@@ -997,13 +1065,14 @@ int cblp_sales(cblp_t h, const void* eta, double* S_out, double* u_out, void* se
     return CBLP_OK;
 }
 
-int cblp_launch_info(cblp_t h, int32_t* seg_grid, int32_t* bins, int32_t* fx_bits,
-                     int32_t* kernel, int64_t* slot_entries)
+int cblp_launch_info(cblp_t h, int32_t* seg_grid, int32_t* bins, int32_t* bins64,
+                     int32_t* fx_bits, int32_t* kernel, int64_t* slot_entries)
 {
     g_err.clear();
     if (!h) return fail(CBLP_EINVAL, "handle is NULL");
     if (seg_grid) *seg_grid = h->seg_grid;
     if (bins) *bins = h->H;
+    if (bins64) *bins64 = h->H64;
     if (fx_bits) {
         int e = 0;
         std::frexp(h->fx_scale, &e);

@@ -21,6 +21,7 @@ constexpr int kSegsPerTile = kSegThreads / kGroup;
 
 // Dual-phase kernels.
 constexpr int kFoldLite = 256;             // products per fold block
+constexpr int kStepWaves = 8;              // waves of a fused fold-and-step block (64 products)
 constexpr int kFoldProducts = 64;          // products per batched fold block
 constexpr int kRowThreads = 256;
 
@@ -101,9 +102,13 @@ struct SegArgs {
     const int32_t* perm;           // [L] position -> original segment
     const void* rho;               // [n] reduced revenues
     int64_t n;                     // products (length of rho)
-    int H;                         // products [0, H) are summed in LDS bins
+    int H;                         // products [0, H) are summed in LDS bins:
+    int H64;                       // [0, H64) in 64-bit ones, [H64, H) in 32-bit
+                                   // ones after them (FP32 quanta only)
     int hp;                        // split-price kernel: prices [0, hp) held in LDS
     unsigned long long* S_fx;      // [n] fixed-point sales of products >= H
+    unsigned long long* brow;      // nullable: each block's bins as one row of
+    int64_t row_words;             // row_words 64-bit words (else atomics into S_fx)
     double fx_scale;               // 2^bits; one segment's sale * 2^bits < 2^31 for FP32
     long long* zpart;              // [gridDim.x] fixed-point partials of sum lambda R* (or kZPoison)
     double z_scale;                // their scale
@@ -158,6 +163,13 @@ struct PhaseArgs {
     double* bpart2;                // [row blocks][8]
     int fold_blocks;
     const int32_t* pnew;           // [n] library product id of caller product j; NULL: j
+    const int32_t* pinv;           // [n] caller product of library id q; NULL: q
+    // the segment blocks' rows of sales bins still to add (nrows 0: none):
+    // row r at brow + r * row_words, 64-bit bins of library ids [0, rows_H64),
+    // then 32-bit ones of [rows_H64, rows_H)
+    const unsigned long long* brow;
+    int64_t row_words;
+    int nrows, rows_H, rows_H64;
     unsigned* arrive;              // blocks of the fused fold-and-step kernel done (0 between launches)
     DevState* st;                  // [2]: read st[par], write st[par ^ 1]
     int par;
@@ -260,12 +272,18 @@ inline bool seg_split(int variant)
 }
 inline bool seg_idx16(int variant) { return variant != kSegMixed3Split32 && variant != kSegSlots32; }
 inline bool seg_lds_prices(int variant) { return seg_mixed3(variant); }
-// dynamic LDS bytes of a segment block: H bins, then the prices held in LDS
-// (n of them, or hp for the split kernels)
-inline size_t seg_lds_bytes(int H, int64_t n, int hp, size_t esz, int variant)
+// bytes of a block's LDS bins: H64 64-bit ones, then H - H64 32-bit ones,
+// rounded up to 8
+__host__ __device__ inline size_t seg_bin_bytes(int H, int H64)
+{
+    return ((size_t)H64 * 8 + (size_t)(H - H64) * 4 + 7) & ~(size_t)7;
+}
+// dynamic LDS bytes of a segment block: the bins, then the prices held in
+// LDS (n of them, or hp for the split kernels)
+inline size_t seg_lds_bytes(int H, int H64, int64_t n, int hp, size_t esz, int variant)
 {
     const size_t np = seg_split(variant) ? (size_t)hp : seg_lds_prices(variant) ? (size_t)n : 0;
-    return (size_t)H * 8 + np * esz;
+    return seg_bin_bytes(H, H64) + np * esz;
 }
 // a2, a4, a8: views of the pair, quad and 8-lane parts of the slot-major
 // copy (the FP64 kernels take a8 only, viewing the whole instance)
@@ -281,7 +299,51 @@ hipError_t launch_entry_sales(int64_t L, const int32_t* perm, const int64_t* seg
                               const int32_t* pnew, const void* rho, const void* thr,
                               const void* lamD, double inv_fx, double* s_out, hipStream_t s);
 template <typename T>
-int segment_blocks_per_cu(int H, int64_t n, int hp, int variant);   // resident blocks per CU
+int segment_blocks_per_cu(int H, int H64, int64_t n, int hp, int variant);   // resident blocks per CU
+// FP32 copies: need = 1 + the largest product id < Hc whose sales within one
+// of the G segment blocks may reach 2^32 quanta (0 if none); Ub is zeroed
+// [Hc x G] scratch, need a zeroed int
+hipError_t launch_bin_bound(int64_t L, int64_t P2, int64_t P4, int G, const int64_t* ptr2,
+                            const int32_t* idx2, const void* v2, const void* den2,
+                            const void* vt0, const void* lam, double fx_scale, int Hc,
+                            unsigned long long* Ub, int* need, hipStream_t s);
+// The sum, as a 64-bit integer, of bin q in rows first, first + stride, ...
+// below nrows of a segment pass's block rows (0 for q >= H): the loads of up
+// to 16 rows are in flight together.
+__device__ __forceinline__ unsigned long long row_bins_sum(const unsigned long long* __restrict__ rows,
+                                                           int64_t row_words, int nrows, int H,
+                                                           int H64, int64_t q, int first, int stride)
+{
+    constexpr int kU = 16;
+    unsigned long long acc = 0ull;
+    if (q >= H) return acc;
+    if (q < H64) {
+        const unsigned long long* p = rows + q;
+        for (int r0 = first; r0 < nrows; r0 += stride * kU) {
+            unsigned long long x[kU];
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                const int r = r0 + u * stride;
+                x[u] = r < nrows ? p[(int64_t)r * row_words] : 0ull;
+            }
+#pragma unroll
+            for (int u = 0; u < kU; ++u) acc += x[u];
+        }
+    } else {
+        const unsigned* p = (const unsigned*)(rows + H64) + (q - H64);
+        for (int r0 = first; r0 < nrows; r0 += stride * kU) {
+            unsigned x[kU];
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                const int r = r0 + u * stride;
+                x[u] = r < nrows ? p[(int64_t)r * row_words * 2] : 0u;
+            }
+#pragma unroll
+            for (int u = 0; u < kU; ++u) acc += x[u];
+        }
+    }
+    return acc;
+}
 template <typename T>
 hipError_t launch_phase(const PhaseArgs& a, bool identity, hipStream_t s);
 constexpr int kPsegBlocks = 256;   // blocks of the per-segment bound pass

@@ -1,15 +1,17 @@
 // Dual phase of one iteration: sales totals, FP64 reductions, certified
 // bound and the projected dual step (eq. 16).
 //
-//   k_fold_lite  per product: S_j = (global 64-bit accumulator, which the
-//             segment blocks fed by integer atomics) / 2^bits and
+//   k_fold_rows  (when a segment pass left rows of bins) S_j of the products
+//             with LDS bins: the 64-bit sum over the pass's block rows
+//   k_fold_lite  per product: S_j = (global 64-bit accumulator) / 2^bits and
 //             P = sum r_j S_j; with A = I also the per-row work below
 //   k_rows    (general A) per resource: u_i = sum_j a_ij S_j through A^T
 //   per row   g_i = u_i - c_i; c.eta, sum (g)^+, the Polyak norm
 //             sum tau_i g_i^2 (g zeroed where the projection binds), ||eta||^2
 //             and the window sums of u for the certified bound
-//   k_fold_step  (A = I, constant step) the fold, the row work and the dual
-//             step in one launch; the last block does k_update's state work
+//   k_fold_step  (A = I, constant step) the rows' fold, the per-product
+//             work and the dual step in one launch; the last block does
+//             k_update's state work
 //   k_update  every block folds the partials in the same fixed order, so all
 //             blocks agree on D = c.eta + sum lambda R*, Dbest, the bound
 //             LB = max over checks of theta * Pbar (theta = min_i min(1,
@@ -30,21 +32,43 @@ namespace {
 
 using namespace dual;
 
-// Fold: one product per thread, kFoldLite threads per block (the segment
-// blocks added their bins to S_fx themselves).
+// Sums over products run in the library's order (products by falling
+// popularity, library id q; caller product j = pinv[q]), where the sales sums
+// and prices live; the arrays of the caller's products (r, c, eta, ...) are
+// read and written at j.
 
+// The segment blocks' rows into the sales sums: 64 products per block of 16
+// waves, each wave adding every 16th row (one contiguous read per wave and
+// row), the first wave the 16 partials.
+__global__ void __launch_bounds__(64 * kStepWaves) k_fold_rows(PhaseArgs a)
+{
+    __shared__ unsigned long long part[kStepWaves][64];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t q = (int64_t)blockIdx.x * 64 + lane;
+    part[wv][lane] = row_bins_sum(a.brow, a.row_words, a.nrows, a.rows_H, a.rows_H64, q, wv,
+                                  kStepWaves);
+    __syncthreads();
+    if (wv == 0 && q < a.rows_H) {
+        unsigned long long t = 0ull;
+#pragma unroll
+        for (int w = 0; w < kStepWaves; ++w) t += part[w][lane];
+        a.S_fx[q] += t;
+    }
+}
+
+// Fold: one product per thread, kFoldLite threads per block.
 template <typename T, bool IDENT>
 __global__ void __launch_bounds__(kFoldLite) k_fold_lite(PhaseArgs a)
 {
     __shared__ double sh[NR * 16];
-    const int64_t j = (int64_t)blockIdx.x * kFoldLite + threadIdx.x;
+    const int64_t q = (int64_t)blockIdx.x * kFoldLite + threadIdx.x;   // library id
     const long long cnt1 = a.mode == 0 ? a.st[a.par].cnt + 1 : 1;
     double x[NR];
     clear(x);
-    if (j < a.n) {
-        const int64_t jq = a.pnew ? a.pnew[j] : j;   // library id of product j
-        const unsigned long long tot = a.S_fx[jq];
-        if (!a.keep_sales) a.S_fx[jq] = 0ull;
+    if (q < a.n) {
+        const int64_t j = a.pinv ? a.pinv[q] : q;   // caller product
+        const unsigned long long tot = a.S_fx[q];
+        if (!a.keep_sales) a.S_fx[q] = 0ull;
         const double sj = (double)(long long)tot * a.inv_fx;
         a.S_d[j] = sj;
         x[R_P] = (double)((const T*)a.r)[j] * sj;
@@ -55,65 +79,76 @@ __global__ void __launch_bounds__(kFoldLite) k_fold_lite(PhaseArgs a)
 }
 
 // A = I with a constant step while iterating: the step needs no global value
-// (the multiplier is 1), so each block also takes the dual step (eq. 16) of
-// its own products, and the last block to arrive (a counter; its partials are
-// published before it counts) folds every block's partials, in k_update's
-// order, into the solver state and the trace row.  One launch instead of two,
-// with the same bits.
+// (the multiplier is 1), so one launch does it all.  A block of 16 waves owns
+// 64 products: the waves add the segment pass's rows for them, the first
+// wave takes each product's sales, row work and dual step (eq. 16) and sums
+// its values by the wave's shuffle tree; the last block to arrive (a
+// counter; partials are published before it counts) folds the partials four
+// at a time (the shape of k_fold_lite's 256-product blocks, so every path
+// gives the same bits) into the solver state and the trace row.
 template <typename T>
-__global__ void __launch_bounds__(kFoldLite) k_fold_step(PhaseArgs a)
+__global__ void __launch_bounds__(64 * kStepWaves) k_fold_step(PhaseArgs a)
 {
     __shared__ double sh[NR * 16];
+    __shared__ unsigned long long part[kStepWaves][64];
+    __shared__ long long zsh[kStepWaves];
     __shared__ int s_last;
-    const int tid = threadIdx.x;
-    const int64_t j = (int64_t)blockIdx.x * kFoldLite + tid;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int64_t q = (int64_t)blockIdx.x * 64 + lane;   // library id
+    const bool own = wv == 0 && q < a.n;
     DevState st = a.st[a.par];
     const long long t1 = st.t + 1, cnt1 = st.cnt + 1;
     const bool restart = t1 == 1 || t1 == 2 * st.t0;   // averaging window restarts
-    double x[NR];
-    clear(x);
-    if (j < a.n) {
-        const int64_t jq = a.pnew ? a.pnew[j] : j;   // library id of product j
-        const unsigned long long tot = a.S_fx[jq];
-        a.S_fx[jq] = 0ull;
-        const double sj = (double)(long long)tot * a.inv_fx;
-        a.S_d[j] = sj;
-        x[R_P] = (double)((const T*)a.r)[j] * sj;
-        row_work<T>(a, j, sj, cnt1, x);
-        T* eta = (T*)a.eta;
+    // the first wave's product values, loaded while the rows are read
+    int64_t j = 0;
+    unsigned long long tot = 0ull;
+    double rj = 0.0, cj = 0.0, ej = 0.0, tj = 0.0, suj = 0.0;
+    if (own) {
+        j = a.pinv ? a.pinv[q] : q;   // caller product
+        tot = a.S_fx[q];
         const T* tauv = (const T*)a.tau_vec;
-        const double ti = a.tau_mult * (tauv ? (double)tauv[j] : a.tau_s);
-        double e = (double)eta[j];
-        e = (1.0 - ti * a.mu) * e + ti * (sj - (double)((const T*)a.c)[j]);
-        if (!(e > 0.0)) e = (e != e) ? e : 0.0;   // projection; NaN stays visible
-        const T et = (T)e;
-        eta[j] = et;
-        if (restart) a.sum_u[j] = 0.0;
-        ((T*)a.rho)[jq] = ((const T*)a.r)[j] - et;
+        rj = (double)((const T*)a.r)[j];
+        cj = (double)((const T*)a.c)[j];
+        ej = (double)((const T*)a.eta)[j];
+        tj = tauv ? (double)tauv[j] : a.tau_s;
+        suj = a.sum_u[j];
     }
-    block_reduce(x, sh);
-    if (tid == 0) {
-        store_part(a.bpart + (size_t)blockIdx.x * 8, x);
-        __threadfence();
-        s_last = atomicAdd(a.arrive, 1u) == gridDim.x - 1 ? 1 : 0;
+    part[wv][lane] = row_bins_sum(a.brow, a.row_words, a.nrows, a.rows_H, a.rows_H64, q, wv,
+                                  kStepWaves);
+    __syncthreads();
+    if (wv == 0) {
+        double x[NR];
+        clear(x);
+        if (own) {
+#pragma unroll
+            for (int w = 0; w < kStepWaves; ++w) tot += part[w][lane];
+            a.S_fx[q] = 0ull;
+            const double sj = (double)(long long)tot * a.inv_fx;
+            a.S_d[j] = sj;
+            x[R_P] = rj * sj;
+            a.u_d[j] = sj;
+            const double su = row_work_values(cj, ej, tj, suj, sj, cnt1, 0, x);
+            const double ti = a.tau_mult * tj;
+            double e = (1.0 - ti * a.mu) * ej + ti * (sj - cj);
+            if (!(e > 0.0)) e = (e != e) ? e : 0.0;   // projection; NaN stays visible
+            const T et = (T)e;
+            ((T*)a.eta)[j] = et;
+            a.sum_u[j] = restart ? 0.0 : su;
+            ((T*)a.rho)[q] = ((const T*)a.r)[j] - et;
+        }
+        wave_reduce(x);
+        if (lane == 0) {
+            store_part(a.bpart + (size_t)blockIdx.x * 8, x);
+            __threadfence();
+            s_last = atomicAdd(a.arrive, 1u) == gridDim.x - 1 ? 1 : 0;
+        }
     }
     __syncthreads();
     if (!s_last) return;
     __threadfence();
-    clear(x);
-    __shared__ long long zsh[kFoldLite / 64];
+    double x[NR];
     const double Zd = fold_z(a.zpart, 0, a.nz, a.inv_z, zsh);
-    for (int q = tid; q < (int)gridDim.x; q += kFoldLite) x[R_P] += a.bpart[(size_t)q * 8 + R_P];
-    for (int q = tid; q < (int)gridDim.x; q += kFoldLite) {
-        const double* p = a.bpart + (size_t)q * 8;
-        x[R_CETA] += p[R_CETA];
-        x[R_INF] += p[R_INF];
-        x[R_G] += p[R_G];
-        x[R_TH] = fmin(x[R_TH], p[R_TH]);
-        x[R_E2] += p[R_E2];
-        x[R_CS] += p[R_CS];
-    }
-    block_reduce(x, sh);
+    fold_partials(a.bpart, (int)gridDim.x, x, sh);
     x[R_Z] = Zd;   // the fixed-point sum, not the FP64 tree
     if (tid != 0) return;
     const double D = x[R_CETA] + x[R_Z];
@@ -351,8 +386,14 @@ hipError_t launch_phase(const PhaseArgs& a, bool identity, hipStream_t s)
         hipLaunchKernelGGL(k_pseg, dim3((unsigned)a.pseg_blocks), dim3(256), 0, s, a);
     };
     if (identity && a.mode == 0 && a.rule != SPFOM_STEP_POLYAK && a.arrive && !a.pseg_part) {
-        hipLaunchKernelGGL((k_fold_step<T>), dim3(fold_grid), dim3(kFoldLite), 0, s, a);
-    } else if (identity) {
+        hipLaunchKernelGGL((k_fold_step<T>), dim3((unsigned)((a.n + 63) / 64)),
+                           dim3(64 * kStepWaves), 0, s, a);
+        return hipGetLastError();
+    }
+    if (a.nrows > 0 && a.rows_H > 0)
+        hipLaunchKernelGGL(k_fold_rows, dim3((unsigned)((a.rows_H + 63) / 64)),
+                           dim3(64 * kStepWaves), 0, s, a);
+    if (identity) {
         hipLaunchKernelGGL((k_fold_lite<T, true>), dim3(fold_grid), dim3(kFoldLite), 0, s, a);
         pseg();
         hipLaunchKernelGGL((k_update<T, true>), dim3(row_grid), dim3(kRowThreads), 0, s, a);

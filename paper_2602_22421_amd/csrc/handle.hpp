@@ -50,10 +50,13 @@ struct cblp_instance {
     void* rho = nullptr;
     unsigned long long* S_fx = nullptr;
     int32_t* pnew = nullptr;        // [n] library id of caller product j (null: ids kept)
+    int32_t* pinv = nullptr;        // [n] caller product of library id q (null with pnew)
     double* S_d = nullptr;
     double* u_d = nullptr;
     double* sum_u = nullptr;
     long long* zpart = nullptr;     // fixed-point Z partials, one per segment block
+    unsigned long long* brow = nullptr;   // [seg_grid x row_words] the blocks' bins
+    int64_t row_words = 0;
     double z_scale = 1.0;           // their scale (a power of two)
     double z_rmax = 0.0;            // largest revenue times (1 + 2^-20)
     double* bpart = nullptr;
@@ -90,7 +93,12 @@ struct cblp_instance {
     bool mb_clear = true;           // the sales must be cleared before the next use
     int seg_grid = 1;
     int seg_variant = 0;
-    int H = 0;
+    int H = 0;                      // products with LDS bins in the segment kernel,
+    int H64 = 0;                    // of which 64-bit ones (the rest 32-bit)
+    int Hb = 0;                     // 64-bit LDS bins of the batched kernels
+    int64_t bin_bytes = 0;          // LDS bytes a segment block has for its bins
+    bool bins_stale = true;         // the values changed: choose H, H64 again
+    bool fold_pending = false;      // a segment pass left rows for the dual phase to fold
     int hp = 0;                     // split-price kernel: prices held in LDS
     int fold_blocks = 1;
     double fx_scale = 1.0;

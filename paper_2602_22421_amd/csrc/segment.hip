@@ -14,12 +14,21 @@
 namespace cblp {
 namespace {
 
-// The block's nonzero bins go straight into the global 64-bit accumulators
-// by atomics (integer sums: the order of the blocks does not matter).
+// Clear the block's LDS bins (64-bit and 32-bit ones, as 64-bit words).
+__device__ __forceinline__ void clear_bins(const SegArgs& a, unsigned long long* bins)
+{
+    const int words = (int)(seg_bin_bytes(a.H, a.H64) / 8);
+    for (int j = threadIdx.x; j < words; j += kSegThreads) bins[j] = 0ull;
+}
+
+// The block's bins leave LDS as the block's row of a.brow (plain stores;
+// k_fold_rows adds the rows into the global sums, integer adds, so the order
+// of the blocks does not matter).
 __device__ __forceinline__ void flush_bins(const SegArgs& a, const unsigned long long* bins)
 {
-    for (int j = threadIdx.x; j < a.H; j += kSegThreads)
-        if (bins[j]) atomicAdd(&a.S_fx[j], bins[j]);
+    const int words = (int)(seg_bin_bytes(a.H, a.H64) / 8);
+    unsigned long long* row = a.brow + (int64_t)blockIdx.x * a.row_words;
+    for (int w = threadIdx.x; w < words; w += kSegThreads) row[w] = bins[w];
 }
 
 // Slot-major kernel: the per-segment step over the slot-major copy (one
@@ -27,11 +36,10 @@ __device__ __forceinline__ void flush_bins(const SegArgs& a, const unsigned long
 template <typename T, int J, bool ALL, bool LDSP, typename IdxT = int32_t, bool PSEG = false>
 __global__ void __launch_bounds__(kSegThreads) k_segments_slots(SegArgs a)
 {
-    extern __shared__ unsigned long long bins[];   // [a.H], then [a.n] prices if LDSP
+    extern __shared__ unsigned long long bins[];   // the bins, then [a.n] prices if LDSP
     __shared__ long long zsh[kSegThreads / 64];
-    const int H = a.H;
-    T* lprice = (T*)(bins + H);
-    for (int j = threadIdx.x; j < H; j += kSegThreads) bins[j] = 0ull;
+    T* lprice = (T*)((char*)bins + seg_bin_bytes(a.H, a.H64));
+    clear_bins(a, bins);
     if (LDSP)
         for (int64_t j = threadIdx.x; j < a.n; j += kSegThreads) lprice[j] = ((const T*)a.rho)[j];
     __syncthreads();
@@ -57,11 +65,10 @@ __global__ void __launch_bounds__(kSegThreads) k_segments_slots(SegArgs a)
 template <typename T, typename IdxT, bool SPLIT = false, bool PSEG = false>
 __global__ void __launch_bounds__(kSegThreads) k_segments_mixed3(SegArgs a2, SegArgs a4, SegArgs a8)
 {
-    extern __shared__ unsigned long long bins[];   // [a2.H], then the LDS prices
+    extern __shared__ unsigned long long bins[];   // the bins, then the LDS prices
     __shared__ long long zsh[kSegThreads / 64];
-    const int H = a2.H;
-    T* lprice = (T*)(bins + H);
-    for (int j = threadIdx.x; j < H; j += kSegThreads) bins[j] = 0ull;
+    T* lprice = (T*)((char*)bins + seg_bin_bytes(a2.H, a2.H64));
+    clear_bins(a2, bins);
     const int64_t np = SPLIT ? (int64_t)a2.hp : a2.n;
     for (int64_t j = threadIdx.x; j < np; j += kSegThreads) lprice[j] = ((const T*)a2.rho)[j];
     __syncthreads();
@@ -112,7 +119,61 @@ __global__ void k_entry_sales(int64_t L, const int32_t* perm, const int64_t* seg
     }
 }
 
+// A bound, in quanta, on the sales of each product within each segment
+// block: an entry's sale lambda v / D, with D = vt0 + the sum of v - w over
+// the assortment (all terms positive, the entry's own among them when it
+// sells), is at most lambda v / (vt0 + v - w); scaled by 2^bits, with a
+// margin far above the FP32 rounding of the kernels' quanta.  Positions map
+// to blocks as in k_segments_mixed3 (the parts' tiles, dealt round robin
+// over G blocks).  Ub[j * G + b] for products j < Hc.
+__global__ void k_bin_bound(int64_t L, int64_t P2, int64_t P4, int G, const int64_t* ptr2,
+                            const int32_t* idx2, const float* v2, const float* den2,
+                            const float* vt0, const float* lam, double fx_scale, int Hc,
+                            unsigned long long* Ub)
+{
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < L;
+         p += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t tile = p < P2 ? p / seg::kPairTileRows
+                             : p < P4 ? (p - P2) / seg::kQuadTileRows
+                                      : (p - P4) / kSegsPerTile;
+        const int64_t b = tile % G;
+        const double lp = (double)lam[p], vt = (double)vt0[p];
+        for (int64_t e = ptr2[p]; e < ptr2[p + 1]; ++e) {
+            const int32_t j = idx2[e];
+            if (j >= Hc) continue;
+            const double ub = lp * (double)v2[e] / (vt + (double)den2[e]) * fx_scale;
+            atomicAdd(&Ub[(int64_t)j * G + b], (unsigned long long)(ub * (1.0 + 1.0 / 1024)) + 2ull);
+        }
+    }
+}
+
+// need = 1 + the largest product id whose bound reaches 2^32 in some block
+// (0 if none): one product per thread.
+__global__ void k_bin_need(const unsigned long long* Ub, int G, int Hc, int* need)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= Hc) return;
+    unsigned long long mx = 0ull;
+    for (int b = 0; b < G; ++b) mx = max(mx, Ub[(int64_t)j * G + b]);
+    if (mx >= (1ull << 32)) atomicMax(need, j + 1);
+}
+
 }  // namespace
+
+hipError_t launch_bin_bound(int64_t L, int64_t P2, int64_t P4, int G, const int64_t* ptr2,
+                            const int32_t* idx2, const void* v2, const void* den2,
+                            const void* vt0, const void* lam, double fx_scale, int Hc,
+                            unsigned long long* Ub, int* need, hipStream_t s)
+{
+    if (L > 0)
+        hipLaunchKernelGGL(k_bin_bound, dim3(2048), dim3(256), 0, s, L, P2, P4, G, ptr2, idx2,
+                           (const float*)v2, (const float*)den2, (const float*)vt0,
+                           (const float*)lam, fx_scale, Hc, Ub);
+    if (Hc > 0)
+        hipLaunchKernelGGL(k_bin_need, dim3((unsigned)((Hc + 255) / 256)), dim3(256), 0, s, Ub, G,
+                           Hc, need);
+    return hipGetLastError();
+}
 
 template <typename T>
 hipError_t launch_entry_sales(int64_t L, const int32_t* perm, const int64_t* seg_ptr,
@@ -156,9 +217,11 @@ template <typename T>
 hipError_t launch_segments(const SegArgs& a2, const SegArgs& a4, const SegArgs& a8, int grid,
                            int variant, bool pseg, hipStream_t s)
 {
-    const size_t lds = seg_lds_bytes(a2.H, a2.n, a2.hp, sizeof(T), variant);
+    const size_t lds = seg_lds_bytes(a2.H, a2.H64, a2.n, a2.hp, sizeof(T), variant);
     const void* f = segment_kernel<T>(variant, pseg);
-    if (pseg) (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    // the bins' layout is per handle: allow this launch's LDS whatever another
+    // handle set last
+    (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (seg_mixed3(variant)) {
         void* args[] = {(void*)&a2, (void*)&a4, (void*)&a8};
         return hipLaunchKernel(f, dim3(grid), dim3(kSegThreads), args, lds, s);
@@ -168,10 +231,10 @@ hipError_t launch_segments(const SegArgs& a2, const SegArgs& a4, const SegArgs& 
 }
 
 template <typename T>
-int segment_blocks_per_cu(int H, int64_t n, int hp, int variant)
+int segment_blocks_per_cu(int H, int H64, int64_t n, int hp, int variant)
 {
     int blocks = 0;
-    const size_t lds = seg_lds_bytes(H, n, hp, sizeof(T), variant);
+    const size_t lds = seg_lds_bytes(H, H64, n, hp, sizeof(T), variant);
     const void* f = segment_kernel<T>(variant, false);
     (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, f, kSegThreads, lds) != hipSuccess)
@@ -191,7 +254,7 @@ template hipError_t launch_entry_sales<double>(int64_t, const int32_t*, const in
                                                const int32_t*, const void*, const void*,
                                                const int32_t*, const void*, const void*,
                                                const void*, double, double*, hipStream_t);
-template int segment_blocks_per_cu<float>(int, int64_t, int, int);
-template int segment_blocks_per_cu<double>(int, int64_t, int, int);
+template int segment_blocks_per_cu<float>(int, int, int64_t, int, int);
+template int segment_blocks_per_cu<double>(int, int, int64_t, int, int);
 
 }  // namespace cblp

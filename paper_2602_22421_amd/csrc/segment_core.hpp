@@ -20,8 +20,8 @@
 // 64-bit ones) and summed as 64-bit integers, so the totals do not depend on
 // the order of the additions.  Products [0, H) - the popular head when
 // products are numbered by popularity - accumulate in LDS bins of each block
-// and are written out as one partial row per block; the rest use global
-// atomics.
+// (64-bit for the first H64, 32-bit for the rest, sized so that no 32-bit
+// sum can wrap) and leave LDS at the block's end; the rest use global atomics.
 //
 // Layout: an 8-lane group owns one segment of the library's size-sorted
 // copy; lane g holds products g, g+8, ..., g+56 of the row in registers and
@@ -215,6 +215,25 @@ __device__ __forceinline__ unsigned long long quantum(double ls, double v)
     return (unsigned long long)__double2ll_rn(ls * v);
 }
 
+// One sale of q quanta of product j.  Products [0, a.H64) are summed in the
+// block's 64-bit LDS bins, [a.H64, a.H) in the 32-bit LDS bins that follow
+// them, the rest straight in the global 64-bit sums.  A product gets a
+// 32-bit bin only when a bound on its sales within every block (each sale
+// at most lambda v / (vt0 + v - w), whatever the assortment) stays below
+// 2^32 quanta, so the 32-bit sums never wrap (the host checks the bound;
+// FP64 handles keep H64 = H).
+template <typename T>
+__device__ __forceinline__ void add_sale(const SegArgs& a, unsigned long long* bins, int j,
+                                         unsigned long long q)
+{
+    if (j < a.H64)
+        atomicAdd(&bins[j], q);
+    else if (sizeof(T) == 4 && j < a.H)
+        atomicAdd((unsigned*)(bins + a.H64) + (j - a.H64), (unsigned)q);
+    else
+        atomicAdd(&a.S_fx[j], q);
+}
+
 // J: products per lane held in registers (rows longer than 8 J stream the
 // rest).  DEPTH 1 keeps the CSR entries of the next tile (and the row bounds
 // of the one after) in flight while a tile is solved; DEPTH 0 none; DEPTH 2
@@ -240,7 +259,6 @@ __device__ __forceinline__ void process_tiles(const SegArgs& a, int64_t tile, in
     const T* __restrict__ dg = (const T*)a.den;
     const PR& rho = prices;
     const int32_t* __restrict__ idx = a.idx;
-    const int H = a.H;
     const int g = threadIdx.x & (kGroup - 1);
     const int grp = threadIdx.x / kGroup;
     auto pos_of = [&](int64_t t) { return t * kSegsPerTile + grp; };
@@ -392,10 +410,7 @@ __device__ __forceinline__ void process_tiles(const SegArgs& a, int64_t tile, in
                 if (num[s] > R * den[s]) {
                     const unsigned long long q = quantum(lamD, Rc.v[s]);
                     const int32_t j = Rc.id[s];
-                    if (j < H)
-                        atomicAdd(&bins[j], q);
-                    else
-                        atomicAdd(&a.S_fx[j], q);
+                    add_sale<T>(a, bins, j, q);
                 }
             }
             for (int q = kGroup * J + g; q < k; q += kGroup) {
@@ -403,10 +418,7 @@ __device__ __forceinline__ void process_tiles(const SegArgs& a, int64_t tile, in
                 const int32_t j = idx[b + q];
                 if (rho[j] * x > R * dg[b + q]) {
                     const unsigned long long qq = quantum(lamD, x);
-                    if (j < H)
-                        atomicAdd(&bins[j], qq);
-                    else
-                        atomicAdd(&a.S_fx[j], qq);
+                    add_sale<T>(a, bins, j, qq);
                 }
             }
             if (g == 0 && p < a.L) {
@@ -522,7 +534,6 @@ __device__ __forceinline__ void process_tiles_slots(const SegArgs& a, int64_t ti
     const T* __restrict__ v3 = (const T*)a.v3;
     const T* __restrict__ d3 = (const T*)a.den3;
     const IdxT* __restrict__ i3 = (const IdxT*)a.idx3;
-    const int H = a.H;
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
     const int q = lane / kGroup;
@@ -629,10 +640,7 @@ __device__ __forceinline__ void process_tiles_slots(const SegArgs& a, int64_t ti
                 const unsigned long long qv = quantum(lamD, Rc.v[s]);
                 const int32_t j = Rc.id[s];
                 if constexpr (PSEG) pl += (double)((const T*)a.rlib)[j] * (double)(long long)qv;
-                if (j < H)
-                    atomicAdd(&bins[j], qv);
-                else
-                    atomicAdd(&a.S_fx[j], qv);
+                add_sale<T>(a, bins, j, qv);
             }
         }
         for (int s = J; s < jw; ++s) {
@@ -642,10 +650,7 @@ __device__ __forceinline__ void process_tiles_slots(const SegArgs& a, int64_t ti
             if (rho[j] * x > R * d3[e]) {
                 const unsigned long long qq = quantum(lamD, x);
                 if constexpr (PSEG) pl += (double)((const T*)a.rlib)[j] * (double)(long long)qq;
-                if (j < H)
-                    atomicAdd(&bins[j], qq);
-                else
-                    atomicAdd(&a.S_fx[j], qq);
+                add_sale<T>(a, bins, j, qq);
             }
         }
         if constexpr (PSEG) pl = group_sum(pl);
@@ -723,7 +728,6 @@ __device__ __forceinline__ void process_tiles_quad(const SegArgs& a, int64_t til
     const T* __restrict__ v3 = (const T*)a.v3;
     const T* __restrict__ d3 = (const T*)a.den3;
     const IdxT* __restrict__ i3 = (const IdxT*)a.idx3;
-    const int H = a.H;
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
     const int q = lane / kQuad;
@@ -842,10 +846,7 @@ __device__ __forceinline__ void process_tiles_quad(const SegArgs& a, int64_t til
                 const unsigned long long qv = quantum(lamD, Rc.v[s]);
                 const int32_t j = Rc.id[s];
                 if constexpr (PSEG) pl += (double)((const T*)a.rlib)[j] * (double)(long long)qv;
-                if (j < H)
-                    atomicAdd(&bins[j], qv);
-                else
-                    atomicAdd(&a.S_fx[j], qv);
+                add_sale<T>(a, bins, j, qv);
             }
         }
         for (int s = J; s < jw; ++s) {
@@ -855,10 +856,7 @@ __device__ __forceinline__ void process_tiles_quad(const SegArgs& a, int64_t til
             if (rho[j] * x > R * d3[e]) {
                 const unsigned long long qq = quantum(lamD, x);
                 if constexpr (PSEG) pl += (double)((const T*)a.rlib)[j] * (double)(long long)qq;
-                if (j < H)
-                    atomicAdd(&bins[j], qq);
-                else
-                    atomicAdd(&a.S_fx[j], qq);
+                add_sale<T>(a, bins, j, qq);
             }
         }
         if constexpr (PSEG) pl = quad_total(pl);
@@ -935,7 +933,6 @@ __device__ __forceinline__ void process_tiles_pair(const SegArgs& a, int64_t til
     const T* __restrict__ v3 = (const T*)a.v3;
     const T* __restrict__ d3 = (const T*)a.den3;
     const IdxT* __restrict__ i3 = (const IdxT*)a.idx3;
-    const int H = a.H;
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
     const int q = lane / kPair;
@@ -1048,10 +1045,7 @@ __device__ __forceinline__ void process_tiles_pair(const SegArgs& a, int64_t til
                 const unsigned long long qv = quantum(lamD, Rc.v[s]);
                 const int32_t j = Rc.id[s];
                 if constexpr (PSEG) pl += (double)((const T*)a.rlib)[j] * (double)(long long)qv;
-                if (j < H)
-                    atomicAdd(&bins[j], qv);
-                else
-                    atomicAdd(&a.S_fx[j], qv);
+                add_sale<T>(a, bins, j, qv);
             }
         }
         for (int s = J; s < jw; ++s) {
@@ -1061,10 +1055,7 @@ __device__ __forceinline__ void process_tiles_pair(const SegArgs& a, int64_t til
             if (rho[j] * x > R * d3[e]) {
                 const unsigned long long qq = quantum(lamD, x);
                 if constexpr (PSEG) pl += (double)((const T*)a.rlib)[j] * (double)(long long)qq;
-                if (j < H)
-                    atomicAdd(&bins[j], qq);
-                else
-                    atomicAdd(&a.S_fx[j], qq);
+                add_sale<T>(a, bins, j, qq);
             }
         }
         if constexpr (PSEG) pl = pl + dpp_move<kQuadSwap1>(pl);

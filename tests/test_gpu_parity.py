@@ -10,7 +10,8 @@ import numpy as np
 import pytest
 
 import oracle
-from paper_2602_22421_amd.instances import (config_instance, make_instance, step_scale)
+from paper_2602_22421_amd.instances import (Instance, config_instance, make_instance,
+                                             step_scale)
 
 pytestmark = pytest.mark.gpu
 
@@ -441,8 +442,8 @@ def test_full_size_config1_equal_iterations(cb):
     """The L=2e6, n=2e4 workload in the benchmark's launch shape: duals, dual
     bound and revenue after 1 and 10 FP32 iterations against the FP64
     oracle, element by element; then, at fixed duals, every segment's
-    assortment and sales against the oracle's (covering the sales of the
-    products past the LDS bins, which take global atomics)."""
+    assortment and sales against the oracle's (covering the sales summed in
+    the 64-bit and in the 32-bit LDS bins)."""
     inst = config_instance(1).cast(np.float32)
     prob, params, orc, _ = _pair(cb, inst, torch.float32, tau0=0.001)
     for t, eg, eo, trg, tro in _run_both(prob, params, orc, [1, 10]):
@@ -454,8 +455,54 @@ def test_full_size_config1_equal_iterations(cb):
     S, u, R, s = prob.sales(prob.tensor(eta), seg_R=True, entries=True)
     ref = oracle.best_response(inst, eta.astype(np.float64))
     info = cb.cblp_launch_info(prob.h)
-    H = info["lds_bins"]
-    assert H < inst.n and np.count_nonzero(ref["S"][H:]) > 1000   # the global-atomic tail is used
+    H, H64 = info["lds_bins"], info["lds_bins64"]
+    assert H64 < H and np.count_nonzero(ref["S"][H64:H]) > 1000   # the 32-bit bins are used
+    assert np.count_nonzero(ref["S"][H:]) == 0 or H < inst.n
+    check_entry_sales(inst, eta, S.cpu().numpy(), u.cpu().numpy(), s.cpu().numpy(), ref, 2e-5,
+                      2.0 ** -info["fx_bits"])
+    prob.close()
+
+
+def _grouped_instance(n, per_group, seg_per_group, v_hi, seed):
+    """Products in groups of per_group; seg_per_group consecutive segments
+    consider one group each, so a segment block holds many sales of the same
+    products.  Attractions U(1, v_hi) against v0 = 1, lambda = 1."""
+    rng = np.random.default_rng(seed)
+    groups = n // per_group
+    L = groups * seg_per_group
+    g = np.repeat(np.arange(groups), seg_per_group)
+    idx = (g[:, None] * per_group + np.arange(per_group)[None, :]).ravel().astype(np.int32)
+    nnz = idx.size
+    v = rng.uniform(1.0, v_hi, nnz)
+    w = v * rng.uniform(0.0, 0.5, nnz)
+    return Instance(L=L, n=n, m=n, seg_ptr=np.arange(L + 1, dtype=np.int64) * per_group,
+                    idx=idx, v=v, w=w, v0=np.ones(L), lam=np.ones(L),
+                    r=rng.uniform(1, 100, n), c=np.full(n, 0.5 * seg_per_group / per_group))
+
+
+@pytest.mark.parametrize("case", ["bound-fails", "bound-holds"])
+def test_bin_layout_from_sales_bound(cb, case):
+    """FP32 handles with more products than 64-bit LDS bins: a product takes
+    a 32-bit bin only when its sales within any segment block are bounded
+    below 2^32 quanta.  bound-fails: 40 segments in a row share each group of
+    10 products, so every product may sell about 40 near-whole units in one
+    block (above 2^32 quanta at 29 bits): no 32-bit bins.  bound-holds: 2
+    segments per group, so every product gets a bin, all 32-bit.  Both
+    against the oracle at fixed duals, with S the exact sum of the per-entry
+    sales."""
+    spg = 40 if case == "bound-fails" else 2
+    inst = _grouped_instance(25000, 10, spg, 50.0, seed=3).cast(np.float32)
+    prob = cb.Problem(inst, dtype=torch.float32)
+    rng = np.random.default_rng(4)
+    eta = (rng.uniform(0, 0.5, inst.m) * inst.r).astype(np.float32)
+    S, u, R, s = prob.sales(prob.tensor(eta), seg_R=True, entries=True)
+    info = cb.cblp_launch_info(prob.h)
+    H, H64 = info["lds_bins"], info["lds_bins64"]
+    if case == "bound-fails":
+        assert H == H64 < inst.n, info
+    else:
+        assert H == inst.n and H64 == 0, info
+    ref = oracle.best_response(inst, eta.astype(np.float64))
     check_entry_sales(inst, eta, S.cpu().numpy(), u.cpu().numpy(), s.cpu().numpy(), ref, 2e-5,
                       2.0 ** -info["fx_bits"])
     prob.close()

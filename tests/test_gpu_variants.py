@@ -3,10 +3,11 @@
 FP32 instances take the three-part kernel (2-, 4- and 8-lane groups) with all
 prices in LDS when they fit, else with the popular head of them in LDS and
 16-bit product ids (n <= 65,536) or 32-bit ids; FP64 instances take the
-8-lane kernel with 16- or 32-bit ids.  Padding an instance with products that
-no segment considers changes which kernel runs (and how many sales bins sit
-in LDS) but not the answer for the real products, so each padded run must
-give the unpadded run's sales, usage, R* and duals bit for bit."""
+8-lane kernel with 16- or 32-bit ids.  Padding an instance with products
+that no segment considers changes which kernel runs (and how many sales bins
+sit in LDS, and how many of them are 32 bits wide) but not the answer for
+the real products, so each padded run must give the unpadded run's sales,
+usage, R* and duals bit for bit."""
 import dataclasses
 
 import numpy as np
@@ -63,15 +64,22 @@ def test_shape_chosen_kernels_agree(cb, dtype, sizes):
                          seed=21).cast(npdt)
     tau0 = step_scale(base, 1e-3)
     ref, tr_ref, info_ref = _run(cb, base, dt, base.n, tau0)
-    bins = [info_ref["lds_bins"]]
+    bins = [(info_ref["lds_bins"], info_ref["lds_bins64"])]
     for n in sizes[1:]:
         got, tr, info = _run(cb, _pad(base, n), dt, base.n, tau0)
-        bins.append(info["lds_bins"])
+        bins.append((info["lds_bins"], info["lds_bins64"]))
         for k, (a, b) in enumerate(zip(ref, got)):
             assert np.array_equal(a, b), (n, k, info)
         # the FP64 sums over products only gain exact zeros
         np.testing.assert_allclose(tr[:, :3], tr_ref[:, :3], rtol=1e-14)
     if dtype == "f32":
-        # all 600 prices and bins in LDS; then the 8,192 head prices and fewer
-        # bins than products (the rest of the sales take global atomics)
-        assert bins[0] == 600 and 600 < bins[1] < 30000 and bins[2] == bins[1], bins
+        # all 600 prices and 64-bit bins in LDS; at n = 30,000 the 8,192 head
+        # prices and a bin for every product: 64-bit ones only for the popular
+        # products whose sales within a block may reach 2^32 quanta, 32-bit
+        # ones for the other real products and the padding; at n = 70,000 the
+        # same, with fewer bins than products (the rest take global atomics)
+        assert bins[0] == (600, 600), bins
+        assert bins[1][0] == 30000 and 0 < bins[1][1] < 600, bins
+        assert 30000 < bins[2][0] < 70000 and bins[2][1] == bins[1][1], bins
+    else:
+        assert all(b == b64 for b, b64 in bins), bins
