@@ -426,6 +426,7 @@ def gosim_bench(args):
                          f"({el:.1f} s, FP64)"}
         log(f"oracle: {cpu['value']:.3e} customers/s")
     sim = cblp.GoSim(mk, dtype=dt)
+    cblp.cblp_batch_persistent(sim.b, args.gs_persistent)
     rule = cblp.SPFOM_STEP_POLYAK if args.gs_rule == "polyak" else cblp.SPFOM_STEP_CONST
     params = cblp.make_params(rule=rule, tau=1.0, check_every=10, tol=args.gs_tol,
                               max_iters=args.gs_max_iters, tau_decay=args.gs_decay,
@@ -459,7 +460,7 @@ def gosim_bench(args):
                       "products": mk.n, "K": args.gs_k, "tol": args.gs_tol,
                       "max_iters": args.gs_max_iters, "tau0": args.gs_tau0,
                       "step_rule": args.gs_rule, "tau_decay": args.gs_decay,
-                      "decay_every": args.gs_decay_every},
+                      "decay_every": args.gs_decay_every, "persistent": args.gs_persistent},
            "lp": {"solved_fraction": float(solved.mean()),
                   "median_gap": float(np.median(out["lp_gap"][solved])) if solved.any() else 0.0,
                   "converged_fraction": float((out["lp_gap"][solved] <= args.gs_tol).mean())
@@ -678,6 +679,9 @@ def main():
     ap.add_argument("--gs-rule", default="const", choices=["const", "polyak"])
     ap.add_argument("--gs-decay", type=float, default=0.7)
     ap.add_argument("--gs-decay-every", type=int, default=100)
+    ap.add_argument("--gs-persistent", type=int, default=-1, choices=[-1, 0, 1],
+                    help="batched solves: -1 library default, 0 per-iteration launches, "
+                         "1 one launch per solve")
     ap.add_argument("--recover", action="store_true",
                     help="time the SBLP -> CBLP recovery of one pass's sales")
     ap.add_argument("--levels", nargs="+", default=["1e-2", "3e-3", "1e-3"],

@@ -346,6 +346,20 @@ int cblp_batch_info(cblp_batch_t b, int32_t* items, int32_t* grid, int32_t* vari
  * CBLP_EINVAL if the variant cannot run on this batch. */
 int cblp_batch_select(cblp_batch_t b, int32_t variant);
 
+/* How spfom_batch_solve runs: mode 1 solves every instance in one launch,
+ * one persistent 1024-thread block per instance that runs its iterations,
+ * folds and gap tests itself (the same bits as the per-iteration launches;
+ * each instance stops at the same iteration); 0 always launches the three
+ * kernels of each iteration (replayed from the graph); -1 (the default)
+ * takes the one-launch form when every instance has at most 2^18 entries.
+ * The one-launch form keeps each instance's product state in LDS for the
+ * whole solve; it needs at most 2048 products per instance, every product in
+ * a 64-bit LDS bin, the handles' slot-major copies with one product id type,
+ * and the largest instance's bins, prices, product state and fold partials
+ * within one block's LDS: CBLP_EINVAL for mode 1 when the batch does not
+ * meet that (mode -1 then keeps the per-iteration launches). */
+int cblp_batch_persistent(cblp_batch_t b, int32_t mode);
+
 /* Instances that take part in the batch's next spfom_batch_iterate and
  * spfom_batch_solve calls: take_part [host] [count], nonzero = takes part;
  * NULL = every instance (the state after cblp_batch_create).  The others

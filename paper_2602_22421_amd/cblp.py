@@ -28,7 +28,8 @@ EXPORTS = ("cblp_create", "cblp_destroy", "spfom_reset", "spfom_iterate", "spfom
            "spfom_minibatch", "cblp_recover", "cblp_gap_static", "cblp_gap_static_max_products",
            "cblp_last_error", "cblp_batch_create", "cblp_batch_destroy", "spfom_batch_iterate",
            "spfom_batch_solve", "cblp_batch_tune", "cblp_batch_tune_cached", "cblp_batch_info",
-           "cblp_batch_select", "cblp_refresh", "cblp_batch_mask", "gosim_lp_inputs",
+           "cblp_batch_select", "cblp_refresh", "cblp_batch_mask", "cblp_batch_persistent",
+           "gosim_lp_inputs",
            "gosim_period", "gosim_run",
            "wsnet_num_params", "wsnet_create", "wsnet_destroy", "wsnet_params", "wsnet_features",
            "wsnet_forward", "wsnet_gradients", "wsnet_train_step", "wsnet_train_epochs",
@@ -132,6 +133,8 @@ def load(path: str = _LIB_PATH) -> ctypes.CDLL:
     lib.cblp_refresh.argtypes = [vp, vp]
     lib.cblp_batch_mask.restype = ctypes.c_int
     lib.cblp_batch_mask.argtypes = [vp, vp]
+    lib.cblp_batch_persistent.restype = ctypes.c_int
+    lib.cblp_batch_persistent.argtypes = [vp, i32]
     lib.gosim_lp_inputs.restype = ctypes.c_int
     lib.gosim_lp_inputs.argtypes = [i32, i64, vp, i64, ctypes.c_double, vp, vp, vp, vp, i32, vp]
     lib.gosim_period.restype = ctypes.c_int
@@ -483,6 +486,10 @@ def cblp_batch_select(b, variant: int) -> None:
     _check(load().cblp_batch_select(ctypes.c_void_p(b), int(variant)))
 
 
+def cblp_batch_persistent(b, mode: int) -> None:
+    _check(load().cblp_batch_persistent(ctypes.c_void_p(b), int(mode)))
+
+
 def cblp_batch_mask(b, take_part=None) -> None:
     arr = None
     if take_part is not None:
@@ -535,6 +542,10 @@ class Batch:
 
     def info(self) -> dict:
         return cblp_batch_info(self.b)
+
+    def persistent(self, mode: int) -> None:
+        """-1: one launch per solve for small batches (default), 0: never, 1: always."""
+        cblp_batch_persistent(self.b, mode)
 
     def select(self, variant: int) -> None:
         cblp_batch_select(self.b, variant)

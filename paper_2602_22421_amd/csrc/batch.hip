@@ -319,6 +319,244 @@ __global__ void __launch_bounds__(kRowThreads) k_bprices(const BInst* inst, cons
         ((T*)I->rho)[I->pnew ? I->pnew[i] : i] = ((const T*)I->r)[i] - ((const T*)I->eta)[i];
 }
 
+// Whole solves of small instances, one block each (a persistent launch): the
+// block runs the iterations of its instance itself - the segment pass over its
+// slot-major parts with the prices and every product's 64-bit bin in LDS, the
+// fold in 64-product waves, the state update and the dual step - and tests the
+// gap every check_every iterations as spfom_batch_solve does, so the batch
+// needs one launch for the whole solve instead of three per iteration.  The
+// products' state (c, eta, tau, r, the window sum of u, u) stays in LDS for the
+// whole solve and goes back to the handle at the end.  The per-segment code,
+// the integer sales and Z sums, the wave reductions and the four-at-a-time
+// fold of the partials are those of k_bsegments, k_bfold and k_bupdate: the
+// same bits.
+constexpr int kSolveMaxProducts = 2048;   // products per instance of the one-launch form
+struct BSolveArgs {
+    int rule, check_every;
+    double gamma, mu;
+    double tau_decay;
+    long long decay_every;
+    long long max_iters;
+    double tol;
+    int* status;               // [count] CBLP_OK, CBLP_ENOTCONVERGED or CBLP_ENONFINITE
+    long long* iters;          // [count] iterations run
+};
+
+// the LDS of one instance: bins [H], then per product (8-byte words) the
+// prices, c, eta, tau, r, sum_u, u, then the fold partials [nf][8]
+__host__ __device__ inline size_t bsolve_words(int H, int64_t n)
+{
+    return (size_t)H + 7 * (size_t)n + (size_t)((n + 63) / 64) * 8;
+}
+
+// NARROW: the instances may have pair and quad parts (FP32); without them
+// only the 8-lane routine is compiled in, which keeps its registers.
+template <typename T, typename IdxT, bool NARROW>
+__global__ void __launch_bounds__(kSegThreads) k_bsolve(const BInst* __restrict__ inst, BSolveArgs sa)
+{
+    using namespace dual;
+    extern __shared__ unsigned long long lds[];
+    __shared__ double sh[NR * 16];
+    __shared__ long long zsh[kSegThreads / 64];
+    __shared__ DevState s_st;
+    __shared__ double s_scale;
+    __shared__ int s_restart, s_stop, s_status;
+    const BInst* I = inst + blockIdx.x;
+    if (!I->active) return;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int H = I->H;
+    const int64_t n = I->n;   // = m (A = I)
+    const int nf = (int)((n + 63) / 64);
+    unsigned long long* bins = lds;
+    T* lprice = (T*)(lds + H);                 // by library id
+    double* c_l = (double*)(lds + H + n);      // the rest by caller product
+    double* e_l = c_l + n;                     // eta, rounded to T as stored
+    double* t_l = e_l + n;
+    T* r_l = (T*)(t_l + n);
+    double* su_l = (double*)(lds + H + 5 * n);
+    double* u_l = su_l + n;
+    double* part = u_l + n;
+    const seg::FlatPrices<T> pr{(const T*)lprice};
+    {
+        const T* r = (const T*)I->r;
+        const T* c = (const T*)I->c;
+        const T* eta = (const T*)I->eta;
+        const T* tauv = (const T*)I->tau_vec;
+        for (int64_t j = tid; j < n; j += kSegThreads) {
+            lprice[j] = ((const T*)I->rho)[j];
+            c_l[j] = (double)c[j];
+            e_l[j] = (double)eta[j];
+            t_l[j] = tauv ? (double)tauv[j] : I->tau_s;
+            r_l[j] = r[j];
+            su_l[j] = I->sum_u[j];
+            u_l[j] = 0.0;
+        }
+    }
+    if (tid == 0) {
+        s_st = I->st[current(I->st)];
+        s_stop = 0;
+        s_status = CBLP_ENOTCONVERGED;
+    }
+    for (long long it = 0; it < sa.max_iters; ++it) {
+        for (int j = tid; j < H; j += kSegThreads) bins[j] = 0ull;
+        __syncthreads();
+        // the segment pass over the instance's parts
+        ZAcc zacc;
+        if constexpr (NARROW && sizeof(T) == 4) {
+            const SegArgs& a0 = I->part_args[0];
+            seg::process_tiles_pair<T, 8, seg::FlatPrices<T>, IdxT>(
+                a0, 0, (a0.L + seg::kPairTileRows - 1) / seg::kPairTileRows, 1, bins, pr, zacc);
+            const SegArgs& a1 = I->part_args[1];
+            seg::process_tiles_quad<T, 8, seg::FlatPrices<T>, IdxT>(
+                a1, 0, (a1.L + seg::kQuadTileRows - 1) / seg::kQuadTileRows, 1, bins, pr, zacc);
+        }
+        {
+            const SegArgs& a2 = I->part_args[2];
+            seg::process_tiles_slots<T, sizeof(T) == 4 ? 7 : 4, false, seg::FlatPrices<T>, IdxT>(
+                a2, 0, (a2.L + kSegsPerTile - 1) / kSegsPerTile, 1, bins, pr, zacc);
+        }
+        __syncthreads();
+        const long long zq = block_z(zacc, zsh);
+        const double Zd = zq == kZPoison ? __longlong_as_double(0x7ff8000000000000ll)
+                                         : (double)zq * I->inv_z;
+        // the fold: 64 products (library ids) per wave, as k_bfold
+        const long long cnt1 = s_st.cnt + 1;
+        for (int f = wv; f < nf; f += kSegThreads / 64) {
+            const int64_t q = (int64_t)f * 64 + lane;
+            double x[NR];
+            clear(x);
+            if (q < n) {
+                const int64_t j = I->pinv ? I->pinv[q] : q;   // caller product
+                const double sj = (double)(long long)bins[q] * I->inv_fx;
+                x[R_P] = (double)r_l[j] * sj;
+                u_l[j] = sj;
+                su_l[j] = row_work_values(c_l[j], e_l[j], t_l[j], su_l[j], sj, cnt1, 0, x);
+            }
+            wave_reduce(x);
+            if (lane == 0)
+                for (int q2 = 0; q2 < NR; ++q2) part[f * 8 + q2] = x[q2];
+        }
+        __syncthreads();
+        // the partials four at a time, as k_bupdate, then the state
+        double x[NR];
+        clear(x);
+        if (tid < kRowThreads)
+            for (int g = tid; g < (nf + 3) / 4; g += kRowThreads) {
+                double y[NR];
+                clear(y);
+                for (int k = 0; k < 4; ++k) {
+                    const int q = 4 * g + k;
+                    double p[NR];
+                    clear(p);   // past the instance's last product: the values of empty waves
+                    if (q < nf)
+                        for (int rr = 0; rr < NR; ++rr)
+                            if (rr != R_Z) p[rr] = part[q * 8 + rr];
+                    for (int rr = 0; rr < NR; ++rr)
+                        y[rr] = k == 0 ? p[rr] : rr == R_TH ? fmin(y[rr], p[rr]) : y[rr] + p[rr];
+                }
+                for (int rr = 0; rr < NR; ++rr) x[rr] = rr == R_TH ? fmin(x[rr], y[rr]) : x[rr] + y[rr];
+            }
+        block_reduce(x, sh, kRowThreads / 64);
+        x[R_Z] = Zd;
+        if (tid == 0) {
+            const double D = x[R_CETA] + x[R_Z];
+            DevState st = s_st;
+            double th = x[R_TH];
+            const long long t1 = st.t + 1;
+            const long long c1 = st.cnt + 1;
+            st.t = t1;
+            if (D < st.dbest) st.dbest = D;
+            st.sum_p += x[R_P];
+            st.cnt = c1;
+            if (t1 % sa.check_every == 0) {
+                const double cand = th * (st.sum_p / (double)c1);
+                if (cand > st.lb) st.lb = cand;
+            } else {
+                th = 1.0;
+            }
+            double scale = 1.0;
+            if (sa.rule == SPFOM_STEP_POLYAK) {
+                const double ex = D - st.lb;
+                scale = (x[R_G] > 0.0 && ex > 0.0) ? sa.gamma * ex / x[R_G] : 0.0;
+            } else if (sa.tau_decay > 0.0 && sa.tau_decay < 1.0) {
+                const long long k = (t1 - 1) / sa.decay_every;
+                for (long long q = 0; q < k; ++q) scale *= sa.tau_decay;
+            }
+            st.scale = scale;
+            bool restart = false;
+            if (t1 == 1 || t1 == 2 * st.t0) {
+                restart = true;
+                st.t0 = t1;
+                st.cnt = 0;
+                st.sum_p = 0.0;
+            }
+            st.restart = restart ? 1 : 0;
+            s_st = st;
+            s_scale = scale;
+            s_restart = restart ? 1 : 0;
+            // the trace row at the batch solve's tests: after every
+            // check_every iterations and at the last one; a non-finite row
+            // stops, a gap within tol converges
+            if (t1 % sa.check_every == 0 || t1 == sa.max_iters) {
+                double row[SPFOM_NTRACE];
+                row[SPFOM_TR_DUAL] = D;
+                row[SPFOM_TR_PRIMAL] = x[R_P];
+                row[SPFOM_TR_Z] = x[R_Z];
+                row[SPFOM_TR_ETA2] = x[R_E2];
+                row[SPFOM_TR_INFEAS] = rel_infeas(x);
+                row[SPFOM_TR_DBEST] = st.dbest;
+                row[SPFOM_TR_LB] = st.lb;
+                row[SPFOM_TR_GAP] = (st.dbest - st.lb) / fmax(fabs(st.dbest), DBL_MIN);
+                row[SPFOM_TR_STEP] = scale;
+                row[SPFOM_TR_THETA] = th;
+                bool finite = true;
+                for (int k = 0; k < SPFOM_NTRACE; ++k) {
+                    I->row[k] = row[k];
+                    finite = finite && isfinite(row[k]);
+                }
+                if (!finite) {
+                    s_status = CBLP_ENONFINITE;
+                    s_stop = 1;
+                } else if (t1 % sa.check_every == 0 && row[SPFOM_TR_GAP] <= sa.tol) {
+                    s_status = CBLP_OK;
+                    s_stop = 1;
+                }
+            }
+        }
+        __syncthreads();
+        // the dual step (eq. 16) of every row, and the prices for the next pass
+        const double scale = s_scale;
+        const bool restart = s_restart != 0;
+        for (int64_t i = tid; i < n; i += kSegThreads) {
+            const double ti = scale * t_l[i];
+            double e = (1.0 - ti * sa.mu) * e_l[i] + ti * (u_l[i] - c_l[i]);
+            if (!(e > 0.0)) e = (e != e) ? e : 0.0;   // projection; NaN stays visible
+            const T et = (T)e;
+            e_l[i] = (double)et;
+            if (restart) su_l[i] = 0.0;
+            lprice[I->pnew ? I->pnew[i] : i] = r_l[i] - et;
+        }
+        __syncthreads();
+        if (s_stop) break;
+    }
+    // the instance's state back to the handle
+    for (int64_t i = tid; i < n; i += kSegThreads) {
+        const int64_t q = I->pnew ? I->pnew[i] : i;
+        ((T*)I->eta)[i] = (T)e_l[i];
+        ((T*)I->rho)[q] = lprice[q];
+        I->sum_u[i] = su_l[i];
+        I->u_d[i] = u_l[i];
+        I->S_d[i] = u_l[i];
+    }
+    if (tid == 0) {
+        DevState* st = (DevState*)I->st;
+        st[0] = s_st;
+        st[1] = s_st;
+        sa.status[blockIdx.x] = s_status;
+        sa.iters[blockIdx.x] = s_st.t;
+    }
+}
+
 // Batched variants (the autotuner's candidates):
 //   0  the row-major copies, prices gathered from global memory, no
 //      cross-tile prefetch (no register spills)
@@ -389,6 +627,9 @@ struct cblp_batch {
     spfom_params graph_p{};          // the step parameters the graph was captured with
     std::vector<int64_t> t;          // per-instance iteration counts
     std::vector<int> mask;           // 1: the instance takes part in iterate and solve calls
+    int persist = -1;                // whole solves in one launch: -1 small batches, 0 never, 1 always
+    int* d_status = nullptr;         // [count] the persistent solve's outcome per instance
+    long long* d_iters = nullptr;    // [count] its iterations
 };
 
 namespace {
@@ -403,7 +644,7 @@ void batch_release(cblp_batch* b)
 {
     if (!b) return;
     void* ptrs[] = {b->d_inst, b->d_items, b->d_fold, b->d_rows, b->zpart,
-                    b->bpart, b->st, b->rows, b->counter};
+                    b->bpart, b->st, b->rows, b->counter, b->d_status, b->d_iters};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     if (b->pinned) (void)hipHostFree(b->pinned);
@@ -527,6 +768,68 @@ int run_prices(cblp_batch* b, hipStream_t s)
     return b->dtype == CBLP_F32 ? batch_prices<float>(b, s) : batch_prices<double>(b, s);
 }
 
+// Whole solves in one launch (k_bsolve): every product of every instance has a
+// 64-bit LDS bin, the handles have slot-major parts with one id type, and a
+// block's bins, prices and fold partials fit its LDS.  Chosen by default when
+// every instance has at most kSmallEntries entries: one block per instance
+// then beats three launches per iteration.
+constexpr int64_t kSmallEntries = 1 << 18;
+
+size_t bsolve_lds(const cblp_batch* b) { return bsolve_words(b->Hmax, b->nmax) * 8; }
+
+bool bsolve_ok(const cblp_batch* b)
+{
+    if (!(b->parts16_ok || b->parts32_ok)) return false;
+    for (const cblp_instance* h : b->hs)
+        if (h->n > h->Hb || h->n > kSolveMaxProducts) return false;
+    int dev = 0, lmax = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&lmax, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+        return false;
+    return bsolve_lds(b) + 2048 <= (size_t)lmax;
+}
+
+bool bsolve_small(const cblp_batch* b)
+{
+    for (const cblp_instance* h : b->hs)
+        if (h->nnz > kSmallEntries) return false;
+    return true;
+}
+
+template <typename T>
+int launch_bsolve(cblp_batch* b, const spfom_params* p, hipStream_t s)
+{
+    if (!b->d_status) {
+        if (hipMalloc((void**)&b->d_status, (size_t)b->count * sizeof(int)) != hipSuccess ||
+            hipMalloc((void**)&b->d_iters, (size_t)b->count * sizeof(long long)) != hipSuccess) {
+            (void)hipGetLastError();
+            return bfail(CBLP_ENOMEM, "no memory for the persistent solve's outcome");
+        }
+    }
+    BSolveArgs sa;
+    sa.rule = p->rule;
+    sa.check_every = p->check_every;
+    sa.gamma = p->gamma;
+    sa.mu = p->mu;
+    sa.tau_decay = p->tau_decay;
+    sa.decay_every = p->decay_every;
+    sa.max_iters = p->max_iters;
+    sa.tol = p->tol;
+    sa.status = b->d_status;
+    sa.iters = b->d_iters;
+    bool narrow = false;   // some instance has rows for the 2- or 4-lane groups
+    for (const cblp_instance* h : b->hs) narrow = narrow || h->quad_end > 0;
+    const void* f = b->parts16_ok ? (narrow ? (const void*)k_bsolve<T, uint16_t, true>
+                                            : (const void*)k_bsolve<T, uint16_t, false>)
+                                  : (narrow ? (const void*)k_bsolve<T, int32_t, true>
+                                            : (const void*)k_bsolve<T, int32_t, false>);
+    const size_t lds = bsolve_lds(b);
+    (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    void* args[] = {(void*)&b->d_inst, (void*)&sa};
+    BHIP(hipLaunchKernel(f, dim3((unsigned)b->count), dim3(kSegThreads), args, lds, s));
+    return CBLP_OK;
+}
+
 // join the batch stream to the caller's stream on entry and the other way on exit
 int enter(cblp_batch* b, hipStream_t caller)
 {
@@ -557,10 +860,19 @@ bool bseg_usable(const cblp_batch* b, int variant)
     if (variant == 3 && !b->parts32_ok) return false;
     const void* f = b->dtype == CBLP_F32 ? bseg_fn<float>(variant) : bseg_fn<double>(variant);
     const size_t lds = bseg_lds(b, variant);
+    // a size past the device's LDS is refused here, not by the runtime (whose
+    // error would stay behind as the thread's last error)
+    int dev = 0, lmax = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&lmax, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess ||
+        lds + 1024 > (size_t)lmax)
+        return false;
     int per_cu = 0;
     (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, kSegThreads, lds) == hipSuccess &&
-           per_cu >= 1;
+    const bool ok = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, kSegThreads, lds) ==
+                        hipSuccess && per_cu >= 1;
+    (void)hipGetLastError();
+    return ok;
 }
 
 // The work list: each instance's parts cut into items of about equal tile
@@ -869,6 +1181,33 @@ int spfom_batch_solve(cblp_batch_t b, void* const* etas, const void* const* tau_
         outs[q].status = b->mask[q] ? CBLP_ENOTCONVERGED : CBLP_OK;
         live += b->mask[q];
     }
+    const bool whole = live > 0 && p->max_iters > 0 && b->persist != 0 && bsolve_ok(b) &&
+                       (b->persist == 1 || bsolve_small(b));
+    if (whole) {   // every solve in one launch
+        rc = b->dtype == CBLP_F32 ? launch_bsolve<float>(b, p, b->stream)
+                                  : launch_bsolve<double>(b, p, b->stream);
+        if (rc) return rc;
+        std::vector<int> status((size_t)b->count);
+        std::vector<long long> iters((size_t)b->count);
+        BHIP(hipMemcpyAsync(status.data(), b->d_status, (size_t)b->count * sizeof(int),
+                            hipMemcpyDeviceToHost, b->stream));
+        BHIP(hipMemcpyAsync(iters.data(), b->d_iters, (size_t)b->count * sizeof(long long),
+                            hipMemcpyDeviceToHost, b->stream));
+        BHIP(hipMemcpyAsync(b->pinned, b->rows, (size_t)b->count * SPFOM_NTRACE * 8,
+                            hipMemcpyDeviceToHost, b->stream));
+        BHIP(hipStreamSynchronize(b->stream));
+        const double el = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        for (int q = 0; q < b->count; ++q) {
+            if (!b->mask[q]) continue;
+            spfom_stats& o = outs[q];
+            o.iters = iters[q];
+            b->t[q] = iters[q];
+            std::memcpy(o.trace, b->pinned + (size_t)q * SPFOM_NTRACE, sizeof(o.trace));
+            o.seconds = el;
+            o.status = status[q];
+        }
+        live = 0;
+    }
     // every active instance has done the same number of iterations t: run
     // blocks of K (the graph), the last one cut to max_iters - t (eager), and
     // test the gap after whole blocks only, as spfom_solve does
@@ -1001,6 +1340,18 @@ int cblp_batch_mask(cblp_batch_t b, const int32_t* take_part)
     set_error(CBLP_OK, "");
     if (!b) return bfail(CBLP_EINVAL, "batch is NULL");
     for (int q = 0; q < b->count; ++q) b->mask[q] = take_part ? (take_part[q] != 0) : 1;
+    return CBLP_OK;
+}
+
+int cblp_batch_persistent(cblp_batch_t b, int32_t mode)
+{
+    set_error(CBLP_OK, "");
+    if (!b) return bfail(CBLP_EINVAL, "NULL batch");
+    if (mode < -1 || mode > 1) return bfail(CBLP_EINVAL, "mode must be -1, 0 or 1");
+    if (mode == 1 && !bsolve_ok(b))
+        return bfail(CBLP_EINVAL, "whole solves in one launch need every product in a 64-bit LDS bin "
+                                  "and the handles' slot-major parts");
+    b->persist = mode;
     return CBLP_OK;
 }
 

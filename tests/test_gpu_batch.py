@@ -301,3 +301,56 @@ def test_batch_solve_iteration_cap(cb):
             assert np.array_equal(etas[q].cpu().numpy(), singles[q][1]), (cap, q)
         for p in probs:
             p.close()
+
+
+@pytest.mark.parametrize("dtype,rule", [("f32", 0), ("f64", 0), ("f32", 1)])
+def test_batch_solve_one_launch_matches_launches(cb, dtype, rule):
+    """The one-launch solve (a persistent block per instance running its own
+    iterations, folds and gap tests) and the per-iteration launches stop each
+    instance at the same iteration with the same duals and last trace row,
+    bit for bit; masked instances are left alone by both."""
+    dt = torch.float64 if dtype == "f64" else torch.float32
+    shapes = [(3000, 300), (800, 40), (5000, 1500), (1200, 700), (2500, 2000)]
+    base = [make_instance(L, n, size_lo=3, size_hi=40, zipf=1.1, cap_lo=0.2, cap_hi=0.6, seed=10 + k)
+            for k, (L, n) in enumerate(shapes)] + \
+        [make_instance(800, 40, size_lo=3, size_hi=9, cap_lo=0.5, cap_hi=3.0, seed=s) for s in (1, 2)]
+    mask = [1, 1, 0, 1, 1, 1, 1]
+    res = {}
+    for mode in (0, 1):
+        _, probs, taus = _setup(cb, base, dt, tau0=0.01, rule=rule)
+        batch = cb.Batch(probs)
+        batch.persistent(mode)
+        cb.cblp_batch_mask(batch.b, mask)
+        etas = [p.zeros_eta() for p in probs]
+        kw = dict(rule=rule, tau=1.0, check_every=10, tol=0.05, max_iters=403)
+        if rule == 0:
+            kw.update(tau_decay=0.7, decay_every=100)
+        outs = batch.solve(etas, cb.make_params(**kw), tau_vecs=taus)
+        res[mode] = (outs, [e.cpu().numpy() for e in etas])
+        batch.close()
+        for p in probs:
+            p.close()
+    (o0, e0), (o1, e1) = res[0], res[1]
+    if rule == 0:   # some stop early, the others run to the cap (the last block cut short)
+        assert any(o["status"] == 0 and o["iters"] < 403 for o, m in zip(o0, mask) if m)
+        assert any(o["iters"] == 403 for o, m in zip(o0, mask) if m)
+    for q in range(len(base)):
+        assert o0[q]["iters"] == o1[q]["iters"] and o0[q]["status"] == o1[q]["status"], (q, o0[q], o1[q])
+        for k in cb.TRACE_COLS:
+            assert o0[q][k] == o1[q][k] or (np.isnan(o0[q][k]) and np.isnan(o1[q][k])), (q, k)
+        assert np.array_equal(e0[q], e1[q]), q
+    assert o1[2]["iters"] == 0 and not np.any(e1[2])
+
+
+def test_batch_one_launch_needs_binned_products(cb):
+    """The one-launch form is refused where a product has no LDS bin."""
+    big = make_instance(200, 30000, size_lo=2, size_hi=4, seed=3)   # bins for 16,256 of 30,000
+    _, probs, _ = _setup(cb, [big], torch.float32)
+    batch = cb.Batch(probs)
+    with pytest.raises(cb.CblpError) as e:
+        batch.persistent(1)
+    assert e.value.code == cb.CBLP_EINVAL
+    batch.persistent(0)
+    batch.persistent(-1)
+    batch.close()
+    probs[0].close()
