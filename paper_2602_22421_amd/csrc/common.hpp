@@ -264,7 +264,7 @@ enum {
 };
 constexpr int kQuadMaxRow = 32;        // rows held in registers by the 4-lane groups
 constexpr int kPairMaxRow = 16;        // rows held in registers by the 2-lane groups
-constexpr int kSplitPrices = 8192;     // head prices held in LDS by the split kernels
+constexpr int kSplitPrices = 16384;    // head prices held in LDS by the split kernels
 inline bool seg_mixed3(int variant) { return variant <= kSegMixed3Split32; }
 inline bool seg_split(int variant)
 {

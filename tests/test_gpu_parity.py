@@ -491,7 +491,7 @@ def test_bin_layout_from_sales_bound(cb, case):
     against the oracle at fixed duals, with S the exact sum of the per-entry
     sales."""
     spg = 40 if case == "bound-fails" else 2
-    inst = _grouped_instance(25000, 10, spg, 50.0, seed=3).cast(np.float32)
+    inst = _grouped_instance(24000, 10, spg, 50.0, seed=3).cast(np.float32)
     prob = cb.Problem(inst, dtype=torch.float32)
     rng = np.random.default_rng(4)
     eta = (rng.uniform(0, 0.5, inst.m) * inst.r).astype(np.float32)

@@ -73,13 +73,13 @@ def test_shape_chosen_kernels_agree(cb, dtype, sizes):
         # the FP64 sums over products only gain exact zeros
         np.testing.assert_allclose(tr[:, :3], tr_ref[:, :3], rtol=1e-14)
     if dtype == "f32":
-        # all 600 prices and 64-bit bins in LDS; at n = 30,000 the 8,192 head
-        # prices and a bin for every product: 64-bit ones only for the popular
-        # products whose sales within a block may reach 2^32 quanta, 32-bit
-        # ones for the other real products and the padding; at n = 70,000 the
-        # same, with fewer bins than products (the rest take global atomics)
+        # all 600 prices and 64-bit bins in LDS; at n = 30,000 and 70,000 the
+        # head of the prices in LDS and bins for fewer products than n (the rest
+        # take global atomics): 64-bit ones only for the popular products whose
+        # sales within a block may reach 2^32 quanta, 32-bit ones for the other
+        # real products and the padding's head
         assert bins[0] == (600, 600), bins
-        assert bins[1][0] == 30000 and 0 < bins[1][1] < 600, bins
-        assert 30000 < bins[2][0] < 70000 and bins[2][1] == bins[1][1], bins
+        assert 600 < bins[1][0] < 30000 and 0 < bins[1][1] < 600, bins
+        assert bins[2] == bins[1], bins
     else:
         assert all(b == b64 for b, b64 in bins), bins
