@@ -436,18 +436,16 @@ int minibatch_impl(cblp_instance* h, void* eta, const spfom_params* p, const int
     a.Rwarm = h->Rwarm;
     a.rho = h->rho;
     a.fx_scale = h->fx_scale;
-    a.H = std::min(h->Hb, 8192);
+    a.H = minibatch_bins<T>(h->n);
     a.S_run = h->mb_S;
     a.yq = h->mb_yq;
-    a.wide = sizeof(T) == 8;
     a.stamp = h->mb_stamp;
     a.err = h->mb_err;
-    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((B + 31) / 32, 1024));
     for (int64_t it = 0; it < iters; ++it) {
         a.batch = batch + it * B;
         a.it = h->mb_it;
         h->mb_it = h->mb_it == INT32_MAX ? 0 : h->mb_it + 1;
-        HIP_TRY(launch_minibatch<T>(a, grid, s));
+        HIP_TRY(launch_minibatch<T>(a, s));
         double* row = h->trace + (keep_trace ? it : 0) * SPFOM_NTRACE;
         if ((rc = run_phase<T>(h, eta, p, 2, row, s))) return rc;
         h->t += 1;

@@ -205,13 +205,15 @@ struct MbArgs {
     double fx_scale;
     int H;                         // products [0, H) accumulate in LDS first
     unsigned long long* S_run;     // [n] running totals (library ids)
-    void* yq;                      // [nnz] sales in quanta: uint32 (FP32) or uint64 (wide)
-    bool wide;
+    void* yq;                      // [nnz] sales in quanta: uint32 (FP32) or uint64 (FP64)
     int* stamp;                    // [L] last iteration that sampled each segment
     unsigned* err;                 // bit 0: id out of range, bit 1: id listed twice
 };
 template <typename T>
-hipError_t launch_minibatch(const MbArgs& a, int grid, hipStream_t s);
+hipError_t launch_minibatch(const MbArgs& a, hipStream_t s);
+// LDS bins of the minibatch kernel for n products
+template <typename T>
+int minibatch_bins(int64_t n);
 hipError_t launch_minibatch_init(int64_t L, const int32_t* perm, int32_t* inv_perm, int* stamp,
                                  hipStream_t s);
 

@@ -15,6 +15,8 @@
 // Its inner solve takes the same steps, in the same rounding, as the
 // full-batch kernels' (Dinkelbach from the segment's last R*, sums in the
 // 8-lane order, the same cycle rule), so B = L gives the full batch's bits.
+#include <type_traits>
+
 #include "segment_core.hpp"
 
 namespace cblp {
@@ -25,51 +27,131 @@ using seg::group_sum;
 using seg::quantum;
 using seg::ratio;
 
+constexpr int kRowRegs = 8;   // entries per lane held in registers (rows up to 64)
+
+// threads per block: FP32 runs one 1024-thread block per CU (4 waves per
+// SIMD at its register count) with up to 16,384 bins; FP64, whose solve needs
+// more registers, 256-thread blocks with up to 8,192
 template <typename T>
-__global__ void __launch_bounds__(256) k_minibatch(MbArgs a)
+constexpr int mb_threads() { return sizeof(T) == 4 ? 1024 : 256; }
+
+template <typename T>
+__global__ void __launch_bounds__(mb_threads<T>()) k_minibatch(MbArgs a)
 {
+    constexpr int NT = mb_threads<T>();
     extern __shared__ unsigned long long bins[];   // [a.H] signed changes of the head products
     const int H = a.H;
-    for (int j = threadIdx.x; j < H; j += 256) bins[j] = 0ull;
+    for (int j = threadIdx.x; j < H; j += NT) bins[j] = 0ull;
     __syncthreads();
     const int g = threadIdx.x & (kGroup - 1);
     const int lane = threadIdx.x & 63;
     const T* __restrict__ rho = (const T*)a.rho;
     const T* __restrict__ v2 = (const T*)a.v2;
     const T* __restrict__ d2 = (const T*)a.den2;
-    const int groups = 256 / kGroup;
-    for (int64_t q = (int64_t)blockIdx.x * groups + threadIdx.x / kGroup; q < a.B;
-         q += (int64_t)gridDim.x * groups) {
-        const int32_t l = a.batch[q];
-        if (l < 0 || (int64_t)l >= a.L) {            // rejected; the host reports it
+    const int groups = NT / kGroup;
+    // Each group walks its segments q, q + qs, ...  The chain that locates a
+    // segment's row (its id, then its position, then its row bounds) runs
+    // ahead of the solve: while segment q is solved, the ids of q + 3 qs,
+    // the position of q + 2 qs and the row bounds of q + qs are loaded.
+    using Q = typename std::conditional<sizeof(T) == 4, unsigned, unsigned long long>::type;
+    Q* __restrict__ yq = (Q*)a.yq;
+    const int64_t qs = (int64_t)gridDim.x * groups;
+    const int64_t q0 = (int64_t)blockIdx.x * groups + threadIdx.x / kGroup;
+    auto ok = [&](int32_t l) { return l >= 0 && (int64_t)l < a.L; };
+    auto id = [&](int64_t q) { return q < a.B ? a.batch[q] : (int32_t)-1; };
+    int32_t lc = id(q0), ln = id(q0 + qs), lnn = id(q0 + 2 * qs);
+    int32_t pc = ok(lc) ? a.inv_perm[lc] : 0, pn = ok(ln) ? a.inv_perm[ln] : 0;
+    int64_t bc = 0;
+    int kc = 0;
+    if (ok(lc)) {
+        bc = a.ptr2[pc];
+        kc = (int)(a.ptr2[pc + 1] - bc);
+    }
+    for (int64_t q = q0; q < a.B; q += qs) {
+        const int32_t l = lc;
+        const int64_t p = pc, b = bc;
+        const int k = kc;
+        {   // advance the chain
+            const int32_t l3 = id(q + 3 * qs);
+            const int32_t p2 = ok(lnn) ? a.inv_perm[lnn] : 0;
+            int64_t b1 = 0;
+            int k1 = 0;
+            if (ok(ln)) {
+                b1 = a.ptr2[pn];
+                k1 = (int)(a.ptr2[pn + 1] - b1);
+            }
+            lc = ln;
+            pc = pn;
+            bc = b1;
+            kc = k1;
+            ln = lnn;
+            pn = p2;
+            lnn = l3;
+        }
+        if (!ok(l)) {                                // rejected; the host reports it
             if (g == 0) atomicOr(a.err, 1u);
             continue;
         }
         if (g == 0 && atomicExch(&a.stamp[l], a.it) == a.it) atomicOr(a.err, 2u);
-        const int64_t p = a.inv_perm[l];
-        const int64_t b = a.ptr2[p];
-        const int k = (int)(a.ptr2[p + 1] - b);
         const T vt0 = ((const T*)a.vt0)[p];
         const T lam = ((const T*)a.lam)[p];
-        // Dinkelbach, as the full-batch kernels take it (their comments)
+        // a row of at most kRowRegs * kGroup entries is held in registers (ids,
+        // rho_j v, the denominator weight and the kept sale), so the rounds
+        // below read it once
+        const bool held = k <= kRowRegs * kGroup;
+        int32_t hj[kRowRegs];
+        T hn[kRowRegs], hd[kRowRegs];
+        Q hq[kRowRegs];
+        if (held) {
+#pragma unroll
+            for (int u = 0; u < kRowRegs; ++u) {
+                const int t = g + u * kGroup;
+                hj[u] = t < k ? a.idx2[b + t] : 0;
+                hd[u] = t < k ? d2[b + t] : T(0);
+                hn[u] = t < k ? v2[b + t] : T(0);
+                hq[u] = t < k ? yq[b + t] : Q(0);
+            }
+#pragma unroll
+            for (int u = 0; u < kRowRegs; ++u)
+                if (g + u * kGroup < k) hn[u] = rho[hj[u]] * hn[u];
+        }
+        // Dinkelbach, as the full-batch kernels take it (their comments); the
+        // held and the streamed forms add the same terms in the same order
         auto full = [&](T R, T& N, T& Dn) {
             T n_ = T(0), d_ = T(0);
-            for (int t = g; t < k; t += kGroup) {
-                const T nn = rho[a.idx2[b + t]] * v2[b + t];
-                const T dd = d2[b + t];
-                const T w = nn > R * dd ? T(1) : T(0);
-                n_ = fmadd(w, nn, n_);
-                d_ = fmadd(w, dd, d_);
+            if (held) {
+#pragma unroll
+                for (int u = 0; u < kRowRegs; ++u)
+                    if (g + u * kGroup < k) {
+                        const T w = hn[u] > R * hd[u] ? T(1) : T(0);
+                        n_ = fmadd(w, hn[u], n_);
+                        d_ = fmadd(w, hd[u], d_);
+                    }
+            } else {
+                for (int t = g; t < k; t += kGroup) {
+                    const T nn = rho[a.idx2[b + t]] * v2[b + t];
+                    const T dd = d2[b + t];
+                    const T w = nn > R * dd ? T(1) : T(0);
+                    n_ = fmadd(w, nn, n_);
+                    d_ = fmadd(w, dd, d_);
+                }
             }
             N = group_sum(n_);
             Dn = group_sum(d_);
         };
         auto changed = [&](T R, T Rn) {
             bool c = false;
-            for (int t = g; t < k; t += kGroup) {
-                const T nn = rho[a.idx2[b + t]] * v2[b + t];
-                const T dd = d2[b + t];
-                c = c || ((nn > Rn * dd) != (nn > R * dd));
+            if (held) {
+#pragma unroll
+                for (int u = 0; u < kRowRegs; ++u)
+                    if (g + u * kGroup < k)
+                        c = c || ((hn[u] > Rn * hd[u]) != (hn[u] > R * hd[u]));
+            } else {
+                for (int t = g; t < k; t += kGroup) {
+                    const T nn = rho[a.idx2[b + t]] * v2[b + t];
+                    const T dd = d2[b + t];
+                    c = c || ((nn > Rn * dd) != (nn > R * dd));
+                }
             }
             return ((__ballot(c) >> (lane & 56)) & 0xFFull) != 0ull;
         };
@@ -97,28 +179,35 @@ __global__ void __launch_bounds__(256) k_minibatch(MbArgs a)
             Rs = pRs;
         }
         const T lamD = ratio(lam, vt0 + Dn) * (T)a.fx_scale;
-        for (int t = g; t < k; t += kGroup) {
-            const int32_t j = a.idx2[b + t];
-            const T x = v2[b + t];
-            const unsigned long long qn = rho[j] * x > R * d2[b + t] ? quantum(lamD, x) : 0ull;
-            const unsigned long long qo = a.wide ? ((const unsigned long long*)a.yq)[b + t]
-                                                 : (unsigned long long)((const unsigned*)a.yq)[b + t];
-            if (qn != qo) {
-                if (a.wide)
-                    ((unsigned long long*)a.yq)[b + t] = qn;
-                else
-                    ((unsigned*)a.yq)[b + t] = (unsigned)qn;
-                const unsigned long long d = qn - qo;   // two's complement change
+        // each entry's new quantum against its kept one; the change goes to
+        // the block's bins (head products) or the global totals
+        auto sale = [&](int t, int32_t j, bool in, Q qo) {
+            const unsigned long long qn = in ? quantum(lamD, v2[b + t]) : 0ull;
+            if (qn != (unsigned long long)qo) {
+                yq[b + t] = (Q)qn;
+                const unsigned long long d = qn - (unsigned long long)qo;
                 if (j < H)
-                    atomicAdd(&bins[j], d);
+                    atomicAdd(&bins[j], d);   // two's complement change
                 else
                     atomicAdd(&a.S_run[j], d);
+            }
+        };
+        if (held) {
+#pragma unroll
+            for (int u = 0; u < kRowRegs; ++u) {
+                const int t = g + u * kGroup;
+                if (t < k) sale(t, hj[u], hn[u] > R * hd[u], hq[u]);
+            }
+        } else {
+            for (int t = g; t < k; t += kGroup) {
+                const int32_t j = a.idx2[b + t];
+                sale(t, j, rho[j] * v2[b + t] > R * d2[b + t], yq[b + t]);
             }
         }
         if (g == 0) ((T*)a.Rwarm)[p] = Rs;
     }
     __syncthreads();
-    for (int j = threadIdx.x; j < H; j += 256)
+    for (int j = threadIdx.x; j < H; j += NT)
         if (bins[j]) atomicAdd(&a.S_run[j], bins[j]);
 }
 
@@ -139,12 +228,23 @@ __global__ void k_mb_inv_perm(int64_t L, const int32_t* perm, int32_t* inv)
 }  // namespace
 
 template <typename T>
-hipError_t launch_minibatch(const MbArgs& a, int grid, hipStream_t s)
+int minibatch_bins(int64_t n)
 {
+    return (int)std::min<int64_t>(n, sizeof(T) == 4 ? 16384 : 8192);
+}
+
+template <typename T>
+hipError_t launch_minibatch(const MbArgs& a, hipStream_t s)
+{
+    constexpr int NT = mb_threads<T>();
+    const int groups = NT / kGroup;
+    const int64_t cap = NT == 1024 ? 256 : 1024;   // about one wave of blocks
+    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((a.B + groups - 1) / groups, cap));
     const size_t lds = (size_t)a.H * 8;
-    (void)hipFuncSetAttribute((const void*)k_minibatch<T>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL(k_minibatch<T>, dim3(grid), dim3(256), lds, s, a);
+    hipError_t e = hipFuncSetAttribute((const void*)k_minibatch<T>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_minibatch<T>, dim3(grid), dim3(NT), lds, s, a);
     return hipGetLastError();
 }
 
@@ -158,7 +258,9 @@ hipError_t launch_minibatch_init(int64_t L, const int32_t* perm, int32_t* inv_pe
     return hipGetLastError();
 }
 
-template hipError_t launch_minibatch<float>(const MbArgs&, int, hipStream_t);
-template hipError_t launch_minibatch<double>(const MbArgs&, int, hipStream_t);
+template int minibatch_bins<float>(int64_t);
+template int minibatch_bins<double>(int64_t);
+template hipError_t launch_minibatch<float>(const MbArgs&, hipStream_t);
+template hipError_t launch_minibatch<double>(const MbArgs&, hipStream_t);
 
 }  // namespace cblp
