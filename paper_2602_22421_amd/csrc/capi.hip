@@ -84,7 +84,7 @@ void release(cblp_instance* h)
                     h->rho, h->S_fx, h->S_d, h->u_d, h->sum_u, h->zpart, h->brow,
                     h->bpart, h->bpart2, h->st, h->arrive, h->trace, h->at_ptr,
                     h->at_prod, h->at_val, h->rlib, h->psum, h->theta_prod, h->pseg_part,
-                    h->eval_thr, h->eval_lamD, h->mb_yq, h->mb_S, h->mb_inv, h->mb_stamp,
+                    h->eval_thr, h->eval_lamD, h->mb_yq, h->mb_S, h->mb_rec, h->mb_stamp,
                     h->mb_err};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
@@ -408,17 +408,18 @@ int minibatch_impl(cblp_instance* h, void* eta, const spfom_params* p, const int
         const size_t qsz = sizeof(T) == 4 ? 4 : 8;
         if ((rc = dalloc(&h->mb_yq, (size_t)std::max<int64_t>(h->nnz, 1) * qsz)) ||
             (rc = dalloc(&h->mb_S, (size_t)h->n * 8)) ||
-            (rc = dalloc(&h->mb_inv, (size_t)std::max<int64_t>(h->L, 1) * 4)) ||
+            (rc = dalloc(&h->mb_rec, (size_t)std::max<int64_t>(h->L, 1) * 32)) ||
             (rc = dalloc(&h->mb_stamp, (size_t)std::max<int64_t>(h->L, 1) * 4)) ||
             (rc = dalloc(&h->mb_err, sizeof(unsigned))))
             return rc;
-        HIP_TRY(launch_minibatch_init(h->L, h->perm, h->mb_inv, h->mb_stamp, s));
+        HIP_TRY(launch_minibatch_init(h->L, h->mb_stamp, s));
         h->mb_clear = true;
     }
     if (h->mb_clear) {   // y^0 = 0
         const size_t qsz = sizeof(T) == 4 ? 4 : 8;
         HIP_TRY(hipMemsetAsync(h->mb_yq, 0, (size_t)h->nnz * qsz, s));
         HIP_TRY(hipMemsetAsync(h->mb_S, 0, (size_t)h->n * 8, s));
+        HIP_TRY(launch_minibatch_records<T>(h->L, h->perm, h->ptr2, h->vt0, h->lam2, h->mb_rec, s));
         h->mb_clear = false;
     }
     HIP_TRY(hipMemsetAsync(h->mb_err, 0, sizeof(unsigned), s));
@@ -426,13 +427,10 @@ int minibatch_impl(cblp_instance* h, void* eta, const spfom_params* p, const int
     MbArgs a;
     a.L = h->L;
     a.B = B;
-    a.inv_perm = h->mb_inv;
-    a.ptr2 = h->ptr2;
+    a.rec = h->mb_rec;
     a.idx2 = h->idx2;
     a.v2 = h->v2;
     a.den2 = h->den2;
-    a.vt0 = h->vt0;
-    a.lam = h->lam2;
     a.Rwarm = h->Rwarm;
     a.rho = h->rho;
     a.fx_scale = h->fx_scale;

@@ -193,13 +193,10 @@ struct MbArgs {
     int64_t L, B;
     int it;                        // iteration number (duplicate detection)
     const int32_t* batch;          // [B] caller segment ids
-    const int32_t* inv_perm;       // [L] position of caller segment l
-    const int64_t* ptr2;           // [L+1] row pointers of the row-major copy
-    const int32_t* idx2;
+    const void* rec;               // [L] per caller segment: row, position, v_t0, lambda
+    const int32_t* idx2;           // row-major library copy
     const void* v2;
     const void* den2;
-    const void* vt0;
-    const void* lam;
     void* Rwarm;
     const void* rho;
     double fx_scale;
@@ -214,8 +211,12 @@ hipError_t launch_minibatch(const MbArgs& a, hipStream_t s);
 // LDS bins of the minibatch kernel for n products
 template <typename T>
 int minibatch_bins(int64_t n);
-hipError_t launch_minibatch_init(int64_t L, const int32_t* perm, int32_t* inv_perm, int* stamp,
-                                 hipStream_t s);
+hipError_t launch_minibatch_init(int64_t L, int* stamp, hipStream_t s);
+// the per-segment records of the minibatch kernel (32 bytes per segment),
+// rebuilt whenever its state restarts, since the values may have changed
+template <typename T>
+hipError_t launch_minibatch_records(int64_t L, const int32_t* perm, const int64_t* ptr2,
+                                    const void* vt0, const void* lam, void* rec, hipStream_t s);
 
 // Launchers (one per kernel family), defined next to their kernels.
 template <typename T>

@@ -86,7 +86,7 @@ struct cblp_instance {
     // quanta, running product totals, segment positions, sampling stamps
     void* mb_yq = nullptr;
     unsigned long long* mb_S = nullptr;
-    int32_t* mb_inv = nullptr;
+    void* mb_rec = nullptr;           // [L] 32-byte per-segment records
     int* mb_stamp = nullptr;
     unsigned* mb_err = nullptr;
     int mb_it = 0;                  // iterations run, for the stamps

@@ -29,6 +29,17 @@ using seg::ratio;
 
 constexpr int kRowRegs = 8;   // entries per lane held in registers (rows up to 64)
 
+// A segment's row and own values, by caller id, in one 32-byte record (one
+// line per sampled segment instead of one for each of five arrays).
+template <typename T>
+struct alignas(32) MbSeg {
+    int64_t b;    // row start in the row-major copy
+    int32_t k;    // entries
+    int32_t p;    // position (the warm start's slot)
+    T vt0, lam;
+};
+static_assert(sizeof(MbSeg<float>) == 32 && sizeof(MbSeg<double>) == 32, "record size");
+
 // threads per block: FP32 runs one 1024-thread block per CU (4 waves per
 // SIMD at its register count) with up to 16,384 bins; FP64, whose solve needs
 // more registers, 256-thread blocks with up to 8,192
@@ -50,51 +61,35 @@ __global__ void __launch_bounds__(mb_threads<T>()) k_minibatch(MbArgs a)
     const T* __restrict__ d2 = (const T*)a.den2;
     const int groups = NT / kGroup;
     // Each group walks its segments q, q + qs, ...  The chain that locates a
-    // segment's row (its id, then its position, then its row bounds) runs
-    // ahead of the solve: while segment q is solved, the ids of q + 3 qs,
-    // the position of q + 2 qs and the row bounds of q + qs are loaded.
+    // segment's row (its id, then its record) runs ahead of the solve: while
+    // segment q is solved, the id of q + 2 qs and the record of q + qs load.
     using Q = typename std::conditional<sizeof(T) == 4, unsigned, unsigned long long>::type;
     Q* __restrict__ yq = (Q*)a.yq;
     const int64_t qs = (int64_t)gridDim.x * groups;
     const int64_t q0 = (int64_t)blockIdx.x * groups + threadIdx.x / kGroup;
     auto ok = [&](int32_t l) { return l >= 0 && (int64_t)l < a.L; };
     auto id = [&](int64_t q) { return q < a.B ? a.batch[q] : (int32_t)-1; };
-    int32_t lc = id(q0), ln = id(q0 + qs), lnn = id(q0 + 2 * qs);
-    int32_t pc = ok(lc) ? a.inv_perm[lc] : 0, pn = ok(ln) ? a.inv_perm[ln] : 0;
-    int64_t bc = 0;
-    int kc = 0;
-    if (ok(lc)) {
-        bc = a.ptr2[pc];
-        kc = (int)(a.ptr2[pc + 1] - bc);
-    }
+    const MbSeg<T>* __restrict__ rec = (const MbSeg<T>*)a.rec;
+    int32_t lc = id(q0), ln = id(q0 + qs);
+    MbSeg<T> rc{};
+    if (ok(lc)) rc = rec[lc];
     for (int64_t q = q0; q < a.B; q += qs) {
         const int32_t l = lc;
-        const int64_t p = pc, b = bc;
-        const int k = kc;
+        const MbSeg<T> r = rc;
         {   // advance the chain
-            const int32_t l3 = id(q + 3 * qs);
-            const int32_t p2 = ok(lnn) ? a.inv_perm[lnn] : 0;
-            int64_t b1 = 0;
-            int k1 = 0;
-            if (ok(ln)) {
-                b1 = a.ptr2[pn];
-                k1 = (int)(a.ptr2[pn + 1] - b1);
-            }
+            const int32_t l2 = id(q + 2 * qs);
+            if (ok(ln)) rc = rec[ln];
             lc = ln;
-            pc = pn;
-            bc = b1;
-            kc = k1;
-            ln = lnn;
-            pn = p2;
-            lnn = l3;
+            ln = l2;
         }
         if (!ok(l)) {                                // rejected; the host reports it
             if (g == 0) atomicOr(a.err, 1u);
             continue;
         }
         if (g == 0 && atomicExch(&a.stamp[l], a.it) == a.it) atomicOr(a.err, 2u);
-        const T vt0 = ((const T*)a.vt0)[p];
-        const T lam = ((const T*)a.lam)[p];
+        const int64_t p = r.p, b = r.b;
+        const int k = r.k;
+        const T vt0 = r.vt0, lam = r.lam;
         // a row of at most kRowRegs * kGroup entries is held in registers (ids,
         // rho_j v, the denominator weight and the kept sale), so the rounds
         // below read it once
@@ -218,11 +213,20 @@ __global__ void k_mb_stamp_init(int64_t L, int* stamp)
         stamp[l] = -1;
 }
 
-__global__ void k_mb_inv_perm(int64_t L, const int32_t* perm, int32_t* inv)
+template <typename T>
+__global__ void k_mb_records(int64_t L, const int32_t* perm, const int64_t* ptr2, const T* vt0,
+                             const T* lam, MbSeg<T>* rec)
 {
     for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < L;
-         p += (int64_t)gridDim.x * blockDim.x)
-        inv[perm[p]] = (int32_t)p;
+         p += (int64_t)gridDim.x * blockDim.x) {
+        MbSeg<T> r;
+        r.b = ptr2[p];
+        r.k = (int32_t)(ptr2[p + 1] - r.b);
+        r.p = (int32_t)p;
+        r.vt0 = vt0[p];
+        r.lam = lam[p];
+        rec[perm[p]] = r;
+    }
 }
 
 }  // namespace
@@ -248,13 +252,19 @@ hipError_t launch_minibatch(const MbArgs& a, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_minibatch_init(int64_t L, const int32_t* perm, int32_t* inv_perm, int* stamp,
-                                 hipStream_t s)
+hipError_t launch_minibatch_init(int64_t L, int* stamp, hipStream_t s)
 {
-    if (L > 0) {
-        hipLaunchKernelGGL(k_mb_stamp_init, dim3(1024), dim3(256), 0, s, L, stamp);
-        hipLaunchKernelGGL(k_mb_inv_perm, dim3(1024), dim3(256), 0, s, L, perm, inv_perm);
-    }
+    if (L > 0) hipLaunchKernelGGL(k_mb_stamp_init, dim3(1024), dim3(256), 0, s, L, stamp);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_minibatch_records(int64_t L, const int32_t* perm, const int64_t* ptr2,
+                                    const void* vt0, const void* lam, void* rec, hipStream_t s)
+{
+    if (L > 0)
+        hipLaunchKernelGGL(k_mb_records<T>, dim3(1024), dim3(256), 0, s, L, perm, ptr2,
+                           (const T*)vt0, (const T*)lam, (MbSeg<T>*)rec);
     return hipGetLastError();
 }
 
@@ -262,5 +272,9 @@ template int minibatch_bins<float>(int64_t);
 template int minibatch_bins<double>(int64_t);
 template hipError_t launch_minibatch<float>(const MbArgs&, hipStream_t);
 template hipError_t launch_minibatch<double>(const MbArgs&, hipStream_t);
+template hipError_t launch_minibatch_records<float>(int64_t, const int32_t*, const int64_t*,
+                                                   const void*, const void*, void*, hipStream_t);
+template hipError_t launch_minibatch_records<double>(int64_t, const int32_t*, const int64_t*,
+                                                    const void*, const void*, void*, hipStream_t);
 
 }  // namespace cblp

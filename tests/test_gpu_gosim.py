@@ -68,6 +68,32 @@ def test_refresh_equals_fresh_handle(cb, dtype):
     pb.close()
 
 
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_minibatch_after_refresh_equals_fresh_handle(cb, dtype):
+    """A refresh restarts the minibatch state and rebuilds the minibatch
+    kernel's per-segment records (v_t0 follows the new w): minibatch
+    iterations after it equal those of a handle made from the new values."""
+    from paper_2602_22421_amd.instances import minibatch_schedule
+    dt = torch.float64 if dtype == "f64" else torch.float32
+    npdt = np.float64 if dtype == "f64" else np.float32
+    a = config_instance(1, scale=0.01).cast(npdt)
+    b = _revalued(a, 9).cast(npdt)
+    pa = cb.Problem(a, dtype=dt)
+    pb = cb.Problem(b, dtype=dt)
+    tau = pa.tensor(step_scale(b, 0.002).astype(npdt))
+    prm = cb.make_params(rule=0, tau_vec=tau)
+    batch = minibatch_schedule(a.L, a.L // 10, 12, seed=3, mode="epoch")
+    pa.minibatch(pa.zeros_eta(), batch[:4], prm)   # records of the old values
+    pa.refresh(v=b.v, w=b.w, c=b.c)
+    ea, eb = pa.zeros_eta(), pb.zeros_eta()
+    ta = pa.minibatch(ea, batch, prm)
+    tb = pb.minibatch(eb, batch, prm)
+    assert torch.equal(ea, eb)
+    assert np.array_equal(ta, tb)
+    pa.close()
+    pb.close()
+
+
 def test_refresh_rejects_invalid_values(cb):
     a = make_instance(50, 8, seed=3)
     p = cb.Problem(a, dtype=torch.float64)
