@@ -20,6 +20,7 @@
 
 #include "common.hpp"
 #include "handle.hpp"
+#include "minibatch.hpp"
 
 using namespace cblp;
 
@@ -84,7 +85,7 @@ void release(cblp_instance* h)
                     h->rho, h->S_fx, h->S_d, h->u_d, h->sum_u, h->zpart, h->brow,
                     h->bpart, h->bpart2, h->st, h->arrive, h->trace, h->at_ptr,
                     h->at_prod, h->at_val, h->rlib, h->psum, h->theta_prod, h->pseg_part,
-                    h->eval_thr, h->eval_lamD, h->mb_yq, h->mb_S, h->mb_rec, h->mb_stamp,
+                    h->eval_thr, h->eval_lamD, h->mb_ent, h->mb_S, h->mb_rec, h->mb_stamp,
                     h->mb_err};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
@@ -405,21 +406,19 @@ int minibatch_impl(cblp_instance* h, void* eta, const spfom_params* p, const int
 {
     int rc;
     if (!h->mb_S) {
-        const size_t qsz = sizeof(T) == 4 ? 4 : 8;
-        if ((rc = dalloc(&h->mb_yq, (size_t)std::max<int64_t>(h->nnz, 1) * qsz)) ||
+        if ((rc = dalloc(&h->mb_ent, (size_t)std::max<int64_t>(h->nnz, 1) * mb_ent_bytes<T>())) ||
             (rc = dalloc(&h->mb_S, (size_t)h->n * 8)) ||
-            (rc = dalloc(&h->mb_rec, (size_t)std::max<int64_t>(h->L, 1) * 32)) ||
+            (rc = dalloc(&h->mb_rec, (size_t)std::max<int64_t>(h->L, 1) * kMbRecBytes)) ||
             (rc = dalloc(&h->mb_stamp, (size_t)std::max<int64_t>(h->L, 1) * 4)) ||
             (rc = dalloc(&h->mb_err, sizeof(unsigned))))
             return rc;
         HIP_TRY(launch_minibatch_init(h->L, h->mb_stamp, s));
         h->mb_clear = true;
     }
-    if (h->mb_clear) {   // y^0 = 0
-        const size_t qsz = sizeof(T) == 4 ? 4 : 8;
-        HIP_TRY(hipMemsetAsync(h->mb_yq, 0, (size_t)h->nnz * qsz, s));
+    if (h->mb_clear) {   // y^0 = 0: the entries' kept sales and the totals
         HIP_TRY(hipMemsetAsync(h->mb_S, 0, (size_t)h->n * 8, s));
-        HIP_TRY(launch_minibatch_records<T>(h->L, h->perm, h->ptr2, h->vt0, h->lam2, h->mb_rec, s));
+        HIP_TRY(launch_minibatch_records<T>(h->L, h->perm, h->ptr2, h->vt0, h->lam2, h->mb_rec,
+                                            h->nnz, h->idx2, h->v2, h->den2, h->mb_ent, s));
         h->mb_clear = false;
     }
     HIP_TRY(hipMemsetAsync(h->mb_err, 0, sizeof(unsigned), s));
@@ -428,15 +427,12 @@ int minibatch_impl(cblp_instance* h, void* eta, const spfom_params* p, const int
     a.L = h->L;
     a.B = B;
     a.rec = h->mb_rec;
-    a.idx2 = h->idx2;
-    a.v2 = h->v2;
-    a.den2 = h->den2;
+    a.ent = h->mb_ent;
     a.Rwarm = h->Rwarm;
     a.rho = h->rho;
     a.fx_scale = h->fx_scale;
     a.H = minibatch_bins<T>(h->n);
     a.S_run = h->mb_S;
-    a.yq = h->mb_yq;
     a.stamp = h->mb_stamp;
     a.err = h->mb_err;
     for (int64_t it = 0; it < iters; ++it) {

@@ -186,38 +186,6 @@ struct PhaseArgs {
     int pseg_blocks;
 };
 
-// Minibatch segment pass (minibatch.hip): re-solves the segments batch[0, B)
-// (caller ids) of iteration `it` over the row-major library copy and adds
-// each entry's change of sale to the running product totals S_run.
-struct MbArgs {
-    int64_t L, B;
-    int it;                        // iteration number (duplicate detection)
-    const int32_t* batch;          // [B] caller segment ids
-    const void* rec;               // [L] per caller segment: row, position, v_t0, lambda
-    const int32_t* idx2;           // row-major library copy
-    const void* v2;
-    const void* den2;
-    void* Rwarm;
-    const void* rho;
-    double fx_scale;
-    int H;                         // products [0, H) accumulate in LDS first
-    unsigned long long* S_run;     // [n] running totals (library ids)
-    void* yq;                      // [nnz] sales in quanta: uint32 (FP32) or uint64 (FP64)
-    int* stamp;                    // [L] last iteration that sampled each segment
-    unsigned* err;                 // bit 0: id out of range, bit 1: id listed twice
-};
-template <typename T>
-hipError_t launch_minibatch(const MbArgs& a, hipStream_t s);
-// LDS bins of the minibatch kernel for n products
-template <typename T>
-int minibatch_bins(int64_t n);
-hipError_t launch_minibatch_init(int64_t L, int* stamp, hipStream_t s);
-// the per-segment records of the minibatch kernel (32 bytes per segment),
-// rebuilt whenever its state restarts, since the values may have changed
-template <typename T>
-hipError_t launch_minibatch_records(int64_t L, const int32_t* perm, const int64_t* ptr2,
-                                    const void* vt0, const void* lam, void* rec, hipStream_t s);
-
 // Launchers (one per kernel family), defined next to their kernels.
 template <typename T>
 hipError_t launch_validate(int64_t L, int64_t n, int64_t m, int64_t nnz, int64_t nnzA,

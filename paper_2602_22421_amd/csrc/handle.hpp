@@ -84,7 +84,7 @@ struct cblp_instance {
     void* eval_lamD = nullptr;
     // stochastic minibatch state (allocated on first use): per-entry sales in
     // quanta, running product totals, segment positions, sampling stamps
-    void* mb_yq = nullptr;
+    void* mb_ent = nullptr;           // [nnz] entry records with the kept sales
     unsigned long long* mb_S = nullptr;
     void* mb_rec = nullptr;           // [L] 32-byte per-segment records
     int* mb_stamp = nullptr;

@@ -15,8 +15,7 @@
 // Its inner solve takes the same steps, in the same rounding, as the
 // full-batch kernels' (Dinkelbach from the segment's last R*, sums in the
 // 8-lane order, the same cycle rule), so B = L gives the full batch's bits.
-#include <type_traits>
-
+#include "minibatch.hpp"
 #include "segment_core.hpp"
 
 namespace cblp {
@@ -38,7 +37,28 @@ struct alignas(32) MbSeg {
     int32_t p;    // position (the warm start's slot)
     T vt0, lam;
 };
-static_assert(sizeof(MbSeg<float>) == 32 && sizeof(MbSeg<double>) == 32, "record size");
+static_assert(sizeof(MbSeg<float>) == kMbRecBytes && sizeof(MbSeg<double>) == kMbRecBytes,
+              "record size");
+
+// An entry's product id, v, denominator weight and kept sale in one record,
+// so a sampled row is one run of lines rather than one in each of four arrays.
+template <typename T>
+struct MbEnt;
+template <>
+struct alignas(16) MbEnt<float> {
+    int32_t j;
+    float v, d;
+    unsigned q;
+};
+template <>
+struct alignas(32) MbEnt<double> {
+    int32_t j, pad;
+    double v, d;
+    unsigned long long q;
+};
+static_assert(sizeof(MbEnt<float>) == mb_ent_bytes<float>() &&
+                  sizeof(MbEnt<double>) == mb_ent_bytes<double>(),
+              "entry record size");
 
 // threads per block: FP32 runs one 1024-thread block per CU (4 waves per
 // SIMD at its register count) with up to 16,384 bins; FP64, whose solve needs
@@ -57,14 +77,12 @@ __global__ void __launch_bounds__(mb_threads<T>()) k_minibatch(MbArgs a)
     const int g = threadIdx.x & (kGroup - 1);
     const int lane = threadIdx.x & 63;
     const T* __restrict__ rho = (const T*)a.rho;
-    const T* __restrict__ v2 = (const T*)a.v2;
-    const T* __restrict__ d2 = (const T*)a.den2;
+    MbEnt<T>* __restrict__ ent = (MbEnt<T>*)a.ent;
     const int groups = NT / kGroup;
     // Each group walks its segments q, q + qs, ...  The chain that locates a
     // segment's row (its id, then its record) runs ahead of the solve: while
     // segment q is solved, the id of q + 2 qs and the record of q + qs load.
-    using Q = typename std::conditional<sizeof(T) == 4, unsigned, unsigned long long>::type;
-    Q* __restrict__ yq = (Q*)a.yq;
+    using Q = decltype(MbEnt<T>::q);
     const int64_t qs = (int64_t)gridDim.x * groups;
     const int64_t q0 = (int64_t)blockIdx.x * groups + threadIdx.x / kGroup;
     auto ok = [&](int32_t l) { return l >= 0 && (int64_t)l < a.L; };
@@ -91,24 +109,25 @@ __global__ void __launch_bounds__(mb_threads<T>()) k_minibatch(MbArgs a)
         const int k = r.k;
         const T vt0 = r.vt0, lam = r.lam;
         // a row of at most kRowRegs * kGroup entries is held in registers (ids,
-        // rho_j v, the denominator weight and the kept sale), so the rounds
+        // v, rho_j v, the denominator weight and the kept sale), so the rounds
         // below read it once
         const bool held = k <= kRowRegs * kGroup;
         int32_t hj[kRowRegs];
-        T hn[kRowRegs], hd[kRowRegs];
+        T hv[kRowRegs], hn[kRowRegs], hd[kRowRegs];
         Q hq[kRowRegs];
         if (held) {
 #pragma unroll
             for (int u = 0; u < kRowRegs; ++u) {
                 const int t = g + u * kGroup;
-                hj[u] = t < k ? a.idx2[b + t] : 0;
-                hd[u] = t < k ? d2[b + t] : T(0);
-                hn[u] = t < k ? v2[b + t] : T(0);
-                hq[u] = t < k ? yq[b + t] : Q(0);
+                const MbEnt<T> e = t < k ? ent[b + t] : MbEnt<T>{};
+                hj[u] = e.j;
+                hv[u] = e.v;
+                hd[u] = e.d;
+                hq[u] = e.q;
             }
 #pragma unroll
             for (int u = 0; u < kRowRegs; ++u)
-                if (g + u * kGroup < k) hn[u] = rho[hj[u]] * hn[u];
+                hn[u] = g + u * kGroup < k ? rho[hj[u]] * hv[u] : T(0);
         }
         // Dinkelbach, as the full-batch kernels take it (their comments); the
         // held and the streamed forms add the same terms in the same order
@@ -124,8 +143,8 @@ __global__ void __launch_bounds__(mb_threads<T>()) k_minibatch(MbArgs a)
                     }
             } else {
                 for (int t = g; t < k; t += kGroup) {
-                    const T nn = rho[a.idx2[b + t]] * v2[b + t];
-                    const T dd = d2[b + t];
+                    const T nn = rho[ent[b + t].j] * ent[b + t].v;
+                    const T dd = ent[b + t].d;
                     const T w = nn > R * dd ? T(1) : T(0);
                     n_ = fmadd(w, nn, n_);
                     d_ = fmadd(w, dd, d_);
@@ -143,8 +162,8 @@ __global__ void __launch_bounds__(mb_threads<T>()) k_minibatch(MbArgs a)
                         c = c || ((hn[u] > Rn * hd[u]) != (hn[u] > R * hd[u]));
             } else {
                 for (int t = g; t < k; t += kGroup) {
-                    const T nn = rho[a.idx2[b + t]] * v2[b + t];
-                    const T dd = d2[b + t];
+                    const T nn = rho[ent[b + t].j] * ent[b + t].v;
+                    const T dd = ent[b + t].d;
                     c = c || ((nn > Rn * dd) != (nn > R * dd));
                 }
             }
@@ -176,10 +195,10 @@ __global__ void __launch_bounds__(mb_threads<T>()) k_minibatch(MbArgs a)
         const T lamD = ratio(lam, vt0 + Dn) * (T)a.fx_scale;
         // each entry's new quantum against its kept one; the change goes to
         // the block's bins (head products) or the global totals
-        auto sale = [&](int t, int32_t j, bool in, Q qo) {
-            const unsigned long long qn = in ? quantum(lamD, v2[b + t]) : 0ull;
+        auto sale = [&](int t, int32_t j, T v, bool in, Q qo) {
+            const unsigned long long qn = in ? quantum(lamD, v) : 0ull;
             if (qn != (unsigned long long)qo) {
-                yq[b + t] = (Q)qn;
+                ent[b + t].q = (Q)qn;
                 const unsigned long long d = qn - (unsigned long long)qo;
                 if (j < H)
                     atomicAdd(&bins[j], d);   // two's complement change
@@ -191,12 +210,12 @@ __global__ void __launch_bounds__(mb_threads<T>()) k_minibatch(MbArgs a)
 #pragma unroll
             for (int u = 0; u < kRowRegs; ++u) {
                 const int t = g + u * kGroup;
-                if (t < k) sale(t, hj[u], hn[u] > R * hd[u], hq[u]);
+                if (t < k) sale(t, hj[u], hv[u], hn[u] > R * hd[u], hq[u]);
             }
         } else {
             for (int t = g; t < k; t += kGroup) {
-                const int32_t j = a.idx2[b + t];
-                sale(t, j, rho[j] * v2[b + t] > R * d2[b + t], yq[b + t]);
+                const MbEnt<T> e = ent[b + t];
+                sale(t, e.j, e.v, rho[e.j] * e.v > R * e.d, e.q);
             }
         }
         if (g == 0) ((T*)a.Rwarm)[p] = Rs;
@@ -204,6 +223,21 @@ __global__ void __launch_bounds__(mb_threads<T>()) k_minibatch(MbArgs a)
     __syncthreads();
     for (int j = threadIdx.x; j < H; j += NT)
         if (bins[j]) atomicAdd(&a.S_run[j], bins[j]);
+}
+
+template <typename T>
+__global__ void k_mb_entries(int64_t nnz, const int32_t* idx2, const T* v2, const T* den2,
+                             MbEnt<T>* ent)
+{
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nnz;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        MbEnt<T> r{};
+        r.j = idx2[e];
+        r.v = v2[e];
+        r.d = den2[e];
+        r.q = 0;   // y^0 = 0
+        ent[e] = r;
+    }
 }
 
 __global__ void k_mb_stamp_init(int64_t L, int* stamp)
@@ -260,11 +294,16 @@ hipError_t launch_minibatch_init(int64_t L, int* stamp, hipStream_t s)
 
 template <typename T>
 hipError_t launch_minibatch_records(int64_t L, const int32_t* perm, const int64_t* ptr2,
-                                    const void* vt0, const void* lam, void* rec, hipStream_t s)
+                                    const void* vt0, const void* lam, void* rec, int64_t nnz,
+                                    const int32_t* idx2, const void* v2, const void* den2,
+                                    void* ent, hipStream_t s)
 {
     if (L > 0)
         hipLaunchKernelGGL(k_mb_records<T>, dim3(1024), dim3(256), 0, s, L, perm, ptr2,
                            (const T*)vt0, (const T*)lam, (MbSeg<T>*)rec);
+    if (nnz > 0)
+        hipLaunchKernelGGL(k_mb_entries<T>, dim3(2048), dim3(256), 0, s, nnz, idx2,
+                           (const T*)v2, (const T*)den2, (MbEnt<T>*)ent);
     return hipGetLastError();
 }
 
@@ -273,8 +312,12 @@ template int minibatch_bins<double>(int64_t);
 template hipError_t launch_minibatch<float>(const MbArgs&, hipStream_t);
 template hipError_t launch_minibatch<double>(const MbArgs&, hipStream_t);
 template hipError_t launch_minibatch_records<float>(int64_t, const int32_t*, const int64_t*,
-                                                   const void*, const void*, void*, hipStream_t);
+                                                   const void*, const void*, void*, int64_t,
+                                                   const int32_t*, const void*, const void*,
+                                                   void*, hipStream_t);
 template hipError_t launch_minibatch_records<double>(int64_t, const int32_t*, const int64_t*,
-                                                    const void*, const void*, void*, hipStream_t);
+                                                    const void*, const void*, void*, int64_t,
+                                                    const int32_t*, const void*, const void*,
+                                                    void*, hipStream_t);
 
 }  // namespace cblp
